@@ -1,0 +1,234 @@
+"""The modular projected eigensolver (Sec. II, Algorithm 1), literally, in FP64.
+
+Each step follows the paper:
+
+* leaf ED: dense diagonalisation of each initial block Hamiltonian, keep the
+  lowest k eigenstates (Algorithm 1, first step; eigenstates ordered by
+  increasing energy as in the block-eigenstate equation);
+* projection: boundary-operator matrix elements o_{aa'} = <a|O|a'> in the
+  retained basis (intra-block matrix-element equations);
+* merge: the k_A k_B x k_A k_B effective Hamiltonian assembled explicitly as
+  diag(E_a^A + E_b^B) plus the projected coupling terms (assembled
+  effective-Hamiltonian equation, with V = -sum J' O_A (x) O_B written as
+  sum c_i O_A^i (x) O_B^i, c_i = -J'_i), then fully diagonalised (reduced
+  eigenproblem; the paper's dense eigensolve of App. A);
+* the lowest k eigenvectors are stored through their coefficients in the product
+  basis and used to transform the boundary operators needed by later merges
+  (Algorithm 1, store/transform step);
+* neighbouring modules are merged pairwise until the whole system is reached and
+  the lowest q eigenvalues of the final effective Hamiltonian are returned;
+  identical blocks are computed once (Sec. II, reuse of identical blocks).
+
+Readings where the paper is silent (the same on the GPU side):
+* product index a*k_B + b, A = left module (np.kron(A, B) order);
+* pairing: adjacent modules left to right; an odd module is carried up as is;
+* gap rule for the cut (``gap_cut``): "keep the lowest k" is ambiguous when the
+  cut falls inside a degenerate cluster, so the cut is moved down to the start
+  of that cluster;
+* k larger than the available dimension keeps the whole space.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import hamiltonian as ham
+
+TAU_GAP = 1e-6
+
+
+def gap_cut(w, k_req, tau_gap=TAU_GAP):
+    """Number of states to keep from ascending eigenvalues w (gap rule).
+
+    Returns (k_eff, gap). If k_req >= len(w) everything is kept (gap = inf).
+    Otherwise the scale is s = max(1, |w[0]|, |w[k_req]|); if
+    w[k_req] - w[k_req-1] > tau_gap * s the cut stays at k_req, else it moves
+    down to the start j of the cluster that w[k_req-1] belongs to (the largest
+    j < k_req with w[j] - w[j-1] > tau_gap * s). If the whole range is one
+    cluster the cut stays at k_req and the (tiny) gap is reported.
+    """
+    n = len(w)
+    if k_req >= n:
+        return n, float("inf")
+    scale = max(1.0, abs(float(w[0])), abs(float(w[k_req])))
+    tol = tau_gap * scale
+    gap = float(w[k_req] - w[k_req - 1])
+    if gap > tol:
+        return k_req, gap
+    j = k_req - 1
+    while j >= 1 and float(w[j] - w[j - 1]) <= tol:
+        j -= 1
+    if j >= 1:
+        return j, float(w[j] - w[j - 1])
+    return k_req, gap
+
+
+def leaf_ed(H, k, tau_gap=TAU_GAP):
+    """Dense ED of a block Hamiltonian; keep the lowest k states (gap rule).
+    Returns (E, V, k_eff, gap, all_eigenvalues)."""
+    w, V = np.linalg.eigh(H)
+    k_eff, gap = gap_cut(w, min(k, len(w)), tau_gap)
+    return w[:k_eff].copy(), V[:, :k_eff].copy(), k_eff, gap, w
+
+
+def project(V, O):
+    """Projected operator o = V^T O V (intra-block matrix elements)."""
+    return V.T @ (O @ V)
+
+
+def effective_hamiltonian(E_A, E_B, terms):
+    """Explicit k_A k_B x k_A k_B effective Hamiltonian
+    diag(E_a + E_b) + sum_i c_i o_A^i (x) o_B^i, terms = [(c_i, o_A^i, o_B^i)]."""
+    kA, kB = len(E_A), len(E_B)
+    H = np.kron(np.diag(E_A), np.eye(kB)) + np.kron(np.eye(kA), np.diag(E_B))
+    for c, oA, oB in terms:
+        H = H + c * np.kron(oA, oB)
+    return H
+
+
+def couple_solve(E_A, E_B, terms, k_keep=None, q=None, tau_gap=TAU_GAP):
+    """One coupling step. Returns (w_all, E_kept, U_kept, k_eff, gap).
+    With k_keep=None nothing is cut (root merge)."""
+    H = effective_hamiltonian(E_A, E_B, terms)
+    w, U = np.linalg.eigh(H)
+    if k_keep is None:
+        return w, None, None, None, None
+    k_eff, gap = gap_cut(w, min(k_keep, len(w)), tau_gap)
+    return w, w[:k_eff].copy(), U[:, :k_eff].copy(), k_eff, gap
+
+
+def transform_left(U, oA, kA, kB):
+    """O^M = U^T (o_A (x) I_kB) U for an operator of the left module."""
+    return U.T @ (np.kron(oA, np.eye(kB)) @ U)
+
+
+def transform_right(U, oB, kA, kB):
+    """O^M = U^T (I_kA (x) o_B) U for an operator of the right module."""
+    return U.T @ (np.kron(np.eye(kA), oB) @ U)
+
+
+@dataclass
+class Module:
+    key: tuple
+    width: int
+    E: np.ndarray
+    basis: np.ndarray            # leaf: V (D0 x k_eff); merge: U (kA*kB x k_eff)
+    k_eff: int
+    gap: float
+    kind: str                    # "leaf" or "merge"
+    left: Optional["Module"] = None
+    right: Optional["Module"] = None
+    ops: Dict[Tuple[int, str], np.ndarray] = field(default_factory=dict)
+
+
+@dataclass
+class Record:
+    level: int
+    width: int
+    kind: str
+    k_req: int
+    k_eff: int
+    gap: float
+
+
+@dataclass
+class Result:
+    energies: np.ndarray
+    records: List[Record]
+    n_leaf_ed: int
+    n_merges: int
+
+
+class Recursion:
+    """Algorithm 1 over a chain job (``paper_2609_02394_amd.workloads.ChainJob``)."""
+
+    def __init__(self, job, tau_gap=TAU_GAP, memo=True, k=None, q=None):
+        self.job = job
+        self.k = job.k if k is None else k
+        self.q = job.q if q is None else q
+        self.tau_gap = tau_gap
+        self.memo = memo
+        self.cache: Dict[tuple, Module] = {}
+        self.records: List[Record] = []
+        self.n_leaf_ed = 0
+        self.n_merges = 0
+
+    # -- modules ---------------------------------------------------------
+    def leaf(self, a, b, level=0):
+        terms = ham.block_terms(self.job, a, b)
+        key = ("leaf", b - a, tuple((c, tuple((s - a, o) for s, o in ops)) for c, ops in terms))
+        if self.memo and key in self.cache:
+            return self.cache[key]
+        H = ham.block_hamiltonian(self.job, a, b)
+        E, V, k_eff, gap, _ = leaf_ed(H, self.k, self.tau_gap)
+        self.n_leaf_ed += 1
+        self.records.append(Record(level, b - a, "leaf", min(self.k, H.shape[0]), k_eff, gap))
+        mod = Module(key, b - a, E, V, k_eff, gap, "leaf")
+        if self.memo:
+            self.cache[key] = mod
+        return mod
+
+    def op(self, mod: Module, rel_site: int, opname: str) -> np.ndarray:
+        """Projected one-site operator at site rel_site of the module."""
+        kk = (rel_site, opname)
+        if kk in mod.ops:
+            return mod.ops[kk]
+        if mod.kind == "leaf":
+            o = project(mod.basis, ham.site_operator(mod.width, rel_site, opname))
+        else:
+            A, B = mod.left, mod.right
+            if rel_site < A.width:
+                o = transform_left(mod.basis, self.op(A, rel_site, opname), A.k_eff, B.k_eff)
+            else:
+                o = transform_right(mod.basis, self.op(B, rel_site - A.width, opname),
+                                    A.k_eff, B.k_eff)
+        mod.ops[kk] = o
+        return o
+
+    def merge(self, A: Module, a, B: Module, m, b, level, root=False):
+        cut = ham.cut_terms(self.job, a, m, b)
+        rel = tuple((c, s - a, oa, t - m, ob) for c, s, oa, t, ob in cut)
+        key = ("merge", A.key, B.key, rel, root)
+        if self.memo and key in self.cache:
+            return self.cache[key]
+        terms = [(c, self.op(A, sa, oa), self.op(B, sb, ob)) for c, sa, oa, sb, ob in rel]
+        self.n_merges += 1
+        if root:
+            w, _, _, _, _ = couple_solve(A.E, B.E, terms, None)
+            mod = Module(key, b - a, w, None, len(w), float("inf"), "root", A, B)
+        else:
+            w, E, U, k_eff, gap = couple_solve(A.E, B.E, terms, self.k, None, self.tau_gap)
+            self.records.append(Record(level, b - a, "merge", min(self.k, len(w)), k_eff, gap))
+            mod = Module(key, b - a, E, U, k_eff, gap, "merge", A, B)
+        if self.memo:
+            self.cache[key] = mod
+        return mod
+
+    # -- tree --------------------------------------------------------------
+    def run(self) -> Result:
+        L0 = self.job.leaf_sites
+        mods = [(self.leaf(a, a + L0), a, a + L0) for a in range(0, self.job.n_sites, L0)]
+        if len(mods) == 1:
+            H = ham.block_hamiltonian(self.job, 0, self.job.n_sites)
+            w = np.linalg.eigvalsh(H)
+            return Result(w[: self.q].copy(), self.records, self.n_leaf_ed, 0)
+        level = 0
+        while len(mods) > 1:
+            level += 1
+            nxt = []
+            last = len(mods) == 2
+            for i in range(0, len(mods) - 1, 2):
+                (A, a, m), (B, _, b) = mods[i], mods[i + 1]
+                nxt.append((self.merge(A, a, B, m, b, level, root=last), a, b))
+            if len(mods) % 2:
+                nxt.append(mods[-1])
+            mods = nxt
+        root = mods[0][0]
+        return Result(root.E[: self.q].copy(), self.records, self.n_leaf_ed, self.n_merges)
+
+
+def recurse(job, tau_gap=TAU_GAP, memo=True, k=None, q=None) -> Result:
+    """Lowest q energies of the job by the recursive module-coupling method."""
+    return Recursion(job, tau_gap, memo, k, q).run()
