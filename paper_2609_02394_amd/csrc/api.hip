@@ -1,0 +1,676 @@
+// librmc C ABI: context and arena, modules, leaf ED, operator projection, one
+// coupling step, and the recursion over a chain (Algorithm 1 of the paper).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <set>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "rmc_internal.h"
+
+namespace rmc {
+
+// ---------------------------------------------------------------------------
+// Arena
+// ---------------------------------------------------------------------------
+static constexpr size_t kAlign = 256;
+
+void Arena::init(char* base, size_t size) {
+  base_ = base;
+  size_ = size & ~(kAlign - 1);
+  free_.clear();
+  used_.clear();
+  if (size_) free_[0] = size_;
+  in_use_ = peak_ = 0;
+}
+
+void* Arena::alloc(size_t bytes) {
+  size_t need = (bytes + kAlign - 1) & ~(kAlign - 1);
+  if (need == 0) need = kAlign;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second >= need) {
+      size_t off = it->first, sz = it->second;
+      free_.erase(it);
+      if (sz > need) free_[off + need] = sz - need;
+      used_[off] = need;
+      in_use_ += need;
+      peak_ = std::max(peak_, in_use_);
+      return base_ + off;
+    }
+  }
+  throw Error(RMC_ERR_OOM, "device arena exhausted (" + std::to_string(bytes) + " bytes requested, " +
+                               std::to_string(size_ - in_use_) + " free)");
+}
+
+void Arena::release(void* p) {
+  if (!p) return;
+  size_t off = (size_t)((char*)p - base_);
+  auto it = used_.find(off);
+  if (it == used_.end()) return;
+  size_t sz = it->second;
+  used_.erase(it);
+  in_use_ -= sz;
+  auto nx = free_.lower_bound(off);
+  if (nx != free_.end() && nx->first == off + sz) {
+    sz += nx->second;
+    free_.erase(nx);
+  }
+  auto pv = free_.lower_bound(off);
+  if (pv != free_.begin()) {
+    --pv;
+    if (pv->first + pv->second == off) {
+      pv->second += sz;
+      return;
+    }
+  }
+  free_[off] = sz;
+}
+
+size_t Arena::largest_free() const {
+  size_t m = 0;
+  for (auto& kv : free_) m = std::max(m, kv.second);
+  return m;
+}
+
+}  // namespace rmc
+
+using namespace rmc;
+
+namespace {
+
+template <class F>
+rmc_status guard(rmc_ctx* ctx, F&& f) {
+  try {
+    f();
+    return RMC_OK;
+  } catch (const rmc::Error& e) {
+    if (ctx) ctx->last_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->last_error = e.what();
+    return RMC_ERR_STATE;
+  }
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+void sync(rmc_ctx* ctx) { RMC_HIP(hipStreamSynchronize(ctx->stream)); }
+
+void free_module_mem(rmc_ctx* ctx, rmc_module* m) {
+  ctx->arena.release(m->E);
+  m->E = nullptr;
+  ctx->arena.release(m->basis);
+  m->basis = nullptr;
+  for (auto& o : m->ops) ctx->arena.release(o.data);
+  m->ops.clear();
+}
+
+void validate_leaf(const rmc_leaf_desc* leaf) {
+  RMC_CHECK(leaf != nullptr, RMC_ERR_ARG, "null leaf descriptor");
+  RMC_CHECK(leaf->n_sites >= 1 && leaf->n_sites <= 12, RMC_ERR_ARG, "leaf n_sites must be 1..12");
+  RMC_CHECK(leaf->n_terms >= 0 && (leaf->n_terms == 0 || leaf->terms), RMC_ERR_ARG, "bad term list");
+  for (int t = 0; t < leaf->n_terms; ++t) {
+    const rmc_term& tm = leaf->terms[t];
+    RMC_CHECK(tm.nsite == 1 || tm.nsite == 2, RMC_ERR_ARG, "term nsite must be 1 or 2");
+    for (int u = 0; u < tm.nsite; ++u) {
+      RMC_CHECK(tm.site[u] >= 0 && tm.site[u] < leaf->n_sites, RMC_ERR_ARG, "term site out of range");
+      RMC_CHECK(tm.op[u] >= RMC_OP_X && tm.op[u] <= RMC_OP_Z, RMC_ERR_ARG, "unknown operator");
+    }
+    if (tm.nsite == 2) RMC_CHECK(tm.site[0] != tm.site[1], RMC_ERR_ARG, "two-site term on one site");
+  }
+}
+
+// Dense leaf H into device memory H (D x D).
+void assemble_leaf(rmc_ctx* ctx, const rmc_leaf_desc* leaf, double* H) {
+  std::vector<DevTerm> dt(std::max(1, leaf->n_terms));
+  for (int t = 0; t < leaf->n_terms; ++t) {
+    const rmc_term& tm = leaf->terms[t];
+    DevTerm d{};
+    d.coef = tm.coef;
+    d.nsite = tm.nsite;
+    for (int u = 0; u < tm.nsite; ++u) {
+      d.bit[u] = leaf->n_sites - 1 - tm.site[u];
+      d.op[u] = tm.op[u];
+    }
+    dt[t] = d;
+  }
+  Scratch sc(&ctx->arena);
+  DevTerm* dterms = sc.get<DevTerm>(dt.size());
+  RMC_HIP(hipMemcpyAsync(dterms, dt.data(), dt.size() * sizeof(DevTerm), hipMemcpyHostToDevice,
+                         ctx->stream));
+  leaf_assemble(ctx->stream, leaf->n_sites, leaf->n_terms, dterms, H);
+  sync(ctx);  // dterms is released at scope exit
+}
+
+// Lowest eigenpairs of a dense leaf; builds a module if `make_module`.
+rmc_module* leaf_solve(rmc_ctx* ctx, const rmc_leaf_desc* leaf, int k, int q_only,
+                       const rmc_solve_opts& o, std::vector<double>& evals, rmc_level_report* rep) {
+  double t0 = now_ms();
+  const int D = 1 << leaf->n_sites;
+  Scratch sc(&ctx->arena);
+  double* H = sc.get<double>((size_t)D * D);
+  assemble_leaf(ctx, leaf, H);
+  CoupledOp op;
+  op.kind = 0;
+  op.n = D;
+  op.H = H;
+  op.D = sc.get<double>(D);
+  double* rb = sc.get<double>(D);
+  double* bmax = sc.get<double>(1);
+  dense_diag(ctx->stream, D, H, op.D, rb);
+  vec_max(ctx->stream, D, rb, bmax);
+  RMC_HIP(hipMemcpyAsync(&op.bup, bmax, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  sync(ctx);
+  const int k_req = std::min(k, D);
+  int nev = q_only > 0 ? std::min(q_only, D) : std::min(D, k_req + 1);
+  double* X = sc.get<double>((size_t)nev * D);
+  SolveStats st;
+  rmc_solve_opts oo = o;
+  oo.precision = RMC_FP64;
+  int status = eig_lowest(ctx, op, nev, oo, X, evals, st);
+  if (rep) {
+    rep->iters = st.iters;
+    rep->matvecs = st.matvecs;
+    rep->max_res = st.max_res;
+    rep->k_req = k_req;
+  }
+  if (status != RMC_OK) throw Error((rmc_status)status, "leaf eigensolver did not converge");
+  if (q_only > 0) {
+    if (rep) rep->ms = now_ms() - t0;
+    return nullptr;
+  }
+  double gap = INFINITY;
+  int k_eff = gap_cut(evals, k_req, o.gap_tol > 0 ? o.gap_tol : 1e-6, &gap);
+  rmc_module* m = new rmc_module();
+  m->kind = 0;
+  m->n_sites = leaf->n_sites;
+  m->dim = D;
+  m->k_eff = k_eff;
+  m->gap = gap;
+  m->E_host.assign(evals.begin(), evals.begin() + k_eff);
+  try {
+    m->E = (double*)ctx->arena.alloc(k_eff * sizeof(double));
+    m->basis = (double*)ctx->arena.alloc((size_t)k_eff * D * sizeof(double));
+  } catch (...) {
+    free_module_mem(ctx, m);
+    delete m;
+    throw;
+  }
+  RMC_HIP(hipMemcpyAsync(m->E, m->E_host.data(), k_eff * sizeof(double), hipMemcpyHostToDevice,
+                         ctx->stream));
+  copy_rows(ctx->stream, k_eff, D, X, D, m->basis, D);
+  sync(ctx);
+  ctx->modules.push_back(m);
+  if (rep) {
+    rep->k_eff = k_eff;
+    rep->gap = gap;
+    rep->ms = now_ms() - t0;
+  }
+  return m;
+}
+
+int find_op(const rmc_module* m, int site, int op) {
+  for (size_t i = 0; i < m->ops.size(); ++i)
+    if (m->ops[i].site == site && m->ops[i].op == op) return (int)i;
+  return -1;
+}
+
+// Projected operator of (site, op) on module m; returns its id (index in m->ops).
+int project_op(rmc_ctx* ctx, rmc_module* m, int site, int op) {
+  int id = find_op(m, site, op);
+  if (id >= 0) return id;
+  RMC_CHECK(site >= 0 && site < m->n_sites, RMC_ERR_ARG, "operator site outside the module");
+  RMC_CHECK(op >= RMC_OP_X && op <= RMC_OP_Z, RMC_ERR_ARG, "unknown operator");
+  RMC_CHECK(m->basis != nullptr, RMC_ERR_STATE, "module basis already freed");
+  hipStream_t s = ctx->stream;
+  const int k = m->k_eff, n = m->dim;
+  double* o = (double*)ctx->arena.alloc((size_t)k * k * sizeof(double));
+  try {
+    Scratch sc(&ctx->arena);
+    double* W = sc.get<double>((size_t)k * n);
+    if (m->kind == 0) {
+      // W_j = O v_j, o = V W^T
+      site_op_apply(s, k, m->n_sites, m->n_sites - 1 - site, op, m->basis, W);
+    } else {
+      const int kA = m->kA, kB = m->kB;
+      if (site < m->A->n_sites) {
+        int ida = project_op(ctx, m->A, site, op);
+        const double* oA = m->A->ops[ida].data;
+        // Z_nu = o_A C_nu (kA x kA times kA x kB), batched over nu
+        gemm_f64(s, false, false, kA, kB, kA, 1.0, oA, kA, 0, m->basis, kB, n, 0.0, W, kB, n, k, 1,
+                 nullptr);
+      } else {
+        int idb = project_op(ctx, m->B, site - m->A->n_sites, op);
+        const double* oB = m->B->ops[idb].data;
+        // Z_nu = C_nu o_B^T
+        gemm_f64(s, false, true, kA, kB, kB, 1.0, m->basis, kB, n, oB, kB, 0, 0.0, W, kB, n, k, 1,
+                 nullptr);
+      }
+    }
+    double* kw = sc.get<double>((size_t)64 * k * k + 64);
+    gemm_f64(s, false, true, k, k, n, 1.0, m->basis, n, 0, W, n, 0, 0.0, o, k, 0, 1,
+             gemm_pick_ksplit(k, k, n, 1), kw);
+    sync(ctx);
+  } catch (...) {
+    ctx->arena.release(o);
+    throw;
+  }
+  m->ops.push_back({site, op, o});
+  return (int)m->ops.size() - 1;
+}
+
+// One coupling step; out module optional.
+rmc_module* couple(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_bond_desc* bond,
+                   int k_keep, int q, const rmc_solve_opts& o, bool want_module,
+                   std::vector<double>& evals, rmc_level_report* rep) {
+  double t0 = now_ms();
+  RMC_CHECK(A && B && bond, RMC_ERR_ARG, "null argument");
+  RMC_CHECK(A->E && B->E, RMC_ERR_STATE, "module freed");
+  const int T = bond->n_terms;
+  RMC_CHECK(T >= 0 && (T == 0 || (bond->coef && bond->opA && bond->opB)), RMC_ERR_ARG, "bad bond");
+  const int kA = A->k_eff, kB = B->k_eff, n = kA * kB;
+  RMC_CHECK(kA <= 256 && kB <= 256, RMC_ERR_ARG, "module dimension above 256");
+  if (want_module) RMC_CHECK(k_keep >= 1 && q <= k_keep, RMC_ERR_ARG, "need 1 <= q <= k_keep");
+  RMC_CHECK(q >= 1, RMC_ERR_ARG, "q must be >= 1");
+  for (int i = 0; i < T; ++i) {
+    RMC_CHECK(bond->opA[i] >= 0 && bond->opA[i] < (int)A->ops.size(), RMC_ERR_ARG, "bad opA id");
+    RMC_CHECK(bond->opB[i] >= 0 && bond->opB[i] < (int)B->ops.size(), RMC_ERR_ARG, "bad opB id");
+    RMC_CHECK(std::isfinite(bond->coef[i]), RMC_ERR_ARG, "non-finite coupling coefficient");
+  }
+  hipStream_t s = ctx->stream;
+  Scratch sc(&ctx->arena);
+  CoupledOp op;
+  op.kind = 1;
+  op.n = n;
+  op.kA = kA;
+  op.kB = kB;
+  op.T = T;
+  op.EA = A->E;
+  op.EB = B->E;
+  op.coef.assign(bond->coef, bond->coef + T);
+  op.coef_dev = sc.get<double>(std::max(T, 1));
+  op.OAcat = sc.get<double>((size_t)std::max(T, 1) * kA * kA);
+  op.OBcat = sc.get<double>((size_t)std::max(T, 1) * kB * kB);
+  op.Ediag = sc.get<double>(n);
+  op.D = sc.get<double>(n);
+  if (T > 0)
+    RMC_HIP(hipMemcpyAsync(op.coef_dev, bond->coef, T * sizeof(double), hipMemcpyHostToDevice, s));
+  double csum = 0.0;
+  for (int i = 0; i < T; ++i) {
+    RMC_HIP(hipMemcpyAsync(op.OAcat + (size_t)i * kA * kA, A->ops[bond->opA[i]].data,
+                           (size_t)kA * kA * sizeof(double), hipMemcpyDeviceToDevice, s));
+    RMC_HIP(hipMemcpyAsync(op.OBcat + (size_t)i * kB * kB, B->ops[bond->opB[i]].data,
+                           (size_t)kB * kB * sizeof(double), hipMemcpyDeviceToDevice, s));
+    csum += std::fabs(bond->coef[i]);
+  }
+  kron_diag(s, kA, kB, A->E, B->E, T, op.coef_dev, op.OAcat, op.OBcat, op.D, op.Ediag);
+  // projected one-site Pauli operators have spectral norm <= 1
+  double emax = A->E_host.back() + B->E_host.back();
+  op.bup = emax + csum + 1e-12 * (std::fabs(emax) + csum + 1.0);
+  op.precision = o.precision;
+
+  const int k_req = std::min(k_keep, n);
+  int nev = want_module ? std::min(n, k_req + 1) : std::min(q, n);
+  nev = std::max(nev, std::min(q, n));
+  double* X = sc.get<double>((size_t)nev * n);
+  SolveStats st;
+  int status = eig_lowest(ctx, op, nev, o, X, evals, st);
+  if (rep) {
+    rep->iters = st.iters;
+    rep->matvecs = st.matvecs;
+    rep->max_res = st.max_res;
+    rep->k_req = k_req;
+    rep->gap = INFINITY;
+    rep->k_eff = 0;
+  }
+  if (status != RMC_OK) throw Error((rmc_status)status, "coupled eigensolver did not converge");
+  rmc_module* m = nullptr;
+  if (want_module) {
+    double gap = INFINITY;
+    int k_eff = gap_cut(evals, k_req, o.gap_tol > 0 ? o.gap_tol : 1e-6, &gap);
+    m = new rmc_module();
+    m->kind = 1;
+    m->n_sites = A->n_sites + B->n_sites;
+    m->dim = n;
+    m->k_eff = k_eff;
+    m->kA = kA;
+    m->kB = kB;
+    m->A = A;
+    m->B = B;
+    m->gap = gap;
+    m->E_host.assign(evals.begin(), evals.begin() + k_eff);
+    try {
+      m->E = (double*)ctx->arena.alloc(k_eff * sizeof(double));
+      m->basis = (double*)ctx->arena.alloc((size_t)k_eff * n * sizeof(double));
+    } catch (...) {
+      free_module_mem(ctx, m);
+      delete m;
+      throw;
+    }
+    RMC_HIP(hipMemcpyAsync(m->E, m->E_host.data(), k_eff * sizeof(double), hipMemcpyHostToDevice, s));
+    copy_rows(s, k_eff, n, X, n, m->basis, n);
+    sync(ctx);
+    ctx->modules.push_back(m);
+    if (rep) {
+      rep->k_eff = k_eff;
+      rep->gap = gap;
+    }
+  }
+  if (rep) rep->ms = now_ms() - t0;
+  return m;
+}
+
+}  // namespace
+
+namespace rmc {
+void linalg_set_attrs();
+void kron_set_attrs();
+
+rmc_module* api_leaf_solve(rmc_ctx* ctx, const rmc_leaf_desc* leaf, int k, int q_only,
+                           const rmc_solve_opts& o, std::vector<double>& evals, rmc_level_report* rep) {
+  return leaf_solve(ctx, leaf, k, q_only, o, evals, rep);
+}
+int api_project_op(rmc_ctx* ctx, rmc_module* m, int site, int op) {
+  return project_op(ctx, m, site, op);
+}
+rmc_module* api_couple(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_bond_desc* bond,
+                       int k_keep, int q, const rmc_solve_opts& o, bool want_module,
+                       std::vector<double>& evals, rmc_level_report* rep) {
+  return couple(ctx, A, B, bond, k_keep, q, o, want_module, evals, rep);
+}
+void api_release_basis(rmc_ctx* ctx, rmc_module* m) {
+  ctx->arena.release(m->basis);
+  m->basis = nullptr;
+}
+void api_free_module(rmc_ctx* ctx, rmc_module* m) {
+  auto it = std::find(ctx->modules.begin(), ctx->modules.end(), m);
+  if (it != ctx->modules.end()) ctx->modules.erase(it);
+  free_module_mem(ctx, m);
+  delete m;
+}
+}  // namespace rmc
+
+static void set_kernel_attrs() {
+  static bool done = false;
+  if (done) return;
+  rmc::linalg_set_attrs();
+  rmc::kron_set_attrs();
+  done = true;
+}
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void rmc_default_opts(rmc_solve_opts* o) {
+  if (!o) return;
+  o->precision = RMC_FP64;
+  o->tol = 1e-13;
+  o->gap_tol = 1e-6;
+  o->max_iter = 200;
+  o->guard = 0;
+  o->max_degree = 0;
+  o->seed = 0x2609023940ull;
+}
+
+rmc_status rmc_create(rmc_ctx** out, int device, void* arena_dev, size_t arena_bytes,
+                      void* hip_stream) {
+  if (!out) return RMC_ERR_ARG;
+  rmc_ctx* ctx = new rmc_ctx();
+  rmc_status st = guard(ctx, [&] {
+    RMC_HIP(hipSetDevice(device));
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    RMC_CHECK(arena_bytes >= (1u << 20), RMC_ERR_ARG, "arena must be at least 1 MiB");
+    if (arena_dev) {
+      ctx->arena_mem = arena_dev;
+      ctx->own_arena = false;
+    } else {
+      RMC_HIP(hipMalloc(&ctx->arena_mem, arena_bytes));
+      ctx->own_arena = true;
+    }
+    RMC_CHECK(((uintptr_t)ctx->arena_mem & 255) == 0, RMC_ERR_ARG, "arena must be 256-byte aligned");
+    ctx->arena.init((char*)ctx->arena_mem, arena_bytes);
+    set_kernel_attrs();
+  });
+  if (st != RMC_OK) {
+    fprintf(stderr, "rmc_create: %s\n", ctx->last_error.c_str());
+    if (ctx->own_arena && ctx->arena_mem) hipFree(ctx->arena_mem);
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return RMC_OK;
+}
+
+rmc_status rmc_destroy(rmc_ctx* ctx) {
+  if (!ctx) return RMC_ERR_ARG;
+  hipStreamSynchronize(ctx->stream);
+  for (rmc_module* m : ctx->modules) delete m;
+  ctx->modules.clear();
+  if (ctx->own_arena && ctx->arena_mem) hipFree(ctx->arena_mem);
+  delete ctx;
+  return RMC_OK;
+}
+
+const char* rmc_last_error(const rmc_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null ctx"; }
+
+rmc_status rmc_arena_usage(const rmc_ctx* ctx, size_t* in_use, size_t* peak) {
+  if (!ctx) return RMC_ERR_ARG;
+  if (in_use) *in_use = ctx->arena.in_use();
+  if (peak) *peak = ctx->arena.peak();
+  return RMC_OK;
+}
+
+rmc_status rmc_module_ed(rmc_ctx* ctx, const rmc_leaf_desc* leaf, int k, const rmc_solve_opts* opts,
+                         rmc_module** out) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    validate_leaf(leaf);
+    RMC_CHECK(k >= 1, RMC_ERR_ARG, "k must be >= 1");
+    RMC_CHECK(out != nullptr, RMC_ERR_ARG, "null output");
+    rmc_solve_opts o;
+    rmc_default_opts(&o);
+    if (opts) o = *opts;
+    std::vector<double> ev;
+    *out = leaf_solve(ctx, leaf, k, 0, o, ev, nullptr);
+  });
+}
+
+rmc_status rmc_project_ops(rmc_ctx* ctx, rmc_module* m, int n_ops, const int* site, const int* op,
+                           int* op_ids) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    RMC_CHECK(m && n_ops >= 0 && (n_ops == 0 || (site && op && op_ids)), RMC_ERR_ARG, "bad arguments");
+    std::vector<int> ids(n_ops);
+    for (int i = 0; i < n_ops; ++i) ids[i] = project_op(ctx, m, site[i], op[i]);
+    for (int i = 0; i < n_ops; ++i) op_ids[i] = ids[i];
+  });
+}
+
+rmc_status rmc_couple_solve(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_bond_desc* bond,
+                            int k_keep, int q, const rmc_solve_opts* opts, rmc_module** out,
+                            double* energies, rmc_level_report* rep) {
+  if (!ctx) return RMC_ERR_ARG;
+  rmc_level_report r{};
+  std::vector<double> ev;
+  rmc_status st = guard(ctx, [&] {
+    rmc_solve_opts o;
+    rmc_default_opts(&o);
+    if (opts) o = *opts;
+    RMC_CHECK(o.precision >= RMC_FP64 && o.precision <= RMC_BF16, RMC_ERR_ARG, "bad precision");
+    rmc_module* m = couple(ctx, A, B, bond, k_keep, q, o, out != nullptr, ev, &r);
+    if (out) *out = m;
+  });
+  if ((st == RMC_OK || st == RMC_ERR_NOCONV) && energies && !ev.empty())
+    for (int i = 0; i < q && i < (int)ev.size(); ++i) energies[i] = ev[i];
+  r.kind = out ? 1 : 2;
+  if (rep && (st == RMC_OK || st == RMC_ERR_NOCONV)) *rep = r;
+  return st;
+}
+
+rmc_status rmc_module_info(const rmc_module* m, int* k_eff, int* dim, int* n_sites, double* energies) {
+  if (!m) return RMC_ERR_ARG;
+  if (k_eff) *k_eff = m->k_eff;
+  if (dim) *dim = m->dim;
+  if (n_sites) *n_sites = m->n_sites;
+  if (energies) memcpy(energies, m->E_host.data(), m->E_host.size() * sizeof(double));
+  return RMC_OK;
+}
+
+rmc_status rmc_module_basis(rmc_ctx* ctx, const rmc_module* m, double* basis_host) {
+  if (!ctx || !m || !basis_host) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    RMC_CHECK(m->basis != nullptr, RMC_ERR_STATE, "module basis freed");
+    RMC_HIP(hipMemcpyAsync(basis_host, m->basis, (size_t)m->k_eff * m->dim * sizeof(double),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+  });
+}
+
+rmc_status rmc_module_op(rmc_ctx* ctx, const rmc_module* m, int op_id, double* op_host) {
+  if (!ctx || !m || !op_host) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    RMC_CHECK(op_id >= 0 && op_id < (int)m->ops.size(), RMC_ERR_ARG, "bad op id");
+    RMC_HIP(hipMemcpyAsync(op_host, m->ops[op_id].data, (size_t)m->k_eff * m->k_eff * sizeof(double),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+  });
+}
+
+rmc_status rmc_module_free(rmc_ctx* ctx, rmc_module* m) {
+  if (!ctx || !m) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    hipStreamSynchronize(ctx->stream);
+    auto it = std::find(ctx->modules.begin(), ctx->modules.end(), m);
+    RMC_CHECK(it != ctx->modules.end(), RMC_ERR_ARG, "module not owned by this context");
+    for (rmc_module* o : ctx->modules)
+      if (o->A == m || o->B == m) {
+        if (o->A == m) o->A = nullptr;
+        if (o->B == m) o->B = nullptr;
+      }
+    free_module_mem(ctx, m);
+    ctx->modules.erase(it);
+    delete m;
+  });
+}
+
+rmc_status rmc_module_import(rmc_ctx* ctx, int n_sites, int k, int dim, const double* E_host,
+                             const double* basis_host, int n_ops, const int* sites, const int* ops,
+                             const double* op_data, rmc_module** out) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    RMC_CHECK(out && E_host && k >= 1 && dim >= k && n_sites >= 1 && n_ops >= 0, RMC_ERR_ARG,
+              "bad import arguments");
+    RMC_CHECK(n_ops == 0 || (sites && ops && op_data), RMC_ERR_ARG, "null operator arrays");
+    for (int i = 1; i < k; ++i) RMC_CHECK(E_host[i] >= E_host[i - 1], RMC_ERR_ARG, "E not ascending");
+    rmc_module* m = new rmc_module();
+    m->kind = (n_sites <= 12 && dim == (1 << n_sites)) ? 0 : 1;
+    m->n_sites = n_sites;
+    m->dim = dim;
+    m->k_eff = k;
+    m->gap = INFINITY;
+    m->E_host.assign(E_host, E_host + k);
+    try {
+      m->E = (double*)ctx->arena.alloc(k * sizeof(double));
+      RMC_HIP(hipMemcpyAsync(m->E, E_host, k * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+      if (basis_host && m->kind == 0) {
+        m->basis = (double*)ctx->arena.alloc((size_t)k * dim * sizeof(double));
+        RMC_HIP(hipMemcpyAsync(m->basis, basis_host, (size_t)k * dim * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+      }
+      for (int i = 0; i < n_ops; ++i) {
+        RMC_CHECK(sites[i] >= 0 && sites[i] < n_sites, RMC_ERR_ARG, "operator site out of range");
+        RMC_CHECK(ops[i] >= RMC_OP_X && ops[i] <= RMC_OP_Z, RMC_ERR_ARG, "unknown operator");
+        double* o = (double*)ctx->arena.alloc((size_t)k * k * sizeof(double));
+        m->ops.push_back({sites[i], ops[i], o});
+        RMC_HIP(hipMemcpyAsync(o, op_data + (size_t)i * k * k, (size_t)k * k * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+      }
+      sync(ctx);
+    } catch (...) {
+      free_module_mem(ctx, m);
+      delete m;
+      throw;
+    }
+    ctx->modules.push_back(m);
+    *out = m;
+  });
+}
+
+rmc_status rmc_leaf_hamiltonian(rmc_ctx* ctx, const rmc_leaf_desc* leaf, double* H_dev) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    validate_leaf(leaf);
+    RMC_CHECK(H_dev != nullptr, RMC_ERR_ARG, "null output");
+    assemble_leaf(ctx, leaf, H_dev);
+  });
+}
+
+rmc_status rmc_kron_apply(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_bond_desc* bond,
+                          int precision, int n_vec, const double* X_dev, double* Y_dev) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    RMC_CHECK(A && B && bond && X_dev && Y_dev && n_vec >= 0, RMC_ERR_ARG, "bad arguments");
+    RMC_CHECK(precision >= RMC_FP64 && precision <= RMC_BF16, RMC_ERR_ARG, "bad precision");
+    const int T = bond->n_terms, kA = A->k_eff, kB = B->k_eff, n = kA * kB;
+    RMC_CHECK(kA <= 256 && kB <= 256, RMC_ERR_ARG, "module dimension above 256");
+    for (int i = 0; i < T; ++i) {
+      RMC_CHECK(bond->opA[i] >= 0 && bond->opA[i] < (int)A->ops.size(), RMC_ERR_ARG, "bad opA id");
+      RMC_CHECK(bond->opB[i] >= 0 && bond->opB[i] < (int)B->ops.size(), RMC_ERR_ARG, "bad opB id");
+    }
+    hipStream_t s = ctx->stream;
+    Scratch sc(&ctx->arena);
+    CoupledOp op;
+    op.kind = 1;
+    op.n = n;
+    op.kA = kA;
+    op.kB = kB;
+    op.T = T;
+    op.coef.assign(bond->coef, bond->coef + T);
+    op.coef_dev = sc.get<double>(std::max(T, 1));
+    op.OAcat = sc.get<double>((size_t)std::max(T, 1) * kA * kA);
+    op.OBcat = sc.get<double>((size_t)std::max(T, 1) * kB * kB);
+    op.Ediag = sc.get<double>(n);
+    if (T > 0)
+      RMC_HIP(hipMemcpyAsync(op.coef_dev, bond->coef, T * sizeof(double), hipMemcpyHostToDevice, s));
+    for (int i = 0; i < T; ++i) {
+      RMC_HIP(hipMemcpyAsync(op.OAcat + (size_t)i * kA * kA, A->ops[bond->opA[i]].data,
+                             (size_t)kA * kA * sizeof(double), hipMemcpyDeviceToDevice, s));
+      RMC_HIP(hipMemcpyAsync(op.OBcat + (size_t)i * kB * kB, B->ops[bond->opB[i]].data,
+                             (size_t)kB * kB * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    kron_diag(s, kA, kB, A->E, B->E, T, op.coef_dev, op.OAcat, op.OBcat, nullptr, op.Ediag);
+    op_apply(ctx, op, n_vec, X_dev, Y_dev, nullptr, 1.0, 0.0, 0.0, nullptr, nullptr, precision);
+    sync(ctx);
+  });
+}
+
+rmc_status rmc_sym_eig(rmc_ctx* ctx, int batch, int m, const double* A_dev, double* evals_dev,
+                       double* V_dev) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    RMC_CHECK(batch >= 0 && m >= 1 && m <= jacobi_max_m(), RMC_ERR_ARG, "m must be 1..192");
+    RMC_CHECK(A_dev && evals_dev && V_dev, RMC_ERR_ARG, "null pointer");
+    if (batch == 0) return;
+    Scratch sc(&ctx->arena);
+    double* Vw = sc.get<double>((size_t)batch * m * m);
+    int* info = sc.get<int>(batch);
+    jacobi_eig(ctx->stream, batch, m, A_dev, (long)m * m, evals_dev, m, V_dev, (long)m * m, Vw, info);
+    sync(ctx);
+  });
+}
+
+}  // extern "C"

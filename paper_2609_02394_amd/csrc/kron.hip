@@ -1,0 +1,263 @@
+// Kronecker-sum matvec of one coupling step (the effective Hamiltonian of the
+// assembled effective-Hamiltonian equation applied without forming it):
+//
+//   out_j = s1 * ( sum_i c_i O_A^i Y_j (O_B^i)^T + (E_A[a] + E_B[b]) .* Y_j )
+//         + s2 * Y_j + s3 * Xprev_j
+//
+// for a block of vectors Y_j, each a k_A x k_B row-major coefficient matrix.
+// (A (x) B) vec(X) = vec(A X B^T) for row-major vec, so this is exactly H_eff Y_j.
+//
+// One workgroup (4 waves) owns one vector j and one 16-wide column tile
+// [b0, b0+16) of the output:
+//   stage 1: Z_i[:, tile] = Y_j (O_B^i[tile, :])^T   (k_A x 16, K = k_B) -> LDS
+//   stage 2: acc[:, tile] = sum_i c_i O_A^i Z_i[:, tile]     (K = k_A)
+//   epilogue: scale, diagonal, Chebyshev three-term recurrence, store FP64.
+// Each wave owns the 16-row tiles w, w+4, ... in both stages. Operands come from
+// global memory (L2-resident at these sizes); the MFMA K index is permuted so that
+// every lane reads contiguous elements: within a K step, lane group g = lane/16
+// takes a contiguous run of K instead of every fourth element (the sum over K is
+// order-free up to rounding).
+//
+// Precisions: FP64 (v_mfma_f64_16x16x4_f64), FP32 (v_mfma_f32_16x16x4_f32) and
+// BF16 inputs with FP32 accumulation (v_mfma_f32_16x16x32_bf16). Storage stays
+// FP64; low precision applies to the products and their accumulation.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "rmc_internal.h"
+
+namespace rmc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int KR_TCH = 4;  // terms per LDS chunk
+
+template <int P>
+struct KTraits;
+template <>
+struct KTraits<0> {  // FP64
+  static constexpr int KS = 4;  // K per MFMA
+  typedef double zt;
+  typedef d4 acc;
+};
+template <>
+struct KTraits<1> {  // FP32
+  static constexpr int KS = 4;
+  typedef float zt;
+  typedef f4 acc;
+};
+template <>
+struct KTraits<2> {  // BF16 in, FP32 accumulate
+  static constexpr int KS = 32;
+  typedef float zt;
+  typedef f4 acc;
+};
+
+// Row of accumulator register r in lane group g: the FP64 16x16x4 instruction
+// places D[4r+g][lane%16] in register r, the FP32 and BF16 ones D[4g+r][lane%16].
+template <int P>
+__device__ inline int acc_row(int g, int r) {
+  return P == 0 ? 4 * r + g : 4 * g + r;
+}
+
+__device__ inline double ld_or0(const double* __restrict__ p, bool ok) { return ok ? *p : 0.0; }
+
+// One MFMA step. a_run/b_run: the lane's contiguous K run (length L = KS/4 for
+// FP64/FP32 -> 1 element per MFMA, 8 for BF16).
+template <int P>
+struct Mfma;
+template <>
+struct Mfma<0> {
+  __device__ static inline d4 step(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<1> {
+  __device__ static inline f4 step(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<2> {
+  __device__ static inline f4 step(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// acc += A(rows r0.., K) * B(K, cols) with A(i,k) = Arow(i)[k] (row-major, ld lda,
+// rows < M, k < K) scaled by `scale`, and B(k,j) supplied by a functor.
+template <int P, class BFn>
+__device__ inline typename KTraits<P>::acc mma_tile(typename KTraits<P>::acc acc,
+                                                    const double* __restrict__ A, int lda, int row,
+                                                    bool row_ok, int K, double scale, BFn bfn) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+  if constexpr (P == 0 || P == 1) {
+    // K step of 16: lane group g takes k = kb + 4g + s, s = 0..3
+    for (int kb = 0; kb < K; kb += 16) {
+      const int k0 = kb + 4 * g;
+      double av[4], bv[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = k0 + s;
+        const bool ok = k < K;
+        av[s] = ld_or0(A + (long)row * lda + k, ok && row_ok) * scale;
+        bv[s] = ok ? bfn(k) : 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if constexpr (P == 0)
+          acc = Mfma<0>::step(av[s], bv[s], acc);
+        else
+          acc = Mfma<1>::step((float)av[s], (float)bv[s], acc);
+      }
+    }
+  } else {
+    // K step of 32: lane group g takes k = kb + 8g + s, s = 0..7
+    for (int kb = 0; kb < K; kb += 32) {
+      const int k0 = kb + 8 * g;
+      bf8 a8, b8;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int k = k0 + s;
+        const bool ok = k < K;
+        float av = (float)(ld_or0(A + (long)row * lda + k, ok && row_ok) * scale);
+        float bv = ok ? (float)bfn(k) : 0.0f;
+        a8[s] = (__bf16)av;
+        b8[s] = (__bf16)bv;
+      }
+      acc = Mfma<2>::step(a8, b8, acc);
+    }
+  }
+  return acc;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void kron_fused_kernel(
+    int kA, int kB, int T, const double* __restrict__ coef, const double* __restrict__ OA,
+    const double* __restrict__ OB, const double* __restrict__ Ediag, const double* __restrict__ Y,
+    const double* __restrict__ Xprev, double* __restrict__ out, double s1, double s2, double s3) {
+  typedef typename KTraits<P>::zt zt;
+  typedef typename KTraits<P>::acc accT;
+  extern __shared__ char smem_raw[];
+  zt* Zs = reinterpret_cast<zt*>(smem_raw);  // [KR_TCH][kApad][16]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int b0 = blockIdx.x * 16;
+  const int j = blockIdx.y;
+  const int n = kA * kB;
+  const int RT = (kA + 15) >> 4;
+  const int kApad = RT * 16;
+  const double* Yj = Y + (long)j * n;
+
+  constexpr int MAXRT = 4;  // row tiles per wave (kA <= 256)
+  accT acc[MAXRT];
+#pragma unroll
+  for (int t = 0; t < MAXRT; ++t) acc[t] = accT{0, 0, 0, 0};
+
+  for (int t0 = 0; t0 < T; t0 += KR_TCH) {
+    const int tn = min(KR_TCH, T - t0);
+    // stage 1: Z_i = Y_j (O_B^i[tile,:])^T, rows = a, cols = tile, K = kB
+    for (int ti = 0; ti < tn; ++ti) {
+      const double* OBi = OB + (long)(t0 + ti) * kB * kB;
+      const int bcol = b0 + l16;
+      const bool bok = bcol < kB;
+#pragma unroll
+      for (int q = 0; q < MAXRT; ++q) {
+        const int rt = wave + 4 * q;
+        if (rt >= RT) break;
+        const int row = rt * 16 + l16;
+        accT z = accT{0, 0, 0, 0};
+        z = mma_tile<P>(z, Yj, kB, row, row < kA, kB, 1.0,
+                        [&](int k) -> double { return bok ? OBi[(long)bcol * kB + k] : 0.0; });
+        zt* Zt = Zs + ((long)ti * kApad) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Zt[(rt * 16 + acc_row<P>(g, r)) * 16 + l16] = (zt)z[r];
+      }
+    }
+    __syncthreads();
+    // stage 2: acc += c_i O_A^i Z_i
+    for (int ti = 0; ti < tn; ++ti) {
+      const double* OAi = OA + (long)(t0 + ti) * kA * kA;
+      const double ci = coef[t0 + ti];
+      const zt* Zt = Zs + ((long)ti * kApad) * 16;
+#pragma unroll
+      for (int q = 0; q < MAXRT; ++q) {
+        const int rt = wave + 4 * q;
+        if (rt >= RT) break;
+        const int row = rt * 16 + l16;
+        acc[q] = mma_tile<P>(acc[q], OAi, kA, row, row < kA, kA, ci,
+                             [&](int k) -> double { return (double)Zt[k * 16 + l16]; });
+      }
+    }
+    __syncthreads();
+  }
+  // epilogue: register r of each row tile holds row acc_row<P>(g, r), column l16
+  const int col = b0 + l16;
+  if (col >= kB) return;
+  const double* Xp = Xprev ? Xprev + (long)j * n : nullptr;
+  double* oj = out + (long)j * n;
+#pragma unroll
+  for (int q = 0; q < MAXRT; ++q) {
+    const int rt = wave + 4 * q;
+    if (rt >= RT) break;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = rt * 16 + acc_row<P>(g, r);
+      if (row >= kA) continue;
+      const long idx = (long)row * kB + col;
+      const double y = Yj[idx];
+      double v = s1 * ((double)acc[q][r] + Ediag[idx] * y) + s2 * y;
+      if (Xp) v += s3 * Xp[idx];
+      oj[idx] = v;
+    }
+  }
+}
+
+static size_t kron_lds_bytes(int kA, int prec) {
+  int kApad = ((kA + 15) / 16) * 16;
+  size_t el = prec == 0 ? sizeof(double) : sizeof(float);
+  return (size_t)KR_TCH * kApad * 16 * el;
+}
+
+int kron_max_k() { return 256; }
+
+void kron_set_attrs() {
+  const int lds = 160 * 1024 - 1024;
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_fused_kernel<0>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_fused_kernel<1>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_fused_kernel<2>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+// out = s1 * H Y + s2 * Y + s3 * Xprev, fused kernel, precision 0/1/2.
+void kron_apply_fused(hipStream_t s, const CoupledOp& op, int nv, const double* Y, double* out,
+                      const double* Xprev, double s1, double s2, double s3, int precision) {
+  if (nv <= 0) return;
+  dim3 grid((op.kB + 15) / 16, nv);
+  size_t lds = kron_lds_bytes(op.kA, precision);
+  const double* xp = (s3 != 0.0) ? Xprev : nullptr;
+  switch (precision) {
+    case RMC_FP64:
+      hipLaunchKernelGGL(kron_fused_kernel<0>, grid, dim3(256), lds, s, op.kA, op.kB, op.T,
+                         op.coef_dev, op.OAcat, op.OBcat, op.Ediag, Y, xp, out, s1, s2, s3);
+      break;
+    case RMC_FP32:
+      hipLaunchKernelGGL(kron_fused_kernel<1>, grid, dim3(256), lds, s, op.kA, op.kB, op.T,
+                         op.coef_dev, op.OAcat, op.OBcat, op.Ediag, Y, xp, out, s1, s2, s3);
+      break;
+    default:
+      hipLaunchKernelGGL(kron_fused_kernel<2>, grid, dim3(256), lds, s, op.kA, op.kB, op.T,
+                         op.coef_dev, op.OAcat, op.OBcat, op.Ediag, Y, xp, out, s1, s2, s3);
+      break;
+  }
+}
+
+}  // namespace rmc

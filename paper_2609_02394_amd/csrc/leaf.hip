@@ -1,0 +1,174 @@
+// Leaf-module kernels: bit-index assembly of the dense leaf Hamiltonian, one-site
+// operator application (for the projected boundary operators o = V^T O V),
+// diagonals of the coupled operator, and the eigensolver's start block.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rmc_kernels.h"
+
+namespace rmc {
+
+// Matrix element <br|O|bc> of a one-site operator for row bit br (column bit
+// bc = br ^ 1 for X and T, bc = br for Z): X -> 1; T = [[0,-1],[1,0]] -> -1 if
+// br == 0 else +1; Z -> +1 if br == 0 else -1.
+__device__ inline bool op_flips(int op) { return op != 3; }
+
+__device__ inline double op_sign(int op, int br) {
+  if (op == 1) return 1.0;
+  if (op == 2) return br == 0 ? -1.0 : 1.0;
+  return br == 0 ? 1.0 : -1.0;
+}
+
+// Zero fill, coalesced.
+__global__ void fill_zero_kernel(long n, double* __restrict__ p) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+    p[t] = 0.0;
+}
+
+// One thread per basis row r: for every term, in list order, find the column
+// c = r with the bits of X/T sites flipped and add coef * (product of +-1 factors)
+// to H[r][c]. Each entry is accumulated in term order from +0.0, exactly as a
+// dense sum of Kronecker products would be.
+__global__ void leaf_assemble_kernel(int D, int n_terms, const DevTerm* __restrict__ terms,
+                                     double* __restrict__ H) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  double* row = H + (long)r * D;
+  for (int t = 0; t < n_terms; ++t) {
+    DevTerm tm = terms[t];
+    int c = r;
+    double sgn = 1.0;
+    for (int u = 0; u < tm.nsite; ++u) {
+      int b = tm.bit[u];
+      int br = (r >> b) & 1;
+      sgn *= op_sign(tm.op[u], br);
+      if (op_flips(tm.op[u])) c ^= (1 << b);
+    }
+    double val = sgn > 0.0 ? tm.coef : -tm.coef;
+    row[c] = row[c] + val;
+  }
+}
+
+void leaf_assemble(hipStream_t s, int n_sites, int n_terms, const DevTerm* terms, double* H) {
+  int D = 1 << n_sites;
+  long nn = (long)D * D;
+  int blocks = (int)((nn + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, s, nn, H);
+  hipLaunchKernelGGL(leaf_assemble_kernel, dim3((D + 63) / 64), dim3(64), 0, s, D, n_terms, terms, H);
+}
+
+// (O v)[r] = sum_c O[r][c] v[c] = sign(op, bit of r) * v[r ^ flip].
+__global__ void site_op_apply_kernel(int nv, int D, int bit, int op, const double* __restrict__ V,
+                                     double* __restrict__ W) {
+  long total = (long)nv * D;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total;
+       t += (long)gridDim.x * blockDim.x) {
+    int j = (int)(t / D), r = (int)(t % D);
+    int br = (r >> bit) & 1;
+    int c = op_flips(op) ? (r ^ (1 << bit)) : r;
+    W[t] = op_sign(op, br) * V[(long)j * D + c];
+  }
+}
+
+void site_op_apply(hipStream_t s, int nv, int n_sites, int bit, int op, const double* V, double* W) {
+  int D = 1 << n_sites;
+  long total = (long)nv * D;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(site_op_apply_kernel, dim3(blocks), dim3(256), 0, s, nv, D, bit, op, V, W);
+}
+
+__global__ void kron_diag_kernel(int kA, int kB, const double* __restrict__ EA, const double* __restrict__ EB,
+                                 int T, const double* __restrict__ coef, const double* __restrict__ OA,
+                                 const double* __restrict__ OB, double* __restrict__ D,
+                                 double* __restrict__ Ediag) {
+  int n = kA * kB;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    int a = t / kB, b = t % kB;
+    double e = EA[a] + EB[b];
+    double d = e;
+    for (int i = 0; i < T; ++i)
+      d += coef[i] * OA[(long)i * kA * kA + (long)a * kA + a] * OB[(long)i * kB * kB + (long)b * kB + b];
+    if (D) D[t] = d;
+    if (Ediag) Ediag[t] = e;
+  }
+}
+
+void kron_diag(hipStream_t s, int kA, int kB, const double* EA, const double* EB, int T,
+               const double* coef_dev, const double* OAcat, const double* OBcat, double* D,
+               double* Ediag) {
+  int n = kA * kB;
+  hipLaunchKernelGGL(kron_diag_kernel, dim3((n + 255) / 256), dim3(256), 0, s, kA, kB, EA, EB, T,
+                     coef_dev, OAcat, OBcat, D, Ediag);
+}
+
+__global__ __launch_bounds__(256) void dense_diag_kernel(int n, const double* __restrict__ H,
+                                                         double* __restrict__ D, double* __restrict__ bound) {
+  __shared__ double red[4];
+  int i = blockIdx.x;
+  const double* row = H + (long)i * n;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256)
+    if (j != i) acc += fabs(row[j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = (red[0] + red[1]) + (red[2] + red[3]);
+    D[i] = row[i];
+    bound[i] = row[i] + s;
+  }
+}
+
+void dense_diag(hipStream_t s, int n, const double* H, double* D, double* rowbound) {
+  hipLaunchKernelGGL(dense_diag_kernel, dim3(n), dim3(256), 0, s, n, H, D, rowbound);
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator.
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ void rank_select_kernel(int n, int m, const double* __restrict__ D, int* __restrict__ sel) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double di = D[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      double dj = D[j];
+      rank += (dj < di) || (dj == di && j < i);
+    }
+    if (rank < m) sel[rank] = i;
+  }
+}
+
+__global__ void start_block_kernel(int n, int m, const int* __restrict__ sel, double eps, uint64_t seed,
+                                   double* __restrict__ X) {
+  long total = (long)m * n;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total;
+       t += (long)gridDim.x * blockDim.x) {
+    int j = (int)(t / n), i = (int)(t % n);
+    uint64_t h = splitmix64(seed ^ splitmix64((uint64_t)t));
+    double u = (double)(h >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    double v = eps * u;
+    if (sel[j] == i) v += 1.0;
+    X[t] = v;
+  }
+}
+
+void start_block(hipStream_t s, int n, int m, const double* D, double eps, unsigned long long seed,
+                 int* sel, double* X) {
+  hipLaunchKernelGGL(rank_select_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, m, D, sel);
+  long total = (long)m * n;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(start_block_kernel, dim3(blocks), dim3(256), 0, s, n, m, sel, eps,
+                     (uint64_t)seed, X);
+}
+
+}  // namespace rmc

@@ -1,0 +1,144 @@
+// Internal host-side structures of librmc: device arena, modules, the coupled
+// operator and the eigensolver interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/rmc.h"
+#include "rmc_kernels.h"
+
+namespace rmc {
+
+struct Error : std::runtime_error {
+  rmc_status code;
+  Error(rmc_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define RMC_HIP(x)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      throw ::rmc::Error(RMC_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define RMC_CHECK(cond, code, msg) \
+  do {                             \
+    if (!(cond)) throw ::rmc::Error((code), (msg)); \
+  } while (0)
+
+// First-fit sub-allocator over one device buffer (256-byte granules).
+class Arena {
+ public:
+  void init(char* base, size_t size);
+  void* alloc(size_t bytes);
+  void release(void* p);
+  size_t in_use() const { return in_use_; }
+  size_t peak() const { return peak_; }
+  size_t size() const { return size_; }
+  size_t largest_free() const;
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0, in_use_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+  std::map<size_t, size_t> used_;  // offset -> bytes
+};
+
+// RAII list of arena allocations released together.
+struct Scratch {
+  Arena* arena;
+  std::vector<void*> ptrs;
+  explicit Scratch(Arena* a) : arena(a) {}
+  ~Scratch() {
+    for (void* p : ptrs) arena->release(p);
+  }
+  template <class T>
+  T* get(size_t count) {
+    void* p = arena->alloc(count * sizeof(T) > 0 ? count * sizeof(T) : 8);
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+};
+
+}  // namespace rmc
+
+struct rmc_module {
+  int kind = 0;        // 0 leaf, 1 merged
+  int n_sites = 0;
+  int dim = 0;         // leaf: 2^n_sites; merged: kA * kB
+  int k_eff = 0;
+  int kA = 0, kB = 0;  // merged: child dimensions
+  double gap = 0.0;
+  double* E = nullptr;          // device, k_eff
+  std::vector<double> E_host;   // host copy
+  double* basis = nullptr;      // device, k_eff x dim (row = retained state); null once freed
+  rmc_module* A = nullptr;      // merged: children (not owned)
+  rmc_module* B = nullptr;
+  struct Op {
+    int site, op;
+    double* data;  // device k_eff x k_eff
+  };
+  std::vector<Op> ops;
+};
+
+struct rmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_arena = false;
+  void* arena_mem = nullptr;
+  rmc::Arena arena;
+  std::string last_error;
+  std::vector<rmc_module*> modules;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace rmc {
+
+// The operator whose lowest eigenpairs are sought: a dense symmetric matrix (leaf
+// module) or the Kronecker-sum effective Hamiltonian of a merge.
+struct CoupledOp {
+  int kind = 0;  // 0 dense, 1 kron
+  int n = 0;
+  const double* H = nullptr;  // dense n x n
+  int kA = 0, kB = 0, T = 0;
+  const double* EA = nullptr;
+  const double* EB = nullptr;
+  std::vector<double> coef;     // host
+  double* coef_dev = nullptr;   // device T
+  double* OAcat = nullptr;      // device T x kA x kA
+  double* OBcat = nullptr;      // device T x kB x kB
+  double* Ediag = nullptr;      // device n: EA[a] + EB[b]
+  double* D = nullptr;          // device n: full diagonal
+  double bup = 0.0;             // upper bound of the spectrum
+  int precision = RMC_FP64;
+  // low-precision copies of the operator for the filter (FP32 / BF16 forms)
+  void* OAlow = nullptr;
+  void* OBlow = nullptr;
+};
+
+struct SolveStats {
+  int iters = 0;
+  int matvecs = 0;
+  double max_res = 0.0;
+  int status = RMC_OK;
+};
+
+// Block apply: out = s1 * (H Y) + s2 * Y + s3 * Xprev for nv vectors (rows).
+void op_apply(rmc_ctx* ctx, const CoupledOp& op, int nv, const double* Y, double* out,
+              const double* Xprev, double s1, double s2, double s3, double* zwork,
+              double* kwork, int precision);
+size_t op_zwork_doubles(const CoupledOp& op, int nv);
+
+// Lowest nev eigenpairs of op. X_out: device nev x n (rows = eigenvectors);
+// evals: host nev. Returns RMC_OK or RMC_ERR_NOCONV.
+int eig_lowest(rmc_ctx* ctx, const CoupledOp& op, int nev, const rmc_solve_opts& o,
+               double* X_out, std::vector<double>& evals, SolveStats& st);
+
+// Gap rule (k_req < len(w) required for a cut); returns k_eff, gap.
+int gap_cut(const std::vector<double>& w, int k_req, double tau, double* gap);
+
+}  // namespace rmc

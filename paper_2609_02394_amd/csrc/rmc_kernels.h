@@ -1,0 +1,74 @@
+// Internal launch wrappers of librmc's HIP kernels (gfx950). All matrices are
+// row-major; a "block" of vectors is stored one vector per row.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rmc {
+
+// C[b] = alpha * op(A[b]) op(B[b]) + beta * C[b], op(A): M x K, op(B): K x N.
+// tA: A is stored K x M (A[k*lda+i]); tB: B is stored N x K (B[j*ldb+k]).
+// ksplit > 1 splits K over workgroups; the partial sums go to `work`
+// (ksplit*batch*M*N doubles) and are reduced in a fixed order.
+void gemm_f64(hipStream_t s, bool tA, bool tB, int M, int N, int K, double alpha,
+              const double* A, long lda, long sA, const double* B, long ldb, long sB,
+              double beta, double* C, long ldc, long sC, int batch, int ksplit, double* work);
+// Pick a split-K factor for an M x N x K product so the launch covers the chip.
+int gemm_pick_ksplit(int M, int N, int K, int batch);
+
+// Y_out = Y_out + s1 * diag .* Y + s2 * Y + s3 * Xprev over nv vectors of length n
+// (diag may be null; Xprev may be null when s3 == 0).
+void axpy_epilogue(hipStream_t s, int nv, int n, double* out, const double* Y,
+                   const double* Xprev, const double* diag, double s1, double s2, double s3,
+                   bool out_is_zero);
+
+// norms[j] = ||Y_j||_2, then Y_j /= norms[j] (if normalize) for nv vectors.
+void row_norms(hipStream_t s, int nv, int n, double* Y, double* norms, bool normalize);
+// res[j] = ||HX_j - theta_j X_j||_2.
+void residual_norms(hipStream_t s, int nv, int n, const double* HX, const double* X,
+                    const double* theta, double* res);
+
+// Cholesky G + shift*I = L L^T (m x m, m <= 192) and Linv = L^{-1} (lower, m x m).
+// info[0] = 0 on success, 1 if a pivot was not positive.
+void chol_inv(hipStream_t s, int m, const double* G, double shift, double* Linv, int* info);
+
+// Parallel cyclic Jacobi eigensolver of `batch` symmetric m x m matrices (m <= 192,
+// symmetrised as (A + A^T)/2). evals ascending, V columns = eigenvectors.
+// Vwork: batch*m*m scratch. info[b] = sweeps used, negative if not converged.
+void jacobi_eig(hipStream_t s, int batch, int m, const double* A, long sA, double* evals,
+                long sE, double* V, long sV, double* Vwork, int* info);
+int jacobi_max_m();
+
+// Dense leaf Hamiltonian from a device term list (bit-index assembly).
+struct DevTerm {
+  double coef;
+  int nsite;
+  int bit[2];   // bit positions (n_sites-1-site)
+  int op[2];
+};
+void leaf_assemble(hipStream_t s, int n_sites, int n_terms, const DevTerm* terms, double* H);
+
+// W_j = O_site v_j for nv vectors of a 2^n_sites space; op in {1:X, 2:T, 3:Z}.
+void site_op_apply(hipStream_t s, int nv, int n_sites, int bit, int op, const double* V,
+                   double* W);
+
+// Diagonal of H_eff: D[a*kB+b] = EA[a] + EB[b] + sum_i c_i OA_i[a,a] OB_i[b,b];
+// Ediag[a*kB+b] = EA[a] + EB[b].
+void kron_diag(hipStream_t s, int kA, int kB, const double* EA, const double* EB, int T,
+               const double* coef_dev, const double* OAcat, const double* OBcat, double* D,
+               double* Ediag);
+// D[i] = H[i,i]; bound[i] = H[i,i] + sum_{j != i} |H[i,j]| (Gershgorin row bound).
+void dense_diag(hipStream_t s, int n, const double* H, double* D, double* rowbound);
+// out[0] = max(v[0..n)).
+void vec_max(hipStream_t s, int n, const double* v, double* out);
+
+// Start block: the m smallest D entries (ties by index) as unit vectors plus eps
+// times a counter-based uniform(-1,1) perturbation; X is m x n.
+void start_block(hipStream_t s, int n, int m, const double* D, double eps,
+                 unsigned long long seed, int* sel, double* X);
+
+// out = src (m x n), strided copy helpers.
+void copy_rows(hipStream_t s, int nv, int n, const double* src, long ld_src, double* dst,
+               long ld_dst);
+
+}  // namespace rmc

@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle, on the GPU.
+
+Tolerances:
+* leaf Hamiltonian: bit-exact (integer basis indexing, sparsity and values);
+* FP64 eigenvalues: |dE| <= 1e-10 * max(|E|, 1) for whole recursions, tighter for
+  single steps;
+* retained subspaces are compared as projectors (bases are unique only up to
+  rotations inside degenerate clusters and signs);
+* Kronecker matvec: FP64 to 1e-12 of the output scale, FP32 to 2e-5, BF16 to 3e-2.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import exact as OX
+from oracle import hamiltonian as OH
+from oracle import recursion as OR
+from paper_2609_02394_amd import spin_models as SM
+from paper_2609_02394_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2609_02394_amd import rmc
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    c = rmc.Context(arena_bytes=6 << 30)
+    yield c
+    c.close()
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.max(np.abs(a - b) / np.maximum(np.abs(b), 1.0))
+
+
+# -- dense building blocks -------------------------------------------------------
+
+@pytest.mark.parametrize("m", [1, 2, 3, 8, 16, 33, 64, 100, 145, 192])
+def test_sym_eig_jacobi(ctx, m):
+    import torch
+
+    say("sym_eig", m)
+    rng = np.random.default_rng(m)
+    A = rng.standard_normal((3, m, m))
+    A = A + A.transpose(0, 2, 1)
+    A[1] = np.diag(np.sort(rng.standard_normal(m))) + 1e-6 * A[1]  # nearly diagonal
+    A[2][: m // 2, : m // 2] = 0.0                                 # degenerate cluster
+    ev, V = ctx.sym_eig(torch.tensor(A, device="cuda"))
+    ev, V = ev.cpu().numpy(), V.cpu().numpy()
+    for b in range(3):
+        ref = np.linalg.eigvalsh(A[b])
+        nrm = np.linalg.norm(A[b])
+        assert np.max(np.abs(ev[b] - ref)) <= 1e-13 * max(nrm, 1.0) * m
+        assert np.max(np.abs(A[b] @ V[b] - V[b] * ev[b])) <= 1e-12 * max(nrm, 1.0) * m
+        assert np.max(np.abs(V[b].T @ V[b] - np.eye(m))) <= 1e-13 * m
+
+
+@pytest.mark.parametrize("job,a,b", [
+    (W.tfim_small(), 0, 2),
+    (W.ChainJob("tfim", 10, 5, 8, 4, J=1.0, h=0.7), 0, 5),
+    (W.xxz_chain64(), 8, 16),
+    (W.ChainJob("xxz", 16, 8, 8, 4, J=1.0, delta=0.37), 0, 8),
+    (W.rfheis_batch(3)[2], 8, 16),
+    (W.tfim_ladder96(), 8, 16),
+    (W.ChainJob("xxz", 12, 12, 8, 4, J=1.0, delta=1.0), 0, 12),
+])
+def test_leaf_hamiltonian_bit_exact(ctx, job, a, b):
+    say("leaf_hamiltonian", job.model, a, b)
+    H = ctx.leaf_hamiltonian(b - a, SM.block_terms(job, a, b)).cpu().numpy()
+    ref = OH.block_hamiltonian(job, a, b)
+    assert np.array_equal(H != 0.0, ref != 0.0)      # sparsity pattern
+    assert np.array_equal(H, ref)                     # values (+0.0 == -0.0)
+
+
+def _projector_rows(B):
+    return B.T @ B
+
+
+@pytest.mark.parametrize("job,k", [
+    (W.ChainJob("tfim", 10, 5, 8, 4, J=1.0, h=0.7), 8),
+    (W.tfim_small(), 8),
+    (W.xxz_chain64(), 64),
+    (W.rfheis_batch(2)[1], 48),
+    (W.tfim_ladder96(), 128),
+])
+def test_module_ed_and_projection(ctx, job, k):
+    say("module_ed", job.model, k)
+    L0 = job.leaf_sites
+    m = ctx.module_ed(L0, SM.block_terms(job, 0, L0), k)
+    inf = m.info()
+    E_or, V_or, k_eff, gap, w = OR.leaf_ed(OH.block_hamiltonian(job, 0, L0), k)
+    assert inf["k_eff"] == k_eff
+    assert rel_err(inf["E"], E_or) <= 1e-12
+    B = m.basis()
+    assert np.max(np.abs(B @ B.T - np.eye(k_eff))) <= 1e-12
+    if gap > 1e-3:
+        assert np.max(np.abs(_projector_rows(B) - V_or @ V_or.T)) <= 1e-9
+    ids = m.project_ops([0, L0 - 1, L0 - 1], ["Z", "X", "T"])
+    for (s, o), i in zip([(0, "Z"), (L0 - 1, "X"), (L0 - 1, "T")], ids):
+        og = m.op(i)
+        Osite = OH.site_operator(L0, s, o)
+        # basis-invariant comparison: lift to the full space
+        lift_g = B.T @ og @ B
+        P = V_or @ V_or.T
+        if gap > 1e-3:
+            assert np.max(np.abs(lift_g - P @ Osite @ P)) <= 1e-10
+        sgn = -1.0 if o == "T" else 1.0
+        assert np.max(np.abs(og.T - sgn * og)) <= 1e-12
+    m.free()
+
+
+def _synthetic_module(ctx, rng, k, n_sites, spread=3.0):
+    E = np.sort(rng.uniform(-spread, 0.0, k))
+    ops = []
+    mats = {}
+    for s, o in [(0, "Z"), (0, "X"), (0, "T"), (n_sites - 1, "Z"), (n_sites - 1, "X"),
+                 (n_sites - 1, "T")]:
+        M = rng.standard_normal((k, k))
+        M = (M - M.T) if o == "T" else (M + M.T)
+        M /= np.linalg.norm(M, 2)
+        ops.append((s, o, M))
+        mats[(s, o)] = M
+    mod = ctx.module_import(n_sites, E, ops, dim=k * 4)
+    return mod, E, mats
+
+
+@pytest.mark.parametrize("kA,kB,T", [(8, 8, 1), (16, 48, 3), (63, 64, 3), (64, 64, 3),
+                                      (96, 96, 3), (128, 128, 2), (5, 37, 2), (33, 17, 0)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_kron_apply_matches_explicit_kron(ctx, kA, kB, T, prec):
+    import torch
+
+    say("kron_apply", kA, kB, T, prec)
+    rng = np.random.default_rng(kA * 1000 + kB * 10 + T)
+    A, EA, mA = _synthetic_module(ctx, rng, kA, 8)
+    B, EB, mB = _synthetic_module(ctx, rng, kB, 8)
+    keys = [(7, "X"), (7, "T"), (7, "Z")][:T]
+    keysB = [(0, "X"), (0, "T"), (0, "Z")][:T]
+    coefs = [0.25, -0.25, 0.3][:T]
+    idA = A.project_ops([s for s, _ in keys], [o for _, o in keys])
+    idB = B.project_ops([s for s, _ in keysB], [o for _, o in keysB])
+    X = rng.standard_normal((5, kA * kB))
+    Y = ctx.kron_apply(A, B, coefs, idA, idB, torch.tensor(X, device="cuda"), prec).cpu().numpy()
+    H = OR.effective_hamiltonian(EA, EB, [(c, mA[ka], mB[kb]) for c, ka, kb in zip(coefs, keys, keysB)])
+    ref = X @ H.T
+    scale = np.max(np.abs(ref))
+    tol = {0: 1e-12, 1: 2e-5, 2: 3e-2}[prec]
+    assert np.max(np.abs(Y - ref)) <= tol * scale
+    A.free()
+    B.free()
+
+
+@pytest.mark.parametrize("kA,kB,T,k_keep,q", [(8, 8, 1, 8, 4), (16, 24, 3, 16, 8),
+                                               (32, 32, 3, 32, 8), (64, 64, 3, 64, 8),
+                                               (20, 20, 0, 12, 4), (6, 5, 2, 40, 4)])
+def test_couple_solve_matches_dense(ctx, kA, kB, T, k_keep, q):
+    say("couple_solve", kA, kB, T, k_keep, q)
+    rng = np.random.default_rng(kA + 7 * kB + T)
+    A, EA, mA = _synthetic_module(ctx, rng, kA, 8)
+    B, EB, mB = _synthetic_module(ctx, rng, kB, 8)
+    keys = [(7, "X"), (7, "T"), (7, "Z")][:T]
+    keysB = [(0, "X"), (0, "T"), (0, "Z")][:T]
+    coefs = [0.6, -0.45, 0.5][:T]
+    idA = A.project_ops([s for s, _ in keys], [o for _, o in keys])
+    idB = B.project_ops([s for s, _ in keysB], [o for _, o in keysB])
+    M, e, rep = ctx.couple_solve(A, B, coefs, idA, idB, k_keep, q)
+    terms = [(c, mA[ka], mB[kb]) for c, ka, kb in zip(coefs, keys, keysB)]
+    w, E_or, U_or, k_eff, gap = OR.couple_solve(EA, EB, terms, k_keep)
+    assert rel_err(e, w[:q]) <= 1e-11
+    inf = M.info()
+    assert inf["k_eff"] == k_eff
+    assert rel_err(inf["E"], E_or) <= 1e-11
+    C = M.basis()
+    assert np.max(np.abs(C @ C.T - np.eye(k_eff))) <= 1e-11
+    if gap > 1e-3:
+        assert np.max(np.abs(C.T @ C - U_or @ U_or.T)) <= 1e-8
+    # root form: energies only
+    _, e2, _ = ctx.couple_solve(A, B, coefs, idA, idB, k_keep, q, want_module=False)
+    assert rel_err(e2, w[:q]) <= 1e-11
+    M.free()
+    A.free()
+    B.free()
+
+
+# -- whole recursions --------------------------------------------------------------
+
+RECURSION_CASES = [
+    ("tfim_small_k8", W.tfim_small()),
+    ("tfim_small_k16", W.ChainJob("tfim", 8, 2, 16, 4, J=1.0, h=1.0)),
+    ("tfim_N16_L4_k8", W.ChainJob("tfim", 16, 4, 8, 4, J=1.0, h=0.7)),
+    ("tfim_N10_L5_k7", W.ChainJob("tfim", 10, 5, 7, 4, J=1.0, h=0.7)),
+    ("xxz_N16_L4_k16", W.ChainJob("xxz", 16, 4, 16, 6, J=1.0, delta=1.0)),
+    ("xx_N24_L4_k12", W.ChainJob("xxz", 24, 4, 12, 4, J=1.0, delta=0.0)),
+    ("rfheis_N32_k32", W.ChainJob("rfheis", 32, 8, 32, 8, J=1.0, fields=W.rfheis_batch(1)[0].fields)),
+    ("ladder_2x8_k32", W.ChainJob("tfim_ladder", 16, 8, 32, 8, J=1.0, h=0.9, j_rung=0.5)),
+    ("ladder_2x6_odd", W.ChainJob("tfim_ladder", 12, 4, 16, 4, J=1.0, h=0.9, j_rung=0.5)),
+    ("single_leaf", W.ChainJob("xxz", 8, 8, 16, 4, J=1.0, delta=0.5)),
+]
+
+
+@pytest.mark.parametrize("name,job", RECURSION_CASES, ids=[c[0] for c in RECURSION_CASES])
+def test_recurse_matches_oracle(ctx, name, job):
+    from paper_2609_02394_amd import rmc
+
+    say("recurse", name)
+    e, rep = ctx.recurse(*rmc.job_chain(job))
+    ref = OR.recurse(job)
+    assert rel_err(e, ref.energies) <= 1e-10, (e, ref.energies)
+    kg = [r["k_eff"] for r in rep["records"] if r["kind"] != 2]
+    ko = [r.k_eff for r in ref.records]
+    assert sorted(set(kg)) == sorted(set(ko))
+
+
+def test_recurse_full_k_is_exact_and_bounds(ctx):
+    from paper_2609_02394_amd import rmc
+
+    say("recurse exactness / bounds")
+    job = W.ChainJob("tfim", 8, 2, 16, 4, J=1.0, h=1.0)
+    e, _ = ctx.recurse(*rmc.job_chain(job))
+    assert np.max(np.abs(e - OX.brute_energies(job, 4))) <= 1e-11
+    for N in (32, 64):
+        job = W.ChainJob("tfim", N, 8, 16, 4, J=1.0, h=0.7)
+        e, _ = ctx.recurse(*rmc.job_chain(job))
+        assert np.all(e >= OX.tfim_free_fermion(N, 1.0, 0.7, 4) - 1e-9)
+
+
+def test_recurse_xxz_chain64(ctx):
+    from paper_2609_02394_amd import rmc
+
+    say("recurse xxz N=64 k=64")
+    job = W.xxz_chain64()
+    e, rep = ctx.recurse(*rmc.job_chain(job))
+    ref = OR.recurse(job)
+    assert rel_err(e, ref.energies) <= 1e-10, (e, ref.energies)
+    assert e[0] / 64 > 0.25 - np.log(2)   # above the infinite-chain Hulthen energy density
+
+
+# -- error paths ---------------------------------------------------------------------
+
+def test_error_paths(ctx):
+    from paper_2609_02394_amd import rmc
+
+    say("error paths")
+    job = W.tfim_small()
+    n, L0, terms, k, q = rmc.job_chain(job)
+    with pytest.raises(rmc.RmcError) as ei:
+        ctx.recurse(n, L0, terms, 4, 5)          # q > k
+    assert ei.value.status == rmc.ERR_ARG
+    with pytest.raises(rmc.RmcError) as ei:
+        ctx.recurse(n, 3, terms, 4, 2)           # leaves do not tile the chain
+    assert ei.value.status == rmc.ERR_ARG
+    with pytest.raises(rmc.RmcError) as ei:
+        ctx.module_ed(2, [(1.0, ((0, "Z"), (5, "Z")))], 2)   # site out of range
+    assert ei.value.status == rmc.ERR_ARG
+    big = W.xxz_chain64()
+    n, L0, terms, k, q = rmc.job_chain(big)
+    o = rmc.default_opts(max_iter=1, max_degree=2)
+    with pytest.raises(rmc.RmcError) as ei:
+        ctx.recurse(n, L0, terms, k, q, opts=o)
+    assert ei.value.status == rmc.ERR_NOCONV
+    # the context still works afterwards
+    e, _ = ctx.recurse(*rmc.job_chain(W.tfim_small()))
+    assert rel_err(e, OR.recurse(W.tfim_small()).energies) <= 1e-10
