@@ -223,6 +223,18 @@ rmc_status rmc_kron_apply(rmc_ctx* ctx, rmc_module* A, rmc_module* B,
 rmc_status rmc_sym_eig(rmc_ctx* ctx, int batch, int m, const double* A_dev,
                        double* evals_dev, double* V_dev);
 
+/* Measurement of the Kronecker matvec (the dominant kernel): with enable = 1
+ * every launch on the ctx stream is bracketed by a pair of HIP events and its
+ * algorithmic work is counted (flops 2 T n (k_A + k_B) + 4 n per vector, n =
+ * k_A k_B; bytes 8 n per vector read and written, plus the previous iterate of
+ * the Chebyshev recurrence, E_A + E_B and the operators, once per launch).
+ * enable = 1 also clears the totals; 0 stops recording. */
+rmc_status rmc_profile(rmc_ctx* ctx, int enable);
+/* Totals since the last rmc_profile(ctx, 1); synchronises the stream. ms is the
+ * sum over launches of the event-measured kernel time. */
+rmc_status rmc_profile_read(rmc_ctx* ctx, long long* launches, double* flops, double* bytes,
+                            double* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -460,6 +460,11 @@ rmc_status rmc_destroy(rmc_ctx* ctx) {
   hipStreamSynchronize(ctx->stream);
   for (rmc_module* m : ctx->modules) delete m;
   ctx->modules.clear();
+  for (auto& r : ctx->prof_recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   if (ctx->own_arena && ctx->arena_mem) hipFree(ctx->arena_mem);
   delete ctx;
   return RMC_OK;
@@ -655,6 +660,46 @@ rmc_status rmc_kron_apply(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_
     kron_diag(s, kA, kB, A->E, B->E, T, op.coef_dev, op.OAcat, op.OBcat, nullptr, op.Ediag);
     op_apply(ctx, op, n_vec, X_dev, Y_dev, nullptr, 1.0, 0.0, 0.0, nullptr, nullptr, precision);
     sync(ctx);
+  });
+}
+
+rmc_status rmc_profile(rmc_ctx* ctx, int enable) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    sync(ctx);
+    for (auto& r : ctx->prof_recs) {
+      ctx->ev_pool.push_back(r.a);
+      ctx->ev_pool.push_back(r.b);
+    }
+    ctx->prof_recs.clear();
+    if (enable) {
+      ctx->prof_launches = 0;
+      ctx->prof_flops = ctx->prof_bytes = ctx->prof_ms = 0.0;
+    }
+    ctx->prof = enable != 0;
+  });
+}
+
+rmc_status rmc_profile_read(rmc_ctx* ctx, long long* launches, double* flops, double* bytes,
+                            double* ms) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    sync(ctx);
+    for (auto& r : ctx->prof_recs) {
+      float t = 0.f;
+      RMC_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      ctx->prof_ms += t;
+      ctx->prof_flops += r.flops;
+      ctx->prof_bytes += r.bytes;
+      ctx->prof_launches += 1;
+      ctx->ev_pool.push_back(r.a);
+      ctx->ev_pool.push_back(r.b);
+    }
+    ctx->prof_recs.clear();
+    if (launches) *launches = ctx->prof_launches;
+    if (flops) *flops = ctx->prof_flops;
+    if (bytes) *bytes = ctx->prof_bytes;
+    if (ms) *ms = ctx->prof_ms;
   });
 }
 

@@ -93,7 +93,16 @@ struct rmc_ctx {
   rmc::Arena arena;
   std::string last_error;
   std::vector<rmc_module*> modules;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // measurement of the Kronecker matvec launches
+  bool prof = false;
+  struct ProfRec {
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> ev_pool;
+  long long prof_launches = 0;
+  double prof_flops = 0.0, prof_bytes = 0.0, prof_ms = 0.0;
 };
 
 namespace rmc {

@@ -42,7 +42,31 @@ void op_apply(rmc_ctx* ctx, const CoupledOp& op, int nv, const double* Y, double
     axpy_epilogue(s, nv, n, out, Y, Xprev, nullptr, s1, s2, s3, false);
     return;
   }
+  if (!ctx->prof) {
+    kron_apply_fused(s, op, nv, Y, out, Xprev, s1, s2, s3, precision);
+    return;
+  }
+  auto take = [&]() {
+    hipEvent_t e;
+    if (!ctx->ev_pool.empty()) {
+      e = ctx->ev_pool.back();
+      ctx->ev_pool.pop_back();
+    } else {
+      RMC_HIP(hipEventCreate(&e));
+    }
+    return e;
+  };
+  rmc_ctx::ProfRec r;
+  r.a = take();
+  r.b = take();
+  RMC_HIP(hipEventRecord(r.a, s));
   kron_apply_fused(s, op, nv, Y, out, Xprev, s1, s2, s3, precision);
+  RMC_HIP(hipEventRecord(r.b, s));
+  const double nn = (double)n;
+  r.flops = (double)nv * (2.0 * op.T * nn * (op.kA + op.kB) + 4.0 * nn);
+  r.bytes = 8.0 * nn * ((double)nv * (s3 != 0.0 ? 3.0 : 2.0) + 1.0) +
+            8.0 * op.T * ((double)op.kA * op.kA + (double)op.kB * op.kB);
+  ctx->prof_recs.push_back(r);
 }
 
 int gap_cut(const std::vector<double>& w, int k_req, double tau, double* gap) {

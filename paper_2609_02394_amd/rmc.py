@@ -26,6 +26,7 @@ EXPORTED = (
     "rmc_module_ed", "rmc_project_ops", "rmc_couple_solve", "rmc_recurse", "rmc_recurse_batch",
     "rmc_module_info", "rmc_module_basis", "rmc_module_op", "rmc_module_free",
     "rmc_leaf_hamiltonian", "rmc_kron_apply", "rmc_sym_eig", "rmc_module_import",
+    "rmc_profile", "rmc_profile_read",
 )
 
 
@@ -93,6 +94,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "rmc_kron_apply": (i, [vp, vp, vp, P(BondDesc), i, i, vp, vp]),
         "rmc_sym_eig": (i, [vp, i, i, vp, vp, vp]),
         "rmc_module_import": (i, [vp, i, i, i, P(d), P(d), i, P(i), P(i), P(d), P(vp)]),
+        "rmc_profile": (i, [vp, i]),
+        "rmc_profile_read": (i, [vp, P(C.c_longlong), P(d), P(d), P(d)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -221,6 +224,14 @@ class Context:
         if st != OK and st not in allow:
             raise RmcError(st, lib().rmc_last_error(self.h).decode())
         return st
+
+    def profile(self, enable: bool):
+        self._check(lib().rmc_profile(self.h, int(bool(enable))))
+
+    def profile_read(self):
+        n, f, b, ms = C.c_longlong(), C.c_double(), C.c_double(), C.c_double()
+        self._check(lib().rmc_profile_read(self.h, C.byref(n), C.byref(f), C.byref(b), C.byref(ms)))
+        return {"launches": n.value, "flops": f.value, "bytes": b.value, "ms": ms.value}
 
     def arena_usage(self) -> Tuple[int, int]:
         a, b = C.c_size_t(), C.c_size_t()
