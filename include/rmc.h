@@ -121,6 +121,7 @@ typedef struct {
   int iters;     /* outer iterations of the eigensolver                  */
   int matvecs;   /* block-vector operator applications                   */
   int reused;    /* 1 if an identical module was reused                  */
+  int rr_sweeps; /* Jacobi sweeps summed over the Rayleigh-Ritz solves   */
   double gap;    /* eigenvalue gap at the cut (inf if nothing was cut)   */
   double max_res;/* largest relative residual among the wanted pairs     */
   double ms;     /* wall time of this module                             */

@@ -153,71 +153,115 @@ void assemble_leaf(rmc_ctx* ctx, const rmc_leaf_desc* leaf, double* H) {
   sync(ctx);  // dterms is released at scope exit
 }
 
-// Lowest eigenpairs of a dense leaf; builds a module if `make_module`.
-rmc_module* leaf_solve(rmc_ctx* ctx, const rmc_leaf_desc* leaf, int k, int q_only,
-                       const rmc_solve_opts& o, std::vector<double>& evals, rmc_level_report* rep) {
+// Lowest eigenpairs of several dense leaves in one batched solve; builds a module
+// per leaf unless q_only > 0 (then only the lowest q_only eigenvalues).
+std::vector<rmc_module*> leaf_solve_batch(rmc_ctx* ctx, const std::vector<const rmc_leaf_desc*>& leaves,
+                                          const std::vector<int>& ks, const std::vector<int>& q_only,
+                                          const rmc_solve_opts& o,
+                                          std::vector<std::vector<double>>& evals,
+                                          std::vector<rmc_level_report>* reps) {
   double t0 = now_ms();
-  const int D = 1 << leaf->n_sites;
+  const int P = (int)leaves.size();
   Scratch sc(&ctx->arena);
-  double* H = sc.get<double>((size_t)D * D);
-  assemble_leaf(ctx, leaf, H);
-  CoupledOp op;
-  op.kind = 0;
-  op.n = D;
-  op.H = H;
-  op.D = sc.get<double>(D);
-  double* rb = sc.get<double>(D);
-  double* bmax = sc.get<double>(1);
-  dense_diag(ctx->stream, D, H, op.D, rb);
-  vec_max(ctx->stream, D, rb, bmax);
-  RMC_HIP(hipMemcpyAsync(&op.bup, bmax, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  std::vector<CoupledOp> ops(P);
+  std::vector<const CoupledOp*> opp(P);
+  std::vector<int> nevs(P), kreq(P);
+  std::vector<double*> Xs(P);
+  double* bmax = sc.get<double>(std::max(P, 1));
+  for (int i = 0; i < P; ++i) {
+    const int D = 1 << leaves[i]->n_sites;
+    double* H = sc.get<double>((size_t)D * D);
+    assemble_leaf(ctx, leaves[i], H);
+    CoupledOp& op = ops[i];
+    op.kind = 0;
+    op.n = D;
+    op.H = H;
+    op.D = sc.get<double>(D);
+    double* rb = sc.get<double>(D);
+    dense_diag(ctx->stream, D, H, op.D, rb);
+    vec_max(ctx->stream, D, rb, bmax + i);
+    kreq[i] = std::min(ks[i], D);
+    nevs[i] = q_only[i] > 0 ? std::min(q_only[i], D) : std::min(D, kreq[i] + 1);
+    Xs[i] = sc.get<double>((size_t)nevs[i] * D);
+    opp[i] = &ops[i];
+  }
+  std::vector<double> bh(P);
+  RMC_HIP(hipMemcpyAsync(bh.data(), bmax, P * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   sync(ctx);
-  const int k_req = std::min(k, D);
-  int nev = q_only > 0 ? std::min(q_only, D) : std::min(D, k_req + 1);
-  double* X = sc.get<double>((size_t)nev * D);
-  SolveStats st;
+  for (int i = 0; i < P; ++i) ops[i].bup = bh[i];
   rmc_solve_opts oo = o;
   oo.precision = RMC_FP64;
-  int status = eig_lowest(ctx, op, nev, oo, X, evals, st);
-  if (rep) {
-    rep->iters = st.iters;
-    rep->matvecs = st.matvecs;
-    rep->max_res = st.max_res;
-    rep->k_req = k_req;
+  std::vector<SolveStats> st;
+  eig_lowest_batch(ctx, opp, nevs, oo, Xs, evals, st);
+  const double dt = now_ms() - t0;
+  if (reps) {
+    reps->assign(P, rmc_level_report{});
+    for (int i = 0; i < P; ++i) {
+      auto& r = (*reps)[i];
+      r.iters = st[i].iters;
+      r.matvecs = st[i].matvecs;
+      r.rr_sweeps = st[i].rr_sweeps;
+      r.max_res = st[i].max_res;
+      r.k_req = kreq[i];
+      r.gap = INFINITY;
+      r.ms = dt;
+      r.width = leaves[i]->n_sites;
+    }
   }
-  if (status != RMC_OK) throw Error((rmc_status)status, "leaf eigensolver did not converge");
-  if (q_only > 0) {
-    if (rep) rep->ms = now_ms() - t0;
-    return nullptr;
-  }
-  double gap = INFINITY;
-  int k_eff = gap_cut(evals, k_req, o.gap_tol > 0 ? o.gap_tol : 1e-6, &gap);
-  rmc_module* m = new rmc_module();
-  m->kind = 0;
-  m->n_sites = leaf->n_sites;
-  m->dim = D;
-  m->k_eff = k_eff;
-  m->gap = gap;
-  m->E_host.assign(evals.begin(), evals.begin() + k_eff);
+  for (int i = 0; i < P; ++i)
+    if (st[i].status != RMC_OK)
+      throw Error((rmc_status)st[i].status,
+                  "leaf eigensolver did not converge (dim=" + std::to_string(ops[i].n) +
+                      ", iters=" + std::to_string(st[i].iters) +
+                      ", max_res=" + std::to_string(st[i].max_res) + ")");
+  std::vector<rmc_module*> out(P, nullptr);
   try {
-    m->E = (double*)ctx->arena.alloc(k_eff * sizeof(double));
-    m->basis = (double*)ctx->arena.alloc((size_t)k_eff * D * sizeof(double));
+    for (int i = 0; i < P; ++i) {
+      if (q_only[i] > 0) continue;
+      const int D = ops[i].n;
+      double gap = INFINITY;
+      int k_eff = gap_cut(evals[i], kreq[i], o.gap_tol > 0 ? o.gap_tol : 1e-6, &gap);
+      rmc_module* m = new rmc_module();
+      m->kind = 0;
+      m->n_sites = leaves[i]->n_sites;
+      m->dim = D;
+      m->k_eff = k_eff;
+      m->gap = gap;
+      m->E_host.assign(evals[i].begin(), evals[i].begin() + k_eff);
+      ctx->modules.push_back(m);
+      out[i] = m;
+      m->E = (double*)ctx->arena.alloc(k_eff * sizeof(double));
+      m->basis = (double*)ctx->arena.alloc((size_t)k_eff * D * sizeof(double));
+      RMC_HIP(hipMemcpyAsync(m->E, m->E_host.data(), k_eff * sizeof(double), hipMemcpyHostToDevice,
+                             ctx->stream));
+      copy_rows(ctx->stream, k_eff, D, Xs[i], D, m->basis, D);
+      if (reps) {
+        (*reps)[i].k_eff = k_eff;
+        (*reps)[i].gap = gap;
+      }
+    }
+    sync(ctx);
   } catch (...) {
-    free_module_mem(ctx, m);
-    delete m;
+    for (rmc_module* m : out)
+      if (m) {
+        auto it = std::find(ctx->modules.begin(), ctx->modules.end(), m);
+        if (it != ctx->modules.end()) ctx->modules.erase(it);
+        free_module_mem(ctx, m);
+        delete m;
+      }
     throw;
   }
-  RMC_HIP(hipMemcpyAsync(m->E, m->E_host.data(), k_eff * sizeof(double), hipMemcpyHostToDevice,
-                         ctx->stream));
-  copy_rows(ctx->stream, k_eff, D, X, D, m->basis, D);
-  sync(ctx);
-  ctx->modules.push_back(m);
-  if (rep) {
-    rep->k_eff = k_eff;
-    rep->gap = gap;
-    rep->ms = now_ms() - t0;
-  }
-  return m;
+  return out;
+}
+
+rmc_module* leaf_solve(rmc_ctx* ctx, const rmc_leaf_desc* leaf, int k, int q_only,
+                       const rmc_solve_opts& o, std::vector<double>& evals, rmc_level_report* rep) {
+  std::vector<std::vector<double>> ev;
+  std::vector<rmc_level_report> reps;
+  auto m = leaf_solve_batch(ctx, {leaf}, {k}, {q_only}, o, ev, rep ? &reps : nullptr);
+  evals = ev[0];
+  if (rep) *rep = reps[0];
+  return m[0];
 }
 
 int find_op(const rmc_module* m, int site, int op) {
@@ -270,105 +314,160 @@ int project_op(rmc_ctx* ctx, rmc_module* m, int site, int op) {
   return (int)m->ops.size() - 1;
 }
 
+struct CoupleReq {
+  rmc_module* A;
+  rmc_module* B;
+  const rmc_bond_desc* bond;
+  bool want_module;
+  int k_keep, q;
+};
+
+// Several coupling steps (one per request) in one batched solve. k_keep: states
+// kept in new modules (gap rule); q: energies returned.
+std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>& reqs,
+                                      const rmc_solve_opts& o,
+                                      std::vector<std::vector<double>>& evals,
+                                      std::vector<rmc_level_report>* reps) {
+  double t0 = now_ms();
+  const int P = (int)reqs.size();
+  hipStream_t s = ctx->stream;
+  Scratch sc(&ctx->arena);
+  std::vector<CoupledOp> ops(P);
+  std::vector<const CoupledOp*> opp(P);
+  std::vector<int> nevs(P), kreq(P);
+  std::vector<double*> Xs(P);
+  for (int p = 0; p < P; ++p) {
+    const CoupleReq& rq = reqs[p];
+    rmc_module* A = rq.A;
+    rmc_module* B = rq.B;
+    const rmc_bond_desc* bond = rq.bond;
+    const int k_keep = rq.k_keep, q = rq.q;
+    RMC_CHECK(A && B && bond, RMC_ERR_ARG, "null argument");
+    RMC_CHECK(A->E && B->E, RMC_ERR_STATE, "module freed");
+    const int T = bond->n_terms;
+    RMC_CHECK(T >= 0 && (T == 0 || (bond->coef && bond->opA && bond->opB)), RMC_ERR_ARG, "bad bond");
+    const int kA = A->k_eff, kB = B->k_eff, n = kA * kB;
+    RMC_CHECK(kA <= 256 && kB <= 256, RMC_ERR_ARG, "module dimension above 256");
+    if (rq.want_module) RMC_CHECK(k_keep >= 1 && q <= k_keep, RMC_ERR_ARG, "need 1 <= q <= k_keep");
+    RMC_CHECK(q >= 1, RMC_ERR_ARG, "q must be >= 1");
+    for (int i = 0; i < T; ++i) {
+      RMC_CHECK(bond->opA[i] >= 0 && bond->opA[i] < (int)A->ops.size(), RMC_ERR_ARG, "bad opA id");
+      RMC_CHECK(bond->opB[i] >= 0 && bond->opB[i] < (int)B->ops.size(), RMC_ERR_ARG, "bad opB id");
+      RMC_CHECK(std::isfinite(bond->coef[i]), RMC_ERR_ARG, "non-finite coupling coefficient");
+    }
+    CoupledOp& op = ops[p];
+    op.kind = 1;
+    op.n = n;
+    op.kA = kA;
+    op.kB = kB;
+    op.T = T;
+    op.EA = A->E;
+    op.EB = B->E;
+    op.coef.assign(bond->coef, bond->coef + T);
+    op.coef_dev = sc.get<double>(std::max(T, 1));
+    op.OAcat = sc.get<double>((size_t)std::max(T, 1) * kA * kA);
+    op.OBcat = sc.get<double>((size_t)std::max(T, 1) * kB * kB);
+    op.Ediag = sc.get<double>(n);
+    op.D = sc.get<double>(n);
+    if (T > 0)
+      RMC_HIP(hipMemcpyAsync(op.coef_dev, bond->coef, T * sizeof(double), hipMemcpyHostToDevice, s));
+    double csum = 0.0;
+    for (int i = 0; i < T; ++i) {
+      RMC_HIP(hipMemcpyAsync(op.OAcat + (size_t)i * kA * kA, A->ops[bond->opA[i]].data,
+                             (size_t)kA * kA * sizeof(double), hipMemcpyDeviceToDevice, s));
+      RMC_HIP(hipMemcpyAsync(op.OBcat + (size_t)i * kB * kB, B->ops[bond->opB[i]].data,
+                             (size_t)kB * kB * sizeof(double), hipMemcpyDeviceToDevice, s));
+      csum += std::fabs(bond->coef[i]);
+    }
+    kron_diag(s, kA, kB, A->E, B->E, T, op.coef_dev, op.OAcat, op.OBcat, op.D, op.Ediag);
+    // projected one-site Pauli operators have spectral norm <= 1
+    const double emax = A->E_host.back() + B->E_host.back();
+    op.bup = emax + csum + 1e-12 * (std::fabs(emax) + csum + 1.0);
+    op.precision = o.precision;
+    kreq[p] = std::min(k_keep, n);
+    int nev = rq.want_module ? std::min(n, kreq[p] + 1) : std::min(q, n);
+    nevs[p] = std::max(nev, std::min(q, n));
+    Xs[p] = sc.get<double>((size_t)nevs[p] * n);
+    opp[p] = &ops[p];
+  }
+  std::vector<SolveStats> st;
+  eig_lowest_batch(ctx, opp, nevs, o, Xs, evals, st);
+  const double dt = now_ms() - t0;
+  if (reps) {
+    reps->assign(P, rmc_level_report{});
+    for (int p = 0; p < P; ++p) {
+      auto& r = (*reps)[p];
+      r.iters = st[p].iters;
+      r.matvecs = st[p].matvecs;
+      r.rr_sweeps = st[p].rr_sweeps;
+      r.max_res = st[p].max_res;
+      r.k_req = kreq[p];
+      r.gap = INFINITY;
+      r.ms = dt;
+      r.kind = reqs[p].want_module ? 1 : 2;
+      r.width = reqs[p].A->n_sites + reqs[p].B->n_sites;
+    }
+  }
+  for (int p = 0; p < P; ++p)
+    if (st[p].status != RMC_OK)
+      throw Error((rmc_status)st[p].status,
+                  "coupled eigensolver did not converge (n=" + std::to_string(ops[p].n) +
+                      ", nev=" + std::to_string(nevs[p]) + ", iters=" + std::to_string(st[p].iters) +
+                      ", max_res=" + std::to_string(st[p].max_res) + ")");
+  std::vector<rmc_module*> out(P, nullptr);
+  try {
+    for (int p = 0; p < P; ++p) {
+      if (!reqs[p].want_module) continue;
+      const int n = ops[p].n;
+      double gap = INFINITY;
+      int k_eff = gap_cut(evals[p], kreq[p], o.gap_tol > 0 ? o.gap_tol : 1e-6, &gap);
+      rmc_module* m = new rmc_module();
+      m->kind = 1;
+      m->n_sites = reqs[p].A->n_sites + reqs[p].B->n_sites;
+      m->dim = n;
+      m->k_eff = k_eff;
+      m->kA = ops[p].kA;
+      m->kB = ops[p].kB;
+      m->A = reqs[p].A;
+      m->B = reqs[p].B;
+      m->gap = gap;
+      m->E_host.assign(evals[p].begin(), evals[p].begin() + k_eff);
+      ctx->modules.push_back(m);
+      out[p] = m;
+      m->E = (double*)ctx->arena.alloc(k_eff * sizeof(double));
+      m->basis = (double*)ctx->arena.alloc((size_t)k_eff * n * sizeof(double));
+      RMC_HIP(hipMemcpyAsync(m->E, m->E_host.data(), k_eff * sizeof(double), hipMemcpyHostToDevice, s));
+      copy_rows(s, k_eff, n, Xs[p], n, m->basis, n);
+      if (reps) {
+        (*reps)[p].k_eff = k_eff;
+        (*reps)[p].gap = gap;
+      }
+    }
+    sync(ctx);
+  } catch (...) {
+    for (rmc_module* m : out)
+      if (m) {
+        auto it = std::find(ctx->modules.begin(), ctx->modules.end(), m);
+        if (it != ctx->modules.end()) ctx->modules.erase(it);
+        free_module_mem(ctx, m);
+        delete m;
+      }
+    throw;
+  }
+  return out;
+}
+
 // One coupling step; out module optional.
 rmc_module* couple(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_bond_desc* bond,
                    int k_keep, int q, const rmc_solve_opts& o, bool want_module,
                    std::vector<double>& evals, rmc_level_report* rep) {
-  double t0 = now_ms();
-  RMC_CHECK(A && B && bond, RMC_ERR_ARG, "null argument");
-  RMC_CHECK(A->E && B->E, RMC_ERR_STATE, "module freed");
-  const int T = bond->n_terms;
-  RMC_CHECK(T >= 0 && (T == 0 || (bond->coef && bond->opA && bond->opB)), RMC_ERR_ARG, "bad bond");
-  const int kA = A->k_eff, kB = B->k_eff, n = kA * kB;
-  RMC_CHECK(kA <= 256 && kB <= 256, RMC_ERR_ARG, "module dimension above 256");
-  if (want_module) RMC_CHECK(k_keep >= 1 && q <= k_keep, RMC_ERR_ARG, "need 1 <= q <= k_keep");
-  RMC_CHECK(q >= 1, RMC_ERR_ARG, "q must be >= 1");
-  for (int i = 0; i < T; ++i) {
-    RMC_CHECK(bond->opA[i] >= 0 && bond->opA[i] < (int)A->ops.size(), RMC_ERR_ARG, "bad opA id");
-    RMC_CHECK(bond->opB[i] >= 0 && bond->opB[i] < (int)B->ops.size(), RMC_ERR_ARG, "bad opB id");
-    RMC_CHECK(std::isfinite(bond->coef[i]), RMC_ERR_ARG, "non-finite coupling coefficient");
-  }
-  hipStream_t s = ctx->stream;
-  Scratch sc(&ctx->arena);
-  CoupledOp op;
-  op.kind = 1;
-  op.n = n;
-  op.kA = kA;
-  op.kB = kB;
-  op.T = T;
-  op.EA = A->E;
-  op.EB = B->E;
-  op.coef.assign(bond->coef, bond->coef + T);
-  op.coef_dev = sc.get<double>(std::max(T, 1));
-  op.OAcat = sc.get<double>((size_t)std::max(T, 1) * kA * kA);
-  op.OBcat = sc.get<double>((size_t)std::max(T, 1) * kB * kB);
-  op.Ediag = sc.get<double>(n);
-  op.D = sc.get<double>(n);
-  if (T > 0)
-    RMC_HIP(hipMemcpyAsync(op.coef_dev, bond->coef, T * sizeof(double), hipMemcpyHostToDevice, s));
-  double csum = 0.0;
-  for (int i = 0; i < T; ++i) {
-    RMC_HIP(hipMemcpyAsync(op.OAcat + (size_t)i * kA * kA, A->ops[bond->opA[i]].data,
-                           (size_t)kA * kA * sizeof(double), hipMemcpyDeviceToDevice, s));
-    RMC_HIP(hipMemcpyAsync(op.OBcat + (size_t)i * kB * kB, B->ops[bond->opB[i]].data,
-                           (size_t)kB * kB * sizeof(double), hipMemcpyDeviceToDevice, s));
-    csum += std::fabs(bond->coef[i]);
-  }
-  kron_diag(s, kA, kB, A->E, B->E, T, op.coef_dev, op.OAcat, op.OBcat, op.D, op.Ediag);
-  // projected one-site Pauli operators have spectral norm <= 1
-  double emax = A->E_host.back() + B->E_host.back();
-  op.bup = emax + csum + 1e-12 * (std::fabs(emax) + csum + 1.0);
-  op.precision = o.precision;
-
-  const int k_req = std::min(k_keep, n);
-  int nev = want_module ? std::min(n, k_req + 1) : std::min(q, n);
-  nev = std::max(nev, std::min(q, n));
-  double* X = sc.get<double>((size_t)nev * n);
-  SolveStats st;
-  int status = eig_lowest(ctx, op, nev, o, X, evals, st);
-  if (rep) {
-    rep->iters = st.iters;
-    rep->matvecs = st.matvecs;
-    rep->max_res = st.max_res;
-    rep->k_req = k_req;
-    rep->gap = INFINITY;
-    rep->k_eff = 0;
-  }
-  if (status != RMC_OK) throw Error((rmc_status)status, "coupled eigensolver did not converge");
-  rmc_module* m = nullptr;
-  if (want_module) {
-    double gap = INFINITY;
-    int k_eff = gap_cut(evals, k_req, o.gap_tol > 0 ? o.gap_tol : 1e-6, &gap);
-    m = new rmc_module();
-    m->kind = 1;
-    m->n_sites = A->n_sites + B->n_sites;
-    m->dim = n;
-    m->k_eff = k_eff;
-    m->kA = kA;
-    m->kB = kB;
-    m->A = A;
-    m->B = B;
-    m->gap = gap;
-    m->E_host.assign(evals.begin(), evals.begin() + k_eff);
-    try {
-      m->E = (double*)ctx->arena.alloc(k_eff * sizeof(double));
-      m->basis = (double*)ctx->arena.alloc((size_t)k_eff * n * sizeof(double));
-    } catch (...) {
-      free_module_mem(ctx, m);
-      delete m;
-      throw;
-    }
-    RMC_HIP(hipMemcpyAsync(m->E, m->E_host.data(), k_eff * sizeof(double), hipMemcpyHostToDevice, s));
-    copy_rows(s, k_eff, n, X, n, m->basis, n);
-    sync(ctx);
-    ctx->modules.push_back(m);
-    if (rep) {
-      rep->k_eff = k_eff;
-      rep->gap = gap;
-    }
-  }
-  if (rep) rep->ms = now_ms() - t0;
-  return m;
+  std::vector<std::vector<double>> ev;
+  std::vector<rmc_level_report> reps;
+  auto m = couple_batch(ctx, {CoupleReq{A, B, bond, want_module, k_keep, q}}, o, ev,
+                        rep ? &reps : nullptr);
+  evals = ev[0];
+  if (rep) *rep = reps[0];
+  return m[0];
 }
 
 }  // namespace
@@ -389,6 +488,29 @@ rmc_module* api_couple(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_bon
                        std::vector<double>& evals, rmc_level_report* rep) {
   return couple(ctx, A, B, bond, k_keep, q, o, want_module, evals, rep);
 }
+std::vector<rmc_module*> api_leaf_solve_batch(rmc_ctx* ctx,
+                                              const std::vector<const rmc_leaf_desc*>& leaves,
+                                              const std::vector<int>& ks,
+                                              const std::vector<int>& q_only,
+                                              const rmc_solve_opts& o,
+                                              std::vector<std::vector<double>>& evals,
+                                              std::vector<rmc_level_report>* reps) {
+  return leaf_solve_batch(ctx, leaves, ks, q_only, o, evals, reps);
+}
+std::vector<rmc_module*> api_couple_batch(rmc_ctx* ctx, const std::vector<rmc_module*>& As,
+                                          const std::vector<rmc_module*>& Bs,
+                                          const std::vector<const rmc_bond_desc*>& bonds,
+                                          const std::vector<char>& want,
+                                          const std::vector<int>& k_keep, const std::vector<int>& q,
+                                          const rmc_solve_opts& o,
+                                          std::vector<std::vector<double>>& evals,
+                                          std::vector<rmc_level_report>* reps) {
+  std::vector<CoupleReq> rq;
+  for (size_t i = 0; i < As.size(); ++i)
+    rq.push_back(CoupleReq{As[i], Bs[i], bonds[i], want[i] != 0, k_keep[i], q[i]});
+  return couple_batch(ctx, rq, o, evals, reps);
+}
+size_t api_arena_free(rmc_ctx* ctx) { return ctx->arena.size() - ctx->arena.in_use(); }
 void api_release_basis(rmc_ctx* ctx, rmc_module* m) {
   ctx->arena.release(m->basis);
   m->basis = nullptr;
@@ -465,6 +587,7 @@ rmc_status rmc_destroy(rmc_ctx* ctx) {
     hipEventDestroy(r.b);
   }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  if (ctx->pinned) hipHostFree(ctx->pinned);
   if (ctx->own_arena && ctx->arena_mem) hipFree(ctx->arena_mem);
   delete ctx;
   return RMC_OK;
@@ -713,7 +836,8 @@ rmc_status rmc_sym_eig(rmc_ctx* ctx, int batch, int m, const double* A_dev, doub
     Scratch sc(&ctx->arena);
     double* Vw = sc.get<double>((size_t)batch * m * m);
     int* info = sc.get<int>(batch);
-    jacobi_eig(ctx->stream, batch, m, A_dev, (long)m * m, evals_dev, m, V_dev, (long)m * m, Vw, info);
+    jacobi_eig(ctx->stream, batch, m, A_dev, (long)m * m, 1, 0, evals_dev, m, V_dev, (long)m * m, Vw,
+               info);
     sync(ctx);
   });
 }

@@ -4,10 +4,14 @@
 //   out_j = s1 * ( sum_i c_i O_A^i Y_j (O_B^i)^T + (E_A[a] + E_B[b]) .* Y_j )
 //         + s2 * Y_j + s3 * Xprev_j
 //
-// for a block of vectors Y_j, each a k_A x k_B row-major coefficient matrix.
+//         [ + s1 * phi_j * Ecorr_j ]
+// for a block of vectors Y_j, each a k_A x k_B row-major coefficient matrix. The
+// optional Ecorr term is the FP64 residual that drives the defect form of the
+// Chebyshev filter in the FP32/BF16 forms (see solver.hip).
 // (A (x) B) vec(X) = vec(A X B^T) for row-major vec, so this is exactly H_eff Y_j.
 //
-// One workgroup (4 waves) owns one vector j and one 16-wide column tile
+// Batched over problems (descriptor per problem, blockIdx.z). One workgroup
+// (4 waves) owns one vector j and one 16-wide column tile
 // [b0, b0+16) of the output:
 //   stage 1: Z_i[:, tile] = Y_j (O_B^i[tile, :])^T   (k_A x 16, K = k_B) -> LDS
 //   stage 2: acc[:, tile] = sum_i c_i O_A^i Z_i[:, tile]     (K = k_A)
@@ -26,6 +30,7 @@
 
 #include <algorithm>
 
+#include "rmc_batch.h"
 #include "rmc_internal.h"
 
 namespace rmc {
@@ -98,23 +103,25 @@ __device__ inline typename KTraits<P>::acc mma_tile(typename KTraits<P>::acc acc
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4;
   if constexpr (P == 0 || P == 1) {
-    // K step of 16: lane group g takes k = kb + 4g + s, s = 0..3
-    for (int kb = 0; kb < K; kb += 16) {
-      const int k0 = kb + 4 * g;
-      double av[4], bv[4];
+    // K in chunks of 64: all operands of a chunk are loaded before its 16 MFMAs so
+    // the loads overlap. Within a step of 16, lane group g takes k = kb + 4g + s.
+    for (int kc = 0; kc < K; kc += 64) {
+      double av[16], bv[16];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = k0 + s;
-        const bool ok = k < K;
-        av[s] = ld_or0(A + (long)row * lda + k, ok && row_ok) * scale;
-        bv[s] = ok ? bfn(k) : 0.0;
-      }
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < 4; ++s) {
+          const int k = kc + 16 * u + 4 * g + s;
+          const bool ok = k < K;
+          av[4 * u + s] = ld_or0(A + (long)row * lda + k, ok && row_ok);
+          bv[4 * u + s] = ok ? bfn(k) : 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
         if constexpr (P == 0)
-          acc = Mfma<0>::step(av[s], bv[s], acc);
+          acc = Mfma<0>::step(av[u] * scale, bv[u], acc);
         else
-          acc = Mfma<1>::step((float)av[s], (float)bv[s], acc);
+          acc = Mfma<1>::step((float)(av[u] * scale), (float)bv[u], acc);
       }
     }
   } else {
@@ -137,23 +144,19 @@ __device__ inline typename KTraits<P>::acc mma_tile(typename KTraits<P>::acc acc
   return acc;
 }
 
+// One workgroup: vector j of descriptor d, output columns [b0, b0+16).
 template <int P>
-__global__ __launch_bounds__(256) void kron_fused_kernel(
-    int kA, int kB, int T, const double* __restrict__ coef, const double* __restrict__ OA,
-    const double* __restrict__ OB, const double* __restrict__ Ediag, const double* __restrict__ Y,
-    const double* __restrict__ Xprev, double* __restrict__ out, double s1, double s2, double s3) {
+__device__ void kron_body(const KronDesc& d, int j, int b0, char* smem_raw) {
   typedef typename KTraits<P>::zt zt;
   typedef typename KTraits<P>::acc accT;
-  extern __shared__ char smem_raw[];
   zt* Zs = reinterpret_cast<zt*>(smem_raw);  // [KR_TCH][kApad][16]
+  const int kA = d.kA, kB = d.kB, T = d.T;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  const int b0 = blockIdx.x * 16;
-  const int j = blockIdx.y;
   const int n = kA * kB;
   const int RT = (kA + 15) >> 4;
   const int kApad = RT * 16;
-  const double* Yj = Y + (long)j * n;
+  const double* Yj = d.Y + (long)j * n;
 
   constexpr int MAXRT = 4;  // row tiles per wave (kA <= 256)
   accT acc[MAXRT];
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(256) void kron_fused_kernel(
     const int tn = min(KR_TCH, T - t0);
     // stage 1: Z_i = Y_j (O_B^i[tile,:])^T, rows = a, cols = tile, K = kB
     for (int ti = 0; ti < tn; ++ti) {
-      const double* OBi = OB + (long)(t0 + ti) * kB * kB;
+      const double* OBi = d.OB + (long)(t0 + ti) * kB * kB;
       const int bcol = b0 + l16;
       const bool bok = bcol < kB;
 #pragma unroll
@@ -183,8 +186,8 @@ __global__ __launch_bounds__(256) void kron_fused_kernel(
     __syncthreads();
     // stage 2: acc += c_i O_A^i Z_i
     for (int ti = 0; ti < tn; ++ti) {
-      const double* OAi = OA + (long)(t0 + ti) * kA * kA;
-      const double ci = coef[t0 + ti];
+      const double* OAi = d.OA + (long)(t0 + ti) * kA * kA;
+      const double ci = d.coef[t0 + ti];
       const zt* Zt = Zs + ((long)ti * kApad) * 16;
 #pragma unroll
       for (int q = 0; q < MAXRT; ++q) {
@@ -200,8 +203,10 @@ __global__ __launch_bounds__(256) void kron_fused_kernel(
   // epilogue: register r of each row tile holds row acc_row<P>(g, r), column l16
   const int col = b0 + l16;
   if (col >= kB) return;
-  const double* Xp = Xprev ? Xprev + (long)j * n : nullptr;
-  double* oj = out + (long)j * n;
+  const double* Xp = d.Xprev ? d.Xprev + (long)j * n : nullptr;
+  const double* Ej = d.E ? d.E + (long)j * n : nullptr;
+  const double ph = d.E ? d.s1 * d.phi[j] : 0.0;
+  double* oj = d.out + (long)j * n;
 #pragma unroll
   for (int q = 0; q < MAXRT; ++q) {
     const int rt = wave + 4 * q;
@@ -212,11 +217,21 @@ __global__ __launch_bounds__(256) void kron_fused_kernel(
       if (row >= kA) continue;
       const long idx = (long)row * kB + col;
       const double y = Yj[idx];
-      double v = s1 * ((double)acc[q][r] + Ediag[idx] * y) + s2 * y;
-      if (Xp) v += s3 * Xp[idx];
+      double v = d.s1 * ((double)acc[q][r] + d.Ediag[idx] * y) + d.s2 * y;
+      if (Xp) v += d.s3 * Xp[idx];
+      if (Ej) v += ph * Ej[idx];
       oj[idx] = v;
     }
   }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void kron_batched_kernel(const KronDesc* __restrict__ descs) {
+  extern __shared__ char smem_raw[];
+  const KronDesc d = descs[blockIdx.z];
+  const int j = blockIdx.y, b0 = blockIdx.x * 16;
+  if (j >= d.nv || b0 >= d.kB) return;
+  kron_body<P>(d, j, b0, smem_raw);
 }
 
 static size_t kron_lds_bytes(int kA, int prec) {
@@ -229,33 +244,28 @@ int kron_max_k() { return 256; }
 
 void kron_set_attrs() {
   const int lds = 160 * 1024 - 1024;
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_fused_kernel<0>),
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_batched_kernel<0>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_fused_kernel<1>),
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_batched_kernel<1>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_fused_kernel<2>),
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_batched_kernel<2>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-// out = s1 * H Y + s2 * Y + s3 * Xprev, fused kernel, precision 0/1/2.
-void kron_apply_fused(hipStream_t s, const CoupledOp& op, int nv, const double* Y, double* out,
-                      const double* Xprev, double s1, double s2, double s3, int precision) {
-  if (nv <= 0) return;
-  dim3 grid((op.kB + 15) / 16, nv);
-  size_t lds = kron_lds_bytes(op.kA, precision);
-  const double* xp = (s3 != 0.0) ? Xprev : nullptr;
+void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
+                  int precision) {
+  if (P <= 0 || nvmax <= 0 || kBmax <= 0) return;
+  dim3 grid((kBmax + 15) / 16, nvmax, P);
+  size_t lds = kron_lds_bytes(kAmax, precision);
   switch (precision) {
     case RMC_FP64:
-      hipLaunchKernelGGL(kron_fused_kernel<0>, grid, dim3(256), lds, s, op.kA, op.kB, op.T,
-                         op.coef_dev, op.OAcat, op.OBcat, op.Ediag, Y, xp, out, s1, s2, s3);
+      hipLaunchKernelGGL(kron_batched_kernel<0>, grid, dim3(256), lds, s, d);
       break;
     case RMC_FP32:
-      hipLaunchKernelGGL(kron_fused_kernel<1>, grid, dim3(256), lds, s, op.kA, op.kB, op.T,
-                         op.coef_dev, op.OAcat, op.OBcat, op.Ediag, Y, xp, out, s1, s2, s3);
+      hipLaunchKernelGGL(kron_batched_kernel<1>, grid, dim3(256), lds, s, d);
       break;
     default:
-      hipLaunchKernelGGL(kron_fused_kernel<2>, grid, dim3(256), lds, s, op.kA, op.kB, op.T,
-                         op.coef_dev, op.OAcat, op.OBcat, op.Ediag, Y, xp, out, s1, s2, s3);
+      hipLaunchKernelGGL(kron_batched_kernel<2>, grid, dim3(256), lds, s, d);
       break;
   }
 }

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "rmc_batch.h"
 #include "rmc_kernels.h"
 
 namespace rmc {
@@ -169,6 +170,43 @@ void start_block(hipStream_t s, int n, int m, const double* D, double eps, unsig
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(start_block_kernel, dim3(blocks), dim3(256), 0, s, n, m, sel, eps,
                      (uint64_t)seed, X);
+}
+
+__global__ void rank_select_batched_kernel(const StartDesc* __restrict__ descs) {
+  const StartDesc d = descs[blockIdx.z];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += gridDim.x * blockDim.x) {
+    double di = d.D[i];
+    int rank = 0;
+    for (int j = 0; j < d.n; ++j) {
+      double dj = d.D[j];
+      rank += (dj < di) || (dj == di && j < i);
+    }
+    if (rank < d.m) d.sel[rank] = i;
+  }
+}
+
+__global__ void start_block_batched_kernel(const StartDesc* __restrict__ descs) {
+  const StartDesc d = descs[blockIdx.z];
+  const long total = (long)d.m * d.n;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total;
+       t += (long)gridDim.x * blockDim.x) {
+    int j = (int)(t / d.n), i = (int)(t % d.n);
+    uint64_t h = splitmix64((uint64_t)d.seed ^ splitmix64((uint64_t)t));
+    double u = (double)(h >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    double v = d.eps * u;
+    if (d.sel[j] == i) v += 1.0;
+    d.X[t] = v;
+  }
+}
+
+void start_batched(hipStream_t s, const StartDesc* d, int P, int nmax, int mmax) {
+  if (P <= 0) return;
+  int bx = (nmax + 255) / 256;
+  hipLaunchKernelGGL(rank_select_batched_kernel, dim3(bx, 1, P), dim3(256), 0, s, d);
+  long tot = (long)nmax * mmax;
+  int bx2 = (int)((tot + 255) / 256);
+  if (bx2 > 2048) bx2 = 2048;
+  hipLaunchKernelGGL(start_block_batched_kernel, dim3(bx2, 1, P), dim3(256), 0, s, d);
 }
 
 }  // namespace rmc

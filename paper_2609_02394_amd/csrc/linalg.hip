@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "rmc_batch.h"
 #include "rmc_kernels.h"
 
 namespace rmc {
@@ -23,7 +24,8 @@ constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
     int tA, int tB, int M, int N, int K, int kchunk, double alpha, const double* __restrict__ A,
     long lda, long sA, const double* __restrict__ B, long ldb, long sB, double beta,
-    double* __restrict__ C, long ldc, long sC, int batch, int ksplit, double* __restrict__ work) {
+    double* __restrict__ C, long ldc, long sC, int batch, int ksplit, double* __restrict__ work,
+    int to_parts) {
   __shared__ double As[GB_K][GB_M + 1];
   __shared__ double Bs[GB_K][GB_N + 1];
   const int tid = threadIdx.x;
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
     __syncthreads();
   }
 
-  if (ksplit > 1) {
+  if (ksplit > 1 || to_parts) {
     double* P = work + ((long)ks * batch + b) * (long)M * N;
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
@@ -128,6 +130,99 @@ __global__ void splitk_reduce_kernel(int M, int N, int batch, int ksplit, const 
   }
 }
 
+// Grouped GEMM: problem = blockIdx.z / ksplit, split = blockIdx.z % ksplit, each
+// problem with its own sizes, pointers and scalars.
+__global__ __launch_bounds__(256) void gemm_grouped_kernel(int tA, int tB, int ksplit,
+                                                           const GemmDesc* __restrict__ descs) {
+  __shared__ double As[GB_K][GB_M + 1];
+  __shared__ double Bs[GB_K][GB_N + 1];
+  const GemmDesc d = descs[blockIdx.z / ksplit];
+  const int ks = blockIdx.z % ksplit;
+  const int M = d.M, N = d.N, K = d.K;
+  const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
+  if (row0 >= M || col0 >= N) return;
+  int kchunk = (K + ksplit - 1) / ksplit;
+  kchunk = ((kchunk + GB_K - 1) / GB_K) * GB_K;
+  if (kchunk < GB_K) kchunk = GB_K;
+  const int kbeg = ks * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const double* Ab = d.A;
+  const double* Bb = d.B;
+  const long lda = d.lda, ldb = d.ldb;
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int idx = tid + e * 256;
+      int i, k;
+      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / GB_M; i = idx % GB_M; }
+      int gi = row0 + i, gk = k0 + k;
+      double v = 0.0;
+      if (gi < M && gk < kend) v = tA ? Ab[(long)gk * lda + gi] : Ab[(long)gi * lda + gk];
+      As[k][i] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int idx = tid + e * 256;
+      int j, k;
+      if (!tB) { k = idx / GB_N; j = idx % GB_N; } else { j = idx / GB_K; k = idx % GB_K; }
+      int gj = col0 + j, gk = k0 + k;
+      double v = 0.0;
+      if (gj < N && gk < kend) v = tB ? Bb[(long)gj * ldb + gk] : Bb[(long)gk * ldb + gj];
+      Bs[k][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GB_K; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a0 = As[kr][wm + (lane & 15)];
+      double a1 = As[kr][wm + 16 + (lane & 15)];
+      double b0 = Bs[kr][wn + (lane & 15)];
+      double b1 = Bs[kr][wn + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const bool parts = d.work != nullptr;
+  double* P = parts ? d.work + (long)ks * M * N : nullptr;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gi = row0 + wm + ti * 16 + 4 * r + (lane >> 4);
+        int gj = col0 + wn + tj * 16 + (lane & 15);
+        if (gi < M && gj < N) {
+          double v = d.alpha * acc[ti][tj][r];
+          if (parts) {
+            P[(long)gi * N + gj] = v;
+          } else {
+            if (d.beta != 0.0) v += d.beta * d.C[(long)gi * d.ldc + gj];
+            d.C[(long)gi * d.ldc + gj] = v;
+          }
+        }
+      }
+}
+
+void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int Mmax, int Nmax,
+                  int ksplit) {
+  if (P <= 0 || Mmax <= 0 || Nmax <= 0) return;
+  if (ksplit < 1) ksplit = 1;
+  dim3 grid((Nmax + GB_N - 1) / GB_N, (Mmax + GB_M - 1) / GB_M, P * ksplit);
+  hipLaunchKernelGGL(gemm_grouped_kernel, grid, dim3(256), 0, s, (int)tA, (int)tB, ksplit, d);
+}
+
 int gemm_pick_ksplit(int M, int N, int K, int batch) {
   long tiles = (long)((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N) * batch;
   if (tiles >= 256) return 1;
@@ -150,7 +245,7 @@ void gemm_f64(hipStream_t s, bool tA, bool tB, int M, int N, int K, double alpha
   ksplit = K > 0 ? (K + kchunk - 1) / kchunk : 1;
   dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch * ksplit);
   hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, s, (int)tA, (int)tB, M, N, K, kchunk,
-                     alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ksplit, work);
+                     alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ksplit, work, 0);
   if (ksplit > 1) {
     long total = (long)batch * M * N;
     int blocks = (int)((total + 255) / 256);
@@ -158,6 +253,21 @@ void gemm_f64(hipStream_t s, bool tA, bool tB, int M, int N, int K, double alpha
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, s, M, N, batch, ksplit,
                        work, beta, C, ldc, sC);
   }
+}
+
+int gemm_f64_partials(hipStream_t s, bool tA, bool tB, int M, int N, int K, const double* A,
+                      long lda, const double* B, long ldb, int ksplit, double* work) {
+  if (M <= 0 || N <= 0) return 1;
+  if (K < 0) K = 0;
+  if (ksplit < 1 || K == 0) ksplit = 1;
+  int kchunk = (K + ksplit - 1) / ksplit;
+  kchunk = ((kchunk + GB_K - 1) / GB_K) * GB_K;
+  if (kchunk < GB_K) kchunk = GB_K;
+  ksplit = K > 0 ? (K + kchunk - 1) / kchunk : 1;
+  dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, ksplit);
+  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, s, (int)tA, (int)tB, M, N, K, kchunk, 1.0,
+                     A, lda, 0L, B, ldb, 0L, 0.0, (double*)nullptr, 0L, 0L, 1, ksplit, work, 1);
+  return ksplit;
 }
 
 // ---------------------------------------------------------------------------
@@ -248,6 +358,29 @@ void residual_norms(hipStream_t s, int nv, int n, const double* HX, const double
   hipLaunchKernelGGL(residual_norms_kernel, dim3(nv), dim3(256), 0, s, n, HX, X, theta, res);
 }
 
+// out_j = a[j] * P_j + b * Q_j (Q may be null), rows of length n.
+__global__ void rows_scale_add_kernel(int nv, int n, double* __restrict__ out, const double* __restrict__ Pm,
+                                      const double* __restrict__ a, double asgn, double b,
+                                      const double* __restrict__ Qm) {
+  long total = (long)nv * n;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total;
+       t += (long)gridDim.x * blockDim.x) {
+    int j = (int)(t / n);
+    double v = asgn * a[j] * Pm[t];
+    if (Qm) v += b * Qm[t];
+    out[t] = v;
+  }
+}
+
+void rows_scale_add(hipStream_t s, int nv, int n, double* out, const double* P, const double* a,
+                    double asgn, double b, const double* Q) {
+  long total = (long)nv * n;
+  if (total <= 0) return;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(rows_scale_add_kernel, dim3(blocks), dim3(256), 0, s, nv, n, out, P, a, asgn, b, Q);
+}
+
 __global__ void copy_rows_kernel(int nv, int n, const double* __restrict__ src, long lds,
                                  double* __restrict__ dst, long ldd) {
   long total = (long)nv * n;
@@ -287,113 +420,164 @@ void vec_max(hipStream_t s, int n, const double* v, double* out) {
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky + inverse of the lower factor, one 1024-thread workgroup, packed
-// lower triangle in LDS (m <= 192 -> at most 148 KB).
+// Cholesky + in-place inverse of the lower factor, one 1024-thread workgroup
+// (a 32 x 32 thread grid), packed lower triangle in LDS (m <= 192 -> at most
+// 148 KB). The input Gram matrix may be given as nparts split-K partial
+// sums (stride pstride), added in a fixed order while loading.
 // ---------------------------------------------------------------------------
 constexpr int JMAX = 192;
+constexpr int CHOL_THREADS = 1024;
 __device__ inline int lidx(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
 
-__global__ __launch_bounds__(1024) void chol_inv_kernel(int m, const double* __restrict__ G, double shift,
-                                                        double* __restrict__ Linv, int* __restrict__ info) {
-  extern __shared__ double L[];
-  __shared__ int fail;
+__device__ inline int tri_row(int t) {  // row i of packed lower index t
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > t) --i;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  return i;
+}
+
+__device__ void chol_inv_body(int m, const double* __restrict__ G, int nparts, long pstride,
+                              double shift, double* __restrict__ Linv, int* __restrict__ info,
+                              double* L, double* col) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int ty = tid >> 5, tx = tid & 31;  // 32 x 32 thread grid
   const int np = m * (m + 1) / 2;
   for (int t = tid; t < np; t += nt) {
-    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while (i * (i + 1) / 2 > t) --i;
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    int i = tri_row(t);
     int j = t - i * (i + 1) / 2;
-    double v = 0.5 * (G[(long)i * m + j] + G[(long)j * m + i]);
+    double v = 0.0;
+    for (int ks = 0; ks < nparts; ++ks) {
+      const double* g = G + (long)ks * pstride;
+      v += 0.5 * (g[(long)i * m + j] + g[(long)j * m + i]);
+    }
     if (i == j) v += shift;
     L[t] = v;
   }
-  if (tid == 0) fail = 0;
   __syncthreads();
+  int fail = 0;
+  // right-looking factorisation; col[] keeps the sqrt of the pivots
   for (int j = 0; j < m; ++j) {
-    if (tid == 0) {
-      double d = L[lidx(j, j)];
-      if (!(d > 0.0)) fail = 1;
-      else L[lidx(j, j)] = sqrt(d);
-    }
+    const double d = L[lidx(j, j)];
+    if (!(d > 0.0)) { fail = 1; break; }
+    const double sd = sqrt(d);
+    if (tid == 0) col[j] = sd;
+    const double inv = 1.0 / sd;
+    for (int i = j + 1 + tid; i < m; i += nt) L[lidx(i, j)] *= inv;
     __syncthreads();
-    if (fail) break;
-    double djj = L[lidx(j, j)];
-    for (int i = j + 1 + tid; i < m; i += nt) L[lidx(i, j)] /= djj;
-    __syncthreads();
-    int r0 = j + 1, w = m - r0;
-    int ntri = w * (w + 1) / 2;
-    for (int t = tid; t < ntri; t += nt) {
-      int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-      while (a * (a + 1) / 2 > t) --a;
-      while ((a + 1) * (a + 2) / 2 <= t) ++a;
-      int c = t - a * (a + 1) / 2;
-      int r = r0 + a, cc = r0 + c;
-      L[lidx(r, cc)] -= L[lidx(r, j)] * L[lidx(cc, j)];
+    for (int r = j + 1 + ty; r < m; r += 32) {
+      const int base = r * (r + 1) / 2;
+      const double lrj = L[base + j];
+      for (int c = j + 1 + tx; c <= r; c += 32) L[base + c] -= lrj * L[c * (c + 1) / 2 + j];
     }
     __syncthreads();
   }
   if (tid == 0) info[0] = fail;
   if (fail) return;
-  // Column c of L^{-1} by forward substitution (one thread per column).
-  for (int c = tid; c < m; c += nt) {
-    double* X = Linv;
-    for (int i = 0; i < c; ++i) X[(long)i * m + c] = 0.0;
-    X[(long)c * m + c] = 1.0 / L[lidx(c, c)];
-    for (int i = c + 1; i < m; ++i) {
+  for (int j = tid; j < m; j += nt) L[lidx(j, j)] = col[j];
+  __syncthreads();
+  // in-place inverse, columns right to left: X[i][j] = -(sum_{k=j+1..i} X[i][k] L[k][j]) / L[j][j]
+  for (int j = m - 1; j >= 0; --j) {
+    for (int i = j + 1 + tid; i < m; i += nt) col[i] = L[lidx(i, j)];
+    const double d = L[lidx(j, j)];
+    __syncthreads();
+    for (int i0 = j + 1; i0 < m; i0 += 32) {
+      const int i = i0 + ty;
       double acc = 0.0;
       const int base = i * (i + 1) / 2;
-      for (int k = c; k < i; ++k) acc += L[base + k] * X[(long)k * m + c];
-      X[(long)i * m + c] = -acc / L[base + i];
+      if (i < m)
+        for (int k = j + 1 + tx; k <= i; k += 32) acc += L[base + k] * col[k];
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 32);
+      if (i < m && tx == 0) L[base + j] = -acc / d;
     }
+    if (tid == 0) L[lidx(j, j)] = 1.0 / d;
+    __syncthreads();
+  }
+  for (long t = tid; t < (long)m * m; t += nt) {
+    int i = (int)(t / m), j = (int)(t % m);
+    Linv[t] = j <= i ? L[lidx(i, j)] : 0.0;
   }
 }
 
-void chol_inv(hipStream_t s, int m, const double* G, double shift, double* Linv, int* info) {
-  size_t lds = (size_t)m * (m + 1) / 2 * sizeof(double);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), lds, s, m, G, shift, Linv, info);
+__global__ __launch_bounds__(CHOL_THREADS) void chol_inv_kernel(int m, const double* __restrict__ G, int nparts,
+                                                                long pstride, double shift,
+                                                                double* __restrict__ Linv, int* __restrict__ info) {
+  extern __shared__ double sm[];
+  chol_inv_body(m, G, nparts, pstride, shift, Linv, info, sm, sm + m * (m + 1) / 2);
+}
+
+size_t chol_lds_bytes(int m) { return ((size_t)m * (m + 1) / 2 + m) * sizeof(double); }
+
+void chol_inv(hipStream_t s, int m, const double* G, int nparts, long pstride, double shift,
+              double* Linv, int* info) {
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CHOL_THREADS), chol_lds_bytes(m), s, m, G,
+                     nparts < 1 ? 1 : nparts, pstride, shift, Linv, info);
+}
+
+__global__ __launch_bounds__(CHOL_THREADS) void chol_batched_kernel(const CholDesc* __restrict__ descs) {
+  extern __shared__ double sm[];
+  const CholDesc d = descs[blockIdx.x];
+  double* L = sm;
+  double* col = sm + d.m * (d.m + 1) / 2;
+  chol_inv_body(d.m, d.G, d.nparts, d.pstride, 0.0, d.Linv, d.info, L, col);
+  __syncthreads();
+  const int failed = d.info[0];
+  __syncthreads();
+  if (failed) {  // shifted CholeskyQR: retry with the shift, flag it in info[1]
+    chol_inv_body(d.m, d.G, d.nparts, d.pstride, d.shift, d.Linv, d.info, L, col);
+    if (threadIdx.x == 0) d.info[1] = 1;
+  } else if (threadIdx.x == 0) {
+    d.info[1] = 0;
+  }
+}
+
+void chol_batched(hipStream_t s, const CholDesc* d, int P, int mmax) {
+  if (P <= 0) return;
+  hipLaunchKernelGGL(chol_batched_kernel, dim3(P), dim3(CHOL_THREADS), chol_lds_bytes(mmax), s, d);
 }
 
 // ---------------------------------------------------------------------------
-// Parallel cyclic Jacobi (round-robin ordering). Packed upper triangle of A in
-// LDS; eigenvector accumulation in global memory (Vwork), one workgroup per
-// matrix. A rotation of pair (p,q) is skipped when |a_pq| is below
-// max(eps*sqrt(|a_pp a_qq|), eps*||A||_F); the sweep loop ends after a sweep
-// with no rotation.
+// Parallel cyclic Jacobi (round-robin ordering) for symmetric m x m, m <= 192.
+// Packed upper triangle of A in LDS; eigenvectors accumulated in LDS when they
+// fit beside it, else in global memory (Vwork). Rotation of pair (p,q) skipped
+// when |a_pq| <= max(eps sqrt|a_pp a_qq|, eps ||A||_F); before each sweep all
+// off-diagonal entries are tested and the loop ends when none exceeds that.
 // ---------------------------------------------------------------------------
-__device__ inline int uidx(int i, int j) {  // i <= j, packed upper by columns
-  return j * (j + 1) / 2 + i;
-}
+constexpr int JAC_THREADS = 1024;
+__device__ inline int uidx(int i, int j) { return j * (j + 1) / 2 + i; }  // i <= j
 __device__ inline int sidx(int i, int j) { return i <= j ? uidx(i, j) : uidx(j, i); }
-
 __device__ inline int rr_player(int pos, int step, int M) {
   if (pos == 0) return 0;
   return 1 + (pos - 1 + step) % (M - 1);
 }
 
-__global__ __launch_bounds__(1024) void jacobi_kernel(int m, const double* __restrict__ Ain, long sA,
-                                                      double* __restrict__ evals, long sE,
-                                                      double* __restrict__ Vout, long sV,
-                                                      double* __restrict__ Vwork, int max_sweeps,
-                                                      int* __restrict__ info) {
-  extern __shared__ double sm[];
+size_t jacobi_lds_doubles(int m, bool vlds) {
+  const int M = m + (m & 1), H = M / 2;
+  size_t d = (size_t)M * (M + 1) / 2 + 3 * (size_t)H + (3 * (size_t)H + 1) / 2 + 2 + 64;
+  if (vlds) d += (size_t)m * m;
+  return d;
+}
+static bool jacobi_v_in_lds(int m) { return jacobi_lds_doubles(m, true) * 8 <= 156 * 1024; }
+
+__device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, long pstride,
+                            double* __restrict__ evals, double* __restrict__ Vout,
+                            double* __restrict__ Vg, int vlds, int max_sweeps, int* __restrict__ info,
+                            double* sm) {
   const int M = m + (m & 1);
   const int H = M / 2;
-  double* A = sm;                         // M*(M+1)/2
-  double* cs = A + M * (M + 1) / 2;       // H
-  double* sn = cs + H;                    // H
-  double* tn = sn + H;                    // H
-  int* pp = (int*)(tn + H);               // H
-  int* qq = pp + H;                       // H
-  int* act = qq + H;                      // H
-  __shared__ int s_rot;
-  __shared__ double red[16];
+  double* A = sm;                        // M*(M+1)/2
+  double* cs = A + M * (M + 1) / 2;      // H
+  double* sn = cs + H;                   // H
+  double* tn = sn + H;                   // H
+  int* pp = (int*)(tn + H);              // H
+  int* qq = pp + H;                      // H
+  int* act = qq + H;                     // H
+  double* red = (double*)(((uintptr_t)(act + H) + 15) & ~(uintptr_t)15);  // 64
+  int* flag = (int*)(red + 32);
+  double* V = vlds ? (red + 64) : Vg;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int b = blockIdx.x;
-  const double* Ab = Ain + (long)b * sA;
-  double* V = Vwork + (long)b * m * m;
+  const int ty = tid >> 5, tx = tid & 31;  // 32 x 32 thread grid
 
-  // load (symmetrised), dummy row/col for odd m
   double nrm = 0.0;
   const int np = M * (M + 1) / 2;
   for (int t = tid; t < np; t += nt) {
@@ -402,7 +586,11 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int m, const double* __res
     while ((j + 1) * (j + 2) / 2 <= t) ++j;
     int i = t - j * (j + 1) / 2;
     double v = 0.0;
-    if (j < m) v = 0.5 * (Ab[(long)i * m + j] + Ab[(long)j * m + i]);
+    if (j < m)
+      for (int ks = 0; ks < nparts; ++ks) {
+        const double* g = Ab + (long)ks * pstride;
+        v += 0.5 * (g[(long)i * m + j] + g[(long)j * m + i]);
+      }
     A[t] = v;
     nrm += (i == j ? 1.0 : 2.0) * v * v;
   }
@@ -417,13 +605,24 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int m, const double* __res
   const double floor_abs = eps * fro;
 
   int sweeps = 0;
-  bool converged = (M <= 1);
-  for (; sweeps < max_sweeps && !converged; ++sweeps) {
-    if (tid == 0) s_rot = 0;
+  bool converged = false;
+  for (;;) {
+    // any off-diagonal entry above its threshold?
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int i = ty; i < m; i += 32)
+      for (int j = i + 1 + ((tx - i - 1) % 32 + 32) % 32; j < m; j += 32) {
+        double thr = fmax(eps * sqrt(fabs(A[uidx(i, i)] * A[uidx(j, j)])), floor_abs);
+        if (fabs(A[uidx(i, j)]) > thr) *flag = 1;
+      }
+    __syncthreads();
+    if (*flag == 0) { converged = true; break; }
+    if (sweeps >= max_sweeps) break;
+    ++sweeps;
     __syncthreads();
     for (int step = 0; step < M - 1; ++step) {
-      if (tid < H) {
-        int p = rr_player(tid, step, M), q = rr_player(M - 1 - tid, step, M);
+      for (int k = tid; k < H; k += nt) {
+        int p = rr_player(k, step, M), q = rr_player(M - 1 - k, step, M);
         if (p > q) { int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0, t = 0.0;
         int a = 0;
@@ -437,19 +636,13 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int m, const double* __res
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
             a = 1;
-            s_rot = 1;
           }
         }
-        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s; tn[tid] = t; act[tid] = a;
+        pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s; tn[k] = t; act[k] = a;
       }
       __syncthreads();
-      // two-sided update of all 2x2 blocks (k <= l)
-      const int nb = H * (H + 1) / 2;
-      for (int t = tid; t < nb; t += nt) {
-        int l = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-        while (l * (l + 1) / 2 > t) --l;
-        while ((l + 1) * (l + 2) / 2 <= t) ++l;
-        int k = t - l * (l + 1) / 2;
+      for (int k = ty; k < H; k += 32)
+        for (int l = k + ((tx - k) % 32 + 32) % 32; l < H; l += 32) {
         if (!act[k] && !act[l]) continue;
         int pk = pp[k], qk = qq[k];
         if (k == l) {
@@ -464,18 +657,15 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int m, const double* __res
         double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
         int i00 = sidx(pk, pl), i01 = sidx(pk, ql), i10 = sidx(qk, pl), i11 = sidx(qk, ql);
         double m00 = A[i00], m01 = A[i01], m10 = A[i10], m11 = A[i11];
-        // rows: J_k^T M
         double r00 = ck * m00 - sk * m10, r01 = ck * m01 - sk * m11;
         double r10 = sk * m00 + ck * m10, r11 = sk * m01 + ck * m11;
-        // cols: (.) J_l
         A[i00] = r00 * cl - r01 * sl;
         A[i01] = r00 * sl + r01 * cl;
         A[i10] = r10 * cl - r11 * sl;
         A[i11] = r10 * sl + r11 * cl;
-      }
-      // eigenvector columns
-      const long nv = (long)m * H;
-      for (long t = tid; t < nv; t += nt) {
+        }
+      const long nvv = (long)m * H;
+      for (long t = tid; t < nvv; t += nt) {
         int k = (int)(t % H);
         int r = (int)(t / H);
         if (!act[k]) continue;
@@ -487,10 +677,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int m, const double* __res
       }
       __syncthreads();
     }
-    converged = (s_rot == 0);
-    __syncthreads();
   }
-  // sort eigenvalues ascending (ties by index) and permute eigenvector columns
   for (int i = tid; i < m; i += nt) {
     double di = A[uidx(i, i)];
     int rank = 0;
@@ -498,10 +685,97 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int m, const double* __res
       double dj = A[uidx(j, j)];
       rank += (dj < di) || (dj == di && j < i);
     }
-    evals[(long)b * sE + rank] = di;
-    for (int r = 0; r < m; ++r) Vout[(long)b * sV + (long)r * m + rank] = V[(long)r * m + i];
+    evals[rank] = di;
+    for (int r = 0; r < m; ++r) Vout[(long)r * m + rank] = V[(long)r * m + i];
   }
-  if (tid == 0) info[b] = converged ? sweeps : -sweeps;
+  if (tid == 0) info[0] = converged ? sweeps : -(sweeps + 1);
+}
+
+__global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, const double* __restrict__ Ain, long sA,
+                                                             int nparts, long pstride,
+                                                             double* __restrict__ evals, long sE,
+                                                             double* __restrict__ Vout, long sV,
+                                                             double* __restrict__ Vwork, int vlds,
+                                                             int max_sweeps, int* __restrict__ info) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x;
+  jacobi_body(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
+              Vwork + (long)b * m * m, vlds, max_sweeps, info + b, sm);
+}
+
+__global__ __launch_bounds__(JAC_THREADS) void jacobi_batched_kernel(const EigDesc* __restrict__ descs,
+                                                                     int vlds, int max_sweeps) {
+  extern __shared__ double sm[];
+  const EigDesc d = descs[blockIdx.x];
+  jacobi_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, d.Vwork, vlds, max_sweeps, d.info, sm);
+}
+
+void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax) {
+  if (P <= 0) return;
+  const int vl = jacobi_v_in_lds(mmax) ? 1 : 0;
+  size_t lds = jacobi_lds_doubles(mmax, vl) * sizeof(double);
+  hipLaunchKernelGGL(jacobi_batched_kernel, dim3(P), dim3(JAC_THREADS), lds, s, d, vl, 40);
+}
+
+// Row-block vector operations (one workgroup per row for the reductions).
+__global__ __launch_bounds__(256) void vec_batched_kernel(int op, const VecDesc* __restrict__ descs) {
+  __shared__ double red[4];
+  const VecDesc d = descs[blockIdx.z];
+  const int n = d.n;
+  if (op == VEC_NORMALIZE || op == VEC_RESIDUAL) {
+    const int j = blockIdx.x;
+    if (j >= d.nv) return;
+    double acc = 0.0;
+    if (op == VEC_NORMALIZE) {
+      double* y = d.out + (long)j * n;
+      for (int i = threadIdx.x; i < n; i += 256) acc += y[i] * y[i];
+      double nr = sqrt(block_sum256(acc, red));
+      if (threadIdx.x == 0 && d.norms) d.norms[j] = nr;
+      if (nr > 0.0) {
+        double inv = 1.0 / nr;
+        for (int i = threadIdx.x; i < n; i += 256) y[i] *= inv;
+      }
+    } else {
+      const double* hx = d.P + (long)j * n;
+      const double* x = d.Q + (long)j * n;
+      const double th = d.a[j];
+      for (int i = threadIdx.x; i < n; i += 256) {
+        double r = hx[i] - th * x[i];
+        acc += r * r;
+      }
+      double nr = sqrt(block_sum256(acc, red));
+      if (threadIdx.x == 0) d.norms[j] = nr;
+    }
+    return;
+  }
+  const long total = (long)d.nv * n;
+  for (long t = blockIdx.x * 256L + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+    const int j = (int)(t / n);
+    double v;
+    if (op == VEC_SCALE_ADD) {
+      v = d.asgn * d.a[j] * d.P[t];
+      if (d.Q) v += d.b * d.Q[t];
+    } else if (op == VEC_COPY) {
+      v = d.P[t];
+    } else {  // VEC_AXPY3
+      v = d.out[t] + d.b * d.P[t];
+      if (d.Q) v += d.c * d.Q[t];
+    }
+    d.out[t] = v;
+  }
+}
+
+void vec_batched(hipStream_t s, VecOp op, const VecDesc* d, int P, int nvmax, long elems_max) {
+  if (P <= 0) return;
+  int gx;
+  if (op == VEC_NORMALIZE || op == VEC_RESIDUAL) {
+    gx = nvmax;
+  } else {
+    long b = (elems_max + 255) / 256;
+    gx = (int)(b > 1024 ? 1024 : b);
+  }
+  if (gx <= 0) return;
+  hipLaunchKernelGGL(vec_batched_kernel, dim3(gx, 1, P), dim3(256), 0, s, (int)op, d);
 }
 
 int jacobi_max_m() { return JMAX; }
@@ -512,14 +786,18 @@ void linalg_set_attrs() {
                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_inv_kernel),
                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_batched_kernel),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_batched_kernel),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-void jacobi_eig(hipStream_t s, int batch, int m, const double* A, long sA, double* evals, long sE,
-                double* V, long sV, double* Vwork, int* info) {
-  int M = m + (m & 1);
-  size_t lds = (size_t)M * (M + 1) / 2 * sizeof(double) + (size_t)(M / 2) * (3 * sizeof(double) + 3 * sizeof(int));
-  hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(1024), lds, s, m, A, sA, evals, sE, V, sV,
-                     Vwork, 40, info);
+void jacobi_eig(hipStream_t s, int batch, int m, const double* A, long sA, int nparts,
+                long pstride, double* evals, long sE, double* V, long sV, double* Vwork, int* info) {
+  const int vl = jacobi_v_in_lds(m) ? 1 : 0;
+  size_t lds = jacobi_lds_doubles(m, vl) * sizeof(double);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(JAC_THREADS), lds, s, m, A, sA,
+                     nparts < 1 ? 1 : nparts, pstride, evals, sE, V, sV, Vwork, vl, 40, info);
 }
 
 }  // namespace rmc

@@ -27,6 +27,22 @@ rmc_module* api_couple(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_bon
                        std::vector<double>& evals, rmc_level_report* rep);
 void api_release_basis(rmc_ctx* ctx, rmc_module* m);
 void api_free_module(rmc_ctx* ctx, rmc_module* m);
+std::vector<rmc_module*> api_leaf_solve_batch(rmc_ctx* ctx,
+                                              const std::vector<const rmc_leaf_desc*>& leaves,
+                                              const std::vector<int>& ks,
+                                              const std::vector<int>& q_only,
+                                              const rmc_solve_opts& o,
+                                              std::vector<std::vector<double>>& evals,
+                                              std::vector<rmc_level_report>* reps);
+std::vector<rmc_module*> api_couple_batch(rmc_ctx* ctx, const std::vector<rmc_module*>& As,
+                                          const std::vector<rmc_module*>& Bs,
+                                          const std::vector<const rmc_bond_desc*>& bonds,
+                                          const std::vector<char>& want,
+                                          const std::vector<int>& k_keep, const std::vector<int>& q,
+                                          const rmc_solve_opts& o,
+                                          std::vector<std::vector<double>>& evals,
+                                          std::vector<rmc_level_report>* reps);
+size_t api_arena_free(rmc_ctx* ctx);
 }  // namespace rmc
 
 using namespace rmc;
@@ -194,84 +210,255 @@ void add_record(rmc_report* rep, const rmc_level_report& r) {
   rep->n_records++;
 }
 
-// Runs the plan; fills energies (q). Modules created are freed before return.
-void run_plan(rmc_ctx* ctx, const rmc_chain_desc* c, const Plan& P, const rmc_solve_opts& o,
-              double* energies, rmc_report* rep) {
-  std::vector<rmc_module*> by_key(P.n_keys, nullptr);
+// One job in flight: its plan, its modules (by structural key) and its results.
+struct JobRun {
+  const rmc_chain_desc* c = nullptr;
+  Plan P;
+  std::vector<rmc_module*> by_key;
   std::vector<rmc_module*> created;
-  double t0 = now_ms();
+  std::vector<double> e;
+  rmc_report* rep = nullptr;
+  rmc_status status = RMC_OK;
+  std::string err;
+  double t0 = 0.0;
+  int level = 0;  // next level to run
+  int max_level = 0;
+  bool done = false;
+};
+
+void job_init(JobRun& J, const rmc_chain_desc* c, rmc_report* rep) {
+  J.c = c;
+  J.P = make_plan(c);
+  J.by_key.assign(J.P.n_keys, nullptr);
+  J.e.assign(c->q, NAN);
+  J.rep = rep;
+  J.t0 = now_ms();
+  J.level = 0;
+  J.max_level = 0;
+  for (const Node& nd : J.P.nodes) J.max_level = std::max(J.max_level, nd.level);
   if (rep) {
     rep->n_records = 0;
     rep->n_leaf_ed = 0;
     rep->n_merges = 0;
   }
-  try {
-    const Node& root = P.nodes[P.root];
-    if (root.kind == 0) {  // a single leaf: its lowest q eigenvalues
-      rmc_leaf_desc ld{root.b - root.a, (int)root.terms.size(), root.terms.data()};
-      std::vector<double> ev;
-      rmc_level_report r{};
-      api_leaf_solve(ctx, &ld, c->k, c->q, o, ev, &r);
-      r.kind = 2;
-      r.width = ld.n_sites;
-      add_record(rep, r);
-      if (rep) rep->n_leaf_ed++;
-      for (int i = 0; i < c->q; ++i) energies[i] = ev[i];
-    } else {
-      for (size_t i = 0; i < P.nodes.size(); ++i) {
-        const Node& nd = P.nodes[i];
-        rmc_level_report r{};
-        r.level = nd.level;
-        r.width = nd.b - nd.a;
-        r.kind = nd.kind == 0 ? 0 : (nd.root ? 2 : 1);
-        if (!nd.root && by_key[nd.key]) {
-          r.reused = 1;
-          r.k_eff = by_key[nd.key]->k_eff;
-          r.gap = by_key[nd.key]->gap;
-          add_record(rep, r);
-          continue;
-        }
-        rmc_module* m = nullptr;
-        std::vector<double> ev;
-        if (nd.kind == 0) {
-          rmc_leaf_desc ld{nd.b - nd.a, (int)nd.terms.size(), nd.terms.data()};
-          m = api_leaf_solve(ctx, &ld, c->k, 0, o, ev, &r);
-          if (rep) rep->n_leaf_ed++;
-        } else {
-          rmc_module* A = by_key[P.nodes[nd.left].key];
-          rmc_module* B = by_key[P.nodes[nd.right].key];
-          RMC_CHECK(A && B, RMC_ERR_STATE, "child module missing");
-          std::vector<double> coef;
-          std::vector<int> ia, ib;
-          for (const CutTerm& ct : nd.cut) {
-            coef.push_back(ct.coef);
-            ia.push_back(api_project_op(ctx, A, ct.sa, ct.oa));
-            ib.push_back(api_project_op(ctx, B, ct.sb, ct.ob));
-          }
-          rmc_bond_desc bd{(int)coef.size(), coef.data(), ia.data(), ib.data()};
-          if (nd.root) {
-            api_couple(ctx, A, B, &bd, c->k, c->q, o, false, ev, &r);
-            for (int q = 0; q < c->q; ++q) energies[q] = ev[q];
-          } else {
-            m = api_couple(ctx, A, B, &bd, c->k, std::min(c->q, c->k), o, true, ev, &r);
-          }
-          if (rep) rep->n_merges++;
-        }
-        if (m) {
-          created.push_back(m);
-          for (auto& so : P.need[nd.key]) api_project_op(ctx, m, so.first, so.second);
-          api_release_basis(ctx, m);
-          by_key[nd.key] = m;
-        }
-        add_record(rep, r);
+}
+
+void job_release(rmc_ctx* ctx, JobRun& J) {
+  for (rmc_module* m : J.created) api_free_module(ctx, m);
+  J.created.clear();
+  std::fill(J.by_key.begin(), J.by_key.end(), nullptr);
+}
+
+void job_fail(rmc_ctx* ctx, JobRun& J, rmc_status st, const std::string& msg) {
+  J.status = st;
+  J.err = msg;
+  J.done = true;
+  job_release(ctx, J);
+}
+
+// Bytes one coupling step (or leaf solve) of dimension n, nev wanted, needs.
+size_t task_bytes(int n, int nev) {
+  const size_t m = (size_t)std::min(n, nev + std::max(8, (nev + 7) / 8) + 8);
+  return (7 * m * n + 6 * m * m + 64 * m * m) * sizeof(double) + (size_t)n * 64 + (1 << 16);
+}
+
+struct Task {
+  JobRun* J;
+  int node;
+};
+
+// Runs one level (the next level of every job in `jobs`) as batched solves.
+void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o) {
+  std::vector<Task> leaf_t, merge_t, reused;
+  for (JobRun* J : jobs) {
+    if (J->done) continue;
+    const int L = J->level;
+    std::vector<char> seen(J->P.n_keys, 0);
+    for (size_t i = 0; i < J->P.nodes.size(); ++i) {
+      const Node& nd = J->P.nodes[i];
+      if (nd.level != L) continue;
+      const bool single = (int)i == J->P.root && nd.kind == 0;
+      if (!nd.root && !single && (J->by_key[nd.key] || seen[nd.key])) {
+        reused.push_back(Task{J, (int)i});
+        continue;
+      }
+      seen[nd.key] = 1;
+      (nd.kind == 0 ? leaf_t : merge_t).push_back(Task{J, (int)i});
+    }
+  }
+  // memory-admitted chunks
+  auto chunks = [&](std::vector<Task>& T, auto size_of) {
+    std::vector<std::vector<Task>> out;
+    const size_t budget = api_arena_free(ctx) / 2;
+    size_t acc = 0;
+    for (const Task& t : T) {
+      size_t b = size_of(t);
+      if (!out.empty() && acc + b <= budget) {
+        out.back().push_back(t);
+        acc += b;
+      } else {
+        out.push_back({t});
+        acc = b;
       }
     }
-  } catch (...) {
-    for (rmc_module* m : created) api_free_module(ctx, m);
-    throw;
+    return out;
+  };
+  auto after_module = [&](JobRun* J, int node, rmc_module* m, rmc_level_report r,
+                          const std::vector<double>& ev) {
+    const Node& nd = J->P.nodes[node];
+    r.level = nd.level;
+    r.width = nd.b - nd.a;
+    if (m) {
+      J->created.push_back(m);
+      for (auto& so : J->P.need[nd.key]) api_project_op(ctx, m, so.first, so.second);
+      api_release_basis(ctx, m);
+      J->by_key[nd.key] = m;
+    } else {  // root: energies
+      for (int q = 0; q < J->c->q; ++q) J->e[q] = ev[q];
+    }
+    add_record(J->rep, r);
+    if (J->rep) (nd.kind == 0 ? J->rep->n_leaf_ed : J->rep->n_merges)++;
+  };
+  // leaves
+  for (auto& ch : chunks(leaf_t, [&](const Task& t) {
+         const Node& nd = t.J->P.nodes[t.node];
+         const int D = 1 << (nd.b - nd.a);
+         return task_bytes(D, std::min(D, t.J->c->k + 1)) + (size_t)D * D * 8;
+       })) {
+    auto solve = [&](std::vector<Task>& C) {
+      std::vector<rmc_leaf_desc> lds(C.size());
+      std::vector<const rmc_leaf_desc*> lp;
+      std::vector<int> ks, qo;
+      for (size_t i = 0; i < C.size(); ++i) {
+        const Node& nd = C[i].J->P.nodes[C[i].node];
+        lds[i] = rmc_leaf_desc{nd.b - nd.a, (int)nd.terms.size(), nd.terms.data()};
+        lp.push_back(&lds[i]);
+        ks.push_back(C[i].J->c->k);
+        const bool single = C[i].node == C[i].J->P.root;
+        qo.push_back(single ? C[i].J->c->q : 0);
+      }
+      std::vector<std::vector<double>> ev;
+      std::vector<rmc_level_report> reps;
+      auto mods = api_leaf_solve_batch(ctx, lp, ks, qo, o, ev, &reps);
+      for (size_t i = 0; i < C.size(); ++i) {
+        reps[i].kind = qo[i] > 0 ? 2 : 0;
+        after_module(C[i].J, C[i].node, mods[i], reps[i], ev[i]);
+      }
+    };
+    try {
+      solve(ch);
+    } catch (const Error& e) {
+      if (ch.size() == 1) {
+        job_fail(ctx, *ch[0].J, e.code, e.what());
+        continue;
+      }
+      for (Task& t : ch) {  // isolate the failing job(s)
+        if (t.J->done) continue;
+        std::vector<Task> one{t};
+        try {
+          solve(one);
+        } catch (const Error& e2) {
+          job_fail(ctx, *t.J, e2.code, e2.what());
+        }
+      }
+    }
   }
-  for (rmc_module* m : created) api_free_module(ctx, m);
-  if (rep) rep->total_ms = now_ms() - t0;
+  // merges
+  for (auto& ch : chunks(merge_t, [&](const Task& t) {
+         const Node& nd = t.J->P.nodes[t.node];
+         rmc_module* A = t.J->by_key[t.J->P.nodes[nd.left].key];
+         rmc_module* B = t.J->by_key[t.J->P.nodes[nd.right].key];
+         const int n = (A && B) ? A->k_eff * B->k_eff : 1;
+         return task_bytes(n, nd.root ? t.J->c->q : t.J->c->k + 1);
+       })) {
+    auto solve = [&](std::vector<Task>& C) {
+      std::vector<rmc_module*> As, Bs;
+      std::vector<std::vector<double>> coefs(C.size());
+      std::vector<std::vector<int>> ia(C.size()), ib(C.size());
+      std::vector<rmc_bond_desc> bds(C.size());
+      std::vector<const rmc_bond_desc*> bp;
+      std::vector<char> want;
+      std::vector<int> kk, qq;
+      std::vector<Task> live;
+      for (size_t i = 0; i < C.size(); ++i) {
+        JobRun* J = C[i].J;
+        if (J->done) continue;
+        const Node& nd = J->P.nodes[C[i].node];
+        rmc_module* A = J->by_key[J->P.nodes[nd.left].key];
+        rmc_module* B = J->by_key[J->P.nodes[nd.right].key];
+        RMC_CHECK(A && B, RMC_ERR_STATE, "child module missing");
+        const size_t w = live.size();
+        for (const CutTerm& ct : nd.cut) {
+          coefs[w].push_back(ct.coef);
+          ia[w].push_back(api_project_op(ctx, A, ct.sa, ct.oa));
+          ib[w].push_back(api_project_op(ctx, B, ct.sb, ct.ob));
+        }
+        bds[w] = rmc_bond_desc{(int)coefs[w].size(), coefs[w].data(), ia[w].data(), ib[w].data()};
+        As.push_back(A);
+        Bs.push_back(B);
+        want.push_back(nd.root ? 0 : 1);
+        kk.push_back(J->c->k);
+        qq.push_back(nd.root ? J->c->q : std::min(J->c->q, J->c->k));
+        live.push_back(C[i]);
+      }
+      for (size_t w = 0; w < live.size(); ++w) bp.push_back(&bds[w]);
+      if (live.empty()) return;
+      std::vector<std::vector<double>> ev;
+      std::vector<rmc_level_report> reps;
+      auto mods = api_couple_batch(ctx, As, Bs, bp, want, kk, qq, o, ev, &reps);
+      for (size_t i = 0; i < live.size(); ++i) after_module(live[i].J, live[i].node, mods[i], reps[i], ev[i]);
+    };
+    try {
+      solve(ch);
+    } catch (const Error& e) {
+      if (ch.size() == 1) {
+        job_fail(ctx, *ch[0].J, e.code, e.what());
+        continue;
+      }
+      for (Task& t : ch) {
+        if (t.J->done) continue;
+        std::vector<Task> one{t};
+        try {
+          solve(one);
+        } catch (const Error& e2) {
+          job_fail(ctx, *t.J, e2.code, e2.what());
+        }
+      }
+    }
+  }
+  for (const Task& t : reused) {  // records of modules computed once and reused
+    if (t.J->done) continue;
+    const Node& nd = t.J->P.nodes[t.node];
+    rmc_level_report r{};
+    r.level = nd.level;
+    r.width = nd.b - nd.a;
+    r.kind = nd.kind;
+    r.reused = 1;
+    if (rmc_module* m = t.J->by_key[nd.key]) {
+      r.k_eff = m->k_eff;
+      r.gap = m->gap;
+    }
+    add_record(t.J->rep, r);
+  }
+  for (JobRun* J : jobs) {
+    if (J->done) continue;
+    if (J->level >= J->max_level) {
+      J->done = true;
+      if (J->rep) J->rep->total_ms = now_ms() - J->t0;
+      job_release(ctx, *J);
+    } else {
+      J->level++;
+    }
+  }
+}
+
+void run_jobs(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o) {
+  for (;;) {
+    bool any = false;
+    for (JobRun* J : jobs) any = any || !J->done;
+    if (!any) break;
+    run_level(ctx, jobs, o);
+  }
 }
 
 template <class F>
@@ -302,10 +489,12 @@ rmc_status rmc_recurse(rmc_ctx* ctx, const rmc_chain_desc* chain, const rmc_solv
     rmc_default_opts(&o);
     if (opts) o = *opts;
     RMC_CHECK(o.precision >= RMC_FP64 && o.precision <= RMC_BF16, RMC_ERR_ARG, "bad precision");
-    Plan P = make_plan(chain);
-    std::vector<double> e(chain->q);
-    run_plan(ctx, chain, P, o, e.data(), report);
-    for (int i = 0; i < chain->q; ++i) energies[i] = e[i];
+    JobRun J;
+    job_init(J, chain, report);
+    std::vector<JobRun*> jobs{&J};
+    run_jobs(ctx, jobs, o);
+    if (J.status != RMC_OK) throw Error(J.status, J.err);
+    for (int i = 0; i < chain->q; ++i) energies[i] = J.e[i];
   });
 }
 
@@ -314,16 +503,33 @@ rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_chain_desc* cha
                              int* status_host) {
   if (!ctx) return RMC_ERR_ARG;
   if (n_jobs < 0 || (n_jobs > 0 && (!chains || !energies))) return RMC_ERR_ARG;
-  rmc_status worst = RMC_OK;
-  for (int j = 0; j < n_jobs; ++j) {
-    if (chains[j].q > q_stride) {
-      if (status_host) status_host[j] = RMC_ERR_ARG;
-      worst = RMC_ERR_ARG;
-      continue;
+  std::vector<JobRun> runs(n_jobs);
+  std::vector<int> st(n_jobs, RMC_OK);
+  rmc_status top = guard(ctx, [&] {
+    rmc_solve_opts o;
+    rmc_default_opts(&o);
+    if (opts) o = *opts;
+    RMC_CHECK(o.precision >= RMC_FP64 && o.precision <= RMC_BF16, RMC_ERR_ARG, "bad precision");
+    std::vector<JobRun*> live;
+    for (int j = 0; j < n_jobs; ++j) {
+      try {
+        validate_chain(&chains[j]);
+        RMC_CHECK(chains[j].q <= q_stride, RMC_ERR_ARG, "q above q_stride");
+        job_init(runs[j], &chains[j], nullptr);
+        live.push_back(&runs[j]);
+      } catch (const Error& e) {
+        st[j] = e.code;
+      }
     }
-    rmc_status st = rmc_recurse(ctx, &chains[j], opts, energies + (size_t)j * q_stride, nullptr);
-    if (status_host) status_host[j] = st;
-    if (st != RMC_OK) worst = st;
+    run_jobs(ctx, live, o);
+  });
+  rmc_status worst = top;
+  for (int j = 0; j < n_jobs; ++j) {
+    if (st[j] == RMC_OK) st[j] = runs[j].status;
+    if (st[j] == RMC_OK && top == RMC_OK)
+      for (int i = 0; i < chains[j].q; ++i) energies[(size_t)j * q_stride + i] = runs[j].e[i];
+    if (status_host) status_host[j] = top != RMC_OK ? top : st[j];
+    if (st[j] != RMC_OK && worst == RMC_OK) worst = (rmc_status)st[j];
   }
   return worst;
 }

@@ -1,0 +1,87 @@
+// Per-problem descriptors of the batched ("grouped") kernels: one launch covers
+// every active problem of a level, blockIdx.z selecting the problem. All
+// pointers are device pointers; descriptors live in device memory.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace rmc {
+
+// out_j = s1 (sum_i c_i O_A^i Y_j O_B^iT + Ediag .* Y_j) + s2 Y_j + s3 Xprev_j
+//         + s1 phi[j] E_j   (E, phi optional), j < nv.
+struct KronDesc {
+  int kA, kB, T, nv;
+  const double* coef;
+  const double* OA;
+  const double* OB;
+  const double* Ediag;
+  const double* Y;
+  const double* Xprev;
+  const double* E;
+  const double* phi;
+  double* out;
+  double s1, s2, s3;
+};
+
+// C = alpha op(A) op(B) + beta C (row-major); with `work` non-null the launch
+// writes split-K partials to work (ksplit x M x N) instead of C.
+struct GemmDesc {
+  int M, N, K, pad;
+  const double* A;
+  const double* B;
+  double* C;
+  long lda, ldb, ldc;
+  double alpha, beta;
+  double* work;
+};
+
+// Symmetric eigensolver / Cholesky on m x m given as nparts partials (pstride apart).
+struct EigDesc {
+  int m, nparts;
+  const double* A;
+  long pstride;
+  double* evals;
+  double* V;
+  double* Vwork;
+  int* info;
+};
+struct CholDesc {
+  int m, nparts;
+  const double* G;
+  long pstride;
+  double* Linv;
+  int* info;
+  double shift;  // added to the diagonal when info[1] == 1 on entry (retry)
+};
+
+// Row-block vector operations over nv rows of length n.
+enum VecOp { VEC_NORMALIZE = 0, VEC_RESIDUAL = 1, VEC_SCALE_ADD = 2, VEC_COPY = 3, VEC_AXPY3 = 4 };
+struct VecDesc {
+  int nv, n;
+  double* out;        // NORMALIZE: rows to normalise; others: output
+  const double* P;    // RESIDUAL: HX; SCALE_ADD: P; COPY: src; AXPY3: Y
+  const double* Q;    // RESIDUAL: X;  SCALE_ADD: Q (nullable); AXPY3: Xprev (nullable)
+  const double* a;    // RESIDUAL: theta; SCALE_ADD: per-row scale
+  double* norms;      // NORMALIZE / RESIDUAL output (nv)
+  double asgn, b, c;  // SCALE_ADD: out = asgn a_j P + b Q; AXPY3: out += b Y + c Q
+};
+
+// Start block: the m smallest D entries as unit vectors plus eps * uniform(-1,1).
+struct StartDesc {
+  int n, m;
+  const double* D;
+  int* sel;
+  double* X;
+  double eps;
+  unsigned long long seed;
+};
+
+void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
+                  int precision);
+void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int Mmax, int Nmax,
+                  int ksplit);
+void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax);
+void chol_batched(hipStream_t s, const CholDesc* d, int P, int mmax);
+void vec_batched(hipStream_t s, VecOp op, const VecDesc* d, int P, int nvmax, long elems_max);
+void start_batched(hipStream_t s, const StartDesc* d, int P, int nmax, int mmax);
+
+}  // namespace rmc

@@ -103,6 +103,9 @@ struct rmc_ctx {
   std::vector<hipEvent_t> ev_pool;
   long long prof_launches = 0;
   double prof_flops = 0.0, prof_bytes = 0.0, prof_ms = 0.0;
+  // pinned host staging of the batched solver's descriptor tables
+  char* pinned = nullptr;
+  size_t pinned_cap = 0;
 };
 
 namespace rmc {
@@ -132,6 +135,7 @@ struct CoupledOp {
 struct SolveStats {
   int iters = 0;
   int matvecs = 0;
+  int rr_sweeps = 0;
   double max_res = 0.0;
   int status = RMC_OK;
 };
@@ -139,13 +143,20 @@ struct SolveStats {
 // Block apply: out = s1 * (H Y) + s2 * Y + s3 * Xprev for nv vectors (rows).
 void op_apply(rmc_ctx* ctx, const CoupledOp& op, int nv, const double* Y, double* out,
               const double* Xprev, double s1, double s2, double s3, double* zwork,
-              double* kwork, int precision);
+              double* kwork, int precision, const double* Ecorr = nullptr,
+              const double* phi = nullptr);
 size_t op_zwork_doubles(const CoupledOp& op, int nv);
 
 // Lowest nev eigenpairs of op. X_out: device nev x n (rows = eigenvectors);
 // evals: host nev. Returns RMC_OK or RMC_ERR_NOCONV.
 int eig_lowest(rmc_ctx* ctx, const CoupledOp& op, int nev, const rmc_solve_opts& o,
                double* X_out, std::vector<double>& evals, SolveStats& st);
+
+// Batched form: lowest nevs[i] eigenpairs of each operator (all of one kind).
+void eig_lowest_batch(rmc_ctx* ctx, const std::vector<const CoupledOp*>& ops,
+                      const std::vector<int>& nevs, const rmc_solve_opts& o,
+                      const std::vector<double*>& X_out, std::vector<std::vector<double>>& evals,
+                      std::vector<SolveStats>& stats);
 
 // Gap rule (k_req < len(w) required for a cut); returns k_eff, gap.
 int gap_cut(const std::vector<double>& w, int k_req, double tau, double* gap);

@@ -15,6 +15,10 @@ void gemm_f64(hipStream_t s, bool tA, bool tB, int M, int N, int K, double alpha
               double beta, double* C, long ldc, long sC, int batch, int ksplit, double* work);
 // Pick a split-K factor for an M x N x K product so the launch covers the chip.
 int gemm_pick_ksplit(int M, int N, int K, int batch);
+// Split-K product that leaves its ksplit partial sums (each M x N, batch-major)
+// in `work` for a consumer that adds them; returns the split used.
+int gemm_f64_partials(hipStream_t s, bool tA, bool tB, int M, int N, int K, const double* A,
+                      long lda, const double* B, long ldb, int ksplit, double* work);
 
 // Y_out = Y_out + s1 * diag .* Y + s2 * Y + s3 * Xprev over nv vectors of length n
 // (diag may be null; Xprev may be null when s3 == 0).
@@ -29,14 +33,17 @@ void residual_norms(hipStream_t s, int nv, int n, const double* HX, const double
                     const double* theta, double* res);
 
 // Cholesky G + shift*I = L L^T (m x m, m <= 192) and Linv = L^{-1} (lower, m x m).
+// G is the sum of nparts split-K partials spaced pstride apart.
 // info[0] = 0 on success, 1 if a pivot was not positive.
-void chol_inv(hipStream_t s, int m, const double* G, double shift, double* Linv, int* info);
+void chol_inv(hipStream_t s, int m, const double* G, int nparts, long pstride, double shift,
+              double* Linv, int* info);
 
 // Parallel cyclic Jacobi eigensolver of `batch` symmetric m x m matrices (m <= 192,
 // symmetrised as (A + A^T)/2). evals ascending, V columns = eigenvectors.
 // Vwork: batch*m*m scratch. info[b] = sweeps used, negative if not converged.
-void jacobi_eig(hipStream_t s, int batch, int m, const double* A, long sA, double* evals,
-                long sE, double* V, long sV, double* Vwork, int* info);
+// A[b] is the sum of nparts partials spaced pstride apart.
+void jacobi_eig(hipStream_t s, int batch, int m, const double* A, long sA, int nparts,
+                long pstride, double* evals, long sE, double* V, long sV, double* Vwork, int* info);
 int jacobi_max_m();
 
 // Dense leaf Hamiltonian from a device term list (bit-index assembly).
@@ -66,6 +73,10 @@ void vec_max(hipStream_t s, int n, const double* v, double* out);
 // times a counter-based uniform(-1,1) perturbation; X is m x n.
 void start_block(hipStream_t s, int n, int m, const double* D, double eps,
                  unsigned long long seed, int* sel, double* X);
+
+// out_j = asgn * a[j] * P_j + b * Q_j (Q may be null) for nv rows of length n.
+void rows_scale_add(hipStream_t s, int nv, int n, double* out, const double* P, const double* a,
+                    double asgn, double b, const double* Q);
 
 // out = src (m x n), strided copy helpers.
 void copy_rows(hipStream_t s, int nv, int n, const double* src, long ld_src, double* dst,

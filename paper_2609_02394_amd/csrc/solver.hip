@@ -1,73 +1,42 @@
-// Matrix-free eigensolver for the lowest eigenpairs of a module-coupling step.
+// Matrix-free eigensolver for the lowest eigenpairs of module-coupling steps,
+// batched: every problem of a level (across jobs) advances in lockstep and each
+// device step is one launch over all active problems (per-problem descriptors).
 //
 // The paper assembles the k_A k_B square effective Hamiltonian and diagonalises it
 // fully (reduced eigenproblem; dense eigensolve of App. A). Here the operator is
-// only applied to blocks of vectors, and the lowest nev eigenpairs are found by a
+// only applied to blocks of vectors, and the lowest nev eigenpairs come from a
 // Chebyshev-filtered block subspace iteration with Rayleigh-Ritz (a block
-// Davidson-type method in which the Chebyshev filter plays the role of the
-// correction step):
-//   1. start block: the m lowest diagonal product states plus a small seeded
-//      random component; CholeskyQR2; Rayleigh-Ritz;
+// Davidson-type method whose correction step is a polynomial filter):
+//   1. start block: the m lowest diagonal entries as unit vectors plus a small
+//      seeded random component; CholeskyQR2; Rayleigh-Ritz;
 //   2. repeat: filter the unconverged Ritz vectors with a scaled Chebyshev
-//      polynomial that damps [theta_{m-1}, upper bound] (degree chosen from the
-//      residuals), orthogonalise against the locked vectors (twice), CholeskyQR2,
-//      Rayleigh-Ritz on the filtered block, residual norms, lock converged ones;
-//   3. a final Rayleigh-Ritz over the whole block and a final FP64 residual check.
-// Everything on the device is FP64 except, in the FP32/BF16 forms, the operator
-// applications inside the filter.
+//      polynomial damping [theta_{m-1}, upper bound] (degree from the residuals),
+//      orthogonalise twice against the locked vectors, CholeskyQR2 (a shifted
+//      first pass and a third pass if a pivot fails), Rayleigh-Ritz on the
+//      filtered block (Jacobi), residual norms, lock the converged leading ones;
+//   3. a final Rayleigh-Ritz over the whole block and the FP64 residual check.
+// Coupling steps filter in the residual-driven (defect) form
+//   Y_k = X phi_k(Theta) + D_k,  E = H X - X Theta (FP64),
+//   D_1 = (sigma_1/e) E,  D_{k+1} = (2 sigma_{k+1}/e)[(H - c) D_k + E phi_k(Theta)]
+//                                  - sigma_k sigma_{k+1} D_{k-1},
+// in which only H D_k runs in the requested precision (FP64, FP32 or BF16 MFMA):
+// its rounding error scales with the defect D, so the FP64 Rayleigh-Ritz and
+// residual check recover full accuracy. A problem whose low-precision filter
+// stops reducing the residual 10x per iteration moves up (BF16 -> FP32 -> FP64).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <cstring>
+#include <functional>
 #include <vector>
 
+#include "rmc_batch.h"
 #include "rmc_internal.h"
 
 namespace rmc {
-
-void kron_apply_fused(hipStream_t s, const CoupledOp& op, int nv, const double* Y, double* out,
-                      const double* Xprev, double s1, double s2, double s3, int precision);
-
-size_t op_zwork_doubles(const CoupledOp& op, int nv) { return 1; }
-
-void op_apply(rmc_ctx* ctx, const CoupledOp& op, int nv, const double* Y, double* out,
-              const double* Xprev, double s1, double s2, double s3, double* zwork, double* kwork,
-              int precision) {
-  hipStream_t s = ctx->stream;
-  const int n = op.n;
-  if (op.kind == 0) {
-    gemm_f64(s, false, true, nv, n, n, s1, Y, n, 0, op.H, n, 0, 0.0, out, n, 0, 1,
-             gemm_pick_ksplit(nv, n, n, 1), kwork);
-    axpy_epilogue(s, nv, n, out, Y, Xprev, nullptr, s1, s2, s3, false);
-    return;
-  }
-  if (!ctx->prof) {
-    kron_apply_fused(s, op, nv, Y, out, Xprev, s1, s2, s3, precision);
-    return;
-  }
-  auto take = [&]() {
-    hipEvent_t e;
-    if (!ctx->ev_pool.empty()) {
-      e = ctx->ev_pool.back();
-      ctx->ev_pool.pop_back();
-    } else {
-      RMC_HIP(hipEventCreate(&e));
-    }
-    return e;
-  };
-  rmc_ctx::ProfRec r;
-  r.a = take();
-  r.b = take();
-  RMC_HIP(hipEventRecord(r.a, s));
-  kron_apply_fused(s, op, nv, Y, out, Xprev, s1, s2, s3, precision);
-  RMC_HIP(hipEventRecord(r.b, s));
-  const double nn = (double)n;
-  r.flops = (double)nv * (2.0 * op.T * nn * (op.kA + op.kB) + 4.0 * nn);
-  r.bytes = 8.0 * nn * ((double)nv * (s3 != 0.0 ? 3.0 : 2.0) + 1.0) +
-            8.0 * op.T * ((double)op.kA * op.kA + (double)op.kB * op.kB);
-  ctx->prof_recs.push_back(r);
-}
 
 int gap_cut(const std::vector<double>& w, int k_req, double tau, double* gap) {
   int n = (int)w.size();
@@ -94,220 +63,817 @@ int gap_cut(const std::vector<double>& w, int k_req, double tau, double* gap) {
 
 namespace {
 
-struct Work {
-  int n, m;
-  double *X, *HX, *Yb[3], *Z, *G, *S, *Linv, *Vwork, *theta, *res, *norms, *P, *kwork, *scal;
-  int *sel, *info;
-};
-
 void sync(rmc_ctx* ctx) { RMC_HIP(hipStreamSynchronize(ctx->stream)); }
 
-// Orthonormalise rows Y[0..cnt) against the locked rows L[0..nlock) and among
-// themselves (two projection passes, then CholeskyQR2, a third pass if the first
-// Cholesky needed a shift).
-void orthonormalize(rmc_ctx* ctx, Work& w, double*& Y, double* spare, int cnt, const double* L,
-                    int nlock) {
-  hipStream_t s = ctx->stream;
-  const int n = w.n;
-  row_norms(s, cnt, n, Y, w.norms, true);
-  if (nlock > 0) {
-    for (int pass = 0; pass < 2; ++pass) {
-      gemm_f64(s, false, true, cnt, nlock, n, 1.0, Y, n, 0, L, n, 0, 0.0, w.P, nlock, 0, 1,
-               gemm_pick_ksplit(cnt, nlock, n, 1), w.kwork);
-      gemm_f64(s, false, false, cnt, n, nlock, -1.0, w.P, nlock, 0, L, n, 0, 1.0, Y, n, 0, 1, 1,
-               nullptr);
+// Descriptor tables uploaded in one copy per phase: host staging (pinned, owned by
+// the ctx) mirrored into a device region of the arena.
+struct DescArena {
+  rmc_ctx* ctx;
+  char* dev = nullptr;
+  size_t cap = 0, used = 0, flushed = 0;
+  DescArena(rmc_ctx* c, Scratch& sc, size_t bytes) : ctx(c) {
+    cap = bytes;
+    dev = sc.get<char>(bytes);
+    if (ctx->pinned_cap < bytes) {
+      if (ctx->pinned) RMC_HIP(hipHostFree(ctx->pinned));
+      ctx->pinned = nullptr;
+      ctx->pinned_cap = 0;
+      RMC_HIP(hipHostMalloc((void**)&ctx->pinned, bytes));
+      ctx->pinned_cap = bytes;
     }
-    row_norms(s, cnt, n, Y, w.norms, true);
   }
-  int passes = 2;
-  for (int pass = 0; pass < passes; ++pass) {
-    gemm_f64(s, false, true, cnt, cnt, n, 1.0, Y, n, 0, Y, n, 0, 0.0, w.G, cnt, 0, 1,
-             gemm_pick_ksplit(cnt, cnt, n, 1), w.kwork);
-    chol_inv(s, cnt, w.G, 0.0, w.Linv, w.info);
-    int info = 0;
-    RMC_HIP(hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s));
-    sync(ctx);
-    if (info != 0) {
-      // shifted CholeskyQR (trace(G) = cnt for normalised rows)
-      double u = 1.1102230246251565e-16;
-      double shift = 11.0 * ((double)n * cnt + (double)cnt * (cnt + 1)) * u * (double)cnt;
-      chol_inv(s, cnt, w.G, shift, w.Linv, w.info);
-      RMC_HIP(hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s));
-      sync(ctx);
-      RMC_CHECK(info == 0, RMC_ERR_NOCONV, "CholeskyQR failed even with a shift");
-      if (passes < 3) passes = 3;
+  template <class T>
+  T* add(const T* p, size_t count) {
+    size_t off = (used + 63) & ~(size_t)63;
+    size_t b = count * sizeof(T);
+    RMC_CHECK(off + b <= cap, RMC_ERR_OOM, "descriptor table overflow");
+    if (b) memcpy(ctx->pinned + off, p, b);
+    used = off + b;
+    return reinterpret_cast<T*>(dev + off);
+  }
+  template <class T>
+  T* add(const std::vector<T>& v) {
+    return add(v.data(), v.size());
+  }
+  // Launches are queued and issued after one upload of everything added so far.
+  std::vector<std::function<void()>> pending;
+  void defer(std::function<void()> f) { pending.push_back(std::move(f)); }
+  void flush() {
+    if (used > flushed)
+      RMC_HIP(hipMemcpyAsync(dev + flushed, ctx->pinned + flushed, used - flushed,
+                             hipMemcpyHostToDevice, ctx->stream));
+    flushed = used;
+    for (auto& f : pending) f();
+    pending.clear();
+  }
+  void reset() { used = flushed = 0; }  // only after the stream has been synchronised
+};
+
+struct BP {
+  const CoupledOp* op;
+  double* Xout;
+  int n, m, nev, guard;
+  double *X, *HX, *Y[3], *E, *S, *Linv, *Vwork, *Pm, *kwork;
+  double *theta, *res;
+  int* info;
+  int* sel;
+  // host state
+  std::vector<double> th, rs;
+  int nlock = 0, nw = 0, prec = RMC_FP64, iters = 0, matvecs = 0, rr_sweeps = 0, cnt = 0;
+  int state = 0;  // 0 active, 1 converged, 2 retry with more guard vectors, 3 out of iterations
+  int deg = 2;
+  double prev_worst = INFINITY, scale = 1.0, a = 0, b = 0, c = 0, e = 1, sigma1 = 0;
+  int shifted = 0;
+};
+
+struct Batch {
+  rmc_ctx* ctx;
+  int kind;
+  int KS = 1;  // split-K of the Gram products
+  int mmax = 0, nmax = 0, kAmax = 0, kBmax = 0;
+  DescArena* da;
+  double* TR = nullptr;  // per-problem theta / res / info block
+  long trs = 0;          // its stride (doubles)
+  std::vector<double> TRh;
+};
+
+// Row-block roles: 0..2 = Y[i], 3 = X + nlock rows, 4 = HX + nlock rows, 5 = E,
+// 6 = X (row 0), 7 = HX (row 0).
+double* role_ptr(BP* p, int role) {
+  switch (role) {
+    case 0: case 1: case 2: return p->Y[role];
+    case 3: return p->X + (size_t)p->nlock * p->n;
+    case 4: return p->HX + (size_t)p->nlock * p->n;
+    case 5: return p->E;
+    case 6: return p->X;
+    case 7: return p->HX;
+  }
+  return nullptr;
+}
+
+void vec_launch(Batch& B, VecOp op, const std::vector<VecDesc>& d) {
+  if (d.empty()) return;
+  int nvmax = 0;
+  long emax = 0;
+  for (auto& x : d) {
+    nvmax = std::max(nvmax, x.nv);
+    emax = std::max(emax, (long)x.nv * x.n);
+  }
+  const VecDesc* dd = B.da->add(d);
+  hipStream_t st = B.ctx->stream;
+  const int P = (int)d.size();
+  B.da->defer([=] { vec_batched(st, op, dd, P, nvmax, emax); });
+}
+
+void gemm_launch(Batch& B, bool tA, bool tB, const std::vector<GemmDesc>& d, int ksplit) {
+  if (d.empty()) return;
+  int Mmax = 0, Nmax = 0;
+  for (auto& x : d) {
+    Mmax = std::max(Mmax, x.M);
+    Nmax = std::max(Nmax, x.N);
+  }
+  const GemmDesc* dd = B.da->add(d);
+  hipStream_t st = B.ctx->stream;
+  const int P = (int)d.size();
+  B.da->defer([=] { gemm_batched(st, tA, tB, dd, P, Mmax, Nmax, ksplit); });
+}
+
+hipEvent_t take_event(rmc_ctx* ctx) {
+  hipEvent_t e;
+  if (!ctx->ev_pool.empty()) {
+    e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+  } else {
+    RMC_HIP(hipEventCreate(&e));
+  }
+  return e;
+}
+
+struct Apply {
+  std::vector<const double*> Y, prev, E, phi;
+  std::vector<double*> out;
+  std::vector<std::array<double, 3>> sc;
+  std::vector<int> cnt;
+};
+
+// out = s1 H Y + s2 Y + s3 Xprev (+ s1 phi E) for every problem of L.
+void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_prec) {
+  if (L.empty()) return;
+  rmc_ctx* ctx = B.ctx;
+  if (B.kind == 0) {  // dense leaf: GEMM then axpy
+    std::vector<GemmDesc> g;
+    std::vector<VecDesc> v;
+    for (size_t i = 0; i < L.size(); ++i) {
+      BP* p = L[i];
+      GemmDesc d{};
+      d.M = a.cnt[i]; d.N = p->n; d.K = p->n;
+      d.A = a.Y[i]; d.lda = p->n;
+      d.B = p->op->H; d.ldb = p->n;
+      d.C = a.out[i]; d.ldc = p->n;
+      d.alpha = a.sc[i][0]; d.beta = 0.0; d.work = nullptr;
+      g.push_back(d);
+      VecDesc w{};
+      w.nv = a.cnt[i]; w.n = p->n; w.out = a.out[i]; w.P = a.Y[i]; w.Q = a.prev[i];
+      w.b = a.sc[i][1]; w.c = a.sc[i][2];
+      v.push_back(w);
     }
-    gemm_f64(s, false, false, cnt, n, cnt, 1.0, w.Linv, cnt, 0, Y, n, 0, 0.0, spare, n, 0, 1, 1,
-             nullptr);
-    std::swap(Y, spare);
+    gemm_launch(B, false, true, g, 1);
+    vec_launch(B, VEC_AXPY3, v);
+    return;
+  }
+  for (int prec = 0; prec < 3; ++prec) {
+    std::vector<KronDesc> kd;
+    int nvmax = 0;
+    for (size_t i = 0; i < L.size(); ++i) {
+      BP* p = L[i];
+      int pr = use_prec ? p->prec : RMC_FP64;
+      if (pr != prec) continue;
+      KronDesc d{};
+      d.kA = p->op->kA; d.kB = p->op->kB; d.T = p->op->T; d.nv = a.cnt[i];
+      d.coef = p->op->coef_dev; d.OA = p->op->OAcat; d.OB = p->op->OBcat; d.Ediag = p->op->Ediag;
+      d.Y = a.Y[i]; d.Xprev = a.prev[i]; d.E = a.E[i]; d.phi = a.phi[i]; d.out = a.out[i];
+      d.s1 = a.sc[i][0]; d.s2 = a.sc[i][1]; d.s3 = a.sc[i][2];
+      kd.push_back(d);
+      nvmax = std::max(nvmax, a.cnt[i]);
+    }
+    if (kd.empty()) continue;
+    const KronDesc* dd = B.da->add(kd);
+    hipStream_t st = ctx->stream;
+    const int P = (int)kd.size(), kBm = B.kBmax, kAm = B.kAmax;
+    if (!ctx->prof) {
+      B.da->defer([=] { kron_batched(st, dd, P, kBm, nvmax, kAm, prec); });
+      continue;
+    }
+    rmc_ctx::ProfRec r;
+    r.a = take_event(ctx);
+    r.b = take_event(ctx);
+    hipEvent_t ea = r.a, eb = r.b;
+    B.da->defer([=] {
+      RMC_HIP(hipEventRecord(ea, st));
+      kron_batched(st, dd, P, kBm, nvmax, kAm, prec);
+      RMC_HIP(hipEventRecord(eb, st));
+    });
+    r.flops = r.bytes = 0.0;
+    for (auto& d : kd) {
+      const double nn = (double)d.kA * d.kB;
+      r.flops += (double)d.nv * (2.0 * d.T * nn * (d.kA + d.kB) + 4.0 * nn);
+      r.bytes += 8.0 * nn * ((double)d.nv * (2.0 + (d.Xprev ? 1.0 : 0.0) + (d.E ? 1.0 : 0.0)) + 1.0) +
+                 8.0 * d.T * ((double)d.kA * d.kA + (double)d.kB * d.kB);
+    }
+    ctx->prof_recs.push_back(r);
   }
 }
 
-// Rayleigh-Ritz of the orthonormal rows Q[0..cnt): W = H Q, G = Q W^T, G = S diag S^T,
-// Xdst = S^T Q, HXdst = S^T W, theta_dst, residuals.
-void rayleigh_ritz(rmc_ctx* ctx, const CoupledOp& op, Work& w, const double* Q, double* Wtmp,
-                   int cnt, double* Xdst, double* HXdst, double* theta_dst, double* res_dst,
-                   bool have_W) {
-  hipStream_t s = ctx->stream;
-  const int n = w.n;
-  if (!have_W) op_apply(ctx, op, cnt, Q, Wtmp, nullptr, 1.0, 0.0, 0.0, w.Z, w.kwork, RMC_FP64);
-  gemm_f64(s, false, true, cnt, cnt, n, 1.0, Q, n, 0, Wtmp, n, 0, 0.0, w.G, cnt, 0, 1,
-           gemm_pick_ksplit(cnt, cnt, n, 1), w.kwork);
-  jacobi_eig(s, 1, cnt, w.G, 0, theta_dst, 0, w.S, 0, w.Vwork, w.info + 1);
-  gemm_f64(s, true, false, cnt, n, cnt, 1.0, w.S, cnt, 0, Q, n, 0, 0.0, Xdst, n, 0, 1, 1, nullptr);
-  gemm_f64(s, true, false, cnt, n, cnt, 1.0, w.S, cnt, 0, Wtmp, n, 0, 0.0, HXdst, n, 0, 1, 1,
-           nullptr);
-  residual_norms(s, cnt, n, HXdst, Xdst, theta_dst, res_dst);
+// Gram partials A B^T (ca x cb per problem) into p->kwork.
+void gram_launch(Batch& B, const std::vector<BP*>& L, const std::vector<const double*>& Ap,
+                 const std::vector<const double*>& Bp, const std::vector<int>& ca,
+                 const std::vector<int>& cb) {
+  std::vector<GemmDesc> g;
+  for (size_t i = 0; i < L.size(); ++i) {
+    BP* p = L[i];
+    GemmDesc d{};
+    d.M = ca[i]; d.N = cb[i]; d.K = p->n;
+    d.A = Ap[i]; d.lda = p->n; d.B = Bp[i]; d.ldb = p->n;
+    d.alpha = 1.0; d.beta = 0.0; d.work = p->kwork;
+    g.push_back(d);
+  }
+  gemm_launch(B, false, true, g, B.KS);
+}
+
+void read_state(Batch& B) {
+  B.da->flush();
+  RMC_HIP(hipMemcpyAsync(B.TRh.data(), B.TR, B.TRh.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         B.ctx->stream));
+  sync(B.ctx);
+  B.da->reset();
+}
+
+int info_of(const Batch& B, int idx, int k) {
+  const int* ip = reinterpret_cast<const int*>(B.TRh.data() + (size_t)idx * B.trs + 2 * B.mmax);
+  return ip[k];
+}
+
+// One CholeskyQR pass from role src to role dst for the problems of L.
+void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst) {
+  const double u = 1.1102230246251565e-16;
+  std::vector<const double*> A;
+  std::vector<int> ca;
+  for (BP* p : L) {
+    A.push_back(role_ptr(p, src));
+    ca.push_back(p->cnt);
+  }
+  gram_launch(B, L, A, A, ca, ca);
+  std::vector<CholDesc> cd;
+  int mm = 0;
+  for (BP* p : L) {
+    CholDesc c{};
+    c.m = p->cnt; c.nparts = B.KS; c.G = p->kwork; c.pstride = (long)p->cnt * p->cnt;
+    c.Linv = p->Linv; c.info = p->info + 2;  // info[2]: failure, info[3]: shifted
+    c.shift = 11.0 * ((double)p->n * p->cnt + (double)p->cnt * (p->cnt + 1)) * u * p->cnt;
+    cd.push_back(c);
+    mm = std::max(mm, p->cnt);
+  }
+  const CholDesc* dd = B.da->add(cd);
+  {
+    hipStream_t st = B.ctx->stream;
+    const int P = (int)cd.size();
+    B.da->defer([=] { chol_batched(st, dd, P, mm); });
+  }
+  std::vector<GemmDesc> g;
+  for (BP* p : L) {
+    GemmDesc d{};
+    d.M = p->cnt; d.N = p->n; d.K = p->cnt;
+    d.A = p->Linv; d.lda = p->cnt; d.B = role_ptr(p, src); d.ldb = p->n;
+    d.C = role_ptr(p, dst); d.ldc = p->n; d.alpha = 1.0; d.beta = 0.0;
+    g.push_back(d);
+  }
+  gemm_launch(B, false, false, g, 1);
+}
+
+// Orthonormalise the cnt rows at Y[r] of each problem against its locked rows
+// X[0..nlock), then among themselves. The result ends in Y[r].
+void orthonormalize(Batch& B, const std::vector<BP*>& L, const std::vector<int>& idx, int r) {
+  std::vector<VecDesc> nd;
+  for (BP* p : L) {
+    VecDesc v{};
+    v.nv = p->cnt; v.n = p->n; v.out = role_ptr(p, r);
+    nd.push_back(v);
+  }
+  vec_launch(B, VEC_NORMALIZE, nd);
+  std::vector<BP*> LL;
+  for (BP* p : L)
+    if (p->nlock > 0) LL.push_back(p);
+  if (!LL.empty()) {
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<GemmDesc> g1, g2;
+      for (BP* p : LL) {
+        GemmDesc d{};
+        d.M = p->cnt; d.N = p->nlock; d.K = p->n;
+        d.A = role_ptr(p, r); d.lda = p->n; d.B = p->X; d.ldb = p->n;
+        d.C = p->Pm; d.ldc = p->nlock; d.alpha = 1.0; d.beta = 0.0;
+        g1.push_back(d);
+        GemmDesc e{};
+        e.M = p->cnt; e.N = p->n; e.K = p->nlock;
+        e.A = p->Pm; e.lda = p->nlock; e.B = p->X; e.ldb = p->n;
+        e.C = role_ptr(p, r); e.ldc = p->n; e.alpha = -1.0; e.beta = 1.0;
+        g2.push_back(e);
+      }
+      gemm_launch(B, false, true, g1, 1);
+      gemm_launch(B, false, false, g2, 1);
+    }
+    std::vector<VecDesc> nd2;
+    for (BP* p : LL) {
+      VecDesc v{};
+      v.nv = p->cnt; v.n = p->n; v.out = role_ptr(p, r);
+      nd2.push_back(v);
+    }
+    vec_launch(B, VEC_NORMALIZE, nd2);
+  }
+  const int sp = (r == 0) ? 1 : 0;
+  cholqr_pass(B, L, r, sp);
+  // a pivot failure of the first pass (retried with a shift in the kernel) calls
+  // for a third pass
+  read_state(B);
+  std::vector<BP*> L3;
+  for (size_t i = 0; i < L.size(); ++i) {
+    RMC_CHECK(info_of(B, idx[i], 2) == 0, RMC_ERR_NOCONV, "CholeskyQR failed even with a shift");
+    if (info_of(B, idx[i], 3)) {
+      L3.push_back(L[i]);
+      L[i]->shifted++;
+    }
+  }
+  cholqr_pass(B, L, sp, r);
+  if (!L3.empty()) {
+    cholqr_pass(B, L3, r, sp);
+    std::vector<VecDesc> cp;
+    for (BP* p : L3) {
+      VecDesc v{};
+      v.nv = p->cnt; v.n = p->n; v.out = role_ptr(p, r); v.P = role_ptr(p, sp);
+      cp.push_back(v);
+    }
+    vec_launch(B, VEC_COPY, cp);
+  }
+}
+
+// Rayleigh-Ritz of the orthonormal rows at role q (cnt rows), W = H Q into role w
+// (already there when `full`); Ritz pairs into X/HX/theta/res at row offset nlock,
+// or, when `full`, into Y[2]/E/theta/res from row 0.
+void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full) {
+  if (!full) {
+    Apply a;
+    for (BP* p : L) {
+      a.Y.push_back(role_ptr(p, q));
+      a.out.push_back(role_ptr(p, w));
+      a.prev.push_back(nullptr);
+      a.E.push_back(nullptr);
+      a.phi.push_back(nullptr);
+      a.sc.push_back({1.0, 0.0, 0.0});
+      a.cnt.push_back(p->cnt);
+    }
+    apply_launch(B, L, a, false);
+    for (BP* p : L) p->matvecs += p->cnt;
+  }
+  std::vector<const double*> A, Bm;
+  std::vector<int> cnt;
+  for (BP* p : L) {
+    A.push_back(role_ptr(p, q));
+    Bm.push_back(role_ptr(p, w));
+    cnt.push_back(p->cnt);
+  }
+  gram_launch(B, L, A, Bm, cnt, cnt);
+  std::vector<EigDesc> ed;
+  int mm = 0;
+  for (BP* p : L) {
+    EigDesc d{};
+    d.m = p->cnt; d.nparts = B.KS; d.A = p->kwork; d.pstride = (long)p->cnt * p->cnt;
+    d.evals = p->theta + (full ? 0 : p->nlock); d.V = p->S; d.Vwork = p->Vwork; d.info = p->info + 1;
+    ed.push_back(d);
+    mm = std::max(mm, p->cnt);
+  }
+  const EigDesc* dd = B.da->add(ed);
+  {
+    hipStream_t st = B.ctx->stream;
+    const int P = (int)ed.size();
+    B.da->defer([=] { jacobi_batched(st, dd, P, mm); });
+  }
+  std::vector<GemmDesc> g1, g2;
+  for (BP* p : L) {
+    const size_t off = full ? 0 : (size_t)p->nlock * p->n;
+    GemmDesc d{};
+    d.M = p->cnt; d.N = p->n; d.K = p->cnt;
+    d.A = p->S; d.lda = p->cnt; d.B = role_ptr(p, q); d.ldb = p->n;
+    d.C = full ? p->Y[2] : p->X + off; d.ldc = p->n; d.alpha = 1.0; d.beta = 0.0;
+    g1.push_back(d);
+    d.B = role_ptr(p, w);
+    d.C = full ? p->E : p->HX + off;
+    g2.push_back(d);
+  }
+  gemm_launch(B, true, false, g1, 1);
+  gemm_launch(B, true, false, g2, 1);
+  std::vector<VecDesc> rd;
+  for (BP* p : L) {
+    const size_t off = full ? 0 : (size_t)p->nlock * p->n;
+    VecDesc v{};
+    v.nv = p->cnt; v.n = p->n;
+    v.P = full ? p->E : p->HX + off;
+    v.Q = full ? p->Y[2] : p->X + off;
+    v.a = p->theta + (full ? 0 : p->nlock);
+    v.norms = p->res + (full ? 0 : p->nlock);
+    rd.push_back(v);
+  }
+  vec_launch(B, VEC_RESIDUAL, rd);
+}
+
+// Convergence bookkeeping after a state read; returns true if the problem goes on.
+bool update_problem(Batch& B, BP* p, int idx, int max_iter, double tol, int pmax, bool last_attempt) {
+  const int m = p->m, n = p->n, nev = p->nev;
+  const double* t = B.TRh.data() + (size_t)idx * B.trs;
+  p->th.assign(t, t + m);
+  p->rs.assign(t + B.mmax, t + B.mmax + m);
+  p->rr_sweeps += std::abs(info_of(B, idx, 1));
+  const auto& th = p->th;
+  const auto& rs = p->rs;
+  p->scale = std::max({1.0, std::fabs(p->op->bup), std::fabs(th[0])});
+  const double scale = p->scale;
+  // wanted set: the nev lowest plus the rest of the cluster holding theta[nev-1]
+  int nw = nev;
+  while (nw < m && th[nw] - th[nw - 1] <= 1e-6 * scale) ++nw;
+  if (nw >= m && m < n) {
+    // the cluster runs to the end of the block: the filter cannot separate it
+    if (!last_attempt) {
+      p->state = 2;
+      return false;
+    }
+    nw = m;
+  }
+  p->nw = nw;
+  int first_bad = nw;
+  for (int j = 0; j < nw; ++j)
+    if (!(rs[j] <= tol * scale)) {
+      first_bad = j;
+      break;
+    }
+  if (first_bad == nw || m == n) {
+    p->state = 1;
+    return false;
+  }
+  if (p->iters >= max_iter) {
+    p->state = last_attempt ? 3 : 2;
+    return false;
+  }
+  p->nlock = std::max(p->nlock, first_bad);
+  double worst = 0.0;
+  for (int j = p->nlock; j < nw; ++j) worst = std::max(worst, rs[j]);
+  if (p->prec != RMC_FP64 && p->iters > 0 && worst > 0.1 * p->prev_worst)
+    p->prec = p->prec == RMC_BF16 ? RMC_FP32 : RMC_FP64;  // low-precision floor reached
+  p->prev_worst = worst;
+  p->cnt = m - p->nlock;
+  double a = th[m - 1], b = p->op->bup, a0 = th[0];
+  if (!(b > a)) b = a + std::max(1e-3 * std::fabs(a), 1e-6);
+  if (!(a0 < a)) a0 = a - 1e-3 * (b - a);
+  p->a = a;
+  p->b = b;
+  p->e = 0.5 * (b - a);
+  p->c = 0.5 * (b + a);
+  p->sigma1 = p->e / (a0 - p->c);
+  int deg = 2;
+  for (int j = p->nlock; j < nw; ++j) {
+    if (rs[j] <= tol * scale) continue;
+    double x = std::fabs((th[j] - p->c) / p->e);
+    double rho = x > 1.0 ? std::acosh(x) : 1e-3;
+    double need = std::log(2.0 * rs[j] / (tol * scale)) / rho;
+    deg = std::max(deg, (int)std::ceil(need));
+  }
+  p->deg = std::min(std::max(deg, 2), pmax);
+  return true;
+}
+
+// One filter application on the problems of L; returns the Y buffer holding it.
+int filter(Batch& B, const std::vector<BP*>& L) {
+  int P = 0;
+  for (BP* p : L) P = std::max(P, p->deg);
+  if (B.kind == 0) {
+    // dense (leaf): direct scaled recurrence Y_{k+1} = (2s'/e)(H-c)Y_k - s s' Y_{k-1}
+    std::vector<double> sig(L.size());
+    Apply a;
+    for (size_t i = 0; i < L.size(); ++i) {
+      BP* p = L[i];
+      sig[i] = p->sigma1;
+      a.Y.push_back(role_ptr(p, 3));
+      a.out.push_back(role_ptr(p, 0));
+      a.prev.push_back(nullptr);
+      a.E.push_back(nullptr);
+      a.phi.push_back(nullptr);
+      a.sc.push_back({sig[i] / p->e, -p->c * sig[i] / p->e, 0.0});
+      a.cnt.push_back(p->cnt);
+    }
+    apply_launch(B, L, a, false);
+    int prev = 3, cur = 0;
+    for (int k = 2; k <= P; ++k) {
+      int nw = -1;
+      for (int q = 0; q < 3; ++q)
+        if (q != cur && q != prev) {
+          nw = q;
+          break;
+        }
+      a.Y.clear(); a.out.clear(); a.prev.clear(); a.sc.clear();
+      for (size_t i = 0; i < L.size(); ++i) {
+        BP* p = L[i];
+        const double tau2 = 2.0 / p->sigma1;
+        const double s2 = 1.0 / (tau2 - sig[i]);
+        a.Y.push_back(role_ptr(p, cur));
+        a.out.push_back(role_ptr(p, nw));
+        a.prev.push_back(role_ptr(p, prev));
+        a.sc.push_back({2.0 * s2 / p->e, -2.0 * p->c * s2 / p->e, -sig[i] * s2});
+        sig[i] = s2;
+      }
+      apply_launch(B, L, a, false);
+      prev = cur;
+      cur = nw;
+    }
+    for (BP* p : L) p->matvecs += p->cnt * P;
+    return cur;
+  }
+  // Kronecker problems, defect form: E = HX - X Theta on the active rows
+  {
+    std::vector<VecDesc> ed;
+    for (BP* p : L) {
+      VecDesc v{};
+      v.nv = p->cnt; v.n = p->n; v.out = p->E; v.P = role_ptr(p, 3);
+      v.a = p->theta + p->nlock; v.asgn = -1.0; v.b = 1.0; v.Q = role_ptr(p, 4);
+      ed.push_back(v);
+    }
+    vec_launch(B, VEC_SCALE_ADD, ed);
+  }
+  // phi tables: row k holds phi_k at the active Ritz values; row 0 holds sigma_1/e
+  std::vector<double*> phid(L.size());
+  std::vector<std::vector<double>> sigs(L.size());
+  for (size_t i = 0; i < L.size(); ++i) {
+    BP* p = L[i];
+    const int cn = p->cnt;
+    std::vector<double> tab((size_t)(P + 1) * cn);
+    for (int j = 0; j < cn; ++j) tab[j] = p->sigma1 / p->e;
+    std::vector<double> pm1(cn, 1.0), pk(cn);
+    for (int j = 0; j < cn; ++j) {
+      pk[j] = (p->sigma1 / p->e) * (p->th[p->nlock + j] - p->c);
+      tab[(size_t)cn + j] = pk[j];
+    }
+    const double tau2 = 2.0 / p->sigma1;
+    double sg = p->sigma1;
+    sigs[i].push_back(sg);
+    for (int k = 1; k < P; ++k) {
+      const double sg2 = 1.0 / (tau2 - sg);
+      for (int j = 0; j < cn; ++j) {
+        double nx = (2.0 * sg2 / p->e) * (p->th[p->nlock + j] - p->c) * pk[j] - sg * sg2 * pm1[j];
+        pm1[j] = pk[j];
+        pk[j] = nx;
+        tab[(size_t)(k + 1) * cn + j] = nx;
+      }
+      sg = sg2;
+      sigs[i].push_back(sg);
+    }
+    phid[i] = B.da->add(tab);
+  }
+  {
+    std::vector<VecDesc> dd;
+    for (size_t i = 0; i < L.size(); ++i) {
+      BP* p = L[i];
+      VecDesc v{};
+      v.nv = p->cnt; v.n = p->n; v.out = p->Y[0]; v.P = p->E; v.a = phid[i]; v.asgn = 1.0;
+      v.b = 0.0; v.Q = nullptr;
+      dd.push_back(v);
+    }
+    vec_launch(B, VEC_SCALE_ADD, dd);  // D_1
+  }
+  int prev = -1, cur = 0;
+  for (int k = 1; k < P; ++k) {
+    int nw = -1;
+    for (int q = 0; q < 3; ++q)
+      if (q != cur && q != prev) {
+        nw = q;
+        break;
+      }
+    Apply a;
+    for (size_t i = 0; i < L.size(); ++i) {
+      BP* p = L[i];
+      const double sk = sigs[i][k - 1], sk1 = sigs[i][k];
+      a.Y.push_back(role_ptr(p, cur));
+      a.out.push_back(role_ptr(p, nw));
+      a.prev.push_back(prev >= 0 ? role_ptr(p, prev) : nullptr);
+      a.E.push_back(p->E);
+      a.phi.push_back(phid[i] + (size_t)k * p->cnt);
+      a.sc.push_back({2.0 * sk1 / p->e, -2.0 * p->c * sk1 / p->e, prev >= 0 ? -sk * sk1 : 0.0});
+      a.cnt.push_back(p->cnt);
+    }
+    apply_launch(B, L, a, true);
+    prev = cur;
+    cur = nw;
+  }
+  const int outr = (cur == 0) ? 1 : 0;
+  {
+    std::vector<VecDesc> dd;
+    for (size_t i = 0; i < L.size(); ++i) {
+      BP* p = L[i];
+      VecDesc v{};
+      v.nv = p->cnt; v.n = p->n; v.out = p->Y[outr]; v.P = role_ptr(p, 3);
+      v.a = phid[i] + (size_t)P * p->cnt; v.asgn = 1.0; v.b = 1.0; v.Q = p->Y[cur];
+      dd.push_back(v);
+    }
+    vec_launch(B, VEC_SCALE_ADD, dd);  // Y_P = X phi_P + D_P
+  }
+  for (BP* p : L) p->matvecs += p->cnt * (P - 1);
+  return outr;
+}
+
+// One attempt at all problems with their current guard sizes.
+void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& o, bool last) {
+  const int JM = jacobi_max_m();
+  Scratch sc(&ctx->arena);
+  Batch B;
+  B.ctx = ctx;
+  B.kind = probs[0]->op->kind;
+  for (BP* p : probs) {
+    p->m = std::min(p->n, p->nev + p->guard);
+    if (p->m > JM) p->m = JM;
+    RMC_CHECK(p->m >= p->nev, RMC_ERR_ARG, "too many eigenpairs requested for the Rayleigh-Ritz size");
+    B.mmax = std::max(B.mmax, p->m);
+    B.nmax = std::max(B.nmax, p->n);
+    B.kAmax = std::max(B.kAmax, p->op->kA);
+    B.kBmax = std::max(B.kBmax, p->op->kB);
+    p->nlock = 0;
+    p->iters = 0;
+    p->state = 0;
+    p->prec = o.precision;
+    p->prev_worst = INFINITY;
+    p->matvecs = 0;
+  }
+  const int P = (int)probs.size();
+  const int t1 = (B.mmax + 63) / 64;
+  B.KS = std::max(1, std::min(64, 512 / std::max(1, P * t1 * t1)));
+  B.trs = 2 * B.mmax + 4;  // theta, res, then room for 8 ints
+  B.TR = sc.get<double>((size_t)P * B.trs);
+  B.TRh.assign((size_t)P * B.trs, 0.0);
+  for (int i = 0; i < P; ++i) {
+    BP* p = probs[i];
+    const size_t mn = (size_t)p->m * p->n;
+    p->X = sc.get<double>(mn);
+    p->HX = sc.get<double>(mn);
+    for (int q = 0; q < 3; ++q) p->Y[q] = sc.get<double>(mn);
+    p->E = sc.get<double>(mn);
+    p->S = sc.get<double>((size_t)p->m * p->m);
+    p->Linv = sc.get<double>((size_t)p->m * p->m);
+    p->Vwork = sc.get<double>((size_t)p->m * p->m);
+    p->Pm = sc.get<double>((size_t)p->m * p->m);
+    p->kwork = sc.get<double>((size_t)B.KS * p->m * p->m);
+    p->theta = B.TR + (size_t)i * B.trs;
+    p->res = p->theta + B.mmax;
+    p->info = reinterpret_cast<int*>(p->res + B.mmax);
+    p->sel = sc.get<int>(p->m);
+  }
+  RMC_HIP(hipMemsetAsync(B.TR, 0, (size_t)P * B.trs * sizeof(double), ctx->stream));
+  const int pmax = o.max_degree > 0 ? o.max_degree : 40;
+  const size_t da_bytes =
+      (size_t)P * ((size_t)(pmax + 4) * B.mmax * 8 + (size_t)(pmax + 48) * 4 * 256) + (1 << 20);
+  DescArena da(ctx, sc, da_bytes);
+  B.da = &da;
+
+  std::vector<int> idx_all(P);
+  for (int i = 0; i < P; ++i) idx_all[i] = i;
+  {
+    std::vector<StartDesc> sd;
+    for (BP* p : probs) {
+      StartDesc d{};
+      d.n = p->n; d.m = p->m; d.D = p->op->D; d.sel = p->sel; d.X = p->Y[0];
+      d.eps = (p->m == p->n) ? 0.0 : 1e-3; d.seed = o.seed;
+      sd.push_back(d);
+    }
+    const StartDesc* dd = da.add(sd);
+    hipStream_t st = ctx->stream;
+    const int nm = B.nmax, mm = B.mmax;
+    da.defer([=] { start_batched(st, dd, P, nm, mm); });
+  }
+  for (BP* p : probs) p->cnt = p->m;
+  orthonormalize(B, probs, idx_all, 0);
+  rayleigh_ritz(B, probs, 0, 1, false);
+
+  const double tol = o.tol > 0 ? o.tol : 1e-13;
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  for (;;) {
+    read_state(B);
+    std::vector<BP*> act;
+    std::vector<int> ai;
+    for (int i = 0; i < P; ++i) {
+      BP* p = probs[i];
+      if (p->state != 0) continue;
+      if (update_problem(B, p, i, max_iter, tol, pmax, last)) {
+        act.push_back(p);
+        ai.push_back(i);
+      }
+    }
+    if (act.empty()) break;
+    const int r = filter(B, act);
+    orthonormalize(B, act, ai, r);
+    rayleigh_ritz(B, act, r, r == 0 ? 1 : 0, false);
+    for (BP* p : act) p->iters++;
+  }
+  // final Rayleigh-Ritz over whole blocks (with the stored H X) and FP64 residual check
+  std::vector<BP*> fin;
+  std::vector<int> fi;
+  for (int i = 0; i < P; ++i)
+    if (probs[i]->state == 1 || probs[i]->state == 3) {
+      fin.push_back(probs[i]);
+      fi.push_back(i);
+    }
+  if (!fin.empty()) {
+    for (BP* p : fin) p->cnt = p->m;
+    rayleigh_ritz(B, fin, 6, 7, true);
+    std::vector<VecDesc> cp;
+    for (BP* p : fin) {
+      VecDesc v{};
+      v.nv = p->nev; v.n = p->n; v.out = p->Xout; v.P = p->Y[2];
+      cp.push_back(v);
+    }
+    vec_launch(B, VEC_COPY, cp);
+    read_state(B);
+    for (size_t t = 0; t < fin.size(); ++t) {
+      BP* p = fin[t];
+      const double* tt = B.TRh.data() + (size_t)fi[t] * B.trs;
+      p->th.assign(tt, tt + p->m);
+      p->rs.assign(tt + B.mmax, tt + B.mmax + p->m);
+      p->rr_sweeps += std::abs(info_of(B, fi[t], 1));
+    }
+  }
 }
 
 }  // namespace
 
+// Lowest nevs[i] eigenpairs of several operators of one kind, in lockstep.
+void eig_lowest_batch(rmc_ctx* ctx, const std::vector<const CoupledOp*>& ops,
+                      const std::vector<int>& nevs, const rmc_solve_opts& o,
+                      const std::vector<double*>& X_out, std::vector<std::vector<double>>& evals,
+                      std::vector<SolveStats>& stats) {
+  const int P = (int)ops.size();
+  evals.assign(P, {});
+  stats.assign(P, SolveStats());
+  if (P == 0) return;
+  const int JM = jacobi_max_m();
+  std::vector<BP> bp(P);
+  std::vector<BP*> todo;
+  for (int i = 0; i < P; ++i) {
+    RMC_CHECK(ops[i]->n >= 1, RMC_ERR_ARG, "empty operator");
+    RMC_CHECK(ops[i]->kind == ops[0]->kind, RMC_ERR_ARG, "mixed operator kinds in one batch");
+    bp[i].op = ops[i];
+    bp[i].n = ops[i]->n;
+    bp[i].nev = std::max(1, std::min(nevs[i], ops[i]->n));
+    bp[i].guard = o.guard > 0 ? o.guard : std::max(8, (bp[i].nev + 7) / 8);
+    bp[i].Xout = X_out[i];
+    todo.push_back(&bp[i]);
+  }
+  for (int attempt = 0; !todo.empty(); ++attempt) {
+    std::vector<BP*> last, more, next;
+    for (BP* p : todo) {
+      const bool is_last = (p->nev + p->guard >= std::min(p->n, JM)) || attempt >= 3;
+      (is_last ? last : more).push_back(p);
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      auto& L = pass == 0 ? more : last;
+      if (L.empty()) continue;
+      solve_attempt(ctx, L, o, pass == 1);
+      for (BP* p : L) {
+        const int i = (int)(p - bp.data());
+        stats[i].iters += p->iters;
+        stats[i].matvecs += p->matvecs;
+        stats[i].rr_sweeps += p->rr_sweeps;
+        p->rr_sweeps = 0;
+        if (p->state == 2) {
+          p->guard = 2 * p->guard + 8;  // a degenerate cluster reaches past the guard vectors
+          next.push_back(p);
+        }
+      }
+    }
+    todo.swap(next);
+  }
+  const double tol = o.tol > 0 ? o.tol : 1e-13;
+  for (int i = 0; i < P; ++i) {
+    BP* p = &bp[i];
+    evals[i].assign(p->th.begin(), p->th.begin() + p->nev);
+    int nwf = p->nev;
+    const double scale = std::max({1.0, std::fabs(p->op->bup), std::fabs(p->th[0])});
+    while (nwf < p->m && p->th[nwf] - p->th[nwf - 1] <= 1e-6 * scale) ++nwf;
+    double mr = 0.0;
+    for (int j = 0; j < std::min(nwf, p->m); ++j) mr = std::max(mr, p->rs[j] / scale);
+    stats[i].max_res = mr;
+    stats[i].status = (p->state == 1 && mr <= 10.0 * tol) ? RMC_OK : RMC_ERR_NOCONV;
+  }
+}
+
 int eig_lowest(rmc_ctx* ctx, const CoupledOp& op, int nev, const rmc_solve_opts& o, double* X_out,
                std::vector<double>& evals, SolveStats& st) {
-  hipStream_t s = ctx->stream;
-  const int n = op.n;
-  RMC_CHECK(n >= 1, RMC_ERR_ARG, "empty operator");
-  if (nev > n) nev = n;
-  RMC_CHECK(nev >= 1, RMC_ERR_ARG, "nev < 1");
-  const int JM = jacobi_max_m();
-  int guard = o.guard > 0 ? o.guard : std::max(8, (nev + 7) / 8);
-  int m = std::min(n, nev + guard);
-  if (m > JM) m = JM;
-  RMC_CHECK(m >= nev, RMC_ERR_ARG, "too many eigenpairs requested for the Rayleigh-Ritz size");
-  RMC_CHECK(m == n || m > nev, RMC_ERR_ARG, "no guard vectors left");
-
-  Scratch sc(&ctx->arena);
-  Work w;
-  w.n = n;
-  w.m = m;
-  w.X = sc.get<double>((size_t)m * n);
-  w.HX = sc.get<double>((size_t)m * n);
-  for (int i = 0; i < 3; ++i) w.Yb[i] = sc.get<double>((size_t)m * n);
-  w.Z = sc.get<double>(op_zwork_doubles(op, m));
-  w.G = sc.get<double>((size_t)m * m);
-  w.S = sc.get<double>((size_t)m * m);
-  w.Linv = sc.get<double>((size_t)m * m);
-  w.Vwork = sc.get<double>((size_t)m * m);
-  w.theta = sc.get<double>(m);
-  w.res = sc.get<double>(m);
-  w.norms = sc.get<double>(m);
-  w.P = sc.get<double>((size_t)m * m);
-  size_t kw = 64 * (size_t)m * std::max(m, 1) + 64 * (size_t)std::max(m, 64) * 64;
-  if (op.kind == 0) kw = std::max(kw, (size_t)64 * m * n);
-  w.kwork = sc.get<double>(kw);
-  w.scal = sc.get<double>(4);
-  w.sel = sc.get<int>(m);
-  w.info = sc.get<int>(4);
-  double* D = op.D;
-
-  // start block
-  double eps0 = (m == n) ? 0.0 : 1e-3;
-  start_block(s, n, m, D, eps0, o.seed, w.sel, w.X);
-  double* Y = w.Yb[0];
-  double* spare = w.Yb[1];
-  copy_rows(s, m, n, w.X, n, Y, n);
-  orthonormalize(ctx, w, Y, spare, m, nullptr, 0);
-  double* Wt = (Y == w.Yb[0]) ? w.Yb[1] : w.Yb[0];
-  rayleigh_ritz(ctx, op, w, Y, Wt, m, w.X, w.HX, w.theta, w.res, false);
-  st.matvecs = m;
-
-  std::vector<double> th(m), rs(m);
-  const double tol = o.tol > 0 ? o.tol : 1e-13;
-  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
-  const int pmax = o.max_degree > 0 ? o.max_degree : 40;
-  const int prec = o.precision;
-  int nlock = 0;
-  int status = RMC_ERR_NOCONV;
-  double scale = 1.0;
-  int it = 0;
-  for (;; ++it) {
-    RMC_HIP(hipMemcpyAsync(th.data(), w.theta, m * sizeof(double), hipMemcpyDeviceToHost, s));
-    RMC_HIP(hipMemcpyAsync(rs.data(), w.res, m * sizeof(double), hipMemcpyDeviceToHost, s));
-    sync(ctx);
-    scale = std::max({1.0, std::fabs(op.bup), std::fabs(th[0])});
-    int first_bad = nev;
-    for (int j = 0; j < nev; ++j)
-      if (!(rs[j] <= tol * scale)) {
-        first_bad = j;
-        break;
-      }
-    if (first_bad == nev || m == n) {
-      status = RMC_OK;
-      break;
-    }
-    if (it >= max_iter) break;
-    nlock = std::max(nlock, first_bad);
-    const int cnt = m - nlock;
-    double a = th[m - 1], b = op.bup, a0 = th[0];
-    if (!(b > a)) b = a + std::max(1e-3 * std::fabs(a), 1e-6);
-    if (!(a0 < a)) a0 = a - 1e-3 * (b - a);
-    const double e = 0.5 * (b - a), c = 0.5 * (b + a);
-    // degree from the slowest unconverged wanted pair
-    int p = 2;
-    for (int j = nlock; j < nev; ++j) {
-      if (rs[j] <= tol * scale) continue;
-      double x = std::fabs((th[j] - c) / e);
-      double rho = x > 1.0 ? std::acosh(x) : 1e-3;
-      double need = std::log(2.0 * rs[j] / (tol * scale)) / rho;
-      p = std::max(p, (int)std::ceil(need));
-    }
-    p = std::min(std::max(p, 2), pmax);
-    // scaled Chebyshev filter on X[nlock..m)
-    const double* Xa = w.X + (size_t)nlock * n;
-    double sigma = e / (a0 - c);
-    const double tau2 = 2.0 / sigma;
-    op_apply(ctx, op, cnt, Xa, w.Yb[0], nullptr, sigma / e, -c * sigma / e, 0.0, w.Z, w.kwork,
-             prec);
-    const double* prev = Xa;
-    double* cur = w.Yb[0];
-    for (int i = 2; i <= p; ++i) {
-      double sig2 = 1.0 / (tau2 - sigma);
-      double* nw = nullptr;
-      for (int q = 0; q < 3 && !nw; ++q)
-        if (w.Yb[q] != cur && w.Yb[q] != prev) nw = w.Yb[q];
-      op_apply(ctx, op, cnt, cur, nw, prev, 2.0 * sig2 / e, -2.0 * c * sig2 / e, -sigma * sig2,
-               w.Z, w.kwork, prec);
-      prev = cur;
-      cur = nw;
-      sigma = sig2;
-    }
-    double* Ycur = cur;
-    st.matvecs += cnt * p;
-    // buffers: Ycur holds the filtered block; pick a spare among Yb not equal to Ycur/Xp
-    double* sp = nullptr;
-    for (int i = 0; i < 3; ++i)
-      if (w.Yb[i] != Ycur) { sp = w.Yb[i]; break; }
-    double* Q = Ycur;
-    orthonormalize(ctx, w, Q, sp, cnt, w.X, nlock);
-    double* Wt2 = nullptr;
-    for (int i = 0; i < 3; ++i)
-      if (w.Yb[i] != Q) { Wt2 = w.Yb[i]; break; }
-    rayleigh_ritz(ctx, op, w, Q, Wt2, cnt, w.X + (size_t)nlock * n, w.HX + (size_t)nlock * n,
-                  w.theta + nlock, w.res + nlock, false);
-    st.matvecs += cnt;
-  }
-  st.iters = it;
-  // final Rayleigh-Ritz over the whole block with the stored H X, and residual check
-  {
-    gemm_f64(s, false, true, m, m, n, 1.0, w.X, n, 0, w.HX, n, 0, 0.0, w.G, m, 0, 1,
-             gemm_pick_ksplit(m, m, n, 1), w.kwork);
-    jacobi_eig(s, 1, m, w.G, 0, w.theta, 0, w.S, 0, w.Vwork, w.info + 1);
-    gemm_f64(s, true, false, m, n, m, 1.0, w.S, m, 0, w.X, n, 0, 0.0, w.Yb[0], n, 0, 1, 1, nullptr);
-    gemm_f64(s, true, false, m, n, m, 1.0, w.S, m, 0, w.HX, n, 0, 0.0, w.Yb[1], n, 0, 1, 1,
-             nullptr);
-    residual_norms(s, m, n, w.Yb[1], w.Yb[0], w.theta, w.res);
-    copy_rows(s, nev, n, w.Yb[0], n, X_out, n);
-  }
-  RMC_HIP(hipMemcpyAsync(th.data(), w.theta, m * sizeof(double), hipMemcpyDeviceToHost, s));
-  RMC_HIP(hipMemcpyAsync(rs.data(), w.res, m * sizeof(double), hipMemcpyDeviceToHost, s));
-  sync(ctx);
-  evals.assign(th.begin(), th.begin() + nev);
-  double mr = 0.0;
-  for (int j = 0; j < nev; ++j) mr = std::max(mr, rs[j] / scale);
-  st.max_res = mr;
-  if (status == RMC_OK && mr > 10.0 * tol) status = RMC_ERR_NOCONV;
-  st.status = status;
-  return status;
+  std::vector<std::vector<double>> ev;
+  std::vector<SolveStats> ss;
+  eig_lowest_batch(ctx, {&op}, {nev}, o, {X_out}, ev, ss);
+  evals = ev[0];
+  st = ss[0];
+  return st.status;
 }
+
+// One block apply through the batched kernel (used by rmc_kron_apply).
+void op_apply(rmc_ctx* ctx, const CoupledOp& op, int nv, const double* Y, double* out,
+              const double* Xprev, double s1, double s2, double s3, double*, double*, int precision,
+              const double* Ecorr, const double* phi) {
+  RMC_CHECK(op.kind == 1, RMC_ERR_ARG, "op_apply supports Kronecker operators");
+  Scratch sc(&ctx->arena);
+  KronDesc d{};
+  d.kA = op.kA; d.kB = op.kB; d.T = op.T; d.nv = nv;
+  d.coef = op.coef_dev; d.OA = op.OAcat; d.OB = op.OBcat; d.Ediag = op.Ediag;
+  d.Y = Y; d.Xprev = s3 != 0.0 ? Xprev : nullptr; d.E = Ecorr; d.phi = phi; d.out = out;
+  d.s1 = s1; d.s2 = s2; d.s3 = s3;
+  KronDesc* dd = sc.get<KronDesc>(1);
+  RMC_HIP(hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream));
+  kron_batched(ctx->stream, dd, 1, op.kB, nv, op.kA, precision);
+  sync(ctx);
+}
+
+size_t op_zwork_doubles(const CoupledOp&, int) { return 1; }
 
 }  // namespace rmc

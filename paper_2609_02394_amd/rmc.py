@@ -57,7 +57,7 @@ class SolveOpts(C.Structure):
 class LevelReport(C.Structure):
     _fields_ = [("level", C.c_int), ("width", C.c_int), ("kind", C.c_int), ("k_req", C.c_int),
                 ("k_eff", C.c_int), ("iters", C.c_int), ("matvecs", C.c_int), ("reused", C.c_int),
-                ("gap", C.c_double), ("max_res", C.c_double), ("ms", C.c_double)]
+                ("rr_sweeps", C.c_int), ("gap", C.c_double), ("max_res", C.c_double), ("ms", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -273,3 +273,84 @@ def test_error_paths(ctx):
     # the context still works afterwards
     e, _ = ctx.recurse(*rmc.job_chain(W.tfim_small()))
     assert rel_err(e, OR.recurse(W.tfim_small()).energies) <= 1e-10
+
+
+# -- mixed precision (FP32 / BF16 Kronecker matvecs, FP64 residual correction) -----
+
+MIXED_CASES = [
+    ("xxz_N16_L4_k16", W.ChainJob("xxz", 16, 4, 16, 6, J=1.0, delta=1.0)),
+    ("rfheis_N32_k48", W.ChainJob("rfheis", 32, 8, 48, 8, J=1.0, fields=W.rfheis_batch(2)[1].fields)),
+    ("tfim_N64_k32", W.ChainJob("tfim", 64, 8, 32, 8, J=1.0, h=0.9)),
+]
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16"])
+@pytest.mark.parametrize("name,job", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_recurse_mixed_precision_matches_oracle(ctx, name, job, prec):
+    from paper_2609_02394_amd import rmc
+
+    say("recurse mixed", name, prec)
+    e, rep = ctx.recurse(*rmc.job_chain(job), opts=rmc.default_opts(precision=prec))
+    ref = OR.recurse(job)
+    assert rel_err(e, ref.energies) <= 1e-8, (e, ref.energies)
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16"])
+def test_recurse_mixed_precision_xxz_chain64(ctx, prec):
+    from paper_2609_02394_amd import rmc
+
+    say("recurse mixed xxz N=64", prec)
+    job = W.xxz_chain64()
+    e, rep = ctx.recurse(*rmc.job_chain(job), opts=rmc.default_opts(precision=prec))
+    e64, _ = ctx.recurse(*rmc.job_chain(job))
+    assert rel_err(e, e64) <= 1e-8, (e, e64)
+
+
+# -- batched levels (many jobs per launch) -----------------------------------------
+
+def _batch_jobs():
+    jobs = W.rfheis_batch(6)                                   # k drawn from {32,48,64,96}
+    jobs.append(W.ChainJob("tfim", 32, 8, 16, 4, J=1.0, h=0.8))
+    jobs.append(W.ChainJob("xxz", 16, 4, 16, 6, J=1.0, delta=0.6))
+    jobs.append(W.ChainJob("xxz", 8, 8, 12, 5, J=1.0, delta=1.3))   # single leaf
+    return jobs
+
+
+def test_recurse_batch_matches_single_jobs(ctx):
+    from paper_2609_02394_amd import rmc
+
+    say("recurse_batch vs single")
+    jobs = _batch_jobs()
+    e, st, top = ctx.recurse_batch([rmc.job_chain(j) for j in jobs])
+    assert top == rmc.OK and all(s == rmc.OK for s in st), st
+    for i, j in enumerate(jobs):
+        e1, _ = ctx.recurse(*rmc.job_chain(j))
+        assert rel_err(e[i, : j.q], e1) <= 1e-10, (i, e[i], e1)
+    for i in (0, 6, 7, 8):
+        assert rel_err(e[i, : jobs[i].q], OR.recurse(jobs[i]).energies) <= 1e-10
+
+
+def test_recurse_batch_isolates_bad_job(ctx):
+    from paper_2609_02394_amd import rmc
+
+    say("recurse_batch bad job")
+    good = W.ChainJob("tfim", 16, 4, 8, 4, J=1.0, h=0.7)
+    chains = [rmc.job_chain(good), (16, 4, rmc.job_chain(good)[2], 4, 6), rmc.job_chain(good)]
+    e, st, top = ctx.recurse_batch(chains)
+    assert st[1] == rmc.ERR_ARG and st[0] == rmc.OK and st[2] == rmc.OK
+    ref = OR.recurse(good).energies
+    assert rel_err(e[0, :4], ref) <= 1e-10 and rel_err(e[2, :4], ref) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16"])
+def test_recurse_batch_mixed_precision(ctx, prec):
+    from paper_2609_02394_amd import rmc
+
+    say("recurse_batch mixed", prec)
+    jobs = _batch_jobs()
+    e64, _, _ = ctx.recurse_batch([rmc.job_chain(j) for j in jobs])
+    e, st, top = ctx.recurse_batch([rmc.job_chain(j) for j in jobs],
+                                   opts=rmc.default_opts(precision=prec))
+    assert all(s == rmc.OK for s in st)
+    for i, j in enumerate(jobs):
+        assert rel_err(e[i, : j.q], e64[i, : j.q]) <= 1e-8
