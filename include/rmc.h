@@ -191,6 +191,26 @@ rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_chain_desc* cha
                              const rmc_solve_opts* opts, double* energies_host,
                              int q_stride, int* status_host);
 
+/* Serving (continuous batching). rmc_serve_start starts a scheduler thread that
+ * owns the ctx's stream and arena until rmc_serve_stop; other calls on the ctx
+ * return RMC_ERR_STATE meanwhile. Each scheduler step admits queued jobs while
+ * at most max_inflight are in flight and their estimated device memory fits in
+ * mem_budget bytes (0 = half the arena), then advances every job in flight by
+ * one tree level in one batched level solve, so jobs that arrive while others run
+ * share the device with them. Module bases and projected operators stay
+ * device-resident between a job's levels. */
+rmc_status rmc_serve_start(rmc_ctx* ctx, const rmc_solve_opts* opts, int max_inflight,
+                           size_t mem_budget);
+/* Queue a job (the descriptor and its terms are copied); never blocks. A job that
+ * can never fit the budget completes at once with RMC_ERR_OOM. */
+rmc_status rmc_submit(rmc_ctx* ctx, const rmc_chain_desc* chain, unsigned long long* job_id);
+/* done = 1 once finished; then energies (q), the job's status and its latency
+ * (submission to completion, ms) are written and the result is released. */
+rmc_status rmc_poll(rmc_ctx* ctx, unsigned long long job_id, int* done, double* energies_host,
+                    int* job_status, double* latency_ms);
+/* Finish every queued and in-flight job, then stop the scheduler thread. */
+rmc_status rmc_serve_stop(rmc_ctx* ctx);
+
 /* Module inspection and lifetime. */
 rmc_status rmc_module_info(const rmc_module* m, int* k_eff, int* dim, int* n_sites,
                            double* energies_host /* k_eff, may be NULL */);

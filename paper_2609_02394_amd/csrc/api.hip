@@ -89,6 +89,7 @@ namespace {
 template <class F>
 rmc_status guard(rmc_ctx* ctx, F&& f) {
   try {
+    RMC_CHECK(!ctx || !ctx->serving, RMC_ERR_STATE, "the context is serving; stop it first");
     f();
     return RMC_OK;
   } catch (const rmc::Error& e) {
@@ -577,8 +578,11 @@ rmc_status rmc_create(rmc_ctx** out, int device, void* arena_dev, size_t arena_b
   return RMC_OK;
 }
 
+rmc_status rmc_serve_stop(rmc_ctx* ctx);
+
 rmc_status rmc_destroy(rmc_ctx* ctx) {
   if (!ctx) return RMC_ERR_ARG;
+  if (ctx->serving) rmc_serve_stop(ctx);
   hipStreamSynchronize(ctx->stream);
   for (rmc_module* m : ctx->modules) delete m;
   ctx->modules.clear();

@@ -104,7 +104,9 @@ __device__ inline typename KTraits<P>::acc mma_tile(typename KTraits<P>::acc acc
   const int g = lane >> 4;
   if constexpr (P == 0 || P == 1) {
     // K in chunks of 64: all operands of a chunk are loaded before its 16 MFMAs so
-    // the loads overlap. Within a step of 16, lane group g takes k = kb + 4g + s.
+    // the loads overlap; two accumulators alternate so consecutive MFMAs do not
+    // wait on each other. Within a step of 16, lane group g takes k = kb + 4g + s.
+    typename KTraits<P>::acc acc2 = {0, 0, 0, 0};
     for (int kc = 0; kc < K; kc += 64) {
       double av[16], bv[16];
 #pragma unroll
@@ -117,13 +119,17 @@ __device__ inline typename KTraits<P>::acc mma_tile(typename KTraits<P>::acc acc
           bv[4 * u + s] = ok ? bfn(k) : 0.0;
         }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        if constexpr (P == 0)
+      for (int u = 0; u < 16; u += 2) {
+        if constexpr (P == 0) {
           acc = Mfma<0>::step(av[u] * scale, bv[u], acc);
-        else
+          acc2 = Mfma<0>::step(av[u + 1] * scale, bv[u + 1], acc2);
+        } else {
           acc = Mfma<1>::step((float)(av[u] * scale), (float)bv[u], acc);
+          acc2 = Mfma<1>::step((float)(av[u + 1] * scale), (float)bv[u + 1], acc2);
+        }
       }
     }
+    acc += acc2;
   } else {
     // K step of 32: lane group g takes k = kb + 8g + s, s = 0..7
     for (int kb = 0; kb < K; kb += 32) {
@@ -142,6 +148,69 @@ __device__ inline typename KTraits<P>::acc mma_tile(typename KTraits<P>::acc acc
     }
   }
   return acc;
+}
+
+// Stage-1 product of one 16-row tile for up to KR_TCH terms: z[t] += Yrow . OBrow_t
+// (K = kB), the Y operand loaded once per K chunk and shared by the terms.
+template <int P>
+__device__ inline void stage1_tile(typename KTraits<P>::acc* z, int tn, const double* __restrict__ yrow,
+                                   bool rok, int K, const double* __restrict__ obrow, bool bok,
+                                   long tstride) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+  if constexpr (P == 0 || P == 1) {
+    for (int kc = 0; kc < K; kc += 64) {
+      double av[16];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = kc + 16 * u + 4 * g + s;
+          av[4 * u + s] = (rok && k < K) ? yrow[k] : 0.0;
+        }
+#pragma unroll
+      for (int t = 0; t < KR_TCH; ++t) {
+        if (t >= tn) break;
+        const double* ob = obrow + t * tstride;
+        double bv[16];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int k = kc + 16 * u + 4 * g + s;
+            bv[4 * u + s] = (bok && k < K) ? ob[k] : 0.0;
+          }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          if constexpr (P == 0)
+            z[t] = Mfma<0>::step(av[u], bv[u], z[t]);
+          else
+            z[t] = Mfma<1>::step((float)av[u], (float)bv[u], z[t]);
+        }
+      }
+    }
+  } else {
+    for (int kc = 0; kc < K; kc += 32) {
+      bf8 a8;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int k = kc + 8 * g + s;
+        a8[s] = (__bf16)(float)((rok && k < K) ? yrow[k] : 0.0);
+      }
+#pragma unroll
+      for (int t = 0; t < KR_TCH; ++t) {
+        if (t >= tn) break;
+        const double* ob = obrow + t * tstride;
+        bf8 b8;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int k = kc + 8 * g + s;
+          b8[s] = (__bf16)(float)((bok && k < K) ? ob[k] : 0.0);
+        }
+        z[t] = Mfma<2>::step(a8, b8, z[t]);
+      }
+    }
+  }
 }
 
 // One workgroup: vector j of descriptor d, output columns [b0, b0+16).
@@ -165,9 +234,9 @@ __device__ void kron_body(const KronDesc& d, int j, int b0, char* smem_raw) {
 
   for (int t0 = 0; t0 < T; t0 += KR_TCH) {
     const int tn = min(KR_TCH, T - t0);
-    // stage 1: Z_i = Y_j (O_B^i[tile,:])^T, rows = a, cols = tile, K = kB
-    for (int ti = 0; ti < tn; ++ti) {
-      const double* OBi = d.OB + (long)(t0 + ti) * kB * kB;
+    // stage 1: Z_i = Y_j (O_B^i[tile,:])^T, rows = a, cols = tile, K = kB; the rows
+    // of Y_j are loaded once per K chunk for all terms of the chunk
+    {
       const int bcol = b0 + l16;
       const bool bok = bcol < kB;
 #pragma unroll
@@ -175,12 +244,19 @@ __device__ void kron_body(const KronDesc& d, int j, int b0, char* smem_raw) {
         const int rt = wave + 4 * q;
         if (rt >= RT) break;
         const int row = rt * 16 + l16;
-        accT z = accT{0, 0, 0, 0};
-        z = mma_tile<P>(z, Yj, kB, row, row < kA, kB, 1.0,
-                        [&](int k) -> double { return bok ? OBi[(long)bcol * kB + k] : 0.0; });
-        zt* Zt = Zs + ((long)ti * kApad) * 16;
+        const bool rok = row < kA;
+        accT z[KR_TCH];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Zt[(rt * 16 + acc_row<P>(g, r)) * 16 + l16] = (zt)z[r];
+        for (int ti = 0; ti < KR_TCH; ++ti) z[ti] = accT{0, 0, 0, 0};
+        stage1_tile<P>(z, tn, Yj + (long)row * kB, rok, kB,
+                       d.OB + (long)t0 * kB * kB + (long)bcol * kB, bok, (long)kB * kB);
+#pragma unroll
+        for (int ti = 0; ti < KR_TCH; ++ti) {
+          if (ti >= tn) break;
+          zt* Zt = Zs + ((long)ti * kApad) * 16;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Zt[(rt * 16 + acc_row<P>(g, r)) * 16 + l16] = (zt)z[ti][r];
+        }
       }
     }
     __syncthreads();

@@ -9,10 +9,15 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
+#include <deque>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rmc_internal.h"
@@ -461,9 +466,120 @@ void run_jobs(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o)
   }
 }
 
+// ---- serving (continuous batching) ------------------------------------------------
+
+struct ServeJob {
+  unsigned long long id = 0;
+  rmc_chain_desc desc{};
+  std::vector<rmc_term> terms;
+  double t_submit = 0.0;
+  size_t mem = 0;
+  JobRun run;
+};
+
+struct ServeResult {
+  std::vector<double> e;
+  int status = RMC_OK;
+  double latency_ms = 0.0;
+};
+
+struct ServeState {
+  rmc_ctx* ctx = nullptr;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool stop = false;
+  rmc_solve_opts opts{};
+  int max_inflight = 64;
+  size_t budget = 0;
+  std::deque<std::unique_ptr<ServeJob>> queue;
+  std::vector<std::unique_ptr<ServeJob>> inflight;  // scheduler thread only
+  std::set<unsigned long long> pending;             // queued or in flight
+  std::map<unsigned long long, ServeResult> done;
+  unsigned long long next_id = 1;
+  size_t inflight_mem = 0;
+  std::string fatal;
+};
+
+// Device memory a job needs at its widest level (solver workspace of the distinct
+// modules of that level), from its plan.
+size_t job_memory(const Plan& P, int k) {
+  std::map<int, std::set<int>> keys_by_level;
+  std::map<int, int> dim_by_level;
+  for (const Node& nd : P.nodes) {
+    keys_by_level[nd.level].insert(nd.key);
+    int dim = nd.kind == 0 ? (1 << (nd.b - nd.a)) : k * k;
+    dim_by_level[nd.level] = std::max(dim_by_level[nd.level], dim);
+  }
+  size_t best = 0;
+  for (auto& kv : keys_by_level) {
+    const int dim = dim_by_level[kv.first];
+    size_t b = kv.second.size() * (task_bytes(dim, std::min(dim, k + 1)) + (size_t)dim * 64);
+    best = std::max(best, b);
+  }
+  return best + (size_t)P.n_keys * 6 * (size_t)k * k * sizeof(double);
+}
+
+void serve_loop(ServeState* S) {
+  rmc_ctx* ctx = S->ctx;
+  hipSetDevice(ctx->device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->inflight.empty(); });
+      if (S->stop && S->queue.empty() && S->inflight.empty()) break;
+      // admission: slots and memory
+      while (!S->queue.empty() && (int)S->inflight.size() < S->max_inflight) {
+        ServeJob* j = S->queue.front().get();
+        if (j->mem > S->budget) {
+          ServeResult r;
+          r.status = RMC_ERR_OOM;
+          r.latency_ms = now_ms() - j->t_submit;
+          S->done[j->id] = r;
+          S->pending.erase(j->id);
+          S->queue.pop_front();
+          continue;
+        }
+        if (!S->inflight.empty() && S->inflight_mem + j->mem > S->budget) break;
+        S->inflight_mem += j->mem;
+        S->inflight.push_back(std::move(S->queue.front()));
+        S->queue.pop_front();
+      }
+    }
+    std::vector<JobRun*> runs;
+    for (auto& j : S->inflight) runs.push_back(&j->run);
+    try {
+      run_level(ctx, runs, S->opts);
+    } catch (const Error& e) {
+      for (JobRun* J : runs)
+        if (!J->done) job_fail(ctx, *J, e.code, e.what());
+    } catch (const std::exception& e) {
+      for (JobRun* J : runs)
+        if (!J->done) job_fail(ctx, *J, RMC_ERR_STATE, e.what());
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t i = 0; i < S->inflight.size();) {
+      ServeJob* j = S->inflight[i].get();
+      if (!j->run.done) {
+        ++i;
+        continue;
+      }
+      ServeResult r;
+      r.e = j->run.e;
+      r.status = j->run.status;
+      r.latency_ms = now_ms() - j->t_submit;
+      S->done[j->id] = std::move(r);
+      S->pending.erase(j->id);
+      S->inflight_mem -= j->mem;
+      S->inflight.erase(S->inflight.begin() + i);
+    }
+  }
+}
+
 template <class F>
 rmc_status guard(rmc_ctx* ctx, F&& f) {
   try {
+    RMC_CHECK(!ctx || !ctx->serving, RMC_ERR_STATE, "the context is serving; stop it first");
     f();
     return RMC_OK;
   } catch (const rmc::Error& e) {
@@ -532,6 +648,87 @@ rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_chain_desc* cha
     if (st[j] != RMC_OK && worst == RMC_OK) worst = (rmc_status)st[j];
   }
   return worst;
+}
+
+rmc_status rmc_serve_start(rmc_ctx* ctx, const rmc_solve_opts* opts, int max_inflight,
+                           size_t mem_budget) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    RMC_CHECK(max_inflight >= 1, RMC_ERR_ARG, "max_inflight must be >= 1");
+    auto* S = new ServeState();
+    S->ctx = ctx;
+    rmc_default_opts(&S->opts);
+    if (opts) S->opts = *opts;
+    RMC_CHECK(S->opts.precision >= RMC_FP64 && S->opts.precision <= RMC_BF16, RMC_ERR_ARG,
+              "bad precision");
+    S->max_inflight = max_inflight;
+    S->budget = mem_budget ? mem_budget : ctx->arena.size() / 2;
+    RMC_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->serve = S;
+    ctx->serving = true;
+    S->th = std::thread(serve_loop, S);
+  });
+}
+
+rmc_status rmc_submit(rmc_ctx* ctx, const rmc_chain_desc* chain, unsigned long long* job_id) {
+  if (!ctx || !ctx->serving || !job_id) return !ctx ? RMC_ERR_ARG : (!job_id ? RMC_ERR_ARG : RMC_ERR_STATE);
+  ServeState* S = (ServeState*)ctx->serve;
+  try {
+    validate_chain(chain);
+    auto j = std::make_unique<ServeJob>();
+    j->desc = *chain;
+    j->terms.assign(chain->terms, chain->terms + chain->n_terms);
+    j->desc.terms = j->terms.data();
+    j->t_submit = now_ms();
+    job_init(j->run, &j->desc, nullptr);
+    j->mem = job_memory(j->run.P, j->desc.k);
+    std::lock_guard<std::mutex> lk(S->mu);
+    j->id = S->next_id++;
+    *job_id = j->id;
+    S->pending.insert(j->id);
+    S->queue.push_back(std::move(j));
+  } catch (const Error& e) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    ctx->last_error = e.what();
+    return e.code;
+  }
+  S->cv.notify_one();
+  return RMC_OK;
+}
+
+rmc_status rmc_poll(rmc_ctx* ctx, unsigned long long job_id, int* done, double* energies,
+                    int* job_status, double* latency_ms) {
+  if (!ctx || !ctx->serving || !done) return !ctx || !done ? RMC_ERR_ARG : RMC_ERR_STATE;
+  ServeState* S = (ServeState*)ctx->serve;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->done.find(job_id);
+  if (it == S->done.end()) {
+    if (!S->pending.count(job_id)) return RMC_ERR_ARG;
+    *done = 0;
+    return RMC_OK;
+  }
+  *done = 1;
+  if (energies) std::copy(it->second.e.begin(), it->second.e.end(), energies);
+  if (job_status) *job_status = it->second.status;
+  if (latency_ms) *latency_ms = it->second.latency_ms;
+  S->done.erase(it);
+  return RMC_OK;
+}
+
+rmc_status rmc_serve_stop(rmc_ctx* ctx) {
+  if (!ctx) return RMC_ERR_ARG;
+  if (!ctx->serving) return RMC_ERR_STATE;
+  ServeState* S = (ServeState*)ctx->serve;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_one();
+  if (S->th.joinable()) S->th.join();
+  ctx->serving = false;
+  ctx->serve = nullptr;
+  delete S;
+  return RMC_OK;
 }
 
 }  // extern "C"

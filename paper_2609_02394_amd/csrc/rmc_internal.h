@@ -106,6 +106,9 @@ struct rmc_ctx {
   // pinned host staging of the batched solver's descriptor tables
   char* pinned = nullptr;
   size_t pinned_cap = 0;
+  // serving: scheduler state (owned by recurse.hip); other calls are refused while set
+  void* serve = nullptr;
+  bool serving = false;
 };
 
 namespace rmc {

@@ -27,6 +27,7 @@ EXPORTED = (
     "rmc_module_info", "rmc_module_basis", "rmc_module_op", "rmc_module_free",
     "rmc_leaf_hamiltonian", "rmc_kron_apply", "rmc_sym_eig", "rmc_module_import",
     "rmc_profile", "rmc_profile_read",
+    "rmc_serve_start", "rmc_submit", "rmc_poll", "rmc_serve_stop",
 )
 
 
@@ -96,6 +97,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "rmc_module_import": (i, [vp, i, i, i, P(d), P(d), i, P(i), P(i), P(d), P(vp)]),
         "rmc_profile": (i, [vp, i]),
         "rmc_profile_read": (i, [vp, P(C.c_longlong), P(d), P(d), P(d)]),
+        "rmc_serve_start": (i, [vp, P(SolveOpts), i, sz]),
+        "rmc_submit": (i, [vp, P(ChainDesc), P(C.c_ulonglong)]),
+        "rmc_poll": (i, [vp, C.c_ulonglong, P(i), P(d), P(i), P(d)]),
+        "rmc_serve_stop": (i, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -310,6 +315,31 @@ class Context:
         st = lib().rmc_recurse_batch(self.h, n, descs, C.byref(opts) if opts else None,
                                      e.ctypes.data_as(C.POINTER(C.c_double)), qmax, sts)
         return e[:n], list(sts)[:n], st
+
+    # -- serving (continuous batching) --------------------------------------------
+    def serve_start(self, opts: Optional[SolveOpts] = None, max_inflight: int = 64,
+                    mem_budget: int = 0):
+        self._check(lib().rmc_serve_start(self.h, C.byref(opts) if opts else None,
+                                          int(max_inflight), int(mem_budget)))
+
+    def submit(self, n_sites: int, leaf_sites: int, terms, k: int, q: int) -> int:
+        arr, nt = make_terms(terms)
+        ch = ChainDesc(n_sites, leaf_sites, nt, arr, int(k), int(q))
+        jid = C.c_ulonglong()
+        self._check(lib().rmc_submit(self.h, C.byref(ch), C.byref(jid)))
+        return jid.value
+
+    def poll(self, job_id: int, q: int):
+        """(done, energies, status, latency_ms); energies valid once done."""
+        done, st, lat = C.c_int(), C.c_int(), C.c_double()
+        e = np.full(q, np.nan)
+        self._check(lib().rmc_poll(self.h, C.c_ulonglong(job_id), C.byref(done),
+                                   e.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st),
+                                   C.byref(lat)))
+        return bool(done.value), e, st.value, lat.value
+
+    def serve_stop(self):
+        self._check(lib().rmc_serve_stop(self.h))
 
     # -- kernel-level entry points ---------------------------------------------
     def leaf_hamiltonian(self, n_sites: int, terms):

@@ -354,3 +354,77 @@ def test_recurse_batch_mixed_precision(ctx, prec):
     assert all(s == rmc.OK for s in st)
     for i, j in enumerate(jobs):
         assert rel_err(e[i, : j.q], e64[i, : j.q]) <= 1e-8
+
+
+# -- serving (continuous batching) ------------------------------------------------
+
+def _serving_jobs():
+    out = []
+    for i, (t, j) in enumerate(W.serving_stream(40)):
+        if j.n_sites <= 64 and j.k <= 64:
+            out.append(j)
+        if len(out) == 8:
+            break
+    return out
+
+
+def test_serving_results_alone_equal_mix(ctx):
+    import time
+
+    from paper_2609_02394_amd import rmc
+
+    say("serving alone vs mix")
+    jobs = _serving_jobs()
+    alone = [ctx.recurse(*rmc.job_chain(j))[0] for j in jobs]
+    ctx.serve_start(max_inflight=8)
+    try:
+        ids = [ctx.submit(*rmc.job_chain(j)) for j in jobs]
+        got = {}
+        t0 = time.time()
+        while len(got) < len(ids) and time.time() - t0 < 120:
+            for jid, j in zip(ids, jobs):
+                if jid in got:
+                    continue
+                done, e, st, lat = ctx.poll(jid, j.q)
+                if done:
+                    got[jid] = (e, st, lat)
+            time.sleep(0.002)
+    finally:
+        ctx.serve_stop()
+    assert len(got) == len(ids)
+    for jid, j, a in zip(ids, jobs, alone):
+        e, st, lat = got[jid]
+        assert st == rmc.OK and lat > 0
+        assert rel_err(e, a) <= 1e-10, (e, a)
+    # the context works normally again after serving
+    e, _ = ctx.recurse(*rmc.job_chain(jobs[0]))
+    assert rel_err(e, alone[0]) <= 1e-10
+
+
+def test_serving_memory_admission_and_oom(ctx):
+    import time
+
+    from paper_2609_02394_amd import rmc
+
+    say("serving admission")
+    small = W.ChainJob("tfim", 16, 8, 16, 4, J=1.0, h=0.9)
+    big = W.ChainJob("xxz", 128, 8, 128, 8, J=1.0, delta=0.9)   # needs > 64 MiB
+    ref = ctx.recurse(*rmc.job_chain(small))[0]
+    ctx.serve_start(max_inflight=4, mem_budget=64 << 20)    # 64 MiB: small jobs one by one
+    try:
+        ids = [ctx.submit(*rmc.job_chain(small)) for _ in range(3)]
+        bid = ctx.submit(*rmc.job_chain(big))
+        res = {}
+        t0 = time.time()
+        while len(res) < 4 and time.time() - t0 < 120:
+            for jid in ids + [bid]:
+                if jid not in res:
+                    done, e, st, lat = ctx.poll(jid, 8)
+                    if done:
+                        res[jid] = (e, st)
+            time.sleep(0.002)
+    finally:
+        ctx.serve_stop()
+    assert res[bid][1] == rmc.ERR_OOM
+    for jid in ids:
+        assert res[jid][1] == rmc.OK and rel_err(res[jid][0][:4], ref) <= 1e-10
