@@ -14,6 +14,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "rmc_batch.h"
 #include "rmc_internal.h"
 
 namespace rmc {
@@ -348,7 +349,7 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
     const int T = bond->n_terms;
     RMC_CHECK(T >= 0 && (T == 0 || (bond->coef && bond->opA && bond->opB)), RMC_ERR_ARG, "bad bond");
     const int kA = A->k_eff, kB = B->k_eff, n = kA * kB;
-    RMC_CHECK(kA <= 256 && kB <= 256, RMC_ERR_ARG, "module dimension above 256");
+    RMC_CHECK(kA <= kron_max_k() && kB <= kron_max_k(), RMC_ERR_ARG, "module dimension above 192");
     if (rq.want_module) RMC_CHECK(k_keep >= 1 && q <= k_keep, RMC_ERR_ARG, "need 1 <= q <= k_keep");
     RMC_CHECK(q >= 1, RMC_ERR_ARG, "q must be >= 1");
     for (int i = 0; i < T; ++i) {
@@ -758,7 +759,7 @@ rmc_status rmc_kron_apply(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_
     RMC_CHECK(A && B && bond && X_dev && Y_dev && n_vec >= 0, RMC_ERR_ARG, "bad arguments");
     RMC_CHECK(precision >= RMC_FP64 && precision <= RMC_BF16, RMC_ERR_ARG, "bad precision");
     const int T = bond->n_terms, kA = A->k_eff, kB = B->k_eff, n = kA * kB;
-    RMC_CHECK(kA <= 256 && kB <= 256, RMC_ERR_ARG, "module dimension above 256");
+    RMC_CHECK(kA <= kron_max_k() && kB <= kron_max_k(), RMC_ERR_ARG, "module dimension above 192");
     for (int i = 0; i < T; ++i) {
       RMC_CHECK(bond->opA[i] >= 0 && bond->opA[i] < (int)A->ops.size(), RMC_ERR_ARG, "bad opA id");
       RMC_CHECK(bond->opB[i] >= 0 && bond->opB[i] < (int)B->ops.size(), RMC_ERR_ARG, "bad opB id");

@@ -29,6 +29,11 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "rmc_batch.h"
 #include "rmc_internal.h"
@@ -38,8 +43,6 @@ namespace rmc {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-constexpr int KR_TCH = 4;  // terms per LDS chunk
 
 template <int P>
 struct KTraits;
@@ -69,8 +72,6 @@ __device__ inline int acc_row(int g, int r) {
   return P == 0 ? 4 * r + g : 4 * g + r;
 }
 
-__device__ inline double ld_or0(const double* __restrict__ p, bool ok) { return ok ? *p : 0.0; }
-
 // One MFMA step. a_run/b_run: the lane's contiguous K run (length L = KS/4 for
 // FP64/FP32 -> 1 element per MFMA, 8 for BF16).
 template <int P>
@@ -94,131 +95,105 @@ struct Mfma<2> {
   }
 };
 
-// acc += A(rows r0.., K) * B(K, cols) with A(i,k) = Arow(i)[k] (row-major, ld lda,
-// rows < M, k < K) scaled by `scale`, and B(k,j) supplied by a functor.
-template <int P, class BFn>
-__device__ inline typename KTraits<P>::acc mma_tile(typename KTraits<P>::acc acc,
-                                                    const double* __restrict__ A, int lda, int row,
-                                                    bool row_ok, int K, double scale, BFn bfn) {
-  const int lane = threadIdx.x & 63;
-  const int g = lane >> 4;
-  if constexpr (P == 0 || P == 1) {
-    // K in chunks of 64: all operands of a chunk are loaded before its 16 MFMAs so
-    // the loads overlap; two accumulators alternate so consecutive MFMAs do not
-    // wait on each other. Within a step of 16, lane group g takes k = kb + 4g + s.
-    typename KTraits<P>::acc acc2 = {0, 0, 0, 0};
-    for (int kc = 0; kc < K; kc += 64) {
-      double av[16], bv[16];
+// Lane-run operand loads. Within a K chunk (64 for FP64/FP32, 32 for BF16) lane
+// group g = lane/16 takes a contiguous run of K: for FP64/FP32 step u (0..3) of the
+// chunk covers k = kc + 16u + 4g + s (s = 0..3, one MFMA per (u, s)); for BF16 the
+// chunk is one MFMA with k = kc + 8g + s (s = 0..7).
+template <int P>
+struct Run;
+template <>
+struct Run<0> {
+  double v[16];
+  __device__ void load(const double* __restrict__ row, bool ok, int kc, int K, double scale, int g) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int k = kc + 16 * u + 4 * g + s;
-          const bool ok = k < K;
-          av[4 * u + s] = ld_or0(A + (long)row * lda + k, ok && row_ok);
-          bv[4 * u + s] = ok ? bfn(k) : 0.0;
-        }
-#pragma unroll
-      for (int u = 0; u < 16; u += 2) {
-        if constexpr (P == 0) {
-          acc = Mfma<0>::step(av[u] * scale, bv[u], acc);
-          acc2 = Mfma<0>::step(av[u + 1] * scale, bv[u + 1], acc2);
-        } else {
-          acc = Mfma<1>::step((float)(av[u] * scale), (float)bv[u], acc);
-          acc2 = Mfma<1>::step((float)(av[u + 1] * scale), (float)bv[u + 1], acc2);
-        }
+      for (int s = 0; s < 4; ++s) {
+        const int k = kc + 16 * u + 4 * g + s;
+        v[4 * u + s] = (ok && k < K) ? row[k] * scale : 0.0;
       }
-    }
-    acc += acc2;
-  } else {
-    // K step of 32: lane group g takes k = kb + 8g + s, s = 0..7
-    for (int kb = 0; kb < K; kb += 32) {
-      const int k0 = kb + 8 * g;
-      bf8 a8, b8;
+  }
+  template <class F>
+  __device__ void load_fn(F f, int kc, int K, int g) {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int k = k0 + s;
-        const bool ok = k < K;
-        float av = (float)(ld_or0(A + (long)row * lda + k, ok && row_ok) * scale);
-        float bv = ok ? (float)bfn(k) : 0.0f;
-        a8[s] = (__bf16)av;
-        b8[s] = (__bf16)bv;
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = kc + 16 * u + 4 * g + s;
+        v[4 * u + s] = k < K ? f(k) : 0.0;
       }
-      acc = Mfma<2>::step(a8, b8, acc);
+  }
+};
+template <>
+struct Run<1> {
+  float v[16];
+  __device__ void load(const double* __restrict__ row, bool ok, int kc, int K, double scale, int g) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = kc + 16 * u + 4 * g + s;
+        v[4 * u + s] = (float)((ok && k < K) ? row[k] * scale : 0.0);
+      }
+  }
+  template <class F>
+  __device__ void load_fn(F f, int kc, int K, int g) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = kc + 16 * u + 4 * g + s;
+        v[4 * u + s] = (float)(k < K ? f(k) : 0.0);
+      }
+  }
+};
+template <>
+struct Run<2> {
+  bf8 v;
+  __device__ void load(const double* __restrict__ row, bool ok, int kc, int K, double scale, int g) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = kc + 8 * g + s;
+      v[s] = (__bf16)(float)((ok && k < K) ? row[k] * scale : 0.0);
     }
   }
-  return acc;
-}
+  template <class F>
+  __device__ void load_fn(F f, int kc, int K, int g) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = kc + 8 * g + s;
+      v[s] = (__bf16)(float)(k < K ? f(k) : 0.0);
+    }
+  }
+};
 
-// Stage-1 product of one 16-row tile for up to KR_TCH terms: z[t] += Yrow . OBrow_t
-// (K = kB), the Y operand loaded once per K chunk and shared by the terms.
 template <int P>
-__device__ inline void stage1_tile(typename KTraits<P>::acc* z, int tn, const double* __restrict__ yrow,
-                                   bool rok, int K, const double* __restrict__ obrow, bool bok,
-                                   long tstride) {
-  const int lane = threadIdx.x & 63;
-  const int g = lane >> 4;
-  if constexpr (P == 0 || P == 1) {
-    for (int kc = 0; kc < K; kc += 64) {
-      double av[16];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int k = kc + 16 * u + 4 * g + s;
-          av[4 * u + s] = (rok && k < K) ? yrow[k] : 0.0;
-        }
-#pragma unroll
-      for (int t = 0; t < KR_TCH; ++t) {
-        if (t >= tn) break;
-        const double* ob = obrow + t * tstride;
-        double bv[16];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int k = kc + 16 * u + 4 * g + s;
-            bv[4 * u + s] = (bok && k < K) ? ob[k] : 0.0;
-          }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          if constexpr (P == 0)
-            z[t] = Mfma<0>::step(av[u], bv[u], z[t]);
-          else
-            z[t] = Mfma<1>::step((float)av[u], (float)bv[u], z[t]);
-        }
-      }
-    }
+__device__ inline void mma_run(typename KTraits<P>::acc& c, const Run<P>& a, const Run<P>& b) {
+  if constexpr (P == 2) {
+    c = Mfma<2>::step(a.v, b.v, c);
   } else {
-    for (int kc = 0; kc < K; kc += 32) {
-      bf8 a8;
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int k = kc + 8 * g + s;
-        a8[s] = (__bf16)(float)((rok && k < K) ? yrow[k] : 0.0);
-      }
-#pragma unroll
-      for (int t = 0; t < KR_TCH; ++t) {
-        if (t >= tn) break;
-        const double* ob = obrow + t * tstride;
-        bf8 b8;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int k = kc + 8 * g + s;
-          b8[s] = (__bf16)(float)((bok && k < K) ? ob[k] : 0.0);
-        }
-        z[t] = Mfma<2>::step(a8, b8, z[t]);
-      }
-    }
+    for (int u = 0; u < 16; ++u) c = Mfma<P>::step(a.v[u], b.v[u], c);
   }
 }
 
-// One workgroup: vector j of descriptor d, output columns [b0, b0+16).
 template <int P>
+constexpr int kchunk() {
+  return P == 2 ? 32 : 64;
+}
+
+// One workgroup: vector j of descriptor d, output columns [b0, b0 + 16 CT). Each
+// wave owns the 16-row tiles w, w+4, ... (at most MRT) and all CT column sub-tiles
+// of them, so a row operand loaded once feeds CT products. Terms go through LDS
+// in chunks of TCH = 4/CT.
+template <int P, int CT, int MRT>
 __device__ void kron_body(const KronDesc& d, int j, int b0, char* smem_raw) {
   typedef typename KTraits<P>::zt zt;
   typedef typename KTraits<P>::acc accT;
-  zt* Zs = reinterpret_cast<zt*>(smem_raw);  // [KR_TCH][kApad][16]
+  constexpr int TCH = 4 / CT;
+  constexpr int W = 16 * CT;  // LDS row width of Z
+  constexpr int KC = kchunk<P>();
+  zt* Zs = reinterpret_cast<zt*>(smem_raw);  // [TCH][kApad][W]
   const int kA = d.kA, kB = d.kB, T = d.T;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
@@ -227,123 +202,250 @@ __device__ void kron_body(const KronDesc& d, int j, int b0, char* smem_raw) {
   const int kApad = RT * 16;
   const double* Yj = d.Y + (long)j * n;
 
-  constexpr int MAXRT = 4;  // row tiles per wave (kA <= 256)
-  accT acc[MAXRT];
+  accT acc[MRT][CT];
 #pragma unroll
-  for (int t = 0; t < MAXRT; ++t) acc[t] = accT{0, 0, 0, 0};
+  for (int q = 0; q < MRT; ++q)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[q][c] = accT{0, 0, 0, 0};
 
-  for (int t0 = 0; t0 < T; t0 += KR_TCH) {
-    const int tn = min(KR_TCH, T - t0);
-    // stage 1: Z_i = Y_j (O_B^i[tile,:])^T, rows = a, cols = tile, K = kB; the rows
-    // of Y_j are loaded once per K chunk for all terms of the chunk
-    {
-      const int bcol = b0 + l16;
-      const bool bok = bcol < kB;
+  for (int t0 = 0; t0 < T; t0 += TCH) {
+    const int tn = min(TCH, T - t0);
+    // stage 1: Z_t[:, tile] = Y_j (O_B^t[tile, :])^T, K = kB
 #pragma unroll
-      for (int q = 0; q < MAXRT; ++q) {
+    for (int q = 0; q < MRT; ++q) {
+      const int rt = wave + 4 * q;
+      if (rt >= RT) break;
+      const int row = rt * 16 + l16;
+      const bool rok = row < kA;
+      accT z[CT][TCH];
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int t = 0; t < TCH; ++t) z[c][t] = accT{0, 0, 0, 0};
+      for (int kc = 0; kc < kB; kc += KC) {
+        Run<P> a;
+        a.load(Yj + (long)row * kB, rok, kc, kB, 1.0, g);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const int bcol = b0 + 16 * c + l16;
+          const bool bok = bcol < kB;
+#pragma unroll
+          for (int t = 0; t < TCH; ++t) {
+            if (t >= tn) break;
+            Run<P> b;
+            b.load(d.OB + (long)(t0 + t) * kB * kB + (long)bcol * kB, bok, kc, kB, 1.0, g);
+            mma_run<P>(z[c][t], a, b);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TCH; ++t) {
+        if (t >= tn) break;
+        zt* Zt = Zs + (long)t * kApad * W;
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Zt[(rt * 16 + acc_row<P>(g, r)) * W + 16 * c + l16] = (zt)z[c][t][r];
+      }
+    }
+    __syncthreads();
+    // stage 2: acc += c_t O_A^t Z_t, K = kA
+    for (int t = 0; t < tn; ++t) {
+      const double* OAt = d.OA + (long)(t0 + t) * kA * kA;
+      const double ct = d.coef[t0 + t];
+      const zt* Zt = Zs + (long)t * kApad * W;
+#pragma unroll
+      for (int q = 0; q < MRT; ++q) {
         const int rt = wave + 4 * q;
         if (rt >= RT) break;
         const int row = rt * 16 + l16;
-        const bool rok = row < kA;
-        accT z[KR_TCH];
+        for (int kc = 0; kc < kA; kc += KC) {
+          Run<P> a;
+          a.load(OAt + (long)row * kA, row < kA, kc, kA, ct, g);
 #pragma unroll
-        for (int ti = 0; ti < KR_TCH; ++ti) z[ti] = accT{0, 0, 0, 0};
-        stage1_tile<P>(z, tn, Yj + (long)row * kB, rok, kB,
-                       d.OB + (long)t0 * kB * kB + (long)bcol * kB, bok, (long)kB * kB);
-#pragma unroll
-        for (int ti = 0; ti < KR_TCH; ++ti) {
-          if (ti >= tn) break;
-          zt* Zt = Zs + ((long)ti * kApad) * 16;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Zt[(rt * 16 + acc_row<P>(g, r)) * 16 + l16] = (zt)z[ti][r];
+          for (int c = 0; c < CT; ++c) {
+            Run<P> b;
+            b.load_fn([&](int k) -> double { return (double)Zt[k * W + 16 * c + l16]; }, kc, kA, g);
+            mma_run<P>(acc[q][c], a, b);
+          }
         }
       }
     }
     __syncthreads();
-    // stage 2: acc += c_i O_A^i Z_i
-    for (int ti = 0; ti < tn; ++ti) {
-      const double* OAi = d.OA + (long)(t0 + ti) * kA * kA;
-      const double ci = d.coef[t0 + ti];
-      const zt* Zt = Zs + ((long)ti * kApad) * 16;
-#pragma unroll
-      for (int q = 0; q < MAXRT; ++q) {
-        const int rt = wave + 4 * q;
-        if (rt >= RT) break;
-        const int row = rt * 16 + l16;
-        acc[q] = mma_tile<P>(acc[q], OAi, kA, row, row < kA, kA, ci,
-                             [&](int k) -> double { return (double)Zt[k * 16 + l16]; });
-      }
-    }
-    __syncthreads();
   }
-  // epilogue: register r of each row tile holds row acc_row<P>(g, r), column l16
-  const int col = b0 + l16;
-  if (col >= kB) return;
+  // epilogue: register r of a tile holds row acc_row<P>(g, r), column l16 of its sub-tile
   const double* Xp = d.Xprev ? d.Xprev + (long)j * n : nullptr;
   const double* Ej = d.E ? d.E + (long)j * n : nullptr;
   const double ph = d.E ? d.s1 * d.phi[j] : 0.0;
   double* oj = d.out + (long)j * n;
 #pragma unroll
-  for (int q = 0; q < MAXRT; ++q) {
+  for (int q = 0; q < MRT; ++q) {
     const int rt = wave + 4 * q;
     if (rt >= RT) break;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = rt * 16 + acc_row<P>(g, r);
-      if (row >= kA) continue;
-      const long idx = (long)row * kB + col;
-      const double y = Yj[idx];
-      double v = d.s1 * ((double)acc[q][r] + d.Ediag[idx] * y) + d.s2 * y;
-      if (Xp) v += d.s3 * Xp[idx];
-      if (Ej) v += ph * Ej[idx];
-      oj[idx] = v;
+    for (int c = 0; c < CT; ++c) {
+      const int col = b0 + 16 * c + l16;
+      if (col >= kB) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + acc_row<P>(g, r);
+        if (row >= kA) continue;
+        const long idx = (long)row * kB + col;
+        const double y = Yj[idx];
+        double v = d.s1 * ((double)acc[q][c][r] + d.Ediag[idx] * y) + d.s2 * y;
+        if (Xp) v += d.s3 * Xp[idx];
+        if (Ej) v += ph * Ej[idx];
+        oj[idx] = v;
+      }
     }
   }
 }
 
-template <int P>
+template <int P, int CT, int MRT>
 __global__ __launch_bounds__(256) void kron_batched_kernel(const KronDesc* __restrict__ descs) {
   extern __shared__ char smem_raw[];
   const KronDesc d = descs[blockIdx.z];
-  const int j = blockIdx.y, b0 = blockIdx.x * 16;
+  const int j = blockIdx.y, b0 = blockIdx.x * 16 * CT;
   if (j >= d.nv || b0 >= d.kB) return;
-  kron_body<P>(d, j, b0, smem_raw);
+  kron_body<P, CT, MRT>(d, j, b0, smem_raw);
 }
 
 static size_t kron_lds_bytes(int kA, int prec) {
-  int kApad = ((kA + 15) / 16) * 16;
-  size_t el = prec == 0 ? sizeof(double) : sizeof(float);
-  return (size_t)KR_TCH * kApad * 16 * el;
+  // TCH * kApad * 16 * CT elements = 64 * kApad for every CT
+  const int kApad = ((kA + 15) / 16) * 16;
+  return (size_t)64 * kApad * (prec == 0 ? sizeof(double) : sizeof(float));
 }
 
-int kron_max_k() { return 256; }
+int kron_max_k() { return 192; }
+
+typedef void (*KronKernel)(const KronDesc*);
+
+template <int P, int CT>
+static KronKernel pick_mrt(int mrt) {
+  switch (mrt) {
+    case 1: return kron_batched_kernel<P, CT, 1>;
+    case 2: return kron_batched_kernel<P, CT, 2>;
+    default: return kron_batched_kernel<P, CT, 3>;
+  }
+}
+
+template <int P>
+static KronKernel pick_ct(int ct, int mrt) {
+  switch (ct) {
+    case 1: return pick_mrt<P, 1>(mrt);
+    case 2: return pick_mrt<P, 2>(mrt);
+    default: return mrt == 3 ? pick_mrt<P, 2>(mrt) : pick_mrt<P, 4>(mrt);
+  }
+}
+
+static KronKernel kron_kernel(int prec, int ct, int mrt) {
+  switch (prec) {
+    case RMC_FP64: return pick_ct<0>(ct, mrt);
+    case RMC_FP32: return pick_ct<1>(ct, mrt);
+    default: return pick_ct<2>(ct, mrt);
+  }
+}
 
 void kron_set_attrs() {
   const int lds = 160 * 1024 - 1024;
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_batched_kernel<0>),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_batched_kernel<1>),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_batched_kernel<2>),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  for (int p = 0; p < 3; ++p)
+    for (int ct : {1, 2, 4})
+      for (int mrt = 1; mrt <= 3; ++mrt)
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kron_kernel(p, ct, mrt)),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
+// ---- tile-shape autotuner ---------------------------------------------------------
+// The column sub-tiles per workgroup (CT = 1, 2 or 4) are chosen per launch shape
+// (precision, k_A, k_B, T, vectors in the launch rounded to a power of two) by timing
+// every candidate on the first launch of that shape; all candidates produce the same
+// result bit for bit (same per-element summation order), so the timed launches are
+// ordinary launches. The choice is cached for the process and, if RMC_TUNE_CACHE
+// names a file, read from and appended to that file.
+namespace {
+std::mutex tune_mu;
+std::map<std::string, int> tune_cache;
+bool tune_loaded = false;
+
+void tune_load() {
+  if (tune_loaded) return;
+  tune_loaded = true;
+  const char* f = getenv("RMC_TUNE_CACHE");
+  if (!f) return;
+  FILE* fp = fopen(f, "r");
+  if (!fp) return;
+  char key[128];
+  int v;
+  while (fscanf(fp, "%127s %d", key, &v) == 2) tune_cache[key] = v;
+  fclose(fp);
+}
+
+void tune_store(const std::string& key, int v) {
+  const char* f = getenv("RMC_TUNE_CACHE");
+  if (!f) return;
+  FILE* fp = fopen(f, "a");
+  if (!fp) return;
+  fprintf(fp, "%s %d\n", key.c_str(), v);
+  fclose(fp);
+}
+}  // namespace
+
+static bool tuning_enabled = true;
+void kron_set_tuning(bool on) { tuning_enabled = on; }
+
 void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
-                  int precision) {
+                  int precision, int T, long total_vecs) {
   if (P <= 0 || nvmax <= 0 || kBmax <= 0) return;
-  dim3 grid((kBmax + 15) / 16, nvmax, P);
-  size_t lds = kron_lds_bytes(kAmax, precision);
-  switch (precision) {
-    case RMC_FP64:
-      hipLaunchKernelGGL(kron_batched_kernel<0>, grid, dim3(256), lds, s, d);
-      break;
-    case RMC_FP32:
-      hipLaunchKernelGGL(kron_batched_kernel<1>, grid, dim3(256), lds, s, d);
-      break;
-    default:
-      hipLaunchKernelGGL(kron_batched_kernel<2>, grid, dim3(256), lds, s, d);
-      break;
+  const int RT = (kAmax + 15) / 16;
+  const int mrt = RT <= 4 ? 1 : (RT <= 8 ? 2 : 3);
+  const size_t lds = kron_lds_bytes(kAmax, precision);
+  auto launch = [&](int ct) {
+    dim3 grid((kBmax + 16 * ct - 1) / (16 * ct), nvmax, P);
+    hipLaunchKernelGGL(kron_kernel(precision, ct, mrt), grid, dim3(256), lds, s, d);
+  };
+  int lg = 0;
+  while ((1L << (lg + 1)) <= total_vecs) ++lg;
+  char kb[128];
+  snprintf(kb, sizeof(kb), "p%d_a%d_b%d_t%d_v%d", precision, kAmax, kBmax, T, lg);
+  const std::string key(kb);
+  int ct = -1;
+  {
+    std::lock_guard<std::mutex> lk(tune_mu);
+    tune_load();
+    auto it = tune_cache.find(key);
+    if (it != tune_cache.end()) ct = it->second;
   }
+  if (ct < 0 && !tuning_enabled) ct = kBmax >= 64 ? 2 : 1;
+  if (ct == 4 && mrt == 3) ct = 2;
+  if (ct < 0) {
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = 1e30f;
+    int best_ct = 1;
+    for (int c : {1, 2, 4}) {
+      if (c > 1 && 16 * c > ((kBmax + 15) / 16) * 16 * 2) break;  // no more than two half-empty tiles
+      if (c == 4 && mrt == 3) break;  // that variant spills registers
+      launch(c);  // warm
+      hipEventRecord(e0, s);
+      launch(c);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_ct = c;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ct = best_ct;
+    std::lock_guard<std::mutex> lk(tune_mu);
+    tune_cache[key] = ct;
+    tune_store(key, ct);
+  }
+  launch(ct);
 }
 
 }  // namespace rmc

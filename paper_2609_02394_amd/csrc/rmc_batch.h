@@ -75,8 +75,12 @@ struct StartDesc {
   unsigned long long seed;
 };
 
+// T: largest term count of the launch; total_vecs: vectors over all problems (both
+// only key the tile-shape autotuner).
 void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
-                  int precision);
+                  int precision, int T, long total_vecs);
+void kron_set_tuning(bool on);
+int kron_max_k();
 void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int Mmax, int Nmax,
                   int ksplit);
 void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax);

@@ -223,7 +223,8 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
   }
   for (int prec = 0; prec < 3; ++prec) {
     std::vector<KronDesc> kd;
-    int nvmax = 0;
+    int nvmax = 0, Tm = 0;
+    long tv = 0;
     for (size_t i = 0; i < L.size(); ++i) {
       BP* p = L[i];
       int pr = use_prec ? p->prec : RMC_FP64;
@@ -235,13 +236,15 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
       d.s1 = a.sc[i][0]; d.s2 = a.sc[i][1]; d.s3 = a.sc[i][2];
       kd.push_back(d);
       nvmax = std::max(nvmax, a.cnt[i]);
+      Tm = std::max(Tm, d.T);
+      tv += a.cnt[i];
     }
     if (kd.empty()) continue;
     const KronDesc* dd = B.da->add(kd);
     hipStream_t st = ctx->stream;
     const int P = (int)kd.size(), kBm = B.kBmax, kAm = B.kAmax;
     if (!ctx->prof) {
-      B.da->defer([=] { kron_batched(st, dd, P, kBm, nvmax, kAm, prec); });
+      B.da->defer([=] { kron_batched(st, dd, P, kBm, nvmax, kAm, prec, Tm, tv); });
       continue;
     }
     rmc_ctx::ProfRec r;
@@ -250,7 +253,7 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
     hipEvent_t ea = r.a, eb = r.b;
     B.da->defer([=] {
       RMC_HIP(hipEventRecord(ea, st));
-      kron_batched(st, dd, P, kBm, nvmax, kAm, prec);
+      kron_batched(st, dd, P, kBm, nvmax, kAm, prec, Tm, tv);
       RMC_HIP(hipEventRecord(eb, st));
     });
     r.flops = r.bytes = 0.0;
@@ -870,7 +873,7 @@ void op_apply(rmc_ctx* ctx, const CoupledOp& op, int nv, const double* Y, double
   d.s1 = s1; d.s2 = s2; d.s3 = s3;
   KronDesc* dd = sc.get<KronDesc>(1);
   RMC_HIP(hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream));
-  kron_batched(ctx->stream, dd, 1, op.kB, nv, op.kA, precision);
+  kron_batched(ctx->stream, dd, 1, op.kB, nv, op.kA, precision, op.T, nv);
   sync(ctx);
 }
 

@@ -428,3 +428,44 @@ def test_serving_memory_admission_and_oom(ctx):
     assert res[bid][1] == rmc.ERR_OOM
     for jid in ids:
         assert res[jid][1] == rmc.OK and rel_err(res[jid][0][:4], ref) <= 1e-10
+
+
+# -- the wide configurations --------------------------------------------------------
+
+def test_ladder_2x16_matches_oracle(ctx):
+    from paper_2609_02394_amd import rmc
+
+    say("ladder 2x16 k=64 vs oracle")
+    job = W.ChainJob("tfim_ladder", 32, 8, 64, 8, J=1.0, h=0.9, j_rung=0.5)
+    e, rep = ctx.recurse(*rmc.job_chain(job))
+    assert rel_err(e, OR.recurse(job).energies) <= 1e-10
+
+
+def test_ladder_2x48_k128_fp32_matches_fp64(ctx):
+    from paper_2609_02394_amd import rmc
+
+    say("ladder 2x48 k=128 fp32 vs fp64")
+    job = W.tfim_ladder96()
+    e64, rep = ctx.recurse(*rmc.job_chain(job))
+    e32, _ = ctx.recurse(*rmc.job_chain(job), opts=rmc.default_opts(precision=1))
+    assert rel_err(e32, e64) <= 1e-8, (e32, e64)
+    ks = sorted({r["k_eff"] for r in rep["records"] if r["kind"] != 2})
+    assert max(ks) <= 128 and len(rep["records"]) >= 12
+    # ascending, finite, and below the classical ferromagnetic energy -(2*47 + 48*0.5)
+    # (a variational state of the same Hamiltonian, with h lowering it further)
+    assert np.all(np.isfinite(e64)) and np.all(np.diff(e64) >= -1e-12)
+    assert e64[0] < -(2 * 47 * 1.0 + 48 * 0.5)
+
+
+def test_rfheis_batch_32_chains_bf16(ctx):
+    from paper_2609_02394_amd import rmc
+
+    say("rfheis 32 chains bf16 vs fp64 batch")
+    jobs = W.rfheis_batch(32)
+    chains = [rmc.job_chain(j) for j in jobs]
+    e64, st64, _ = ctx.recurse_batch(chains)
+    e16, st16, _ = ctx.recurse_batch(chains, opts=rmc.default_opts(precision=2))
+    assert all(s == 0 for s in st64) and all(s == 0 for s in st16)
+    assert rel_err(e16, e64) <= 1e-8
+    for i in (0, 5):
+        assert rel_err(e64[i], OR.recurse(jobs[i]).energies) <= 1e-10
