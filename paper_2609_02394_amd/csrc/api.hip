@@ -307,7 +307,8 @@ int project_op(rmc_ctx* ctx, rmc_module* m, int site, int op) {
     double* kw = sc.get<double>((size_t)64 * k * k + 64);
     gemm_f64(s, false, true, k, k, n, 1.0, m->basis, n, 0, W, n, 0, 0.0, o, k, 0, 1,
              gemm_pick_ksplit(k, k, n, 1), kw);
-    sync(ctx);
+    // no host sync: scratch released here is reused only by later work on the same
+    // stream, which runs after these kernels
   } catch (...) {
     ctx->arena.release(o);
     throw;

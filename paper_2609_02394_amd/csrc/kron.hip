@@ -310,6 +310,154 @@ __global__ __launch_bounds__(256) void kron_batched_kernel(const KronDesc* __res
   kron_body<P, CT, MRT>(d, j, b0, smem_raw);
 }
 
+// ---- LDS-staged variant (small k) ---------------------------------------------------
+// One workgroup computes the whole k_A x k_B output of one vector. Y_j is staged in
+// LDS once; for each term O_B^t and O_A^t are staged with coalesced loads, then
+//   stage 1: Z_t = Y_j (O_B^t)^T            (MFMA operands from LDS) -> LDS
+//   stage 2: acc += c_t O_A^t Z_t           (MFMA operands from LDS)
+// Wave w owns row tiles w, w+4, ... and every column tile of them, so each A
+// fragment feeds KM/16 independent MFMA chains. The tiles are zero-padded to the
+// compile-time size KM (32, 64 or 96), so every K loop unrolls fully and needs no
+// bounds test. LDS rows are padded by one element against bank conflicts; LDS
+// holds FP64 for the FP64 form and FP32 for the FP32/BF16 forms.
+template <int P>
+struct LdsT {
+  typedef double T;
+};
+template <>
+struct LdsT<1> {
+  typedef float T;
+};
+template <>
+struct LdsT<2> {
+  typedef float T;
+};
+
+template <int P, int KM>
+__global__ __launch_bounds__(256) void kron_lds_kernel(const KronDesc* __restrict__ descs) {
+  typedef typename LdsT<P>::T lt;
+  typedef typename KTraits<P>::acc accT;
+  constexpr int RTM = KM / 16;        // row / column tiles of the padded square
+  constexpr int MRT = (RTM + 3) / 4;  // row tiles per wave
+  constexpr int PW = KM + 1;          // padded row pitch
+  constexpr int KSTEP = P == 2 ? 32 : 4;
+  constexpr int NK = KM / KSTEP;
+  extern __shared__ char smem_raw[];
+  lt* Ys = reinterpret_cast<lt*>(smem_raw);
+  lt* Bs = Ys + KM * PW;
+  lt* As = Bs + KM * PW;
+  lt* Zs = As + KM * PW;
+  const KronDesc d = descs[blockIdx.z];
+  const int j = blockIdx.y;
+  if (j >= d.nv || blockIdx.x != 0) return;
+  const int kA = d.kA, kB = d.kB, T = d.T;
+  const int n = kA * kB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const double* Yj = d.Y + (long)j * n;
+  // stage Y_j, zero-padded to KM x KM so the unrolled K loops need no bounds
+  for (int t = tid; t < KM * KM; t += 256) {
+    const int r = t / KM, c = t % KM;
+    Ys[r * PW + c] = (lt)((r < kA && c < kB) ? Yj[(long)r * kB + c] : 0.0);
+  }
+  accT acc[MRT][RTM];
+#pragma unroll
+  for (int q = 0; q < MRT; ++q)
+#pragma unroll
+    for (int c = 0; c < RTM; ++c) acc[q][c] = accT{0, 0, 0, 0};
+  // A fragment of a padded LDS row at K step s
+  auto frag_row = [&](const lt* base, int s) {
+    if constexpr (P == 2) {
+      bf8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (__bf16)(float)base[32 * s + 8 * g + e];
+      return v;
+    } else {
+      return base[4 * s + g];
+    }
+  };
+  for (int tt = 0; tt < T; ++tt) {
+    const double* OB = d.OB + (long)tt * kB * kB;
+    const double* OA = d.OA + (long)tt * kA * kA;
+    const double ct = d.coef[tt];
+    for (int t = tid; t < KM * KM; t += 256) {
+      const int r = t / KM, c = t % KM;
+      Bs[r * PW + c] = (lt)((r < kB && c < kB) ? OB[(long)r * kB + c] : 0.0);
+      As[r * PW + c] = (lt)((r < kA && c < kA) ? ct * OA[(long)r * kA + c] : 0.0);
+    }
+    __syncthreads();
+    // stage 1: Z[a][b] = sum_k Y[a][k] OB[b][k]
+#pragma unroll
+    for (int q = 0; q < MRT; ++q) {
+      const int rt = wave + 4 * q;
+      if (rt >= RTM) break;
+      accT z[RTM];
+#pragma unroll
+      for (int c = 0; c < RTM; ++c) z[c] = accT{0, 0, 0, 0};
+      const lt* yrow = Ys + (rt * 16 + l16) * PW;
+#pragma unroll
+      for (int sk = 0; sk < NK; ++sk) {
+        const auto a = frag_row(yrow, sk);
+#pragma unroll
+        for (int c = 0; c < RTM; ++c) z[c] = Mfma<P>::step(a, frag_row(Bs + (c * 16 + l16) * PW, sk), z[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < RTM; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Zs[(rt * 16 + acc_row<P>(g, r)) * PW + c * 16 + l16] = (lt)z[c][r];
+    }
+    __syncthreads();
+    // stage 2: acc[a][b] += sum_k As[a][k] Z[k][b]
+#pragma unroll
+    for (int q = 0; q < MRT; ++q) {
+      const int rt = wave + 4 * q;
+      if (rt >= RTM) break;
+      const lt* arow = As + (rt * 16 + l16) * PW;
+#pragma unroll
+      for (int sk = 0; sk < NK; ++sk) {
+        const auto a = frag_row(arow, sk);
+#pragma unroll
+        for (int c = 0; c < RTM; ++c) {
+          if constexpr (P == 2) {
+            bf8 b;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) b[e] = (__bf16)(float)Zs[(32 * sk + 8 * g + e) * PW + c * 16 + l16];
+            acc[q][c] = Mfma<2>::step(a, b, acc[q][c]);
+          } else {
+            acc[q][c] = Mfma<P>::step(a, Zs[(4 * sk + g) * PW + c * 16 + l16], acc[q][c]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const double* Xp = d.Xprev ? d.Xprev + (long)j * n : nullptr;
+  const double* Ej = d.E ? d.E + (long)j * n : nullptr;
+  const double ph = d.E ? d.s1 * d.phi[j] : 0.0;
+  double* oj = d.out + (long)j * n;
+#pragma unroll
+  for (int q = 0; q < MRT; ++q) {
+    const int rt = wave + 4 * q;
+    if (rt >= RTM) break;
+#pragma unroll
+    for (int c = 0; c < RTM; ++c) {
+      const int col = c * 16 + l16;
+      if (col >= kB) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + acc_row<P>(g, r);
+        if (row >= kA) continue;
+        const long idx = (long)row * kB + col;
+        const double y = Yj[idx];
+        double v = d.s1 * ((double)acc[q][c][r] + d.Ediag[idx] * y) + d.s2 * y;
+        if (Xp) v += d.s3 * Xp[idx];
+        if (Ej) v += ph * Ej[idx];
+        oj[idx] = v;
+      }
+    }
+  }
+}
+
 static size_t kron_lds_bytes(int kA, int prec) {
   // TCH * kApad * 16 * CT elements = 64 * kApad for every CT
   const int kApad = ((kA + 15) / 16) * 16;
@@ -346,22 +494,37 @@ static KronKernel kron_kernel(int prec, int ct, int mrt) {
   }
 }
 
+static KronKernel lds_kernel(int prec, int km) {
+  if (prec == RMC_FP64) return km <= 32 ? kron_lds_kernel<0, 32> : kron_lds_kernel<0, 64>;
+  if (prec == RMC_FP32)
+    return km <= 32 ? kron_lds_kernel<1, 32> : (km <= 64 ? kron_lds_kernel<1, 64> : kron_lds_kernel<1, 96>);
+  return km <= 32 ? kron_lds_kernel<2, 32> : (km <= 64 ? kron_lds_kernel<2, 64> : kron_lds_kernel<2, 96>);
+}
+
 void kron_set_attrs() {
   const int lds = 160 * 1024 - 1024;
+  const KronKernel ldsk[8] = {kron_lds_kernel<0, 32>, kron_lds_kernel<0, 64>, kron_lds_kernel<1, 32>,
+                              kron_lds_kernel<1, 64>, kron_lds_kernel<1, 96>, kron_lds_kernel<2, 32>,
+                              kron_lds_kernel<2, 64>, kron_lds_kernel<2, 96>};
+  for (KronKernel k : ldsk)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   for (int p = 0; p < 3; ++p)
     for (int ct : {1, 2, 4})
       for (int mrt = 1; mrt <= 3; ++mrt)
-        hipFuncSetAttribute(reinterpret_cast<const void*>(kron_kernel(p, ct, mrt)),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kron_kernel(p, ct, mrt)),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 // ---- tile-shape autotuner ---------------------------------------------------------
 // The column sub-tiles per workgroup (CT = 1, 2 or 4) are chosen per launch shape
 // (precision, k_A, k_B, T, vectors in the launch rounded to a power of two) by timing
-// every candidate on the first launch of that shape; all candidates produce the same
-// result bit for bit (same per-element summation order), so the timed launches are
-// ordinary launches. The choice is cached for the process and, if RMC_TUNE_CACHE
-// names a file, read from and appended to that file.
+// every candidate on the first launch of that shape; candidate 0 is the LDS-staged
+// whole-output kernel (small k only). The timed launches are ordinary launches (the
+// output does not alias the inputs). The CT candidates give bit-identical results;
+// the LDS one sums K in another order, so it agrees with them to rounding. The
+// choice is cached for the process and, if RMC_TUNE_CACHE names a file, read from
+// and appended to that file, which makes a run reproducible bit for bit.
 namespace {
 std::mutex tune_mu;
 std::map<std::string, int> tune_cache;
@@ -399,7 +562,21 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
   const int RT = (kAmax + 15) / 16;
   const int mrt = RT <= 4 ? 1 : (RT <= 8 ? 2 : 3);
   const size_t lds = kron_lds_bytes(kAmax, precision);
+  // candidate 0: LDS-staged whole-output kernel (k_A, k_B <= 64 in FP64, <= 96 otherwise)
+  const int kmax_lds = precision == RMC_FP64 ? 64 : 96;
+  const int km = std::max(kAmax, kBmax);
+  const bool lds_ok = km <= kmax_lds;
+  const int KMsel = km <= 32 ? 32 : (km <= 64 ? 64 : 96);
   auto launch = [&](int ct) {
+    if (ct == 0) {
+      dim3 grid(1, nvmax, P);
+      KronKernel kk;
+      size_t bytes;
+      kk = lds_kernel(precision, KMsel);
+      bytes = (size_t)4 * KMsel * (KMsel + 1) * (precision == RMC_FP64 ? 8 : 4);
+      hipLaunchKernelGGL(kk, grid, dim3(256), bytes, s, d);
+      return;
+    }
     dim3 grid((kBmax + 16 * ct - 1) / (16 * ct), nvmax, P);
     hipLaunchKernelGGL(kron_kernel(precision, ct, mrt), grid, dim3(256), lds, s, d);
   };
@@ -417,13 +594,15 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
   }
   if (ct < 0 && !tuning_enabled) ct = kBmax >= 64 ? 2 : 1;
   if (ct == 4 && mrt == 3) ct = 2;
+  if (ct == 0 && !lds_ok) ct = 1;
   if (ct < 0) {
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     float best = 1e30f;
     int best_ct = 1;
-    for (int c : {1, 2, 4}) {
+    for (int c : {0, 1, 2, 4}) {
+      if (c == 0 && !lds_ok) continue;
       if (c > 1 && 16 * c > ((kBmax + 15) / 16) * 16 * 2) break;  // no more than two half-empty tiles
       if (c == 4 && mrt == 3) break;  // that variant spills registers
       launch(c);  // warm

@@ -21,67 +21,88 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
 
+// One 64x64 output tile over K range [kbeg, kend): LDS double-buffered, the next
+// 16-deep K slice is loaded into registers while the MFMAs consume the current one.
+__device__ inline void gemm_tile(int tA, int tB, int M, int N, const double* __restrict__ Ab, long lda,
+                                 const double* __restrict__ Bb, long ldb, int row0, int col0,
+                                 int kbeg, int kend, d4 (&acc)[2][2]) {
+  __shared__ double As[2][GB_K][GB_M + 1];
+  __shared__ double Bs[2][GB_K][GB_N + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256;
+      int i, k;
+      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / GB_M; i = idx % GB_M; }
+      const int gi = row0 + i, gk = k0 + k;
+      ra[e] = (gi < M && gk < kend) ? (tA ? Ab[(long)gk * lda + gi] : Ab[(long)gi * lda + gk]) : 0.0;
+      int j, kb;
+      if (!tB) { kb = idx / GB_N; j = idx % GB_N; } else { j = idx / GB_K; kb = idx % GB_K; }
+      const int gj = col0 + j, gkb = k0 + kb;
+      rb[e] = (gj < N && gkb < kend) ? (tB ? Bb[(long)gj * ldb + gkb] : Bb[(long)gkb * ldb + gj]) : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256;
+      int i, k;
+      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / GB_M; i = idx % GB_M; }
+      As[buf][k][i] = ra[e];
+      int j, kb;
+      if (!tB) { kb = idx / GB_N; j = idx % GB_N; } else { j = idx / GB_K; kb = idx % GB_K; }
+      Bs[buf][kb][j] = rb[e];
+    }
+  };
+  if (kbeg >= kend) return;
+  load(kbeg);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
+    const bool more = k0 + GB_K < kend;
+    if (more) load(k0 + GB_K);
+#pragma unroll
+    for (int kk = 0; kk < GB_K; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double a0 = As[buf][kr][wm + (lane & 15)];
+      const double a1 = As[buf][kr][wm + 16 + (lane & 15)];
+      const double b0 = Bs[buf][kr][wn + (lane & 15)];
+      const double b1 = Bs[buf][kr][wn + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
     int tA, int tB, int M, int N, int K, int kchunk, double alpha, const double* __restrict__ A,
     long lda, long sA, const double* __restrict__ B, long ldb, long sB, double beta,
     double* __restrict__ C, long ldc, long sC, int batch, int ksplit, double* __restrict__ work,
     int to_parts) {
-  __shared__ double As[GB_K][GB_M + 1];
-  __shared__ double Bs[GB_K][GB_N + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int bz = blockIdx.z;
   const int b = bz / ksplit, ks = bz % ksplit;
   const int row0 = blockIdx.y * GB_M, col0 = blockIdx.x * GB_N;
-  const double* Ab = A + (long)b * sA;
-  const double* Bb = B + (long)b * sB;
   const int kbeg = ks * kchunk;
   const int kend = min(K, kbeg + kchunk);
-
   d4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-
-  for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
-    // A tile: GB_M x GB_K elements, 4 per thread.
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int idx = tid + e * 256;
-      int i, k;
-      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / GB_M; i = idx % GB_M; }
-      int gi = row0 + i, gk = k0 + k;
-      double v = 0.0;
-      if (gi < M && gk < kend) v = tA ? Ab[(long)gk * lda + gi] : Ab[(long)gi * lda + gk];
-      As[k][i] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int idx = tid + e * 256;
-      int j, k;
-      if (!tB) { k = idx / GB_N; j = idx % GB_N; } else { j = idx / GB_K; k = idx % GB_K; }
-      int gj = col0 + j, gk = k0 + k;
-      double v = 0.0;
-      if (gj < N && gk < kend) v = tB ? Bb[(long)gj * ldb + gk] : Bb[(long)gk * ldb + gj];
-      Bs[k][j] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GB_K; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double a0 = As[kr][wm + (lane & 15)];
-      double a1 = As[kr][wm + 16 + (lane & 15)];
-      double b0 = Bs[kr][wn + (lane & 15)];
-      double b1 = Bs[kr][wn + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-    }
-    __syncthreads();
-  }
+  gemm_tile(tA, tB, M, N, A + (long)b * sA, lda, B + (long)b * sB, ldb, row0, col0, kbeg, kend, acc);
 
   if (ksplit > 1 || to_parts) {
     double* P = work + ((long)ks * batch + b) * (long)M * N;
@@ -134,8 +155,6 @@ __global__ void splitk_reduce_kernel(int M, int N, int batch, int ksplit, const 
 // problem with its own sizes, pointers and scalars.
 __global__ __launch_bounds__(256) void gemm_grouped_kernel(int tA, int tB, int ksplit,
                                                            const GemmDesc* __restrict__ descs) {
-  __shared__ double As[GB_K][GB_M + 1];
-  __shared__ double Bs[GB_K][GB_N + 1];
   const GemmDesc d = descs[blockIdx.z / ksplit];
   const int ks = blockIdx.z % ksplit;
   const int M = d.M, N = d.N, K = d.K;
@@ -149,50 +168,12 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(int tA, int tB, int k
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const double* Ab = d.A;
-  const double* Bb = d.B;
-  const long lda = d.lda, ldb = d.ldb;
   d4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int idx = tid + e * 256;
-      int i, k;
-      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / GB_M; i = idx % GB_M; }
-      int gi = row0 + i, gk = k0 + k;
-      double v = 0.0;
-      if (gi < M && gk < kend) v = tA ? Ab[(long)gk * lda + gi] : Ab[(long)gi * lda + gk];
-      As[k][i] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int idx = tid + e * 256;
-      int j, k;
-      if (!tB) { k = idx / GB_N; j = idx % GB_N; } else { j = idx / GB_K; k = idx % GB_K; }
-      int gj = col0 + j, gk = k0 + k;
-      double v = 0.0;
-      if (gj < N && gk < kend) v = tB ? Bb[(long)gj * ldb + gk] : Bb[(long)gk * ldb + gj];
-      Bs[k][j] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GB_K; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double a0 = As[kr][wm + (lane & 15)];
-      double a1 = As[kr][wm + 16 + (lane & 15)];
-      double b0 = Bs[kr][wn + (lane & 15)];
-      double b1 = Bs[kr][wn + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-    }
-    __syncthreads();
-  }
+  gemm_tile(tA, tB, M, N, d.A, d.lda, d.B, d.ldb, row0, col0, kbeg, kend, acc);
   const bool parts = d.work != nullptr;
   double* P = parts ? d.work + (long)ks * M * N : nullptr;
 #pragma unroll
@@ -745,6 +726,14 @@ __global__ __launch_bounds__(256) void vec_batched_kernel(int op, const VecDesc*
       }
       double nr = sqrt(block_sum256(acc, red));
       if (threadIdx.x == 0) d.norms[j] = nr;
+    }
+    return;
+  }
+  if (op == VEC_REDUCE) {
+    for (long t = blockIdx.x * 256L + threadIdx.x; t < n; t += (long)gridDim.x * 256) {
+      double v = 0.0;
+      for (int j = 0; j < d.nv; ++j) v += d.P[(long)j * n + t];
+      d.out[t] = v;
     }
     return;
   }

@@ -54,7 +54,14 @@ struct CholDesc {
 };
 
 // Row-block vector operations over nv rows of length n.
-enum VecOp { VEC_NORMALIZE = 0, VEC_RESIDUAL = 1, VEC_SCALE_ADD = 2, VEC_COPY = 3, VEC_AXPY3 = 4 };
+enum VecOp {
+  VEC_NORMALIZE = 0,
+  VEC_RESIDUAL = 1,
+  VEC_SCALE_ADD = 2,
+  VEC_COPY = 3,
+  VEC_AXPY3 = 4,
+  VEC_REDUCE = 5  // out[i] = sum_{j < nv} P[j n + i], i < n (split-K partial sums)
+};
 struct VecDesc {
   int nv, n;
   double* out;        // NORMALIZE: rows to normalise; others: output

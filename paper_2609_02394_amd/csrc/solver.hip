@@ -348,20 +348,29 @@ void orthonormalize(Batch& B, const std::vector<BP*>& L, const std::vector<int>&
     if (p->nlock > 0) LL.push_back(p);
   if (!LL.empty()) {
     for (int pass = 0; pass < 2; ++pass) {
-      std::vector<GemmDesc> g1, g2;
+      // P = Y X_lock^T as split-K partials, reduced, then Y -= P X_lock
+      std::vector<const double*> A, Bl;
+      std::vector<int> ca, cb;
       for (BP* p : LL) {
-        GemmDesc d{};
-        d.M = p->cnt; d.N = p->nlock; d.K = p->n;
-        d.A = role_ptr(p, r); d.lda = p->n; d.B = p->X; d.ldb = p->n;
-        d.C = p->Pm; d.ldc = p->nlock; d.alpha = 1.0; d.beta = 0.0;
-        g1.push_back(d);
+        A.push_back(role_ptr(p, r));
+        Bl.push_back(p->X);
+        ca.push_back(p->cnt);
+        cb.push_back(p->nlock);
+      }
+      gram_launch(B, LL, A, Bl, ca, cb);
+      std::vector<VecDesc> rd;
+      std::vector<GemmDesc> g2;
+      for (BP* p : LL) {
+        VecDesc v{};
+        v.nv = B.KS; v.n = p->cnt * p->nlock; v.out = p->Pm; v.P = p->kwork;
+        rd.push_back(v);
         GemmDesc e{};
         e.M = p->cnt; e.N = p->n; e.K = p->nlock;
         e.A = p->Pm; e.lda = p->nlock; e.B = p->X; e.ldb = p->n;
         e.C = role_ptr(p, r); e.ldc = p->n; e.alpha = -1.0; e.beta = 1.0;
         g2.push_back(e);
       }
-      gemm_launch(B, false, true, g1, 1);
+      vec_launch(B, VEC_REDUCE, rd);
       gemm_launch(B, false, false, g2, 1);
     }
     std::vector<VecDesc> nd2;
