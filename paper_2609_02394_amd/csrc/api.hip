@@ -87,6 +87,19 @@ using namespace rmc;
 
 namespace {
 
+// Operators of a coupling in the streaming Kronecker kernel's layout, for every
+// precision whose streaming kernel takes the size (held in the caller's scratch).
+void build_packs(hipStream_t s, Scratch& sc, CoupledOp& op) {
+  op.pkm = kron_pack_km(op.kA, op.kB);
+  if (op.T == 0) return;  // no operators to stage
+  for (int pr = 0; pr < 3; ++pr) {
+    const size_t b = kron_pack_bytes(pr, op.kA, op.kB, op.T);
+    op.pack[pr] = b ? static_cast<void*>(sc.get<char>(b)) : nullptr;
+  }
+  kron_pack(s, op.T, op.kA, op.kB, op.coef_dev, op.OAcat, op.OBcat, op.pack[0], op.pack[1],
+            op.pack[2]);
+}
+
 template <class F>
 rmc_status guard(rmc_ctx* ctx, F&& f) {
   try {
@@ -383,6 +396,7 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
       csum += std::fabs(bond->coef[i]);
     }
     kron_diag(s, kA, kB, A->E, B->E, T, op.coef_dev, op.OAcat, op.OBcat, op.D, op.Ediag);
+    build_packs(s, sc, op);
     // projected one-site Pauli operators have spectral norm <= 1
     const double emax = A->E_host.back() + B->E_host.back();
     op.bup = emax + csum + 1e-12 * (std::fabs(emax) + csum + 1.0);
@@ -787,6 +801,7 @@ rmc_status rmc_kron_apply(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_
                              (size_t)kB * kB * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     kron_diag(s, kA, kB, A->E, B->E, T, op.coef_dev, op.OAcat, op.OBcat, nullptr, op.Ediag);
+    build_packs(s, sc, op);
     op_apply(ctx, op, n_vec, X_dev, Y_dev, nullptr, 1.0, 0.0, 0.0, nullptr, nullptr, precision);
     sync(ctx);
   });

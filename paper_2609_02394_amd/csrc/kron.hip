@@ -310,151 +310,335 @@ __global__ __launch_bounds__(256) void kron_batched_kernel(const KronDesc* __res
   kron_body<P, CT, MRT>(d, j, b0, smem_raw);
 }
 
-// ---- LDS-staged variant (small k) ---------------------------------------------------
-// One workgroup computes the whole k_A x k_B output of one vector. Y_j is staged in
-// LDS once; for each term O_B^t and O_A^t are staged with coalesced loads, then
-//   stage 1: Z_t = Y_j (O_B^t)^T            (MFMA operands from LDS) -> LDS
-//   stage 2: acc += c_t O_A^t Z_t           (MFMA operands from LDS)
-// Wave w owns row tiles w, w+4, ... and every column tile of them, so each A
-// fragment feeds KM/16 independent MFMA chains. The tiles are zero-padded to the
-// compile-time size KM (32, 64 or 96), so every K loop unrolls fully and needs no
-// bounds test. LDS rows are padded by one element against bank conflicts; LDS
-// holds FP64 for the FP64 form and FP32 for the FP32/BF16 forms.
+// ---- streaming variant (k_A, k_B <= KM) ----------------------------------------------
+// A persistent grid: workgroup L owns the launch-wide vectors [L V / G, (L+1) V / G)
+// (V vectors over all descriptors, G workgroups) and walks them one (vector, term)
+// step at a time. The padded KM x KM tiles of one step live in LDS in the MFMA
+// input type: Bs = O_B^t, As = c_t O_A^t and Zt = Z^T, so every MFMA operand is one
+// contiguous K run of an LDS row (vector LDS reads):
+//   stage 1: Z = Y_j (O_B^t)^T   A operand: rows of Y_j (registers), B: rows of Bs
+//   stage 2: acc += As Z         A operand: rows of As, B: rows of Zt
+// Wave (rt, cw) owns row tile rt and column tiles [cw CPW, (cw+1) CPW) of Z and of
+// the output. The operators of the next step are loaded from global memory into
+// registers while the current step computes and are written to LDS behind the two
+// barriers of the step (O_B in flight during stage 1 and stored after it, c O_A in
+// flight during stage 2 and stored after it); the rows of the next vector are
+// prefetched the same way. Logical workgroups are spread so that each
+// XCD (hardware workgroup id mod 8) owns a contiguous run of vectors, which keeps
+// one problem's operators in one L2. Tiles are zero-padded to KM, so the K loops
+// unroll fully and padded rows and columns contribute exact zeros.
 template <int P>
-struct LdsT {
-  typedef double T;
+struct SK;
+template <>
+struct SK<0> {
+  typedef double lt;  // LDS / operand element
+  typedef d4 acc;
+  static constexpr int KR = 4;   // contiguous K per lane per chunk
+  static constexpr int CH = 16;  // K per chunk
 };
 template <>
-struct LdsT<1> {
-  typedef float T;
+struct SK<1> {
+  typedef float lt;
+  typedef f4 acc;
+  static constexpr int KR = 4;
+  static constexpr int CH = 16;
 };
 template <>
-struct LdsT<2> {
-  typedef float T;
+struct SK<2> {
+  typedef __bf16 lt;
+  typedef f4 acc;
+  static constexpr int KR = 8;
+  static constexpr int CH = 32;
 };
 
-template <int P, int KM>
-__global__ __launch_bounds__(256) void kron_lds_kernel(const KronDesc* __restrict__ descs) {
-  typedef typename LdsT<P>::T lt;
-  typedef typename KTraits<P>::acc accT;
-  constexpr int RTM = KM / 16;        // row / column tiles of the padded square
-  constexpr int MRT = (RTM + 3) / 4;  // row tiles per wave
-  constexpr int PW = KM + 1;          // padded row pitch
-  constexpr int KSTEP = P == 2 ? 32 : 4;
-  constexpr int NK = KM / KSTEP;
+template <int P>
+constexpr int sk_pitch(int KM) {
+  return KM + 16 / (int)sizeof(typename SK<P>::lt);  // 16-byte row padding
+}
+
+// Rounds to the element type through FP32 (for BF16: RNE to FP32, then RNE to BF16;
+// the empty asm keeps the compiler from fusing the two into one slower rounding).
+template <int P>
+__device__ inline typename SK<P>::lt to_lt(double x) {
+  if constexpr (P == 0) {
+    return x;
+  } else if constexpr (P == 1) {
+    return (float)x;
+  } else {
+    float f = (float)x;
+    asm volatile("" : "+v"(f));
+    return (__bf16)f;
+  }
+}
+
+// Global-address-space views: loads through them compile to global (not flat)
+// memory instructions, which LDS waits do not have to drain.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+using gptr_w = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ inline gptr<T> gview(const T* p) {
+  return (gptr<T>)p;
+}
+template <class T>
+__device__ inline gptr_w<T> gview_w(T* p) {
+  return (gptr_w<T>)p;
+}
+
+// Four consecutive tile elements (the unit of the staging copies) as one vector.
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+template <int P>
+struct Grp;
+template <>
+struct Grp<0> {
+  typedef d4 t;
+};
+template <>
+struct Grp<1> {
+  typedef f4 t;
+};
+template <>
+struct Grp<2> {
+  typedef bf4 t;
+};
+
+// The KR-element K run of chunk u of an LDS row for lane group g.
+template <int P>
+struct Frag {
+  typename SK<P>::lt v[SK<P>::KR];
+  __device__ void load(const typename SK<P>::lt* row, int u, int g) {
+    const typename SK<P>::lt* q = row + SK<P>::CH * u + SK<P>::KR * g;
+    if constexpr (P == 0) {
+      const double2 a = *reinterpret_cast<const double2*>(q);
+      const double2 b = *reinterpret_cast<const double2*>(q + 2);
+      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else if constexpr (P == 1) {
+      const float4 a = *reinterpret_cast<const float4*>(q);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    } else {
+      const uint4 a = *reinterpret_cast<const uint4*>(q);
+      *reinterpret_cast<uint4*>(v) = a;
+    }
+  }
+};
+
+template <int P>
+__device__ inline void mma_frag(typename SK<P>::acc& c, const typename SK<P>::lt* a, const Frag<P>& b) {
+  if constexpr (P == 2) {
+    bf8 av, bv;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) { av[e] = a[e]; bv[e] = b.v[e]; }
+    c = Mfma<2>::step(av, bv, c);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = Mfma<P>::step(a[s], b.v[s], c);
+  }
+}
+
+template <int P, int KM, int NWC>
+__global__ __launch_bounds__(64 * (KM / 16) * NWC) void kron_stream_kernel(
+    const KronDesc* __restrict__ descs, int P_, long V, int G) {
+  typedef typename SK<P>::lt lt;
+  typedef typename SK<P>::acc accT;
+  constexpr int RTM = KM / 16;            // row (and column) tiles
+  constexpr int CPW = RTM / NWC;          // column tiles per wave
+  constexpr int NT = 64 * RTM * NWC;      // threads
+  constexpr int PW = sk_pitch<P>(KM);
+  constexpr int KR = SK<P>::KR, CH = SK<P>::CH;
+  constexpr int NCH = KM / CH;            // K chunks
+  constexpr int NYE = KM / 4;             // Y elements per lane (NCH * KR)
+  constexpr int NG = KM * KM / (4 * NT);  // 4-element staging groups per thread per matrix
+  static_assert(RTM % NWC == 0 && NG * 4 * NT == KM * KM, "tile split");
   extern __shared__ char smem_raw[];
-  lt* Ys = reinterpret_cast<lt*>(smem_raw);
-  lt* Bs = Ys + KM * PW;
+  lt* Bs = reinterpret_cast<lt*>(smem_raw);
   lt* As = Bs + KM * PW;
-  lt* Zs = As + KM * PW;
-  const KronDesc d = descs[blockIdx.z];
-  const int j = blockIdx.y;
-  if (j >= d.nv || blockIdx.x != 0) return;
-  const int kA = d.kA, kB = d.kB, T = d.T;
-  const int n = kA * kB;
+  lt* Zt = As + KM * PW;
+
+  const int w = blockIdx.x;
+  const int L = (w & 7) * (G >> 3) + (w >> 3);
+  const long v0 = (long)L * V / G, v1 = (long)(L + 1) * V / G;
+  if (v0 >= v1) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  const double* Yj = d.Y + (long)j * n;
-  // stage Y_j, zero-padded to KM x KM so the unrolled K loops need no bounds
-  for (int t = tid; t < KM * KM; t += 256) {
-    const int r = t / KM, c = t % KM;
-    Ys[r * PW + c] = (lt)((r < kA && c < kB) ? Yj[(long)r * kB + c] : 0.0);
+  const int rt = wave / NWC, c0 = (wave % NWC) * CPW;
+
+  // descriptor of vector v0: the last one whose vbase <= v0 (empty ones share vbase)
+  int p = 0;
+  {
+    int lo = 0, hi = P_ - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (descs[mid].vbase <= v0) lo = mid;
+      else hi = mid - 1;
+    }
+    p = lo;
   }
-  accT acc[MRT][RTM];
+  int j = (int)(v0 - descs[p].vbase), t = 0;
+  long v = v0;
+
+  typedef typename Grp<P>::t gv;
+  gv pf[NG];  // next operator tile in flight (O_B, then c O_A)
+  auto load_tile = [&](const KronDesc* e, int tt, bool isA) {
+    const int pk = e->pkm;
+    const bool on = tt < e->T;
+    // a term-less descriptor has no pack: read nothing and stage zeros
+    gptr<lt> base = on ? gview(static_cast<const lt*>(e->pack)) + ((long)tt * 2 + (isA ? 1 : 0)) * pk * pk
+                       : nullptr;
 #pragma unroll
-  for (int q = 0; q < MRT; ++q)
-#pragma unroll
-    for (int c = 0; c < RTM; ++c) acc[q][c] = accT{0, 0, 0, 0};
-  // A fragment of a padded LDS row at K step s
-  auto frag_row = [&](const lt* base, int s) {
-    if constexpr (P == 2) {
-      bf8 v;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (__bf16)(float)base[32 * s + 8 * g + e];
-      return v;
-    } else {
-      return base[4 * s + g];
+    for (int i = 0; i < NG; ++i) {
+      const int q = tid + i * NT, r = q / (KM / 4), cc = (q % (KM / 4)) * 4;
+      const bool in = on && r < pk && cc < pk;
+      gv x = gv{0, 0, 0, 0};
+      if (in) x = *reinterpret_cast<gptr<gv>>(base + r * pk + cc);
+      pf[i] = x;
     }
   };
-  for (int tt = 0; tt < T; ++tt) {
-    const double* OB = d.OB + (long)tt * kB * kB;
-    const double* OA = d.OA + (long)tt * kA * kA;
-    const double ct = d.coef[tt];
-    for (int t = tid; t < KM * KM; t += 256) {
-      const int r = t / KM, c = t % KM;
-      Bs[r * PW + c] = (lt)((r < kB && c < kB) ? OB[(long)r * kB + c] : 0.0);
-      As[r * PW + c] = (lt)((r < kA && c < kA) ? ct * OA[(long)r * kA + c] : 0.0);
-    }
-    __syncthreads();
-    // stage 1: Z[a][b] = sum_k Y[a][k] OB[b][k]
+  auto store_tile = [&](lt* dst) {
 #pragma unroll
-    for (int q = 0; q < MRT; ++q) {
-      const int rt = wave + 4 * q;
-      if (rt >= RTM) break;
-      accT z[RTM];
-#pragma unroll
-      for (int c = 0; c < RTM; ++c) z[c] = accT{0, 0, 0, 0};
-      const lt* yrow = Ys + (rt * 16 + l16) * PW;
-#pragma unroll
-      for (int sk = 0; sk < NK; ++sk) {
-        const auto a = frag_row(yrow, sk);
-#pragma unroll
-        for (int c = 0; c < RTM; ++c) z[c] = Mfma<P>::step(a, frag_row(Bs + (c * 16 + l16) * PW, sk), z[c]);
+    for (int i = 0; i < NG; ++i) {
+      const int q = tid + i * NT, r = q / (KM / 4), cc = (q % (KM / 4)) * 4;
+      lt* o = dst + r * PW + cc;
+      if constexpr (P == 0) {  // rows are 16-byte aligned
+        *reinterpret_cast<double2*>(o) = double2{pf[i][0], pf[i][1]};
+        *reinterpret_cast<double2*>(o + 2) = double2{pf[i][2], pf[i][3]};
+      } else {
+        *reinterpret_cast<gv*>(o) = pf[i];
       }
+    }
+  };
+  lt yf[NYE], yn[NYE];
+  auto load_y = [&](const KronDesc* e, int jj, lt* dst) {
+    const int kA = e->kA, kB = e->kB;
+    gptr<double> Y = gview(e->Y) + (long)jj * kA * kB;
+    const int a = rt * 16 + l16;
 #pragma unroll
-      for (int c = 0; c < RTM; ++c)
+    for (int u = 0; u < NCH; ++u)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Zs[(rt * 16 + acc_row<P>(g, r)) * PW + c * 16 + l16] = (lt)z[c][r];
+      for (int x = 0; x < KR; ++x) {
+        const int k = CH * u + KR * g + x;
+        const bool in = a < kA && k < kB;
+        const double y = Y[in ? (long)a * kB + k : 0];
+        dst[u * KR + x] = to_lt<P>(in ? y : 0.0);
+      }
+  };
+
+  load_tile(descs + p, 0, false);
+  store_tile(Bs);
+  load_tile(descs + p, 0, true);
+  store_tile(As);
+  load_y(descs + p, j, yf);
+  __syncthreads();
+  accT acc[CPW];
+  while (true) {
+    const KronDesc* d = descs + p;
+    const int Td = d->T > 0 ? d->T : 1;
+    // coordinates of the next step
+    bool has_next = true;
+    int nj = j, nt = t + 1, np = p;
+    if (nt >= Td) {
+      nt = 0;
+      if (v + 1 >= v1) {
+        has_next = false;
+      } else {
+        nj = j + 1;
+        if (nj >= d->nv) {
+          np = p + 1;
+          while (descs[np].nv == 0) ++np;
+          nj = 0;
+        }
+      }
+    }
+    const KronDesc* nd = descs + np;
+    if (has_next) load_tile(nd, nt, false);
+    if (has_next && nt == 0) load_y(nd, nj, yn);
+    if (t == 0) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) acc[c] = accT{0, 0, 0, 0};
+    }
+    // stage 1: Z tile = Y rows x (O_B rows)^T -> Zt
+    {
+      accT z[CPW];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) z[c] = accT{0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < NCH; ++u)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          Frag<P> b;
+          b.load(Bs + ((c0 + c) * 16 + l16) * PW, u, g);
+          mma_frag<P>(z[c], yf + u * KR, b);
+        }
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        lt* zr = Zt + ((c0 + c) * 16 + l16) * PW + rt * 16;
+        if constexpr (P == 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) zr[acc_row<0>(g, r)] = z[c][r];
+        } else if constexpr (P == 1) {
+          *reinterpret_cast<float4*>(zr + 4 * g) = float4{z[c][0], z[c][1], z[c][2], z[c][3]};
+        } else {
+          lt h[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) h[r] = (__bf16)z[c][r];
+          *reinterpret_cast<uint2*>(zr + 4 * g) = *reinterpret_cast<const uint2*>(h);
+        }
+      }
     }
     __syncthreads();
-    // stage 2: acc[a][b] += sum_k As[a][k] Z[k][b]
+    if (has_next) {
+      store_tile(Bs);
+      load_tile(nd, nt, true);
+    }
+    // stage 2: acc += As rows x Z
 #pragma unroll
-    for (int q = 0; q < MRT; ++q) {
-      const int rt = wave + 4 * q;
-      if (rt >= RTM) break;
-      const lt* arow = As + (rt * 16 + l16) * PW;
+    for (int u = 0; u < NCH; ++u) {
+      Frag<P> a;
+      a.load(As + (rt * 16 + l16) * PW, u, g);
 #pragma unroll
-      for (int sk = 0; sk < NK; ++sk) {
-        const auto a = frag_row(arow, sk);
+      for (int c = 0; c < CPW; ++c) {
+        Frag<P> b;
+        b.load(Zt + ((c0 + c) * 16 + l16) * PW, u, g);
+        mma_frag<P>(acc[c], a.v, b);
+      }
+    }
+    if (t == Td - 1) {
+      const int kA = d->kA, kB = d->kB, n = kA * kB;
+      const double s1 = d->s1, s2 = d->s2, s3 = d->s3;
+      gptr<double> Yj = gview(d->Y) + (long)j * n;
+      gptr<double> Ed = gview(d->Ediag);
+      gptr<double> Xp = d->Xprev ? gview(d->Xprev) + (long)j * n : nullptr;
+      gptr<double> Ej = d->E ? gview(d->E) + (long)j * n : nullptr;
+      const double ph = d->E ? s1 * d->phi[j] : 0.0;
+      gptr_w<double> oj = gview_w(d->out) + (long)j * n;
 #pragma unroll
-        for (int c = 0; c < RTM; ++c) {
-          if constexpr (P == 2) {
-            bf8 b;
+      for (int c = 0; c < CPW; ++c) {
+        const int col = (c0 + c) * 16 + l16;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) b[e] = (__bf16)(float)Zs[(32 * sk + 8 * g + e) * PW + c * 16 + l16];
-            acc[q][c] = Mfma<2>::step(a, b, acc[q][c]);
-          } else {
-            acc[q][c] = Mfma<P>::step(a, Zs[(4 * sk + g) * PW + c * 16 + l16], acc[q][c]);
+        for (int r = 0; r < 4; ++r) {
+          const int row = rt * 16 + acc_row<P>(g, r);
+          if (row < kA && col < kB) {
+            const long idx = (long)row * kB + col;
+            const double y = Yj[idx];
+            double o = s1 * ((double)acc[c][r] + Ed[idx] * y) + s2 * y;
+            if (Xp) o += s3 * Xp[idx];
+            if (Ej) o += ph * Ej[idx];
+            oj[idx] = o;
           }
         }
       }
     }
     __syncthreads();
-  }
-  const double* Xp = d.Xprev ? d.Xprev + (long)j * n : nullptr;
-  const double* Ej = d.E ? d.E + (long)j * n : nullptr;
-  const double ph = d.E ? d.s1 * d.phi[j] : 0.0;
-  double* oj = d.out + (long)j * n;
+    if (!has_next) break;
+    store_tile(As);
+    if (nt == 0) {
 #pragma unroll
-  for (int q = 0; q < MRT; ++q) {
-    const int rt = wave + 4 * q;
-    if (rt >= RTM) break;
-#pragma unroll
-    for (int c = 0; c < RTM; ++c) {
-      const int col = c * 16 + l16;
-      if (col >= kB) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rt * 16 + acc_row<P>(g, r);
-        if (row >= kA) continue;
-        const long idx = (long)row * kB + col;
-        const double y = Yj[idx];
-        double v = d.s1 * ((double)acc[q][c][r] + d.Ediag[idx] * y) + d.s2 * y;
-        if (Xp) v += d.s3 * Xp[idx];
-        if (Ej) v += ph * Ej[idx];
-        oj[idx] = v;
-      }
+      for (int e = 0; e < NYE; ++e) yf[e] = yn[e];
+      ++v;
     }
+    p = np;
+    j = nj;
+    t = nt;
   }
 }
 
@@ -494,21 +678,75 @@ static KronKernel kron_kernel(int prec, int ct, int mrt) {
   }
 }
 
-static KronKernel lds_kernel(int prec, int km) {
-  if (prec == RMC_FP64) return km <= 32 ? kron_lds_kernel<0, 32> : kron_lds_kernel<0, 64>;
-  if (prec == RMC_FP32)
-    return km <= 32 ? kron_lds_kernel<1, 32> : (km <= 64 ? kron_lds_kernel<1, 64> : kron_lds_kernel<1, 96>);
-  return km <= 32 ? kron_lds_kernel<2, 32> : (km <= 64 ? kron_lds_kernel<2, 64> : kron_lds_kernel<2, 96>);
+typedef void (*StreamKernel)(const KronDesc*, int, long, int);
+
+// Streaming kernels by precision, padded size KM and column split NWC; null where
+// the three KM x KM tiles do not fit in LDS.
+static StreamKernel stream_kernel(int prec, int km, int nwc) {
+#define RMC_SK(P_, KM_) \
+  if (km <= KM_) return nwc == 1 ? kron_stream_kernel<P_, KM_, 1> : kron_stream_kernel<P_, KM_, 2>;
+  if (prec == RMC_FP64) {
+    RMC_SK(0, 32) RMC_SK(0, 64)
+  } else if (prec == RMC_FP32) {
+    RMC_SK(1, 32) RMC_SK(1, 64) RMC_SK(1, 96)
+  } else {
+    RMC_SK(2, 32) RMC_SK(2, 64) RMC_SK(2, 96)
+    if (km <= 128 && nwc == 1) return kron_stream_kernel<2, 128, 1>;
+  }
+#undef RMC_SK
+  return nullptr;
+}
+
+static int stream_km(int km) { return km <= 32 ? 32 : (km <= 64 ? 64 : (km <= 96 ? 96 : 128)); }
+
+static size_t stream_lds_bytes(int prec, int KM) {
+  const int esz = prec == RMC_FP64 ? 8 : (prec == RMC_FP32 ? 4 : 2);
+  return (size_t)3 * KM * (KM + 16 / esz) * esz;
+}
+
+// Workgroups of a streaming launch: resident workgroups per CU times the CU count
+// (a multiple of 8 for the XCD mapping), at most one per vector.
+static int stream_grid(StreamKernel k, int threads, size_t lds, long V) {
+  static std::mutex mu;
+  static std::map<const void*, int> per_cu;
+  static int cus = 0;
+  int n;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (cus == 0) {
+      int dev = 0;
+      (void)hipGetDevice(&dev);
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          cus <= 0)
+        cus = 256;
+    }
+    auto it = per_cu.find(reinterpret_cast<const void*>(k));
+    if (it == per_cu.end()) {
+      int b = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(k),
+                                                       threads, lds) != hipSuccess || b <= 0)
+        b = 1;
+      it = per_cu.emplace(reinterpret_cast<const void*>(k), b).first;
+    }
+    n = it->second * cus;
+  }
+  // RMC_KRON_MAX_GRID caps the grid, so that each workgroup walks many vectors (tests)
+  if (const char* f = getenv("RMC_KRON_MAX_GRID")) {
+    const int cap = atoi(f);
+    if (cap >= 8) n = std::min(n, cap);
+  }
+  const long g = std::min<long>(n, V);
+  return (int)(((g + 7) / 8) * 8);
 }
 
 void kron_set_attrs() {
   const int lds = 160 * 1024 - 1024;
-  const KronKernel ldsk[8] = {kron_lds_kernel<0, 32>, kron_lds_kernel<0, 64>, kron_lds_kernel<1, 32>,
-                              kron_lds_kernel<1, 64>, kron_lds_kernel<1, 96>, kron_lds_kernel<2, 32>,
-                              kron_lds_kernel<2, 64>, kron_lds_kernel<2, 96>};
-  for (KronKernel k : ldsk)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  for (int p = 0; p < 3; ++p)
+    for (int km : {32, 64, 96, 128})
+      for (int nwc : {1, 2})
+        if (StreamKernel k = stream_kernel(p, km, nwc))
+          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   for (int p = 0; p < 3; ++p)
     for (int ct : {1, 2, 4})
       for (int mrt = 1; mrt <= 3; ++mrt)
@@ -516,13 +754,54 @@ void kron_set_attrs() {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
+// ---- operator packs for the streaming kernel ----------------------------------------
+// pack[t][0] = O_B^t, pack[t][1] = c_t O_A^t, each pkm x pkm zero-padded, in the
+// element type of the precision (rounded through FP32 for BF16, as the kernel
+// rounds its vectors).
+__global__ void kron_pack_kernel(int T, int kA, int kB, int pkm, const double* __restrict__ coef,
+                                 const double* __restrict__ OA, const double* __restrict__ OB,
+                                 double* p64, float* p32, __bf16* p16) {
+  const int t = blockIdx.y >> 1, isA = blockIdx.y & 1;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T || i >= (long)pkm * pkm) return;
+  const int r = (int)(i / pkm), c = (int)(i % pkm);
+  const int k = isA ? kA : kB;
+  double v = 0.0;
+  if (r < k && c < k)
+    v = isA ? coef[t] * OA[(long)t * kA * kA + (long)r * kA + c] : OB[(long)t * kB * kB + (long)r * kB + c];
+  const long o = ((long)t * 2 + isA) * pkm * pkm + i;
+  if (p64) p64[o] = v;
+  if (p32) p32[o] = (float)v;
+  if (p16) p16[o] = to_lt<2>(v);
+}
+
+int kron_pack_km(int kA, int kB) { return stream_km(std::max(kA, kB)); }
+
+size_t kron_pack_bytes(int precision, int kA, int kB, int T) {
+  if (T <= 0) return 0;
+  const int km = kron_pack_km(kA, kB);
+  if (!stream_kernel(precision, km, 1)) return 0;
+  const size_t esz = precision == RMC_FP64 ? 8 : (precision == RMC_FP32 ? 4 : 2);
+  return (size_t)T * 2 * km * km * esz;
+}
+
+void kron_pack(hipStream_t s, int T, int kA, int kB, const double* coef, const double* OA,
+               const double* OB, void* p64, void* p32, void* p16) {
+  if (T <= 0 || (!p64 && !p32 && !p16)) return;
+  const int pkm = kron_pack_km(kA, kB);
+  dim3 grid((unsigned)(((long)pkm * pkm + 255) / 256), 2 * T);
+  hipLaunchKernelGGL(kron_pack_kernel, grid, dim3(256), 0, s, T, kA, kB, pkm, coef, OA, OB,
+                     static_cast<double*>(p64), static_cast<float*>(p32), static_cast<__bf16*>(p16));
+}
+
 // ---- tile-shape autotuner ---------------------------------------------------------
 // The column sub-tiles per workgroup (CT = 1, 2 or 4) are chosen per launch shape
 // (precision, k_A, k_B, T, vectors in the launch rounded to a power of two) by timing
-// every candidate on the first launch of that shape; candidate 0 is the LDS-staged
-// whole-output kernel (small k only). The timed launches are ordinary launches (the
-// output does not alias the inputs). The CT candidates give bit-identical results;
-// the LDS one sums K in another order, so it agrees with them to rounding. The
+// every candidate on the first launch of that shape; candidates 8 and 9 are the
+// streaming kernel (k <= 64 in FP64, 96 in FP32, 128 in BF16). The timed launches are
+// ordinary launches (the output does not alias the inputs). The CT candidates give
+// bit-identical results; the streaming one sums K in another order, so it agrees
+// with them to rounding. The
 // choice is cached for the process and, if RMC_TUNE_CACHE names a file, read from
 // and appended to that file, which makes a run reproducible bit for bit.
 namespace {
@@ -558,28 +837,41 @@ void kron_set_tuning(bool on) { tuning_enabled = on; }
 
 void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
                   int precision, int T, long total_vecs) {
-  if (P <= 0 || nvmax <= 0 || kBmax <= 0) return;
+  if (P <= 0 || nvmax <= 0 || kBmax <= 0 || total_vecs <= 0) return;
   const int RT = (kAmax + 15) / 16;
   const int mrt = RT <= 4 ? 1 : (RT <= 8 ? 2 : 3);
   const size_t lds = kron_lds_bytes(kAmax, precision);
-  // candidate 0: LDS-staged whole-output kernel (k_A, k_B <= 64 in FP64, <= 96 otherwise)
-  const int kmax_lds = precision == RMC_FP64 ? 64 : 96;
-  const int km = std::max(kAmax, kBmax);
-  const bool lds_ok = km <= kmax_lds;
-  const int KMsel = km <= 32 ? 32 : (km <= 64 ? 64 : 96);
-  auto launch = [&](int ct) {
-    if (ct == 0) {
-      dim3 grid(1, nvmax, P);
-      KronKernel kk;
-      size_t bytes;
-      kk = lds_kernel(precision, KMsel);
-      bytes = (size_t)4 * KMsel * (KMsel + 1) * (precision == RMC_FP64 ? 8 : 4);
-      hipLaunchKernelGGL(kk, grid, dim3(256), bytes, s, d);
+  const int KM = stream_km(std::max(kAmax, kBmax));
+  const size_t slds = stream_lds_bytes(precision, KM);
+  // candidates: 1, 2, 4 = column sub-tiles of the tiled kernel; 8, 9 = streaming
+  // kernel with one or two waves per row tile
+  auto valid = [&](int c) {
+    if (c == 8 || c == 9) return stream_kernel(precision, KM, c - 7) != nullptr;
+    if (c == 1) return true;
+    if (c != 2 && c != 4) return false;
+    if (16 * c > ((kBmax + 15) / 16) * 16 * 2) return false;  // at most two half-empty tiles
+    return !(c == 4 && mrt == 3);                             // that variant spills registers
+  };
+  auto launch = [&](int c) {
+    if (c >= 8) {
+      const int nwc = c - 7;
+      StreamKernel k = stream_kernel(precision, KM, nwc);
+      const int threads = 4 * KM * nwc;
+      const int G = stream_grid(k, threads, slds, total_vecs);
+      hipLaunchKernelGGL(k, dim3(G), dim3(threads), slds, s, d, P, total_vecs, G);
       return;
     }
-    dim3 grid((kBmax + 16 * ct - 1) / (16 * ct), nvmax, P);
-    hipLaunchKernelGGL(kron_kernel(precision, ct, mrt), grid, dim3(256), lds, s, d);
+    dim3 grid((kBmax + 16 * c - 1) / (16 * c), nvmax, P);
+    hipLaunchKernelGGL(kron_kernel(precision, c, mrt), grid, dim3(256), lds, s, d);
   };
+  // RMC_KRON_VARIANT forces a candidate (where valid for the shape), e.g. to test it
+  if (const char* f = getenv("RMC_KRON_VARIANT")) {
+    const int c = atoi(f);
+    if (valid(c)) {
+      launch(c);
+      return;
+    }
+  }
   int lg = 0;
   while ((1L << (lg + 1)) <= total_vecs) ++lg;
   char kb[128];
@@ -590,30 +882,30 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
     std::lock_guard<std::mutex> lk(tune_mu);
     tune_load();
     auto it = tune_cache.find(key);
-    if (it != tune_cache.end()) ct = it->second;
+    if (it != tune_cache.end() && valid(it->second)) ct = it->second;
   }
-  if (ct < 0 && !tuning_enabled) ct = kBmax >= 64 ? 2 : 1;
-  if (ct == 4 && mrt == 3) ct = 2;
-  if (ct == 0 && !lds_ok) ct = 1;
+  if (ct < 0 && !tuning_enabled) ct = valid(8) ? 8 : (valid(2) ? 2 : 1);
   if (ct < 0) {
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     float best = 1e30f;
     int best_ct = 1;
-    for (int c : {0, 1, 2, 4}) {
-      if (c == 0 && !lds_ok) continue;
-      if (c > 1 && 16 * c > ((kBmax + 15) / 16) * 16 * 2) break;  // no more than two half-empty tiles
-      if (c == 4 && mrt == 3) break;  // that variant spills registers
+    for (int c : {1, 2, 4, 8, 9}) {
+      if (!valid(c)) continue;
       launch(c);  // warm
-      hipEventRecord(e0, s);
-      launch(c);
-      hipEventRecord(e1, s);
-      hipEventSynchronize(e1);
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
-        best = ms;
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        hipEventRecord(e0, s);
+        launch(c);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        tmin = std::min(tmin, ms);
+      }
+      if (tmin < best) {
+        best = tmin;
         best_ct = c;
       }
     }

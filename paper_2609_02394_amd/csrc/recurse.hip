@@ -20,6 +20,7 @@
 #include <thread>
 #include <vector>
 
+#include "rmc_batch.h"
 #include "rmc_internal.h"
 
 namespace rmc {
@@ -374,7 +375,11 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
          rmc_module* A = t.J->by_key[t.J->P.nodes[nd.left].key];
          rmc_module* B = t.J->by_key[t.J->P.nodes[nd.right].key];
          const int n = (A && B) ? A->k_eff * B->k_eff : 1;
-         return task_bytes(n, nd.root ? t.J->c->q : t.J->c->k + 1);
+         size_t packs = 0;
+         if (A && B)
+           for (int pr = 0; pr < 3; ++pr)
+             packs += kron_pack_bytes(pr, A->k_eff, B->k_eff, (int)nd.cut.size()) + 256;
+         return task_bytes(n, nd.root ? t.J->c->q : t.J->c->k + 1) + packs;
        })) {
     auto solve = [&](std::vector<Task>& C) {
       std::vector<rmc_module*> As, Bs;
@@ -506,15 +511,22 @@ struct ServeState {
 size_t job_memory(const Plan& P, int k) {
   std::map<int, std::set<int>> keys_by_level;
   std::map<int, int> dim_by_level;
+  std::map<int, size_t> pack_by_level;
   for (const Node& nd : P.nodes) {
     keys_by_level[nd.level].insert(nd.key);
     int dim = nd.kind == 0 ? (1 << (nd.b - nd.a)) : k * k;
     dim_by_level[nd.level] = std::max(dim_by_level[nd.level], dim);
+    if (nd.kind == 1) {
+      size_t pk = 0;
+      for (int pr = 0; pr < 3; ++pr) pk += kron_pack_bytes(pr, k, k, (int)nd.cut.size()) + 256;
+      pack_by_level[nd.level] = std::max(pack_by_level[nd.level], pk);
+    }
   }
   size_t best = 0;
   for (auto& kv : keys_by_level) {
     const int dim = dim_by_level[kv.first];
-    size_t b = kv.second.size() * (task_bytes(dim, std::min(dim, k + 1)) + (size_t)dim * 64);
+    size_t b = kv.second.size() *
+               (task_bytes(dim, std::min(dim, k + 1)) + (size_t)dim * 64 + pack_by_level[kv.first]);
     best = std::max(best, b);
   }
   return best + (size_t)P.n_keys * 6 * (size_t)k * k * sizeof(double);

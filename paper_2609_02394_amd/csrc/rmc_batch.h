@@ -8,8 +8,14 @@ namespace rmc {
 
 // out_j = s1 (sum_i c_i O_A^i Y_j O_B^iT + Ediag .* Y_j) + s2 Y_j + s3 Xprev_j
 //         + s1 phi[j] E_j   (E, phi optional), j < nv.
+// vbase: number of vectors in the launch's earlier descriptors (the problem's first
+// vector in the launch-wide numbering). pack: the operators in the streaming
+// kernel's layout for the launch precision (kron_pack), pkm its tile size.
 struct KronDesc {
   int kA, kB, T, nv;
+  long vbase;
+  const void* pack;
+  int pkm, pad_;
   const double* coef;
   const double* OA;
   const double* OB;
@@ -88,6 +94,14 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
                   int precision, int T, long total_vecs);
 void kron_set_tuning(bool on);
 int kron_max_k();
+// Operators of one coupling in the streaming kernel's layout: for term t, the
+// pkm x pkm zero-padded tiles O_B^t and c_t O_A^t (in that order, row-major) in the
+// element type of the precision (FP64, FP32, BF16). kron_pack_bytes is 0 where the
+// streaming kernel does not take the size in that precision; null outputs are skipped.
+int kron_pack_km(int kA, int kB);
+size_t kron_pack_bytes(int precision, int kA, int kB, int T);
+void kron_pack(hipStream_t s, int T, int kA, int kB, const double* coef, const double* OA,
+               const double* OB, void* p64, void* p32, void* p16);
 void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int Mmax, int Nmax,
                   int ksplit);
 void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax);

@@ -130,9 +130,10 @@ struct CoupledOp {
   double* D = nullptr;          // device n: full diagonal
   double bup = 0.0;             // upper bound of the spectrum
   int precision = RMC_FP64;
-  // low-precision copies of the operator for the filter (FP32 / BF16 forms)
-  void* OAlow = nullptr;
-  void* OBlow = nullptr;
+  // operators in the streaming Kronecker kernel's layout per precision (null where
+  // that kernel does not take the size), tile size pkm
+  void* pack[3] = {nullptr, nullptr, nullptr};
+  int pkm = 0;
 };
 
 struct SolveStats {

@@ -234,6 +234,9 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
       d.coef = p->op->coef_dev; d.OA = p->op->OAcat; d.OB = p->op->OBcat; d.Ediag = p->op->Ediag;
       d.Y = a.Y[i]; d.Xprev = a.prev[i]; d.E = a.E[i]; d.phi = a.phi[i]; d.out = a.out[i];
       d.s1 = a.sc[i][0]; d.s2 = a.sc[i][1]; d.s3 = a.sc[i][2];
+      d.vbase = tv;
+      d.pack = p->op->pack[prec];
+      d.pkm = p->op->pkm;
       kd.push_back(d);
       nvmax = std::max(nvmax, a.cnt[i]);
       Tm = std::max(Tm, d.T);
@@ -876,7 +879,8 @@ void op_apply(rmc_ctx* ctx, const CoupledOp& op, int nv, const double* Y, double
   RMC_CHECK(op.kind == 1, RMC_ERR_ARG, "op_apply supports Kronecker operators");
   Scratch sc(&ctx->arena);
   KronDesc d{};
-  d.kA = op.kA; d.kB = op.kB; d.T = op.T; d.nv = nv;
+  d.kA = op.kA; d.kB = op.kB; d.T = op.T; d.nv = nv; d.vbase = 0;
+  d.pack = op.pack[precision]; d.pkm = op.pkm;
   d.coef = op.coef_dev; d.OA = op.OAcat; d.OB = op.OBcat; d.Ediag = op.Ediag;
   d.Y = Y; d.Xprev = s3 != 0.0 ? Xprev : nullptr; d.E = Ecorr; d.phi = phi; d.out = out;
   d.s1 = s1; d.s2 = s2; d.s3 = s3;

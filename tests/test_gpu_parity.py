@@ -8,6 +8,7 @@ Tolerances:
   rotations inside degenerate clusters and signs);
 * Kronecker matvec: FP64 to 1e-12 of the output scale, FP32 to 2e-5, BF16 to 3e-2.
 """
+import os
 import sys
 
 import numpy as np
@@ -159,6 +160,79 @@ def test_kron_apply_matches_explicit_kron(ctx, kA, kB, T, prec):
     assert np.max(np.abs(Y - ref)) <= tol * scale
     A.free()
     B.free()
+
+
+@pytest.fixture
+def kron_env():
+    """Sets RMC_KRON_VARIANT / RMC_KRON_MAX_GRID for one test and restores them."""
+    saved = {k: os.environ.get(k) for k in ("RMC_KRON_VARIANT", "RMC_KRON_MAX_GRID")}
+
+    def set_(variant=None, max_grid=None):
+        for k, v in (("RMC_KRON_VARIANT", variant), ("RMC_KRON_MAX_GRID", max_grid)):
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = str(v)
+
+    yield set_
+    for k, v in saved.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
+# every kernel variant of the Kronecker matvec (1, 2, 4: column sub-tiles of the
+# tiled kernel; 8, 9: streaming kernel), at the largest k each streaming form takes,
+# ragged shapes, no terms, and a capped grid so that workgroups walk many vectors
+@pytest.mark.parametrize("variant", [1, 2, 4, 8, 9])
+@pytest.mark.parametrize("prec,kA,kB,T,nv", [(0, 64, 64, 3, 7), (0, 33, 17, 2, 9), (0, 20, 20, 0, 3),
+                                            (1, 96, 96, 3, 5), (1, 50, 70, 2, 6),
+                                            (2, 128, 128, 2, 4), (2, 90, 40, 3, 11)])
+@pytest.mark.parametrize("max_grid", [None, 8])
+def test_kron_apply_variants(ctx, kron_env, variant, prec, kA, kB, T, nv, max_grid):
+    import torch
+
+    say("kron_variant", variant, prec, kA, kB, T, nv, max_grid)
+    kron_env(variant, max_grid)
+    rng = np.random.default_rng(kA * 31 + kB * 7 + T + 1000 * prec)
+    A, EA, mA = _synthetic_module(ctx, rng, kA, 8)
+    B, EB, mB = _synthetic_module(ctx, rng, kB, 8)
+    keys = [(7, "X"), (7, "T"), (7, "Z")][:T]
+    keysB = [(0, "X"), (0, "T"), (0, "Z")][:T]
+    coefs = [0.25, -0.25, 0.3][:T]
+    idA = A.project_ops([s for s, _ in keys], [o for _, o in keys])
+    idB = B.project_ops([s for s, _ in keysB], [o for _, o in keysB])
+    X = rng.standard_normal((nv, kA * kB))
+    Y = ctx.kron_apply(A, B, coefs, idA, idB, torch.tensor(X, device="cuda"), prec).cpu().numpy()
+    H = OR.effective_hamiltonian(EA, EB, [(c, mA[ka], mB[kb]) for c, ka, kb in zip(coefs, keys, keysB)])
+    ref = X @ H.T
+    scale = np.max(np.abs(ref))
+    tol = {0: 1e-12, 1: 2e-5, 2: 3e-2}[prec]
+    assert np.max(np.abs(Y - ref)) <= tol * scale
+    A.free()
+    B.free()
+
+
+@pytest.mark.parametrize("variant", [8, 9])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_batch_recursion_streaming_kernel_many_vectors_per_workgroup(ctx, kron_env, variant, prec):
+    """Level launches over several problems with a capped grid: each workgroup's
+    vector range crosses descriptor boundaries (problems of different k)."""
+    from paper_2609_02394_amd import rmc
+
+    say("batch_stream", variant, prec)
+    jobs = [j for j in W.rfheis_batch(12) if j.k <= 64][:5]
+    jobs.append(W.ChainJob("xxz", 16, 4, 16, 6, J=1.0, delta=0.6))
+    chains = [rmc.job_chain(j) for j in jobs]
+    kron_env(None, None)
+    e_ref, st_ref, _ = ctx.recurse_batch(chains)
+    kron_env(variant, 8)
+    e, st, top = ctx.recurse_batch(chains, opts=rmc.default_opts(precision=prec))
+    kron_env(None, None)
+    assert top == rmc.OK and all(x == rmc.OK for x in st) and all(x == rmc.OK for x in st_ref)
+    for i, j in enumerate(jobs):
+        assert rel_err(e[i, : j.q], e_ref[i, : j.q]) <= (1e-10 if prec == 0 else 1e-8)
 
 
 @pytest.mark.parametrize("kA,kB,T,k_keep,q", [(8, 8, 1, 8, 4), (16, 24, 3, 16, 8),
