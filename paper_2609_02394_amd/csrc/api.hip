@@ -11,6 +11,7 @@
 #include <map>
 #include <set>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -330,6 +331,130 @@ int project_op(rmc_ctx* ctx, rmc_module* m, int site, int op) {
   return (int)m->ops.size() - 1;
 }
 
+// Many projections at once (the operators every new module of a level needs): the
+// same products as project_op, as one grouped GEMM for the operator applications,
+// one grouped split-K GEMM for the basis contractions and one reduction. For a
+// merged module, an operator of the A side acts on the rows of each k_A x k_B
+// coefficient block, so the blocks are transposed first: then both sides are one
+// plain (k k_X) x k_X product, Ct_v o_A^T or C_v o_B^T, and the contraction uses
+// the matching (transposed or not) basis.
+struct ProjReq {
+  rmc_module* m;
+  int site, op;
+};
+
+void project_ops_batch(rmc_ctx* ctx, const std::vector<ProjReq>& in) {
+  std::vector<ProjReq> reqs;
+  std::set<std::tuple<rmc_module*, int, int>> seen;
+  for (const ProjReq& r : in) {
+    if (find_op(r.m, r.site, r.op) >= 0 || !seen.insert({r.m, r.site, r.op}).second) continue;
+    RMC_CHECK(r.site >= 0 && r.site < r.m->n_sites, RMC_ERR_ARG, "operator site outside the module");
+    RMC_CHECK(r.op >= RMC_OP_X && r.op <= RMC_OP_Z, RMC_ERR_ARG, "unknown operator");
+    RMC_CHECK(r.m->basis != nullptr, RMC_ERR_STATE, "module basis already freed");
+    reqs.push_back(r);
+  }
+  if (reqs.empty()) return;
+  if (reqs.size() == 1) {
+    project_op(ctx, reqs[0].m, reqs[0].site, reqs[0].op);
+    return;
+  }
+  hipStream_t s = ctx->stream;
+  const int R = (int)reqs.size();
+  std::vector<double*> outs(R, nullptr);
+  try {
+    Scratch sc(&ctx->arena);
+    // child operators (present unless a caller skipped them) and transposed bases
+    std::vector<const double*> child(R, nullptr);
+    std::vector<char> aside(R, 0);
+    std::map<rmc_module*, double*> ct;
+    for (int i = 0; i < R; ++i) {
+      rmc_module* m = reqs[i].m;
+      if (m->kind == 0) continue;
+      aside[i] = reqs[i].site < m->A->n_sites;
+      if (aside[i]) {
+        child[i] = m->A->ops[project_op(ctx, m->A, reqs[i].site, reqs[i].op)].data;
+        if (!ct.count(m)) ct[m] = sc.get<double>((size_t)m->k_eff * m->dim);
+      } else {
+        child[i] = m->B->ops[project_op(ctx, m->B, reqs[i].site - m->A->n_sites, reqs[i].op)].data;
+      }
+    }
+    std::vector<TrDesc> td;
+    int tk = 0, tn = 0;
+    for (auto& kv : ct) {
+      rmc_module* m = kv.first;
+      td.push_back(TrDesc{m->k_eff, m->kA, m->kB, 0, m->basis, kv.second});
+      tk = std::max(tk, m->k_eff);
+      tn = std::max(tn, m->dim);
+    }
+    std::vector<double*> W(R);
+    std::vector<GemmDesc> g1, g2;
+    std::vector<VecDesc> red;
+    int M1 = 0, N1 = 0, M2 = 0;
+    long kwmax = 0;
+    int KS = 1;
+    for (int i = 0; i < R; ++i) {
+      rmc_module* m = reqs[i].m;
+      const int k = m->k_eff, n = m->dim;
+      W[i] = sc.get<double>((size_t)k * n);
+      KS = std::max(KS, gemm_pick_ksplit(k, k, n, R));
+    }
+    for (int i = 0; i < R; ++i) {
+      rmc_module* m = reqs[i].m;
+      const int k = m->k_eff, n = m->dim;
+      const double* basis = aside[i] ? ct[m] : m->basis;
+      if (m->kind == 0) {
+        site_op_apply(s, k, m->n_sites, m->n_sites - 1 - reqs[i].site, reqs[i].op, m->basis, W[i]);
+      } else {
+        const int kx = aside[i] ? m->kA : m->kB, ky = aside[i] ? m->kB : m->kA;
+        GemmDesc d{};
+        d.M = k * ky; d.N = kx; d.K = kx;
+        d.A = basis; d.lda = kx;
+        d.B = child[i]; d.ldb = kx;
+        d.C = W[i]; d.ldc = kx;
+        d.alpha = 1.0; d.beta = 0.0; d.work = nullptr;
+        g1.push_back(d);
+        M1 = std::max(M1, d.M);
+        N1 = std::max(N1, d.N);
+      }
+      outs[i] = (double*)ctx->arena.alloc((size_t)k * k * sizeof(double));
+      double* kw = sc.get<double>((size_t)KS * k * k);
+      GemmDesc d{};
+      d.M = k; d.N = k; d.K = n;
+      d.A = basis; d.lda = n;
+      d.B = W[i]; d.ldb = n;
+      d.alpha = 1.0; d.beta = 0.0; d.work = kw;
+      g2.push_back(d);
+      M2 = std::max(M2, k);
+      VecDesc v{};
+      v.nv = KS; v.n = k * k; v.out = outs[i]; v.P = kw;
+      red.push_back(v);
+      kwmax = std::max(kwmax, (long)k * k);
+    }
+    auto upload = [&](auto& vec) {
+      typedef typename std::decay<decltype(vec)>::type::value_type T;
+      T* dptr = sc.get<T>(std::max<size_t>(vec.size(), 1));
+      if (!vec.empty())
+        RMC_HIP(hipMemcpyAsync(dptr, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      return dptr;
+    };
+    const TrDesc* tdd = upload(td);
+    const GemmDesc* g1d = upload(g1);
+    const GemmDesc* g2d = upload(g2);
+    const VecDesc* rd = upload(red);
+    transpose_blocks_batched(s, tdd, (int)td.size(), tk, tn);
+    gemm_batched(s, false, true, g1d, (int)g1.size(), M1, N1, 1);
+    gemm_batched(s, false, true, g2d, R, M2, M2, KS);
+    vec_batched(s, VEC_REDUCE, rd, R, KS, kwmax);
+    // the host descriptor tables must outlive their uploads
+    sync(ctx);
+  } catch (...) {
+    for (double* o : outs)
+      if (o) ctx->arena.release(o);
+    throw;
+  }
+  for (int i = 0; i < R; ++i) reqs[i].m->ops.push_back({reqs[i].site, reqs[i].op, outs[i]});
+}
+
 struct CoupleReq {
   rmc_module* A;
   rmc_module* B;
@@ -499,6 +624,12 @@ rmc_module* api_leaf_solve(rmc_ctx* ctx, const rmc_leaf_desc* leaf, int k, int q
 }
 int api_project_op(rmc_ctx* ctx, rmc_module* m, int site, int op) {
   return project_op(ctx, m, site, op);
+}
+void api_project_ops_batch(rmc_ctx* ctx, const std::vector<rmc_module*>& ms,
+                           const std::vector<std::pair<int, int>>& so) {
+  std::vector<ProjReq> r;
+  for (size_t i = 0; i < ms.size(); ++i) r.push_back(ProjReq{ms[i], so[i].first, so[i].second});
+  project_ops_batch(ctx, r);
 }
 rmc_module* api_couple(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_bond_desc* bond,
                        int k_keep, int q, const rmc_solve_opts& o, bool want_module,

@@ -5,6 +5,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "rmc_batch.h"
 #include "rmc_kernels.h"
 
@@ -768,6 +770,27 @@ void vec_batched(hipStream_t s, VecOp op, const VecDesc* d, int P, int nvmax, lo
 }
 
 int jacobi_max_m() { return JMAX; }
+
+// Ct_v = (C_v)^T for the k_A x k_B coefficient blocks C_v of a merged basis:
+// Ct[v][b k_A + a] = C[v][a k_B + b], one descriptor per module (blockIdx.z).
+__global__ __launch_bounds__(256) void transpose_blocks_kernel(const TrDesc* __restrict__ descs) {
+  const TrDesc d = descs[blockIdx.z];
+  const int v = blockIdx.y;
+  if (v >= d.k) return;
+  const int n = d.kA * d.kB;
+  const double* src = d.C + (long)v * n;
+  double* dst = d.Ct + (long)v * n;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    const int a = e / d.kB, b = e % d.kB;
+    dst[(long)b * d.kA + a] = src[e];
+  }
+}
+
+void transpose_blocks_batched(hipStream_t s, const TrDesc* d, int P, int kmax, int nmax) {
+  if (P <= 0 || kmax <= 0 || nmax <= 0) return;
+  const int gx = std::min((nmax + 255) / 256, 16);
+  hipLaunchKernelGGL(transpose_blocks_kernel, dim3(gx, kmax, P), dim3(256), 0, s, d);
+}
 
 void linalg_set_attrs() {
   const int lds = 160 * 1024 - 1024;

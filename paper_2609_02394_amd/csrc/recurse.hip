@@ -28,6 +28,8 @@ namespace rmc {
 rmc_module* api_leaf_solve(rmc_ctx* ctx, const rmc_leaf_desc* leaf, int k, int q_only,
                            const rmc_solve_opts& o, std::vector<double>& evals, rmc_level_report* rep);
 int api_project_op(rmc_ctx* ctx, rmc_module* m, int site, int op);
+void api_project_ops_batch(rmc_ctx* ctx, const std::vector<rmc_module*>& ms,
+                           const std::vector<std::pair<int, int>>& so);
 rmc_module* api_couple(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_bond_desc* bond,
                        int k_keep, int q, const rmc_solve_opts& o, bool want_module,
                        std::vector<double>& evals, rmc_level_report* rep);
@@ -316,7 +318,7 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
     r.width = nd.b - nd.a;
     if (m) {
       J->created.push_back(m);
-      for (auto& so : J->P.need[nd.key]) api_project_op(ctx, m, so.first, so.second);
+      for (auto& so : J->P.need[nd.key]) api_project_op(ctx, m, so.first, so.second);  // already batched
       api_release_basis(ctx, m);
       J->by_key[nd.key] = m;
     } else {  // root: energies
@@ -324,6 +326,20 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
     }
     add_record(J->rep, r);
     if (J->rep) (nd.kind == 0 ? J->rep->n_leaf_ed : J->rep->n_merges)++;
+  };
+  // the operators later steps need from the new modules, in one batch
+  auto project_new = [&](const std::vector<Task>& C, const std::vector<rmc_module*>& mods) {
+    std::vector<rmc_module*> ms;
+    std::vector<std::pair<int, int>> so;
+    for (size_t i = 0; i < C.size() && i < mods.size(); ++i) {
+      if (!mods[i]) continue;
+      const Node& nd = C[i].J->P.nodes[C[i].node];
+      for (auto& x : C[i].J->P.need[nd.key]) {
+        ms.push_back(mods[i]);
+        so.push_back(x);
+      }
+    }
+    api_project_ops_batch(ctx, ms, so);
   };
   // leaves
   for (auto& ch : chunks(leaf_t, [&](const Task& t) {
@@ -346,6 +362,7 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
       std::vector<std::vector<double>> ev;
       std::vector<rmc_level_report> reps;
       auto mods = api_leaf_solve_batch(ctx, lp, ks, qo, o, ev, &reps);
+      project_new(C, mods);
       for (size_t i = 0; i < C.size(); ++i) {
         reps[i].kind = qo[i] > 0 ? 2 : 0;
         after_module(C[i].J, C[i].node, mods[i], reps[i], ev[i]);
@@ -416,6 +433,7 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
       std::vector<std::vector<double>> ev;
       std::vector<rmc_level_report> reps;
       auto mods = api_couple_batch(ctx, As, Bs, bp, want, kk, qq, o, ev, &reps);
+      project_new(live, mods);
       for (size_t i = 0; i < live.size(); ++i) after_module(live[i].J, live[i].node, mods[i], reps[i], ev[i]);
     };
     try {

@@ -78,6 +78,13 @@ struct VecDesc {
   double asgn, b, c;  // SCALE_ADD: out = asgn a_j P + b Q; AXPY3: out += b Y + c Q
 };
 
+// Block transpose of a merged basis (k vectors of k_A x k_B blocks).
+struct TrDesc {
+  int k, kA, kB, pad;
+  const double* C;
+  double* Ct;
+};
+
 // Start block: the m smallest D entries as unit vectors plus eps * uniform(-1,1).
 struct StartDesc {
   int n, m;
@@ -108,5 +115,6 @@ void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax);
 void chol_batched(hipStream_t s, const CholDesc* d, int P, int mmax);
 void vec_batched(hipStream_t s, VecOp op, const VecDesc* d, int P, int nvmax, long elems_max);
 void start_batched(hipStream_t s, const StartDesc* d, int P, int nmax, int mmax);
+void transpose_blocks_batched(hipStream_t s, const TrDesc* d, int P, int kmax, int nmax);
 
 }  // namespace rmc
