@@ -436,8 +436,8 @@ __device__ inline void mma_frag(typename SK<P>::acc& c, const typename SK<P>::lt
   }
 }
 
-template <int P, int KM, int NWC>
-__global__ __launch_bounds__(64 * (KM / 16) * NWC) void kron_stream_kernel(
+template <int P, int KM, int NWC, bool SH>
+__global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_kernel(
     const KronDesc* __restrict__ descs, int P_, long V, int G) {
   typedef typename SK<P>::lt lt;
   typedef typename SK<P>::acc accT;
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC) void kron_stream_kernel(
   static_assert(RTM % NWC == 0 && NG * 4 * NT == KM * KM, "tile split");
   extern __shared__ char smem_raw[];
   lt* Bs = reinterpret_cast<lt*>(smem_raw);
-  lt* As = Bs + KM * PW;
+  lt* As = SH ? Bs : Bs + KM * PW;  // SH: one buffer holds O_B, then c O_A, of a step
   lt* Zt = As + KM * PW;
 
   const int w = blockIdx.x;
@@ -525,8 +525,10 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC) void kron_stream_kernel(
 
   load_tile(descs + p, 0, false);
   store_tile(Bs);
-  load_tile(descs + p, 0, true);
-  store_tile(As);
+  if constexpr (!SH) {
+    load_tile(descs + p, 0, true);
+    store_tile(As);
+  }
   load_y(descs + p, j, yf);
   __syncthreads();
   accT acc[CPW];
@@ -550,7 +552,8 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC) void kron_stream_kernel(
       }
     }
     const KronDesc* nd = descs + np;
-    if (has_next) load_tile(nd, nt, false);
+    if constexpr (SH) load_tile(d, t, true);  // this step's c O_A, stored after stage 1
+    else if (has_next) load_tile(nd, nt, false);
     if (has_next && nt == 0) load_y(nd, nj, yn);
     if (t == 0) {
 #pragma unroll
@@ -586,7 +589,11 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC) void kron_stream_kernel(
       }
     }
     __syncthreads();
-    if (has_next) {
+    if constexpr (SH) {
+      store_tile(As);
+      __syncthreads();
+      if (has_next) load_tile(nd, nt, false);
+    } else if (has_next) {
       store_tile(Bs);
       load_tile(nd, nt, true);
     }
@@ -630,7 +637,12 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC) void kron_stream_kernel(
     }
     __syncthreads();
     if (!has_next) break;
-    store_tile(As);
+    if constexpr (SH) {
+      store_tile(Bs);
+      __syncthreads();
+    } else {
+      store_tile(As);
+    }
     if (nt == 0) {
 #pragma unroll
       for (int e = 0; e < NYE; ++e) yf[e] = yn[e];
@@ -682,16 +694,18 @@ typedef void (*StreamKernel)(const KronDesc*, int, long, int);
 
 // Streaming kernels by precision, padded size KM and column split NWC; null where
 // the three KM x KM tiles do not fit in LDS.
-static StreamKernel stream_kernel(int prec, int km, int nwc) {
-#define RMC_SK(P_, KM_) \
-  if (km <= KM_) return nwc == 1 ? kron_stream_kernel<P_, KM_, 1> : kron_stream_kernel<P_, KM_, 2>;
+static StreamKernel stream_kernel(int prec, int km, int nwc, bool sh = false) {
+#define RMC_SK(P_, KM_)                                                                \
+  if (km <= KM_)                                                                       \
+    return nwc == 1 ? (sh ? kron_stream_kernel<P_, KM_, 1, true> : kron_stream_kernel<P_, KM_, 1, false>) \
+                    : (sh ? kron_stream_kernel<P_, KM_, 2, true> : kron_stream_kernel<P_, KM_, 2, false>);
   if (prec == RMC_FP64) {
     RMC_SK(0, 32) RMC_SK(0, 64)
   } else if (prec == RMC_FP32) {
     RMC_SK(1, 32) RMC_SK(1, 64) RMC_SK(1, 96)
   } else {
     RMC_SK(2, 32) RMC_SK(2, 64) RMC_SK(2, 96)
-    if (km <= 128 && nwc == 1) return kron_stream_kernel<2, 128, 1>;
+    if (km <= 128 && nwc == 1) return sh ? kron_stream_kernel<2, 128, 1, true> : kron_stream_kernel<2, 128, 1, false>;
   }
 #undef RMC_SK
   return nullptr;
@@ -699,9 +713,9 @@ static StreamKernel stream_kernel(int prec, int km, int nwc) {
 
 static int stream_km(int km) { return km <= 32 ? 32 : (km <= 64 ? 64 : (km <= 96 ? 96 : 128)); }
 
-static size_t stream_lds_bytes(int prec, int KM) {
+static size_t stream_lds_bytes(int prec, int KM, bool sh = false) {
   const int esz = prec == RMC_FP64 ? 8 : (prec == RMC_FP32 ? 4 : 2);
-  return (size_t)3 * KM * (KM + 16 / esz) * esz;
+  return (size_t)(sh ? 2 : 3) * KM * (KM + 16 / esz) * esz;
 }
 
 // Workgroups of a streaming launch: resident workgroups per CU times the CU count
@@ -744,9 +758,10 @@ void kron_set_attrs() {
   for (int p = 0; p < 3; ++p)
     for (int km : {32, 64, 96, 128})
       for (int nwc : {1, 2})
-        if (StreamKernel k = stream_kernel(p, km, nwc))
-          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        for (bool sh : {false, true})
+          if (StreamKernel k = stream_kernel(p, km, nwc, sh))
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   for (int p = 0; p < 3; ++p)
     for (int ct : {1, 2, 4})
       for (int mrt = 1; mrt <= 3; ++mrt)
@@ -797,7 +812,7 @@ void kron_pack(hipStream_t s, int T, int kA, int kB, const double* coef, const d
 // ---- tile-shape autotuner ---------------------------------------------------------
 // The column sub-tiles per workgroup (CT = 1, 2 or 4) are chosen per launch shape
 // (precision, k_A, k_B, T, vectors in the launch rounded to a power of two) by timing
-// every candidate on the first launch of that shape; candidates 8 and 9 are the
+// every candidate on the first launch of that shape; candidates 8 to 11 are the
 // streaming kernel (k <= 64 in FP64, 96 in FP32, 128 in BF16). The timed launches are
 // ordinary launches (the output does not alias the inputs). The CT candidates give
 // bit-identical results; the streaming one sums K in another order, so it agrees
@@ -842,11 +857,11 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
   const int mrt = RT <= 4 ? 1 : (RT <= 8 ? 2 : 3);
   const size_t lds = kron_lds_bytes(kAmax, precision);
   const int KM = stream_km(std::max(kAmax, kBmax));
-  const size_t slds = stream_lds_bytes(precision, KM);
   // candidates: 1, 2, 4 = column sub-tiles of the tiled kernel; 8, 9 = streaming
-  // kernel with one or two waves per row tile
+  // kernel with one or two waves per row tile; 10, 11 = the same with one LDS buffer
+  // for both operators of a step (two more barriers, one tile less of LDS)
   auto valid = [&](int c) {
-    if (c == 8 || c == 9) return stream_kernel(precision, KM, c - 7) != nullptr;
+    if (c >= 8 && c <= 11) return stream_kernel(precision, KM, (c - 8) % 2 + 1, c >= 10) != nullptr;
     if (c == 1) return true;
     if (c != 2 && c != 4) return false;
     if (16 * c > ((kBmax + 15) / 16) * 16 * 2) return false;  // at most two half-empty tiles
@@ -854,9 +869,11 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
   };
   auto launch = [&](int c) {
     if (c >= 8) {
-      const int nwc = c - 7;
-      StreamKernel k = stream_kernel(precision, KM, nwc);
+      const int nwc = (c - 8) % 2 + 1;
+      const bool sh = c >= 10;
+      StreamKernel k = stream_kernel(precision, KM, nwc, sh);
       const int threads = 4 * KM * nwc;
+      const size_t slds = stream_lds_bytes(precision, KM, sh);
       const int G = stream_grid(k, threads, slds, total_vecs);
       hipLaunchKernelGGL(k, dim3(G), dim3(threads), slds, s, d, P, total_vecs, G);
       return;
@@ -891,7 +908,7 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
     hipEventCreate(&e1);
     float best = 1e30f;
     int best_ct = 1;
-    for (int c : {1, 2, 4, 8, 9}) {
+    for (int c : {1, 2, 4, 8, 9, 10, 11}) {
       if (!valid(c)) continue;
       launch(c);  // warm
       float tmin = 1e30f;

@@ -122,7 +122,7 @@ struct BP {
   int nlock = 0, nw = 0, prec = RMC_FP64, iters = 0, matvecs = 0, rr_sweeps = 0, cnt = 0;
   int state = 0;  // 0 active, 1 converged, 2 retry with more guard vectors, 3 out of iterations
   int deg = 2;
-  double prev_worst = INFINITY, scale = 1.0, a = 0, b = 0, c = 0, e = 1, sigma1 = 0;
+  double prev_worst = INFINITY, prev_expect = 1.0, scale = 1.0, a = 0, b = 0, c = 0, e = 1, sigma1 = 0;
   int shifted = 0;
 };
 
@@ -519,8 +519,15 @@ bool update_problem(Batch& B, BP* p, int idx, int max_iter, double tol, int pmax
   p->nlock = std::max(p->nlock, first_bad);
   double worst = 0.0;
   for (int j = p->nlock; j < nw; ++j) worst = std::max(worst, rs[j]);
-  if (p->prec != RMC_FP64 && p->iters > 0 && worst > 0.1 * p->prev_worst)
-    p->prec = p->prec == RMC_BF16 ? RMC_FP32 : RMC_FP64;  // low-precision floor reached
+  // Per-iteration residual reduction the low-precision filter can deliver (its
+  // rounding noise relative to the filtered defect); the filter does not aim below it.
+  const double floor_red = p->prec == RMC_BF16 ? 3e-2 : (p->prec == RMC_FP32 ? 1e-5 : 0.0);
+  // escalate when the last filter fell well short of both its Chebyshev damping and
+  // that floor: the rounding noise of this precision now dominates
+  static const bool no_ladder = getenv("RMC_NO_LADDER") != nullptr;
+  if (p->prec != RMC_FP64 && p->iters > 0 && !no_ladder &&
+      worst > std::max(floor_red, 30.0 * p->prev_expect) * p->prev_worst)
+    p->prec = p->prec == RMC_BF16 ? RMC_FP32 : RMC_FP64;
   p->prev_worst = worst;
   p->cnt = m - p->nlock;
   double a = th[m - 1], b = p->op->bup, a0 = th[0];
@@ -531,15 +538,31 @@ bool update_problem(Batch& B, BP* p, int idx, int max_iter, double tol, int pmax
   p->e = 0.5 * (b - a);
   p->c = 0.5 * (b + a);
   p->sigma1 = p->e / (a0 - p->c);
+  const double fl = p->prec == RMC_BF16 ? 3e-2 : (p->prec == RMC_FP32 ? 1e-5 : 0.0);
   int deg = 2;
   for (int j = p->nlock; j < nw; ++j) {
     if (rs[j] <= tol * scale) continue;
     double x = std::fabs((th[j] - p->c) / p->e);
     double rho = x > 1.0 ? std::acosh(x) : 1e-3;
-    double need = std::log(2.0 * rs[j] / (tol * scale)) / rho;
+    double target = 2.0 * rs[j] / (tol * scale);
+    if (fl > 0.0) target = std::min(target, 1.0 / fl);
+    double need = std::log(target) / rho;
     deg = std::max(deg, (int)std::ceil(need));
   }
+  // FP32 filters above degree ~24 stall at a noise floor on these spectra (rounding
+  // noise grows with the spread of T_deg over the wanted set); BF16 is held lower by
+  // its reduction target above
+  if (p->prec == RMC_FP32) deg = std::min(deg, 24);
   p->deg = std::min(std::max(deg, 2), pmax);
+  // damping 1 / T_deg(x) of the slowest active wanted vector
+  double expect = 0.0;
+  for (int j = p->nlock; j < nw; ++j) {
+    if (rs[j] <= tol * scale) continue;
+    double x = std::fabs((th[j] - p->c) / p->e);
+    double rho = x > 1.0 ? std::acosh(x) : 0.0;
+    expect = std::max(expect, rho * p->deg > 700.0 ? 0.0 : 1.0 / std::cosh(rho * p->deg));
+  }
+  p->prev_expect = expect;
   return true;
 }
 
@@ -700,6 +723,7 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
     p->state = 0;
     p->prec = o.precision;
     p->prev_worst = INFINITY;
+    p->prev_expect = 1.0;
     p->matvecs = 0;
   }
   const int P = (int)probs.size();
@@ -757,12 +781,16 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
     read_state(B);
     std::vector<BP*> act;
     std::vector<int> ai;
+    static const bool trace = getenv("RMC_TRACE_SOLVER") != nullptr;
     for (int i = 0; i < P; ++i) {
       BP* p = probs[i];
       if (p->state != 0) continue;
       if (update_problem(B, p, i, max_iter, tol, pmax, last)) {
         act.push_back(p);
         ai.push_back(i);
+        if (trace)
+          fprintf(stderr, "[rmc] n=%d it=%d prec=%d deg=%d nlock=%d worst=%.3e expect=%.3e\n", p->n,
+                  p->iters, p->prec, p->deg, p->nlock, p->prev_worst, p->prev_expect);
       }
     }
     if (act.empty()) break;
