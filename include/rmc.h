@@ -255,6 +255,11 @@ rmc_status rmc_profile(rmc_ctx* ctx, int enable);
  * sum over launches of the event-measured kernel time. */
 rmc_status rmc_profile_read(rmc_ctx* ctx, long long* launches, double* flops, double* bytes,
                             double* ms);
+/* The same totals restricted to the launches of one precision (rmc_precision): in
+ * the FP32 / BF16 forms a problem whose filter reached that precision's noise floor
+ * continues in FP64, so a run mixes launches of several precisions. */
+rmc_status rmc_profile_read_precision(rmc_ctx* ctx, int precision, long long* launches,
+                                      double* flops, double* bytes, double* ms);
 
 #ifdef __cplusplus
 }

@@ -948,33 +948,61 @@ rmc_status rmc_profile(rmc_ctx* ctx, int enable) {
     }
     ctx->prof_recs.clear();
     if (enable) {
-      ctx->prof_launches = 0;
-      ctx->prof_flops = ctx->prof_bytes = ctx->prof_ms = 0.0;
+      for (int p = 0; p < 3; ++p) {
+        ctx->prof_launches[p] = 0;
+        ctx->prof_flops[p] = ctx->prof_bytes[p] = ctx->prof_ms[p] = 0.0;
+      }
     }
     ctx->prof = enable != 0;
   });
 }
 
+namespace {
+void profile_collect(rmc_ctx* ctx) {
+  sync(ctx);
+  for (auto& r : ctx->prof_recs) {
+    float t = 0.f;
+    RMC_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ctx->prof_ms[r.prec] += t;
+    ctx->prof_flops[r.prec] += r.flops;
+    ctx->prof_bytes[r.prec] += r.bytes;
+    ctx->prof_launches[r.prec] += 1;
+    ctx->ev_pool.push_back(r.a);
+    ctx->ev_pool.push_back(r.b);
+  }
+  ctx->prof_recs.clear();
+}
+}  // namespace
+
 rmc_status rmc_profile_read(rmc_ctx* ctx, long long* launches, double* flops, double* bytes,
                             double* ms) {
   if (!ctx) return RMC_ERR_ARG;
   return guard(ctx, [&] {
-    sync(ctx);
-    for (auto& r : ctx->prof_recs) {
-      float t = 0.f;
-      RMC_HIP(hipEventElapsedTime(&t, r.a, r.b));
-      ctx->prof_ms += t;
-      ctx->prof_flops += r.flops;
-      ctx->prof_bytes += r.bytes;
-      ctx->prof_launches += 1;
-      ctx->ev_pool.push_back(r.a);
-      ctx->ev_pool.push_back(r.b);
+    profile_collect(ctx);
+    long long n = 0;
+    double f = 0.0, b = 0.0, t = 0.0;
+    for (int p = 0; p < 3; ++p) {
+      n += ctx->prof_launches[p];
+      f += ctx->prof_flops[p];
+      b += ctx->prof_bytes[p];
+      t += ctx->prof_ms[p];
     }
-    ctx->prof_recs.clear();
-    if (launches) *launches = ctx->prof_launches;
-    if (flops) *flops = ctx->prof_flops;
-    if (bytes) *bytes = ctx->prof_bytes;
-    if (ms) *ms = ctx->prof_ms;
+    if (launches) *launches = n;
+    if (flops) *flops = f;
+    if (bytes) *bytes = b;
+    if (ms) *ms = t;
+  });
+}
+
+rmc_status rmc_profile_read_precision(rmc_ctx* ctx, int precision, long long* launches,
+                                      double* flops, double* bytes, double* ms) {
+  if (!ctx || precision < RMC_FP64 || precision > RMC_BF16) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    profile_collect(ctx);
+    if (launches) *launches = ctx->prof_launches[precision];
+    if (flops) *flops = ctx->prof_flops[precision];
+    if (bytes) *bytes = ctx->prof_bytes[precision];
+    if (ms) *ms = ctx->prof_ms[precision];
   });
 }
 

@@ -98,11 +98,13 @@ struct rmc_ctx {
   struct ProfRec {
     hipEvent_t a, b;
     double flops, bytes;
+    int prec;
   };
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
-  long long prof_launches = 0;
-  double prof_flops = 0.0, prof_bytes = 0.0, prof_ms = 0.0;
+  // totals per precision of the Kronecker launches (index: rmc_precision)
+  long long prof_launches[3] = {0, 0, 0};
+  double prof_flops[3] = {0, 0, 0}, prof_bytes[3] = {0, 0, 0}, prof_ms[3] = {0, 0, 0};
   // pinned host staging of the batched solver's descriptor tables
   char* pinned = nullptr;
   size_t pinned_cap = 0;

@@ -260,6 +260,7 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
       RMC_HIP(hipEventRecord(eb, st));
     });
     r.flops = r.bytes = 0.0;
+    r.prec = prec;
     for (auto& d : kd) {
       const double nn = (double)d.kA * d.kB;
       r.flops += (double)d.nv * (2.0 * d.T * nn * (d.kA + d.kB) + 4.0 * nn);

@@ -26,7 +26,7 @@ EXPORTED = (
     "rmc_module_ed", "rmc_project_ops", "rmc_couple_solve", "rmc_recurse", "rmc_recurse_batch",
     "rmc_module_info", "rmc_module_basis", "rmc_module_op", "rmc_module_free",
     "rmc_leaf_hamiltonian", "rmc_kron_apply", "rmc_sym_eig", "rmc_module_import",
-    "rmc_profile", "rmc_profile_read",
+    "rmc_profile", "rmc_profile_read", "rmc_profile_read_precision",
     "rmc_serve_start", "rmc_submit", "rmc_poll", "rmc_serve_stop",
 )
 
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "rmc_module_import": (i, [vp, i, i, i, P(d), P(d), i, P(i), P(i), P(d), P(vp)]),
         "rmc_profile": (i, [vp, i]),
         "rmc_profile_read": (i, [vp, P(C.c_longlong), P(d), P(d), P(d)]),
+        "rmc_profile_read_precision": (i, [vp, i, P(C.c_longlong), P(d), P(d), P(d)]),
         "rmc_serve_start": (i, [vp, P(SolveOpts), i, sz]),
         "rmc_submit": (i, [vp, P(ChainDesc), P(C.c_ulonglong)]),
         "rmc_poll": (i, [vp, C.c_ulonglong, P(i), P(d), P(i), P(d)]),
@@ -233,9 +234,16 @@ class Context:
     def profile(self, enable: bool):
         self._check(lib().rmc_profile(self.h, int(bool(enable))))
 
-    def profile_read(self):
+    def profile_read(self, precision: Optional[int] = None):
+        """Kronecker-launch totals since profile(True): all launches, or those of one
+        precision (FP64 / FP32 / BF16)."""
         n, f, b, ms = C.c_longlong(), C.c_double(), C.c_double(), C.c_double()
-        self._check(lib().rmc_profile_read(self.h, C.byref(n), C.byref(f), C.byref(b), C.byref(ms)))
+        if precision is None:
+            self._check(lib().rmc_profile_read(self.h, C.byref(n), C.byref(f), C.byref(b),
+                                               C.byref(ms)))
+        else:
+            self._check(lib().rmc_profile_read_precision(self.h, int(precision), C.byref(n),
+                                                         C.byref(f), C.byref(b), C.byref(ms)))
         return {"launches": n.value, "flops": f.value, "bytes": b.value, "ms": ms.value}
 
     def arena_usage(self) -> Tuple[int, int]:
