@@ -184,23 +184,48 @@ std::vector<rmc_module*> leaf_solve_batch(rmc_ctx* ctx, const std::vector<const 
   std::vector<int> nevs(P), kreq(P);
   std::vector<double*> Xs(P);
   double* bmax = sc.get<double>(std::max(P, 1));
+  // term lists of every leaf in one table, one upload, four launches
+  std::vector<DevTerm> terms;
+  std::vector<size_t> toff(P);
+  for (int i = 0; i < P; ++i) {
+    toff[i] = terms.size();
+    for (int t = 0; t < leaves[i]->n_terms; ++t) {
+      const rmc_term& tm = leaves[i]->terms[t];
+      DevTerm d{};
+      d.coef = tm.coef;
+      d.nsite = tm.nsite;
+      for (int u = 0; u < tm.nsite; ++u) {
+        d.bit[u] = leaves[i]->n_sites - 1 - tm.site[u];
+        d.op[u] = tm.op[u];
+      }
+      terms.push_back(d);
+    }
+  }
+  DevTerm* terms_dev = sc.get<DevTerm>(std::max<size_t>(terms.size(), 1));
+  std::vector<LeafSetDesc> ld(P);
+  int ns_max = 0;
   for (int i = 0; i < P; ++i) {
     const int D = 1 << leaves[i]->n_sites;
-    double* H = sc.get<double>((size_t)D * D);
-    assemble_leaf(ctx, leaves[i], H);
     CoupledOp& op = ops[i];
     op.kind = 0;
     op.n = D;
+    double* H = sc.get<double>((size_t)D * D);
     op.H = H;
     op.D = sc.get<double>(D);
-    double* rb = sc.get<double>(D);
-    dense_diag(ctx->stream, D, H, op.D, rb);
-    vec_max(ctx->stream, D, rb, bmax + i);
+    ld[i] = LeafSetDesc{leaves[i]->n_sites, leaves[i]->n_terms, terms_dev + toff[i], H, op.D,
+                        sc.get<double>(D), bmax + i};
+    ns_max = std::max(ns_max, leaves[i]->n_sites);
     kreq[i] = std::min(ks[i], D);
     nevs[i] = q_only[i] > 0 ? std::min(q_only[i], D) : std::min(D, kreq[i] + 1);
     Xs[i] = sc.get<double>((size_t)nevs[i] * D);
     opp[i] = &ops[i];
   }
+  LeafSetDesc* ld_dev = sc.get<LeafSetDesc>(P);
+  if (!terms.empty())
+    RMC_HIP(hipMemcpyAsync(terms_dev, terms.data(), terms.size() * sizeof(DevTerm),
+                           hipMemcpyHostToDevice, ctx->stream));
+  RMC_HIP(hipMemcpyAsync(ld_dev, ld.data(), P * sizeof(LeafSetDesc), hipMemcpyHostToDevice, ctx->stream));
+  leaf_setup_batched(ctx->stream, ld_dev, P, ns_max);
   std::vector<double> bh(P);
   RMC_HIP(hipMemcpyAsync(bh.data(), bmax, P * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   sync(ctx);
@@ -232,6 +257,10 @@ std::vector<rmc_module*> leaf_solve_batch(rmc_ctx* ctx, const std::vector<const 
                       ", max_res=" + std::to_string(st[i].max_res) + ")");
   std::vector<rmc_module*> out(P, nullptr);
   try {
+    std::vector<double> e_all;
+    std::vector<VecDesc> copies;
+    std::vector<size_t> e_off;
+    long cmax = 0;
     for (int i = 0; i < P; ++i) {
       if (q_only[i] > 0) continue;
       const int D = ops[i].n;
@@ -248,13 +277,29 @@ std::vector<rmc_module*> leaf_solve_batch(rmc_ctx* ctx, const std::vector<const 
       out[i] = m;
       m->E = (double*)ctx->arena.alloc(k_eff * sizeof(double));
       m->basis = (double*)ctx->arena.alloc((size_t)k_eff * D * sizeof(double));
-      RMC_HIP(hipMemcpyAsync(m->E, m->E_host.data(), k_eff * sizeof(double), hipMemcpyHostToDevice,
-                             ctx->stream));
-      copy_rows(ctx->stream, k_eff, D, Xs[i], D, m->basis, D);
+      e_off.push_back(e_all.size());
+      e_all.insert(e_all.end(), m->E_host.begin(), m->E_host.end());
+      VecDesc v{};
+      v.nv = k_eff; v.n = D; v.out = m->basis; v.P = Xs[i];
+      copies.push_back(v);
+      VecDesc ve{};
+      ve.nv = 1; ve.n = k_eff; ve.out = m->E;
+      copies.push_back(ve);
+      cmax = std::max(cmax, (long)k_eff * D);
       if (reps) {
         (*reps)[i].k_eff = k_eff;
         (*reps)[i].gap = gap;
       }
+    }
+    if (!copies.empty()) {
+      double* e_dev = sc.get<double>(std::max<size_t>(e_all.size(), 1));
+      for (size_t t = 0; t < e_off.size(); ++t) copies[2 * t + 1].P = e_dev + e_off[t];
+      VecDesc* cd = sc.get<VecDesc>(copies.size());
+      RMC_HIP(hipMemcpyAsync(e_dev, e_all.data(), e_all.size() * sizeof(double), hipMemcpyHostToDevice,
+                             ctx->stream));
+      RMC_HIP(hipMemcpyAsync(cd, copies.data(), copies.size() * sizeof(VecDesc), hipMemcpyHostToDevice,
+                             ctx->stream));
+      vec_batched(ctx->stream, VEC_COPY, cd, (int)copies.size(), 1, cmax);
     }
     sync(ctx);
   } catch (...) {
@@ -387,6 +432,8 @@ void project_ops_batch(rmc_ctx* ctx, const std::vector<ProjReq>& in) {
       tn = std::max(tn, m->dim);
     }
     std::vector<double*> W(R);
+    std::vector<SiteOpDesc> so;
+    long so_max = 0;
     std::vector<GemmDesc> g1, g2;
     std::vector<VecDesc> red;
     int M1 = 0, N1 = 0, M2 = 0;
@@ -403,7 +450,8 @@ void project_ops_batch(rmc_ctx* ctx, const std::vector<ProjReq>& in) {
       const int k = m->k_eff, n = m->dim;
       const double* basis = aside[i] ? ct[m] : m->basis;
       if (m->kind == 0) {
-        site_op_apply(s, k, m->n_sites, m->n_sites - 1 - reqs[i].site, reqs[i].op, m->basis, W[i]);
+        so.push_back(SiteOpDesc{k, m->n_sites, m->n_sites - 1 - reqs[i].site, reqs[i].op, m->basis, W[i]});
+        so_max = std::max(so_max, (long)k * n);
       } else {
         const int kx = aside[i] ? m->kA : m->kB, ky = aside[i] ? m->kB : m->kA;
         GemmDesc d{};
@@ -438,10 +486,12 @@ void project_ops_batch(rmc_ctx* ctx, const std::vector<ProjReq>& in) {
       return dptr;
     };
     const TrDesc* tdd = upload(td);
+    const SiteOpDesc* sod = upload(so);
     const GemmDesc* g1d = upload(g1);
     const GemmDesc* g2d = upload(g2);
     const VecDesc* rd = upload(red);
     transpose_blocks_batched(s, tdd, (int)td.size(), tk, tn);
+    site_op_batched(s, sod, (int)so.size(), so_max);
     gemm_batched(s, false, true, g1d, (int)g1.size(), M1, N1, 1);
     gemm_batched(s, false, true, g2d, R, M2, M2, KS);
     vec_batched(s, VEC_REDUCE, rd, R, KS, kwmax);
@@ -477,6 +527,12 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
   std::vector<const CoupledOp*> opp(P);
   std::vector<int> nevs(P), kreq(P);
   std::vector<double*> Xs(P);
+  // one batched set-up launch for every problem's operators (tables below)
+  std::vector<OpSetDesc> setup(P);
+  std::vector<double> coef_all;
+  std::vector<const double*> ptr_all;
+  std::vector<size_t> coef_off(P), ptr_off(P);
+  long work_max = 0;
   for (int p = 0; p < P; ++p) {
     const CoupleReq& rq = reqs[p];
     rmc_module* A = rq.A;
@@ -505,23 +561,34 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
     op.EA = A->E;
     op.EB = B->E;
     op.coef.assign(bond->coef, bond->coef + T);
-    op.coef_dev = sc.get<double>(std::max(T, 1));
     op.OAcat = sc.get<double>((size_t)std::max(T, 1) * kA * kA);
     op.OBcat = sc.get<double>((size_t)std::max(T, 1) * kB * kB);
     op.Ediag = sc.get<double>(n);
     op.D = sc.get<double>(n);
-    if (T > 0)
-      RMC_HIP(hipMemcpyAsync(op.coef_dev, bond->coef, T * sizeof(double), hipMemcpyHostToDevice, s));
+    op.pkm = kron_pack_km(kA, kB);
+    for (int pr = 0; pr < 3; ++pr) {
+      const size_t b = kron_pack_bytes(pr, kA, kB, T);
+      op.pack[pr] = b ? static_cast<void*>(sc.get<char>(b)) : nullptr;
+    }
     double csum = 0.0;
+    coef_off[p] = coef_all.size();
+    ptr_off[p] = ptr_all.size();
     for (int i = 0; i < T; ++i) {
-      RMC_HIP(hipMemcpyAsync(op.OAcat + (size_t)i * kA * kA, A->ops[bond->opA[i]].data,
-                             (size_t)kA * kA * sizeof(double), hipMemcpyDeviceToDevice, s));
-      RMC_HIP(hipMemcpyAsync(op.OBcat + (size_t)i * kB * kB, B->ops[bond->opB[i]].data,
-                             (size_t)kB * kB * sizeof(double), hipMemcpyDeviceToDevice, s));
+      coef_all.push_back(bond->coef[i]);
       csum += std::fabs(bond->coef[i]);
     }
-    kron_diag(s, kA, kB, A->E, B->E, T, op.coef_dev, op.OAcat, op.OBcat, op.D, op.Ediag);
-    build_packs(s, sc, op);
+    for (int i = 0; i < T; ++i) ptr_all.push_back(A->ops[bond->opA[i]].data);
+    for (int i = 0; i < T; ++i) ptr_all.push_back(B->ops[bond->opB[i]].data);
+    OpSetDesc& sd = setup[p];
+    sd.T = T; sd.kA = kA; sd.kB = kB; sd.pkm = op.pkm;
+    sd.EA = A->E; sd.EB = B->E;
+    sd.OAcat = op.OAcat; sd.OBcat = op.OBcat; sd.D = op.D; sd.Ediag = op.Ediag;
+    sd.p64 = static_cast<double*>(op.pack[0]);
+    sd.p32 = static_cast<float*>(op.pack[1]);
+    sd.p16 = op.pack[2];
+    const bool pk = op.pack[0] || op.pack[1] || op.pack[2];
+    work_max = std::max(work_max, (long)T * (kA * kA + kB * kB) + n +
+                                      (pk ? 2L * T * op.pkm * op.pkm : 0L));
     // projected one-site Pauli operators have spectral norm <= 1
     const double emax = A->E_host.back() + B->E_host.back();
     op.bup = emax + csum + 1e-12 * (std::fabs(emax) + csum + 1.0);
@@ -531,6 +598,26 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
     nevs[p] = std::max(nev, std::min(q, n));
     Xs[p] = sc.get<double>((size_t)nevs[p] * n);
     opp[p] = &ops[p];
+  }
+  {
+    double* coef_dev = sc.get<double>(std::max<size_t>(coef_all.size(), 1));
+    const double** ptr_dev = sc.get<const double*>(std::max<size_t>(ptr_all.size(), 1));
+    OpSetDesc* sd_dev = sc.get<OpSetDesc>(P);
+    for (int p = 0; p < P; ++p) {
+      ops[p].coef_dev = coef_dev + coef_off[p];
+      setup[p].coef = ops[p].coef_dev;
+      setup[p].opa = ptr_dev + ptr_off[p];
+      setup[p].opb = ptr_dev + ptr_off[p] + ops[p].T;
+    }
+    // pageable sources: the copies are staged before the calls return
+    if (!coef_all.empty())
+      RMC_HIP(hipMemcpyAsync(coef_dev, coef_all.data(), coef_all.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+    if (!ptr_all.empty())
+      RMC_HIP(hipMemcpyAsync(ptr_dev, ptr_all.data(), ptr_all.size() * sizeof(double*),
+                             hipMemcpyHostToDevice, s));
+    RMC_HIP(hipMemcpyAsync(sd_dev, setup.data(), P * sizeof(OpSetDesc), hipMemcpyHostToDevice, s));
+    op_setup_batched(s, sd_dev, P, work_max);
   }
   std::vector<SolveStats> st;
   eig_lowest_batch(ctx, opp, nevs, o, Xs, evals, st);
@@ -558,6 +645,10 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
                       ", max_res=" + std::to_string(st[p].max_res) + ")");
   std::vector<rmc_module*> out(P, nullptr);
   try {
+    std::vector<double> e_all;
+    std::vector<VecDesc> copies;
+    std::vector<size_t> e_off;
+    long cmax = 0;
     for (int p = 0; p < P; ++p) {
       if (!reqs[p].want_module) continue;
       const int n = ops[p].n;
@@ -578,12 +669,28 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
       out[p] = m;
       m->E = (double*)ctx->arena.alloc(k_eff * sizeof(double));
       m->basis = (double*)ctx->arena.alloc((size_t)k_eff * n * sizeof(double));
-      RMC_HIP(hipMemcpyAsync(m->E, m->E_host.data(), k_eff * sizeof(double), hipMemcpyHostToDevice, s));
-      copy_rows(s, k_eff, n, Xs[p], n, m->basis, n);
+      e_off.push_back(e_all.size());
+      e_all.insert(e_all.end(), m->E_host.begin(), m->E_host.end());
+      VecDesc v{};
+      v.nv = k_eff; v.n = n; v.out = m->basis; v.P = Xs[p];
+      copies.push_back(v);
+      VecDesc ve{};
+      ve.nv = 1; ve.n = k_eff; ve.out = m->E; ve.P = nullptr;  // source set after staging
+      copies.push_back(ve);
+      cmax = std::max(cmax, (long)k_eff * n);
       if (reps) {
         (*reps)[p].k_eff = k_eff;
         (*reps)[p].gap = gap;
       }
+    }
+    if (!copies.empty()) {
+      // every new module's basis and energies in one copy launch
+      double* e_dev = sc.get<double>(std::max<size_t>(e_all.size(), 1));
+      for (size_t i = 0; i < e_off.size(); ++i) copies[2 * i + 1].P = e_dev + e_off[i];
+      VecDesc* cd = sc.get<VecDesc>(copies.size());
+      RMC_HIP(hipMemcpyAsync(e_dev, e_all.data(), e_all.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      RMC_HIP(hipMemcpyAsync(cd, copies.data(), copies.size() * sizeof(VecDesc), hipMemcpyHostToDevice, s));
+      vec_batched(s, VEC_COPY, cd, (int)copies.size(), 1, cmax);
     }
     sync(ctx);
   } catch (...) {

@@ -790,6 +790,53 @@ __global__ void kron_pack_kernel(int T, int kA, int kB, int pkm, const double* _
   if (p16) p16[o] = to_lt<2>(v);
 }
 
+// One workgroup row per problem; a grid-stride loop over the concatenated work of
+// the problem: T k_A^2 copies, T k_B^2 copies, n diagonal entries, the pack entries.
+// The values are those of the per-operator path (same sums in the same order).
+__global__ __launch_bounds__(256) void op_setup_kernel(const OpSetDesc* __restrict__ descs) {
+  const OpSetDesc d = descs[blockIdx.y];
+  const int T = d.T, kA = d.kA, kB = d.kB, pk = d.pkm;
+  const long a2 = (long)kA * kA, b2 = (long)kB * kB, n = (long)kA * kB;
+  const long nA = T * a2, nB = T * b2;
+  const bool packs = d.p64 || d.p32 || d.p16;
+  const long nP = packs ? 2L * T * pk * pk : 0;
+  const long total = nA + nB + n + nP;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+    if (i < nA) {
+      d.OAcat[i] = d.opa[i / a2][i % a2];
+    } else if (i < nA + nB) {
+      const long j = i - nA;
+      d.OBcat[j] = d.opb[j / b2][j % b2];
+    } else if (i < nA + nB + n) {
+      const long t = i - nA - nB;
+      const int a = (int)(t / kB), b = (int)(t % kB);
+      const double e = d.EA[a] + d.EB[b];
+      double v = e;
+      for (int q = 0; q < T; ++q) v += d.coef[q] * d.opa[q][(long)a * kA + a] * d.opb[q][(long)b * kB + b];
+      if (d.D) d.D[t] = v;
+      d.Ediag[t] = e;
+    } else {
+      const long o = i - nA - nB - n;
+      const long pp = (long)pk * pk;
+      const int t = (int)(o / (2 * pp)), isA = (int)((o / pp) & 1);
+      const int r = (int)((o % pp) / pk), c = (int)(o % pk);
+      const int k = isA ? kA : kB;
+      double v = 0.0;
+      if (r < k && c < k) v = isA ? d.coef[t] * d.opa[t][(long)r * kA + c] : d.opb[t][(long)r * kB + c];
+      if (d.p64) d.p64[o] = v;
+      if (d.p32) d.p32[o] = (float)v;
+      if (d.p16) static_cast<__bf16*>(d.p16)[o] = to_lt<2>(v);
+    }
+  }
+}
+
+void op_setup_batched(hipStream_t s, const OpSetDesc* d, int P, long work_max) {
+  if (P <= 0 || work_max <= 0) return;
+  const long b = (work_max + 255) / 256;
+  const int gx = (int)(b > 512 ? 512 : b);
+  hipLaunchKernelGGL(op_setup_kernel, dim3(gx, P), dim3(256), 0, s, d);
+}
+
 int kron_pack_km(int kA, int kB) { return stream_km(std::max(kA, kB)); }
 
 size_t kron_pack_bytes(int precision, int kA, int kB, int T) {

@@ -5,6 +5,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "rmc_batch.h"
 #include "rmc_kernels.h"
 
@@ -60,6 +62,84 @@ void leaf_assemble(hipStream_t s, int n_sites, int n_terms, const DevTerm* terms
   hipLaunchKernelGGL(leaf_assemble_kernel, dim3((D + 63) / 64), dim3(64), 0, s, D, n_terms, terms, H);
 }
 
+// ---- batched leaf set-up (every leaf of a level in four launches) ------------------
+__global__ void leaf_zero_batched_kernel(const LeafSetDesc* __restrict__ descs) {
+  const LeafSetDesc d = descs[blockIdx.y];
+  const long D = 1L << d.n_sites, nn = D * D;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nn; t += (long)gridDim.x * blockDim.x)
+    d.H[t] = 0.0;
+}
+
+// The row-per-thread accumulation of leaf_assemble_kernel (same order, same values).
+__global__ void leaf_assemble_batched_kernel(const LeafSetDesc* __restrict__ descs) {
+  const LeafSetDesc d = descs[blockIdx.y];
+  const int D = 1 << d.n_sites;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  double* row = d.H + (long)r * D;
+  for (int t = 0; t < d.n_terms; ++t) {
+    DevTerm tm = d.terms[t];
+    int c = r;
+    double sgn = 1.0;
+    for (int u = 0; u < tm.nsite; ++u) {
+      int b = tm.bit[u];
+      int br = (r >> b) & 1;
+      sgn *= op_sign(tm.op[u], br);
+      if (op_flips(tm.op[u])) c ^= (1 << b);
+    }
+    double val = sgn > 0.0 ? tm.coef : -tm.coef;
+    row[c] = row[c] + val;
+  }
+}
+
+// Diagonal and Gershgorin row bounds (as dense_diag_kernel), one workgroup per row.
+__global__ __launch_bounds__(256) void leaf_diag_batched_kernel(const LeafSetDesc* __restrict__ descs) {
+  __shared__ double red[4];
+  const LeafSetDesc d = descs[blockIdx.y];
+  const int n = 1 << d.n_sites;
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const double* row = d.H + (long)i * n;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256)
+    if (j != i) acc += fabs(row[j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = (red[0] + red[1]) + (red[2] + red[3]);
+    d.D[i] = row[i];
+    d.rb[i] = row[i] + s;
+  }
+}
+
+// bmax = max over rows of the Gershgorin bound (as vec_max_kernel).
+__global__ __launch_bounds__(256) void leaf_bound_batched_kernel(const LeafSetDesc* __restrict__ descs) {
+  __shared__ double red[256];
+  const LeafSetDesc d = descs[blockIdx.x];
+  const int n = 1 << d.n_sites;
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, d.rb[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.bmax[0] = red[0];
+}
+
+void leaf_setup_batched(hipStream_t s, const LeafSetDesc* d, int P, int n_sites_max) {
+  if (P <= 0) return;
+  const long D = 1L << n_sites_max, nn = D * D;
+  const int zb = (int)std::min<long>((nn + 255) / 256, 1024);
+  hipLaunchKernelGGL(leaf_zero_batched_kernel, dim3(zb, P), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(leaf_assemble_batched_kernel, dim3((unsigned)((D + 63) / 64), P), dim3(64), 0, s, d);
+  hipLaunchKernelGGL(leaf_diag_batched_kernel, dim3((unsigned)D, P), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(leaf_bound_batched_kernel, dim3(P), dim3(256), 0, s, d);
+}
+
 // (O v)[r] = sum_c O[r][c] v[c] = sign(op, bit of r) * v[r ^ flip].
 __global__ void site_op_apply_kernel(int nv, int D, int bit, int op, const double* __restrict__ V,
                                      double* __restrict__ W) {
@@ -71,6 +151,25 @@ __global__ void site_op_apply_kernel(int nv, int D, int bit, int op, const doubl
     int c = op_flips(op) ? (r ^ (1 << bit)) : r;
     W[t] = op_sign(op, br) * V[(long)j * D + c];
   }
+}
+
+__global__ void site_op_batched_kernel(const SiteOpDesc* __restrict__ descs) {
+  const SiteOpDesc d = descs[blockIdx.y];
+  const int D = 1 << d.n_sites;
+  const long total = (long)d.nv * D;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total;
+       t += (long)gridDim.x * blockDim.x) {
+    int j = (int)(t / D), r = (int)(t % D);
+    int br = (r >> d.bit) & 1;
+    int c = op_flips(d.op) ? (r ^ (1 << d.bit)) : r;
+    d.W[t] = op_sign(d.op, br) * d.V[(long)j * D + c];
+  }
+}
+
+void site_op_batched(hipStream_t s, const SiteOpDesc* d, int P, long total_max) {
+  if (P <= 0 || total_max <= 0) return;
+  const int blocks = (int)std::min<long>((total_max + 255) / 256, 1024);
+  hipLaunchKernelGGL(site_op_batched_kernel, dim3(blocks, P), dim3(256), 0, s, d);
 }
 
 void site_op_apply(hipStream_t s, int nv, int n_sites, int bit, int op, const double* V, double* W) {

@@ -105,6 +105,25 @@ int kron_max_k();
 // pkm x pkm zero-padded tiles O_B^t and c_t O_A^t (in that order, row-major) in the
 // element type of the precision (FP64, FP32, BF16). kron_pack_bytes is 0 where the
 // streaming kernel does not take the size in that precision; null outputs are skipped.
+// Batched set-up of the coupling operators of a level (one descriptor per problem):
+// OAcat / OBcat (the T operators of each side, concatenated), the diagonal D and
+// E_A[a] + E_B[b] (Ediag) of H_eff, and the streaming packs (nullable).
+struct OpSetDesc {
+  int T, kA, kB, pkm;
+  const double* coef;          // T
+  const double* const* opa;    // T device pointers, k_A x k_A each
+  const double* const* opb;    // T device pointers, k_B x k_B each
+  const double* EA;
+  const double* EB;
+  double* OAcat;
+  double* OBcat;
+  double* D;
+  double* Ediag;
+  double* p64;
+  float* p32;
+  void* p16;
+};
+void op_setup_batched(hipStream_t s, const OpSetDesc* d, int P, long work_max);
 int kron_pack_km(int kA, int kB);
 size_t kron_pack_bytes(int precision, int kA, int kB, int T);
 void kron_pack(hipStream_t s, int T, int kA, int kB, const double* coef, const double* OA,

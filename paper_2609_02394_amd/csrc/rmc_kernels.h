@@ -55,9 +55,28 @@ struct DevTerm {
 };
 void leaf_assemble(hipStream_t s, int n_sites, int n_terms, const DevTerm* terms, double* H);
 
+// Every leaf of a batch: H (zeroed, then assembled as leaf_assemble does), its
+// diagonal D, Gershgorin row bounds rb and their maximum bmax[0]; four launches.
+struct LeafSetDesc {
+  int n_sites, n_terms;
+  const DevTerm* terms;
+  double* H;
+  double* D;
+  double* rb;
+  double* bmax;
+};
+void leaf_setup_batched(hipStream_t s, const LeafSetDesc* d, int P, int n_sites_max);
+
 // W_j = O_site v_j for nv vectors of a 2^n_sites space; op in {1:X, 2:T, 3:Z}.
 void site_op_apply(hipStream_t s, int nv, int n_sites, int bit, int op, const double* V,
                    double* W);
+// The same for several (V, W, site, op) at once, one descriptor each.
+struct SiteOpDesc {
+  int nv, n_sites, bit, op;
+  const double* V;
+  double* W;
+};
+void site_op_batched(hipStream_t s, const SiteOpDesc* d, int P, long total_max);
 
 // Diagonal of H_eff: D[a*kB+b] = EA[a] + EB[b] + sum_i c_i OA_i[a,a] OB_i[b,b];
 // Ediag[a*kB+b] = EA[a] + EB[b].

@@ -685,6 +685,7 @@ int filter(Batch& B, const std::vector<BP*>& L) {
       a.cnt.push_back(p->cnt);
     }
     apply_launch(B, L, a, true);
+    if (k % 8 == 1) B.da->flush();
     prev = cur;
     cur = nw;
   }
@@ -795,8 +796,12 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
       }
     }
     if (act.empty()) break;
+    // each phase's launches go out as soon as their tables are built, so the host
+    // prepares the next phase while the device runs this one
     const int r = filter(B, act);
+    B.da->flush();
     orthonormalize(B, act, ai, r);
+    B.da->flush();
     rayleigh_ritz(B, act, r, r == 0 ? 1 : 0, false);
     for (BP* p : act) p->iters++;
   }
