@@ -449,6 +449,9 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_
   constexpr int NCH = KM / CH;            // K chunks
   constexpr int NYE = KM / 4;             // Y elements per lane (NCH * KR)
   constexpr int NG = KM * KM / (4 * NT);  // 4-element staging groups per thread per matrix
+  // epilogue prefetch where the registers allow it (the FP64 single-buffer forms and
+  // the widest tiles are at the register limit already)
+  constexpr bool EPF = KM <= 64 && !(P == 0 && NWC == 1);
   static_assert(RTM % NWC == 0 && NG * 4 * NT == KM * KM, "tile split");
   extern __shared__ char smem_raw[];
   lt* Bs = reinterpret_cast<lt*>(smem_raw);
@@ -597,6 +600,29 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_
       store_tile(Bs);
       load_tile(nd, nt, true);
     }
+    // On a vector's last step, the epilogue's HBM operands (previous iterate and
+    // defect term) are loaded before stage 2 so that stage 2 hides their latency.
+    const bool last = t == Td - 1;
+    double exq[EPF ? CPW : 1][4], eeq[EPF ? CPW : 1][4];
+    if constexpr (EPF) {
+      if (last) {
+        const int kA = d->kA, kB = d->kB;
+        const long n = (long)kA * kB;
+        gptr<double> Xp = d->Xprev ? gview(d->Xprev) + (long)j * n : nullptr;
+        gptr<double> Ej = d->E ? gview(d->E) + (long)j * n : nullptr;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          const int col = (c0 + c) * 16 + l16;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rt * 16 + acc_row<P>(g, r);
+            const long idx = (row < kA && col < kB) ? (long)row * kB + col : 0;
+            exq[c][r] = Xp ? Xp[idx] : 0.0;
+            eeq[c][r] = Ej ? Ej[idx] : 0.0;
+          }
+        }
+      }
+    }
     // stage 2: acc += As rows x Z
 #pragma unroll
     for (int u = 0; u < NCH; ++u) {
@@ -609,7 +635,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_
         mma_frag<P>(acc[c], a.v, b);
       }
     }
-    if (t == Td - 1) {
+    if (last) {
       const int kA = d->kA, kB = d->kB, n = kA * kB;
       const double s1 = d->s1, s2 = d->s2, s3 = d->s3;
       gptr<double> Yj = gview(d->Y) + (long)j * n;
@@ -628,8 +654,13 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_
             const long idx = (long)row * kB + col;
             const double y = Yj[idx];
             double o = s1 * ((double)acc[c][r] + Ed[idx] * y) + s2 * y;
-            if (Xp) o += s3 * Xp[idx];
-            if (Ej) o += ph * Ej[idx];
+            if constexpr (EPF) {
+              if (Xp) o += s3 * exq[c][r];
+              if (Ej) o += ph * eeq[c][r];
+            } else {
+              if (Xp) o += s3 * Xp[idx];
+              if (Ej) o += ph * Ej[idx];
+            }
             oj[idx] = o;
           }
         }
