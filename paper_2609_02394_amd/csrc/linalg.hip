@@ -531,17 +531,47 @@ __device__ inline int uidx(int i, int j) { return j * (j + 1) / 2 + i; }  // i <
 __device__ inline int sidx(int i, int j) { return i <= j ? uidx(i, j) : uidx(j, i); }
 __device__ inline int rr_player(int pos, int step, int M) {
   if (pos == 0) return 0;
-  return 1 + (pos - 1 + step) % (M - 1);
+  int x = pos - 1 + step;  // < 2 (M - 1)
+  if (x >= M - 1) x -= M - 1;
+  return 1 + x;
 }
 
 size_t jacobi_lds_doubles(int m, bool vlds) {
   const int M = m + (m & 1), H = M / 2;
-  size_t d = (size_t)M * (M + 1) / 2 + 3 * (size_t)H + (3 * (size_t)H + 1) / 2 + 2 + 64;
+  // A (packed upper), two rotation buffers (c, s, t doubles; p, q, active ints),
+  // reduction scratch and flag
+  size_t d = (size_t)M * (M + 1) / 2 + 6 * (size_t)H + 3 * (size_t)H + 2 + 64;
   if (vlds) d += (size_t)m * m;
   return d;
 }
 static bool jacobi_v_in_lds(int m) { return jacobi_lds_doubles(m, true) * 8 <= 156 * 1024; }
 
+// 1/sqrt(x) and 1/x for x > 0 (normal range): the hardware estimates refined by two
+// Newton steps (each one squares the relative error). Only the rotation's c stays
+// tied to working precision through these (c^2 (1 + t^2) = 1); an inexact t leaves
+// a slightly larger off-diagonal entry for the next sweep.
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  y = y * (2.0 - x * y);
+  return y;
+}
+
+// Parallel cyclic Jacobi (round-robin ordering: M-1 rounds of M/2 disjoint pairs per
+// sweep), one 1024-thread workgroup, A packed in LDS. Each round has two phases
+// separated by barriers: (R) the round's rotations are computed from A while every
+// thread applies the previous round's rotations to V (double-buffered rotation
+// tables), (U) the 2x2 blocks of A touched by each pair of rotations are updated,
+// one flat work item per block. Rotation (Rutishauser's form of the symmetric 2x2
+// Schur decomposition): d = a_qq - a_pp, h = 2 a_pq, t = sign(d) h / (|d| + hypot(d, h)),
+// c = 1/sqrt(1 + t^2), s = t c (reciprocals and roots by refined estimates). A pair is rotated when a_pq^2 > eps^2 |a_pp a_qq| and
+// |a_pq| > eps ||A||_F; the sweep loop stops when no pair qualifies.
 __device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, long pstride,
                             double* __restrict__ evals, double* __restrict__ Vout,
                             double* __restrict__ Vg, int vlds, int max_sweeps, int* __restrict__ info,
@@ -549,17 +579,16 @@ __device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, lo
   const int M = m + (m & 1);
   const int H = M / 2;
   double* A = sm;                        // M*(M+1)/2
-  double* cs = A + M * (M + 1) / 2;      // H
-  double* sn = cs + H;                   // H
-  double* tn = sn + H;                   // H
-  int* pp = (int*)(tn + H);              // H
-  int* qq = pp + H;                      // H
-  int* act = qq + H;                     // H
-  double* red = (double*)(((uintptr_t)(act + H) + 15) & ~(uintptr_t)15);  // 64
+  double* cs = A + M * (M + 1) / 2;      // [2][H]
+  double* sn = cs + 2 * H;               // [2][H]
+  double* tn = sn + 2 * H;               // [2][H]
+  int* pp = (int*)(tn + 2 * H);          // [2][H]
+  int* qq = pp + 2 * H;                  // [2][H]
+  int* act = qq + 2 * H;                 // [2][H]
+  double* red = (double*)(((uintptr_t)(act + 2 * H) + 15) & ~(uintptr_t)15);  // 64
   int* flag = (int*)(red + 32);
   double* V = vlds ? (red + 64) : Vg;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int ty = tid >> 5, tx = tid & 31;  // 32 x 32 thread grid
 
   double nrm = 0.0;
   const int np = M * (M + 1) / 2;
@@ -584,8 +613,37 @@ __device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, lo
   double fro = 0.0;
   for (int w = 0; w < (nt >> 6); ++w) fro += red[w];
   fro = sqrt(fro);
-  const double eps = 2.220446049250313e-16;
+  const double eps = 2.220446049250313e-16, eps2 = eps * eps;
   const double floor_abs = eps * fro;
+  const int npair = H * (H + 1) / 2;  // blocks (k, l), k <= l
+  const long nvv = (long)m * H;
+
+  // (row, rotation) of this thread's first V item and the stride, without divisions
+  // in the loop
+  const int vk0 = tid % H, vr0 = tid / H, vdk = nt % H, vdr = nt / H;
+  auto apply_v = [&](int b) {
+    const double* c_ = cs + b * H;
+    const double* s_ = sn + b * H;
+    const int* p_ = pp + b * H;
+    const int* q_ = qq + b * H;
+    const int* a_ = act + b * H;
+    int k = vk0, r = vr0;
+    for (long t = tid; t < nvv; t += nt) {
+      if (a_[k]) {
+        const int p = p_[k], q = q_[k];
+        const double c = c_[k], s = s_[k];
+        const double vp = V[(long)r * m + p], vq = V[(long)r * m + q];
+        V[(long)r * m + p] = c * vp - s * vq;
+        V[(long)r * m + q] = s * vp + c * vq;
+      }
+      k += vdk;
+      r += vdr;
+      if (k >= H) {
+        k -= H;
+        ++r;
+      }
+    }
+  };
 
   int sweeps = 0;
   bool converged = false;
@@ -593,73 +651,80 @@ __device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, lo
     // any off-diagonal entry above its threshold?
     if (tid == 0) *flag = 0;
     __syncthreads();
-    for (int i = ty; i < m; i += 32)
-      for (int j = i + 1 + ((tx - i - 1) % 32 + 32) % 32; j < m; j += 32) {
-        double thr = fmax(eps * sqrt(fabs(A[uidx(i, i)] * A[uidx(j, j)])), floor_abs);
-        if (fabs(A[uidx(i, j)]) > thr) *flag = 1;
-      }
+    for (int t = tid; t < np; t += nt) {
+      int j = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+      while (j * (j + 1) / 2 > t) --j;
+      while ((j + 1) * (j + 2) / 2 <= t) ++j;
+      const int i = t - j * (j + 1) / 2;
+      if (i == j || j >= m) continue;
+      const double apq = A[t];
+      if (apq * apq > eps2 * fabs(A[uidx(i, i)] * A[uidx(j, j)]) && fabs(apq) > floor_abs) *flag = 1;
+    }
     __syncthreads();
     if (*flag == 0) { converged = true; break; }
     if (sweeps >= max_sweeps) break;
     ++sweeps;
     __syncthreads();
     for (int step = 0; step < M - 1; ++step) {
+      const int b = step & 1;
+      // (R) rotations of this round; V update with the previous round's
       for (int k = tid; k < H; k += nt) {
         int p = rr_player(k, step, M), q = rr_player(M - 1 - k, step, M);
         if (p > q) { int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0, t = 0.0;
         int a = 0;
         if (q < m) {
-          double apq = A[uidx(p, q)];
-          double app = A[uidx(p, p)], aqq = A[uidx(q, q)];
-          double thr = fmax(eps * sqrt(fabs(app * aqq)), floor_abs);
-          if (fabs(apq) > thr) {
-            double tau = (aqq - app) / (2.0 * apq);
-            t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
+          const double apq = A[uidx(p, q)];
+          const double app = A[uidx(p, p)], aqq = A[uidx(q, q)];
+          if (apq * apq > eps2 * fabs(app * aqq) && fabs(apq) > floor_abs) {
+            const double d = aqq - app, h = 2.0 * apq;
+            const double x = d * d + h * h;
+            const double r = x * rsqrt_nr(x);
+            t = (d >= 0.0 ? h : -h) * rcp_nr(fabs(d) + r);
+            c = rsqrt_nr(1.0 + t * t);
             s = t * c;
             a = 1;
           }
         }
-        pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s; tn[k] = t; act[k] = a;
+        pp[b * H + k] = p; qq[b * H + k] = q; cs[b * H + k] = c; sn[b * H + k] = s;
+        tn[b * H + k] = t; act[b * H + k] = a;
       }
+      if (step > 0) apply_v(b ^ 1);
       __syncthreads();
-      for (int k = ty; k < H; k += 32)
-        for (int l = k + ((tx - k) % 32 + 32) % 32; l < H; l += 32) {
-        if (!act[k] && !act[l]) continue;
-        int pk = pp[k], qk = qq[k];
+      // (U) 2x2 blocks of A, one flat work item per block (k, l), k <= l
+      const int* p_ = pp + b * H;
+      const int* q_ = qq + b * H;
+      const int* a_ = act + b * H;
+      for (int w = tid; w < npair; w += nt) {
+        int l = (int)((sqrtf(8.0f * w + 1.0f) - 1.0f) * 0.5f);
+        while (l * (l + 1) / 2 > w) --l;
+        while ((l + 1) * (l + 2) / 2 <= w) ++l;
+        const int k = w - l * (l + 1) / 2;
+        if (!a_[k] && !a_[l]) continue;
+        const int pk = p_[k], qk = q_[k];
         if (k == l) {
-          double apq = A[uidx(pk, qk)];
-          double tk = tn[k];
+          const double apq = A[uidx(pk, qk)];
+          const double tk = tn[b * H + k];
           A[uidx(pk, pk)] -= tk * apq;
           A[uidx(qk, qk)] += tk * apq;
           A[uidx(pk, qk)] = 0.0;
           continue;
         }
-        int pl = pp[l], ql = qq[l];
-        double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
-        int i00 = sidx(pk, pl), i01 = sidx(pk, ql), i10 = sidx(qk, pl), i11 = sidx(qk, ql);
-        double m00 = A[i00], m01 = A[i01], m10 = A[i10], m11 = A[i11];
-        double r00 = ck * m00 - sk * m10, r01 = ck * m01 - sk * m11;
-        double r10 = sk * m00 + ck * m10, r11 = sk * m01 + ck * m11;
+        const int pl = p_[l], ql = q_[l];
+        const double ck = cs[b * H + k], sk = sn[b * H + k], cl = cs[b * H + l], sl = sn[b * H + l];
+        const int i00 = sidx(pk, pl), i01 = sidx(pk, ql), i10 = sidx(qk, pl), i11 = sidx(qk, ql);
+        const double m00 = A[i00], m01 = A[i01], m10 = A[i10], m11 = A[i11];
+        const double r00 = ck * m00 - sk * m10, r01 = ck * m01 - sk * m11;
+        const double r10 = sk * m00 + ck * m10, r11 = sk * m01 + ck * m11;
         A[i00] = r00 * cl - r01 * sl;
         A[i01] = r00 * sl + r01 * cl;
         A[i10] = r10 * cl - r11 * sl;
         A[i11] = r10 * sl + r11 * cl;
-        }
-      const long nvv = (long)m * H;
-      for (long t = tid; t < nvv; t += nt) {
-        int k = (int)(t % H);
-        int r = (int)(t / H);
-        if (!act[k]) continue;
-        int p = pp[k], q = qq[k];
-        double c = cs[k], s = sn[k];
-        double vp = V[(long)r * m + p], vq = V[(long)r * m + q];
-        V[(long)r * m + p] = c * vp - s * vq;
-        V[(long)r * m + q] = s * vp + c * vq;
       }
       __syncthreads();
     }
+    apply_v((M - 2) & 1);  // the sweep's last round
+    __syncthreads();
   }
   for (int i = tid; i < m; i += nt) {
     double di = A[uidx(i, i)];
