@@ -206,6 +206,90 @@ void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int
   hipLaunchKernelGGL(gemm_grouped_kernel, grid, dim3(256), 0, s, (int)tA, (int)tB, ksplit, d);
 }
 
+// ---- Gram partials of tall-skinny blocks -------------------------------------------
+// One workgroup (8 waves) per (problem, K-slice): the slice of every row of A (and of
+// B unless B == A) is staged in LDS 32 columns at a time, and each wave accumulates
+// its 16x16 output tiles with FP64 MFMA. Lane group g takes the K run 8g..8g+7 of a
+// chunk (the order of K inside an MFMA step is free), so operands are contiguous
+// LDS reads. Rows past ca / cb are staged as zeros. A slice past n writes zeros.
+constexpr int GR_KC = 32, GR_PW = GR_KC + 2, GR_ROWS = 192;
+
+template <int TPW>
+__global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ descs, int ks) {
+  __shared__ double As[GR_ROWS * GR_PW];
+  __shared__ double Bs[GR_ROWS * GR_PW];
+  const GramDesc d = descs[blockIdx.y];
+  const int ca = d.ca, cb = d.cb, n = d.n;
+  if (ca <= 0 || cb <= 0) return;
+  const int s = blockIdx.x;
+  int lk = (n + ks - 1) / ks;
+  lk = ((lk + GR_KC - 1) / GR_KC) * GR_KC;
+  const int k0 = s * lk, k1 = min(n, k0 + lk);
+  const bool same = d.A == d.B && ca == cb;
+  const int TA = (ca + 15) / 16, TB = (cb + 15) / 16, nt = TA * TB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  d4 acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  const double* Bsrc = same ? As : Bs;
+  for (int kc = k0; kc < k1; kc += GR_KC) {
+    const int ra = TA * 16, rb = TB * 16;
+    for (int e = tid; e < ra * GR_KC; e += 512) {
+      const int r = e / GR_KC, c = e % GR_KC, k = kc + c;
+      As[r * GR_PW + c] = (r < ca && k < k1) ? d.A[(long)r * n + k] : 0.0;
+    }
+    if (!same)
+      for (int e = tid; e < rb * GR_KC; e += 512) {
+        const int r = e / GR_KC, c = e % GR_KC, k = kc + c;
+        Bs[r * GR_PW + c] = (r < cb && k < k1) ? d.B[(long)r * n + k] : 0.0;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = wave + 8 * i;
+      if (t >= nt) break;
+      const int tr = t / TB, tc = t % TB;
+      const double* ar = As + (tr * 16 + l16) * GR_PW + 8 * g;
+      const double* br = Bsrc + (tc * 16 + l16) * GR_PW + 8 * g;
+      double av[8], bv[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 x = *reinterpret_cast<const double2*>(ar + 2 * q);
+        const double2 y = *reinterpret_cast<const double2*>(br + 2 * q);
+        av[2 * q] = x.x; av[2 * q + 1] = x.y;
+        bv[2 * q] = y.x; bv[2 * q + 1] = y.y;
+      }
+#pragma unroll
+      for (int st = 0; st < 8; ++st) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st], acc[i], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* out = d.work + (long)s * ca * cb;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int t = wave + 8 * i;
+    if (t >= nt) break;
+    const int tr = t / TB, tc = t % TB;
+    const int col = tc * 16 + l16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = tr * 16 + 4 * r + g;  // FP64 accumulator layout
+      if (row < ca && col < cb) out[(long)row * cb + col] = acc[i][r];
+    }
+  }
+}
+
+void gram_batched(hipStream_t s, const GramDesc* d, int P, int ks, int cmax) {
+  if (P <= 0 || cmax <= 0) return;
+  if (ks < 1) ks = 1;
+  const int t = (cmax + 15) / 16;
+  if (t * t <= 8 * 5)
+    hipLaunchKernelGGL(gram_kernel<5>, dim3(ks, P), dim3(512), 0, s, d, ks);
+  else
+    hipLaunchKernelGGL(gram_kernel<18>, dim3(ks, P), dim3(512), 0, s, d, ks);
+}
+
 int gemm_pick_ksplit(int M, int N, int K, int batch) {
   long tiles = (long)((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N) * batch;
   if (tiles >= 256) return 1;

@@ -40,6 +40,15 @@ struct GemmDesc {
   double* work;
 };
 
+// Gram partials of tall-skinny blocks: work[s][i][j] = sum over K-slice s of
+// A[i][k] B[j][k] (A: ca x n, B: cb x n, row-major, ca, cb <= 192), ks slices.
+struct GramDesc {
+  int ca, cb, n, pad;
+  const double* A;
+  const double* B;
+  double* work;
+};
+
 // Symmetric eigensolver / Cholesky on m x m given as nparts partials (pstride apart).
 struct EigDesc {
   int m, nparts;
@@ -130,6 +139,7 @@ void kron_pack(hipStream_t s, int T, int kA, int kB, const double* coef, const d
                const double* OB, void* p64, void* p32, void* p16);
 void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int Mmax, int Nmax,
                   int ksplit);
+void gram_batched(hipStream_t s, const GramDesc* d, int P, int ks, int cmax);
 void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax);
 void chol_batched(hipStream_t s, const CholDesc* d, int P, int mmax);
 void vec_batched(hipStream_t s, VecOp op, const VecDesc* d, int P, int nvmax, long elems_max);

@@ -275,16 +275,21 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
 void gram_launch(Batch& B, const std::vector<BP*>& L, const std::vector<const double*>& Ap,
                  const std::vector<const double*>& Bp, const std::vector<int>& ca,
                  const std::vector<int>& cb) {
-  std::vector<GemmDesc> g;
+  if (L.empty()) return;
+  std::vector<GramDesc> g;
+  int cmax = 0;
   for (size_t i = 0; i < L.size(); ++i) {
     BP* p = L[i];
-    GemmDesc d{};
-    d.M = ca[i]; d.N = cb[i]; d.K = p->n;
-    d.A = Ap[i]; d.lda = p->n; d.B = Bp[i]; d.ldb = p->n;
-    d.alpha = 1.0; d.beta = 0.0; d.work = p->kwork;
+    GramDesc d{};
+    d.ca = ca[i]; d.cb = cb[i]; d.n = p->n;
+    d.A = Ap[i]; d.B = Bp[i]; d.work = p->kwork;
     g.push_back(d);
+    cmax = std::max(cmax, std::max(ca[i], cb[i]));
   }
-  gemm_launch(B, false, true, g, B.KS);
+  const GramDesc* dd = B.da->add(g);
+  hipStream_t st = B.ctx->stream;
+  const int P = (int)g.size(), ks = B.KS;
+  B.da->defer([=] { gram_batched(st, dd, P, ks, cmax); });
 }
 
 void read_state(Batch& B) {
@@ -729,8 +734,9 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
     p->matvecs = 0;
   }
   const int P = (int)probs.size();
-  const int t1 = (B.mmax + 63) / 64;
-  B.KS = std::max(1, std::min(64, 512 / std::max(1, P * t1 * t1)));
+  // K-slices of the Gram products: enough workgroups to cover the chip, slices of at
+  // least 128 columns
+  B.KS = std::max(1, std::min({64, (384 + P - 1) / P, std::max(1, B.nmax / 128)}));
   B.trs = 2 * B.mmax + 4;  // theta, res, then room for 8 ints
   B.TR = sc.get<double>((size_t)P * B.trs);
   B.TRh.assign((size_t)P * B.trs, 0.0);
