@@ -271,6 +271,8 @@ void start_block(hipStream_t s, int n, int m, const double* D, double eps, unsig
                      (uint64_t)seed, X);
 }
 
+// sel[rank of D[i]] = i for the m smallest entries (ties by index), one thread per
+// entry ranking it against all others (D is read from L2; the same j for every lane).
 __global__ void rank_select_batched_kernel(const StartDesc* __restrict__ descs) {
   const StartDesc d = descs[blockIdx.z];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += gridDim.x * blockDim.x) {

@@ -629,41 +629,28 @@ int filter(Batch& B, const std::vector<BP*>& L) {
     }
     vec_launch(B, VEC_SCALE_ADD, ed);
   }
-  // phi tables: row k holds phi_k at the active Ritz values; row 0 holds sigma_1/e
-  std::vector<double*> phid(L.size());
-  std::vector<std::vector<double>> sigs(L.size());
-  for (size_t i = 0; i < L.size(); ++i) {
-    BP* p = L[i];
-    const int cn = p->cnt;
-    std::vector<double> tab((size_t)(P + 1) * cn);
-    for (int j = 0; j < cn; ++j) tab[j] = p->sigma1 / p->e;
-    std::vector<double> pm1(cn, 1.0), pk(cn);
-    for (int j = 0; j < cn; ++j) {
-      pk[j] = (p->sigma1 / p->e) * (p->th[p->nlock + j] - p->c);
-      tab[(size_t)cn + j] = pk[j];
-    }
-    const double tau2 = 2.0 / p->sigma1;
-    double sg = p->sigma1;
-    sigs[i].push_back(sg);
-    for (int k = 1; k < P; ++k) {
-      const double sg2 = 1.0 / (tau2 - sg);
-      for (int j = 0; j < cn; ++j) {
-        double nx = (2.0 * sg2 / p->e) * (p->th[p->nlock + j] - p->c) * pk[j] - sg * sg2 * pm1[j];
-        pm1[j] = pk[j];
-        pk[j] = nx;
-        tab[(size_t)(k + 1) * cn + j] = nx;
-      }
-      sg = sg2;
-      sigs[i].push_back(sg);
-    }
-    phid[i] = B.da->add(tab);
-  }
+  // phi_k at the active Ritz values, one row per filter step, computed on the host just
+  // before the step that uses it (so the device starts on the first steps while later
+  // rows are still being computed); row 0 holds sigma_1/e
+  const size_t NL = L.size();
+  std::vector<std::vector<double>> pm1(NL), pk(NL);
+  std::vector<double> sgp(NL), tau2(NL);
+  std::vector<const double*> rowk(NL);
   {
     std::vector<VecDesc> dd;
-    for (size_t i = 0; i < L.size(); ++i) {
+    for (size_t i = 0; i < NL; ++i) {
       BP* p = L[i];
+      const int cn = p->cnt;
+      std::vector<double> r0(cn, p->sigma1 / p->e);
+      const double* row0 = B.da->add(r0);
+      pk[i].resize(cn);
+      for (int j = 0; j < cn; ++j) pk[i][j] = (p->sigma1 / p->e) * (p->th[p->nlock + j] - p->c);
+      pm1[i].assign(cn, 1.0);
+      rowk[i] = B.da->add(pk[i]);
+      sgp[i] = p->sigma1;
+      tau2[i] = 2.0 / p->sigma1;
       VecDesc v{};
-      v.nv = p->cnt; v.n = p->n; v.out = p->Y[0]; v.P = p->E; v.a = phid[i]; v.asgn = 1.0;
+      v.nv = p->cnt; v.n = p->n; v.out = p->Y[0]; v.P = p->E; v.a = row0; v.asgn = 1.0;
       v.b = 0.0; v.Q = nullptr;
       dd.push_back(v);
     }
@@ -678,19 +665,34 @@ int filter(Batch& B, const std::vector<BP*>& L) {
         break;
       }
     Apply a;
-    for (size_t i = 0; i < L.size(); ++i) {
+    std::vector<double> sk1v(NL);
+    for (size_t i = 0; i < NL; ++i) {
       BP* p = L[i];
-      const double sk = sigs[i][k - 1], sk1 = sigs[i][k];
+      const double sk = sgp[i], sk1 = 1.0 / (tau2[i] - sk);
+      sk1v[i] = sk1;
       a.Y.push_back(role_ptr(p, cur));
       a.out.push_back(role_ptr(p, nw));
       a.prev.push_back(prev >= 0 ? role_ptr(p, prev) : nullptr);
       a.E.push_back(p->E);
-      a.phi.push_back(phid[i] + (size_t)k * p->cnt);
+      a.phi.push_back(rowk[i]);
       a.sc.push_back({2.0 * sk1 / p->e, -2.0 * p->c * sk1 / p->e, prev >= 0 ? -sk * sk1 : 0.0});
       a.cnt.push_back(p->cnt);
     }
     apply_launch(B, L, a, true);
     if (k % 8 == 1) B.da->flush();
+    // row k+1 of every problem
+    for (size_t i = 0; i < NL; ++i) {
+      BP* p = L[i];
+      const int cn = p->cnt;
+      const double sg = sgp[i], sg2 = sk1v[i];
+      for (int j = 0; j < cn; ++j) {
+        const double nx = (2.0 * sg2 / p->e) * (p->th[p->nlock + j] - p->c) * pk[i][j] - sg * sg2 * pm1[i][j];
+        pm1[i][j] = pk[i][j];
+        pk[i][j] = nx;
+      }
+      rowk[i] = B.da->add(pk[i]);
+      sgp[i] = sg2;
+    }
     prev = cur;
     cur = nw;
   }
@@ -701,7 +703,7 @@ int filter(Batch& B, const std::vector<BP*>& L) {
       BP* p = L[i];
       VecDesc v{};
       v.nv = p->cnt; v.n = p->n; v.out = p->Y[outr]; v.P = role_ptr(p, 3);
-      v.a = phid[i] + (size_t)P * p->cnt; v.asgn = 1.0; v.b = 1.0; v.Q = p->Y[cur];
+      v.a = rowk[i]; v.asgn = 1.0; v.b = 1.0; v.Q = p->Y[cur];
       dd.push_back(v);
     }
     vec_launch(B, VEC_SCALE_ADD, dd);  // Y_P = X phi_P + D_P
