@@ -529,10 +529,11 @@ bool update_problem(Batch& B, BP* p, int idx, int max_iter, double tol, int pmax
   // rounding noise relative to the filtered defect); the filter does not aim below it.
   const double floor_red = p->prec == RMC_BF16 ? 3e-2 : (p->prec == RMC_FP32 ? 1e-5 : 0.0);
   // escalate when the last filter fell well short of both its Chebyshev damping and
-  // that floor: the rounding noise of this precision now dominates
+  // that floor: the rounding noise of this precision now dominates (not judged on the
+  // first filter, whose Ritz values and bounds come from the start block)
   static const bool no_ladder = getenv("RMC_NO_LADDER") != nullptr;
-  if (p->prec != RMC_FP64 && p->iters > 0 && !no_ladder &&
-      worst > std::max(floor_red, 30.0 * p->prev_expect) * p->prev_worst)
+  if (p->prec != RMC_FP64 && p->iters > 1 && !no_ladder &&
+      worst > std::max(floor_red, 100.0 * p->prev_expect) * p->prev_worst)
     p->prec = p->prec == RMC_BF16 ? RMC_FP32 : RMC_FP64;
   p->prev_worst = worst;
   p->cnt = m - p->nlock;
