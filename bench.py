@@ -353,6 +353,16 @@ def serve_bench(args):
         time.sleep(0.0005)
     th.join()
     ctx.serve_stop()
+    # the plain per-job FP64 recursion over the first measured jobs, one at a time
+    plain = None
+    if not args.no_plain:
+        nplain = min(24, args.jobs)
+        p0 = time.perf_counter()
+        for i in range(warm, warm + nplain):
+            ctx.recurse(*rmc.job_chain(stream[i][1]))
+        plain = {"form": "plain per-job FP64 recursion, one job at a time (first jobs of the "
+                         "measured stream)", "jobs": nplain,
+                 "value": nplain / (time.perf_counter() - p0), "unit": "solves/s"}
     meas = list(range(warm, len(stream)))
     lat = np.array([res[i][2] for i in meas])
     ok = sum(res[i][1] == 0 for i in meas)
@@ -369,6 +379,7 @@ def serve_bench(args):
                    "jobs": args.jobs, "warmup_jobs": warm, "precision": args.precision,
                    "completed_ok": ok, "offered_span_s": stream[-1][0] - stream[warm][0],
                    "max_rel_err_sample": max(errs), "sample_size": len(sample)},
+        "plain_per_job_fp64": plain,
     }
     print(json.dumps(out))
     ctx.close()

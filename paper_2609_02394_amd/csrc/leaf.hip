@@ -271,18 +271,93 @@ void start_block(hipStream_t s, int n, int m, const double* D, double eps, unsig
                      (uint64_t)seed, X);
 }
 
-// sel[rank of D[i]] = i for the m smallest entries (ties by index), one thread per
-// entry ranking it against all others (D is read from L2; the same j for every lane).
-__global__ void rank_select_batched_kernel(const StartDesc* __restrict__ descs) {
-  const StartDesc d = descs[blockIdx.z];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.n; i += gridDim.x * blockDim.x) {
-    double di = d.D[i];
-    int rank = 0;
-    for (int j = 0; j < d.n; ++j) {
-      double dj = d.D[j];
-      rank += (dj < di) || (dj == di && j < i);
+// sel[r] = index of the entry of rank r among the m smallest of D (ties by index), one
+// workgroup per problem. An MSD radix select over order-preserving 64-bit keys
+// (8 passes of 8 bits, LDS histograms) finds the key K of rank m-1 and how many
+// entries equal to K are needed; the entries below K plus the lowest-index entries
+// equal to K are then gathered and ranked among themselves (m <= 192).
+__device__ inline unsigned long long order_key(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x + 0.0);  // -0 -> +0
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ __launch_bounds__(256) void rank_select_batched_kernel(const StartDesc* __restrict__ descs) {
+  __shared__ unsigned int hist[256];
+  __shared__ unsigned long long s_prefix, s_mask;
+  __shared__ int s_need;
+  __shared__ int cnt_eq[256];
+  __shared__ int n_less;
+  __shared__ unsigned long long ck[192];
+  __shared__ int ci[192];
+  const StartDesc d = descs[blockIdx.x];
+  const int n = d.n, m = d.m, tid = threadIdx.x;
+  if (m <= 0 || m > 192) return;
+  if (tid == 0) { s_prefix = 0; s_mask = 0; s_need = m; n_less = 0; }
+  __syncthreads();
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 56 - 8 * pass;
+    hist[tid] = 0;
+    __syncthreads();
+    const unsigned long long pre = s_prefix, msk = s_mask;
+    for (int i = tid; i < n; i += 256) {
+      const unsigned long long k = order_key(d.D[i]);
+      if ((k & msk) == pre) atomicAdd(&hist[(k >> shift) & 255u], 1u);
     }
-    if (rank < d.m) d.sel[rank] = i;
+    __syncthreads();
+    if (tid == 0) {
+      int need = s_need, b = 0;
+      while (b < 255 && (int)hist[b] < need) need -= (int)hist[b++];
+      s_need = need;
+      s_prefix = pre | ((unsigned long long)b << shift);
+      s_mask = msk | (255ull << shift);
+    }
+    __syncthreads();
+  }
+  const unsigned long long K = s_prefix;
+  const int need = s_need;  // entries equal to K to take (>= 1)
+  // contiguous index chunk per thread: counts of entries equal to K, exclusive scan
+  const int chunk = (n + 255) / 256;
+  const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+  int ce = 0;
+  for (int i = lo; i < hi; ++i) {
+    const unsigned long long k = order_key(d.D[i]);
+    if (k < K) {
+      const int slot = atomicAdd(&n_less, 1);
+      ck[slot] = k;
+      ci[slot] = i;
+    } else if (k == K) {
+      ++ce;
+    }
+  }
+  cnt_eq[tid] = ce;
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int t = 0; t < 256; ++t) {
+      const int c = cnt_eq[t];
+      cnt_eq[t] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  const int base_less = m - need;  // == n_less
+  int before = cnt_eq[tid];
+  for (int i = lo; i < hi && before < need; ++i) {
+    const unsigned long long k = order_key(d.D[i]);
+    if (k == K) {
+      ck[base_less + before] = k;
+      ci[base_less + before] = i;
+      ++before;
+    }
+  }
+  __syncthreads();
+  // rank the m candidates by (key, index)
+  for (int c = tid; c < m; c += 256) {
+    const unsigned long long kc = ck[c];
+    const int ic = ci[c];
+    int r = 0;
+    for (int e = 0; e < m; ++e) r += (ck[e] < kc) || (ck[e] == kc && ci[e] < ic);
+    d.sel[r] = ic;
   }
 }
 
@@ -302,8 +377,7 @@ __global__ void start_block_batched_kernel(const StartDesc* __restrict__ descs) 
 
 void start_batched(hipStream_t s, const StartDesc* d, int P, int nmax, int mmax) {
   if (P <= 0) return;
-  int bx = (nmax + 255) / 256;
-  hipLaunchKernelGGL(rank_select_batched_kernel, dim3(bx, 1, P), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(rank_select_batched_kernel, dim3(P), dim3(256), 0, s, d);
   long tot = (long)nmax * mmax;
   int bx2 = (int)((tot + 255) / 256);
   if (bx2 > 2048) bx2 = 2048;

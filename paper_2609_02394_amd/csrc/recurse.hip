@@ -371,6 +371,8 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
     try {
       solve(ch);
     } catch (const Error& e) {
+      if (getenv("RMC_TRACE_SOLVER"))
+        fprintf(stderr, "[rmc] level chunk of %zu tasks failed: %s\n", ch.size(), e.what());
       if (ch.size() == 1) {
         job_fail(ctx, *ch[0].J, e.code, e.what());
         continue;
@@ -439,6 +441,8 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
     try {
       solve(ch);
     } catch (const Error& e) {
+      if (getenv("RMC_TRACE_SOLVER"))
+        fprintf(stderr, "[rmc] level chunk of %zu tasks failed: %s\n", ch.size(), e.what());
       if (ch.size() == 1) {
         job_fail(ctx, *ch[0].J, e.code, e.what());
         continue;

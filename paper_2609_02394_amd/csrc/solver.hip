@@ -823,7 +823,9 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
       fi.push_back(i);
     }
   if (!fin.empty()) {
-    for (BP* p : fin) p->cnt = p->m;
+    // converged problems: the wanted set only (every row of it met the tolerance); the
+    // unconverged guard rows would otherwise mix into it at residual / gap
+    for (BP* p : fin) p->cnt = p->state == 1 ? std::max(p->nev, std::min(p->nw, p->m)) : p->m;
     rayleigh_ritz(B, fin, 6, 7, true);
     std::vector<VecDesc> cp;
     for (BP* p : fin) {
@@ -897,11 +899,16 @@ void eig_lowest_batch(rmc_ctx* ctx, const std::vector<const CoupledOp*>& ops,
     evals[i].assign(p->th.begin(), p->th.begin() + p->nev);
     int nwf = p->nev;
     const double scale = std::max({1.0, std::fabs(p->op->bup), std::fabs(p->th[0])});
-    while (nwf < p->m && p->th[nwf] - p->th[nwf - 1] <= 1e-6 * scale) ++nwf;
+    const int lim = std::min(p->cnt > 0 ? p->cnt : p->m, p->m);  // rows of the final Rayleigh-Ritz
+    while (nwf < lim && p->th[nwf] - p->th[nwf - 1] <= 1e-6 * scale) ++nwf;
     double mr = 0.0;
-    for (int j = 0; j < std::min(nwf, p->m); ++j) mr = std::max(mr, p->rs[j] / scale);
+    for (int j = 0; j < std::min(nwf, lim); ++j) mr = std::max(mr, p->rs[j] / scale);
     stats[i].max_res = mr;
     stats[i].status = (p->state == 1 && mr <= 10.0 * tol) ? RMC_OK : RMC_ERR_NOCONV;
+    if (stats[i].status != RMC_OK && getenv("RMC_TRACE_SOLVER"))
+      fprintf(stderr, "[rmc] problem %d of %d not converged: n=%d nev=%d m=%d guard=%d state=%d iters=%d "
+              "th0=%.6e res0=%.3e nlock=%d\n", i, P, p->n, p->nev, p->m, p->guard, p->state, p->iters,
+              p->th.empty() ? 0.0 : p->th[0], p->rs.empty() ? 0.0 : p->rs[0], p->nlock);
   }
 }
 
