@@ -20,6 +20,7 @@ Models (J, h, Delta, fields as in ``ChainJob``):
                   = sum (J/4) XX - (J/4) TT + (J Delta/4) ZZ
   rfheis      : H = J sum S_s . S_{s+1} + sum h_s Sz_s
   tfim_ladder : H = -J sum_legs ZZ - J_rung sum_rungs ZZ - h sum X
+  tfim_nnn    : H = -J sum Z_s Z_{s+1} - j2 sum Z_s Z_{s+2} - h sum X_s
 """
 from __future__ import annotations
 
@@ -36,8 +37,11 @@ PAULI = {
 
 
 def bonds(job):
-    """Nearest-neighbour site pairs (s, t), s < t, in lexicographic order."""
+    """Bonded site pairs (s, t), s < t, in lexicographic order."""
     n = job.n_sites
+    if job.model == "tfim_nnn":
+        pairs = [(s, s + 1) for s in range(n - 1)] + [(s, s + 2) for s in range(n - 2)]
+        return sorted(pairs)
     if job.model == "tfim_ladder":
         out = []
         for s in range(n):
@@ -58,6 +62,8 @@ def bond_terms(job, s, t):
         if t - s == 2:
             return [(-job.J, "Z", "Z")]
         return [(-job.j_rung, "Z", "Z")]
+    if job.model == "tfim_nnn":
+        return [(-job.J if t - s == 1 else -job.j2, "Z", "Z")]
     if job.model == "xxz":
         return [(0.25 * job.J, "X", "X"), (-0.25 * job.J, "T", "T"),
                 (0.25 * job.J * job.delta, "Z", "Z")]
@@ -69,7 +75,7 @@ def bond_terms(job, s, t):
 
 def site_terms(job, s):
     """One-site terms at site s as (coef, op)."""
-    if job.model in ("tfim", "tfim_ladder"):
+    if job.model in ("tfim", "tfim_ladder", "tfim_nnn"):
         return [(-job.h, "X")]
     if job.model == "rfheis":
         return [(0.5 * job.fields[s], "Z")]

@@ -14,6 +14,7 @@ Models (parameters from ``workloads.ChainJob``):
   rfheis      : J/4 XX - J/4 TT + J/4 ZZ per bond, h_s/2 Z_s   (J S.S + h_s Sz_s)
   tfim_ladder : spins s = 2x + y; legs (s, s+2) -J ZZ, rungs (2x, 2x+1) -J_rung ZZ,
                 fields -h X_s
+  tfim_nnn    : -J Z_s Z_{s+1}, -j2 Z_s Z_{s+2}, -h X_s
 """
 from __future__ import annotations
 
@@ -27,6 +28,8 @@ def _pairs(job) -> List[Tuple[int, int]]:
     if job.model == "tfim_ladder":
         out = [(s, s + 1) for s in range(0, n, 2)] + [(s, s + 2) for s in range(n - 2)]
         return sorted(out)
+    if job.model == "tfim_nnn":
+        return sorted([(s, s + 1) for s in range(n - 1)] + [(s, s + 2) for s in range(n - 2)])
     return [(s, s + 1) for s in range(n - 1)]
 
 
@@ -36,6 +39,8 @@ def _pair_terms(job, s, t):
         return [(-job.J, "Z", "Z")]
     if m == "tfim_ladder":
         return [(-job.J if t - s == 2 else -job.j_rung, "Z", "Z")]
+    if m == "tfim_nnn":
+        return [(-job.J if t - s == 1 else -job.j2, "Z", "Z")]
     if m == "xxz":
         return [(0.25 * job.J, "X", "X"), (-0.25 * job.J, "T", "T"),
                 (0.25 * job.J * job.delta, "Z", "Z")]
@@ -45,7 +50,7 @@ def _pair_terms(job, s, t):
 
 
 def _site_terms(job, s):
-    if job.model in ("tfim", "tfim_ladder"):
+    if job.model in ("tfim", "tfim_ladder", "tfim_nnn"):
         return [(-job.h, "X")]
     if job.model == "rfheis":
         return [(0.5 * job.fields[s], "Z")]

@@ -12,7 +12,8 @@ paper's classical section (Sec. III, block Hamiltonian and long-chain TFIM
 equations), plus the XXZ chain, the random-field Heisenberg chain and the
 transverse-field Ising ladder, which the paper does not treat but which share
 its two-module coupling form (Sec. II, two-block Hamiltonian and general
-coupling equations).
+coupling equations), and the TFIM with next-nearest-neighbour ZZ bonds, whose
+cuts carry the longer-range terms of the coupling-geometry appendix (App. B).
 """
 from __future__ import annotations
 
@@ -21,7 +22,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-MODELS = ("tfim", "xxz", "rfheis", "tfim_ladder")
+MODELS = ("tfim", "xxz", "rfheis", "tfim_ladder", "tfim_nnn")
 
 
 @dataclass(frozen=True)
@@ -38,6 +39,7 @@ class ChainJob:
     delta      : XXZ anisotropy.
     j_rung     : rung coupling (tfim_ladder).
     fields     : per-site longitudinal random fields (rfheis), length n_sites.
+    j2         : next-nearest-neighbour ZZ coupling (tfim_nnn).
     """
 
     model: str
@@ -50,6 +52,7 @@ class ChainJob:
     delta: float = 1.0
     j_rung: float = 0.0
     fields: Tuple[float, ...] = field(default_factory=tuple)
+    j2: float = 0.0
 
     def __post_init__(self):
         if self.model not in MODELS:
@@ -90,6 +93,15 @@ def rfheis_batch(n_chains: int = 512, W: float = 2.0) -> List[ChainJob]:
         jobs.append(ChainJob("rfheis", n_sites=32, leaf_sites=8, k=int(ks[i]), q=8,
                              J=1.0, fields=tuple(float(x) for x in hs)))
     return jobs
+
+
+def tfim_nnn(n_sites: int = 24, leaf_sites: int = 4, k: int = 16, q: int = 4,
+             J: float = 1.0, h: float = 0.7, gamma: float = 0.2) -> ChainJob:
+    """TFIM with next-nearest ZZ bonds of strength gamma*J on every pair (s, s+2):
+    each cut carries one nearest and two next-nearest terms, two of them on the
+    sites next to the module edges (the longer-range coupling of App. B)."""
+    return ChainJob("tfim_nnn", n_sites=n_sites, leaf_sites=leaf_sites, k=k, q=q, J=J, h=h,
+                    j2=gamma * J)
 
 
 def tfim_ladder96() -> ChainJob:

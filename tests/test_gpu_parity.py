@@ -121,6 +121,25 @@ def test_module_ed_and_projection(ctx, job, k):
     m.free()
 
 
+@pytest.mark.parametrize("chain,leaf", [(60, 0), (195, 3), (227, 1)])
+def test_leaf_ed_guard_rows_stay_out_of_the_final_rayleigh_ritz(ctx, chain, leaf):
+    """Random-field leaves whose guard Ritz values sit just outside the wanted
+    cluster window: the final Rayleigh-Ritz over the whole block used to mix them
+    into converged wanted vectors (residual ~1e-7) and fail the leaf solve."""
+    say("leaf guard rows", chain, leaf)
+    job = W.rfheis_batch(chain + 1)[chain]
+    L0 = job.leaf_sites
+    a = leaf * L0
+    m = ctx.module_ed(L0, SM.block_terms(job, a, a + L0), job.k)
+    inf = m.info()
+    E_or, V_or, k_eff, gap, w = OR.leaf_ed(OH.block_hamiltonian(job, a, a + L0), job.k)
+    assert inf["k_eff"] == k_eff
+    assert rel_err(inf["E"], E_or) <= 1e-12
+    B = m.basis()
+    assert np.max(np.abs(B @ B.T - np.eye(k_eff))) <= 1e-12
+    m.free()
+
+
 def _synthetic_module(ctx, rng, k, n_sites, spread=3.0):
     E = np.sort(rng.uniform(-spread, 0.0, k))
     ops = []
@@ -280,6 +299,10 @@ RECURSION_CASES = [
     ("ladder_2x8_k32", W.ChainJob("tfim_ladder", 16, 8, 32, 8, J=1.0, h=0.9, j_rung=0.5)),
     ("ladder_2x6_odd", W.ChainJob("tfim_ladder", 12, 4, 16, 4, J=1.0, h=0.9, j_rung=0.5)),
     ("single_leaf", W.ChainJob("xxz", 8, 8, 16, 4, J=1.0, delta=0.5)),
+    # next-nearest bonds: three cut terms, two on the sites next to the module edges
+    ("tfim_nnn_N16_L4_k16", W.tfim_nnn(n_sites=16, leaf_sites=4, k=16, q=4)),
+    ("tfim_nnn_N24_L4_k12_odd", W.tfim_nnn(n_sites=24, leaf_sites=4, k=12, q=6)),
+    ("tfim_nnn_N10_L2_k128", W.tfim_nnn(n_sites=10, leaf_sites=2, k=128, q=6)),
 ]
 
 
@@ -295,6 +318,35 @@ def test_recurse_matches_oracle(ctx, name, job):
         kg = [r["k_eff"] for r in rep["records"] if r["kind"] != 2]
         ko = [r.k_eff for r in ref.records]
         assert sorted(set(kg)) == sorted(set(ko))
+
+
+# App. B coupling geometries: two 5-site TFIM modules (J=1, h=0.7) coupled by
+# -J' Z_i Z_j at (i in A, j in B) = (5,1), (5,2), (5,3), (3,3) (1-based), and the
+# next-nearest form -J'(Z5 Z1 + g Z4 Z1 + g Z5 Z2), g = 0.2; interior-site operators
+GEOMETRIES = {"I": [(1.0, 5, 1)], "II": [(1.0, 5, 2)], "III": [(1.0, 5, 3)], "IV": [(1.0, 3, 3)],
+              "NNN": [(1.0, 5, 1), (0.2, 4, 1), (0.2, 5, 2)]}
+
+
+@pytest.mark.parametrize("geom", sorted(GEOMETRIES))
+@pytest.mark.parametrize("k,Jp", [(32, 0.8), (10, 0.8), (6, 1.5)])
+def test_couple_solve_coupling_geometries(ctx, geom, k, Jp):
+    say("geometry", geom, k, Jp)
+    L = 5
+    blk = W.ChainJob("tfim", L, L, k, 8, J=1.0, h=0.7)
+    A = ctx.module_ed(L, SM.block_terms(blk, 0, L), k)
+    B = ctx.module_ed(L, SM.block_terms(blk, 0, L), k)
+    pairs = GEOMETRIES[geom]
+    ida = A.project_ops([i - 1 for _, i, _ in pairs], ["Z"] * len(pairs))
+    idb = B.project_ops([j - 1 for _, _, j in pairs], ["Z"] * len(pairs))
+    coefs = [-Jp * c for c, _, _ in pairs]
+    _, e, _ = ctx.couple_solve(A, B, coefs, ida, idb, 8, 8, want_module=False)
+    E, V, k_eff, _, _ = OR.leaf_ed(OH.block_hamiltonian(blk, 0, L), k)
+    terms = [(cf, OR.project(V, OH.site_operator(L, i - 1, "Z")),
+              OR.project(V, OH.site_operator(L, j - 1, "Z"))) for cf, (_, i, j) in zip(coefs, pairs)]
+    w, _, _, _, _ = OR.couple_solve(E, E, terms, None)
+    assert rel_err(e, w[:8]) <= 1e-10
+    A.free()
+    B.free()
 
 
 def test_recurse_full_k_is_exact_and_bounds(ctx):

@@ -71,6 +71,7 @@ def test_default_opts_without_gpu():
     W.ChainJob("xxz", 8, 8, 8, 4, J=1.0, delta=0.7),
     W.ChainJob("rfheis", 8, 8, 8, 4, J=1.0, fields=tuple(np.linspace(-2, 2, 8))),
     W.ChainJob("tfim_ladder", 8, 8, 8, 4, J=1.0, h=0.9, j_rung=0.5),
+    W.tfim_nnn(n_sites=8, leaf_sites=8, k=8),
 ])
 def test_product_terms_match_oracle_hamiltonian_bitwise(job):
     H_prod = _dense(job.n_sites, SM.chain_terms(job))

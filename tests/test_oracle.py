@@ -250,3 +250,62 @@ def test_gap_cut_rules():
     assert R.gap_cut(w, 10)[0] == 7
     w2 = np.array([1.0, 1.0, 1.0, 2.0])
     assert R.gap_cut(w2, 2)[0] == 2          # whole range one cluster: unchanged, flagged
+
+
+# -- longer-range and interior couplings (the coupling-geometry appendix) -----------
+
+def test_nnn_chain_full_k_exact_with_odd_carry():
+    # 5 two-site leaves: every cut carries one nearest and two next-nearest ZZ terms,
+    # two of them on the site next to the module edge
+    job = W.tfim_nnn(n_sites=10, leaf_sites=2, k=256, q=6)
+    res = R.recurse(job)
+    np.testing.assert_allclose(res.energies, X.brute_energies(job, 6), atol=1e-11)
+
+
+def test_nnn_chain_zero_j2_is_tfim():
+    nnn = W.ChainJob("tfim_nnn", 16, 4, 8, 4, J=1.0, h=0.7, j2=0.0)
+    tf = W.ChainJob("tfim", 16, 4, 8, 4, J=1.0, h=0.7)
+    np.testing.assert_allclose(R.recurse(nnn).energies, R.recurse(tf).energies, atol=1e-12)
+    assert np.all(R.recurse(nnn).energies >= X.tfim_free_fermion(16, 1.0, 0.7, 4) - 1e-11)
+
+
+def test_nnn_chain_variational_bound():
+    ex = X.brute_energies(W.tfim_nnn(n_sites=12, leaf_sites=3, q=4), 4)
+    for k, bound in ((6, 0.1), (24, 1e-3)):
+        res = R.recurse(W.tfim_nnn(n_sites=12, leaf_sites=3, k=k, q=4))
+        assert np.all(res.energies >= ex - 1e-12)
+        assert np.all(res.energies - ex < bound)
+
+
+def _two_module_dense(L, J, h, pairs):
+    """Dense H of two L-site TFIM modules A (sites 0..L-1) and B (L..2L-1) coupled by
+    sum c Z_i Z_j over pairs (c, i_in_A, j_in_B) (1-based sites within each module)."""
+    n = 2 * L
+    Hm = np.zeros((2 ** n, 2 ** n))
+    for s in range(n - 1):
+        if s != L - 1:
+            Hm += -J * H.term_matrix(n, {s: "Z", s + 1: "Z"})
+    for s in range(n):
+        Hm += -h * H.term_matrix(n, {s: "X"})
+    for c, i, j in pairs:
+        Hm += c * H.term_matrix(n, {i - 1: "Z", L + j - 1: "Z"})
+    return Hm
+
+
+GEOMETRIES = {  # App. B: (i in A, j in B), 1-based, and the next-nearest coupling
+    "I": [(1.0, 5, 1)], "II": [(1.0, 5, 2)], "III": [(1.0, 5, 3)], "IV": [(1.0, 3, 3)],
+    "NNN": [(1.0, 5, 1), (0.2, 4, 1), (0.2, 5, 2)],
+}
+
+
+@pytest.mark.parametrize("geom", sorted(GEOMETRIES))
+def test_single_merge_coupling_geometries_full_k_exact(geom):
+    L, J, h, Jp = 5, 1.0, 0.7, 0.8
+    blk = W.ChainJob("tfim", L, L, 32, 8, J=J, h=h)
+    Hb = H.block_hamiltonian(blk, 0, L)
+    E, V, k_eff, _, _ = R.leaf_ed(Hb, 32)
+    terms = [(-Jp * c, R.project(V, H.site_operator(L, i - 1, "Z")),
+              R.project(V, H.site_operator(L, j - 1, "Z"))) for c, i, j in GEOMETRIES[geom]]
+    w, _, _, _, _ = R.couple_solve(E, E, terms, None)
+    ex = np.linalg.eigvalsh(_two_module_dense(L, J, h, [(-Jp * c, i, j) for c, i, j in GEOMETRIES[geom]]))
+    np.testing.assert_allclose(w[:8], ex[:8], atol=1e-11)
