@@ -595,3 +595,40 @@ def test_rfheis_batch_32_chains_bf16(ctx):
     assert rel_err(e16, e64) <= 1e-8
     for i in (0, 5):
         assert rel_err(e64[i], OR.recurse(jobs[i]).energies) <= 1e-10
+
+
+# -- error density vs the free-fermion reference (Sec. IV study) -------------------
+
+def test_error_density_study_tfim_vs_free_fermions(ctx):
+    """Open TFIM, J=1, h=0.7, 5-site leaves, L = 10, 20, 40, 80, k = 2..32: the
+    ground-state error dE0 = E0(k) - E0(free fermions) is non-negative, the error
+    density dE0/L falls with k at every L and its growth with L slows down (towards
+    the size-independent bound R(k)/L0 of Sec. IV), and at L = 80 it falls roughly
+    like a power of k over k = 4..32 (the paper fits an exponent near 0.87 on its
+    runs; these runs give about 0.96). L = 10, 20 also match the oracle recursion."""
+    from paper_2609_02394_amd import rmc
+
+    Ls, ks = (10, 20, 40, 80), (2, 4, 8, 16, 32)
+    dens = {}
+    for L in Ls:
+        ref = OX.tfim_free_fermion(L, 1.0, 0.7, 1)[0]
+        for k in ks:
+            job = W.ChainJob("tfim", L, 5, k, 1, J=1.0, h=0.7)
+            e, _ = ctx.recurse(*rmc.job_chain(job))
+            d = (e[0] - ref) / L
+            assert d >= -1e-12, (L, k, d)
+            dens[L, k] = d
+            if L <= 20:
+                assert rel_err(e, OR.recurse(job).energies) <= 1e-10
+    say("error density dE0/L (rows L, columns k=2..32):")
+    for L in Ls:
+        say(L, " ".join(f"{dens[L, k]:.3e}" for k in ks))
+    for L in Ls:
+        assert all(dens[L, a] >= dens[L, b] - 1e-12 for a, b in zip(ks, ks[1:]))
+    for k in ks:  # growth with L slows down (towards the size-independent bound)
+        assert dens[80, k] - dens[40, k] <= 1.1 * (dens[40, k] - dens[20, k]) + 1e-12, k
+    x = np.log(np.array(ks[1:], float))
+    y = np.log(np.array([max(dens[80, k], 1e-16) for k in ks[1:]]))
+    p = -np.polyfit(x, y, 1)[0]
+    say("fitted exponent p in dE0/L ~ k^-p at L=80:", p)
+    assert 0.5 < p < 1.5
