@@ -216,6 +216,14 @@ rmc_status rmc_module_info(const rmc_module* m, int* k_eff, int* dim, int* n_sit
                            double* energies_host /* k_eff, may be NULL */);
 /* Copy the basis (k_eff x dim, row-major: row = retained state) to the host. */
 rmc_status rmc_module_basis(rmc_ctx* ctx, const rmc_module* m, double* basis_host);
+/* The retained states of a module as full-space vectors (Sec. II, states of the
+ * combined system from the stored coefficients, read recursively down to the
+ * leaves): out_dev (device, caller-owned, k_eff x 2^n_sites doubles, row-major)
+ * row mu = the state mu in the site basis (site 0 = most significant bit). Needs
+ * the bases of the module and of every module below it, all still owned by ctx:
+ * modules from rmc_module_ed / rmc_couple_solve keep them; rmc_recurse releases
+ * them. n_sites <= 24. RMC_ERR_STATE if a basis is missing. */
+rmc_status rmc_module_lift(rmc_ctx* ctx, const rmc_module* m, double* out_dev);
 /* Copy a projected operator (k_eff x k_eff) to the host. */
 rmc_status rmc_module_op(rmc_ctx* ctx, const rmc_module* m, int op_id, double* op_host);
 rmc_status rmc_module_free(rmc_ctx* ctx, rmc_module* m);

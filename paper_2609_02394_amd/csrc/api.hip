@@ -926,6 +926,54 @@ rmc_status rmc_module_basis(rmc_ctx* ctx, const rmc_module* m, double* basis_hos
   });
 }
 
+namespace {
+// Full-space vectors of a module's retained states (k_eff x 2^n_sites, row-major):
+// a leaf's basis is already in the site basis; a merged module's state mu is
+// sum_{a,b} C_mu[a][b] psi_A[a] (x) psi_B[b], i.e. psi_A^T C_mu psi_B as a
+// 2^{n_A} x 2^{n_B} matrix (A holds the high bits). Two GEMMs per level: one for
+// all mu (C psi_B), one strided batch over mu (psi_A^T T_mu).
+void lift_module(rmc_ctx* ctx, const rmc_module* m, double* out) {
+  RMC_CHECK(std::find(ctx->modules.begin(), ctx->modules.end(), m) != ctx->modules.end(),
+            RMC_ERR_STATE, "module (or a module below it) is not owned by this context");
+  RMC_CHECK(m->basis != nullptr, RMC_ERR_STATE, "module basis freed");
+  hipStream_t s = ctx->stream;
+  const long D = 1L << m->n_sites;
+  if (m->kind == 0) {
+    RMC_CHECK(m->dim == D, RMC_ERR_STATE, "module basis not in the site basis");
+    copy_rows(s, m->k_eff, m->dim, m->basis, m->dim, out, m->dim);
+    return;
+  }
+  RMC_CHECK(m->A && m->B, RMC_ERR_STATE, "merged module without children");
+  const rmc_module* A = m->A;
+  const rmc_module* B = m->B;
+  RMC_CHECK(A->k_eff == m->kA && B->k_eff == m->kB, RMC_ERR_STATE, "children changed");
+  const int DA = 1 << A->n_sites, DB = 1 << B->n_sites;
+  const int k = m->k_eff, kA = m->kA, kB = m->kB;
+  Scratch sc(&ctx->arena);
+  double* pa = sc.get<double>((size_t)kA * DA);
+  double* pb = sc.get<double>((size_t)kB * DB);
+  lift_module(ctx, A, pa);
+  lift_module(ctx, B, pb);
+  double* T = sc.get<double>((size_t)k * kA * DB);
+  // T (k kA x DB) = C (k kA x kB) psi_B (kB x DB)
+  gemm_f64(s, false, false, k * kA, DB, kB, 1.0, m->basis, kB, 0, pb, DB, 0, 0.0, T, DB, 0, 1, 1,
+           nullptr);
+  // out_mu (DA x DB) = psi_A^T (DA x kA) T_mu (kA x DB)
+  gemm_f64(s, true, false, DA, DB, kA, 1.0, pa, DA, 0, T, DB, (long)kA * DB, 0.0, out, DB,
+           (long)DA * DB, k, 1, nullptr);
+  // scratch released here is reused only by work enqueued later on the same stream
+}
+}  // namespace
+
+rmc_status rmc_module_lift(rmc_ctx* ctx, const rmc_module* m, double* out_dev) {
+  if (!ctx || !m || !out_dev) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    RMC_CHECK(m->n_sites >= 1 && m->n_sites <= 24, RMC_ERR_ARG, "lifting needs 1 <= n_sites <= 24");
+    lift_module(ctx, m, out_dev);
+    sync(ctx);
+  });
+}
+
 rmc_status rmc_module_op(rmc_ctx* ctx, const rmc_module* m, int op_id, double* op_host) {
   if (!ctx || !m || !op_host) return RMC_ERR_ARG;
   return guard(ctx, [&] {

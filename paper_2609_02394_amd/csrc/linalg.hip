@@ -751,6 +751,7 @@ __device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, lo
     __syncthreads();
     for (int step = 0; step < M - 1; ++step) {
       const int b = step & 1;
+      int any_rot = 0;
       // (R) rotations of this round; V update with the previous round's
       for (int k = tid; k < H; k += nt) {
         int p = rr_player(k, step, M), q = rr_player(M - 1 - k, step, M);
@@ -772,9 +773,11 @@ __device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, lo
         }
         pp[b * H + k] = p; qq[b * H + k] = q; cs[b * H + k] = c; sn[b * H + k] = s;
         tn[b * H + k] = t; act[b * H + k] = a;
+        any_rot |= a;
       }
       if (step > 0) apply_v(b ^ 1);
-      __syncthreads();
+      // barrier and vote: a round with no rotation leaves A as it is
+      if (!__syncthreads_or(any_rot)) continue;
       // (U) 2x2 blocks of A, one flat work item per block (k, l), k <= l
       const int* p_ = pp + b * H;
       const int* q_ = qq + b * H;

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_NOCONV", 4: "ERR_HI
 EXPORTED = (
     "rmc_default_opts", "rmc_create", "rmc_destroy", "rmc_last_error", "rmc_arena_usage",
     "rmc_module_ed", "rmc_project_ops", "rmc_couple_solve", "rmc_recurse", "rmc_recurse_batch",
-    "rmc_module_info", "rmc_module_basis", "rmc_module_op", "rmc_module_free",
+    "rmc_module_info", "rmc_module_basis", "rmc_module_op", "rmc_module_free", "rmc_module_lift",
     "rmc_leaf_hamiltonian", "rmc_kron_apply", "rmc_sym_eig", "rmc_module_import",
     "rmc_profile", "rmc_profile_read", "rmc_profile_read_precision",
     "rmc_serve_start", "rmc_submit", "rmc_poll", "rmc_serve_stop",
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "rmc_recurse_batch": (i, [vp, i, P(ChainDesc), P(SolveOpts), P(d), i, P(i)]),
         "rmc_module_info": (i, [vp, P(i), P(i), P(i), P(d)]),
         "rmc_module_basis": (i, [vp, vp, P(d)]),
+        "rmc_module_lift": (i, [vp, vp, vp]),
         "rmc_module_op": (i, [vp, vp, i, P(d)]),
         "rmc_module_free": (i, [vp, vp]),
         "rmc_leaf_hamiltonian": (i, [vp, P(LeafDesc), vp]),
@@ -165,6 +166,16 @@ class Module:
         out = np.zeros((inf["k_eff"], inf["dim"]))
         self.ctx._check(lib().rmc_module_basis(self.ctx.h, self.h,
                                                out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def lift(self):
+        """Retained states as full-space vectors: device tensor (k_eff, 2**n_sites)."""
+        import torch
+
+        inf = self.info()
+        out = torch.empty((inf["k_eff"], 1 << inf["n_sites"]), dtype=torch.float64,
+                          device=f"cuda:{self.ctx.device}")
+        self.ctx._check(lib().rmc_module_lift(self.ctx.h, self.h, C.c_void_p(out.data_ptr())))
         return out
 
     def op(self, op_id: int) -> np.ndarray:
