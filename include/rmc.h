@@ -224,6 +224,27 @@ rmc_status rmc_module_basis(rmc_ctx* ctx, const rmc_module* m, double* basis_hos
  * modules from rmc_module_ed / rmc_couple_solve keep them; rmc_recurse releases
  * them. n_sites <= 24. RMC_ERR_STATE if a basis is missing. */
 rmc_status rmc_module_lift(rmc_ctx* ctx, const rmc_module* m, double* out_dev);
+
+/* Single-merge truncation diagnostics (Sec. IV, single-merge bound; App. on the error
+ * bounds: block form of H, discarded-sector gap, r(b, gamma)). A and B are leaf
+ * modules from rmc_module_ed built from leaf_A and leaf_B (bases kept); bond is the
+ * coupling as for rmc_couple_solve. With H the Hamiltonian of the nA + nB sites
+ * (A's sites first; nA + nB <= 24), P the projector on the retained product states
+ * psi_A[a] (x) psi_B[b] and Q = I - P, writes out_host[7] =
+ *   a = lambda_min(P H P) on range(P) (the merged module's lowest energy),
+ *   b = ||P H Q||_2, c = lambda_min(Q H Q) on range(Q), gamma = c - a,
+ *   r = (sqrt(gamma^2 + 4 b^2) - gamma) / 2, b^2 / gamma, E0 = lambda_min(H).
+ * b comes from the retained states alone (b^2 = largest eigenvalue of
+ * P V^2 P - (P V P)^2, V the coupling); c and E0 from the block eigensolver on the
+ * full 2^(nA+nB) space with H applied matrix-free (and Q H Q + sigma P, sigma the sum
+ * of |coef|, for c). If the leaves keep every state, range(Q) is empty: b = r = 0 and
+ * c = gamma = +inf. gamma <= 0 (the bound's assumption fails) gives b^2/gamma = +inf.
+ * Always FP64 (opts->precision is ignored). Needs about 10 (nev + guard) x 2^(nA+nB)
+ * doubles of arena. RMC_ERR_NOCONV if a solve does not converge. */
+rmc_status rmc_merge_bound(rmc_ctx* ctx, rmc_module* A, const rmc_leaf_desc* leaf_A,
+                           rmc_module* B, const rmc_leaf_desc* leaf_B,
+                           const rmc_bond_desc* bond, const rmc_solve_opts* opts,
+                           double* out_host);
 /* Copy a projected operator (k_eff x k_eff) to the host. */
 rmc_status rmc_module_op(rmc_ctx* ctx, const rmc_module* m, int op_id, double* op_host);
 rmc_status rmc_module_free(rmc_ctx* ctx, rmc_module* m);

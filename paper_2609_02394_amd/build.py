@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librmc.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["linalg.hip", "leaf.hip", "kron.hip", "solver.hip", "api.hip", "recurse.hip"]
+SOURCES = ["linalg.hip", "leaf.hip", "kron.hip", "solver.hip", "api.hip", "recurse.hip", "fullspace.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

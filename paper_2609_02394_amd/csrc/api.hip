@@ -35,6 +35,7 @@ void Arena::init(char* base, size_t size) {
 }
 
 void* Arena::alloc(size_t bytes) {
+  std::lock_guard<std::mutex> lk(mu_);
   size_t need = (bytes + kAlign - 1) & ~(kAlign - 1);
   if (need == 0) need = kAlign;
   for (auto it = free_.begin(); it != free_.end(); ++it) {
@@ -54,6 +55,7 @@ void* Arena::alloc(size_t bytes) {
 
 void Arena::release(void* p) {
   if (!p) return;
+  std::lock_guard<std::mutex> lk(mu_);
   size_t off = (size_t)((char*)p - base_);
   auto it = used_.find(off);
   if (it == used_.end()) return;
@@ -77,6 +79,7 @@ void Arena::release(void* p) {
 }
 
 size_t Arena::largest_free() const {
+  std::lock_guard<std::mutex> lk(mu_);
   size_t m = 0;
   for (auto& kv : free_) m = std::max(m, kv.second);
   return m;
@@ -845,7 +848,14 @@ rmc_status rmc_destroy(rmc_ctx* ctx) {
     hipEventDestroy(r.b);
   }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
-  if (ctx->pinned) hipHostFree(ctx->pinned);
+  for (char* h : ctx->pinned)
+    if (h) hipHostFree(h);
+  if (ctx->lane_stream) {
+    hipStreamSynchronize(ctx->lane_stream);
+    hipStreamDestroy(ctx->lane_stream);
+  }
+  for (hipEvent_t e : ctx->lane_ev)
+    if (e) hipEventDestroy(e);
   if (ctx->own_arena && ctx->arena_mem) hipFree(ctx->arena_mem);
   delete ctx;
   return RMC_OK;
@@ -1090,6 +1100,220 @@ rmc_status rmc_kron_apply(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_
     build_packs(s, sc, op);
     op_apply(ctx, op, n_vec, X_dev, Y_dev, nullptr, 1.0, 0.0, 0.0, nullptr, nullptr, precision);
     sync(ctx);
+  });
+}
+
+namespace {
+// A product of one-site operators on an L-site block as a FullTerm (bit L-1-s = site s).
+FullTerm full_term(double coef, int L, int n, const int* site, const int* op) {
+  FullTerm t{};
+  t.coef = coef;
+  for (int u = 0; u < n; ++u) {
+    const unsigned b = 1u << (L - 1 - site[u]);
+    if (op[u] == RMC_OP_X) t.flip |= b;
+    if (op[u] == RMC_OP_T) t.flip |= b, t.tm |= b;
+    if (op[u] == RMC_OP_Z) t.zm |= b;
+  }
+  return t;
+}
+
+// o = Psi (O_1 O_2 Psi^T) for a leaf basis Psi (k x 2^n rows), O_2 applied first
+// (op2 = 0: a single operator).
+void leaf_op_product(hipStream_t s, Scratch& sc, const rmc_module* m, int site1, int op1, int site2,
+                     int op2, double* o) {
+  const int k = m->k_eff, D = m->dim, n = m->n_sites;
+  double* W1 = sc.get<double>((size_t)k * D);
+  if (op2) {
+    double* W2 = sc.get<double>((size_t)k * D);
+    site_op_apply(s, k, n, n - 1 - site2, op2, m->basis, W2);
+    site_op_apply(s, k, n, n - 1 - site1, op1, W2, W1);
+  } else {
+    site_op_apply(s, k, n, n - 1 - site1, op1, m->basis, W1);
+  }
+  double* kw = sc.get<double>((size_t)64 * k * k + 64);
+  gemm_f64(s, false, true, k, k, D, 1.0, m->basis, D, 0, W1, D, 0, 0.0, o, k, 0, 1,
+           gemm_pick_ksplit(k, k, D, 1), kw);
+}
+
+// Single-merge diagnostics of two leaf modules (the quantities of the single-merge
+// bound, App. on the error bounds); out = {a, b, c, gamma, r, b^2/gamma, E0}.
+void merge_bound(rmc_ctx* ctx, rmc_module* A, const rmc_leaf_desc* la, rmc_module* B,
+                 const rmc_leaf_desc* lb, const rmc_bond_desc* bond, rmc_solve_opts o, double* out) {
+  validate_leaf(la);
+  validate_leaf(lb);
+  RMC_CHECK(A && B && bond && out, RMC_ERR_ARG, "null argument");
+  for (const rmc_module* m : {A, B}) {
+    RMC_CHECK(std::find(ctx->modules.begin(), ctx->modules.end(), m) != ctx->modules.end(),
+              RMC_ERR_ARG, "module not owned by this context");
+    RMC_CHECK(m->kind == 0 && m->dim == (1 << m->n_sites), RMC_ERR_ARG,
+              "the diagnostics need two leaf modules");
+    RMC_CHECK(m->basis != nullptr, RMC_ERR_STATE, "module basis freed");
+  }
+  RMC_CHECK(la->n_sites == A->n_sites && lb->n_sites == B->n_sites, RMC_ERR_ARG,
+            "leaf descriptors do not match the modules");
+  const int nA = A->n_sites, nB = B->n_sites, L = nA + nB;
+  RMC_CHECK(L <= 24, RMC_ERR_ARG, "the full space is limited to 24 sites");
+  RMC_CHECK(bond->n_terms >= 0 && (bond->n_terms == 0 || (bond->coef && bond->opA && bond->opB)),
+            RMC_ERR_ARG, "bad coupling descriptor");
+  const int T = bond->n_terms;
+  std::vector<int> sa(T), oa(T), sb(T), ob(T);
+  for (int i = 0; i < T; ++i) {
+    RMC_CHECK(bond->opA[i] >= 0 && bond->opA[i] < (int)A->ops.size() && bond->opB[i] >= 0 &&
+                  bond->opB[i] < (int)B->ops.size(),
+              RMC_ERR_ARG, "bad operator id");
+    sa[i] = A->ops[bond->opA[i]].site;
+    oa[i] = A->ops[bond->opA[i]].op;
+    sb[i] = B->ops[bond->opB[i]].site;
+    ob[i] = B->ops[bond->opB[i]].op;
+  }
+  o.precision = RMC_FP64;
+  hipStream_t s = ctx->stream;
+  // a: lowest eigenvalue of the effective Hamiltonian, i.e. of P H P on range(P)
+  std::vector<double> ev;
+  couple(ctx, A, B, bond, std::max(1, A->k_eff * B->k_eff), 1, o, false, ev, nullptr);
+  const double a = ev[0];
+  const int kA = A->k_eff, kB = B->k_eff, DA = A->dim, DB = B->dim;
+  const bool q_empty = (kA == DA && kB == DB);
+  Scratch sc(&ctx->arena);
+  // b^2 = lambda_max(P V Q V P) = lambda_max(P V^2 P - (P V P)^2) on the retained
+  // product states (P (H_A + H_B) Q = 0): both terms from projected products of the
+  // boundary operators, so -M = (P V P)^2 - P V^2 P is solved for its lowest eigenvalue
+  double b = 0.0;
+  if (!q_empty && T > 0) {
+    const int nr = kA * kB;
+    double* Ap = sc.get<double>((size_t)T * T * kA * kA);
+    double* Bp = sc.get<double>((size_t)T * T * kB * kB);
+    double* As = sc.get<double>((size_t)T * kA * kA);
+    double* Bs = sc.get<double>((size_t)T * kB * kB);
+    std::vector<double> wp(T * T), ws(T);
+    for (int i = 0; i < T; ++i) {
+      ws[i] = bond->coef[i];
+      leaf_op_product(s, sc, A, sa[i], oa[i], 0, 0, As + (size_t)i * kA * kA);
+      leaf_op_product(s, sc, B, sb[i], ob[i], 0, 0, Bs + (size_t)i * kB * kB);
+      for (int j = 0; j < T; ++j) {
+        wp[i * T + j] = -bond->coef[i] * bond->coef[j];
+        leaf_op_product(s, sc, A, sa[i], oa[i], sa[j], oa[j], Ap + (size_t)(i * T + j) * kA * kA);
+        leaf_op_product(s, sc, B, sb[i], ob[i], sb[j], ob[j], Bp + (size_t)(i * T + j) * kB * kB);
+      }
+    }
+    double* wdev = sc.get<double>(T * T + T);
+    RMC_HIP(hipMemcpyAsync(wdev, wp.data(), T * T * sizeof(double), hipMemcpyHostToDevice, s));
+    RMC_HIP(hipMemcpyAsync(wdev + T * T, ws.data(), T * sizeof(double), hipMemcpyHostToDevice, s));
+    double* negM = sc.get<double>((size_t)nr * nr);
+    double* Vh = sc.get<double>((size_t)nr * nr);
+    kron_dense(s, T * T, kA, kB, wdev, Ap, Bp, negM);
+    kron_dense(s, T, kA, kB, wdev + T * T, As, Bs, Vh);
+    gemm_f64(s, false, false, nr, nr, nr, 1.0, Vh, nr, 0, Vh, nr, 0, 1.0, negM, nr, 0, 1, 1, nullptr);
+    double lam;
+    if (nr == 1) {
+      RMC_HIP(hipMemcpyAsync(&lam, negM, sizeof(double), hipMemcpyDeviceToHost, s));
+      sync(ctx);
+    } else {
+      CoupledOp op;
+      op.kind = 0;
+      op.n = nr;
+      op.H = negM;
+      op.D = sc.get<double>(nr);
+      double* rb = sc.get<double>(nr);
+      double* bm = sc.get<double>(1);
+      dense_diag(s, nr, negM, op.D, rb);
+      vec_max(s, nr, rb, bm);
+      RMC_HIP(hipMemcpyAsync(&op.bup, bm, sizeof(double), hipMemcpyDeviceToHost, s));
+      sync(ctx);
+      double* X = sc.get<double>(nr);
+      std::vector<double> e1;
+      SolveStats st;
+      RMC_CHECK(eig_lowest(ctx, op, 1, o, X, e1, st) == RMC_OK, RMC_ERR_NOCONV,
+                "eigensolver did not converge on P V Q V P");
+      lam = e1[0];
+    }
+    b = std::sqrt(std::max(0.0, -lam));
+  }
+  // E0 = lambda_min(H) and c = lambda_min(Q H Q + sigma P) (range(P) moved to sigma >=
+  // ||H||) in the full space, as one batched solve of two matrix-free operators
+  std::vector<FullTerm> ft;
+  std::vector<int> st2(2), op2(2);
+  for (int t = 0; t < la->n_terms; ++t) {
+    const rmc_term& tm = la->terms[t];
+    for (int u = 0; u < tm.nsite; ++u) st2[u] = tm.site[u], op2[u] = tm.op[u];
+    ft.push_back(full_term(tm.coef, L, tm.nsite, st2.data(), op2.data()));
+  }
+  for (int t = 0; t < lb->n_terms; ++t) {
+    const rmc_term& tm = lb->terms[t];
+    for (int u = 0; u < tm.nsite; ++u) st2[u] = nA + tm.site[u], op2[u] = tm.op[u];
+    ft.push_back(full_term(tm.coef, L, tm.nsite, st2.data(), op2.data()));
+  }
+  for (int i = 0; i < T; ++i) {
+    st2[0] = sa[i], op2[0] = oa[i], st2[1] = nA + sb[i], op2[1] = ob[i];
+    ft.push_back(full_term(bond->coef[i], L, 2, st2.data(), op2.data()));
+  }
+  double sigma = 0.0;
+  for (auto& t : ft) sigma += std::fabs(t.coef);
+  sigma = std::max(sigma, 1e-300);
+  FullTerm* fdev = sc.get<FullTerm>(std::max<size_t>(ft.size(), 1));
+  if (!ft.empty())
+    RMC_HIP(hipMemcpyAsync(fdev, ft.data(), ft.size() * sizeof(FullTerm), hipMemcpyHostToDevice, s));
+  const size_t n = (size_t)1 << L;
+  std::vector<CoupledOp> ops(q_empty ? 1 : 2);
+  for (size_t i = 0; i < ops.size(); ++i) {
+    CoupledOp& op = ops[i];
+    op.kind = 2;
+    op.n = (int)n;
+    op.fterms = fdev;
+    op.n_fterms = (int)ft.size();
+    op.nA = nA;
+    op.nB = nB;
+    op.bup = sigma;
+    op.D = sc.get<double>(n);
+    if (i == 1) {
+      op.PsiA = A->basis;
+      op.PsiB = B->basis;
+      op.kA = kA;
+      op.kB = kB;
+      op.sigma = sigma;
+      double* pA = sc.get<double>(DA);
+      double* pB = sc.get<double>(DB);
+      col_sumsq(s, kA, DA, A->basis, pA);
+      col_sumsq(s, kB, DB, B->basis, pB);
+      full_diag(s, L, nB, op.n_fterms, fdev, pA, pB, sigma, op.D);
+    } else {
+      full_diag(s, L, nB, op.n_fterms, fdev, nullptr, nullptr, 0.0, op.D);
+    }
+  }
+  std::vector<const CoupledOp*> opp;
+  std::vector<double*> Xs;
+  for (auto& op : ops) {
+    opp.push_back(&op);
+    Xs.push_back(sc.get<double>(n));
+  }
+  std::vector<std::vector<double>> evs;
+  std::vector<SolveStats> sts;
+  eig_lowest_batch(ctx, opp, std::vector<int>(ops.size(), 1), o, Xs, evs, sts);
+  for (auto& x : sts)
+    RMC_CHECK(x.status == RMC_OK, RMC_ERR_NOCONV, "full-space eigensolver did not converge");
+  const double E0 = evs[0][0];
+  const double c = q_empty ? INFINITY : evs[1][0];
+  const double g = c - a;
+  out[0] = a;
+  out[1] = b;
+  out[2] = c;
+  out[3] = g;
+  out[4] = b == 0.0 ? 0.0 : 0.5 * (std::sqrt(g * g + 4.0 * b * b) - g);
+  out[5] = b == 0.0 ? 0.0 : (g > 0.0 ? b * b / g : INFINITY);
+  out[6] = E0;
+  sync(ctx);
+}
+}  // namespace
+
+rmc_status rmc_merge_bound(rmc_ctx* ctx, rmc_module* A, const rmc_leaf_desc* leaf_A, rmc_module* B,
+                           const rmc_leaf_desc* leaf_B, const rmc_bond_desc* bond,
+                           const rmc_solve_opts* opts, double* out_host) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    rmc_solve_opts o;
+    rmc_default_opts(&o);
+    if (opts) o = *opts;
+    merge_bound(ctx, A, leaf_A, B, leaf_B, bond, o, out_host);
   });
 }
 

@@ -146,4 +146,44 @@ void vec_batched(hipStream_t s, VecOp op, const VecDesc* d, int P, int nvmax, lo
 void start_batched(hipStream_t s, const StartDesc* d, int P, int nmax, int mmax);
 void transpose_blocks_batched(hipStream_t s, const TrDesc* d, int P, int kmax, int nmax);
 
+// ---- full-space operators (single-merge truncation diagnostics) -------------------
+// One Pauli string of an n-site block in the real alphabet {X, T, Z}: for basis row r,
+// (term y)[r] = coef * (-1)^{|r & zm| + |~r & tm|} * y[r ^ flip] (flip: X and T sites,
+// zm: Z sites, tm: T sites; bit n-1-s is site s).
+struct FullTerm {
+  double coef;
+  unsigned flip, zm, tm, pad;
+};
+// out = s1 H (Y - sub) + s2 Y0 + s3 Xprev for nv vectors of 2^n_sites (sub, Y0, Xprev
+// nullable), H = sum of the terms.
+struct PauliDesc {
+  int n_sites, n_terms, nv, pad;
+  const FullTerm* terms;
+  const double* Y;
+  const double* sub;
+  const double* Y0;
+  const double* Xprev;
+  double* out;
+  double s1, s2, s3;
+};
+void pauli_batched(hipStream_t s, const PauliDesc* d, int P, long elems_max);
+// out = sum_{i<5} w[i] U[i] over n elements (null U[i] skipped).
+struct LinDesc {
+  long n;
+  double* out;
+  const double* U[5];
+  double w[5];
+};
+void lincomb_batched(hipStream_t s, const LinDesc* d, int P, long nmax);
+// D[r] = sum of the diagonal terms at r, plus sigma * pA[r >> nB] * pB[r & (2^nB - 1)]
+// where pA, pB are given (null: no projector part).
+void full_diag(hipStream_t s, int n_sites, int nB, int n_terms, const FullTerm* terms,
+               const double* pA, const double* pB, double sigma, double* D);
+// p[j] = sum_i Psi[i][j]^2 for a k x D row-major Psi.
+void col_sumsq(hipStream_t s, int k, int D, const double* Psi, double* p);
+// M[(a kB + b)(kA kB) + a' kB + b'] = sum_t w[t] A_t[a][a'] B_t[b][b'] (A_t: kA x kA,
+// B_t: kB x kB, consecutive; w on the device).
+void kron_dense(hipStream_t s, int T, int kA, int kB, const double* w, const double* Acat,
+                const double* Bcat, double* M);
+
 }  // namespace rmc

@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
 
 #include "../../include/rmc.h"
+#include "rmc_batch.h"
 #include "rmc_kernels.h"
 
 namespace rmc {
@@ -44,6 +46,7 @@ class Arena {
  private:
   char* base_ = nullptr;
   size_t size_ = 0, in_use_ = 0, peak_ = 0;
+  mutable std::mutex mu_;          // the solver's lanes allocate from their own threads
   std::map<size_t, size_t> free_;  // offset -> bytes
   std::map<size_t, size_t> used_;  // offset -> bytes
 };
@@ -102,12 +105,17 @@ struct rmc_ctx {
   };
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
+  std::mutex prof_mu;  // guards prof_recs and ev_pool against the solver's second lane
   // totals per precision of the Kronecker launches (index: rmc_precision)
   long long prof_launches[3] = {0, 0, 0};
   double prof_flops[3] = {0, 0, 0}, prof_bytes[3] = {0, 0, 0}, prof_ms[3] = {0, 0, 0};
-  // pinned host staging of the batched solver's descriptor tables
-  char* pinned = nullptr;
-  size_t pinned_cap = 0;
+  // pinned host staging of the batched solver's descriptor tables, one per lane
+  char* pinned[2] = {nullptr, nullptr};
+  size_t pinned_cap[2] = {0, 0};
+  // the batched solver's second lane: a library-owned stream (default priority) and
+  // the events that order it against `stream`
+  hipStream_t lane_stream = nullptr;
+  hipEvent_t lane_ev[2] = {nullptr, nullptr};
   // serving: scheduler state (owned by recurse.hip); other calls are refused while set
   void* serve = nullptr;
   bool serving = false;
@@ -118,7 +126,7 @@ namespace rmc {
 // The operator whose lowest eigenpairs are sought: a dense symmetric matrix (leaf
 // module) or the Kronecker-sum effective Hamiltonian of a merge.
 struct CoupledOp {
-  int kind = 0;  // 0 dense, 1 kron
+  int kind = 0;  // 0 dense, 1 kron, 2 full-space Pauli sum
   int n = 0;
   const double* H = nullptr;  // dense n x n
   int kA = 0, kB = 0, T = 0;
@@ -136,6 +144,14 @@ struct CoupledOp {
   // that kernel does not take the size), tile size pkm
   void* pack[3] = {nullptr, nullptr, nullptr};
   int pkm = 0;
+  // kind 2: H = sum of n_fterms Pauli strings on nA + nB sites (n = 2^(nA+nB)); with
+  // PsiA / PsiB set, the operator is Q H Q + sigma P instead, P the projector on the
+  // retained product states PsiA[a] (x) PsiB[b] (rows of kA x 2^nA and kB x 2^nB)
+  const FullTerm* fterms = nullptr;
+  int n_fterms = 0, nA = 0, nB = 0;
+  const double* PsiA = nullptr;
+  const double* PsiB = nullptr;
+  double sigma = 0.0;
 };
 
 struct SolveStats {

@@ -30,7 +30,9 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <functional>
+#include <thread>
 #include <vector>
 
 #include "rmc_batch.h"
@@ -69,25 +71,28 @@ void sync(rmc_ctx* ctx) { RMC_HIP(hipStreamSynchronize(ctx->stream)); }
 // the ctx) mirrored into a device region of the arena.
 struct DescArena {
   rmc_ctx* ctx;
+  hipStream_t st;
+  char* host = nullptr;
   char* dev = nullptr;
   size_t cap = 0, used = 0, flushed = 0;
-  DescArena(rmc_ctx* c, Scratch& sc, size_t bytes) : ctx(c) {
+  DescArena(rmc_ctx* c, hipStream_t s, int lane, Scratch& sc, size_t bytes) : ctx(c), st(s) {
     cap = bytes;
     dev = sc.get<char>(bytes);
-    if (ctx->pinned_cap < bytes) {
-      if (ctx->pinned) RMC_HIP(hipHostFree(ctx->pinned));
-      ctx->pinned = nullptr;
-      ctx->pinned_cap = 0;
-      RMC_HIP(hipHostMalloc((void**)&ctx->pinned, bytes));
-      ctx->pinned_cap = bytes;
+    if (ctx->pinned_cap[lane] < bytes) {
+      if (ctx->pinned[lane]) RMC_HIP(hipHostFree(ctx->pinned[lane]));
+      ctx->pinned[lane] = nullptr;
+      ctx->pinned_cap[lane] = 0;
+      RMC_HIP(hipHostMalloc((void**)&ctx->pinned[lane], bytes));
+      ctx->pinned_cap[lane] = bytes;
     }
+    host = ctx->pinned[lane];
   }
   template <class T>
   T* add(const T* p, size_t count) {
     size_t off = (used + 63) & ~(size_t)63;
     size_t b = count * sizeof(T);
     RMC_CHECK(off + b <= cap, RMC_ERR_OOM, "descriptor table overflow");
-    if (b) memcpy(ctx->pinned + off, p, b);
+    if (b) memcpy(host + off, p, b);
     used = off + b;
     return reinterpret_cast<T*>(dev + off);
   }
@@ -100,8 +105,8 @@ struct DescArena {
   void defer(std::function<void()> f) { pending.push_back(std::move(f)); }
   void flush() {
     if (used > flushed)
-      RMC_HIP(hipMemcpyAsync(dev + flushed, ctx->pinned + flushed, used - flushed,
-                             hipMemcpyHostToDevice, ctx->stream));
+      RMC_HIP(hipMemcpyAsync(dev + flushed, host + flushed, used - flushed,
+                             hipMemcpyHostToDevice, st));
     flushed = used;
     for (auto& f : pending) f();
     pending.clear();
@@ -115,6 +120,7 @@ struct BP {
   int n, m, nev, guard;
   double *X, *HX, *Y[3], *E, *S, *Linv, *Vwork, *Pm, *kwork;
   double *theta, *res;
+  double *wPY = nullptr, *wH = nullptr, *wPH = nullptr, *wT = nullptr, *wU = nullptr;  // kind 2, projected
   int* info;
   int* sel;
   // host state
@@ -128,6 +134,8 @@ struct BP {
 
 struct Batch {
   rmc_ctx* ctx;
+  hipStream_t st = nullptr;  // the lane's stream: every launch of this batch goes there
+  int lane = 0;
   int kind;
   int KS = 1;  // split-K of the Gram products
   int mmax = 0, nmax = 0, kAmax = 0, kBmax = 0;
@@ -160,7 +168,7 @@ void vec_launch(Batch& B, VecOp op, const std::vector<VecDesc>& d) {
     emax = std::max(emax, (long)x.nv * x.n);
   }
   const VecDesc* dd = B.da->add(d);
-  hipStream_t st = B.ctx->stream;
+  hipStream_t st = B.st;
   const int P = (int)d.size();
   B.da->defer([=] { vec_batched(st, op, dd, P, nvmax, emax); });
 }
@@ -173,11 +181,12 @@ void gemm_launch(Batch& B, bool tA, bool tB, const std::vector<GemmDesc>& d, int
     Nmax = std::max(Nmax, x.N);
   }
   const GemmDesc* dd = B.da->add(d);
-  hipStream_t st = B.ctx->stream;
+  hipStream_t st = B.st;
   const int P = (int)d.size();
   B.da->defer([=] { gemm_batched(st, tA, tB, dd, P, Mmax, Nmax, ksplit); });
 }
 
+// (caller holds ctx->prof_mu)
 hipEvent_t take_event(rmc_ctx* ctx) {
   hipEvent_t e;
   if (!ctx->ev_pool.empty()) {
@@ -196,10 +205,118 @@ struct Apply {
   std::vector<int> cnt;
 };
 
+// dst = P src for cnt rows of 2^(nA+nB) per problem, P = (PsiA^T PsiA) (x) (PsiB^T PsiB):
+// each row as a 2^nA x 2^nB matrix Y, P Y = PsiA^T (PsiA Y PsiB^T) PsiB, in four
+// grouped GEMMs (the outer two over all rows of a problem at once).
+void proj_launch(Batch& B, const std::vector<BP*>& L, const std::vector<const double*>& src,
+                 const std::vector<double*>& dst, const std::vector<int>& cnt) {
+  std::vector<GemmDesc> g1, g2, g3, g4;
+  for (size_t i = 0; i < L.size(); ++i) {
+    const CoupledOp& op = *L[i]->op;
+    const int DA = 1 << op.nA, DB = 1 << op.nB, kA = op.kA, kB = op.kB, c = cnt[i];
+    double* T = L[i]->wT;
+    double* U = L[i]->wU;
+    GemmDesc d{};
+    d.alpha = 1.0; d.beta = 0.0;
+    // T (c DA x kB) = Y (c DA x DB) PsiB^T
+    d.M = c * DA; d.N = kB; d.K = DB;
+    d.A = src[i]; d.lda = DB; d.B = op.PsiB; d.ldb = DB; d.C = T; d.ldc = kB;
+    g1.push_back(d);
+    // Q = P Y = T2 (c DA x kB) PsiB with T2_v = PsiA^T U_v
+    d.M = c * DA; d.N = DB; d.K = kB;
+    d.A = T; d.lda = kB; d.B = op.PsiB; d.ldb = DB; d.C = dst[i]; d.ldc = DB;
+    g4.push_back(d);
+    for (int v = 0; v < c; ++v) {
+      GemmDesc e{};
+      e.alpha = 1.0; e.beta = 0.0;
+      // U_v (kA x kB) = PsiA (kA x DA) T_v (DA x kB)
+      e.M = kA; e.N = kB; e.K = DA;
+      e.A = op.PsiA; e.lda = DA; e.B = T + (size_t)v * DA * kB; e.ldb = kB;
+      e.C = U + (size_t)v * kA * kB; e.ldc = kB;
+      g2.push_back(e);
+      // T_v (DA x kB) = PsiA^T U_v
+      e.M = DA; e.N = kB; e.K = kA;
+      e.A = op.PsiA; e.lda = DA; e.B = U + (size_t)v * kA * kB; e.ldb = kB;
+      e.C = T + (size_t)v * DA * kB; e.ldc = kB;
+      g3.push_back(e);
+    }
+  }
+  gemm_launch(B, false, true, g1, 1);
+  gemm_launch(B, false, false, g2, 1);
+  gemm_launch(B, true, false, g3, 1);
+  gemm_launch(B, false, false, g4, 1);
+}
+
+void pauli_launch(Batch& B, const std::vector<PauliDesc>& d) {
+  if (d.empty()) return;
+  long emax = 0;
+  for (auto& x : d) emax = std::max(emax, (long)x.nv << x.n_sites);
+  const PauliDesc* dd = B.da->add(d);
+  hipStream_t st = B.st;
+  const int P = (int)d.size();
+  B.da->defer([=] { pauli_batched(st, dd, P, emax); });
+}
+
+// Full-space operators: out = s1 Hsel Y + s2 Y + s3 Xprev, Hsel = H, or
+// Q H Q + sigma P = (H q - P H q) + sigma P Y with q = Y - P Y.
+void apply_full(Batch& B, const std::vector<BP*>& L, const Apply& a) {
+  std::vector<PauliDesc> pd;
+  std::vector<BP*> L1;
+  std::vector<size_t> i1;
+  std::vector<const double*> s1;
+  std::vector<double*> d1;
+  std::vector<int> c1;
+  for (size_t i = 0; i < L.size(); ++i) {
+    BP* p = L[i];
+    const CoupledOp& op = *p->op;
+    PauliDesc d{};
+    d.n_sites = op.nA + op.nB; d.n_terms = op.n_fterms; d.nv = a.cnt[i]; d.terms = op.fterms;
+    d.Y = a.Y[i];
+    if (!op.PsiA) {
+      d.out = a.out[i]; d.Y0 = a.Y[i]; d.Xprev = a.prev[i];
+      d.s1 = a.sc[i][0]; d.s2 = a.sc[i][1]; d.s3 = a.sc[i][2];
+    } else {
+      d.sub = p->wPY; d.out = p->wH; d.s1 = 1.0;
+      L1.push_back(p); i1.push_back(i);
+      s1.push_back(a.Y[i]); d1.push_back(p->wPY); c1.push_back(a.cnt[i]);
+    }
+    pd.push_back(d);
+  }
+  proj_launch(B, L1, s1, d1, c1);  // P Y
+  pauli_launch(B, pd);             // plain problems done; H (Y - P Y) for the others
+  if (L1.empty()) return;
+  for (size_t t = 0; t < L1.size(); ++t) s1[t] = L1[t]->wH, d1[t] = L1[t]->wPH;
+  proj_launch(B, L1, s1, d1, c1);  // P H q
+  std::vector<LinDesc> ld;
+  long nmax = 0;
+  for (size_t t = 0; t < L1.size(); ++t) {
+    BP* p = L1[t];
+    const size_t i = i1[t];
+    const double sA = a.sc[i][0];
+    LinDesc d{};
+    d.n = (long)a.cnt[i] * p->n; d.out = a.out[i];
+    d.U[0] = p->wH; d.w[0] = sA;
+    d.U[1] = p->wPH; d.w[1] = -sA;
+    d.U[2] = p->wPY; d.w[2] = sA * p->op->sigma;
+    d.U[3] = a.Y[i]; d.w[3] = a.sc[i][1];
+    d.U[4] = a.prev[i]; d.w[4] = a.sc[i][2];
+    ld.push_back(d);
+    nmax = std::max(nmax, d.n);
+  }
+  const LinDesc* dd = B.da->add(ld);
+  hipStream_t st = B.st;
+  const int P = (int)ld.size();
+  B.da->defer([=] { lincomb_batched(st, dd, P, nmax); });
+}
+
 // out = s1 H Y + s2 Y + s3 Xprev (+ s1 phi E) for every problem of L.
 void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_prec) {
   if (L.empty()) return;
   rmc_ctx* ctx = B.ctx;
+  if (B.kind == 2) {
+    apply_full(B, L, a);
+    return;
+  }
   if (B.kind == 0) {  // dense leaf: GEMM then axpy
     std::vector<GemmDesc> g;
     std::vector<VecDesc> v;
@@ -244,15 +361,18 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
     }
     if (kd.empty()) continue;
     const KronDesc* dd = B.da->add(kd);
-    hipStream_t st = ctx->stream;
+    hipStream_t st = B.st;
     const int P = (int)kd.size(), kBm = B.kBmax, kAm = B.kAmax;
     if (!ctx->prof) {
       B.da->defer([=] { kron_batched(st, dd, P, kBm, nvmax, kAm, prec, Tm, tv); });
       continue;
     }
     rmc_ctx::ProfRec r;
-    r.a = take_event(ctx);
-    r.b = take_event(ctx);
+    {
+      std::lock_guard<std::mutex> lk(ctx->prof_mu);
+      r.a = take_event(ctx);
+      r.b = take_event(ctx);
+    }
     hipEvent_t ea = r.a, eb = r.b;
     B.da->defer([=] {
       RMC_HIP(hipEventRecord(ea, st));
@@ -267,6 +387,7 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
       r.bytes += 8.0 * nn * ((double)d.nv * (2.0 + (d.Xprev ? 1.0 : 0.0) + (d.E ? 1.0 : 0.0)) + 1.0) +
                  8.0 * d.T * ((double)d.kA * d.kA + (double)d.kB * d.kB);
     }
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
     ctx->prof_recs.push_back(r);
   }
 }
@@ -287,7 +408,7 @@ void gram_launch(Batch& B, const std::vector<BP*>& L, const std::vector<const do
     cmax = std::max(cmax, std::max(ca[i], cb[i]));
   }
   const GramDesc* dd = B.da->add(g);
-  hipStream_t st = B.ctx->stream;
+  hipStream_t st = B.st;
   const int P = (int)g.size(), ks = B.KS;
   B.da->defer([=] { gram_batched(st, dd, P, ks, cmax); });
 }
@@ -295,8 +416,8 @@ void gram_launch(Batch& B, const std::vector<BP*>& L, const std::vector<const do
 void read_state(Batch& B) {
   B.da->flush();
   RMC_HIP(hipMemcpyAsync(B.TRh.data(), B.TR, B.TRh.size() * sizeof(double), hipMemcpyDeviceToHost,
-                         B.ctx->stream));
-  sync(B.ctx);
+                         B.st));
+  RMC_HIP(hipStreamSynchronize(B.st));
   B.da->reset();
 }
 
@@ -327,7 +448,7 @@ void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst) {
   }
   const CholDesc* dd = B.da->add(cd);
   {
-    hipStream_t st = B.ctx->stream;
+    hipStream_t st = B.st;
     const int P = (int)cd.size();
     B.da->defer([=] { chol_batched(st, dd, P, mm); });
   }
@@ -453,7 +574,7 @@ void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full)
   }
   const EigDesc* dd = B.da->add(ed);
   {
-    hipStream_t st = B.ctx->stream;
+    hipStream_t st = B.st;
     const int P = (int)ed.size();
     B.da->defer([=] { jacobi_batched(st, dd, P, mm); });
   }
@@ -577,7 +698,7 @@ bool update_problem(Batch& B, BP* p, int idx, int max_iter, double tol, int pmax
 int filter(Batch& B, const std::vector<BP*>& L) {
   int P = 0;
   for (BP* p : L) P = std::max(P, p->deg);
-  if (B.kind == 0) {
+  if (B.kind != 1) {
     // dense (leaf): direct scaled recurrence Y_{k+1} = (2s'/e)(H-c)Y_k - s s' Y_{k-1}
     std::vector<double> sig(L.size());
     Apply a;
@@ -714,11 +835,14 @@ int filter(Batch& B, const std::vector<BP*>& L) {
 }
 
 // One attempt at all problems with their current guard sizes.
-void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& o, bool last) {
+void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& o, bool last,
+                   hipStream_t stream, int lane) {
   const int JM = jacobi_max_m();
   Scratch sc(&ctx->arena);
   Batch B;
   B.ctx = ctx;
+  B.st = stream;
+  B.lane = lane;
   B.kind = probs[0]->op->kind;
   for (BP* p : probs) {
     p->m = std::min(p->n, p->nev + p->guard);
@@ -759,12 +883,20 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
     p->res = p->theta + B.mmax;
     p->info = reinterpret_cast<int*>(p->res + B.mmax);
     p->sel = sc.get<int>(p->m);
+    if (p->op->kind == 2 && p->op->PsiA) {
+      const size_t DA = (size_t)1 << p->op->nA;
+      p->wPY = sc.get<double>(mn);
+      p->wH = sc.get<double>(mn);
+      p->wPH = sc.get<double>(mn);
+      p->wT = sc.get<double>((size_t)p->m * DA * p->op->kB);
+      p->wU = sc.get<double>((size_t)p->m * p->op->kA * p->op->kB);
+    }
   }
-  RMC_HIP(hipMemsetAsync(B.TR, 0, (size_t)P * B.trs * sizeof(double), ctx->stream));
+  RMC_HIP(hipMemsetAsync(B.TR, 0, (size_t)P * B.trs * sizeof(double), B.st));
   const int pmax = o.max_degree > 0 ? o.max_degree : 40;
   const size_t da_bytes =
       (size_t)P * ((size_t)(pmax + 4) * B.mmax * 8 + (size_t)(pmax + 48) * 4 * 256) + (1 << 20);
-  DescArena da(ctx, sc, da_bytes);
+  DescArena da(ctx, B.st, lane, sc, da_bytes);
   B.da = &da;
 
   std::vector<int> idx_all(P);
@@ -778,7 +910,7 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
       sd.push_back(d);
     }
     const StartDesc* dd = da.add(sd);
-    hipStream_t st = ctx->stream;
+    hipStream_t st = B.st;
     const int nm = B.nmax, mm = B.mmax;
     da.defer([=] { start_batched(st, dd, P, nm, mm); });
   }
@@ -845,6 +977,64 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
   }
 }
 
+// Solver lanes (RMC_LANES = 1 or 2, default 2). With two, a batch of at least eight
+// problems is split into two halves that run the same lockstep iteration on two
+// streams from two host threads: the Rayleigh-Ritz, Cholesky and Gram kernels of one
+// half (one or a few workgroups per problem, far fewer than the chip holds) then run
+// beside the other half's Kronecker filter, and each half's host-side bookkeeping
+// overlaps the other's device work. The halves share nothing but the arena and the
+// profiling records, both locked.
+int solver_lanes() {
+  static const int n = [] {
+    const char* e = getenv("RMC_LANES");
+    return (e && atoi(e) == 1) ? 1 : 2;
+  }();
+  return n;
+}
+
+void run_attempt(rmc_ctx* ctx, std::vector<BP*>& L, const rmc_solve_opts& o, bool last) {
+  constexpr size_t kMinSplit = 8;
+  if (solver_lanes() < 2 || L.size() < kMinSplit) {
+    solve_attempt(ctx, L, o, last, ctx->stream, 0);
+    return;
+  }
+  if (!ctx->lane_stream) {
+    RMC_HIP(hipStreamCreateWithFlags(&ctx->lane_stream, hipStreamNonBlocking));
+    for (auto& e : ctx->lane_ev) RMC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  // deal the problems out by size so both halves carry a similar load
+  std::vector<BP*> srt(L), half[2];
+  std::stable_sort(srt.begin(), srt.end(), [](const BP* a, const BP* b) {
+    return (long)a->n * (a->nev + a->guard) > (long)b->n * (b->nev + b->guard);
+  });
+  for (size_t i = 0; i < srt.size(); ++i) half[i % 2].push_back(srt[i]);
+  // lane 1 starts once everything queued on the ctx stream so far has run
+  RMC_HIP(hipEventRecord(ctx->lane_ev[0], ctx->stream));
+  RMC_HIP(hipStreamWaitEvent(ctx->lane_stream, ctx->lane_ev[0], 0));
+  std::exception_ptr err[2];
+  std::thread t([&] {
+    try {
+      RMC_HIP(hipSetDevice(ctx->device));
+      solve_attempt(ctx, half[1], o, last, ctx->lane_stream, 1);
+    } catch (...) {
+      err[1] = std::current_exception();
+    }
+  });
+  try {
+    solve_attempt(ctx, half[0], o, last, ctx->stream, 0);
+  } catch (...) {
+    err[0] = std::current_exception();
+  }
+  t.join();
+  // later work on the ctx stream runs after lane 1 (each lane has already drained its
+  // stream before returning; this keeps the order explicit)
+  hipError_t e = hipEventRecord(ctx->lane_ev[1], ctx->lane_stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ctx->lane_ev[1], 0);
+  for (auto& x : err)
+    if (x) std::rethrow_exception(x);
+  RMC_HIP(e);
+}
+
 }  // namespace
 
 // Lowest nevs[i] eigenpairs of several operators of one kind, in lockstep.
@@ -878,7 +1068,7 @@ void eig_lowest_batch(rmc_ctx* ctx, const std::vector<const CoupledOp*>& ops,
     for (int pass = 0; pass < 2; ++pass) {
       auto& L = pass == 0 ? more : last;
       if (L.empty()) continue;
-      solve_attempt(ctx, L, o, pass == 1);
+      run_attempt(ctx, L, o, pass == 1);
       for (BP* p : L) {
         const int i = (int)(p - bp.data());
         stats[i].iters += p->iters;

@@ -27,7 +27,7 @@ EXPORTED = (
     "rmc_module_info", "rmc_module_basis", "rmc_module_op", "rmc_module_free", "rmc_module_lift",
     "rmc_leaf_hamiltonian", "rmc_kron_apply", "rmc_sym_eig", "rmc_module_import",
     "rmc_profile", "rmc_profile_read", "rmc_profile_read_precision",
-    "rmc_serve_start", "rmc_submit", "rmc_poll", "rmc_serve_stop",
+    "rmc_serve_start", "rmc_submit", "rmc_poll", "rmc_serve_stop", "rmc_merge_bound",
 )
 
 
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "rmc_submit": (i, [vp, P(ChainDesc), P(C.c_ulonglong)]),
         "rmc_poll": (i, [vp, C.c_ulonglong, P(i), P(d), P(i), P(d)]),
         "rmc_serve_stop": (i, [vp]),
+        "rmc_merge_bound": (i, [vp, vp, P(LeafDesc), vp, P(LeafDesc), P(BondDesc), P(SolveOpts),
+                                P(d)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -304,6 +306,21 @@ class Context:
                                     e.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rep))
         self._check(st)
         return (Module(self, out) if want_module else None), e, rep.as_dict()
+
+    def merge_bound(self, A: Module, terms_A, B: Module, terms_B, coefs, opA, opB,
+                    opts: Optional[SolveOpts] = None):
+        """Single-merge diagnostics of two leaf modules built from terms_A / terms_B:
+        dict with a, b, c, gamma, r, b2_over_gamma, E0."""
+        arr_a, na = make_terms(terms_A)
+        arr_b, nb = make_terms(terms_B)
+        la = LeafDesc(A.info()["n_sites"], na, arr_a)
+        lb = LeafDesc(B.info()["n_sites"], nb, arr_b)
+        bd, keep = _bond(coefs, opA, opB)
+        out = np.zeros(7)
+        self._check(lib().rmc_merge_bound(self.h, A.h, C.byref(la), B.h, C.byref(lb), C.byref(bd),
+                                          C.byref(opts) if opts else None,
+                                          out.ctypes.data_as(C.POINTER(C.c_double))))
+        return dict(zip(("a", "b", "c", "gamma", "r", "b2_over_gamma", "E0"), out.tolist()))
 
     def recurse(self, n_sites: int, leaf_sites: int, terms, k: int, q: int,
                 opts: Optional[SolveOpts] = None, report_capacity: int = 64):

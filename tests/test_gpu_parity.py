@@ -14,6 +14,7 @@ import sys
 import numpy as np
 import pytest
 
+from oracle import bounds as OB
 from oracle import exact as OX
 from oracle import hamiltonian as OH
 from oracle import recursion as OR
@@ -693,3 +694,83 @@ def test_lifted_states_three_levels(ctx):
     assert np.all(Ek[:4] >= np.linalg.eigvalsh(Hf)[:4] - 1e-10)
     for mod in [top, M01, M23] + leaves:
         mod.free()
+
+
+# --- single-merge truncation diagnostics (Sec. IV single-merge bound; App. on the
+# error bounds and its validation figure at L = 10 and 20) ---------------------------
+
+
+def _merge_bound_gpu(ctx, job, nA, k):
+    L = job.n_sites
+    tA, tB = SM.block_terms(job, 0, nA), SM.block_terms(job, nA, L)
+    A = ctx.module_ed(nA, tA, k)
+    B = ctx.module_ed(L - nA, tB, k)
+    cut = [ops for c, ops in SM.chain_terms(job) if len(ops) == 2 and ops[0][0] < nA <= ops[1][0]]
+    coefs = [c for c, ops in SM.chain_terms(job) if len(ops) == 2 and ops[0][0] < nA <= ops[1][0]]
+    opA = A.project_ops([o[0][0] for o in cut], [o[0][1] for o in cut])
+    opB = B.project_ops([o[1][0] - nA for o in cut], [o[1][1] for o in cut])
+    d = ctx.merge_bound(A, tA, B, tB, coefs, opA, opB)
+    d["kA"], d["kB"] = A.info()["k_eff"], B.info()["k_eff"]
+    A.free()
+    B.free()
+    return d
+
+
+BOUND_CASES = [
+    ("tfim10", W.ChainJob("tfim", 10, 5, 4, 1, J=1.0, h=0.7), 5),
+    ("xxz8", W.ChainJob("xxz", 8, 4, 4, 1, J=1.0, delta=0.5), 4),
+    ("nnn8", W.ChainJob("tfim_nnn", 8, 4, 4, 1, J=1.0, h=0.7, j2=0.2), 4),
+    ("nnn10_6_4", W.ChainJob("tfim_nnn", 10, 5, 4, 1, J=1.0, h=0.9, j2=0.3), 6),
+]
+
+
+@pytest.mark.parametrize("name,job,nA", BOUND_CASES, ids=[c[0] for c in BOUND_CASES])
+@pytest.mark.parametrize("k", [1, 2, 5, 8, 12])
+def test_merge_bound_matches_oracle(ctx, name, job, nA, k):
+    """a, b, c and E0 of one merge against the oracle's full-space dense definitions;
+    gamma, r and b^2/gamma follow from them."""
+    say("merge bound", name, k)
+    d = _merge_bound_gpu(ctx, job, nA, k)
+    ref = OB.merge_bound_dense(job, nA, k)
+    assert (d["kA"], d["kB"]) == (ref.kA, ref.kB)
+    for f in ("a", "b", "c", "E0"):
+        assert abs(d[f] - getattr(ref, f)) <= 1e-10 * max(1.0, abs(getattr(ref, f))), (f, d, ref)
+    assert d["gamma"] == pytest.approx(ref.gamma, abs=1e-9)
+    assert d["r"] == pytest.approx(ref.r, abs=1e-9)
+    if ref.gamma > 0:
+        assert d["b2_over_gamma"] == pytest.approx(ref.b2_over_gamma, rel=1e-9)
+        assert -1e-10 <= d["a"] - d["E0"] <= d["r"] + 1e-10
+    else:
+        assert d["b2_over_gamma"] == float("inf")
+
+
+def test_merge_bound_full_k_has_no_discarded_sector(ctx):
+    say("merge bound full k")
+    job = W.ChainJob("tfim", 10, 5, 4, 1, J=1.0, h=0.7)
+    d = _merge_bound_gpu(ctx, job, 5, 32)
+    assert d["b"] == 0.0 and d["r"] == 0.0 and d["c"] == float("inf")
+    assert d["a"] == pytest.approx(d["E0"], abs=1e-10)
+
+
+def test_merge_bound_twenty_sites(ctx):
+    """The paper's L = 20 validation (two ten-site TFIM leaves, J = 1, g = 0.7): values
+    against the stored oracle results (sparse full-space route), E0 against the
+    free-fermion ground energy, gamma > 0 and a - E0 <= r(b, gamma) for every k."""
+    rows = {}
+    p = os.path.join(os.path.dirname(__file__), "golden", "merge_bounds_tfim20.txt")
+    for line in open(p):
+        if line.strip() and not line.startswith("#"):
+            k, kA, kB, a, b, c, E0 = line.split()
+            rows[int(k)] = (int(kA), int(kB), float(a), float(b), float(c), float(E0))
+    job = W.ChainJob("tfim", 20, 10, 4, 1, J=1.0, h=0.7)
+    e0 = OX.tfim_free_fermion(20, 1.0, 0.7, 1)[0]
+    for k, (kA, kB, a, b, c, E0) in sorted(rows.items()):
+        say("merge bound L=20", k)
+        d = _merge_bound_gpu(ctx, job, 10, k)
+        assert (d["kA"], d["kB"]) == (kA, kB)
+        assert abs(d["a"] - a) <= 1e-10 * abs(a)
+        assert abs(d["b"] - b) <= 1e-10
+        assert abs(d["c"] - c) <= 1e-10 * abs(c)
+        assert abs(d["E0"] - e0) <= 1e-10 * abs(e0)
+        assert d["gamma"] > 0
+        assert 0.0 <= d["a"] - d["E0"] <= d["r"] <= d["b2_over_gamma"]
