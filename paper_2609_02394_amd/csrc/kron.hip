@@ -685,6 +685,172 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_
   }
 }
 
+// ---- fused Chebyshev filter ---------------------------------------------------------
+// Every step of the filter's recurrence acts on each vector alone, so one workgroup
+// carries a vector through all of its steps: the FP64 iterates D_k, D_{k-1}, the
+// defect E_j and the diagonal stay in registers (one 16 x 16 tile per wave, in the
+// accumulator layout), the low-precision copy of D_k that feeds the MFMAs sits in
+// LDS, and the problem's 2T operator tiles are resident in LDS for as long as the
+// workgroup stays on that problem. HBM sees E_j and X_j once and out_j once per
+// vector instead of four vectors per step. Per step and term: stage 1 (Z = D O_B^T,
+// stored transposed, double-buffered across terms) and stage 2 (acc += c O_A Z),
+// one barrier after each stage 1 and one after the new iterate is written.
+// The arithmetic is that of the per-step kernel in the same order.
+template <int P, int KM>
+__global__ __launch_bounds__(64 * (KM / 16) * (KM / 16)) void kron_filter_kernel(
+    const FilterDesc* __restrict__ descs, int P_, long V, int G) {
+  typedef typename SK<P>::lt lt;
+  typedef typename SK<P>::acc accT;
+  typedef typename Grp<P>::t gv;
+  constexpr int RTM = KM / 16;
+  constexpr int NT = 64 * RTM * RTM;
+  constexpr int PW = sk_pitch<P>(KM);
+  constexpr int NCH = KM / SK<P>::CH;
+  constexpr int TILE = KM * PW;
+  extern __shared__ char smem_raw[];
+  lt* Ys = reinterpret_cast<lt*>(smem_raw);
+  lt* Zt0 = Ys + TILE;
+  lt* Ops = Zt0 + 2 * TILE;  // tile 2t: O_B^t, tile 2t+1: c_t O_A^t
+
+  const int w = blockIdx.x;
+  const int L = (w & 7) * (G >> 3) + (w >> 3);
+  const long v0 = (long)L * V / G, v1 = (long)(L + 1) * V / G;
+  if (v0 >= v1) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int rt = wave / RTM, ct = wave % RTM;
+  const int col = ct * 16 + l16;
+
+  int p = 0;
+  {
+    int lo = 0, hi = P_ - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (descs[mid].vbase <= v0) lo = mid;
+      else hi = mid - 1;
+    }
+    p = lo;
+  }
+  int j = (int)(v0 - descs[p].vbase);
+  int loaded = -1;
+  for (long v = v0; v < v1; ++v) {
+    while (j >= descs[p].nv) {
+      j = 0;
+      ++p;
+    }
+    const FilterDesc* d = descs + p;
+    const int kA = d->kA, kB = d->kB, T = d->T, steps = d->steps, nv = d->nv;
+    const long n = (long)kA * kB;
+    if (loaded != p) {
+      __syncthreads();  // every wave is done with the previous operators
+      gptr<lt> pk = gview(static_cast<const lt*>(d->pack));
+      for (int q = tid; q < 2 * T * (KM * KM / 4); q += NT) {
+        const int tile = q / (KM * KM / 4), rem = q - tile * (KM * KM / 4);
+        const int r = rem / (KM / 4), cc = (rem % (KM / 4)) * 4;
+        const gv x = *reinterpret_cast<gptr<gv>>(pk + (long)tile * KM * KM + r * KM + cc);
+        lt* o = Ops + tile * TILE + r * PW + cc;
+        if constexpr (P == 0) {
+          *reinterpret_cast<double2*>(o) = double2{x[0], x[1]};
+          *reinterpret_cast<double2*>(o + 2) = double2{x[2], x[3]};
+        } else {
+          *reinterpret_cast<gv*>(o) = x;
+        }
+      }
+      loaded = p;
+    }
+    gptr<double> Ej = gview(d->E) + (long)j * n;
+    gptr<double> Edg = gview(d->Ediag);
+    double Dc[4], Dp[4], Ev[4], Ed[4];
+    int idx[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = rt * 16 + acc_row<P>(g, r);
+      const bool in = row < kA && col < kB;
+      idx[r] = in ? row * kB + col : -1;
+      Ev[r] = in ? Ej[idx[r]] : 0.0;
+      Ed[r] = in ? Edg[idx[r]] : 0.0;
+      Dc[r] = d->r0 * Ev[r];
+      Dp[r] = 0.0;
+      Ys[row * PW + col] = to_lt<P>(Dc[r]);
+    }
+    __syncthreads();
+    for (int k = 1; k <= steps; ++k) {
+      const double s1 = d->sc[3 * (k - 1)], s2 = d->sc[3 * (k - 1) + 1], s3 = d->sc[3 * (k - 1) + 2];
+      const double ph = s1 * d->phi[(long)(k - 1) * nv + j];
+      accT acc = accT{0, 0, 0, 0};
+      for (int t = 0; t < T; ++t) {
+        lt* Zt = Zt0 + (t & 1) * TILE;
+        const lt* Bs = Ops + 2 * t * TILE;
+        const lt* As = Bs + TILE;
+        accT z = accT{0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+          Frag<P> a, b;
+          a.load(Ys + (rt * 16 + l16) * PW, u, g);
+          b.load(Bs + (ct * 16 + l16) * PW, u, g);
+          mma_frag<P>(z, a.v, b);
+        }
+        lt* zr = Zt + (ct * 16 + l16) * PW + rt * 16;
+        if constexpr (P == 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) zr[acc_row<0>(g, r)] = z[r];
+        } else if constexpr (P == 1) {
+          *reinterpret_cast<float4*>(zr + 4 * g) = float4{z[0], z[1], z[2], z[3]};
+        } else {
+          lt h[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) h[r] = (__bf16)z[r];
+          *reinterpret_cast<uint2*>(zr + 4 * g) = *reinterpret_cast<const uint2*>(h);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+          Frag<P> a, b;
+          a.load(As + (rt * 16 + l16) * PW, u, g);
+          b.load(Zt + (ct * 16 + l16) * PW, u, g);
+          mma_frag<P>(acc, a.v, b);
+        }
+      }
+      // the per-step kernel's epilogue, on the register-resident iterates
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double o = s1 * ((double)acc[r] + Ed[r] * Dc[r]) + s2 * Dc[r];
+        o += s3 * Dp[r];
+        o += ph * Ev[r];
+        Dp[r] = Dc[r];
+        Dc[r] = idx[r] >= 0 ? o : 0.0;
+      }
+      if (k < steps) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ys[(rt * 16 + acc_row<P>(g, r)) * PW + col] = to_lt<P>(Dc[r]);
+        __syncthreads();
+      }
+    }
+    const double phP = d->phi[(long)steps * nv + j];
+    gptr<double> Xj = gview(d->X) + (long)j * n;
+    gptr_w<double> oj = gview_w(d->out) + (long)j * n;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (idx[r] >= 0) oj[idx[r]] = phP * Xj[idx[r]] + Dc[r];
+    ++j;
+  }
+}
+
+typedef void (*FilterKernel)(const FilterDesc*, int, long, int);
+
+static FilterKernel filter_kernel(int prec, int km) {
+  if (prec == RMC_FP64) return km <= 32 ? kron_filter_kernel<0, 32> : nullptr;
+  if (prec == RMC_FP32) return km <= 32 ? kron_filter_kernel<1, 32> : (km <= 64 ? kron_filter_kernel<1, 64> : nullptr);
+  return km <= 32 ? kron_filter_kernel<2, 32> : (km <= 64 ? kron_filter_kernel<2, 64> : nullptr);
+}
+
+static size_t filter_lds_bytes(int prec, int KM, int T) {
+  const int esz = prec == RMC_FP64 ? 8 : (prec == RMC_FP32 ? 4 : 2);
+  return (size_t)(3 + 2 * std::max(T, 0)) * KM * (KM + 16 / esz) * esz;
+}
+
+static constexpr size_t kFilterLdsMax = 159 * 1024;
+
 static size_t kron_lds_bytes(int kA, int prec) {
   // TCH * kApad * 16 * CT elements = 64 * kApad for every CT
   const int kApad = ((kA + 15) / 16) * 16;
@@ -751,9 +917,9 @@ static size_t stream_lds_bytes(int prec, int KM, bool sh = false) {
 
 // Workgroups of a streaming launch: resident workgroups per CU times the CU count
 // (a multiple of 8 for the XCD mapping), at most one per vector.
-static int stream_grid(StreamKernel k, int threads, size_t lds, long V) {
+static int stream_grid(const void* k, int threads, size_t lds, long V) {
   static std::mutex mu;
-  static std::map<const void*, int> per_cu;
+  static std::map<std::pair<const void*, size_t>, int> per_cu;
   static int cus = 0;
   int n;
   {
@@ -765,13 +931,12 @@ static int stream_grid(StreamKernel k, int threads, size_t lds, long V) {
           cus <= 0)
         cus = 256;
     }
-    auto it = per_cu.find(reinterpret_cast<const void*>(k));
+    auto it = per_cu.find({k, lds});
     if (it == per_cu.end()) {
       int b = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(k),
-                                                       threads, lds) != hipSuccess || b <= 0)
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, threads, lds) != hipSuccess || b <= 0)
         b = 1;
-      it = per_cu.emplace(reinterpret_cast<const void*>(k), b).first;
+      it = per_cu.emplace(std::make_pair(k, lds), b).first;
     }
     n = it->second * cus;
   }
@@ -798,6 +963,28 @@ void kron_set_attrs() {
       for (int mrt = 1; mrt <= 3; ++mrt)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kron_kernel(p, ct, mrt)),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  for (int p = 0; p < 3; ++p)
+    for (int km : {32, 64})
+      if (FilterKernel k = filter_kernel(p, km))
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFilterLdsMax);
+}
+
+bool kron_filter_fits(int precision, int kA, int kB, int T) {
+  const int km = stream_km(std::max(kA, kB));
+  return filter_kernel(precision, km) != nullptr && stream_kernel(precision, km, 1) != nullptr &&
+         filter_lds_bytes(precision, km, T) <= kFilterLdsMax;
+}
+
+void kron_filter_batched(hipStream_t s, const FilterDesc* d, int P, long total_vecs, int precision,
+                         int kmax, int Tmax) {
+  if (P <= 0 || total_vecs <= 0) return;
+  const int KM = stream_km(kmax);
+  FilterKernel k = filter_kernel(precision, KM);
+  const int threads = 64 * (KM / 16) * (KM / 16);
+  const size_t lds = filter_lds_bytes(precision, KM, Tmax);
+  const int G = stream_grid(reinterpret_cast<const void*>(k), threads, lds, total_vecs);
+  hipLaunchKernelGGL(k, dim3(G), dim3(threads), lds, s, d, P, total_vecs, G);
 }
 
 // ---- operator packs for the streaming kernel ----------------------------------------
@@ -952,7 +1139,7 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
       StreamKernel k = stream_kernel(precision, KM, nwc, sh);
       const int threads = 4 * KM * nwc;
       const size_t slds = stream_lds_bytes(precision, KM, sh);
-      const int G = stream_grid(k, threads, slds, total_vecs);
+      const int G = stream_grid(reinterpret_cast<const void*>(k), threads, slds, total_vecs);
       hipLaunchKernelGGL(k, dim3(G), dim3(threads), slds, s, d, P, total_vecs, G);
       return;
     }

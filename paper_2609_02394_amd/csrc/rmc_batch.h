@@ -28,6 +28,30 @@ struct KronDesc {
   double s1, s2, s3;
 };
 
+// The whole Chebyshev filter of one problem in defect form, every vector carried
+// through all its steps by one workgroup (steps = degree - 1 matvecs):
+//   D_1 = r0 E_j;  D_{k+1} = s1_k (H_low D_k + Ediag .* D_k) + s2_k D_k + s3_k D_{k-1}
+//                            + s1_k phi_k[j] E_j   (k = 1..steps, D_0 = 0)
+//   out_j = phi_{steps+1}[j] X_j + D_{steps+1}
+// sc: steps x {s1, s2, s3}; phi: (steps + 1) x nv, row k-1 = phi_k. pack: the
+// operators in the streaming layout of the launch precision (tile KM = pkm).
+struct FilterDesc {
+  int kA, kB, T, nv;
+  long vbase;
+  const void* pack;
+  int pkm, steps;
+  const double* Ediag;
+  const double* E;
+  const double* X;
+  double* out;
+  const double* sc;
+  const double* phi;
+  double r0;
+};
+bool kron_filter_fits(int precision, int kA, int kB, int T);
+void kron_filter_batched(hipStream_t s, const FilterDesc* d, int P, long total_vecs, int precision,
+                         int kmax, int Tmax);
+
 // C = alpha op(A) op(B) + beta C (row-major); with `work` non-null the launch
 // writes split-K partials to work (ksplit x M x N) instead of C.
 struct GemmDesc {

@@ -694,6 +694,84 @@ bool update_problem(Batch& B, BP* p, int idx, int max_iter, double tol, int pmax
   return true;
 }
 
+int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr);
+
+// Whole-filter launches (kron_filter_batched), one per precision: the step scalars
+// and the phi_k rows of every problem are computed on the host up front (the same
+// recurrences as the per-step path) and travel in the descriptor tables.
+void fused_filter(Batch& B, const std::vector<BP*>& L, int P, int outr) {
+  rmc_ctx* ctx = B.ctx;
+  for (int prec = 0; prec < 3; ++prec) {
+    std::vector<FilterDesc> fd;
+    int kmax = 0, Tm = 0;
+    long tv = 0;
+    double flops = 0.0, bytes = 0.0;
+    for (BP* p : L) {
+      if (p->prec != prec) continue;
+      const CoupledOp& op = *p->op;
+      const int cn = p->cnt, steps = P - 1;
+      std::vector<double> sc(3 * (size_t)std::max(steps, 1)), phi((size_t)(steps + 1) * cn);
+      std::vector<double> pm1(cn, 1.0), pk(cn);
+      for (int j = 0; j < cn; ++j) pk[j] = (p->sigma1 / p->e) * (p->th[p->nlock + j] - p->c);
+      std::copy(pk.begin(), pk.end(), phi.begin());
+      double sg = p->sigma1;
+      const double tau2 = 2.0 / p->sigma1;
+      for (int k = 1; k <= steps; ++k) {
+        const double sk1 = 1.0 / (tau2 - sg);
+        sc[3 * (k - 1)] = 2.0 * sk1 / p->e;
+        sc[3 * (k - 1) + 1] = -2.0 * p->c * sk1 / p->e;
+        sc[3 * (k - 1) + 2] = k > 1 ? -sg * sk1 : 0.0;
+        for (int j = 0; j < cn; ++j) {
+          const double nx = (2.0 * sk1 / p->e) * (p->th[p->nlock + j] - p->c) * pk[j] - sg * sk1 * pm1[j];
+          pm1[j] = pk[j];
+          pk[j] = nx;
+        }
+        std::copy(pk.begin(), pk.end(), phi.begin() + (size_t)k * cn);
+        sg = sk1;
+      }
+      FilterDesc d{};
+      d.kA = op.kA; d.kB = op.kB; d.T = op.T; d.nv = cn; d.vbase = tv;
+      d.pack = op.pack[prec]; d.pkm = op.pkm; d.steps = steps;
+      d.Ediag = op.Ediag; d.E = p->E; d.X = role_ptr(p, 3); d.out = p->Y[outr];
+      d.sc = B.da->add(sc);
+      d.phi = B.da->add(phi);
+      d.r0 = p->sigma1 / p->e;
+      fd.push_back(d);
+      kmax = std::max(kmax, std::max(op.kA, op.kB));
+      Tm = std::max(Tm, op.T);
+      tv += cn;
+      const double nn = (double)op.kA * op.kB;
+      flops += (double)cn * steps * (2.0 * op.T * nn * (op.kA + op.kB) + 4.0 * nn);
+      bytes += 8.0 * nn * (3.0 * cn + 1.0) + 8.0 * op.T * ((double)op.kA * op.kA + (double)op.kB * op.kB);
+    }
+    if (fd.empty()) continue;
+    const FilterDesc* dd = B.da->add(fd);
+    hipStream_t st = B.st;
+    const int nd = (int)fd.size();
+    if (!ctx->prof) {
+      B.da->defer([=] { kron_filter_batched(st, dd, nd, tv, prec, kmax, Tm); });
+      continue;
+    }
+    rmc_ctx::ProfRec r;
+    {
+      std::lock_guard<std::mutex> lk(ctx->prof_mu);
+      r.a = take_event(ctx);
+      r.b = take_event(ctx);
+    }
+    hipEvent_t ea = r.a, eb = r.b;
+    B.da->defer([=] {
+      RMC_HIP(hipEventRecord(ea, st));
+      kron_filter_batched(st, dd, nd, tv, prec, kmax, Tm);
+      RMC_HIP(hipEventRecord(eb, st));
+    });
+    r.flops = flops;
+    r.bytes = bytes;
+    r.prec = prec;
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    ctx->prof_recs.push_back(r);
+  }
+}
+
 // One filter application on the problems of L; returns the Y buffer holding it.
 int filter(Batch& B, const std::vector<BP*>& L) {
   int P = 0;
@@ -751,6 +829,39 @@ int filter(Batch& B, const std::vector<BP*>& L) {
     }
     vec_launch(B, VEC_SCALE_ADD, ed);
   }
+  // buffer that holds the result: the per-step path rotates three buffers
+  int outr;
+  {
+    int pv = -1, cu = 0;
+    for (int k = 1; k < P; ++k) {
+      int nw = 0;
+      while (nw == cu || nw == pv) ++nw;
+      pv = cu;
+      cu = nw;
+    }
+    outr = (cu == 0) ? 1 : 0;
+  }
+  // problems whose operators fit the fused kernel's LDS run the whole filter in one
+  // launch per precision (RMC_FUSED_FILTER=0 keeps every problem on the per-step path)
+  std::vector<BP*> Lf, Ls;
+  {
+    const char* f = getenv("RMC_FUSED_FILTER");
+    const bool fused = !(f && atoi(f) == 0);
+    for (BP* p : L) {
+      const CoupledOp& op = *p->op;
+      const bool ok = fused && op.pack[p->prec] && kron_filter_fits(p->prec, op.kA, op.kB, op.T);
+      (ok ? Lf : Ls).push_back(p);
+    }
+  }
+  if (!Lf.empty()) fused_filter(B, Lf, P, outr);
+  for (BP* p : Lf) p->matvecs += p->cnt * (P - 1);
+  if (Ls.empty()) return outr;
+  return filter_steps(B, Ls, P, outr);
+}
+
+// The per-step path of the defect-form filter (one Kronecker launch per step for all
+// problems of L); the result ends in Y[outr].
+int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr) {
   // phi_k at the active Ritz values, one row per filter step, computed on the host just
   // before the step that uses it (so the device starts on the first steps while later
   // rows are still being computed); row 0 holds sigma_1/e
@@ -818,7 +929,7 @@ int filter(Batch& B, const std::vector<BP*>& L) {
     prev = cur;
     cur = nw;
   }
-  const int outr = (cur == 0) ? 1 : 0;
+  RMC_CHECK(outr == ((cur == 0) ? 1 : 0), RMC_ERR_STATE, "filter buffer rotation");
   {
     std::vector<VecDesc> dd;
     for (size_t i = 0; i < L.size(); ++i) {

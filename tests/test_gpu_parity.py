@@ -433,6 +433,54 @@ def test_recurse_mixed_precision_xxz_chain64(ctx, prec):
     assert rel_err(e, e64) <= 1e-8, (e, e64)
 
 
+FUSED_CASES = [
+    ("xxz_N64_k64", W.xxz_chain64(), [1, 2]),
+    ("tfim_N32_k16", W.ChainJob("tfim", 32, 8, 16, 8, J=1.0, h=0.9), [0, 1, 2]),
+    ("xxz_N16_k24", W.ChainJob("xxz", 16, 4, 24, 6, J=1.0, delta=0.7), [0, 1, 2]),
+    ("rfheis_N32_k48", W.ChainJob("rfheis", 32, 8, 48, 8, J=1.0, fields=W.rfheis_batch(2)[1].fields),
+     [1, 2]),
+]
+
+
+@pytest.mark.parametrize("name,job,precs", FUSED_CASES, ids=[c[0] for c in FUSED_CASES])
+def test_fused_filter_equals_per_step_filter(ctx, name, job, precs):
+    """The whole-filter launch (every vector through all of its Chebyshev steps in one
+    workgroup) against the per-step launches: the same arithmetic in the same order,
+    so the energies agree to rounding noise, and both match FP64 to 1e-8."""
+    from paper_2609_02394_amd import rmc
+
+    e64, _ = ctx.recurse(*rmc.job_chain(job))
+    for prec in precs:
+        say("fused filter", name, prec)
+        out = {}
+        for flag in ("1", "0"):
+            os.environ["RMC_FUSED_FILTER"] = flag
+            try:
+                out[flag], _ = ctx.recurse(*rmc.job_chain(job), opts=rmc.default_opts(precision=prec))
+            finally:
+                os.environ.pop("RMC_FUSED_FILTER", None)
+        assert rel_err(out["1"], out["0"]) <= 1e-13, (prec, out)
+        assert rel_err(out["1"], e64) <= 1e-8, (prec, out["1"], e64)
+
+
+def test_fused_filter_batch_mixes_fused_and_per_step_problems(ctx):
+    """A batch whose levels hold problems the fused kernel takes (k <= 64) beside
+    problems it does not (k = 96): both paths in one filter call, against single jobs."""
+    from paper_2609_02394_amd import rmc
+
+    say("fused filter mixed batch")
+    jobs = [W.ChainJob("rfheis", 32, 8, k, 6, J=1.0, fields=W.rfheis_batch(4)[i].fields)
+            for i, k in enumerate((32, 96, 64, 96))]
+    opts = rmc.default_opts(precision=1)
+    E, sts, st = ctx.recurse_batch([rmc.job_chain(j) for j in jobs], opts=opts)
+    assert st == 0 and all(x == 0 for x in sts), sts
+    for i, j in enumerate(jobs):
+        e1, _ = ctx.recurse(*rmc.job_chain(j), opts=opts)
+        ref = OR.recurse(j)
+        assert rel_err(E[i][: len(e1)], e1) <= 1e-10
+        assert rel_err(E[i][: len(ref.energies)], ref.energies) <= 1e-8
+
+
 # -- batched levels (many jobs per launch) -----------------------------------------
 
 def _batch_jobs():
