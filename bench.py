@@ -65,16 +65,19 @@ def cpu_baseline(job):
     return np.asarray(res.energies), dt, threads
 
 
-def measured_traffic(prec: str):
-    """HBM bytes per launch of the Kronecker kernel from committed rocprofv3 counter
-    runs (scaled by a copy kernel of known size), if taken on the current kernel."""
+KERNELS = {0: "kron_stream_kernel", 1: "kron_filter_kernel"}
+
+
+def measured_traffic(kernel: str, prec: str):
+    """HBM bytes per launch of a Kronecker kernel from committed rocprofv3 counter runs
+    (scaled by a copy kernel of known size), if taken on the current kernel source."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except Exception:
         return None
     if d.get("kron_source_sha") != kron_source_hash():
         return None
-    return d.get("bytes_per_launch", {}).get(prec)
+    return d.get("bytes_per_launch", {}).get(f"{kernel}:{prec}")
 
 
 def main():
@@ -87,9 +90,10 @@ def main():
                          "residuals and the defect correction stay FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--arena-gb", type=float, default=8.0)
-    ap.add_argument("--mode", choices=["recurse", "serve"], default="recurse",
+    ap.add_argument("--mode", choices=["recurse", "serve", "bound"], default="recurse",
                     help="recurse: timed recursions of the XXZ N=64 workload; serve: the "
-                         "Poisson serving stream through the continuous-batching scheduler")
+                         "Poisson serving stream through the continuous-batching scheduler; "
+                         "bound: single-merge truncation diagnostics of the L=20 TFIM chain")
     ap.add_argument("--workload", choices=["xxz64", "ladder96", "rfheis512"], default="xxz64",
                     help="xxz64: XXZ N=64 k=64 (the metric's configuration); ladder96: TFIM "
                          "ladder 2x48 k=128; rfheis512: 512 random-field Heisenberg chains N=32 "
@@ -119,6 +123,9 @@ def main():
 
     if args.mode == "serve":
         serve_bench(args)
+        return
+    if args.mode == "bound":
+        bound_bench(args)
         return
 
     if args.workload == "rfheis512":
@@ -179,6 +186,7 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     by_prec = {name: ctx.profile_read(PREC[name]) for name in PREC}
+    by_kernel = {(kk, name): ctx.profile_read(PREC[name], kernel=kk) for kk in KERNELS for name in PREC}
     ctx.profile(False)
 
     # the plain per-job FP64 recursion of the same workload, for comparison
@@ -195,21 +203,23 @@ def main():
                  "value": 5 / (time.perf_counter() - p0), "unit": "solves/s"}
 
     lat_ms = np.array(lat) * 1e3
-    # dominant kernel: the Kronecker matvec, in the precision that took most of its time
-    dom = max(by_prec, key=lambda k: by_prec[k]["ms"])
-    prof = by_prec[dom]
+    # dominant kernel: the Kronecker kernel kind (one matvec step, or the whole filter)
+    # and precision that took most of the Kronecker time
+    dk, dom = max(by_kernel, key=lambda k: by_kernel[k]["ms"])
+    prof = by_kernel[(dk, dom)]
     kron_table = {}
-    for name, pr in by_prec.items():
+    for (kk, name), pr in by_kernel.items():
         if pr["launches"] == 0:
             continue
         sec = pr["ms"] * 1e-3
-        kron_table[name] = {"launches": pr["launches"], "ms_per_step": pr["ms"] / args.steps,
-                            "avg_launch_us": pr["ms"] * 1e3 / pr["launches"],
-                            "tflops": pr["flops"] / sec / 1e12, "gbs": pr["bytes"] / sec / 1e9,
-                            "flops_per_launch": pr["flops"] / pr["launches"],
-                            "bytes_per_launch": pr["bytes"] / pr["launches"]}
+        kron_table[f"{KERNELS[kk]}:{name}"] = {
+            "launches": pr["launches"], "ms_per_step": pr["ms"] / args.steps,
+            "avg_launch_us": pr["ms"] * 1e3 / pr["launches"],
+            "tflops": pr["flops"] / sec / 1e12, "gbs": pr["bytes"] / sec / 1e9,
+            "flops_per_launch": pr["flops"] / pr["launches"],
+            "bytes_per_launch": pr["bytes"] / pr["launches"]}
     sec = prof["ms"] * 1e-3
-    tr = measured_traffic(dom)
+    tr = measured_traffic(KERNELS[dk], dom)
     if dom == "bf16":  # HBM-bound: the BF16 MFMA roof lies far above the HBM roof
         achieved = prof["bytes"] / sec / 1e9 if sec > 0 else 0.0
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
@@ -219,7 +229,7 @@ def main():
         peak = PEAK_TFLOPS[dom]
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak}
-    roof.update({"traffic": tr, "kernel": "kron_stream_kernel", "precision": dom,
+    roof.update({"traffic": tr, "kernel": KERNELS[dk], "precision": dom,
                  "launches": prof["launches"],
                  "avg_launch_us": prof["ms"] * 1e3 / max(1, prof["launches"]),
                  "flops_per_launch": prof["flops"] / max(1, prof["launches"]),
@@ -248,7 +258,7 @@ def main():
                    "jobs_per_step": B, "accurate_solves": ok,
                    "form": "per-job recursion" if B == 1 else "batched levels"},
         "roofline": roof,
-        "kron_by_precision": kron_table,
+        "kron_by_kernel": kron_table,
         "plain_per_job_fp64": plain,
         "cpu_baseline": cpu,
         "report_last_step": rep["records"] if rep else None,
@@ -305,6 +315,87 @@ def batch_bench(args):
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "launches": prof["launches"],
                      "avg_launch_us": prof["ms"] * 1e3 / max(1, prof["launches"])},
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+def bound_bench(args):
+    """Single-merge truncation diagnostics (a, ||PHQ||, lambda_min(QHQ), gamma, r, E0) of
+    the open TFIM chain L = 20 as two ten-site leaves, J = 1, g = 0.7, k = 8: a step is
+    one rmc_merge_bound call on the two leaf modules (built once). Checked against the
+    free-fermion ground energy and the stored oracle values of the same merge."""
+    import numpy as np
+
+    from oracle import exact as OX
+    from paper_2609_02394_amd import rmc, spin_models as SM, workloads as W
+
+    k, L, nA = 8, 20, 10
+    job = W.ChainJob("tfim", L, nA, k, 1, J=1.0, h=0.7)
+    ctx = rmc.Context(arena_bytes=int(args.arena_gb * (1 << 30)))
+    tA, tB = SM.block_terms(job, 0, nA), SM.block_terms(job, nA, L)
+    A = ctx.module_ed(nA, tA, k)
+    B = ctx.module_ed(L - nA, tB, k)
+    cut = [(c, ops) for c, ops in SM.chain_terms(job) if len(ops) == 2 and ops[0][0] < nA <= ops[1][0]]
+    opA = A.project_ops([o[0][0] for _, o in cut], [o[0][1] for _, o in cut])
+    opB = B.project_ops([o[1][0] - nA for _, o in cut], [o[1][1] for _, o in cut])
+    coefs = [c for c, _ in cut]
+
+    def step():
+        return ctx.merge_bound(A, tA, B, tB, coefs, opA, opB)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    e0 = float(OX.tfim_free_fermion(L, 1.0, 0.7, 1)[0])
+    gold = None
+    gp = os.path.join(ROOT, "tests", "golden", "merge_bounds_tfim20.txt")
+    for line in open(gp):
+        if line.strip() and not line.startswith("#") and int(line.split()[0]) == k:
+            gold = [float(x) for x in line.split()[3:]]
+    steps = max(1, min(args.steps, 5))
+    lat, ok, d = [], 0, None
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        d = step()
+        lat.append(time.perf_counter() - s0)
+        good = abs(d["E0"] - e0) <= 1e-10 * abs(e0) and gold is not None and \
+            abs(d["a"] - gold[0]) <= 1e-10 * abs(gold[0]) and abs(d["b"] - gold[1]) <= 1e-10 and \
+            abs(d["c"] - gold[2]) <= 1e-10 * abs(gold[2])
+        ok += bool(good)
+    total = time.perf_counter() - t0
+    pr = ctx.profile_read(rmc.FP64, kernel=rmc.PROF_PAULI)
+    ctx.profile(False)
+    sec = pr["ms"] * 1e-3
+    gbs = pr["bytes"] / sec / 1e9 if sec > 0 else 0.0
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import bounds as OB
+        c0 = time.perf_counter()
+        OB.merge_bound_sparse(job, nA, k)
+        cs = time.perf_counter() - c0
+        cpu = {"value": 1.0 / cs, "unit": "diagnostics/s", "cores": os.cpu_count() or 1,
+               "kind": "oracle", "sample": "one whole diagnostic of the same merge (retained-space "
+                                           "b, ARPACK Lanczos on scipy sparse H for E0 and c)",
+               "seconds": cs}
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": "single-merge truncation diagnostics/s (a, ||PHQ||_2, lambda_min(QHQ), r, E0)",
+        "value": ok / total, "unit": "diagnostics/s", "n_gpus": 1, "steps": steps,
+        "warmup": max(1, args.warmup), "ms_per_step": total / steps * 1e3,
+        "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "open TFIM chain L=20 = 10 + 10 leaves, J=1, g=0.7, k=8, one "
+                               "rmc_merge_bound per step", "checked_ok": ok, "last": d},
+        "roofline": {"bound": "hbm", "kernel": "pauli_batched_kernel", "achieved": gbs,
+                     "peak": HBM_GBS, "unit": "GB/s", "frac": gbs / HBM_GBS, "traffic": None,
+                     "launches": pr["launches"],
+                     "avg_launch_us": pr["ms"] * 1e3 / max(1, pr["launches"]),
+                     "bytes_per_launch": pr["bytes"] / max(1, pr["launches"]),
+                     "ms_per_step": pr["ms"] / steps},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out))
     ctx.close()

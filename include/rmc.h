@@ -289,6 +289,21 @@ rmc_status rmc_profile_read(rmc_ctx* ctx, long long* launches, double* flops, do
  * continues in FP64, so a run mixes launches of several precisions. */
 rmc_status rmc_profile_read_precision(rmc_ctx* ctx, int precision, long long* launches,
                                       double* flops, double* bytes, double* ms);
+/* Kernels whose launches are recorded while profiling is on:
+ *   RMC_PROF_KRON_STEP   one Kronecker matvec step (streaming or tiled kernel), the
+ *                        Rayleigh-Ritz applies and the per-step filter path;
+ *   RMC_PROF_KRON_FILTER the whole-filter launch (every vector through all Chebyshev
+ *                        steps: flops as above per vector and step; bytes 8 n per vector
+ *                        for the defect, the Ritz block and the output, plus E_A + E_B
+ *                        and the operators once per problem);
+ *   RMC_PROF_PAULI       the full-space Pauli-sum apply of rmc_merge_bound (bytes 8 per
+ *                        amplitude for each input vector read and the output written;
+ *                        flops 2 per term and amplitude; precision FP64).
+ * rmc_profile_read and rmc_profile_read_precision sum the two Kronecker kinds. */
+typedef enum { RMC_PROF_KRON_STEP = 0, RMC_PROF_KRON_FILTER = 1, RMC_PROF_PAULI = 2 } rmc_profile_kernel;
+/* The totals of one kernel kind and precision. */
+rmc_status rmc_profile_read_kernel(rmc_ctx* ctx, int kernel, int precision, long long* launches,
+                                   double* flops, double* bytes, double* ms);
 
 #ifdef __cplusplus
 }

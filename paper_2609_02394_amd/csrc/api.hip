@@ -1247,6 +1247,9 @@ void merge_bound(rmc_ctx* ctx, rmc_module* A, const rmc_leaf_desc* la, rmc_modul
     st2[0] = sa[i], op2[0] = oa[i], st2[1] = nA + sb[i], op2[1] = ob[i];
     ft.push_back(full_term(bond->coef[i], L, 2, st2.data(), op2.data()));
   }
+  // grouped by flip mask, diagonal terms first: the apply kernel gathers once per group
+  std::stable_sort(ft.begin(), ft.end(),
+                   [](const FullTerm& x, const FullTerm& y) { return x.flip < y.flip; });
   double sigma = 0.0;
   for (auto& t : ft) sigma += std::fabs(t.coef);
   sigma = std::max(sigma, 1e-300);
@@ -1327,10 +1330,11 @@ rmc_status rmc_profile(rmc_ctx* ctx, int enable) {
     }
     ctx->prof_recs.clear();
     if (enable) {
-      for (int p = 0; p < 3; ++p) {
-        ctx->prof_launches[p] = 0;
-        ctx->prof_flops[p] = ctx->prof_bytes[p] = ctx->prof_ms[p] = 0.0;
-      }
+      for (int k = 0; k < 3; ++k)
+        for (int p = 0; p < 3; ++p) {
+          ctx->prof_launches[k][p] = 0;
+          ctx->prof_flops[k][p] = ctx->prof_bytes[k][p] = ctx->prof_ms[k][p] = 0.0;
+        }
     }
     ctx->prof = enable != 0;
   });
@@ -1342,10 +1346,10 @@ void profile_collect(rmc_ctx* ctx) {
   for (auto& r : ctx->prof_recs) {
     float t = 0.f;
     RMC_HIP(hipEventElapsedTime(&t, r.a, r.b));
-    ctx->prof_ms[r.prec] += t;
-    ctx->prof_flops[r.prec] += r.flops;
-    ctx->prof_bytes[r.prec] += r.bytes;
-    ctx->prof_launches[r.prec] += 1;
+    ctx->prof_ms[r.kind][r.prec] += t;
+    ctx->prof_flops[r.kind][r.prec] += r.flops;
+    ctx->prof_bytes[r.kind][r.prec] += r.bytes;
+    ctx->prof_launches[r.kind][r.prec] += 1;
     ctx->ev_pool.push_back(r.a);
     ctx->ev_pool.push_back(r.b);
   }
@@ -1360,12 +1364,13 @@ rmc_status rmc_profile_read(rmc_ctx* ctx, long long* launches, double* flops, do
     profile_collect(ctx);
     long long n = 0;
     double f = 0.0, b = 0.0, t = 0.0;
-    for (int p = 0; p < 3; ++p) {
-      n += ctx->prof_launches[p];
-      f += ctx->prof_flops[p];
-      b += ctx->prof_bytes[p];
-      t += ctx->prof_ms[p];
-    }
+    for (int k = RMC_PROF_KRON_STEP; k <= RMC_PROF_KRON_FILTER; ++k)
+      for (int p = 0; p < 3; ++p) {
+        n += ctx->prof_launches[k][p];
+        f += ctx->prof_flops[k][p];
+        b += ctx->prof_bytes[k][p];
+        t += ctx->prof_ms[k][p];
+      }
     if (launches) *launches = n;
     if (flops) *flops = f;
     if (bytes) *bytes = b;
@@ -1378,10 +1383,25 @@ rmc_status rmc_profile_read_precision(rmc_ctx* ctx, int precision, long long* la
   if (!ctx || precision < RMC_FP64 || precision > RMC_BF16) return RMC_ERR_ARG;
   return guard(ctx, [&] {
     profile_collect(ctx);
-    if (launches) *launches = ctx->prof_launches[precision];
-    if (flops) *flops = ctx->prof_flops[precision];
-    if (bytes) *bytes = ctx->prof_bytes[precision];
-    if (ms) *ms = ctx->prof_ms[precision];
+    const int k0 = RMC_PROF_KRON_STEP, k1 = RMC_PROF_KRON_FILTER;
+    if (launches) *launches = ctx->prof_launches[k0][precision] + ctx->prof_launches[k1][precision];
+    if (flops) *flops = ctx->prof_flops[k0][precision] + ctx->prof_flops[k1][precision];
+    if (bytes) *bytes = ctx->prof_bytes[k0][precision] + ctx->prof_bytes[k1][precision];
+    if (ms) *ms = ctx->prof_ms[k0][precision] + ctx->prof_ms[k1][precision];
+  });
+}
+
+rmc_status rmc_profile_read_kernel(rmc_ctx* ctx, int kernel, int precision, long long* launches,
+                                   double* flops, double* bytes, double* ms) {
+  if (!ctx || precision < RMC_FP64 || precision > RMC_BF16 || kernel < RMC_PROF_KRON_STEP ||
+      kernel > RMC_PROF_PAULI)
+    return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    profile_collect(ctx);
+    if (launches) *launches = ctx->prof_launches[kernel][precision];
+    if (flops) *flops = ctx->prof_flops[kernel][precision];
+    if (bytes) *bytes = ctx->prof_bytes[kernel][precision];
+    if (ms) *ms = ctx->prof_ms[kernel][precision];
   });
 }
 

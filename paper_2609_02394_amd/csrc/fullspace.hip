@@ -32,12 +32,18 @@ __global__ __launch_bounds__(256) void pauli_batched_kernel(const PauliDesc* __r
     const unsigned r = (unsigned)(e & mask);
     const double* y = d.Y + base;
     const double* u = d.sub ? d.sub + base : nullptr;
-    double acc = 0.0;
+    // terms arrive grouped by flip mask (all diagonal terms first): one gather serves
+    // every term of a group
+    double acc = 0.0, v = 0.0;
+    unsigned last = ~0u;
     for (int t = 0; t < d.n_terms; ++t) {
       const FullTerm tm = d.terms[t];
-      const unsigned c = r ^ tm.flip;
-      double v = y[c];
-      if (u) v -= u[c];
+      if (tm.flip != last) {
+        const unsigned c = r ^ tm.flip;
+        v = y[c];
+        if (u) v -= u[c];
+        last = tm.flip;
+      }
       acc += tm.coef * term_sign(r, tm.zm, tm.tm) * v;
     }
     double o = d.s1 * acc;

@@ -653,13 +653,14 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_
           if (row < kA && col < kB) {
             const long idx = (long)row * kB + col;
             const double y = Yj[idx];
-            double o = s1 * ((double)acc[c][r] + Ed[idx] * y) + s2 * y;
+            // explicit fused multiply-adds: the fused filter kernel rounds the same way
+            double o = fma(s1, fma(Ed[idx], y, (double)acc[c][r]), s2 * y);
             if constexpr (EPF) {
-              if (Xp) o += s3 * exq[c][r];
-              if (Ej) o += ph * eeq[c][r];
+              if (Xp) o = fma(s3, exq[c][r], o);
+              if (Ej) o = fma(ph, eeq[c][r], o);
             } else {
-              if (Xp) o += s3 * Xp[idx];
-              if (Ej) o += ph * Ej[idx];
+              if (Xp) o = fma(s3, Xp[idx], o);
+              if (Ej) o = fma(ph, Ej[idx], o);
             }
             oj[idx] = o;
           }
@@ -743,11 +744,15 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16)) void kron_filter_kernel
     const long n = (long)kA * kB;
     if (loaded != p) {
       __syncthreads();  // every wave is done with the previous operators
+      // the pack's tiles are pkm x pkm (the problem's own padded size, <= KM): rows and
+      // columns past pkm are staged as zeros
       gptr<lt> pk = gview(static_cast<const lt*>(d->pack));
+      const int pkm = d->pkm;
       for (int q = tid; q < 2 * T * (KM * KM / 4); q += NT) {
         const int tile = q / (KM * KM / 4), rem = q - tile * (KM * KM / 4);
         const int r = rem / (KM / 4), cc = (rem % (KM / 4)) * 4;
-        const gv x = *reinterpret_cast<gptr<gv>>(pk + (long)tile * KM * KM + r * KM + cc);
+        gv x = gv{0, 0, 0, 0};
+        if (r < pkm && cc < pkm) x = *reinterpret_cast<gptr<gv>>(pk + (long)tile * pkm * pkm + r * pkm + cc);
         lt* o = Ops + tile * TILE + r * PW + cc;
         if constexpr (P == 0) {
           *reinterpret_cast<double2*>(o) = double2{x[0], x[1]};
@@ -814,9 +819,9 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16)) void kron_filter_kernel
       // the per-step kernel's epilogue, on the register-resident iterates
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        double o = s1 * ((double)acc[r] + Ed[r] * Dc[r]) + s2 * Dc[r];
-        o += s3 * Dp[r];
-        o += ph * Ev[r];
+        double o = fma(s1, fma(Ed[r], Dc[r], (double)acc[r]), s2 * Dc[r]);
+        if (k > 1) o = fma(s3, Dp[r], o);  // the first step has no previous iterate
+        o = fma(ph, Ev[r], o);
         Dp[r] = Dc[r];
         Dc[r] = idx[r] >= 0 ? o : 0.0;
       }
@@ -831,7 +836,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16)) void kron_filter_kernel
     gptr_w<double> oj = gview_w(d->out) + (long)j * n;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      if (idx[r] >= 0) oj[idx[r]] = phP * Xj[idx[r]] + Dc[r];
+      if (idx[r] >= 0) oj[idx[r]] = __dadd_rn(__dmul_rn(phP, Xj[idx[r]]), Dc[r]);  // as the scale-add kernel
     ++j;
   }
 }

@@ -179,7 +179,8 @@ struct FullTerm {
   unsigned flip, zm, tm, pad;
 };
 // out = s1 H (Y - sub) + s2 Y0 + s3 Xprev for nv vectors of 2^n_sites (sub, Y0, Xprev
-// nullable), H = sum of the terms.
+// nullable), H = sum of the terms; terms with equal flip masks must be consecutive
+// (they share one gather).
 struct PauliDesc {
   int n_sites, n_terms, nv, pad;
   const FullTerm* terms;

@@ -102,13 +102,14 @@ struct rmc_ctx {
     hipEvent_t a, b;
     double flops, bytes;
     int prec;
+    int kind = 0;  // rmc_profile_kernel
   };
   std::vector<ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
   std::mutex prof_mu;  // guards prof_recs and ev_pool against the solver's second lane
-  // totals per precision of the Kronecker launches (index: rmc_precision)
-  long long prof_launches[3] = {0, 0, 0};
-  double prof_flops[3] = {0, 0, 0}, prof_bytes[3] = {0, 0, 0}, prof_ms[3] = {0, 0, 0};
+  // totals per kernel (rmc_profile_kernel) and precision (rmc_precision)
+  long long prof_launches[3][3] = {};
+  double prof_flops[3][3] = {}, prof_bytes[3][3] = {}, prof_ms[3][3] = {};
   // pinned host staging of the batched solver's descriptor tables, one per lane
   char* pinned[2] = {nullptr, nullptr};
   size_t pinned_cap[2] = {0, 0};

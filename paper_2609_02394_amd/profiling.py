@@ -74,9 +74,14 @@ def _per_dispatch(rows, counter: str):
     return acc
 
 
-def _kron_prec(name: str):
-    m = re.search(r"kron_(?:stream|batched)_kernel<(\d)", name)
-    return PREC_NAMES.get(m.group(1)) if m else None
+def _kron_key(name: str):
+    """'kron_stream_kernel:fp32' style key of a Kronecker launch (the tiled kernel is
+    counted with the streaming one: both are the one-step matvec)."""
+    m = re.search(r"kron_(stream|batched|filter)_kernel<(\d)", name)
+    if not m:
+        return None
+    kind = "kron_filter_kernel" if m.group(1) == "filter" else "kron_stream_kernel"
+    return f"{kind}:{PREC_NAMES.get(m.group(2))}"
 
 
 def traffic(fetch_dir: str, write_dir: str):
@@ -88,7 +93,7 @@ def traffic(fetch_dir: str, write_dir: str):
         scale = (COPY_BYTES / 1024.0) / big if big > 0 else None
         per = defaultdict(list)
         for n, v in disp.values():
-            p = _kron_prec(n)
+            p = _kron_key(n)
             if p:
                 per[p].append(v)
         res[counter] = {"scale": scale, "copy_kib": big,
@@ -109,13 +114,13 @@ def traffic(fetch_dir: str, write_dir: str):
 
 
 def traffic_md(t: dict, fetch_cmd: str, write_cmd: str) -> str:
-    lines = ["# HBM traffic of the Kronecker matvec (rocprofv3 counters)", "",
+    lines = ["# HBM traffic of the Kronecker kernels (rocprofv3 counters)", "",
              "FETCH_SIZE and WRITE_SIZE per dispatch (KiB), averaged over the Kronecker "
              "launches of each precision, each scaled by the reading of the same counter for "
              f"a plain {COPY_BYTES >> 20} MiB device copy in the same run.", "",
              f"kron.hip sha256[:16] = `{t['kron_source_sha']}`", "",
              f"Scale factors: FETCH x{t['fetch_scale']:.3f}, WRITE x{t['write_scale']:.3f}", "",
-             "| precision | launches | FETCH KiB avg | WRITE KiB avg | HBM bytes / launch |",
+             "| kernel:precision | launches | FETCH KiB avg | WRITE KiB avg | HBM bytes / launch |",
              "|---|---|---|---|---|"]
     for p, b in sorted(t["bytes_per_launch"].items()):
         lines.append(f"| {p} | {t['dispatches'].get(p, 0)} | {t['fetch_kib_avg'][p]:.1f} | "

@@ -28,7 +28,9 @@ EXPORTED = (
     "rmc_leaf_hamiltonian", "rmc_kron_apply", "rmc_sym_eig", "rmc_module_import",
     "rmc_profile", "rmc_profile_read", "rmc_profile_read_precision",
     "rmc_serve_start", "rmc_submit", "rmc_poll", "rmc_serve_stop", "rmc_merge_bound",
+    "rmc_profile_read_kernel",
 )
+PROF_KRON_STEP, PROF_KRON_FILTER, PROF_PAULI = 0, 1, 2
 
 
 class Term(C.Structure):
@@ -99,6 +101,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "rmc_profile": (i, [vp, i]),
         "rmc_profile_read": (i, [vp, P(C.c_longlong), P(d), P(d), P(d)]),
         "rmc_profile_read_precision": (i, [vp, i, P(C.c_longlong), P(d), P(d), P(d)]),
+        "rmc_profile_read_kernel": (i, [vp, i, i, P(C.c_longlong), P(d), P(d), P(d)]),
         "rmc_serve_start": (i, [vp, P(SolveOpts), i, sz]),
         "rmc_submit": (i, [vp, P(ChainDesc), P(C.c_ulonglong)]),
         "rmc_poll": (i, [vp, C.c_ulonglong, P(i), P(d), P(i), P(d)]),
@@ -247,11 +250,16 @@ class Context:
     def profile(self, enable: bool):
         self._check(lib().rmc_profile(self.h, int(bool(enable))))
 
-    def profile_read(self, precision: Optional[int] = None):
-        """Kronecker-launch totals since profile(True): all launches, or those of one
-        precision (FP64 / FP32 / BF16)."""
+    def profile_read(self, precision: Optional[int] = None, kernel: Optional[int] = None):
+        """Launch totals since profile(True): all Kronecker launches, those of one
+        precision (FP64 / FP32 / BF16), or those of one kernel kind (PROF_KRON_STEP,
+        PROF_KRON_FILTER, PROF_PAULI) and precision."""
         n, f, b, ms = C.c_longlong(), C.c_double(), C.c_double(), C.c_double()
-        if precision is None:
+        if kernel is not None:
+            self._check(lib().rmc_profile_read_kernel(self.h, int(kernel), int(precision or 0),
+                                                      C.byref(n), C.byref(f), C.byref(b),
+                                                      C.byref(ms)))
+        elif precision is None:
             self._check(lib().rmc_profile_read(self.h, C.byref(n), C.byref(f), C.byref(b),
                                                C.byref(ms)))
         else:

@@ -442,38 +442,68 @@ FUSED_CASES = [
 ]
 
 
+def _run_both_filter_paths(ctx, run):
+    """run() once with the fused filter and once with the per-step launches, the
+    per-step Kronecker kernel pinned to the streaming variant (the fused kernel's
+    arithmetic in the same order, up to last-bit rounding): returns
+    {flag: (result, Kronecker flops)}. The flop totals follow the iteration histories
+    (filter degrees, locked rows); last-bit differences can flip a locking decision, so
+    they are compared within 3%."""
+    out = {}
+    for flag in ("1", "0"):
+        os.environ["RMC_FUSED_FILTER"] = flag
+        os.environ["RMC_KRON_VARIANT"] = "10"
+        try:
+            ctx.profile(True)
+            r = run()
+            flops = ctx.profile_read()["flops"]
+            ctx.profile(False)
+        finally:
+            os.environ.pop("RMC_FUSED_FILTER", None)
+            os.environ.pop("RMC_KRON_VARIANT", None)
+        out[flag] = (r, flops)
+    return out
+
+
 @pytest.mark.parametrize("name,job,precs", FUSED_CASES, ids=[c[0] for c in FUSED_CASES])
 def test_fused_filter_equals_per_step_filter(ctx, name, job, precs):
     """The whole-filter launch (every vector through all of its Chebyshev steps in one
     workgroup) against the per-step launches: the same arithmetic in the same order,
-    so the energies agree to rounding noise, and both match FP64 to 1e-8."""
+    so the iteration histories match (Kronecker flop totals within 3%), the energies
+    agree to rounding noise, and both match FP64 to 1e-8."""
     from paper_2609_02394_amd import rmc
 
     e64, _ = ctx.recurse(*rmc.job_chain(job))
     for prec in precs:
         say("fused filter", name, prec)
-        out = {}
-        for flag in ("1", "0"):
-            os.environ["RMC_FUSED_FILTER"] = flag
-            try:
-                out[flag], _ = ctx.recurse(*rmc.job_chain(job), opts=rmc.default_opts(precision=prec))
-            finally:
-                os.environ.pop("RMC_FUSED_FILTER", None)
-        assert rel_err(out["1"], out["0"]) <= 1e-13, (prec, out)
-        assert rel_err(out["1"], e64) <= 1e-8, (prec, out["1"], e64)
+        opts = rmc.default_opts(precision=prec)
+        out = _run_both_filter_paths(ctx, lambda: ctx.recurse(*rmc.job_chain(job), opts=opts)[0])
+        assert abs(out["1"][1] - out["0"][1]) <= 0.03 * out["0"][1], (prec, out["1"][1], out["0"][1])
+        assert rel_err(out["1"][0], out["0"][0]) <= 1e-13, (prec, out)
+        assert rel_err(out["1"][0], e64) <= 1e-8, (prec, out["1"][0], e64)
 
 
-def test_fused_filter_batch_mixes_fused_and_per_step_problems(ctx):
-    """A batch whose levels hold problems the fused kernel takes (k <= 64) beside
-    problems it does not (k = 96): both paths in one filter call, against single jobs."""
+def test_fused_filter_batch_mixes_sizes_and_paths(ctx):
+    """Batches whose levels mix problem sizes: k = 32 beside k = 64 in one fused launch
+    (the smaller problem's operator tiles are padded inside the larger tile), and k = 96
+    (per-step path) in the same filter call. The iteration histories of the per-step
+    path (flops within 3%), and the energies of single jobs and of the oracle."""
     from paper_2609_02394_amd import rmc
 
     say("fused filter mixed batch")
     jobs = [W.ChainJob("rfheis", 32, 8, k, 6, J=1.0, fields=W.rfheis_batch(4)[i].fields)
-            for i, k in enumerate((32, 96, 64, 96))]
+            for i, k in enumerate((32, 96, 64, 32))]
     opts = rmc.default_opts(precision=1)
-    E, sts, st = ctx.recurse_batch([rmc.job_chain(j) for j in jobs], opts=opts)
-    assert st == 0 and all(x == 0 for x in sts), sts
+
+    def run():
+        E, sts, st = ctx.recurse_batch([rmc.job_chain(j) for j in jobs], opts=opts)
+        assert st == 0 and all(x == 0 for x in sts), sts
+        return E
+
+    out = _run_both_filter_paths(ctx, run)
+    assert abs(out["1"][1] - out["0"][1]) <= 0.03 * out["0"][1], (out["1"][1], out["0"][1])
+    E = out["1"][0]
+    assert rel_err(E, out["0"][0]) <= 1e-13
     for i, j in enumerate(jobs):
         e1, _ = ctx.recurse(*rmc.job_chain(j), opts=opts)
         ref = OR.recurse(j)
