@@ -31,7 +31,8 @@ def kron_source_hash() -> str:
 
 
 def _short(name: str) -> str:
-    name = re.sub(r"\(.*\)$", "", name.strip())
+    name = name.strip().replace("(anonymous namespace)::", "")
+    name = re.sub(r"\(.*\)$", "", name)
     return name.replace("void ", "")
 
 
