@@ -850,10 +850,11 @@ rmc_status rmc_destroy(rmc_ctx* ctx) {
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   for (char* h : ctx->pinned)
     if (h) hipHostFree(h);
-  if (ctx->lane_stream) {
-    hipStreamSynchronize(ctx->lane_stream);
-    hipStreamDestroy(ctx->lane_stream);
-  }
+  for (hipStream_t ls : ctx->lane_stream)
+    if (ls) {
+      hipStreamSynchronize(ls);
+      hipStreamDestroy(ls);
+    }
   for (hipEvent_t e : ctx->lane_ev)
     if (e) hipEventDestroy(e);
   if (ctx->own_arena && ctx->arena_mem) hipFree(ctx->arena_mem);

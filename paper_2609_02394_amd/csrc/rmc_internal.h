@@ -111,12 +111,14 @@ struct rmc_ctx {
   long long prof_launches[3][3] = {};
   double prof_flops[3][3] = {}, prof_bytes[3][3] = {}, prof_ms[3][3] = {};
   // pinned host staging of the batched solver's descriptor tables, one per lane
-  char* pinned[2] = {nullptr, nullptr};
-  size_t pinned_cap[2] = {0, 0};
-  // the batched solver's second lane: a library-owned stream (default priority) and
-  // the events that order it against `stream`
-  hipStream_t lane_stream = nullptr;
-  hipEvent_t lane_ev[2] = {nullptr, nullptr};
+  static constexpr int kMaxLanes = 4;
+  char* pinned[kMaxLanes] = {};
+  size_t pinned_cap[kMaxLanes] = {};
+  // the batched solver's extra lanes: library-owned streams (default priority) and
+  // the events that order them against `stream` (lane_ev[0]: fork; lane_ev[l]: join of
+  // lane l)
+  hipStream_t lane_stream[kMaxLanes] = {};  // [0] unused: lane 0 runs on `stream`
+  hipEvent_t lane_ev[kMaxLanes] = {};
   // serving: scheduler state (owned by recurse.hip); other calls are refused while set
   void* serve = nullptr;
   bool serving = false;

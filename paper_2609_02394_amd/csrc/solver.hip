@@ -1108,8 +1108,9 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
         act.push_back(p);
         ai.push_back(i);
         if (trace)
-          fprintf(stderr, "[rmc] n=%d it=%d prec=%d deg=%d nlock=%d worst=%.3e expect=%.3e\n", p->n,
-                  p->iters, p->prec, p->deg, p->nlock, p->prev_worst, p->prev_expect);
+          fprintf(stderr, "[rmc] n=%d it=%d prec=%d deg=%d nlock=%d worst=%.3e expect=%.3e sweeps=%d\n",
+                  p->n, p->iters, p->prec, p->deg, p->nlock, p->prev_worst, p->prev_expect,
+                  p->rr_sweeps);
       }
     }
     if (act.empty()) break;
@@ -1153,59 +1154,69 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
   }
 }
 
-// Solver lanes (RMC_LANES = 1 or 2, default 2). With two, a batch of at least eight
-// problems is split into two halves that run the same lockstep iteration on two
-// streams from two host threads: the Rayleigh-Ritz, Cholesky and Gram kernels of one
-// half (one or a few workgroups per problem, far fewer than the chip holds) then run
-// beside the other half's Kronecker filter, and each half's host-side bookkeeping
-// overlaps the other's device work. The halves share nothing but the arena and the
-// profiling records, both locked.
+// Solver lanes (RMC_LANES = 1..4, default 2). With L > 1, a batch of at least 4 L
+// problems is split into L parts that run the same lockstep iteration on L streams
+// from L host threads: the Rayleigh-Ritz, Cholesky and Gram kernels of one part (one
+// or a few workgroups per problem, far fewer than the chip holds) then run beside the
+// other parts' Kronecker filters, and each part's host-side bookkeeping overlaps the
+// others' device work. The parts share nothing but the arena and the profiling
+// records, both locked.
 int solver_lanes() {
   static const int n = [] {
     const char* e = getenv("RMC_LANES");
-    return (e && atoi(e) == 1) ? 1 : 2;
+    const int v = e ? atoi(e) : 2;
+    return std::max(1, std::min(v, (int)rmc_ctx::kMaxLanes));
   }();
   return n;
 }
 
 void run_attempt(rmc_ctx* ctx, std::vector<BP*>& L, const rmc_solve_opts& o, bool last) {
-  constexpr size_t kMinSplit = 8;
-  if (solver_lanes() < 2 || L.size() < kMinSplit) {
+  int nl = solver_lanes();
+  while (nl > 1 && L.size() < (size_t)(4 * nl)) --nl;
+  if (nl < 2) {
     solve_attempt(ctx, L, o, last, ctx->stream, 0);
     return;
   }
-  if (!ctx->lane_stream) {
-    RMC_HIP(hipStreamCreateWithFlags(&ctx->lane_stream, hipStreamNonBlocking));
-    for (auto& e : ctx->lane_ev) RMC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  }
-  // deal the problems out by size so both halves carry a similar load
-  std::vector<BP*> srt(L), half[2];
+  if (!ctx->lane_ev[0]) RMC_HIP(hipEventCreateWithFlags(&ctx->lane_ev[0], hipEventDisableTiming));
+  for (int l = 1; l < nl; ++l)
+    if (!ctx->lane_stream[l]) {
+      RMC_HIP(hipStreamCreateWithFlags(&ctx->lane_stream[l], hipStreamNonBlocking));
+      RMC_HIP(hipEventCreateWithFlags(&ctx->lane_ev[l], hipEventDisableTiming));
+    }
+  // deal the problems out by size so every part carries a similar load
+  std::vector<BP*> srt(L);
+  std::vector<std::vector<BP*>> part(nl);
   std::stable_sort(srt.begin(), srt.end(), [](const BP* a, const BP* b) {
     return (long)a->n * (a->nev + a->guard) > (long)b->n * (b->nev + b->guard);
   });
-  for (size_t i = 0; i < srt.size(); ++i) half[i % 2].push_back(srt[i]);
-  // lane 1 starts once everything queued on the ctx stream so far has run
+  for (size_t i = 0; i < srt.size(); ++i) part[i % nl].push_back(srt[i]);
+  // the extra lanes start once everything queued on the ctx stream so far has run
   RMC_HIP(hipEventRecord(ctx->lane_ev[0], ctx->stream));
-  RMC_HIP(hipStreamWaitEvent(ctx->lane_stream, ctx->lane_ev[0], 0));
-  std::exception_ptr err[2];
-  std::thread t([&] {
-    try {
-      RMC_HIP(hipSetDevice(ctx->device));
-      solve_attempt(ctx, half[1], o, last, ctx->lane_stream, 1);
-    } catch (...) {
-      err[1] = std::current_exception();
-    }
-  });
+  for (int l = 1; l < nl; ++l) RMC_HIP(hipStreamWaitEvent(ctx->lane_stream[l], ctx->lane_ev[0], 0));
+  std::vector<std::exception_ptr> err(nl);
+  std::vector<std::thread> th;
+  for (int l = 1; l < nl; ++l)
+    th.emplace_back([&, l] {
+      try {
+        RMC_HIP(hipSetDevice(ctx->device));
+        solve_attempt(ctx, part[l], o, last, ctx->lane_stream[l], l);
+      } catch (...) {
+        err[l] = std::current_exception();
+      }
+    });
   try {
-    solve_attempt(ctx, half[0], o, last, ctx->stream, 0);
+    solve_attempt(ctx, part[0], o, last, ctx->stream, 0);
   } catch (...) {
     err[0] = std::current_exception();
   }
-  t.join();
-  // later work on the ctx stream runs after lane 1 (each lane has already drained its
-  // stream before returning; this keeps the order explicit)
-  hipError_t e = hipEventRecord(ctx->lane_ev[1], ctx->lane_stream);
-  if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ctx->lane_ev[1], 0);
+  for (auto& t : th) t.join();
+  // later work on the ctx stream runs after every lane (each lane has already drained
+  // its stream before returning; this keeps the order explicit)
+  hipError_t e = hipSuccess;
+  for (int l = 1; l < nl && e == hipSuccess; ++l) {
+    e = hipEventRecord(ctx->lane_ev[l], ctx->lane_stream[l]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ctx->lane_ev[l], 0);
+  }
   for (auto& x : err)
     if (x) std::rethrow_exception(x);
   RMC_HIP(e);
