@@ -950,7 +950,11 @@ static int stream_grid(const void* k, int threads, size_t lds, long V) {
     const int cap = atoi(f);
     if (cap >= 8) n = std::min(n, cap);
   }
-  const long g = std::min<long>(n, V);
+  // as few workgroups as give the same makespan: every workgroup walks
+  // ceil(V / n) vectors at most, so ceil(V / that) workgroups suffice and the CUs
+  // left over take other streams' work (the solver's other lanes)
+  const long per = (V + n - 1) / n;
+  const long g = std::min<long>(n, (V + per - 1) / per);
   return (int)(((g + 7) / 8) * 8);
 }
 

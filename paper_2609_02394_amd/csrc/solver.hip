@@ -743,7 +743,11 @@ bool update_problem(Batch& B, BP* p, int idx, int max_iter, double tol, int pmax
   // FP32 filters above degree ~24 stall at a noise floor on these spectra (rounding
   // noise grows with the spread of T_deg over the wanted set); BF16 is held lower by
   // its reduction target above
-  if (p->prec == RMC_FP32) deg = std::min(deg, 24);
+  static const int fp32_cap = [] {
+    const char* e = getenv("RMC_FP32_MAXDEG");
+    return e ? std::max(2, atoi(e)) : 24;
+  }();
+  if (p->prec == RMC_FP32) deg = std::min(deg, fp32_cap);
   p->deg = std::min(std::max(deg, 2), pmax);
   // damping 1 / T_deg(x) of the slowest active wanted vector
   double expect = 0.0;
