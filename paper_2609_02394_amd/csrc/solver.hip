@@ -471,6 +471,21 @@ int info_of(const Batch& B, int idx, int k) {
   return ip[k];
 }
 
+// Sum of the Gram's split-K partials (cnt x cnt each, in p->kwork) into p->Pm with one
+// chip-wide launch, so that the one-workgroup Cholesky and Jacobi kernels read a single
+// matrix instead of every partial; returns null when there is one partial only.
+const double* reduce_parts(Batch& B, const std::vector<BP*>& L) {
+  if (B.KS <= 1 || L.empty()) return nullptr;
+  std::vector<VecDesc> rd;
+  for (BP* p : L) {
+    VecDesc v{};
+    v.nv = B.KS; v.n = p->cnt * p->cnt; v.out = p->Pm; v.P = p->kwork;
+    rd.push_back(v);
+  }
+  vec_launch(B, VEC_REDUCE, rd);
+  return L[0]->Pm;  // non-null marker: every problem's sum is in its own Pm
+}
+
 // One CholeskyQR pass from role src to role dst for the problems of L.
 void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst) {
   const double u = 1.1102230246251565e-16;
@@ -481,11 +496,12 @@ void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst) {
     ca.push_back(p->cnt);
   }
   gram_launch(B, L, A, A, ca, ca);
+  const double* G = reduce_parts(B, L);
   std::vector<CholDesc> cd;
   int mm = 0;
   for (BP* p : L) {
     CholDesc c{};
-    c.m = p->cnt; c.nparts = B.KS; c.G = p->kwork; c.pstride = (long)p->cnt * p->cnt;
+    c.m = p->cnt; c.nparts = G ? 1 : B.KS; c.G = G ? p->Pm : p->kwork; c.pstride = (long)p->cnt * p->cnt;
     c.Linv = p->Linv; c.info = p->info + 2;  // info[2]: failure, info[3]: shifted
     c.shift = 11.0 * ((double)p->n * p->cnt + (double)p->cnt * (p->cnt + 1)) * u * p->cnt;
     cd.push_back(c);
@@ -608,11 +624,12 @@ void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full)
     cnt.push_back(p->cnt);
   }
   gram_launch(B, L, A, Bm, cnt, cnt);
+  const double* G = reduce_parts(B, L);
   std::vector<EigDesc> ed;
   int mm = 0;
   for (BP* p : L) {
     EigDesc d{};
-    d.m = p->cnt; d.nparts = B.KS; d.A = p->kwork; d.pstride = (long)p->cnt * p->cnt;
+    d.m = p->cnt; d.nparts = G ? 1 : B.KS; d.A = G ? p->Pm : p->kwork; d.pstride = (long)p->cnt * p->cnt;
     d.evals = p->theta + (full ? 0 : p->nlock); d.V = p->S; d.Vwork = p->Vwork; d.info = p->info + 1;
     ed.push_back(d);
     mm = std::max(mm, p->cnt);
