@@ -700,34 +700,32 @@ __device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, lo
   const double eps = 2.220446049250313e-16, eps2 = eps * eps;
   const double floor_abs = eps * fro;
   const int npair = H * (H + 1) / 2;  // blocks (k, l), k <= l
-  const long nvv = (long)m * H;
 
-  // (row, rotation) of this thread's first V item and the stride, without divisions
-  // in the loop
-  const int vk0 = tid % H, vr0 = tid / H, vdk = nt % H, vdr = nt / H;
+  // V update: thread (k, g) applies rotation k to the rows g, g + VG, g + 2 VG, ...
+  // (VG row groups), so each thread reads its rotation's table entries once per round
+  const int VG = nt / H;
+  const int vk = tid % H, vg = tid / H;
   auto apply_v = [&](int b) {
-    const double* c_ = cs + b * H;
-    const double* s_ = sn + b * H;
-    const int* p_ = pp + b * H;
-    const int* q_ = qq + b * H;
-    const int* a_ = act + b * H;
-    int k = vk0, r = vr0;
-    for (long t = tid; t < nvv; t += nt) {
-      if (a_[k]) {
-        const int p = p_[k], q = q_[k];
-        const double c = c_[k], s = s_[k];
-        const double vp = V[(long)r * m + p], vq = V[(long)r * m + q];
-        V[(long)r * m + p] = c * vp - s * vq;
-        V[(long)r * m + q] = s * vp + c * vq;
-      }
-      k += vdk;
-      r += vdr;
-      if (k >= H) {
-        k -= H;
-        ++r;
-      }
+    if (vg >= VG || !act[b * H + vk]) return;
+    const int p = pp[b * H + vk], q = qq[b * H + vk];
+    const double c = cs[b * H + vk], s = sn[b * H + vk];
+    for (int r = vg; r < m; r += VG) {
+      double* row = V + (long)r * m;
+      const double vp = row[p], vq = row[q];
+      row[p] = c * vp - s * vq;
+      row[q] = s * vp + c * vq;
     }
   };
+  // this thread's first 2x2 block (k, l), k <= l, of the A update (the same in every
+  // round); further blocks (m > 88) are decoded on the fly
+  int uk0 = 0, ul0 = 0;
+  if (tid < npair) {
+    int l = (int)((sqrtf(8.0f * tid + 1.0f) - 1.0f) * 0.5f);
+    while (l * (l + 1) / 2 > tid) --l;
+    while ((l + 1) * (l + 2) / 2 <= tid) ++l;
+    ul0 = l;
+    uk0 = tid - l * (l + 1) / 2;
+  }
 
   int sweeps = 0;
   bool converged = false;
@@ -783,10 +781,13 @@ __device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, lo
       const int* q_ = qq + b * H;
       const int* a_ = act + b * H;
       for (int w = tid; w < npair; w += nt) {
-        int l = (int)((sqrtf(8.0f * w + 1.0f) - 1.0f) * 0.5f);
-        while (l * (l + 1) / 2 > w) --l;
-        while ((l + 1) * (l + 2) / 2 <= w) ++l;
-        const int k = w - l * (l + 1) / 2;
+        int l = ul0, k = uk0;
+        if (w != tid) {
+          l = (int)((sqrtf(8.0f * w + 1.0f) - 1.0f) * 0.5f);
+          while (l * (l + 1) / 2 > w) --l;
+          while ((l + 1) * (l + 2) / 2 <= w) ++l;
+          k = w - l * (l + 1) / 2;
+        }
         if (!a_[k] && !a_[l]) continue;
         const int pk = p_[k], qk = q_[k];
         if (k == l) {
