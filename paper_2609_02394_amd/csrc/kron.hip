@@ -436,8 +436,14 @@ __device__ inline void mma_frag(typename SK<P>::acc& c, const typename SK<P>::lt
   }
 }
 
+// Two workgroups share a CU where their LDS fits (the SH forms up to KM = 96), else one.
+template <int P, int KM, bool SH>
+constexpr int sk_blocks_per_cu() {
+  return SH && 2 * 2 * KM * sk_pitch<P>(KM) * (int)sizeof(typename SK<P>::lt) <= 160 * 1024 ? 2 : 1;
+}
+
 template <int P, int KM, int NWC, bool SH>
-__global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_kernel(
+__global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>())) void kron_stream_kernel(
     const KronDesc* __restrict__ descs, int P_, long V, int G) {
   typedef typename SK<P>::lt lt;
   typedef typename SK<P>::acc accT;
@@ -450,8 +456,10 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_
   constexpr int NYE = KM / 4;             // Y elements per lane (NCH * KR)
   constexpr int NG = KM * KM / (4 * NT);  // 4-element staging groups per thread per matrix
   // epilogue prefetch where the registers allow it (the FP64 single-buffer forms and
-  // the widest tiles are at the register limit already)
+  // the widest tiles are at the register limit already); the next vector's rows are
+  // prefetched up to KM = 96 and loaded at the vector boundary beyond
   constexpr bool EPF = KM <= 64 && !(P == 0 && NWC == 1);
+  constexpr bool YPF = KM <= 96;
   static_assert(RTM % NWC == 0 && NG * 4 * NT == KM * KM, "tile split");
   extern __shared__ char smem_raw[];
   lt* Bs = reinterpret_cast<lt*>(smem_raw);
@@ -510,7 +518,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_
       }
     }
   };
-  lt yf[NYE], yn[NYE];
+  lt yf[NYE], yn[YPF ? NYE : 1];
   auto load_y = [&](const KronDesc* e, int jj, lt* dst) {
     const int kA = e->kA, kB = e->kB;
     gptr<double> Y = gview(e->Y) + (long)jj * kA * kB;
@@ -557,7 +565,8 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_
     const KronDesc* nd = descs + np;
     if constexpr (SH) load_tile(d, t, true);  // this step's c O_A, stored after stage 1
     else if (has_next) load_tile(nd, nt, false);
-    if (has_next && nt == 0) load_y(nd, nj, yn);
+    if constexpr (YPF)
+      if (has_next && nt == 0) load_y(nd, nj, yn);
     if (t == 0) {
 #pragma unroll
       for (int c = 0; c < CPW; ++c) acc[c] = accT{0, 0, 0, 0};
@@ -676,8 +685,12 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, SH ? 2 : 1) void kron_stream_
       store_tile(As);
     }
     if (nt == 0) {
+      if constexpr (YPF) {
 #pragma unroll
-      for (int e = 0; e < NYE; ++e) yf[e] = yn[e];
+        for (int e = 0; e < NYE; ++e) yf[e] = yn[e];
+      } else {
+        load_y(nd, nj, yf);  // every wave is past its last read of yf (barrier above)
+      }
       ++v;
     }
     p = np;
@@ -901,16 +914,24 @@ static StreamKernel stream_kernel(int prec, int km, int nwc, bool sh = false) {
   if (km <= KM_)                                                                       \
     return nwc == 1 ? (sh ? kron_stream_kernel<P_, KM_, 1, true> : kron_stream_kernel<P_, KM_, 1, false>) \
                     : (sh ? kron_stream_kernel<P_, KM_, 2, true> : kron_stream_kernel<P_, KM_, 2, false>);
+  // the widest tiles fit in LDS only with one buffer for both operators (SH)
   if (prec == RMC_FP64) {
     RMC_SK(0, 32) RMC_SK(0, 64)
   } else if (prec == RMC_FP32) {
     RMC_SK(1, 32) RMC_SK(1, 64) RMC_SK(1, 96)
+    if (km <= 128) return (sh && nwc == 1) ? kron_stream_kernel<1, 128, 1, true> : nullptr;
   } else {
     RMC_SK(2, 32) RMC_SK(2, 64) RMC_SK(2, 96)
     if (km <= 128 && nwc == 1) return sh ? kron_stream_kernel<2, 128, 1, true> : kron_stream_kernel<2, 128, 1, false>;
   }
 #undef RMC_SK
   return nullptr;
+}
+
+// Some streaming kernel (either LDS form) takes tiles of this size and precision: the
+// operators are then packed for it.
+static bool has_stream(int prec, int km) {
+  return stream_kernel(prec, km, 1, false) != nullptr || stream_kernel(prec, km, 1, true) != nullptr;
 }
 
 static int stream_km(int km) { return km <= 32 ? 32 : (km <= 64 ? 64 : (km <= 96 ? 96 : 128)); }
@@ -981,7 +1002,7 @@ void kron_set_attrs() {
 
 bool kron_filter_fits(int precision, int kA, int kB, int T) {
   const int km = stream_km(std::max(kA, kB));
-  return filter_kernel(precision, km) != nullptr && stream_kernel(precision, km, 1) != nullptr &&
+  return filter_kernel(precision, km) != nullptr && has_stream(precision, km) &&
          filter_lds_bytes(precision, km, T) <= kFilterLdsMax;
 }
 
@@ -1069,7 +1090,7 @@ int kron_pack_km(int kA, int kB) { return stream_km(std::max(kA, kB)); }
 size_t kron_pack_bytes(int precision, int kA, int kB, int T) {
   if (T <= 0) return 0;
   const int km = kron_pack_km(kA, kB);
-  if (!stream_kernel(precision, km, 1)) return 0;
+  if (!has_stream(precision, km)) return 0;
   const size_t esz = precision == RMC_FP64 ? 8 : (precision == RMC_FP32 ? 4 : 2);
   return (size_t)T * 2 * km * km * esz;
 }

@@ -203,11 +203,13 @@ def kron_env():
 
 
 # every kernel variant of the Kronecker matvec (1, 2, 4: column sub-tiles of the
-# tiled kernel; 8, 9: streaming kernel), at the largest k each streaming form takes,
-# ragged shapes, no terms, and a capped grid so that workgroups walk many vectors
-@pytest.mark.parametrize("variant", [1, 2, 4, 8, 9])
+# tiled kernel; 8, 9: streaming kernel; 10, 11: streaming with one LDS buffer for both
+# operators), at the largest k each streaming form takes, ragged shapes, no terms, and
+# a capped grid so that workgroups walk many vectors
+@pytest.mark.parametrize("variant", [1, 2, 4, 8, 9, 10, 11])
 @pytest.mark.parametrize("prec,kA,kB,T,nv", [(0, 64, 64, 3, 7), (0, 33, 17, 2, 9), (0, 20, 20, 0, 3),
                                             (1, 96, 96, 3, 5), (1, 50, 70, 2, 6),
+                                            (1, 128, 128, 2, 5), (1, 100, 120, 3, 4),
                                             (2, 128, 128, 2, 4), (2, 90, 40, 3, 11)])
 @pytest.mark.parametrize("max_grid", [None, 8])
 def test_kron_apply_variants(ctx, kron_env, variant, prec, kA, kB, T, nv, max_grid):
