@@ -710,17 +710,19 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
 // stored transposed, double-buffered across terms) and stage 2 (acc += c O_A Z),
 // one barrier after each stage 1 and one after the new iterate is written.
 // The arithmetic is that of the per-step kernel in the same order.
-template <int P, int KM>
-__global__ __launch_bounds__(64 * (KM / 16) * (KM / 16)) void kron_filter_kernel(
+template <int P, int KM, int CPW>
+__global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_kernel(
     const FilterDesc* __restrict__ descs, int P_, long V, int G) {
   typedef typename SK<P>::lt lt;
   typedef typename SK<P>::acc accT;
   typedef typename Grp<P>::t gv;
   constexpr int RTM = KM / 16;
-  constexpr int NT = 64 * RTM * RTM;
+  constexpr int NWR = RTM / CPW;  // waves per row tile; wave (rt, cw) owns CPW column tiles
+  constexpr int NT = 64 * RTM * NWR;
   constexpr int PW = sk_pitch<P>(KM);
   constexpr int NCH = KM / SK<P>::CH;
   constexpr int TILE = KM * PW;
+  static_assert(RTM % CPW == 0, "column tiles per wave");
   extern __shared__ char smem_raw[];
   lt* Ys = reinterpret_cast<lt*>(smem_raw);
   lt* Zt0 = Ys + TILE;
@@ -732,8 +734,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16)) void kron_filter_kernel
   if (v0 >= v1) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  const int rt = wave / RTM, ct = wave % RTM;
-  const int col = ct * 16 + l16;
+  const int rt = wave / NWR, c0 = (wave % NWR) * CPW;
 
   int p = 0;
   {
@@ -778,69 +779,93 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16)) void kron_filter_kernel
     }
     gptr<double> Ej = gview(d->E) + (long)j * n;
     gptr<double> Edg = gview(d->Ediag);
-    double Dc[4], Dp[4], Ev[4], Ed[4];
-    int idx[4];
+    double Dc[CPW][4], Dp[CPW][4], Ev[CPW][4], Ed[CPW][4];
+    int idx[CPW][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = rt * 16 + acc_row<P>(g, r);
-      const bool in = row < kA && col < kB;
-      idx[r] = in ? row * kB + col : -1;
-      Ev[r] = in ? Ej[idx[r]] : 0.0;
-      Ed[r] = in ? Edg[idx[r]] : 0.0;
-      Dc[r] = d->r0 * Ev[r];
-      Dp[r] = 0.0;
-      Ys[row * PW + col] = to_lt<P>(Dc[r]);
+    for (int c = 0; c < CPW; ++c) {
+      const int col = (c0 + c) * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + acc_row<P>(g, r);
+        const bool in = row < kA && col < kB;
+        idx[c][r] = in ? row * kB + col : -1;
+        Ev[c][r] = in ? Ej[idx[c][r]] : 0.0;
+        Ed[c][r] = in ? Edg[idx[c][r]] : 0.0;
+        Dc[c][r] = d->r0 * Ev[c][r];
+        Dp[c][r] = 0.0;
+        Ys[row * PW + col] = to_lt<P>(Dc[c][r]);
+      }
     }
     __syncthreads();
     for (int k = 1; k <= steps; ++k) {
       const double s1 = d->sc[3 * (k - 1)], s2 = d->sc[3 * (k - 1) + 1], s3 = d->sc[3 * (k - 1) + 2];
       const double ph = s1 * d->phi[(long)(k - 1) * nv + j];
-      accT acc = accT{0, 0, 0, 0};
+      accT acc[CPW];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) acc[c] = accT{0, 0, 0, 0};
       for (int t = 0; t < T; ++t) {
         lt* Zt = Zt0 + (t & 1) * TILE;
         const lt* Bs = Ops + 2 * t * TILE;
         const lt* As = Bs + TILE;
-        accT z = accT{0, 0, 0, 0};
+        accT z[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) z[c] = accT{0, 0, 0, 0};
 #pragma unroll
         for (int u = 0; u < NCH; ++u) {
-          Frag<P> a, b;
+          Frag<P> a;
           a.load(Ys + (rt * 16 + l16) * PW, u, g);
-          b.load(Bs + (ct * 16 + l16) * PW, u, g);
-          mma_frag<P>(z, a.v, b);
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            Frag<P> b;
+            b.load(Bs + ((c0 + c) * 16 + l16) * PW, u, g);
+            mma_frag<P>(z[c], a.v, b);
+          }
         }
-        lt* zr = Zt + (ct * 16 + l16) * PW + rt * 16;
-        if constexpr (P == 0) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) zr[acc_row<0>(g, r)] = z[r];
-        } else if constexpr (P == 1) {
-          *reinterpret_cast<float4*>(zr + 4 * g) = float4{z[0], z[1], z[2], z[3]};
-        } else {
-          lt h[4];
+        for (int c = 0; c < CPW; ++c) {
+          lt* zr = Zt + ((c0 + c) * 16 + l16) * PW + rt * 16;
+          if constexpr (P == 0) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) h[r] = (__bf16)z[r];
-          *reinterpret_cast<uint2*>(zr + 4 * g) = *reinterpret_cast<const uint2*>(h);
+            for (int r = 0; r < 4; ++r) zr[acc_row<0>(g, r)] = z[c][r];
+          } else if constexpr (P == 1) {
+            *reinterpret_cast<float4*>(zr + 4 * g) = float4{z[c][0], z[c][1], z[c][2], z[c][3]};
+          } else {
+            lt h[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h[r] = (__bf16)z[c][r];
+            *reinterpret_cast<uint2*>(zr + 4 * g) = *reinterpret_cast<const uint2*>(h);
+          }
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < NCH; ++u) {
-          Frag<P> a, b;
+          Frag<P> a;
           a.load(As + (rt * 16 + l16) * PW, u, g);
-          b.load(Zt + (ct * 16 + l16) * PW, u, g);
-          mma_frag<P>(acc, a.v, b);
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            Frag<P> b;
+            b.load(Zt + ((c0 + c) * 16 + l16) * PW, u, g);
+            mma_frag<P>(acc[c], a.v, b);
+          }
         }
       }
       // the per-step kernel's epilogue, on the register-resident iterates
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double o = fma(s1, fma(Ed[r], Dc[r], (double)acc[r]), s2 * Dc[r]);
-        if (k > 1) o = fma(s3, Dp[r], o);  // the first step has no previous iterate
-        o = fma(ph, Ev[r], o);
-        Dp[r] = Dc[r];
-        Dc[r] = idx[r] >= 0 ? o : 0.0;
-      }
+      for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double o = fma(s1, fma(Ed[c][r], Dc[c][r], (double)acc[c][r]), s2 * Dc[c][r]);
+          if (k > 1) o = fma(s3, Dp[c][r], o);  // the first step has no previous iterate
+          o = fma(ph, Ev[c][r], o);
+          Dp[c][r] = Dc[c][r];
+          Dc[c][r] = idx[c][r] >= 0 ? o : 0.0;
+        }
       if (k < steps) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Ys[(rt * 16 + acc_row<P>(g, r)) * PW + col] = to_lt<P>(Dc[r]);
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            Ys[(rt * 16 + acc_row<P>(g, r)) * PW + (c0 + c) * 16 + l16] = to_lt<P>(Dc[c][r]);
         __syncthreads();
       }
     }
@@ -848,18 +873,47 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16)) void kron_filter_kernel
     gptr<double> Xj = gview(d->X) + (long)j * n;
     gptr_w<double> oj = gview_w(d->out) + (long)j * n;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (idx[r] >= 0) oj[idx[r]] = __dadd_rn(__dmul_rn(phP, Xj[idx[r]]), Dc[r]);  // as the scale-add kernel
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (idx[c][r] >= 0)
+          oj[idx[c][r]] = __dadd_rn(__dmul_rn(phP, Xj[idx[c][r]]), Dc[c][r]);  // as the scale-add kernel
     ++j;
   }
 }
 
 typedef void (*FilterKernel)(const FilterDesc*, int, long, int);
 
-static FilterKernel filter_kernel(int prec, int km) {
-  if (prec == RMC_FP64) return km <= 32 ? kron_filter_kernel<0, 32> : nullptr;
-  if (prec == RMC_FP32) return km <= 32 ? kron_filter_kernel<1, 32> : (km <= 64 ? kron_filter_kernel<1, 64> : nullptr);
-  return km <= 32 ? kron_filter_kernel<2, 32> : (km <= 64 ? kron_filter_kernel<2, 64> : nullptr);
+// Column tiles per wave of the fused filter (RMC_FILTER_CPW = 1, 2 or 4): more tiles per
+// wave reuse each row fragment across them (fewer LDS reads per MFMA) with fewer waves.
+static int filter_cpw() {
+  static const int c = [] {
+    const char* e = getenv("RMC_FILTER_CPW");
+    const int v = e ? atoi(e) : 1;
+    return (v == 2 || v == 4) ? v : 1;
+  }();
+  return c;
+}
+
+template <int P, int KM>
+static FilterKernel filter_kernel_cpw(int cpw) {
+  if constexpr (KM / 16 >= 4)
+    if (cpw == 4) return kron_filter_kernel<P, KM, 4>;
+  if (cpw >= 2) return kron_filter_kernel<P, KM, 2>;
+  return kron_filter_kernel<P, KM, 1>;
+}
+
+static FilterKernel filter_kernel(int prec, int km, int cpw) {
+  if (prec == RMC_FP64) return km <= 32 ? filter_kernel_cpw<0, 32>(cpw) : nullptr;
+  if (prec == RMC_FP32)
+    return km <= 32 ? filter_kernel_cpw<1, 32>(cpw) : (km <= 64 ? filter_kernel_cpw<1, 64>(cpw) : nullptr);
+  return km <= 32 ? filter_kernel_cpw<2, 32>(cpw) : (km <= 64 ? filter_kernel_cpw<2, 64>(cpw) : nullptr);
+}
+
+static int filter_threads(int km, int cpw) {
+  const int rtm = km / 16;
+  const int c = (cpw == 4 && rtm < 4) ? 2 : cpw;
+  return 64 * rtm * rtm / c;
 }
 
 static size_t filter_lds_bytes(int prec, int KM, int T) {
@@ -995,14 +1049,15 @@ void kron_set_attrs() {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   for (int p = 0; p < 3; ++p)
     for (int km : {32, 64})
-      if (FilterKernel k = filter_kernel(p, km))
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFilterLdsMax);
+      for (int cpw : {1, 2, 4})
+        if (FilterKernel k = filter_kernel(p, km, cpw))
+          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFilterLdsMax);
 }
 
 bool kron_filter_fits(int precision, int kA, int kB, int T) {
   const int km = stream_km(std::max(kA, kB));
-  return filter_kernel(precision, km) != nullptr && has_stream(precision, km) &&
+  return filter_kernel(precision, km, 1) != nullptr && has_stream(precision, km) &&
          filter_lds_bytes(precision, km, T) <= kFilterLdsMax;
 }
 
@@ -1010,8 +1065,9 @@ void kron_filter_batched(hipStream_t s, const FilterDesc* d, int P, long total_v
                          int kmax, int Tmax) {
   if (P <= 0 || total_vecs <= 0) return;
   const int KM = stream_km(kmax);
-  FilterKernel k = filter_kernel(precision, KM);
-  const int threads = 64 * (KM / 16) * (KM / 16);
+  const int cpw = filter_cpw();
+  FilterKernel k = filter_kernel(precision, KM, cpw);
+  const int threads = filter_threads(KM, cpw);
   const size_t lds = filter_lds_bytes(precision, KM, Tmax);
   const int G = stream_grid(reinterpret_cast<const void*>(k), threads, lds, total_vecs);
   hipLaunchKernelGGL(k, dim3(G), dim3(threads), lds, s, d, P, total_vecs, G);
