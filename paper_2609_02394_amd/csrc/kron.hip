@@ -700,6 +700,8 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
 }
 
 // ---- fused Chebyshev filter ---------------------------------------------------------
+__device__ inline int tid_of() { return threadIdx.x; }
+
 // Every step of the filter's recurrence acts on each vector alone, so one workgroup
 // carries a vector through all of its steps: the FP64 iterates D_k, D_{k-1}, the
 // defect E_j and the diagonal stay in registers (one 16 x 16 tile per wave, in the
@@ -710,7 +712,12 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
 // stored transposed, double-buffered across terms) and stage 2 (acc += c O_A Z),
 // one barrier after each stage 1 and one after the new iterate is written.
 // The arithmetic is that of the per-step kernel in the same order.
-template <int P, int KM, int CPW>
+//
+// RES = false is the form for operators too large to stay resident: LDS holds the
+// iterate, one Z^T buffer and the current term's two operator tiles; the next term's
+// tiles are loaded into registers while the current term computes and are stored
+// behind its two barriers (O_B after stage 1, c O_A after stage 2).
+template <int P, int KM, int CPW, bool RES>
 __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_kernel(
     const FilterDesc* __restrict__ descs, int P_, long V, int G) {
   typedef typename SK<P>::lt lt;
@@ -722,11 +729,48 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
   constexpr int PW = sk_pitch<P>(KM);
   constexpr int NCH = KM / SK<P>::CH;
   constexpr int TILE = KM * PW;
+  constexpr int NG = RES ? 1 : KM * KM / (4 * NT);  // streamed form: staging groups per thread
+  // one tile per wave holds the defect and the diagonal in registers; with more tiles
+  // per wave they are re-read each step (L2-resident) to stay within the registers
+  constexpr bool HOLD = CPW == 1;
   static_assert(RTM % CPW == 0, "column tiles per wave");
+  static_assert(RES || NG * 4 * NT == KM * KM, "tile staging");
   extern __shared__ char smem_raw[];
   lt* Ys = reinterpret_cast<lt*>(smem_raw);
   lt* Zt0 = Ys + TILE;
-  lt* Ops = Zt0 + 2 * TILE;  // tile 2t: O_B^t, tile 2t+1: c_t O_A^t
+  // resident: tile 2t O_B^t, tile 2t+1 c_t O_A^t; streamed: the current term's pair
+  lt* Ops = Zt0 + (RES ? 2 : 1) * TILE;
+  gv pfB[NG], pfA[NG];
+  // streamed form: term tt of problem e into the staging registers (zeros past pkm)
+  auto fetch = [&](const FilterDesc* e, int tt) {
+    gptr<lt> base = gview(static_cast<const lt*>(e->pack)) + (long)tt * 2 * e->pkm * e->pkm;
+    const int pkm = e->pkm;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const int q = tid_of() + i * NT, r = q / (KM / 4), cc = (q % (KM / 4)) * 4;
+      gv xb = gv{0, 0, 0, 0}, xa = gv{0, 0, 0, 0};
+      if (r < pkm && cc < pkm) {
+        xb = *reinterpret_cast<gptr<gv>>(base + r * pkm + cc);
+        xa = *reinterpret_cast<gptr<gv>>(base + (long)pkm * pkm + r * pkm + cc);
+      }
+      pfB[i] = xb;
+      pfA[i] = xa;
+    }
+  };
+  auto put = [&](lt* dst, const gv* pf) {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const int q = tid_of() + i * NT, r = q / (KM / 4), cc = (q % (KM / 4)) * 4;
+      lt* o = dst + r * PW + cc;
+      if constexpr (P == 0) {
+        *reinterpret_cast<double2*>(o) = double2{pf[i][0], pf[i][1]};
+        *reinterpret_cast<double2*>(o + 2) = double2{pf[i][2], pf[i][3]};
+      } else {
+        *reinterpret_cast<gv*>(o) = pf[i];
+      }
+    }
+  };
+  int staged = -1;  // streamed form: problem whose term-0 tiles sit in LDS
 
   const int w = blockIdx.x;
   const int L = (w & 7) * (G >> 3) + (w >> 3);
@@ -756,7 +800,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
     const FilterDesc* d = descs + p;
     const int kA = d->kA, kB = d->kB, T = d->T, steps = d->steps, nv = d->nv;
     const long n = (long)kA * kB;
-    if (loaded != p) {
+    if (RES && loaded != p) {
       __syncthreads();  // every wave is done with the previous operators
       // the pack's tiles are pkm x pkm (the problem's own padded size, <= KM): rows and
       // columns past pkm are staged as zeros
@@ -779,7 +823,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
     }
     gptr<double> Ej = gview(d->E) + (long)j * n;
     gptr<double> Edg = gview(d->Ediag);
-    double Dc[CPW][4], Dp[CPW][4], Ev[CPW][4], Ed[CPW][4];
+    double Dc[CPW][4], Dp[CPW][4], Ev[HOLD ? CPW : 1][4], Ed[HOLD ? CPW : 1][4];
     int idx[CPW][4];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
@@ -789,11 +833,24 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
         const int row = rt * 16 + acc_row<P>(g, r);
         const bool in = row < kA && col < kB;
         idx[c][r] = in ? row * kB + col : -1;
-        Ev[c][r] = in ? Ej[idx[c][r]] : 0.0;
-        Ed[c][r] = in ? Edg[idx[c][r]] : 0.0;
-        Dc[c][r] = d->r0 * Ev[c][r];
+        const double e0 = in ? Ej[idx[c][r]] : 0.0;
+        if constexpr (HOLD) {
+          Ev[c][r] = e0;
+          Ed[c][r] = in ? Edg[idx[c][r]] : 0.0;
+        }
+        Dc[c][r] = d->r0 * e0;
         Dp[c][r] = 0.0;
         Ys[row * PW + col] = to_lt<P>(Dc[c][r]);
+      }
+    }
+    if constexpr (!RES) {
+      // every wave is past its last read of the operator tiles (the previous vector's
+      // last barrier) when the first problem, or one after a term-less problem, starts
+      if (T > 0 && staged != p) {
+        fetch(d, 0);
+        put(Ops, pfB);
+        put(Ops + TILE, pfA);
+        staged = p;
       }
     }
     __syncthreads();
@@ -804,9 +861,29 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
 #pragma unroll
       for (int c = 0; c < CPW; ++c) acc[c] = accT{0, 0, 0, 0};
       for (int t = 0; t < T; ++t) {
-        lt* Zt = Zt0 + (t & 1) * TILE;
-        const lt* Bs = Ops + 2 * t * TILE;
-        const lt* As = Bs + TILE;
+        lt* Zt = Zt0 + (RES ? (t & 1) * TILE : 0);
+        lt* Bs = Ops + (RES ? 2 * t * TILE : 0);
+        lt* As = Bs + TILE;
+        // streamed form: the next term's tiles (this problem's next term, its term 0 for
+        // the next step, or the next vector's problem), loaded during this term
+        const FilterDesc* nd = nullptr;
+        if constexpr (!RES) {
+          if (t + 1 < T) {
+            nd = d;
+          } else if (k < steps) {
+            nd = d;
+          } else if (v + 1 < v1) {
+            int pn = p, jn = j + 1;
+            while (jn >= descs[pn].nv) {
+              jn = 0;
+              ++pn;
+            }
+            nd = descs + pn;
+            staged = descs[pn].T > 0 ? pn : -1;
+          }
+          if (nd && nd->T > 0) fetch(nd, t + 1 < T ? t + 1 : 0);
+          else nd = nullptr;
+        }
         accT z[CPW];
 #pragma unroll
         for (int c = 0; c < CPW; ++c) z[c] = accT{0, 0, 0, 0};
@@ -837,6 +914,8 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
           }
         }
         __syncthreads();
+        if constexpr (!RES)
+          if (nd) put(Bs, pfB);  // every wave is past stage 1's reads of O_B
 #pragma unroll
         for (int u = 0; u < NCH; ++u) {
           Frag<P> a;
@@ -848,17 +927,30 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
             mma_frag<P>(acc[c], a.v, b);
           }
         }
+        if constexpr (!RES) {
+          __syncthreads();          // every wave is past stage 2's reads of c O_A and Z^T
+          if (nd) put(As, pfA);     // visible to the next stage 2 after the next barrier
+        }
       }
       // the per-step kernel's epilogue, on the register-resident iterates
 #pragma unroll
       for (int c = 0; c < CPW; ++c)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          double o = fma(s1, fma(Ed[c][r], Dc[c][r], (double)acc[c][r]), s2 * Dc[c][r]);
+          const bool in = idx[c][r] >= 0;
+          double ed, ev;
+          if constexpr (HOLD) {
+            ed = Ed[c][r];
+            ev = Ev[c][r];
+          } else {
+            ed = in ? Edg[idx[c][r]] : 0.0;
+            ev = in ? Ej[idx[c][r]] : 0.0;
+          }
+          double o = fma(s1, fma(ed, Dc[c][r], (double)acc[c][r]), s2 * Dc[c][r]);
           if (k > 1) o = fma(s3, Dp[c][r], o);  // the first step has no previous iterate
-          o = fma(ph, Ev[c][r], o);
+          o = fma(ph, ev, o);
           Dp[c][r] = Dc[c][r];
-          Dc[c][r] = idx[c][r] >= 0 ? o : 0.0;
+          Dc[c][r] = in ? o : 0.0;
         }
       if (k < steps) {
 #pragma unroll
@@ -895,30 +987,52 @@ static int filter_cpw() {
   return c;
 }
 
+// Streamed form: column tiles per wave of the one instance per precision and tile size
+// (0: none). FP64 at KM = 64 takes two tiles per wave for the registers. Wider tiles
+// need three or more tiles per wave (the 16-wave limit), and those forms spill
+// registers, so they are left out.
+static int filter_streamed_cpw(int prec, int km) {
+  if (prec == RMC_FP64) return km <= 32 ? 1 : (km <= 64 ? 2 : 0);
+  if (km <= 32) return 0;  // resident at this size in every precision
+  return km <= 64 ? 1 : 0;
+}
+
 template <int P, int KM>
 static FilterKernel filter_kernel_cpw(int cpw) {
   if constexpr (KM / 16 >= 4)
-    if (cpw == 4) return kron_filter_kernel<P, KM, 4>;
-  if (cpw >= 2) return kron_filter_kernel<P, KM, 2>;
-  return kron_filter_kernel<P, KM, 1>;
+    if (cpw == 4) return kron_filter_kernel<P, KM, 4, true>;
+  if (cpw >= 2) return kron_filter_kernel<P, KM, 2, true>;
+  return kron_filter_kernel<P, KM, 1, true>;
 }
 
-static FilterKernel filter_kernel(int prec, int km, int cpw) {
+// res: operators resident in LDS; else the streamed form (one per precision and size,
+// column tiles per wave fixed by the 16-wave limit: 1 at KM <= 64, 3 at 96, 4 at 128)
+static FilterKernel filter_kernel(int prec, int km, int cpw, bool res = true) {
+  if (!res) {
+    switch (filter_streamed_cpw(prec, km)) {
+      case 0: return nullptr;
+      case 1: return prec == RMC_FP64 ? kron_filter_kernel<0, 32, 1, false>
+                                      : (prec == RMC_FP32 ? kron_filter_kernel<1, 64, 1, false> : kron_filter_kernel<2, 64, 1, false>);
+      default: return kron_filter_kernel<0, 64, 2, false>;
+    }
+  }
   if (prec == RMC_FP64) return km <= 32 ? filter_kernel_cpw<0, 32>(cpw) : nullptr;
   if (prec == RMC_FP32)
     return km <= 32 ? filter_kernel_cpw<1, 32>(cpw) : (km <= 64 ? filter_kernel_cpw<1, 64>(cpw) : nullptr);
   return km <= 32 ? filter_kernel_cpw<2, 32>(cpw) : (km <= 64 ? filter_kernel_cpw<2, 64>(cpw) : nullptr);
 }
 
-static int filter_threads(int km, int cpw) {
+static int filter_threads(int prec, int km, int cpw, bool res = true) {
   const int rtm = km / 16;
-  const int c = (cpw == 4 && rtm < 4) ? 2 : cpw;
+  int c = cpw;
+  if (!res) c = filter_streamed_cpw(prec, km);
+  else if (cpw == 4 && rtm < 4) c = 2;
   return 64 * rtm * rtm / c;
 }
 
-static size_t filter_lds_bytes(int prec, int KM, int T) {
+static size_t filter_lds_bytes(int prec, int KM, int T, bool res = true) {
   const int esz = prec == RMC_FP64 ? 8 : (prec == RMC_FP32 ? 4 : 2);
-  return (size_t)(3 + 2 * std::max(T, 0)) * KM * (KM + 16 / esz) * esz;
+  return (size_t)(res ? 3 + 2 * std::max(T, 0) : 4) * KM * (KM + 16 / esz) * esz;
 }
 
 static constexpr size_t kFilterLdsMax = 159 * 1024;
@@ -1048,27 +1162,42 @@ void kron_set_attrs() {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kron_kernel(p, ct, mrt)),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   for (int p = 0; p < 3; ++p)
-    for (int km : {32, 64})
+    for (int km : {32, 64, 96, 128})
       for (int cpw : {1, 2, 4})
-        if (FilterKernel k = filter_kernel(p, km, cpw))
-          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFilterLdsMax);
+        for (bool res : {true, false})
+          if (FilterKernel k = filter_kernel(p, km, cpw, res))
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFilterLdsMax);
+}
+
+// Resident form where its LDS fits, else the streamed form (RMC_FILTER_STREAMED=1
+// takes the streamed form wherever it exists, to test it).
+static bool filter_resident(int precision, int km, int T) {
+  const char* fe = getenv("RMC_FILTER_STREAMED");
+  const bool force_streamed = fe && atoi(fe) != 0;
+  const bool res_ok = filter_kernel(precision, km, 1, true) != nullptr &&
+                      filter_lds_bytes(precision, km, T, true) <= kFilterLdsMax;
+  const bool str_ok = filter_kernel(precision, km, 1, false) != nullptr &&
+                      filter_lds_bytes(precision, km, T, false) <= kFilterLdsMax;
+  return res_ok && !(force_streamed && str_ok);
 }
 
 bool kron_filter_fits(int precision, int kA, int kB, int T) {
   const int km = stream_km(std::max(kA, kB));
-  return filter_kernel(precision, km, 1) != nullptr && has_stream(precision, km) &&
-         filter_lds_bytes(precision, km, T) <= kFilterLdsMax;
+  if (!has_stream(precision, km)) return false;  // no operator pack for this size
+  return (filter_kernel(precision, km, 1, true) && filter_lds_bytes(precision, km, T, true) <= kFilterLdsMax) ||
+         (filter_kernel(precision, km, 1, false) && filter_lds_bytes(precision, km, T, false) <= kFilterLdsMax);
 }
 
 void kron_filter_batched(hipStream_t s, const FilterDesc* d, int P, long total_vecs, int precision,
                          int kmax, int Tmax) {
   if (P <= 0 || total_vecs <= 0) return;
   const int KM = stream_km(kmax);
+  const bool res = filter_resident(precision, KM, Tmax);
   const int cpw = filter_cpw();
-  FilterKernel k = filter_kernel(precision, KM, cpw);
-  const int threads = filter_threads(KM, cpw);
-  const size_t lds = filter_lds_bytes(precision, KM, Tmax);
+  FilterKernel k = filter_kernel(precision, KM, cpw, res);
+  const int threads = filter_threads(precision, KM, cpw, res);
+  const size_t lds = filter_lds_bytes(precision, KM, Tmax, res);
   const int G = stream_grid(reinterpret_cast<const void*>(k), threads, lds, total_vecs);
   hipLaunchKernelGGL(k, dim3(G), dim3(threads), lds, s, d, P, total_vecs, G);
 }

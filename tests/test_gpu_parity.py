@@ -436,7 +436,7 @@ def test_recurse_mixed_precision_xxz_chain64(ctx, prec):
 
 
 FUSED_CASES = [
-    ("xxz_N64_k64", W.xxz_chain64(), [1, 2]),
+    ("xxz_N64_k64", W.xxz_chain64(), [0, 1, 2]),
     ("tfim_N32_k16", W.ChainJob("tfim", 32, 8, 16, 8, J=1.0, h=0.9), [0, 1, 2]),
     ("xxz_N16_k24", W.ChainJob("xxz", 16, 4, 24, 6, J=1.0, delta=0.7), [0, 1, 2]),
     ("rfheis_N32_k48", W.ChainJob("rfheis", 32, 8, 48, 8, J=1.0, fields=W.rfheis_batch(2)[1].fields),
@@ -445,15 +445,17 @@ FUSED_CASES = [
 
 
 def _run_both_filter_paths(ctx, run):
-    """run() once with the fused filter and once with the per-step launches, the
-    per-step Kronecker kernel pinned to the streaming variant (the fused kernel's
-    arithmetic in the same order, up to last-bit rounding): returns
-    {flag: (result, Kronecker flops)}. The flop totals follow the iteration histories
-    (filter degrees, locked rows); last-bit differences can flip a locking decision, so
-    they are compared within 3%."""
+    """run() with the fused filter (its resident-operator form where it fits, then its
+    streamed-operator form forced) and with the per-step launches, the per-step
+    Kronecker kernel pinned to the streaming variant (the fused kernel's arithmetic in
+    the same order, up to last-bit rounding): returns {flag: (result, Kronecker flops)}
+    for flags "1", "s" (streamed) and "0". The flop totals follow the iteration
+    histories (filter degrees, locked rows); last-bit differences can flip a locking
+    decision, so they are compared within 3%."""
     out = {}
-    for flag in ("1", "0"):
-        os.environ["RMC_FUSED_FILTER"] = flag
+    for flag in ("1", "s", "0"):
+        os.environ["RMC_FUSED_FILTER"] = "0" if flag == "0" else "1"
+        os.environ["RMC_FILTER_STREAMED"] = "1" if flag == "s" else "0"
         os.environ["RMC_KRON_VARIANT"] = "10"
         try:
             ctx.profile(True)
@@ -462,6 +464,7 @@ def _run_both_filter_paths(ctx, run):
             ctx.profile(False)
         finally:
             os.environ.pop("RMC_FUSED_FILTER", None)
+            os.environ.pop("RMC_FILTER_STREAMED", None)
             os.environ.pop("RMC_KRON_VARIANT", None)
         out[flag] = (r, flops)
     return out
@@ -480,9 +483,10 @@ def test_fused_filter_equals_per_step_filter(ctx, name, job, precs):
         say("fused filter", name, prec)
         opts = rmc.default_opts(precision=prec)
         out = _run_both_filter_paths(ctx, lambda: ctx.recurse(*rmc.job_chain(job), opts=opts)[0])
-        assert abs(out["1"][1] - out["0"][1]) <= 0.03 * out["0"][1], (prec, out["1"][1], out["0"][1])
-        assert rel_err(out["1"][0], out["0"][0]) <= 1e-13, (prec, out)
-        assert rel_err(out["1"][0], e64) <= 1e-8, (prec, out["1"][0], e64)
+        for f in ("1", "s"):
+            assert abs(out[f][1] - out["0"][1]) <= 0.03 * out["0"][1], (prec, f, out[f][1], out["0"][1])
+            assert rel_err(out[f][0], out["0"][0]) <= 1e-13, (prec, f, out)
+            assert rel_err(out[f][0], e64) <= 1e-8, (prec, f, out[f][0], e64)
 
 
 def test_fused_filter_batch_mixes_sizes_and_paths(ctx):
@@ -503,9 +507,10 @@ def test_fused_filter_batch_mixes_sizes_and_paths(ctx):
         return E
 
     out = _run_both_filter_paths(ctx, run)
-    assert abs(out["1"][1] - out["0"][1]) <= 0.03 * out["0"][1], (out["1"][1], out["0"][1])
+    for f in ("1", "s"):
+        assert abs(out[f][1] - out["0"][1]) <= 0.03 * out["0"][1], (f, out[f][1], out["0"][1])
+        assert rel_err(out[f][0], out["0"][0]) <= 1e-13
     E = out["1"][0]
-    assert rel_err(E, out["0"][0]) <= 1e-13
     for i, j in enumerate(jobs):
         e1, _ = ctx.recurse(*rmc.job_chain(j), opts=opts)
         ref = OR.recurse(j)
