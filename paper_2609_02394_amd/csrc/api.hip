@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <tuple>
@@ -172,6 +173,175 @@ void assemble_leaf(rmc_ctx* ctx, const rmc_leaf_desc* leaf, double* H) {
   sync(ctx);  // dterms is released at scope exit
 }
 
+// ---- block-diagonal leaves ---------------------------------------------------------
+// A leaf Hamiltonian whose nonzero pattern splits into several connected components
+// (a conserved quantity that is diagonal in the site basis, such as total S^z for the
+// Heisenberg and XXZ chains) is block diagonal after a permutation of the basis; its
+// dense ED is then the union of the blocks' EDs. The components come from the term
+// list with the device assembly's rule and accumulation order, so exact cancellations
+// (X X - T T on |00> -> |11>) drop the same entries.
+struct LeafBlocks {
+  bool usable = false;  // two or more components, each within the Jacobi kernel's size
+  std::vector<std::vector<int>> comps;
+  int maxb = 0;
+};
+
+LeafBlocks analyse_leaf(const rmc_leaf_desc* leaf) {
+  const int n = leaf->n_sites, D = 1 << n;
+  std::vector<std::vector<std::pair<int, double>>> row(D);
+  for (int r = 0; r < D; ++r) {
+    auto& R = row[r];
+    for (int t = 0; t < leaf->n_terms; ++t) {
+      const rmc_term& tm = leaf->terms[t];
+      int c = r;
+      double sgn = 1.0;
+      for (int u = 0; u < tm.nsite; ++u) {
+        const int b = n - 1 - tm.site[u], br = (r >> b) & 1;
+        if (tm.op[u] == RMC_OP_T) sgn *= br == 0 ? -1.0 : 1.0;
+        if (tm.op[u] == RMC_OP_Z) sgn *= br == 0 ? 1.0 : -1.0;
+        if (tm.op[u] != RMC_OP_Z) c ^= 1 << b;
+      }
+      const double val = sgn > 0.0 ? tm.coef : -tm.coef;
+      auto it = std::find_if(R.begin(), R.end(), [c](const std::pair<int, double>& x) { return x.first == c; });
+      if (it == R.end()) R.push_back({c, 0.0 + val});
+      else it->second = it->second + val;
+    }
+  }
+  std::vector<int> comp(D, -1);
+  LeafBlocks lb;
+  for (int s0 = 0; s0 < D; ++s0) {
+    if (comp[s0] >= 0) continue;
+    const int id = (int)lb.comps.size();
+    lb.comps.push_back({s0});
+    comp[s0] = id;
+    for (size_t q = 0; q < lb.comps[id].size(); ++q) {
+      const int r = lb.comps[id][q];
+      for (auto& e : row[r])
+        if (e.second != 0.0 && comp[e.first] < 0) {
+          comp[e.first] = id;
+          lb.comps[id].push_back(e.first);
+        }
+    }
+  }
+  for (auto& c : lb.comps) {
+    std::sort(c.begin(), c.end());
+    lb.maxb = std::max(lb.maxb, (int)c.size());
+  }
+  lb.usable = lb.comps.size() >= 2 && lb.maxb <= jacobi_max_m();
+  return lb;
+}
+
+// The analysis of each distinct term list, kept for the life of the process.
+const LeafBlocks& leaf_blocks(const rmc_leaf_desc* leaf) {
+  static std::mutex mu;
+  static std::map<std::string, LeafBlocks> cache;
+  // the term list field by field (no struct padding in the key)
+  std::string key(reinterpret_cast<const char*>(&leaf->n_sites), sizeof(int));
+  for (int t = 0; t < leaf->n_terms; ++t) {
+    const rmc_term& tm = leaf->terms[t];
+    key.append(reinterpret_cast<const char*>(&tm.coef), sizeof(double));
+    key.push_back((char)tm.nsite);
+    for (int u = 0; u < tm.nsite; ++u) {
+      key.push_back((char)tm.site[u]);
+      key.push_back((char)tm.op[u]);
+    }
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it == cache.end()) it = cache.emplace(key, analyse_leaf(leaf)).first;
+  return it->second;
+}
+
+// Lowest nevs[i] eigenpairs of the block-diagonal leaves `sel` (H assembled on the
+// device): every block of every leaf gathered and diagonalised by the batched Jacobi
+// kernel in one launch; the leaf's eigenvalues are the sorted union (ties by block,
+// then by position), its eigenvectors the block vectors scattered into full rows.
+void leaf_blocks_solve(rmc_ctx* ctx, Scratch& sc, const std::vector<const rmc_leaf_desc*>& leaves,
+                       const std::vector<int>& sel, const std::vector<CoupledOp>& ops,
+                       const std::vector<int>& nevs, const std::vector<double*>& Xs,
+                       std::vector<std::vector<double>>& evals, std::vector<SolveStats>& st) {
+  hipStream_t s = ctx->stream;
+  struct Blk {
+    int leaf, nb;
+    size_t off, offsq;
+  };
+  std::vector<Blk> blks;
+  std::vector<int> idx;
+  size_t sq = 0;
+  int nbmax = 0;
+  for (int i : sel) {
+    for (const auto& c : leaf_blocks(leaves[i]).comps) {
+      blks.push_back({i, (int)c.size(), idx.size(), sq});
+      idx.insert(idx.end(), c.begin(), c.end());
+      sq += c.size() * c.size();
+      nbmax = std::max(nbmax, (int)c.size());
+    }
+  }
+  const int NB = (int)blks.size();
+  int* idx_dev = sc.get<int>(idx.size());
+  double* A = sc.get<double>(sq);
+  double* V = sc.get<double>(sq);
+  double* Vw = sc.get<double>(sq);
+  double* ev = sc.get<double>(idx.size());
+  int* info = sc.get<int>(NB);
+  std::vector<BlockGatherDesc> gd(NB);
+  std::vector<EigDesc> ed(NB);
+  for (int b = 0; b < NB; ++b) {
+    const Blk& B = blks[b];
+    gd[b] = BlockGatherDesc{B.nb, ops[B.leaf].n, idx_dev + B.off, ops[B.leaf].H, A + B.offsq};
+    EigDesc e{};
+    e.m = B.nb; e.nparts = 1; e.A = A + B.offsq; e.pstride = (long)B.nb * B.nb;
+    e.evals = ev + B.off; e.V = V + B.offsq; e.Vwork = Vw + B.offsq; e.info = info + b;
+    ed[b] = e;
+  }
+  BlockGatherDesc* gd_dev = sc.get<BlockGatherDesc>(NB);
+  EigDesc* ed_dev = sc.get<EigDesc>(NB);
+  RMC_HIP(hipMemcpyAsync(idx_dev, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  RMC_HIP(hipMemcpyAsync(gd_dev, gd.data(), NB * sizeof(BlockGatherDesc), hipMemcpyHostToDevice, s));
+  RMC_HIP(hipMemcpyAsync(ed_dev, ed.data(), NB * sizeof(EigDesc), hipMemcpyHostToDevice, s));
+  gather_blocks(s, gd_dev, NB, nbmax);
+  jacobi_batched(s, ed_dev, NB, nbmax);
+  std::vector<double> evh(idx.size());
+  std::vector<int> infoh(NB);
+  RMC_HIP(hipMemcpyAsync(evh.data(), ev, evh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  RMC_HIP(hipMemcpyAsync(infoh.data(), info, NB * sizeof(int), hipMemcpyDeviceToHost, s));
+  sync(ctx);
+  // per leaf: (eigenvalue, block, column) sorted; the lowest nevs rows scattered
+  std::vector<BlockScatterDesc> sd;
+  for (int i : sel) {
+    std::vector<std::tuple<double, int, int>> all;
+    int sweeps = 0;
+    bool ok = true;
+    for (int b = 0; b < NB; ++b) {
+      if (blks[b].leaf != i) continue;
+      for (int j = 0; j < blks[b].nb; ++j) all.emplace_back(evh[blks[b].off + j], b, j);
+      sweeps += std::abs(infoh[b]);
+      ok = ok && infoh[b] >= 0;
+    }
+    std::sort(all.begin(), all.end());
+    const int ne = std::min<int>(nevs[i], (int)all.size());
+    evals[i].resize(ne);
+    RMC_HIP(hipMemsetAsync(Xs[i], 0, (size_t)ne * ops[i].n * sizeof(double), s));
+    for (int mu = 0; mu < ne; ++mu) {
+      const int b = std::get<1>(all[mu]), j = std::get<2>(all[mu]);
+      evals[i][mu] = std::get<0>(all[mu]);
+      sd.push_back(BlockScatterDesc{blks[b].nb, j, idx_dev + blks[b].off, V + blks[b].offsq,
+                                    Xs[i] + (size_t)mu * ops[i].n});
+    }
+    st[i] = SolveStats();
+    st[i].rr_sweeps = sweeps;
+    st[i].status = ok ? RMC_OK : RMC_ERR_NOCONV;
+  }
+  if (!sd.empty()) {
+    BlockScatterDesc* sd_dev = sc.get<BlockScatterDesc>(sd.size());
+    RMC_HIP(hipMemcpyAsync(sd_dev, sd.data(), sd.size() * sizeof(BlockScatterDesc), hipMemcpyHostToDevice, s));
+    scatter_block_rows(s, sd_dev, (int)sd.size(), nbmax);
+  }
+  // the scratch tables are read by kernels queued on the stream; the caller's later
+  // copies and its final synchronisation on the same stream order them
+  sync(ctx);
+}
+
 // Lowest eigenpairs of several dense leaves in one batched solve; builds a module
 // per leaf unless q_only > 0 (then only the lowest q_only eigenvalues).
 std::vector<rmc_module*> leaf_solve_batch(rmc_ctx* ctx, const std::vector<const rmc_leaf_desc*>& leaves,
@@ -235,8 +405,34 @@ std::vector<rmc_module*> leaf_solve_batch(rmc_ctx* ctx, const std::vector<const 
   for (int i = 0; i < P; ++i) ops[i].bup = bh[i];
   rmc_solve_opts oo = o;
   oo.precision = RMC_FP64;
-  std::vector<SolveStats> st;
-  eig_lowest_batch(ctx, opp, nevs, oo, Xs, evals, st);
+  // block-diagonal leaves: blockwise Jacobi; the others: the batched block solver
+  // (RMC_LEAF_BLOCKS=0 sends every leaf to the iterative solver)
+  std::vector<int> blk, itr;
+  {
+    const char* e = getenv("RMC_LEAF_BLOCKS");
+    const bool on = !(e && atoi(e) == 0);
+    for (int i = 0; i < P; ++i) (on && leaf_blocks(leaves[i]).usable ? blk : itr).push_back(i);
+  }
+  std::vector<SolveStats> st(P);
+  evals.assign(P, {});
+  if (!itr.empty()) {
+    std::vector<const CoupledOp*> so;
+    std::vector<int> sn;
+    std::vector<double*> sx;
+    for (int i : itr) {
+      so.push_back(opp[i]);
+      sn.push_back(nevs[i]);
+      sx.push_back(Xs[i]);
+    }
+    std::vector<std::vector<double>> se;
+    std::vector<SolveStats> ss;
+    eig_lowest_batch(ctx, so, sn, oo, sx, se, ss);
+    for (size_t t = 0; t < itr.size(); ++t) {
+      evals[itr[t]] = se[t];
+      st[itr[t]] = ss[t];
+    }
+  }
+  if (!blk.empty()) leaf_blocks_solve(ctx, sc, leaves, blk, ops, nevs, Xs, evals, st);
   const double dt = now_ms() - t0;
   if (reps) {
     reps->assign(P, rmc_level_report{});

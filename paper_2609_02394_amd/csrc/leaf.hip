@@ -375,6 +375,35 @@ __global__ void start_block_batched_kernel(const StartDesc* __restrict__ descs) 
   }
 }
 
+// ---- block-diagonal leaves -----------------------------------------------------------
+__global__ __launch_bounds__(256) void gather_blocks_kernel(const BlockGatherDesc* __restrict__ descs) {
+  const BlockGatherDesc& d = descs[blockIdx.y];
+  const long total = (long)d.nb * d.nb;
+  for (long t = blockIdx.x * 256L + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+    const int i = (int)(t / d.nb), j = (int)(t - (long)i * d.nb);
+    d.A[t] = d.H[(long)d.idx[i] * d.D + d.idx[j]];
+  }
+}
+
+void gather_blocks(hipStream_t s, const BlockGatherDesc* d, int P, int nbmax) {
+  if (P <= 0 || nbmax <= 0) return;
+  const long tot = (long)nbmax * nbmax;
+  const int bx = (int)std::min<long>((tot + 255) / 256, 64);
+  hipLaunchKernelGGL(gather_blocks_kernel, dim3(bx, P), dim3(256), 0, s, d);
+}
+
+__global__ __launch_bounds__(256) void scatter_block_rows_kernel(const BlockScatterDesc* __restrict__ descs) {
+  const BlockScatterDesc& d = descs[blockIdx.y];
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < d.nb; r += gridDim.x * 256)
+    d.out[d.idx[r]] = d.V[(long)r * d.nb + d.col];
+}
+
+void scatter_block_rows(hipStream_t s, const BlockScatterDesc* d, int P, int nbmax) {
+  if (P <= 0 || nbmax <= 0) return;
+  const int bx = std::max(1, std::min((nbmax + 255) / 256, 16));
+  hipLaunchKernelGGL(scatter_block_rows_kernel, dim3(bx, P), dim3(256), 0, s, d);
+}
+
 void start_batched(hipStream_t s, const StartDesc* d, int P, int nmax, int mmax) {
   if (P <= 0) return;
   hipLaunchKernelGGL(rank_select_batched_kernel, dim3(P), dim3(256), 0, s, d);

@@ -78,6 +78,25 @@ struct SiteOpDesc {
 };
 void site_op_batched(hipStream_t s, const SiteOpDesc* d, int P, long total_max);
 
+// Symmetric blocks of a leaf Hamiltonian: A[i][j] = H[idx[i]][idx[j]] (nb x nb, from the
+// D x D matrix H), one descriptor per block.
+struct BlockGatherDesc {
+  int nb, D;
+  const int* idx;
+  const double* H;
+  double* A;
+};
+void gather_blocks(hipStream_t s, const BlockGatherDesc* d, int P, int nbmax);
+// Full-space rows from block eigenvectors: out[idx[r]] = V[r * nb + col], r < nb (the row
+// is zero elsewhere and must be cleared first).
+struct BlockScatterDesc {
+  int nb, col;
+  const int* idx;
+  const double* V;
+  double* out;
+};
+void scatter_block_rows(hipStream_t s, const BlockScatterDesc* d, int P, int nbmax);
+
 // Diagonal of H_eff: D[a*kB+b] = EA[a] + EB[b] + sum_i c_i OA_i[a,a] OB_i[b,b];
 // Ediag[a*kB+b] = EA[a] + EB[b].
 void kron_diag(hipStream_t s, int kA, int kB, const double* EA, const double* EB, int T,

@@ -122,6 +122,40 @@ def test_module_ed_and_projection(ctx, job, k):
     m.free()
 
 
+@pytest.mark.parametrize("job,k", [
+    (W.xxz_chain64(), 64),
+    (W.rfheis_batch(3)[2], 96),
+    (W.ChainJob("xxz", 8, 8, 32, 4, J=1.0, delta=0.0), 32),
+    (W.ChainJob("xxz", 10, 10, 100, 4, J=1.0, delta=1.0), 100),
+    (W.ChainJob("tfim", 8, 8, 24, 4, J=1.0, h=0.7), 24),
+])
+def test_leaf_blocks_equal_iterative_leaf_ed(ctx, job, k):
+    """Leaves whose Hamiltonian is block diagonal in the site basis (conserved total S^z)
+    are diagonalised block by block; the same leaves through the iterative solver
+    (RMC_LEAF_BLOCKS=0) give the same spectrum and retained subspace. The ten-site
+    S^z = 0 block (252 states) exceeds the block solver and the TFIM leaf has a single
+    component: both take the iterative path either way."""
+    say("leaf blocks", job.model, job.n_sites, k)
+    L0 = job.leaf_sites
+    res = {}
+    for flag in ("1", "0"):
+        os.environ["RMC_LEAF_BLOCKS"] = flag
+        try:
+            m = ctx.module_ed(L0, SM.block_terms(job, 0, L0), k)
+            res[flag] = (m.info(), m.basis())
+            m.free()
+        finally:
+            os.environ.pop("RMC_LEAF_BLOCKS", None)
+    (i1, B1), (i0, B0) = res["1"], res["0"]
+    assert i1["k_eff"] == i0["k_eff"]
+    assert rel_err(i1["E"], i0["E"]) <= 1e-12
+    assert np.max(np.abs(B1 @ B1.T - np.eye(i1["k_eff"]))) <= 1e-12
+    E_or, V_or, k_eff, gap, w = OR.leaf_ed(OH.block_hamiltonian(job, 0, L0), k)
+    assert i1["k_eff"] == k_eff and rel_err(i1["E"], E_or) <= 1e-12
+    if gap > 1e-3:
+        assert np.max(np.abs(_projector_rows(B1) - _projector_rows(B0))) <= 1e-9
+
+
 @pytest.mark.parametrize("chain,leaf", [(60, 0), (195, 3), (227, 1)])
 def test_leaf_ed_guard_rows_stay_out_of_the_final_rayleigh_ritz(ctx, chain, leaf):
     """Random-field leaves whose guard Ritz values sit just outside the wanted
