@@ -656,7 +656,7 @@ __device__ inline double rcp_nr(double x) {
 // Schur decomposition): d = a_qq - a_pp, h = 2 a_pq, t = sign(d) h / (|d| + hypot(d, h)),
 // c = 1/sqrt(1 + t^2), s = t c (reciprocals and roots by refined estimates). A pair is rotated when a_pq^2 > eps^2 |a_pp a_qq| and
 // |a_pq| > eps ||A||_F; the sweep loop stops when no pair qualifies.
-__device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, long pstride,
+__device__ __forceinline__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, long pstride,
                             double* __restrict__ evals, double* __restrict__ Vout,
                             double* __restrict__ Vg, int vlds, int max_sweeps, int* __restrict__ info,
                             double* sm) {
@@ -827,6 +827,270 @@ __device__ void jacobi_body(int m, const double* __restrict__ Ab, int nparts, lo
   if (tid == 0) info[0] = converged ? sweeps : -(sweeps + 1);
 }
 
+// ---------------------------------------------------------------------------
+// The same cyclic Jacobi for 8 <= m <= 80 with A and V kept in the frame of the
+// round-robin schedule. Positions 0..M-1 are paired (k, M-1-k) into H = M/2 slots;
+// after every round each index moves from position j to j-1 (position 1 to M-1,
+// position 0 fixed), which is what makes the schedule visit every pair once per
+// sweep. Storing A and V by position instead of by index makes every address a
+// thread touches fixed for the whole run: a round reads one buffer and writes the
+// rotated values to the positions they move to in the other.
+//   A: for each slot pair (k <= l) the 2x2 block of entries between positions
+//      {k, M-1-k} x {l, M-1-l}, as four planes (LL, LR, RL, RR) of H(H+1)/2 blocks.
+//   V: column of position j (the eigenvector estimate of the index there), rows in
+//      pairs so that a lane moves 16 bytes.
+// Roles (1024 threads): wave 0 lane k updates the block holding the two indices
+// that meet in slot k next round and computes that rotation from the updated entry
+// and the new diagonals (a rotation table carries c, s and the pair's diagonals
+// after its rotation), so a round needs one barrier; waves 1..15 update the other
+// blocks and the eigenvectors. Same rotation and thresholds as jacobi_body; m odd
+// is padded with a zero index whose rotations never qualify.
+// ---------------------------------------------------------------------------
+constexpr int JS_MIN = 8, JS_MAX = 80;
+
+__device__ inline int js_next(int j, int M) { return j == 0 ? 0 : (j == M - 1 ? 1 : j + 1); }  // pos -> its index's previous pos
+__device__ inline int js_prev(int x, int M) { return x == 0 ? 0 : (x == 1 ? M - 1 : x - 1); }  // where pos x moves
+__device__ inline int js_blk(int k, int l) { return l * (l + 1) / 2 + k; }
+// plane * npair + block of the entry at positions (i, j) after the move
+__device__ inline int js_dest(int i, int j, int M, int H, int npair) {
+  const int i2 = js_prev(i, M), j2 = js_prev(j, M);
+  const int si = i2 < H ? i2 : M - 1 - i2, ri = i2 < H ? 0 : 1;
+  const int sj = j2 < H ? j2 : M - 1 - j2, rj = j2 < H ? 0 : 1;
+  if (si < sj) return (ri * 2 + rj) * npair + js_blk(si, sj);
+  if (si > sj) return (rj * 2 + ri) * npair + js_blk(sj, si);
+  return ((i2 == j2) ? (ri ? 3 : 0) : 1) * npair + js_blk(si, si);
+}
+size_t jacobi_shift_lds_doubles(int m) {
+  const int M = m + (m & 1), H = M / 2, np = H * (H + 1) / 2;
+  return 8 * (size_t)np + 2 * (size_t)M * M + 8 * (size_t)H + (size_t)M + 64 + 8;
+}
+__device__ inline void js_rot(double apq, double app, double aqq, double eps2, double floor_abs,
+                              double& c, double& s, double& t) {
+  c = 1.0; s = 0.0; t = 0.0;
+  if (apq * apq > eps2 * fabs(app * aqq) && fabs(apq) > floor_abs) {
+    const double d = aqq - app, h = 2.0 * apq;
+    const double x = d * d + h * h;
+    const double r = x * rsqrt_nr(x);
+    t = (d >= 0.0 ? h : -h) * rcp_nr(fabs(d) + r);
+    c = rsqrt_nr(1.0 + t * t);
+    s = t * c;
+  }
+}
+
+__device__ __forceinline__ void jacobi_shift_body(int m, const double* __restrict__ Ab, int nparts, long pstride,
+                                  double* __restrict__ evals, double* __restrict__ Vout, int max_sweeps,
+                                  int* __restrict__ info, double* sm) {
+  constexpr int VJ = 2;  // eigenvector items per thread: ceil(H / ((1024 - 64) / (M / 2))) <= 2
+  const int M = m + (m & 1), H = M / 2, hp = M / 2;
+  const int npair = H * (H + 1) / 2;
+  double* PL = sm;                                // [2][4][npair]
+  double* VP = PL + 8 * npair;                    // [2][M][M]
+  double2* CS = (double2*)(VP + 2 * M * M);       // [2][H] (c, s)
+  double2* DD = CS + 2 * H;                       // [2][H] pair diagonals after the rotation
+  double* dpos = (double*)(DD + 2 * H);           // [M]
+  double* red = dpos + M;
+  int* flag = (int*)(red + 32);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63;
+  const bool w0 = tid < 64;
+
+  auto a_at = [&](int i, int j) -> double {
+    if (i >= m || j >= m) return 0.0;
+    double v = 0.0;
+    for (int ks = 0; ks < nparts; ++ks) {
+      const double* g = Ab + (long)ks * pstride;
+      v += 0.5 * (g[(long)i * m + j] + g[(long)j * m + i]);
+    }
+    return v;
+  };
+  double nrm = 0.0;
+  for (int w = tid; w < npair; w += nt) {
+    int l = (int)((sqrtf(8.0f * w + 1.0f) - 1.0f) * 0.5f);
+    while (l * (l + 1) / 2 > w) --l;
+    while ((l + 1) * (l + 2) / 2 <= w) ++l;
+    const int k = w - l * (l + 1) / 2;
+    const double e0 = a_at(k, l), e1 = a_at(k, M - 1 - l), e2 = a_at(M - 1 - k, l), e3 = a_at(M - 1 - k, M - 1 - l);
+    PL[w] = e0; PL[npair + w] = e1; PL[2 * npair + w] = e2; PL[3 * npair + w] = e3;
+    nrm += (k == l) ? e0 * e0 + 2.0 * e1 * e1 + e3 * e3 : 2.0 * (e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3);
+  }
+  for (int t = tid; t < M * M; t += nt) VP[t] = ((t / M) == (t % M)) ? 1.0 : 0.0;
+  nrm = wave_sum(nrm);
+  if ((tid & 63) == 0) red[tid >> 6] = nrm;
+  __syncthreads();
+  double fro = 0.0;
+  for (int w = 0; w < (nt >> 6); ++w) fro += red[w];
+  fro = sqrt(fro);
+  const double eps = 2.220446049250313e-16, eps2 = eps * eps;
+  const double floor_abs = eps * fro;
+
+  // This thread's block. The block holding the indices that meet in slot kp next
+  // round joins slots a = slot(js_next(kp)) and b = slot(js_next(M-1-kp)); these are
+  // (k, k+2) for k <= H-3, (0, 1) and (H-2, H-1). Wave 0 lane kp takes it; waves
+  // 1.. take the other blocks in column order (column l >= 1 starts at index
+  // 1 + (l-1) l / 2 of that order).
+  int bk = -1, bl = -1, sel = 0, pa = 0, psa = 0, pb = 0, psb = 0;
+  if (w0) {
+    if (lane < H) {
+      const int x = js_next(lane, M), y = js_next(M - 1 - lane, M);
+      pa = x < H ? x : M - 1 - x; psa = x < H ? 0 : 1;
+      pb = y < H ? y : M - 1 - y; psb = y < H ? 0 : 1;
+      bk = min(pa, pb); bl = max(pa, pb);
+      sel = pa < pb ? psa * 2 + psb : psb * 2 + psa;
+    }
+  } else {
+    const int j = tid - 64;
+    if (j == 0) {
+      bk = 0; bl = 0;
+    } else if (j < npair - H) {
+      int l = 1;
+      while (l + 1 < H && 1 + l * (l + 1) / 2 <= j) ++l;
+      const int r = j - (1 + (l - 1) * l / 2);
+      bl = l;
+      if (l == 1) bk = 1;
+      else if (l == H - 1) bk = r < H - 3 ? r : r + 2;
+      else bk = r < l - 2 ? r : r + 1;
+    }
+  }
+  const bool has_blk = bk >= 0;
+  int myb = 0, d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+  if (has_blk) {
+    myb = js_blk(bk, bl);
+    d0 = js_dest(bk, bl, M, H, npair);
+    d1 = js_dest(bk, M - 1 - bl, M, H, npair);
+    d2 = js_dest(M - 1 - bk, bl, M, H, npair);
+    d3 = js_dest(M - 1 - bk, M - 1 - bl, M, H, npair);
+  }
+  // eigenvector items (waves 1..): row pair vr, slots vrg, vrg + RG
+  const int RG = (nt - 64) / hp;
+  const int vr = (tid - 64) % hp, vrg = (tid - 64) / hp;
+  int vs0[VJ], vs1[VJ], vd0[VJ], vd1[VJ], vk[VJ];
+#pragma unroll
+  for (int j = 0; j < VJ; ++j) {
+    const int k = vrg + j * RG;
+    vk[j] = (!w0 && vrg < RG && k < H) ? k : -1;
+    const int kk = vk[j] < 0 ? 0 : k;
+    vs0[j] = kk * hp + vr; vs1[j] = (M - 1 - kk) * hp + vr;
+    vd0[j] = js_prev(kk, M) * hp + vr; vd1[j] = js_prev(M - 1 - kk, M) * hp + vr;
+  }
+  for (int k = tid; k < H; k += nt) {
+    const int w = js_blk(k, k);
+    const double app = PL[w], apq = PL[npair + w], aqq = PL[3 * npair + w];
+    double c, s, t;
+    js_rot(apq, app, aqq, eps2, floor_abs, c, s, t);
+    CS[k] = make_double2(c, s);
+    DD[k] = make_double2(app - t * apq, aqq + t * apq);
+  }
+
+  int sweeps = 0, rc = 0;
+  bool converged = false;
+  for (;;) {
+    // any off-diagonal entry above its threshold?
+    const double* src = PL + (rc & 1) * 4 * npair;
+    if (tid == 0) *flag = 0;
+    for (int k = tid; k < H; k += nt) {
+      const int w = js_blk(k, k);
+      dpos[k] = src[w];
+      dpos[M - 1 - k] = src[3 * npair + w];
+    }
+    __syncthreads();
+    if (has_blk) {
+      bool big = false;
+      auto test = [&](double apq, int i, int j) {
+        big |= apq * apq > eps2 * fabs(dpos[i] * dpos[j]) && fabs(apq) > floor_abs;
+      };
+      const int kL = bk, kR = M - 1 - bk, lL = bl, lR = M - 1 - bl;
+      if (bk == bl) {
+        test(src[npair + myb], kL, kR);
+      } else {
+        test(src[myb], kL, lL); test(src[npair + myb], kL, lR);
+        test(src[2 * npair + myb], kR, lL); test(src[3 * npair + myb], kR, lR);
+      }
+      if (big) *flag = 1;
+    }
+    __syncthreads();
+    if (*flag == 0) { converged = true; break; }
+    if (sweeps >= max_sweeps) break;
+    ++sweeps;
+    for (int step = 0; step < M - 1; ++step, ++rc) {
+      const int bb = rc & 1;
+      const double* S = PL + bb * 4 * npair;
+      double* D = PL + (bb ^ 1) * 4 * npair;
+      const double2* Vs = (const double2*)(VP + bb * M * M);
+      double2* Vd = (double2*)(VP + (bb ^ 1) * M * M);
+      const double2* cs_ = CS + bb * H;
+      const double2* dd_ = DD + bb * H;
+      if (!w0) {
+        double2 c_[VJ], x0[VJ], x1[VJ];
+#pragma unroll
+        for (int j = 0; j < VJ; ++j)
+          if (vk[j] >= 0) { c_[j] = cs_[vk[j]]; x0[j] = Vs[vs0[j]]; x1[j] = Vs[vs1[j]]; }
+        if (has_blk) {
+          if (bk == bl) {
+            const double2 dk = dd_[bk];
+            const bool act = cs_[bk].y != 0.0;
+            D[d0] = dk.x;
+            D[d1] = act ? 0.0 : S[npair + myb];
+            D[d3] = dk.y;
+          } else {
+            const double2 k2 = cs_[bk], l2 = cs_[bl];
+            const double m00 = S[myb], m01 = S[npair + myb], m10 = S[2 * npair + myb], m11 = S[3 * npair + myb];
+            const double r00 = k2.x * m00 - k2.y * m10, r01 = k2.x * m01 - k2.y * m11;
+            const double r10 = k2.y * m00 + k2.x * m10, r11 = k2.y * m01 + k2.x * m11;
+            D[d0] = r00 * l2.x - r01 * l2.y;
+            D[d1] = r00 * l2.y + r01 * l2.x;
+            D[d2] = r10 * l2.x - r11 * l2.y;
+            D[d3] = r10 * l2.y + r11 * l2.x;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < VJ; ++j)
+          if (vk[j] >= 0) {
+            const double c = c_[j].x, s = c_[j].y;
+            Vd[vd0[j]] = make_double2(c * x0[j].x - s * x1[j].x, c * x0[j].y - s * x1[j].y);
+            Vd[vd1[j]] = make_double2(s * x0[j].x + c * x1[j].x, s * x0[j].y + c * x1[j].y);
+          }
+      } else if (has_blk) {
+        const double2 k2 = cs_[bk], l2 = cs_[bl];
+        const double2 da = dd_[pa], db = dd_[pb];
+        const double m00 = S[myb], m01 = S[npair + myb], m10 = S[2 * npair + myb], m11 = S[3 * npair + myb];
+        const double r00 = k2.x * m00 - k2.y * m10, r01 = k2.x * m01 - k2.y * m11;
+        const double r10 = k2.y * m00 + k2.x * m10, r11 = k2.y * m01 + k2.x * m11;
+        const double n00 = r00 * l2.x - r01 * l2.y, n01 = r00 * l2.y + r01 * l2.x;
+        const double n10 = r10 * l2.x - r11 * l2.y, n11 = r10 * l2.y + r11 * l2.x;
+        D[d0] = n00; D[d1] = n01; D[d2] = n10; D[d3] = n11;
+        const double apq = sel == 0 ? n00 : sel == 1 ? n01 : sel == 2 ? n10 : n11;
+        const double app = psa ? da.y : da.x, aqq = psb ? db.y : db.x;
+        double c, s, t;
+        js_rot(apq, app, aqq, eps2, floor_abs, c, s, t);
+        CS[(bb ^ 1) * H + lane] = make_double2(c, s);
+        DD[(bb ^ 1) * H + lane] = make_double2(app - t * apq, aqq + t * apq);
+      }
+      __syncthreads();
+    }
+  }
+  // eigenpairs by position, ascending; with m odd the padding index sits at the
+  // position that holds index M-1 after rc moves
+  const int ph = (m & 1) ? (M - 2 - rc % (M - 1) + (M - 1)) % (M - 1) + 1 : -1;
+  const double* src = PL + (rc & 1) * 4 * npair;
+  const double* Vf = VP + (rc & 1) * M * M;
+  for (int k = tid; k < H; k += nt) {
+    const int w = js_blk(k, k);
+    dpos[k] = src[w];
+    dpos[M - 1 - k] = src[3 * npair + w];
+  }
+  __syncthreads();
+  for (int i = tid; i < M; i += nt) {
+    if (i == ph) continue;
+    const double di = dpos[i];
+    int rank = 0;
+    for (int j = 0; j < M; ++j)
+      if (j != ph) rank += (dpos[j] < di) || (dpos[j] == di && j < i);
+    evals[rank] = di;
+    for (int r = 0; r < m; ++r) Vout[(long)r * m + rank] = Vf[(long)i * M + r];
+  }
+  if (tid == 0) info[0] = converged ? sweeps : -(sweeps + 1);
+}
+
 __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, const double* __restrict__ Ain, long sA,
                                                              int nparts, long pstride,
                                                              double* __restrict__ evals, long sE,
@@ -835,21 +1099,35 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, const double
                                                              int max_sweeps, int* __restrict__ info) {
   extern __shared__ double sm[];
   const int b = blockIdx.x;
-  jacobi_body(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
-              Vwork + (long)b * m * m, vlds, max_sweeps, info + b, sm);
+  if (m >= JS_MIN && m <= JS_MAX)
+    jacobi_shift_body(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
+                      max_sweeps, info + b, sm);
+  else
+    jacobi_body(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
+                Vwork + (long)b * m * m, vlds, max_sweeps, info + b, sm);
 }
 
 __global__ __launch_bounds__(JAC_THREADS) void jacobi_batched_kernel(const EigDesc* __restrict__ descs,
                                                                      int vlds, int max_sweeps) {
   extern __shared__ double sm[];
   const EigDesc d = descs[blockIdx.x];
-  jacobi_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, d.Vwork, vlds, max_sweeps, d.info, sm);
+  if (d.m >= JS_MIN && d.m <= JS_MAX)
+    jacobi_shift_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, max_sweeps, d.info, sm);
+  else
+    jacobi_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, d.Vwork, vlds, max_sweeps, d.info, sm);
+}
+
+// LDS for a launch whose largest matrix is mmax: either body may run
+static size_t jacobi_launch_lds(int mmax, int vl) {
+  size_t d = jacobi_lds_doubles(mmax, vl);
+  if (mmax >= JS_MIN) d = std::max(d, jacobi_shift_lds_doubles(std::min(mmax, JS_MAX)));
+  return d * sizeof(double);
 }
 
 void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax) {
   if (P <= 0) return;
   const int vl = jacobi_v_in_lds(mmax) ? 1 : 0;
-  size_t lds = jacobi_lds_doubles(mmax, vl) * sizeof(double);
+  size_t lds = jacobi_launch_lds(mmax, vl);
   hipLaunchKernelGGL(jacobi_batched_kernel, dim3(P), dim3(JAC_THREADS), lds, s, d, vl, 40);
 }
 
@@ -960,7 +1238,7 @@ void linalg_set_attrs() {
 void jacobi_eig(hipStream_t s, int batch, int m, const double* A, long sA, int nparts,
                 long pstride, double* evals, long sE, double* V, long sV, double* Vwork, int* info) {
   const int vl = jacobi_v_in_lds(m) ? 1 : 0;
-  size_t lds = jacobi_lds_doubles(m, vl) * sizeof(double);
+  size_t lds = jacobi_launch_lds(m, vl);
   hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(JAC_THREADS), lds, s, m, A, sA,
                      nparts < 1 ? 1 : nparts, pstride, evals, sE, V, sV, Vwork, vl, 40, info);
 }
