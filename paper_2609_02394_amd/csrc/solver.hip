@@ -131,6 +131,9 @@ struct BP {
   double prev_worst = INFINITY, prev_expect = 1.0, scale = 1.0, a = 0, b = 0, c = 0, e = 1, sigma1 = 0;
   int shifted = 0;
   int slow = 0;  // consecutive filters far short of their damping, not rounding-limited
+  // CholeskyQR flags to read with the next state: 1 after a two-pass orthonormalisation
+  // (role ortho_r), 2 after a third pass
+  int ortho_check = 0, ortho_r = 0;
 };
 
 struct Batch {
@@ -486,8 +489,9 @@ const double* reduce_parts(Batch& B, const std::vector<BP*>& L) {
   return L[0]->Pm;  // non-null marker: every problem's sum is in its own Pm
 }
 
-// One CholeskyQR pass from role src to role dst for the problems of L.
-void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst) {
+// One CholeskyQR pass from role src to role dst for the problems of L; the Cholesky
+// kernel leaves its failure flag in info[slot] and its shift flag in info[slot + 1].
+void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst, int slot) {
   const double u = 1.1102230246251565e-16;
   std::vector<const double*> A;
   std::vector<int> ca;
@@ -502,7 +506,7 @@ void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst) {
   for (BP* p : L) {
     CholDesc c{};
     c.m = p->cnt; c.nparts = G ? 1 : B.KS; c.G = G ? p->Pm : p->kwork; c.pstride = (long)p->cnt * p->cnt;
-    c.Linv = p->Linv; c.info = p->info + 2;  // info[2]: failure, info[3]: shifted
+    c.Linv = p->Linv; c.info = p->info + slot;
     c.shift = 11.0 * ((double)p->n * p->cnt + (double)p->cnt * (p->cnt + 1)) * u * p->cnt;
     cd.push_back(c);
     mm = std::max(mm, p->cnt);
@@ -526,7 +530,7 @@ void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst) {
 
 // Orthonormalise the cnt rows at Y[r] of each problem against its locked rows
 // X[0..nlock), then among themselves. The result ends in Y[r].
-void orthonormalize(Batch& B, const std::vector<BP*>& L, const std::vector<int>& idx, int r) {
+void orthonormalize(Batch& B, const std::vector<BP*>& L, int r) {
   std::vector<VecDesc> nd;
   for (BP* p : L) {
     VecDesc v{};
@@ -572,29 +576,14 @@ void orthonormalize(Batch& B, const std::vector<BP*>& L, const std::vector<int>&
     }
     vec_launch(B, VEC_NORMALIZE, nd2);
   }
+  // CholeskyQR2; its flags are read with the next state (ortho_fixup), so that the
+  // common case costs no host round trip
   const int sp = (r == 0) ? 1 : 0;
-  cholqr_pass(B, L, r, sp);
-  // a pivot failure of the first pass (retried with a shift in the kernel) calls
-  // for a third pass
-  read_state(B);
-  std::vector<BP*> L3;
-  for (size_t i = 0; i < L.size(); ++i) {
-    RMC_CHECK(info_of(B, idx[i], 2) == 0, RMC_ERR_NOCONV, "CholeskyQR failed even with a shift");
-    if (info_of(B, idx[i], 3)) {
-      L3.push_back(L[i]);
-      L[i]->shifted++;
-    }
-  }
-  cholqr_pass(B, L, sp, r);
-  if (!L3.empty()) {
-    cholqr_pass(B, L3, r, sp);
-    std::vector<VecDesc> cp;
-    for (BP* p : L3) {
-      VecDesc v{};
-      v.nv = p->cnt; v.n = p->n; v.out = role_ptr(p, r); v.P = role_ptr(p, sp);
-      cp.push_back(v);
-    }
-    vec_launch(B, VEC_COPY, cp);
+  cholqr_pass(B, L, r, sp, 2);
+  cholqr_pass(B, L, sp, r, 4);
+  for (BP* p : L) {
+    p->ortho_check = 1;
+    p->ortho_r = r;
   }
 }
 
@@ -666,6 +655,47 @@ void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full)
     rd.push_back(v);
   }
   vec_launch(B, VEC_RESIDUAL, rd);
+}
+
+// After a state read: a failed Cholesky (even with its shift) is an error; problems
+// whose first CholeskyQR pass needed the shift (shifted CholeskyQR) get the third pass
+// and their Rayleigh-Ritz again. Returns true when the state must be read again.
+bool ortho_fixup(Batch& B, const std::vector<BP*>& probs) {
+  std::vector<BP*> L3;
+  for (size_t i = 0; i < probs.size(); ++i) {
+    BP* p = probs[i];
+    const int chk = p->ortho_check;
+    p->ortho_check = 0;
+    if (chk == 1) {
+      RMC_CHECK(info_of(B, (int)i, 2) == 0 && info_of(B, (int)i, 4) == 0, RMC_ERR_NOCONV,
+                "CholeskyQR failed even with a shift");
+      if (info_of(B, (int)i, 3)) L3.push_back(p);
+    } else if (chk == 2) {
+      RMC_CHECK(info_of(B, (int)i, 6) == 0, RMC_ERR_NOCONV, "CholeskyQR failed even with a shift");
+    }
+  }
+  if (L3.empty()) return false;
+  for (int r = 0; r < 2; ++r) {
+    std::vector<BP*> Lr;
+    for (BP* p : L3)
+      if (p->ortho_r == r) Lr.push_back(p);
+    if (Lr.empty()) continue;
+    const int sp = r == 0 ? 1 : 0;
+    cholqr_pass(B, Lr, r, sp, 6);
+    std::vector<VecDesc> cp;
+    for (BP* p : Lr) {
+      VecDesc v{};
+      v.nv = p->cnt; v.n = p->n; v.out = role_ptr(p, r); v.P = role_ptr(p, sp);
+      cp.push_back(v);
+      p->shifted++;
+      p->ortho_check = 2;
+      if (getenv("RMC_TRACE_SOLVER"))
+        fprintf(stderr, "[rmc] n=%d it=%d third CholeskyQR pass\n", p->n, p->iters);
+    }
+    vec_launch(B, VEC_COPY, cp);
+    rayleigh_ritz(B, Lr, r, sp, false);
+  }
+  return true;
 }
 
 // Convergence bookkeeping after a state read; returns true if the problem goes on.
@@ -1096,8 +1126,6 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
   DescArena da(ctx, B.st, lane, sc, da_bytes);
   B.da = &da;
 
-  std::vector<int> idx_all(P);
-  for (int i = 0; i < P; ++i) idx_all[i] = i;
   {
     std::vector<StartDesc> sd;
     for (BP* p : probs) {
@@ -1112,13 +1140,14 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
     da.defer([=] { start_batched(st, dd, P, nm, mm); });
   }
   for (BP* p : probs) p->cnt = p->m;
-  orthonormalize(B, probs, idx_all, 0);
+  orthonormalize(B, probs, 0);
   rayleigh_ritz(B, probs, 0, 1, false);
 
   const double tol = o.tol > 0 ? o.tol : 1e-13;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
   for (;;) {
     read_state(B);
+    if (ortho_fixup(B, probs)) read_state(B);
     std::vector<BP*> act;
     std::vector<int> ai;
     static const bool trace = getenv("RMC_TRACE_SOLVER") != nullptr;
@@ -1139,7 +1168,7 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
     // prepares the next phase while the device runs this one
     const int r = filter(B, act);
     B.da->flush();
-    orthonormalize(B, act, ai, r);
+    orthonormalize(B, act, r);
     B.da->flush();
     rayleigh_ritz(B, act, r, r == 0 ? 1 : 0, false);
     for (BP* p : act) p->iters++;
