@@ -198,10 +198,114 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(int tA, int tB, int k
       }
 }
 
+// The same product for 64 < M <= 80 (a Rayleigh-Ritz block with its guard vectors):
+// one 80 x 64 output tile per workgroup, so M is not padded to two 64-row tiles. Wave
+// w owns columns 16w..16w+15 as five 16 x 16 MFMA tiles down the rows.
+constexpr int G80_M = 80;
+__global__ __launch_bounds__(256) void gemm_grouped80_kernel(int tA, int tB, int ksplit,
+                                                             const GemmDesc* __restrict__ descs) {
+  __shared__ double As[2][GB_K][G80_M + 1];
+  __shared__ double Bs[2][GB_K][GB_N + 1];
+  const GemmDesc d = descs[blockIdx.z / ksplit];
+  const int ks = blockIdx.z % ksplit;
+  const int M = d.M, N = d.N, K = d.K;
+  const int col0 = blockIdx.x * GB_N;
+  if (col0 >= N || M <= 0) return;
+  int kchunk = (K + ksplit - 1) / ksplit;
+  kchunk = ((kchunk + GB_K - 1) / GB_K) * GB_K;
+  if (kchunk < GB_K) kchunk = GB_K;
+  const int kbeg = ks * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  d4 acc[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  double ra[5], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 5; ++e) {
+      const int idx = tid + e * 256;  // < 80 * 16
+      int i, k;
+      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / G80_M; i = idx % G80_M; }
+      const int gk = k0 + k;
+      ra[e] = (i < M && gk < kend) ? (tA ? d.A[(long)gk * d.lda + i] : d.A[(long)i * d.lda + gk]) : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256;
+      int j, kb;
+      if (!tB) { kb = idx / GB_N; j = idx % GB_N; } else { j = idx / GB_K; kb = idx % GB_K; }
+      const int gj = col0 + j, gkb = k0 + kb;
+      rb[e] = (gj < N && gkb < kend) ? (tB ? d.B[(long)gj * d.ldb + gkb] : d.B[(long)gkb * d.ldb + gj]) : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 5; ++e) {
+      const int idx = tid + e * 256;
+      int i, k;
+      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / G80_M; i = idx % G80_M; }
+      As[buf][k][i] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256;
+      int j, kb;
+      if (!tB) { kb = idx / GB_N; j = idx % GB_N; } else { j = idx / GB_K; kb = idx % GB_K; }
+      Bs[buf][kb][j] = rb[e];
+    }
+  };
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
+      const bool more = k0 + GB_K < kend;
+      if (more) load(k0 + GB_K);
+#pragma unroll
+      for (int kk = 0; kk < GB_K; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        const double b = Bs[buf][kr][wave * 16 + (lane & 15)];
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[buf][kr][t * 16 + (lane & 15)], b, acc[t], 0, 0, 0);
+      }
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  const bool parts = d.work != nullptr;
+  double* P = parts ? d.work + (long)ks * M * N : nullptr;
+  const int gj = col0 + wave * 16 + (lane & 15);
+#pragma unroll
+  for (int t = 0; t < 5; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gi = t * 16 + 4 * r + (lane >> 4);
+      if (gi < M && gj < N) {
+        double v = d.alpha * acc[t][r];
+        if (parts) {
+          P[(long)gi * N + gj] = v;
+        } else {
+          if (d.beta != 0.0) v += d.beta * d.C[(long)gi * d.ldc + gj];
+          d.C[(long)gi * d.ldc + gj] = v;
+        }
+      }
+    }
+}
+
 void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int Mmax, int Nmax,
                   int ksplit) {
   if (P <= 0 || Mmax <= 0 || Nmax <= 0) return;
   if (ksplit < 1) ksplit = 1;
+  if (Mmax > GB_M && Mmax <= G80_M) {
+    dim3 grid((Nmax + GB_N - 1) / GB_N, 1, P * ksplit);
+    hipLaunchKernelGGL(gemm_grouped80_kernel, grid, dim3(256), 0, s, (int)tA, (int)tB, ksplit, d);
+    return;
+  }
   dim3 grid((Nmax + GB_N - 1) / GB_N, (Mmax + GB_M - 1) / GB_M, P * ksplit);
   hipLaunchKernelGGL(gemm_grouped_kernel, grid, dim3(256), 0, s, (int)tA, (int)tB, ksplit, d);
 }
@@ -212,12 +316,14 @@ void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int
 // its 16x16 output tiles with FP64 MFMA. Lane group g takes the K run 8g..8g+7 of a
 // chunk (the order of K inside an MFMA step is free), so operands are contiguous
 // LDS reads. Rows past ca / cb are staged as zeros. A slice past n writes zeros.
-constexpr int GR_KC = 32, GR_PW = GR_KC + 2, GR_ROWS = 192;
+// For A A^T only the tiles on and above the diagonal are formed and each is written
+// to both triangles. ROWS bounds ca, cb (LDS is sized for it).
+constexpr int GR_KC = 32, GR_PW = GR_KC + 2;
 
-template <int TPW>
+template <int TPW, int ROWS>
 __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ descs, int ks) {
-  __shared__ double As[GR_ROWS * GR_PW];
-  __shared__ double Bs[GR_ROWS * GR_PW];
+  __shared__ double As[ROWS * GR_PW];
+  __shared__ double Bs[ROWS * GR_PW];
   const GramDesc d = descs[blockIdx.y];
   const int ca = d.ca, cb = d.cb, n = d.n;
   if (ca <= 0 || cb <= 0) return;
@@ -226,9 +332,17 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
   lk = ((lk + GR_KC - 1) / GR_KC) * GR_KC;
   const int k0 = s * lk, k1 = min(n, k0 + lk);
   const bool same = d.A == d.B && ca == cb;
-  const int TA = (ca + 15) / 16, TB = (cb + 15) / 16, nt = TA * TB;
+  const int TA = (ca + 15) / 16, TB = (cb + 15) / 16;
+  const int nt = same ? TA * (TA + 1) / 2 : TA * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
+  // output tile of slot i: row-major over TA x TB, or the upper triangle row by row
+  auto tile_of = [&](int t, int& tr, int& tc) {
+    if (!same) { tr = t / TB; tc = t % TB; return; }
+    int r = 0, left = t;
+    while (left >= TA - r) { left -= TA - r; ++r; }
+    tr = r; tc = r + left;
+  };
   d4 acc[TPW];
 #pragma unroll
   for (int i = 0; i < TPW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
@@ -249,7 +363,8 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
     for (int i = 0; i < TPW; ++i) {
       const int t = wave + 8 * i;
       if (t >= nt) break;
-      const int tr = t / TB, tc = t % TB;
+      int tr, tc;
+      tile_of(t, tr, tc);
       const double* ar = As + (tr * 16 + l16) * GR_PW + 8 * g;
       const double* br = Bsrc + (tc * 16 + l16) * GR_PW + 8 * g;
       double av[8], bv[8];
@@ -270,12 +385,16 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
   for (int i = 0; i < TPW; ++i) {
     const int t = wave + 8 * i;
     if (t >= nt) break;
-    const int tr = t / TB, tc = t % TB;
+    int tr, tc;
+    tile_of(t, tr, tc);
     const int col = tc * 16 + l16;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = tr * 16 + 4 * r + g;  // FP64 accumulator layout
-      if (row < ca && col < cb) out[(long)row * cb + col] = acc[i][r];
+      if (row < ca && col < cb) {
+        out[(long)row * cb + col] = acc[i][r];
+        if (same && tr != tc) out[(long)col * cb + row] = acc[i][r];
+      }
     }
   }
 }
@@ -284,10 +403,10 @@ void gram_batched(hipStream_t s, const GramDesc* d, int P, int ks, int cmax) {
   if (P <= 0 || cmax <= 0) return;
   if (ks < 1) ks = 1;
   const int t = (cmax + 15) / 16;
-  if (t * t <= 8 * 5)
-    hipLaunchKernelGGL(gram_kernel<5>, dim3(ks, P), dim3(512), 0, s, d, ks);
+  if (t <= 5)
+    hipLaunchKernelGGL((gram_kernel<4, 80>), dim3(ks, P), dim3(512), 0, s, d, ks);
   else
-    hipLaunchKernelGGL(gram_kernel<18>, dim3(ks, P), dim3(512), 0, s, d, ks);
+    hipLaunchKernelGGL((gram_kernel<18, 192>), dim3(ks, P), dim3(512), 0, s, d, ks);
 }
 
 int gemm_pick_ksplit(int M, int N, int K, int batch) {

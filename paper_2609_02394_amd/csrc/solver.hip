@@ -1090,7 +1090,7 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
   const int P = (int)probs.size();
   // K-slices of the Gram products: enough workgroups to cover the chip, slices of at
   // least 128 columns
-  B.KS = std::max(1, std::min({64, (384 + P - 1) / P, std::max(1, B.nmax / 128)}));
+  B.KS = std::max(1, std::min({64, (512 + P - 1) / P, std::max(1, B.nmax / 128)}));
   B.trs = 2 * B.mmax + 4;  // theta, res, then room for 8 ints
   B.TR = sc.get<double>((size_t)P * B.trs);
   B.TRh.assign((size_t)P * B.trs, 0.0);
