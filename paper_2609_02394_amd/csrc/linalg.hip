@@ -605,6 +605,23 @@ void vec_max(hipStream_t s, int n, const double* v, double* out) {
   hipLaunchKernelGGL(vec_max_kernel, dim3(1), dim3(256), 0, s, n, v, out);
 }
 
+// 1/sqrt(x) and 1/x for x > 0 (normal range): the hardware estimates refined by two
+// Newton steps (each one squares the relative error). Only the rotation's c stays
+// tied to working precision through these (c^2 (1 + t^2) = 1); an inexact t leaves
+// a slightly larger off-diagonal entry for the next sweep.
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  y = y * (2.0 - x * y);
+  return y;
+}
+
 // ---------------------------------------------------------------------------
 // Cholesky + in-place inverse of the lower factor, one 1024-thread workgroup
 // (a 32 x 32 thread grid), packed lower triangle in LDS (m <= 192 -> at most
@@ -685,6 +702,146 @@ __device__ void chol_inv_body(int m, const double* __restrict__ G, int nparts, l
   }
 }
 
+// The same factorisation and inverse for m <= 80 by 8-wide blocks, so that a panel
+// costs three barriers instead of eight steps of two. Matrix in LDS with an odd row
+// stride, padded to a multiple of 8 with the identity. Per panel: wave 0 factors the
+// 8 x 8 diagonal block in registers (lane (r, c), shuffles), the rows below are solved
+// against it, then the trailing matrix takes the rank-8 update. The inverse X = L^{-1}
+// goes to the unused upper triangle (X[i][j] at (j, i)) and its diagonal to xd: the
+// diagonal blocks first (one wave each), then the blocks below them one block
+// diagonal at a time, X_IJ = -X_II (sum_{J <= K < I} L_IK X_KJ).
+constexpr int CB_MAX = 80;
+size_t chol_blocked_lds_bytes(int m) {
+  const int mp = (m + 7) & ~7;
+  return ((size_t)mp * (mp + 1) + 2 * (size_t)mp + 2) * sizeof(double);
+}
+
+__device__ __forceinline__ void chol_blocked_body(int m, const double* __restrict__ G, int nparts, long pstride,
+                                                  double shift, double* __restrict__ Linv,
+                                                  int* __restrict__ info, double* sm) {
+  const int mp = (m + 7) & ~7, nb = mp / 8, LD = mp + 1;
+  double* A = sm;            // [mp][LD]
+  double* xd = A + mp * LD;  // diagonal of X
+  double* rd = xd + mp;      // 1 / L[i][i]
+  int* flag = (int*)(rd + mp);
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const int r8 = lane >> 3, c8 = lane & 7;
+  for (int t = tid; t < mp * mp; t += nt) {
+    const int i = t / mp, j = t % mp;
+    if (j > i) continue;
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < m) {
+      v = 0.0;
+      for (int ks = 0; ks < nparts; ++ks) {
+        const double* g = G + (long)ks * pstride;
+        v += 0.5 * (g[(long)i * m + j] + g[(long)j * m + i]);
+      }
+      if (i == j) v += shift;
+    }
+    A[i * LD + j] = v;
+  }
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  for (int J = 0; J < nb; ++J) {
+    const int j0 = 8 * J;
+    if (wave == 0) {
+      double D = (c8 <= r8) ? A[(j0 + r8) * LD + j0 + c8] : 0.0;
+      bool bad = false;
+      for (int k = 0; k < 8; ++k) {
+        const double dkk = __shfl(D, k * 9, 64);
+        if (!(dkk > 0.0)) { bad = true; break; }
+        const double inv = rsqrt_nr(dkk);
+        if (c8 == k) D = (r8 == k) ? dkk * inv : (r8 > k ? D * inv : D);
+        const double lrk = __shfl(D, r8 * 8 + k, 64);
+        const double lck = __shfl(D, c8 * 8 + k, 64);
+        if (r8 > k && c8 > k && c8 <= r8) D -= lrk * lck;
+        if (lane == 0) rd[j0 + k] = inv;
+      }
+      if (bad) {
+        if (lane == 0) *flag = 1;
+      } else if (c8 <= r8) {
+        A[(j0 + r8) * LD + j0 + c8] = D;
+      }
+    }
+    __syncthreads();
+    if (*flag) break;
+    // rows below the block: x L_JJ^T = a
+    for (int i = j0 + 8 + tid; i < mp; i += nt) {
+      double x[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) x[c] = A[i * LD + j0 + c];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        double a = x[c];
+#pragma unroll
+        for (int k = 0; k < c; ++k) a -= x[k] * A[(j0 + c) * LD + j0 + k];
+        x[c] = a * rd[j0 + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) A[i * LD + j0 + c] = x[c];
+    }
+    __syncthreads();
+    // trailing rank-8 update
+    const int t0 = j0 + 8, nr = mp - t0;
+    for (int e = tid; e < nr * nr; e += nt) {
+      const int i = t0 + e / nr, k = t0 + e % nr;
+      if (k > i) continue;
+      double acc = A[i * LD + k];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc -= A[i * LD + j0 + c] * A[k * LD + j0 + c];
+      A[i * LD + k] = acc;
+    }
+    __syncthreads();
+  }
+  if (*flag) {
+    if (tid == 0) info[0] = 1;
+    return;
+  }
+  // diagonal blocks of X, wave J
+  if (wave < nb) {
+    const int j0 = 8 * wave;
+    double X = (r8 == c8) ? rd[j0 + r8] : 0.0;
+    for (int rr = 1; rr < 8; ++rr) {
+      double acc = 0.0;
+      for (int k = 0; k < rr; ++k) {
+        const double xkc = __shfl(X, k * 8 + c8, 64);
+        if (k >= c8) acc += A[(j0 + rr) * LD + j0 + k] * xkc;
+      }
+      if (r8 == rr && c8 < rr) X = -acc * rd[j0 + rr];
+    }
+    if (c8 < r8) A[(j0 + c8) * LD + j0 + r8] = X;
+    else if (c8 == r8) xd[j0 + r8] = X;
+  }
+  __syncthreads();
+  // blocks (J + d, J), one wave each
+  for (int d = 1; d < nb; ++d) {
+    const int J = wave;
+    if (J < nb - d) {
+      const int I = J + d, i0 = 8 * I, j0 = 8 * J;
+      double T = 0.0;
+      for (int a = j0; a < i0; ++a) {
+        const int b = j0 + c8;
+        const double xab = a > b ? A[b * LD + a] : (a == b ? xd[a] : 0.0);
+        T += A[(i0 + r8) * LD + a] * xab;
+      }
+      double X = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double tkc = __shfl(T, k * 8 + c8, 64);
+        const double xrk = k < r8 ? A[(i0 + k) * LD + i0 + r8] : (k == r8 ? xd[i0 + r8] : 0.0);
+        X -= xrk * tkc;
+      }
+      A[(j0 + c8) * LD + i0 + r8] = X;
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < m * m; t += nt) {
+    const int i = t / m, j = t % m;
+    Linv[t] = j < i ? A[j * LD + i] : (j == i ? xd[i] : 0.0);
+  }
+  if (tid == 0) info[0] = 0;
+}
+
 __global__ __launch_bounds__(CHOL_THREADS) void chol_inv_kernel(int m, const double* __restrict__ G, int nparts,
                                                                 long pstride, double shift,
                                                                 double* __restrict__ Linv, int* __restrict__ info) {
@@ -705,12 +862,15 @@ __global__ __launch_bounds__(CHOL_THREADS) void chol_batched_kernel(const CholDe
   const CholDesc d = descs[blockIdx.x];
   double* L = sm;
   double* col = sm + d.m * (d.m + 1) / 2;
-  chol_inv_body(d.m, d.G, d.nparts, d.pstride, 0.0, d.Linv, d.info, L, col);
+  const bool blk = d.m <= CB_MAX;
+  if (blk) chol_blocked_body(d.m, d.G, d.nparts, d.pstride, 0.0, d.Linv, d.info, sm);
+  else chol_inv_body(d.m, d.G, d.nparts, d.pstride, 0.0, d.Linv, d.info, L, col);
   __syncthreads();
   const int failed = d.info[0];
   __syncthreads();
   if (failed) {  // shifted CholeskyQR: retry with the shift, flag it in info[1]
-    chol_inv_body(d.m, d.G, d.nparts, d.pstride, d.shift, d.Linv, d.info, L, col);
+    if (blk) chol_blocked_body(d.m, d.G, d.nparts, d.pstride, d.shift, d.Linv, d.info, sm);
+    else chol_inv_body(d.m, d.G, d.nparts, d.pstride, d.shift, d.Linv, d.info, L, col);
     if (threadIdx.x == 0) d.info[1] = 1;
   } else if (threadIdx.x == 0) {
     d.info[1] = 0;
@@ -719,7 +879,8 @@ __global__ __launch_bounds__(CHOL_THREADS) void chol_batched_kernel(const CholDe
 
 void chol_batched(hipStream_t s, const CholDesc* d, int P, int mmax) {
   if (P <= 0) return;
-  hipLaunchKernelGGL(chol_batched_kernel, dim3(P), dim3(CHOL_THREADS), chol_lds_bytes(mmax), s, d);
+  const size_t lds = std::max(chol_lds_bytes(mmax), chol_blocked_lds_bytes(std::min(mmax, CB_MAX)));
+  hipLaunchKernelGGL(chol_batched_kernel, dim3(P), dim3(CHOL_THREADS), lds, s, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -749,22 +910,6 @@ size_t jacobi_lds_doubles(int m, bool vlds) {
 }
 static bool jacobi_v_in_lds(int m) { return jacobi_lds_doubles(m, true) * 8 <= 156 * 1024; }
 
-// 1/sqrt(x) and 1/x for x > 0 (normal range): the hardware estimates refined by two
-// Newton steps (each one squares the relative error). Only the rotation's c stays
-// tied to working precision through these (c^2 (1 + t^2) = 1); an inexact t leaves
-// a slightly larger off-diagonal entry for the next sweep.
-__device__ inline double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * (1.5 - 0.5 * x * y * y);
-  y = y * (1.5 - 0.5 * x * y * y);
-  return y;
-}
-__device__ inline double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = y * (2.0 - x * y);
-  y = y * (2.0 - x * y);
-  return y;
-}
 
 // Parallel cyclic Jacobi (round-robin ordering: M-1 rounds of M/2 disjoint pairs per
 // sweep), one 1024-thread workgroup, A packed in LDS. Each round has two phases

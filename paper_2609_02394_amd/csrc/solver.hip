@@ -641,8 +641,8 @@ void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full)
     d.C = full ? p->E : p->HX + off;
     g2.push_back(d);
   }
+  g1.insert(g1.end(), g2.begin(), g2.end());  // X and H X in one launch
   gemm_launch(B, true, false, g1, 1);
-  gemm_launch(B, true, false, g2, 1);
   std::vector<VecDesc> rd;
   for (BP* p : L) {
     const size_t off = full ? 0 : (size_t)p->nlock * p->n;
