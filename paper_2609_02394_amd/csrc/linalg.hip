@@ -1417,9 +1417,11 @@ __global__ __launch_bounds__(256) void vec_batched_kernel(int op, const VecDesc*
       const double* hx = d.P + (long)j * n;
       const double* x = d.Q + (long)j * n;
       const double th = d.a[j];
+      double* rout = d.out ? d.out + (long)j * n : nullptr;
       for (int i = threadIdx.x; i < n; i += 256) {
         double r = hx[i] - th * x[i];
         acc += r * r;
+        if (rout) rout[i] = r;
       }
       double nr = sqrt(block_sum256(acc, red));
       if (threadIdx.x == 0) d.norms[j] = nr;

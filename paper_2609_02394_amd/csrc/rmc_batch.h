@@ -103,7 +103,7 @@ enum VecOp {
 };
 struct VecDesc {
   int nv, n;
-  double* out;        // NORMALIZE: rows to normalise; others: output
+  double* out;        // NORMALIZE: rows to normalise; RESIDUAL: the residual rows (nullable); others: output
   const double* P;    // RESIDUAL: HX; SCALE_ADD: P; COPY: src; AXPY3: Y
   const double* Q;    // RESIDUAL: X;  SCALE_ADD: Q (nullable); AXPY3: Xprev (nullable)
   const double* a;    // RESIDUAL: theta; SCALE_ADD: per-row scale

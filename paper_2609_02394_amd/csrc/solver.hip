@@ -151,6 +151,9 @@ struct Batch {
 
 // Row-block roles: 0..2 = Y[i], 3 = X + nlock rows, 4 = HX + nlock rows, 5 = E,
 // 6 = X (row 0), 7 = HX (row 0).
+// defect rows E of the active block (E is kept for every row of the block)
+const double* defect_of(const BP* p) { return p->E + (size_t)p->nlock * p->n; }
+
 double* role_ptr(BP* p, int role) {
   switch (role) {
     case 0: case 1: case 2: return p->Y[role];
@@ -652,6 +655,9 @@ void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full)
     v.Q = full ? p->Y[2] : p->X + off;
     v.a = p->theta + (full ? 0 : p->nlock);
     v.norms = p->res + (full ? 0 : p->nlock);
+    // inside the iteration the residual rows are the next filter's defect E = HX - X Theta
+    // (E holds every row of the block; the filter starts at its own lock count)
+    v.out = full ? nullptr : p->E + off;
     rd.push_back(v);
   }
   vec_launch(B, VEC_RESIDUAL, rd);
@@ -846,7 +852,7 @@ void fused_filter(Batch& B, const std::vector<BP*>& L, int P, int outr) {
       FilterDesc d{};
       d.kA = op.kA; d.kB = op.kB; d.T = op.T; d.nv = cn; d.vbase = tv;
       d.pack = op.pack[prec]; d.pkm = op.pkm; d.steps = steps;
-      d.Ediag = op.Ediag; d.E = p->E; d.X = role_ptr(p, 3); d.out = p->Y[outr];
+      d.Ediag = op.Ediag; d.E = defect_of(p); d.X = role_ptr(p, 3); d.out = p->Y[outr];
       d.sc = B.da->add(sc);
       d.phi = B.da->add(phi);
       d.r0 = p->sigma1 / p->e;
@@ -933,17 +939,8 @@ int filter(Batch& B, const std::vector<BP*>& L) {
     for (BP* p : L) p->matvecs += p->cnt * P;
     return cur;
   }
-  // Kronecker problems, defect form: E = HX - X Theta on the active rows
-  {
-    std::vector<VecDesc> ed;
-    for (BP* p : L) {
-      VecDesc v{};
-      v.nv = p->cnt; v.n = p->n; v.out = p->E; v.P = role_ptr(p, 3);
-      v.a = p->theta + p->nlock; v.asgn = -1.0; v.b = 1.0; v.Q = role_ptr(p, 4);
-      ed.push_back(v);
-    }
-    vec_launch(B, VEC_SCALE_ADD, ed);
-  }
+  // Kronecker problems, defect form: E = HX - X Theta on the active rows was written by
+  // the last Rayleigh-Ritz step's residual pass (rows from the lock count on: defect_of)
   // buffer that holds the result: the per-step path rotates three buffers
   int outr;
   {
@@ -998,7 +995,7 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr) {
       sgp[i] = p->sigma1;
       tau2[i] = 2.0 / p->sigma1;
       VecDesc v{};
-      v.nv = p->cnt; v.n = p->n; v.out = p->Y[0]; v.P = p->E; v.a = row0; v.asgn = 1.0;
+      v.nv = p->cnt; v.n = p->n; v.out = p->Y[0]; v.P = defect_of(p); v.a = row0; v.asgn = 1.0;
       v.b = 0.0; v.Q = nullptr;
       dd.push_back(v);
     }
@@ -1021,7 +1018,7 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr) {
       a.Y.push_back(role_ptr(p, cur));
       a.out.push_back(role_ptr(p, nw));
       a.prev.push_back(prev >= 0 ? role_ptr(p, prev) : nullptr);
-      a.E.push_back(p->E);
+      a.E.push_back(defect_of(p));
       a.phi.push_back(rowk[i]);
       a.sc.push_back({2.0 * sk1 / p->e, -2.0 * p->c * sk1 / p->e, prev >= 0 ? -sk * sk1 : 0.0});
       a.cnt.push_back(p->cnt);
