@@ -92,6 +92,105 @@ using namespace rmc;
 
 namespace {
 
+// Largest eigenvalue of a coupling before projection, sum_i c_i P_i (x) Q_i on the
+// sites its terms touch (P_i, Q_i one-site operators of the real alphabet). In the
+// merged block the coupling is V^T (this) V for the isometry V of the two kept
+// bases, so its largest eigenvalue is at most this value (Rayleigh quotient), a
+// tighter bound than sum |c_i| when the terms do not align. Dense cyclic Jacobi on
+// the 2^s states, s <= 6 sites; +inf beyond that or for an unknown operator. Cached
+// by the coupling's structure.
+double coupling_top(const rmc_module* A, const rmc_module* B, const rmc_bond_desc* bond) {
+  static std::mutex mu;
+  static std::map<std::string, double> cache;
+  const int T = bond->n_terms;
+  std::vector<std::pair<int, int>> qs;  // (side, site)
+  for (int i = 0; i < T; ++i) {
+    qs.push_back({0, A->ops[bond->opA[i]].site});
+    qs.push_back({1, B->ops[bond->opB[i]].site});
+  }
+  std::sort(qs.begin(), qs.end());
+  qs.erase(std::unique(qs.begin(), qs.end()), qs.end());
+  const int ns = (int)qs.size();
+  if (ns > 6) return INFINITY;
+  auto qubit = [&](int side, int site) {
+    return (int)(std::lower_bound(qs.begin(), qs.end(), std::make_pair(side, site)) - qs.begin());
+  };
+  std::string key;
+  char buf[96];
+  for (int i = 0; i < T; ++i) {
+    const auto& a = A->ops[bond->opA[i]];
+    const auto& b = B->ops[bond->opB[i]];
+    if (a.op < RMC_OP_X || a.op > RMC_OP_Z || b.op < RMC_OP_X || b.op > RMC_OP_Z) return INFINITY;
+    snprintf(buf, sizeof buf, "%a:%d%d:%d%d;", bond->coef[i], qubit(0, a.site), a.op, qubit(1, b.site), b.op);
+    key += buf;
+  }
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  const int D = 1 << ns;
+  std::vector<double> M((size_t)D * D, 0.0);
+  // one-site action on basis bit v: X flips (+1); T flips, +1 from 0 and -1 from 1;
+  // Z keeps, +1 on 0 and -1 on 1
+  auto act = [](int op, int v, int& flip, double& val) {
+    flip = op == RMC_OP_Z ? 0 : 1;
+    val = (op == RMC_OP_X || v == 0) ? 1.0 : -1.0;
+  };
+  for (int i = 0; i < T; ++i) {
+    const int qa = qubit(0, A->ops[bond->opA[i]].site), qb = qubit(1, B->ops[bond->opB[i]].site);
+    const int oa = A->ops[bond->opA[i]].op, ob = B->ops[bond->opB[i]].op;
+    for (int r = 0; r < D; ++r) {
+      int fa, fb;
+      double va, vb;
+      act(oa, (r >> qa) & 1, fa, va);
+      act(ob, (r >> qb) & 1, fb, vb);
+      const int r2 = r ^ (fa << qa) ^ (fb << qb);
+      M[(size_t)r2 * D + r] += bond->coef[i] * va * vb;
+    }
+  }
+  for (int r = 0; r < D; ++r)
+    for (int c = 0; c < r; ++c) {
+      const double v = 0.5 * (M[(size_t)r * D + c] + M[(size_t)c * D + r]);
+      M[(size_t)r * D + c] = M[(size_t)c * D + r] = v;
+    }
+  double fro = 0.0;
+  for (double v : M) fro += v * v;
+  fro = std::sqrt(fro);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < D; ++p)
+      for (int q = p + 1; q < D; ++q) off += M[(size_t)p * D + q] * M[(size_t)p * D + q];
+    if (std::sqrt(off) <= 1e-15 * (fro + 1e-300)) break;
+    for (int p = 0; p < D; ++p)
+      for (int q = p + 1; q < D; ++q) {
+        const double apq = M[(size_t)p * D + q];
+        if (apq == 0.0) continue;
+        const double app = M[(size_t)p * D + p], aqq = M[(size_t)q * D + q];
+        const double th = 0.5 * (aqq - app) / apq;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < D; ++k) {
+          const double mkp = M[(size_t)k * D + p], mkq = M[(size_t)k * D + q];
+          M[(size_t)k * D + p] = c * mkp - sn * mkq;
+          M[(size_t)k * D + q] = sn * mkp + c * mkq;
+        }
+        for (int k = 0; k < D; ++k) {
+          const double mpk = M[(size_t)p * D + k], mqk = M[(size_t)q * D + k];
+          M[(size_t)p * D + k] = c * mpk - sn * mqk;
+          M[(size_t)q * D + k] = sn * mpk + c * mqk;
+        }
+      }
+  }
+  double top = -INFINITY;
+  for (int r = 0; r < D; ++r) top = std::max(top, M[(size_t)r * D + r]);
+  // Jacobi's rounding: a few ulps of the norm
+  top += 1e-13 * (fro + 1.0);
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = top;
+  return top;
+}
+
 // Operators of a coupling in the streaming Kronecker kernel's layout, for every
 // precision whose streaming kernel takes the size (held in the caller's scratch).
 void build_packs(hipStream_t s, Scratch& sc, CoupledOp& op) {
@@ -788,9 +887,12 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
     const bool pk = op.pack[0] || op.pack[1] || op.pack[2];
     work_max = std::max(work_max, (long)T * (kA * kA + kB * kB) + n +
                                       (pk ? 2L * T * op.pkm * op.pkm : 0L));
-    // projected one-site Pauli operators have spectral norm <= 1
+    // upper end of H_eff: the largest kept energies plus the coupling's largest
+    // eigenvalue, bounded by that of the unprojected coupling and by sum |c_i|
+    // (projected one-site operators have spectral norm <= 1)
     const double emax = A->E_host.back() + B->E_host.back();
-    op.bup = emax + csum + 1e-12 * (std::fabs(emax) + csum + 1.0);
+    const double ctop = T > 0 ? std::min(csum, coupling_top(A, B, bond)) : 0.0;
+    op.bup = emax + ctop + 1e-12 * (std::fabs(emax) + csum + 1.0);
     op.precision = o.precision;
     kreq[p] = std::min(k_keep, n);
     int nev = rq.want_module ? std::min(n, kreq[p] + 1) : std::min(q, n);
