@@ -625,8 +625,11 @@ __device__ inline double rcp_nr(double x) {
 // ---------------------------------------------------------------------------
 // Cholesky + in-place inverse of the lower factor, one 1024-thread workgroup
 // (a 32 x 32 thread grid), packed lower triangle in LDS (m <= 192 -> at most
-// 148 KB). The input Gram matrix may be given as nparts split-K partial
-// sums (stride pstride), added in a fixed order while loading.
+// 151 KB). The input Gram matrix may be given as nparts split-K partial
+// sums (stride pstride), added in a fixed order while loading. The factor is
+// taken of the equilibrated D^-1 G D^-1 (d_i = sqrt(G_ii)) and the output is
+// L^-1 D^-1 = (D L)^-1, so rows of any scale need no normalisation beforehand
+// (CholeskyQR is invariant to it) and the pivots stay on the unit scale.
 // ---------------------------------------------------------------------------
 constexpr int JMAX = 192;
 constexpr int CHOL_THREADS = 1024;
@@ -641,10 +644,18 @@ __device__ inline int tri_row(int t) {  // row i of packed lower index t
 
 __device__ void chol_inv_body(int m, const double* __restrict__ G, int nparts, long pstride,
                               double shift, double* __restrict__ Linv, int* __restrict__ info,
-                              double* L, double* col) {
+                              double* L, double* col, double* dinv) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int ty = tid >> 5, tx = tid & 31;  // 32 x 32 thread grid
   const int np = m * (m + 1) / 2;
+  // equilibration: factor D^-1 G D^-1 (d_i = sqrt(G_ii), 1 for an empty row) and
+  // return L^-1 D^-1, the inverse of G's own lower factor D L
+  for (int i = tid; i < m; i += nt) {
+    double v = 0.0;
+    for (int ks = 0; ks < nparts; ++ks) v += G[(long)ks * pstride + (long)i * m + i];
+    dinv[i] = v > 0.0 ? 1.0 / sqrt(v) : 1.0;
+  }
+  __syncthreads();
   for (int t = tid; t < np; t += nt) {
     int i = tri_row(t);
     int j = t - i * (i + 1) / 2;
@@ -653,6 +664,7 @@ __device__ void chol_inv_body(int m, const double* __restrict__ G, int nparts, l
       const double* g = G + (long)ks * pstride;
       v += 0.5 * (g[(long)i * m + j] + g[(long)j * m + i]);
     }
+    v *= dinv[i] * dinv[j];
     if (i == j) v += shift;
     L[t] = v;
   }
@@ -698,11 +710,12 @@ __device__ void chol_inv_body(int m, const double* __restrict__ G, int nparts, l
   }
   for (long t = tid; t < (long)m * m; t += nt) {
     int i = (int)(t / m), j = (int)(t % m);
-    Linv[t] = j <= i ? L[lidx(i, j)] : 0.0;
+    Linv[t] = j <= i ? L[lidx(i, j)] * dinv[j] : 0.0;
   }
 }
 
-// The same factorisation and inverse for m <= 80 by 8-wide blocks, so that a panel
+// The same factorisation (equilibrated the same way) and inverse for m <= 80 by
+// 8-wide blocks, so that a panel
 // costs three barriers instead of eight steps of two. Matrix in LDS with an odd row
 // stride, padded to a multiple of 8 with the identity. Per panel: wave 0 factors the
 // 8 x 8 diagonal block in registers (lane (r, c), shuffles), the rows below are solved
@@ -713,7 +726,7 @@ __device__ void chol_inv_body(int m, const double* __restrict__ G, int nparts, l
 constexpr int CB_MAX = 80;
 size_t chol_blocked_lds_bytes(int m) {
   const int mp = (m + 7) & ~7;
-  return ((size_t)mp * (mp + 1) + 2 * (size_t)mp + 2) * sizeof(double);
+  return ((size_t)mp * (mp + 1) + 3 * (size_t)mp + 2) * sizeof(double);
 }
 
 __device__ __forceinline__ void chol_blocked_body(int m, const double* __restrict__ G, int nparts, long pstride,
@@ -723,9 +736,17 @@ __device__ __forceinline__ void chol_blocked_body(int m, const double* __restric
   double* A = sm;            // [mp][LD]
   double* xd = A + mp * LD;  // diagonal of X
   double* rd = xd + mp;      // 1 / L[i][i]
-  int* flag = (int*)(rd + mp);
+  double* dv = rd + mp;      // 1 / d_i of the equilibration
+  int* flag = (int*)(dv + mp);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int r8 = lane >> 3, c8 = lane & 7;
+  for (int i = tid; i < mp; i += nt) {
+    double v = 0.0;
+    if (i < m)
+      for (int ks = 0; ks < nparts; ++ks) v += G[(long)ks * pstride + (long)i * m + i];
+    dv[i] = v > 0.0 ? 1.0 / sqrt(v) : 1.0;
+  }
+  __syncthreads();
   for (int t = tid; t < mp * mp; t += nt) {
     const int i = t / mp, j = t % mp;
     if (j > i) continue;
@@ -736,6 +757,7 @@ __device__ __forceinline__ void chol_blocked_body(int m, const double* __restric
         const double* g = G + (long)ks * pstride;
         v += 0.5 * (g[(long)i * m + j] + g[(long)j * m + i]);
       }
+      v *= dv[i] * dv[j];
       if (i == j) v += shift;
     }
     A[i * LD + j] = v;
@@ -837,7 +859,7 @@ __device__ __forceinline__ void chol_blocked_body(int m, const double* __restric
   }
   for (int t = tid; t < m * m; t += nt) {
     const int i = t / m, j = t % m;
-    Linv[t] = j < i ? A[j * LD + i] : (j == i ? xd[i] : 0.0);
+    Linv[t] = (j < i ? A[j * LD + i] : (j == i ? xd[i] : 0.0)) * dv[j];
   }
   if (tid == 0) info[0] = 0;
 }
@@ -846,10 +868,10 @@ __global__ __launch_bounds__(CHOL_THREADS) void chol_inv_kernel(int m, const dou
                                                                 long pstride, double shift,
                                                                 double* __restrict__ Linv, int* __restrict__ info) {
   extern __shared__ double sm[];
-  chol_inv_body(m, G, nparts, pstride, shift, Linv, info, sm, sm + m * (m + 1) / 2);
+  chol_inv_body(m, G, nparts, pstride, shift, Linv, info, sm, sm + m * (m + 1) / 2, sm + m * (m + 1) / 2 + m);
 }
 
-size_t chol_lds_bytes(int m) { return ((size_t)m * (m + 1) / 2 + m) * sizeof(double); }
+size_t chol_lds_bytes(int m) { return ((size_t)m * (m + 1) / 2 + 2 * (size_t)m) * sizeof(double); }
 
 void chol_inv(hipStream_t s, int m, const double* G, int nparts, long pstride, double shift,
               double* Linv, int* info) {
@@ -862,15 +884,16 @@ __global__ __launch_bounds__(CHOL_THREADS) void chol_batched_kernel(const CholDe
   const CholDesc d = descs[blockIdx.x];
   double* L = sm;
   double* col = sm + d.m * (d.m + 1) / 2;
+  double* dinv = col + d.m;
   const bool blk = d.m <= CB_MAX;
   if (blk) chol_blocked_body(d.m, d.G, d.nparts, d.pstride, 0.0, d.Linv, d.info, sm);
-  else chol_inv_body(d.m, d.G, d.nparts, d.pstride, 0.0, d.Linv, d.info, L, col);
+  else chol_inv_body(d.m, d.G, d.nparts, d.pstride, 0.0, d.Linv, d.info, L, col, dinv);
   __syncthreads();
   const int failed = d.info[0];
   __syncthreads();
   if (failed) {  // shifted CholeskyQR: retry with the shift, flag it in info[1]
     if (blk) chol_blocked_body(d.m, d.G, d.nparts, d.pstride, d.shift, d.Linv, d.info, sm);
-    else chol_inv_body(d.m, d.G, d.nparts, d.pstride, d.shift, d.Linv, d.info, L, col);
+    else chol_inv_body(d.m, d.G, d.nparts, d.pstride, d.shift, d.Linv, d.info, L, col, dinv);
     if (threadIdx.x == 0) d.info[1] = 1;
   } else if (threadIdx.x == 0) {
     d.info[1] = 0;
