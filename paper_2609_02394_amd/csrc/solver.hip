@@ -534,8 +534,13 @@ void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst, int slot
 // Orthonormalise the cnt rows at Y[r] of each problem against its locked rows
 // X[0..nlock), then among themselves. The result ends in Y[r].
 void orthonormalize(Batch& B, const std::vector<BP*>& L, int r) {
-  // rows of any scale: the projection below is invariant to it and the Cholesky
-  // kernel equilibrates the Gram
+  std::vector<VecDesc> nd;
+  for (BP* p : L) {
+    VecDesc v{};
+    v.nv = p->cnt; v.n = p->n; v.out = role_ptr(p, r);
+    nd.push_back(v);
+  }
+  vec_launch(B, VEC_NORMALIZE, nd);
   std::vector<BP*> LL;
   for (BP* p : L)
     if (p->nlock > 0) LL.push_back(p);
@@ -566,6 +571,13 @@ void orthonormalize(Batch& B, const std::vector<BP*>& L, int r) {
       vec_launch(B, VEC_REDUCE, rd);
       gemm_launch(B, false, false, g2, 1);
     }
+    std::vector<VecDesc> nd2;
+    for (BP* p : LL) {
+      VecDesc v{};
+      v.nv = p->cnt; v.n = p->n; v.out = role_ptr(p, r);
+      nd2.push_back(v);
+    }
+    vec_launch(B, VEC_NORMALIZE, nd2);
   }
   // CholeskyQR2; its flags are read with the next state (ortho_fixup), so that the
   // common case costs no host round trip
