@@ -1411,11 +1411,11 @@ static size_t jacobi_launch_lds(int mmax, int vl) {
   return d * sizeof(double);
 }
 
-void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax, int max_sweeps) {
+void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax) {
   if (P <= 0) return;
   const int vl = jacobi_v_in_lds(mmax) ? 1 : 0;
   size_t lds = jacobi_launch_lds(mmax, vl);
-  hipLaunchKernelGGL(jacobi_batched_kernel, dim3(P), dim3(JAC_THREADS), lds, s, d, vl, max_sweeps);
+  hipLaunchKernelGGL(jacobi_batched_kernel, dim3(P), dim3(JAC_THREADS), lds, s, d, vl, 40);
 }
 
 // Row-block vector operations (one workgroup per row for the reductions).

@@ -164,9 +164,7 @@ void kron_pack(hipStream_t s, int T, int kA, int kB, const double* coef, const d
 void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int Mmax, int Nmax,
                   int ksplit);
 void gram_batched(hipStream_t s, const GramDesc* d, int P, int ks, int cmax);
-// max_sweeps: a problem still above threshold after that many sweeps stops there
-// (info = -(sweeps + 1)) with its current rotation
-void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax, int max_sweeps = 40);
+void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax);
 void chol_batched(hipStream_t s, const CholDesc* d, int P, int mmax);
 void vec_batched(hipStream_t s, VecOp op, const VecDesc* d, int P, int nvmax, long elems_max);
 void start_batched(hipStream_t s, const StartDesc* d, int P, int nmax, int mmax);

@@ -593,7 +593,7 @@ void orthonormalize(Batch& B, const std::vector<BP*>& L, int r) {
 // Rayleigh-Ritz of the orthonormal rows at role q (cnt rows), W = H Q into role w
 // (already there when `full`); Ritz pairs into X/HX/theta/res at row offset nlock,
 // or, when `full`, into Y[2]/E/theta/res from row 0.
-void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full, int max_sweeps = 40) {
+void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full) {
   if (!full) {
     Apply a;
     for (BP* p : L) {
@@ -630,7 +630,7 @@ void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full,
   {
     hipStream_t st = B.st;
     const int P = (int)ed.size();
-    B.da->defer([=] { jacobi_batched(st, dd, P, mm, max_sweeps); });
+    B.da->defer([=] { jacobi_batched(st, dd, P, mm); });
   }
   std::vector<GemmDesc> g1, g2;
   for (BP* p : L) {
@@ -1138,13 +1138,7 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
   }
   for (BP* p : probs) p->cnt = p->m;
   orthonormalize(B, probs, 0);
-  // with m < n the start block's Rayleigh-Ritz only seeds the first filter (the
-  // subspace is the same for any rotation of it, the residuals are taken as they are
-  // and nothing locks before the first filter), so a few Jacobi sweeps suffice; with
-  // m = n it is already the answer
-  bool seed_only = true;
-  for (BP* p : probs) seed_only = seed_only && p->m < p->n;
-  rayleigh_ritz(B, probs, 0, 1, false, seed_only ? 3 : 40);
+  rayleigh_ritz(B, probs, 0, 1, false);
 
   const double tol = o.tol > 0 ? o.tol : 1e-13;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
