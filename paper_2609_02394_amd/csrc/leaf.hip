@@ -276,6 +276,23 @@ void start_block(hipStream_t s, int n, int m, const double* D, double eps, unsig
 // (8 passes of 8 bits, LDS histograms) finds the key K of rank m-1 and how many
 // entries equal to K are needed; the entries below K plus the lowest-index entries
 // equal to K are then gathered and ranked among themselves (m <= 192).
+// inclusive prefix sum over a 256-thread workgroup (wave shuffles, then the wave
+// totals); wsum: 4 entries of LDS. Contains the barriers it needs.
+__device__ inline unsigned scan256(unsigned v, unsigned* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  unsigned x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[tid >> 6] = x;
+  __syncthreads();
+  for (int w = 0; w < (tid >> 6); ++w) x += wsum[w];
+  __syncthreads();
+  return x;
+}
+
 __device__ inline unsigned long long order_key(double x) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(x + 0.0);  // -0 -> +0
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
@@ -289,6 +306,7 @@ __global__ __launch_bounds__(256) void rank_select_batched_kernel(const StartDes
   __shared__ int n_less;
   __shared__ unsigned long long ck[192];
   __shared__ int ci[192];
+  __shared__ unsigned wsum[4];
   const StartDesc d = descs[blockIdx.x];
   const int n = d.n, m = d.m, tid = threadIdx.x;
   if (m <= 0 || m > 192) return;
@@ -304,11 +322,14 @@ __global__ __launch_bounds__(256) void rank_select_batched_kernel(const StartDes
       if ((k & msk) == pre) atomicAdd(&hist[(k >> shift) & 255u], 1u);
     }
     __syncthreads();
-    if (tid == 0) {
-      int need = s_need, b = 0;
-      while (b < 255 && (int)hist[b] < need) need -= (int)hist[b++];
-      s_need = need;
-      s_prefix = pre | ((unsigned long long)b << shift);
+    // the first bin whose running count reaches the rank still needed: bin b with
+    // excl(b) < need <= incl(b) (the counts under the prefix cover need)
+    const int need = s_need;
+    const unsigned hv = hist[tid];
+    const unsigned incl = scan256(hv, wsum), excl = incl - hv;
+    if ((int)excl < need && (int)incl >= need) {
+      s_need = need - (int)excl;
+      s_prefix = pre | ((unsigned long long)tid << shift);
       s_mask = msk | (255ull << shift);
     }
     __syncthreads();
@@ -329,16 +350,7 @@ __global__ __launch_bounds__(256) void rank_select_batched_kernel(const StartDes
       ++ce;
     }
   }
-  cnt_eq[tid] = ce;
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int t = 0; t < 256; ++t) {
-      const int c = cnt_eq[t];
-      cnt_eq[t] = acc;
-      acc += c;
-    }
-  }
+  cnt_eq[tid] = (int)scan256((unsigned)ce, wsum) - ce;  // exclusive
   __syncthreads();
   const int base_less = m - need;  // == n_less
   int before = cnt_eq[tid];
