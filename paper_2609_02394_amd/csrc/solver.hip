@@ -534,17 +534,12 @@ void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst, int slot
 // Orthonormalise the cnt rows at Y[r] of each problem against its locked rows
 // X[0..nlock), then among themselves. The result ends in Y[r].
 void orthonormalize(Batch& B, const std::vector<BP*>& L, int r) {
-  std::vector<VecDesc> nd;
-  for (BP* p : L) {
-    VecDesc v{};
-    v.nv = p->cnt; v.n = p->n; v.out = role_ptr(p, r);
-    nd.push_back(v);
-  }
-  vec_launch(B, VEC_NORMALIZE, nd);
   std::vector<BP*> LL;
   for (BP* p : L)
     if (p->nlock > 0) LL.push_back(p);
   if (!LL.empty()) {
+    // Y -= (Y X_lock^T) X_lock twice (invariant to the scale of Y's rows, so it runs
+    // before the normalisation)
     for (int pass = 0; pass < 2; ++pass) {
       // P = Y X_lock^T as split-K partials, reduced, then Y -= P X_lock
       std::vector<const double*> A, Bl;
@@ -571,14 +566,15 @@ void orthonormalize(Batch& B, const std::vector<BP*>& L, int r) {
       vec_launch(B, VEC_REDUCE, rd);
       gemm_launch(B, false, false, g2, 1);
     }
-    std::vector<VecDesc> nd2;
-    for (BP* p : LL) {
-      VecDesc v{};
-      v.nv = p->cnt; v.n = p->n; v.out = role_ptr(p, r);
-      nd2.push_back(v);
-    }
-    vec_launch(B, VEC_NORMALIZE, nd2);
   }
+  // unit rows into CholeskyQR
+  std::vector<VecDesc> nd;
+  for (BP* p : L) {
+    VecDesc v{};
+    v.nv = p->cnt; v.n = p->n; v.out = role_ptr(p, r);
+    nd.push_back(v);
+  }
+  vec_launch(B, VEC_NORMALIZE, nd);
   // CholeskyQR2; its flags are read with the next state (ortho_fixup), so that the
   // common case costs no host round trip
   const int sp = (r == 0) ? 1 : 0;
