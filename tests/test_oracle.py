@@ -422,3 +422,42 @@ def BD_GOLDEN():
         rows.append(dict(k=int(k), kA=int(kA), kB=int(kB), a=float(a), b=float(b), c=float(c),
                          E0=float(E0)))
     return rows
+
+
+# --- the filter's spectral upper bound of a merge (a reading where the paper is
+# silent): lambda_max(H_eff) <= E_A,max + E_B,max + lambda_max(C), C the coupling
+# before projection on the sites it touches, and lambda_max(C) <= sum |c_i| ----------
+
+@pytest.mark.parametrize("job,nA,k", [
+    (W.ChainJob("xxz", 8, 4, 8, 4, J=1.0, delta=1.0), 4, 6),
+    (W.ChainJob("xxz", 8, 4, 8, 4, J=1.0, delta=0.37), 4, 9),
+    (W.ChainJob("xxz", 8, 4, 8, 4, J=0.7, delta=-0.5), 4, 16),
+    (W.ChainJob("tfim", 8, 4, 8, 4, J=1.0, h=0.7), 4, 5),
+    (W.ChainJob("tfim_nnn", 8, 4, 8, 4, J=1.0, h=0.9, j2=0.3), 4, 7),
+    (W.ChainJob("tfim_ladder", 8, 4, 8, 4, J=1.0, h=0.8, j_rung=0.6), 4, 6),
+    (W.ChainJob("rfheis", 8, 4, 8, 4, J=1.0, fields=(0.3, -0.5, 0.9, -0.1, 0.4, -0.7, 0.2, 0.6)), 4, 10),
+])
+def test_merge_upper_bound_by_the_unprojected_coupling(job, nA, k):
+    N = job.n_sites
+    E_A, V_A, _, _, _ = R.leaf_ed(H.block_hamiltonian(job, 0, nA), k)
+    E_B, V_B, _, _, _ = R.leaf_ed(H.block_hamiltonian(job, nA, N), k)
+    cut = H.cut_terms(job, 0, nA, N)
+    assert cut, "the cut must carry coupling terms"
+    terms = [(c, R.project(V_A, H.site_operator(nA, s, oa)),
+              R.project(V_B, H.site_operator(N - nA, t - nA, ob))) for c, s, oa, t, ob in cut]
+    top = np.linalg.eigvalsh(R.effective_hamiltonian(E_A, E_B, terms))[-1]
+    # the coupling before projection, as a dense matrix on the sites its terms touch
+    sites = sorted({s for _, s, _, _, _ in cut} | {t for _, _, _, t, _ in cut})
+    at = {s: i for i, s in enumerate(sites)}
+    C = sum(c * H.term_matrix(len(sites), {at[s]: oa, at[t]: ob}) for c, s, oa, t, ob in cut)
+    ctop = np.linalg.eigvalsh(0.5 * (C + C.T))[-1]
+    csum = sum(abs(c) for c, _, _, _, _ in cut)
+    assert ctop <= csum + 1e-12
+    assert top <= E_A[-1] + E_B[-1] + ctop + 1e-10
+    # strictly below the sum-of-|c| bound where the bond's terms cannot all reach
+    # their maximum on one state (XX + YY + Delta ZZ with Delta > 0); with Delta < 0
+    # the triplet m = 0 state aligns all three and the two bounds coincide
+    if job.model == "rfheis" or (job.model == "xxz" and job.delta > 0):
+        assert ctop < csum - 1e-3
+    if job.model == "xxz" and job.delta < 0:
+        assert abs(ctop - csum) < 1e-12
