@@ -73,6 +73,61 @@ def test_ladder_bonds_geometry():
     assert b == [(0, 1), (0, 2), (1, 3), (2, 3), (2, 4), (3, 5), (4, 5), (4, 6), (5, 7), (6, 7)]
 
 
+# -- the random-field on-site term h_s S^z_s and the next-nearest coupling ---------
+
+def test_random_field_single_spin_is_plus_minus_half_h():
+    # one spin in a longitudinal field: h S^z = (h/2) sigma^z, eigenvalues -|h|/2, +|h|/2
+    for h in (1.7, -0.6):
+        job = W.ChainJob("rfheis", 1, 1, 2, 2, J=1.0, fields=(h,))
+        np.testing.assert_allclose(X.brute_energies(job, 2), [-abs(h) / 2, abs(h) / 2], atol=1e-15)
+
+
+def test_random_field_without_exchange_is_sum_of_half_fields():
+    # J = 0: H = sum_s h_s S^z_s is diagonal; its spectrum is every sum of +-h_s/2
+    fields = (0.83, -1.41, 0.27, 1.96, -0.55)
+    job = W.ChainJob("rfheis", 5, 5, 4, 32, J=0.0, fields=fields)
+    sums = sorted(sum(0.5 * f * (1 - 2 * ((m >> s) & 1)) for s, f in enumerate(fields))
+                  for m in range(32))
+    np.testing.assert_allclose(X.brute_energies(job, 32), sums, atol=1e-14)
+
+
+@pytest.mark.parametrize("J,h1,h2", [(1.0, 0.9, -0.4), (0.7, -1.3, 1.1)])
+def test_random_field_two_spins_closed_form(J, h1, h2):
+    # J S1.S2 + h1 S1z + h2 S2z. Total S^z is conserved: |uu>, |dd> give J/4 +- (h1+h2)/2;
+    # the {ud, du} block [[-J/4 + (h1-h2)/2, J/2], [J/2, -J/4 - (h1-h2)/2]] gives
+    # -J/4 +- sqrt((J/2)^2 + ((h1-h2)/2)^2). This fixes the field's scale against the exchange.
+    job = W.ChainJob("rfheis", 2, 2, 4, 4, J=J, fields=(h1, h2))
+    r = np.hypot(J / 2, (h1 - h2) / 2)
+    want = sorted([J / 4 + (h1 + h2) / 2, J / 4 - (h1 + h2) / 2, -J / 4 + r, -J / 4 - r])
+    np.testing.assert_allclose(X.brute_energies(job, 4), want, atol=1e-14)
+
+
+@pytest.mark.parametrize("N,J,j2", [(3, 0.0, 0.35), (4, 0.0, 0.35), (4, 1.0, 0.6), (5, -0.8, 0.45)])
+def test_next_nearest_classical_energies_by_enumeration(N, J, j2):
+    # h = 0: -J sum Z_s Z_{s+1} - j2 sum Z_s Z_{s+2} is diagonal; enumerate the 2^N spin
+    # configurations by hand (J = 0: the ground energy is -j2 (N - 2), all spins aligned)
+    job = W.ChainJob("tfim_nnn", N, N, 4, 2 ** N, J=J, h=0.0, j2=j2)
+    energies = []
+    for m in range(2 ** N):
+        z = [1 - 2 * ((m >> s) & 1) for s in range(N)]
+        energies.append(-J * sum(z[s] * z[s + 1] for s in range(N - 1))
+                        - j2 * sum(z[s] * z[s + 2] for s in range(N - 2)))
+    np.testing.assert_allclose(X.brute_energies(job, 2 ** N), sorted(energies), atol=1e-14)
+    if J == 0.0:
+        assert abs(min(energies) + j2 * (N - 2)) <= 1e-15
+
+
+def test_next_nearest_without_nearest_is_two_tfim_chains():
+    # J = 0: the even and the odd sublattices are two decoupled open TFIM chains with
+    # coupling j2 and field h, so the spectrum is every sum of one level of each
+    # (free fermions for both)
+    N, j2, h = 10, 0.8, 0.6
+    job = W.ChainJob("tfim_nnn", N, N, 4, 12, J=0.0, h=h, j2=j2)
+    a = X.tfim_free_fermion(5, j2, h, 12)
+    want = np.sort((a[:, None] + a[None, :]).ravel())[:12]
+    np.testing.assert_allclose(X.brute_energies(job, 12), want, atol=1e-12)
+
+
 # -- building blocks -------------------------------------------------------------
 
 def test_site_order_msb_is_leftmost():
