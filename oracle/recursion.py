@@ -232,3 +232,149 @@ class Recursion:
 def recurse(job, tau_gap=TAU_GAP, memo=True, k=None, q=None) -> Result:
     """Lowest q energies of the job by the recursive module-coupling method."""
     return Recursion(job, tau_gap, memo, k, q).run()
+
+
+# -- Algorithm 1 over a caller-defined module tree ------------------------------------
+# The inputs of Algorithm 1 are the initial block Hamiltonians {H_b} and the couplings
+# {V_bb'} between blocks; the merge order is a binary tree (Fig. 1, recursive block
+# merging). A tree is a list of nodes, children before parents, the last one the root:
+#   ("leaf", n_sites, terms, k)          terms: [(coef, ((site, op), ...))], local sites
+#   ("merge", left, right, terms, k)     terms: [(coef, site_left, op_left, site_right,
+#                                                 op_right)], sites local to each child
+# k = 0 takes the tree's k. A merged module numbers its sites left child first. A node
+# may be the child of several parents (a declared shared subtree: one module).
+
+
+def leaf_matrix(n_sites, terms):
+    """Dense block Hamiltonian of a leaf from its term list (local sites), accumulated
+    term by term from +0.0 in list order."""
+    H = np.zeros((2 ** n_sites, 2 ** n_sites))
+    for c, ops in terms:
+        H = H + c * ham.term_matrix(n_sites, dict(ops))
+    return H
+
+
+class TreeRecursion:
+    """Algorithm 1 over a tree of nodes (see above)."""
+
+    def __init__(self, nodes, k, q, tau_gap=TAU_GAP, memo=True):
+        self.nodes, self.k, self.q = list(nodes), k, q
+        self.tau_gap, self.memo = tau_gap, memo
+        self.cache: Dict[tuple, Module] = {}
+        self.records: List[Record] = []
+        self.n_leaf_ed = 0
+        self.n_merges = 0
+
+    def _k(self, node):
+        return node[-1] if node[-1] > 0 else self.k
+
+    def op(self, mod: Module, rel_site: int, opname: str) -> np.ndarray:
+        """Projected one-site operator (as Recursion.op)."""
+        kk = (rel_site, opname)
+        if kk in mod.ops:
+            return mod.ops[kk]
+        if mod.kind == "leaf":
+            o = project(mod.basis, ham.site_operator(mod.width, rel_site, opname))
+        else:
+            A, B = mod.left, mod.right
+            if rel_site < A.width:
+                o = transform_left(mod.basis, self.op(A, rel_site, opname), A.k_eff, B.k_eff)
+            else:
+                o = transform_right(mod.basis, self.op(B, rel_site - A.width, opname),
+                                    A.k_eff, B.k_eff)
+        mod.ops[kk] = o
+        return o
+
+    def build(self, i, levels, root):
+        node = self.nodes[i]
+        k = self._k(node)
+        if node[0] == "leaf":
+            _, n, terms, _ = node
+            key = ("leaf", n, k, tuple((c, tuple(ops)) for c, ops in terms))
+            if self.memo and key in self.cache:
+                return self.cache[key]
+            H = leaf_matrix(n, terms)
+            E, V, k_eff, gap, _ = leaf_ed(H, k, self.tau_gap)
+            self.n_leaf_ed += 1
+            self.records.append(Record(0, n, "leaf", min(k, H.shape[0]), k_eff, gap))
+            mod = Module(key, n, E, V, k_eff, gap, "leaf")
+        else:
+            _, l, r, terms, _ = node
+            A, B = self.mods[l], self.mods[r]
+            level = 1 + max(levels[l], levels[r])
+            key = ("merge", A.key, B.key, k, tuple(tuple(t) for t in terms), root)
+            if self.memo and key in self.cache:
+                return self.cache[key]
+            ops = [(c, self.op(A, sa, oa), self.op(B, sb, ob)) for c, sa, oa, sb, ob in terms]
+            self.n_merges += 1
+            if root:
+                w, _, _, _, _ = couple_solve(A.E, B.E, ops, None)
+                mod = Module(key, A.width + B.width, w, None, len(w), float("inf"), "root", A, B)
+            else:
+                w, E, U, k_eff, gap = couple_solve(A.E, B.E, ops, k, None, self.tau_gap)
+                self.records.append(Record(level, A.width + B.width, "merge", min(k, len(w)),
+                                           k_eff, gap))
+                mod = Module(key, A.width + B.width, E, U, k_eff, gap, "merge", A, B)
+        if self.memo:
+            self.cache[key] = mod
+        return mod
+
+    def run(self) -> Result:
+        n = len(self.nodes)
+        levels = [0] * n
+        self.mods: List[Module] = [None] * n
+        for i, node in enumerate(self.nodes):
+            if node[0] == "merge":
+                levels[i] = 1 + max(levels[node[1]], levels[node[2]])
+        root = self.nodes[-1]
+        if root[0] == "leaf":  # a single block: its lowest q energies, nothing cut
+            w = np.linalg.eigvalsh(leaf_matrix(root[1], root[2]))
+            return Result(w[: self.q].copy(), self.records, self.n_leaf_ed, 0)
+        for i in range(n):
+            self.mods[i] = self.build(i, levels, i == n - 1)
+        return Result(self.mods[-1].E[: self.q].copy(), self.records, self.n_leaf_ed,
+                      self.n_merges)
+
+
+def recurse_tree(nodes, k, q, tau_gap=TAU_GAP, memo=True) -> Result:
+    """Lowest q energies of the root of a module tree by the recursive method."""
+    return TreeRecursion(nodes, k, q, tau_gap, memo).run()
+
+
+def tree_from_spec(job, spec, k_of=None):
+    """Tree nodes of the sites of `job` split and merged as `spec`: a leaf is a site
+    range (a, b); a merge is a pair (left spec, right spec) of adjacent ranges, left
+    first. Leaf terms are the model's terms inside the range; a merge carries the bonds
+    with one site in each child (the cut), each child's sites numbered from 0.
+    k_of(width) gives a node's k (default 0: the tree's k)."""
+    nodes = []
+
+    def go(s):
+        if isinstance(s[0], int):
+            a, b = s
+            terms = [(c, tuple((site - a, o) for site, o in ops))
+                     for c, ops in ham.block_terms(job, a, b)]
+            nodes.append(("leaf", b - a, terms, k_of(b - a) if k_of else 0))
+            return len(nodes) - 1, a, b
+        li, a, m = go(s[0])
+        ri, m2, b = go(s[1])
+        if m2 != m:
+            raise ValueError("children of a merge must be adjacent, left first")
+        cut = [(c, sa - a, oa, sb - m, ob) for c, sa, oa, sb, ob in ham.cut_terms(job, a, m, b)]
+        nodes.append(("merge", li, ri, cut, k_of(b - a) if k_of else 0))
+        return len(nodes) - 1, a, b
+
+    go(spec)
+    return nodes
+
+
+def chain_spec(n_sites, leaf_sites):
+    """The spec of Algorithm 1's default order on a chain: leaves of leaf_sites
+    consecutive sites merged pairwise left to right, an odd module carried up."""
+    mods = [(a, a + leaf_sites) for a in range(0, n_sites, leaf_sites)]
+    while len(mods) > 1:
+        nxt = [(mods[i], mods[i + 1]) for i in range(0, len(mods) - 1, 2)]
+        if len(mods) % 2:
+            nxt.append(mods[-1])
+        mods = nxt
+    return mods[0]

@@ -516,3 +516,73 @@ def test_merge_upper_bound_by_the_unprojected_coupling(job, nA, k):
         assert ctop < csum - 1e-3
     if job.model == "xxz" and job.delta < 0:
         assert abs(ctop - csum) < 1e-12
+
+
+# -- Algorithm 1 over a caller-defined module tree (unequal leaves, any merge order) ----
+
+TREE_SPECS = [
+    ("tfim", dict(model="tfim", n_sites=10, leaf_sites=1, k=4, q=4, J=1.0, h=0.7),
+     ((0, 3), ((3, 7), (7, 10)))),
+    ("xxz", dict(model="xxz", n_sites=9, leaf_sites=1, k=4, q=5, J=1.0, delta=0.6),
+     (((0, 2), (2, 5)), (5, 9))),
+    ("nnn", dict(model="tfim_nnn", n_sites=10, leaf_sites=1, k=4, q=4, J=1.0, h=0.8, j2=0.3),
+     ((0, 4), ((4, 5), (5, 10)))),
+    ("ladder", dict(model="tfim_ladder", n_sites=10, leaf_sites=2, k=4, q=4, J=1.0, h=0.9,
+                    j_rung=0.5), (((0, 2), (2, 6)), (6, 10))),
+]
+
+
+@pytest.mark.parametrize("name,kw,spec", TREE_SPECS, ids=[t[0] for t in TREE_SPECS])
+def test_tree_full_k_is_exact_with_unequal_leaves(name, kw, spec):
+    # nothing truncated: the root's spectrum is that of the whole system, whatever the
+    # leaves and the merge order
+    job = W.ChainJob(**kw)
+    nodes = R.tree_from_spec(job, spec)
+    res = R.recurse_tree(nodes, 4096, job.q)
+    np.testing.assert_allclose(res.energies, X.brute_energies(job, job.q), atol=1e-11)
+
+
+@pytest.mark.parametrize("name,kw,spec", TREE_SPECS, ids=[t[0] for t in TREE_SPECS])
+def test_tree_truncated_is_a_variational_upper_bound(name, kw, spec):
+    job = W.ChainJob(**kw)
+    ex = X.brute_energies(job, job.q)
+    for k in (3, 6, 10):
+        res = R.recurse_tree(R.tree_from_spec(job, spec), k, job.q)
+        assert np.all(res.energies >= ex - 1e-11), (k, res.energies, ex)
+
+
+def test_tree_of_the_chain_order_equals_the_chain_recursion():
+    for job in [W.tfim_small(), W.ChainJob("tfim_ladder", 12, 4, 16, 4, J=1.0, h=0.9, j_rung=0.5),
+                W.tfim_nnn(n_sites=24, leaf_sites=4, k=12, q=6)]:
+        a = R.recurse(job)
+        t = R.recurse_tree(R.tree_from_spec(job, R.chain_spec(job.n_sites, job.leaf_sites)),
+                           job.k, job.q)
+        assert np.array_equal(a.energies, t.energies)
+        assert [(r.level, r.width, r.kind, r.k_eff) for r in a.records] == \
+               [(r.level, r.width, r.kind, r.k_eff) for r in t.records]
+
+
+def test_tree_declared_shared_subtree_equals_the_full_tree():
+    # a homogeneous chain of four 3-site leaves: one leaf node and one pair node, each
+    # referenced twice (a DAG), against the plain tree with and without reuse
+    job = W.ChainJob("tfim", 12, 3, 6, 4, J=1.0, h=0.7)
+    full = R.tree_from_spec(job, (((0, 3), (3, 6)), ((6, 9), (9, 12))))
+    leaf = full[0]
+    pair = ("merge", 0, 0, full[2][3], 0)
+    top = ("merge", 1, 1, full[-1][3], 0)
+    dag = [leaf, pair, top]
+    a = R.recurse_tree(full, job.k, job.q)
+    b = R.recurse_tree(dag, job.k, job.q)
+    c = R.recurse_tree(full, job.k, job.q, memo=False)
+    assert np.array_equal(a.energies, b.energies) and np.array_equal(a.energies, c.energies)
+    assert b.n_leaf_ed == 1 and b.n_merges == 2 and c.n_leaf_ed == 4 and c.n_merges == 3
+
+
+def test_tree_per_node_k_at_full_dimension_is_exact():
+    # a node-level k that keeps every state of its module (here the 3-site leaves and
+    # their merge) while the tree default truncates elsewhere: with every module whole,
+    # the root is exact
+    job = W.ChainJob("tfim", 9, 3, 2, 4, J=1.0, h=0.7)
+    nodes = R.tree_from_spec(job, (((0, 3), (3, 6)), (6, 9)), k_of=lambda w: 2 ** w)
+    res = R.recurse_tree(nodes, 2, job.q)
+    np.testing.assert_allclose(res.energies, X.brute_energies(job, job.q), atol=1e-11)
