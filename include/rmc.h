@@ -22,7 +22,8 @@
  * General conventions
  *  - Every call returns an rmc_status; nothing throws or aborts across the ABI.
  *    On error outputs are left untouched, except RMC_ERR_NOCONV, which still
- *    fills energies (best Ritz values) and the report.
+ *    fills the report and, where the failed solve is the one that returns them,
+ *    the energies (best Ritz values; see each call).
  *  - rmc_last_error() gives a message for the last non-OK status of the ctx.
  *  - Pointers named *_host are host memory owned by the caller; pointers named
  *    *_dev are device memory owned by the caller. Modules are owned by the ctx
@@ -86,13 +87,45 @@ typedef struct {
   const int* opB;
 } rmc_bond_desc;
 
-/* A whole chain for rmc_recurse (Algorithm 1 inputs): sites 0..n_sites-1 split
- * into leaves of leaf_sites consecutive sites; terms is the global term list.
- * A leaf's Hamiltonian is the terms lying in it, in list order; a merge of
- * A = [a, m) with B = [m, b) couples through the two-site terms with one site in
- * A and one in B, in list order. Adjacent modules are merged pairwise left to
- * right; an odd module is carried up unchanged. Identical modules (same terms up
- * to a shift of sites, same children) are computed once. */
+/* A module tree for rmc_recurse (the inputs of Algorithm 1 over a caller-defined
+ * hierarchy: the initial block Hamiltonians H_b, the couplings V_bb' between blocks, and
+ * the order in which blocks are merged, Fig. 1's recursive block merging).
+ *
+ * A leaf node (left = right = -1) is a block of n_sites sites (1..12), numbered
+ * 0..n_sites-1; its terms are its Hamiltonian H_b, accumulated in list order from +0.0.
+ * A merge node couples its children left (module A) and right (module B); its merged
+ * module numbers its sites A's first (0..w_A-1), then B's (w_A..w_A+w_B-1). Its terms
+ * are the coupling V_AB: two-site terms (nsite = 2) with site[0] / op[0] on A (a site
+ * of A, 0..w_A-1) and site[1] / op[1] on B (0..w_B-1); n_sites is ignored.
+ * Children come before their parents (left, right < the node's index) and the last
+ * node is the root. A node referenced by several parents (or as both children of one)
+ * is one module computed once: a declared shared subtree. Independently of that,
+ * modules with identical content (terms, k and children, up to a shift of sites) are
+ * computed once (the paper's reuse of identical blocks).
+ * k of a node is the number of states its module keeps (0: the tree's k); the root
+ * keeps nothing and returns its lowest q eigenvalues. Every node must belong to the
+ * tree (reachable from the root). */
+typedef struct {
+  int left, right;        /* child node indices; -1, -1 for a leaf            */
+  int n_sites;            /* leaf: sites of the block                         */
+  int n_terms;
+  const rmc_term* terms;  /* leaf: H_b; merge: the coupling V_AB             */
+  int k;                  /* retained states of this module (0 = tree's k)    */
+} rmc_tree_node;
+
+typedef struct {
+  int n_nodes;
+  const rmc_tree_node* nodes;
+  int k; /* retained states per module, unless a node sets its own */
+  int q; /* lowest eigenvalues returned, 1 <= q <= k                */
+} rmc_tree_desc;
+
+/* A chain (the default order of Algorithm 1): sites 0..n_sites-1 split into leaves of
+ * leaf_sites consecutive sites; terms is the global term list. A leaf's Hamiltonian is
+ * the terms lying in it, in list order; a merge of A = [a, m) with B = [m, b) couples
+ * through the two-site terms with one site in A and one in B, in list order. Adjacent
+ * modules are merged pairwise left to right; an odd module is carried up unchanged.
+ * rmc_recurse_chain builds that tree and solves it as rmc_recurse does. */
 typedef struct {
   int n_sites;
   int leaf_sites;
@@ -101,6 +134,12 @@ typedef struct {
   int k; /* retained states per module */
   int q; /* lowest eigenvalues returned, 1 <= q <= k */
 } rmc_chain_desc;
+
+/* One job of a batch or of the serving queue: exactly one of tree / chain is set. */
+typedef struct {
+  const rmc_tree_desc* tree;
+  const rmc_chain_desc* chain;
+} rmc_job_desc;
 
 typedef struct {
   int precision;          /* rmc_precision                                          */
@@ -178,16 +217,23 @@ rmc_status rmc_couple_solve(rmc_ctx* ctx, rmc_module* A, rmc_module* B,
                             const rmc_solve_opts* opts, rmc_module** out,
                             double* energies_host, rmc_level_report* rep_host);
 
-/* (4) The whole recursion over a chain (Algorithm 1). Writes the lowest q
- * eigenvalues to energies_host; report is optional (NULL). */
-rmc_status rmc_recurse(rmc_ctx* ctx, const rmc_chain_desc* chain,
-                       const rmc_solve_opts* opts, double* energies_host,
-                       rmc_report* report);
+/* (4) The whole recursion over a module tree (Algorithm 1). Writes the lowest q
+ * eigenvalues of the root to energies_host; report is optional (NULL). Errors:
+ * RMC_ERR_ARG for a malformed tree (a child index not below its parent, a node not in
+ * the tree, a leaf outside 1..12 sites, a coupling term not of the form site of A /
+ * site of B, q outside 1..k); RMC_ERR_NOCONV when a solve does not converge: if it was
+ * the root's, energies_host holds its best Ritz values, else NaN. */
+rmc_status rmc_recurse(rmc_ctx* ctx, const rmc_tree_desc* tree, const rmc_solve_opts* opts,
+                       double* energies_host, rmc_report* report);
+/* The same over a chain (its default tree, see rmc_chain_desc). */
+rmc_status rmc_recurse_chain(rmc_ctx* ctx, const rmc_chain_desc* chain,
+                             const rmc_solve_opts* opts, double* energies_host,
+                             rmc_report* report);
 
-/* Batched recursion: n_jobs chains solved level by level, each level's leaf EDs
- * and merges of all jobs in batched launches. energies_host is n_jobs x q_stride;
+/* Batched recursion: n_jobs trees or chains solved level by level, each level's leaf
+ * EDs and merges of all jobs in batched launches. energies_host is n_jobs x q_stride;
  * status_host (optional) gets one rmc_status per job. */
-rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_chain_desc* chains,
+rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_job_desc* jobs,
                              const rmc_solve_opts* opts, double* energies_host,
                              int q_stride, int* status_host);
 
@@ -201,13 +247,14 @@ rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_chain_desc* cha
  * device-resident between a job's levels. */
 rmc_status rmc_serve_start(rmc_ctx* ctx, const rmc_solve_opts* opts, int max_inflight,
                            size_t mem_budget);
-/* Queue a job (the descriptor and its terms are copied); never blocks. A job that
- * can never fit the budget completes at once with RMC_ERR_OOM. */
-rmc_status rmc_submit(rmc_ctx* ctx, const rmc_chain_desc* chain, unsigned long long* job_id);
-/* done = 1 once finished; then energies (q), the job's status and its latency
- * (submission to completion, ms) are written and the result is released. */
+/* Queue a job (the descriptor, its tree or chain and their terms are copied); never
+ * blocks. A job that can never fit the budget completes at once with RMC_ERR_OOM. */
+rmc_status rmc_submit(rmc_ctx* ctx, const rmc_job_desc* job, unsigned long long* job_id);
+/* done = 1 once finished; then min(q, capacity) energies, the job's status and its
+ * latency (submission to completion, ms) are written and the result is released.
+ * energies_host may be NULL (capacity is then ignored). */
 rmc_status rmc_poll(rmc_ctx* ctx, unsigned long long job_id, int* done, double* energies_host,
-                    int* job_status, double* latency_ms);
+                    int capacity, int* job_status, double* latency_ms);
 /* Finish every queued and in-flight job, then stop the scheduler thread. */
 rmc_status rmc_serve_stop(rmc_ctx* ctx);
 

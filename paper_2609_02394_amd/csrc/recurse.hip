@@ -1,8 +1,10 @@
-// Recursion over a chain (Algorithm 1): leaves of consecutive sites, pairwise
-// merges of neighbouring modules left to right (an odd module is carried up),
-// boundary operators projected and transformed as later merges require, identical
-// modules computed once (the paper's reuse of identical blocks), the lowest q
-// eigenvalues of the final merge returned.
+// Recursion over a module tree (Algorithm 1 with a caller-defined hierarchy, Fig. 1's
+// recursive block merging): leaf blocks with their own Hamiltonians, merges with
+// their children and coupling terms, run level by level (a merge one level above its
+// deeper child); boundary operators projected and transformed as later merges
+// require; identical modules computed once (the paper's reuse of identical blocks);
+// the lowest q eigenvalues of the root returned. A chain is one such tree: leaves of
+// consecutive sites merged pairwise left to right, an odd module carried up.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -62,11 +64,25 @@ struct CutTerm {
   int sa, oa, sb, ob;
 };
 
+// An owned copy of a module tree (the caller's descriptor, or the tree of a chain).
+struct TreeStore {
+  std::vector<rmc_tree_node> nodes;
+  std::vector<std::vector<rmc_term>> terms;  // per node
+  int k = 0, q = 0;
+  void fix() {  // point the nodes at their own term storage
+    for (size_t i = 0; i < nodes.size(); ++i) {
+      nodes[i].n_terms = (int)terms[i].size();
+      nodes[i].terms = terms[i].empty() ? nullptr : terms[i].data();
+    }
+  }
+};
+
 struct Node {
   int kind = 0;  // 0 leaf, 1 merge
-  int a = 0, b = 0;
+  int width = 0;
   int left = -1, right = -1;
   int level = 0;
+  int k = 0;     // retained states
   bool root = false;
   int key = -1;
   std::vector<rmc_term> terms;  // leaf: local sites
@@ -77,16 +93,25 @@ struct Plan {
   std::vector<Node> nodes;
   int root = -1;
   int n_keys = 0;
+  int q = 0;
   std::vector<std::set<std::pair<int, int>>> need;  // per key: (site, op)
 };
 
-std::string term_bytes(const rmc_term& t, int shift) {
+std::string term_bytes(const rmc_term& t) {
   std::string s;
   s.append((const char*)&t.coef, sizeof(double));
-  int v[5] = {t.nsite, t.site[0] - shift, t.nsite > 1 ? t.site[1] - shift : -1, t.op[0],
-              t.nsite > 1 ? t.op[1] : 0};
+  int v[5] = {t.nsite, t.site[0], t.nsite > 1 ? t.site[1] : -1, t.op[0], t.nsite > 1 ? t.op[1] : 0};
   s.append((const char*)v, sizeof(v));
   return s;
+}
+
+void validate_term(const rmc_term& tm, int n_sites) {
+  RMC_CHECK(tm.nsite == 1 || tm.nsite == 2, RMC_ERR_ARG, "term nsite must be 1 or 2");
+  for (int u = 0; u < tm.nsite; ++u) {
+    RMC_CHECK(tm.site[u] >= 0 && tm.site[u] < n_sites, RMC_ERR_ARG, "term site out of range");
+    RMC_CHECK(tm.op[u] >= RMC_OP_X && tm.op[u] <= RMC_OP_Z, RMC_ERR_ARG, "unknown operator");
+  }
+  if (tm.nsite == 2) RMC_CHECK(tm.site[0] != tm.site[1], RMC_ERR_ARG, "two-site term on one site");
 }
 
 void validate_chain(const rmc_chain_desc* c) {
@@ -97,18 +122,120 @@ void validate_chain(const rmc_chain_desc* c) {
   RMC_CHECK(c->k >= 1, RMC_ERR_ARG, "k must be >= 1");
   RMC_CHECK(c->q >= 1 && c->q <= c->k, RMC_ERR_ARG, "need 1 <= q <= k");
   RMC_CHECK(c->n_terms >= 0 && (c->n_terms == 0 || c->terms), RMC_ERR_ARG, "bad term list");
-  for (int t = 0; t < c->n_terms; ++t) {
-    const rmc_term& tm = c->terms[t];
-    RMC_CHECK(tm.nsite == 1 || tm.nsite == 2, RMC_ERR_ARG, "term nsite must be 1 or 2");
-    for (int u = 0; u < tm.nsite; ++u) {
-      RMC_CHECK(tm.site[u] >= 0 && tm.site[u] < c->n_sites, RMC_ERR_ARG, "term site out of range");
-      RMC_CHECK(tm.op[u] >= RMC_OP_X && tm.op[u] <= RMC_OP_Z, RMC_ERR_ARG, "unknown operator");
-    }
-    if (tm.nsite == 2) RMC_CHECK(tm.site[0] != tm.site[1], RMC_ERR_ARG, "two-site term on one site");
-  }
+  for (int t = 0; t < c->n_terms; ++t) validate_term(c->terms[t], c->n_sites);
 }
 
-Plan make_plan(const rmc_chain_desc* c) {
+// The tree of a chain: leaves of leaf_sites consecutive sites, pairwise merges of
+// adjacent modules left to right, an odd module carried up. A leaf takes the terms
+// lying in it, a merge the two-site terms with one site in each child (in list order,
+// oriented A first, sites local to each child).
+TreeStore tree_of_chain(const rmc_chain_desc* c) {
+  validate_chain(c);
+  TreeStore T;
+  T.k = c->k;
+  T.q = c->q;
+  struct Span { int node, a, b; };
+  std::vector<Span> cur;
+  const int L0 = c->leaf_sites;
+  for (int a = 0; a < c->n_sites; a += L0) {
+    rmc_tree_node nd{-1, -1, L0, 0, nullptr, 0};
+    std::vector<rmc_term> ts;
+    for (int t = 0; t < c->n_terms; ++t) {
+      const rmc_term& tm = c->terms[t];
+      bool in = true;
+      for (int u = 0; u < tm.nsite; ++u) in = in && tm.site[u] >= a && tm.site[u] < a + L0;
+      if (!in) continue;
+      rmc_term lt = tm;
+      for (int u = 0; u < tm.nsite; ++u) lt.site[u] -= a;
+      ts.push_back(lt);
+    }
+    T.nodes.push_back(nd);
+    T.terms.push_back(std::move(ts));
+    cur.push_back({(int)T.nodes.size() - 1, a, a + L0});
+  }
+  while (cur.size() > 1) {
+    std::vector<Span> nxt;
+    for (size_t i = 0; i + 1 < cur.size(); i += 2) {
+      const int a = cur[i].a, m = cur[i].b, b = cur[i + 1].b;
+      rmc_tree_node nd{cur[i].node, cur[i + 1].node, 0, 0, nullptr, 0};
+      std::vector<rmc_term> ts;
+      for (int t = 0; t < c->n_terms; ++t) {
+        const rmc_term& tm = c->terms[t];
+        if (tm.nsite != 2) continue;
+        const int s0 = tm.site[0], s1 = tm.site[1];
+        const bool f = s0 >= a && s0 < m && s1 >= m && s1 < b;
+        const bool r = s1 >= a && s1 < m && s0 >= m && s0 < b;
+        if (!f && !r) continue;
+        rmc_term ct = tm;
+        ct.site[0] = (f ? s0 : s1) - a;
+        ct.op[0] = f ? tm.op[0] : tm.op[1];
+        ct.site[1] = (f ? s1 : s0) - m;
+        ct.op[1] = f ? tm.op[1] : tm.op[0];
+        ts.push_back(ct);
+      }
+      T.nodes.push_back(nd);
+      T.terms.push_back(std::move(ts));
+      nxt.push_back({(int)T.nodes.size() - 1, a, b});
+    }
+    if (cur.size() % 2) nxt.push_back(cur.back());
+    cur.swap(nxt);
+  }
+  T.fix();
+  return T;
+}
+
+// A validated copy of a caller's tree.
+TreeStore tree_copy(const rmc_tree_desc* t) {
+  RMC_CHECK(t != nullptr, RMC_ERR_ARG, "null tree");
+  RMC_CHECK(t->n_nodes >= 1 && t->nodes, RMC_ERR_ARG, "a tree needs at least one node");
+  RMC_CHECK(t->k >= 1, RMC_ERR_ARG, "k must be >= 1");
+  RMC_CHECK(t->q >= 1 && t->q <= t->k, RMC_ERR_ARG, "need 1 <= q <= k");
+  const int n = t->n_nodes;
+  TreeStore T;
+  T.k = t->k;
+  T.q = t->q;
+  std::vector<int> width(n, 0);
+  std::vector<char> reached(n, 0);
+  reached[n - 1] = 1;
+  for (int i = 0; i < n; ++i) {
+    const rmc_tree_node& nd = t->nodes[i];
+    RMC_CHECK(nd.n_terms >= 0 && (nd.n_terms == 0 || nd.terms), RMC_ERR_ARG, "bad term list");
+    RMC_CHECK(nd.k >= 0, RMC_ERR_ARG, "a node's k must be >= 0");
+    const bool leaf = nd.left < 0 && nd.right < 0;
+    if (leaf) {
+      RMC_CHECK(nd.left == -1 && nd.right == -1, RMC_ERR_ARG, "a leaf has left = right = -1");
+      RMC_CHECK(nd.n_sites >= 1 && nd.n_sites <= 12, RMC_ERR_ARG, "a leaf has 1..12 sites");
+      width[i] = nd.n_sites;
+      for (int u = 0; u < nd.n_terms; ++u) validate_term(nd.terms[u], nd.n_sites);
+    } else {
+      RMC_CHECK(nd.left >= 0 && nd.left < i && nd.right >= 0 && nd.right < i, RMC_ERR_ARG,
+                "a merge's children must come before it");
+      const int wA = width[nd.left], wB = width[nd.right];
+      RMC_CHECK(wA + wB <= (1 << 24), RMC_ERR_ARG, "tree too wide");
+      width[i] = wA + wB;
+      for (int u = 0; u < nd.n_terms; ++u) {
+        const rmc_term& tm = nd.terms[u];
+        RMC_CHECK(tm.nsite == 2, RMC_ERR_ARG, "a coupling term acts on one site of each child");
+        RMC_CHECK(tm.site[0] >= 0 && tm.site[0] < wA && tm.site[1] >= 0 && tm.site[1] < wB,
+                  RMC_ERR_ARG, "coupling term site outside its child");
+        for (int v = 0; v < 2; ++v)
+          RMC_CHECK(tm.op[v] >= RMC_OP_X && tm.op[v] <= RMC_OP_Z, RMC_ERR_ARG, "unknown operator");
+      }
+    }
+    T.nodes.push_back(nd);
+    T.terms.emplace_back(nd.terms, nd.terms + nd.n_terms);
+  }
+  for (int i = n - 1; i >= 0; --i)
+    if (reached[i] && t->nodes[i].left >= 0) reached[t->nodes[i].left] = reached[t->nodes[i].right] = 1;
+  for (int i = 0; i < n; ++i) RMC_CHECK(reached[i], RMC_ERR_ARG, "a node is not part of the tree");
+  T.fix();
+  return T;
+}
+
+// Plan of a tree: levels (leaf 0, merge 1 + deeper child), structural keys (modules
+// with equal content are computed once), and the operators each module must project
+// for the merges above it.
+Plan make_plan(const TreeStore& T) {
   Plan P;
   std::map<std::string, int> keys;
   auto intern = [&](const std::string& s) {
@@ -118,91 +245,63 @@ Plan make_plan(const rmc_chain_desc* c) {
     keys[s] = id;
     return id;
   };
-  const int L0 = c->leaf_sites;
-  std::vector<int> cur;
-  for (int a = 0; a < c->n_sites; a += L0) {
-    Node nd;
-    nd.kind = 0;
-    nd.a = a;
-    nd.b = a + L0;
-    std::string ks = "L" + std::to_string(L0) + ":";
-    for (int t = 0; t < c->n_terms; ++t) {
-      const rmc_term& tm = c->terms[t];
-      bool in = true;
-      for (int u = 0; u < tm.nsite; ++u) in = in && tm.site[u] >= a && tm.site[u] < a + L0;
-      if (!in) continue;
-      rmc_term lt = tm;
-      for (int u = 0; u < tm.nsite; ++u) lt.site[u] -= a;
-      nd.terms.push_back(lt);
-      ks += term_bytes(tm, a);
-    }
-    nd.key = intern(ks);
-    P.nodes.push_back(nd);
-    cur.push_back((int)P.nodes.size() - 1);
-  }
-  int level = 0;
-  while (cur.size() > 1) {
-    ++level;
-    std::vector<int> nxt;
-    const bool last = cur.size() == 2;
-    for (size_t i = 0; i + 1 < cur.size(); i += 2) {
-      const Node& L = P.nodes[cur[i]];
-      const Node& R = P.nodes[cur[i + 1]];
-      Node nd;
-      nd.kind = 1;
-      nd.a = L.a;
-      nd.b = R.b;
-      nd.left = cur[i];
-      nd.right = cur[i + 1];
-      nd.level = level;
-      nd.root = last;
-      const int a = L.a, m = L.b, b = R.b;
-      std::string ks = "M" + std::to_string(L.key) + "," + std::to_string(R.key) + (last ? "R:" : ":");
-      for (int t = 0; t < c->n_terms; ++t) {
-        const rmc_term& tm = c->terms[t];
-        if (tm.nsite != 2) continue;
-        int s0 = tm.site[0], s1 = tm.site[1];
-        bool f = s0 >= a && s0 < m && s1 >= m && s1 < b;
-        bool r = s1 >= a && s1 < m && s0 >= m && s0 < b;
-        if (!f && !r) continue;
-        CutTerm ct;
-        ct.coef = tm.coef;
-        if (f) {
-          ct.sa = s0 - a; ct.oa = tm.op[0]; ct.sb = s1 - m; ct.ob = tm.op[1];
-        } else {
-          ct.sa = s1 - a; ct.oa = tm.op[1]; ct.sb = s0 - m; ct.ob = tm.op[0];
-        }
-        nd.cut.push_back(ct);
-        int v[4] = {ct.sa, ct.oa, ct.sb, ct.ob};
-        ks.append((const char*)&ct.coef, sizeof(double));
-        ks.append((const char*)v, sizeof(v));
+  const int n = (int)T.nodes.size();
+  P.nodes.resize(n);
+  P.root = n - 1;
+  P.q = T.q;
+  for (int i = 0; i < n; ++i) {
+    const rmc_tree_node& tn = T.nodes[i];
+    Node& nd = P.nodes[i];
+    nd.k = tn.k > 0 ? tn.k : T.k;
+    nd.root = i == n - 1;
+    if (tn.left < 0) {
+      nd.kind = 0;
+      nd.width = tn.n_sites;
+      std::string ks = "L" + std::to_string(nd.width) + "k" + std::to_string(nd.k) + ":";
+      for (int u = 0; u < tn.n_terms; ++u) {
+        nd.terms.push_back(tn.terms[u]);
+        ks += term_bytes(tn.terms[u]);
       }
       nd.key = intern(ks);
-      P.nodes.push_back(nd);
-      nxt.push_back((int)P.nodes.size() - 1);
+      continue;
     }
-    if (cur.size() % 2) nxt.push_back(cur.back());
-    cur.swap(nxt);
+    const Node& L = P.nodes[tn.left];
+    const Node& R = P.nodes[tn.right];
+    nd.kind = 1;
+    nd.left = tn.left;
+    nd.right = tn.right;
+    nd.width = L.width + R.width;
+    nd.level = 1 + std::max(L.level, R.level);
+    std::string ks = "M" + std::to_string(L.key) + "," + std::to_string(R.key) + "k" +
+                     std::to_string(nd.k) + (nd.root ? "R:" : ":");
+    for (int u = 0; u < tn.n_terms; ++u) {
+      const rmc_term& tm = tn.terms[u];
+      CutTerm ct{tm.coef, tm.site[0], tm.op[0], tm.site[1], tm.op[1]};
+      nd.cut.push_back(ct);
+      int v[4] = {ct.sa, ct.oa, ct.sb, ct.ob};
+      ks.append((const char*)&ct.coef, sizeof(double));
+      ks.append((const char*)v, sizeof(v));
+    }
+    nd.key = intern(ks);
   }
-  P.root = cur[0];
   P.n_keys = (int)keys.size();
-  // operator requirements: top-down per node, then per key
-  std::vector<std::set<std::pair<int, int>>> nneed(P.nodes.size());
-  for (int i = (int)P.nodes.size() - 1; i >= 0; --i) {
+  // operator requirements: top-down (parents have larger indices), then per key
+  std::vector<std::set<std::pair<int, int>>> nneed(n);
+  for (int i = n - 1; i >= 0; --i) {
     const Node& nd = P.nodes[i];
     if (nd.kind != 1) continue;
     for (const CutTerm& ct : nd.cut) {
       nneed[nd.left].insert({ct.sa, ct.oa});
       nneed[nd.right].insert({ct.sb, ct.ob});
     }
-    const int wA = P.nodes[nd.left].b - P.nodes[nd.left].a;
+    const int wA = P.nodes[nd.left].width;
     for (auto& so : nneed[i]) {
       if (so.first < wA) nneed[nd.left].insert(so);
       else nneed[nd.right].insert({so.first - wA, so.second});
     }
   }
   P.need.assign(P.n_keys, {});
-  for (size_t i = 0; i < P.nodes.size(); ++i)
+  for (int i = 0; i < n; ++i)
     for (auto& so : nneed[i]) P.need[P.nodes[i].key].insert(so);
   return P;
 }
@@ -218,9 +317,9 @@ void add_record(rmc_report* rep, const rmc_level_report& r) {
   rep->n_records++;
 }
 
-// One job in flight: its plan, its modules (by structural key) and its results.
+// One job in flight: its tree, plan, modules (by structural key) and results.
 struct JobRun {
-  const rmc_chain_desc* c = nullptr;
+  TreeStore tree;
   Plan P;
   std::vector<rmc_module*> by_key;
   std::vector<rmc_module*> created;
@@ -234,11 +333,12 @@ struct JobRun {
   bool done = false;
 };
 
-void job_init(JobRun& J, const rmc_chain_desc* c, rmc_report* rep) {
-  J.c = c;
-  J.P = make_plan(c);
+void job_init(JobRun& J, TreeStore&& T, rmc_report* rep) {
+  J.tree = std::move(T);
+  J.tree.fix();
+  J.P = make_plan(J.tree);
   J.by_key.assign(J.P.n_keys, nullptr);
-  J.e.assign(c->q, NAN);
+  J.e.assign(J.P.q, NAN);
   J.rep = rep;
   J.t0 = now_ms();
   J.level = 0;
@@ -249,6 +349,13 @@ void job_init(JobRun& J, const rmc_chain_desc* c, rmc_report* rep) {
     rep->n_leaf_ed = 0;
     rep->n_merges = 0;
   }
+}
+
+TreeStore tree_of_job(const rmc_job_desc* j) {
+  RMC_CHECK(j != nullptr, RMC_ERR_ARG, "null job");
+  RMC_CHECK((j->tree != nullptr) != (j->chain != nullptr), RMC_ERR_ARG,
+            "a job sets exactly one of tree and chain");
+  return j->tree ? tree_copy(j->tree) : tree_of_chain(j->chain);
 }
 
 void job_release(rmc_ctx* ctx, JobRun& J) {
@@ -277,6 +384,7 @@ struct Task {
 
 // Runs one level (the next level of every job in `jobs`) as batched solves.
 void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o) {
+  std::unique_ptr<HostScope> tasks_scope(new HostScope("level.tasks"));
   std::vector<Task> leaf_t, merge_t, reused;
   for (JobRun* J : jobs) {
     if (J->done) continue;
@@ -311,24 +419,27 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
     }
     return out;
   };
+  tasks_scope.reset();
   auto after_module = [&](JobRun* J, int node, rmc_module* m, rmc_level_report r,
                           const std::vector<double>& ev) {
+    RMC_HOST_SCOPE("level.after_module");
     const Node& nd = J->P.nodes[node];
     r.level = nd.level;
-    r.width = nd.b - nd.a;
+    r.width = nd.width;
     if (m) {
       J->created.push_back(m);
       for (auto& so : J->P.need[nd.key]) api_project_op(ctx, m, so.first, so.second);  // already batched
       api_release_basis(ctx, m);
       J->by_key[nd.key] = m;
     } else {  // root: energies
-      for (int q = 0; q < J->c->q; ++q) J->e[q] = ev[q];
+      for (int q = 0; q < J->P.q; ++q) J->e[q] = ev[q];
     }
     add_record(J->rep, r);
     if (J->rep) (nd.kind == 0 ? J->rep->n_leaf_ed : J->rep->n_merges)++;
   };
   // the operators later steps need from the new modules, in one batch
   auto project_new = [&](const std::vector<Task>& C, const std::vector<rmc_module*>& mods) {
+    RMC_HOST_SCOPE("level.project_new");
     std::vector<rmc_module*> ms;
     std::vector<std::pair<int, int>> so;
     for (size_t i = 0; i < C.size() && i < mods.size(); ++i) {
@@ -344,8 +455,8 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
   // leaves
   for (auto& ch : chunks(leaf_t, [&](const Task& t) {
          const Node& nd = t.J->P.nodes[t.node];
-         const int D = 1 << (nd.b - nd.a);
-         return task_bytes(D, std::min(D, t.J->c->k + 1)) + (size_t)D * D * 8;
+         const int D = 1 << nd.width;
+         return task_bytes(D, std::min(D, nd.k + 1)) + (size_t)D * D * 8;
        })) {
     auto solve = [&](std::vector<Task>& C) {
       std::vector<rmc_leaf_desc> lds(C.size());
@@ -353,15 +464,24 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
       std::vector<int> ks, qo;
       for (size_t i = 0; i < C.size(); ++i) {
         const Node& nd = C[i].J->P.nodes[C[i].node];
-        lds[i] = rmc_leaf_desc{nd.b - nd.a, (int)nd.terms.size(), nd.terms.data()};
+        lds[i] = rmc_leaf_desc{nd.width, (int)nd.terms.size(), nd.terms.data()};
         lp.push_back(&lds[i]);
-        ks.push_back(C[i].J->c->k);
+        ks.push_back(nd.k);
         const bool single = C[i].node == C[i].J->P.root;
-        qo.push_back(single ? C[i].J->c->q : 0);
+        qo.push_back(single ? C[i].J->P.q : 0);
       }
       std::vector<std::vector<double>> ev;
       std::vector<rmc_level_report> reps;
-      auto mods = api_leaf_solve_batch(ctx, lp, ks, qo, o, ev, &reps);
+      std::vector<rmc_module*> mods;
+      try {
+        mods = api_leaf_solve_batch(ctx, lp, ks, qo, o, ev, &reps);
+      } catch (const Error& e) {
+        if (e.code == RMC_ERR_NOCONV)  // a single-leaf job's best Ritz values
+          for (size_t i = 0; i < C.size() && i < ev.size(); ++i)
+            if (qo[i] > 0 && (int)ev[i].size() >= qo[i])
+              for (int q = 0; q < qo[i]; ++q) C[i].J->e[q] = ev[i][q];
+        throw;
+      }
       project_new(C, mods);
       for (size_t i = 0; i < C.size(); ++i) {
         reps[i].kind = qo[i] > 0 ? 2 : 0;
@@ -398,7 +518,7 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
          if (A && B)
            for (int pr = 0; pr < 3; ++pr)
              packs += kron_pack_bytes(pr, A->k_eff, B->k_eff, (int)nd.cut.size()) + 256;
-         return task_bytes(n, nd.root ? t.J->c->q : t.J->c->k + 1) + packs;
+         return task_bytes(n, nd.root ? t.J->P.q : nd.k + 1) + packs;
        })) {
     auto solve = [&](std::vector<Task>& C) {
       std::vector<rmc_module*> As, Bs;
@@ -426,15 +546,26 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
         As.push_back(A);
         Bs.push_back(B);
         want.push_back(nd.root ? 0 : 1);
-        kk.push_back(J->c->k);
-        qq.push_back(nd.root ? J->c->q : std::min(J->c->q, J->c->k));
+        kk.push_back(nd.k);
+        qq.push_back(nd.root ? J->P.q : std::min(J->P.q, nd.k));
         live.push_back(C[i]);
       }
       for (size_t w = 0; w < live.size(); ++w) bp.push_back(&bds[w]);
       if (live.empty()) return;
       std::vector<std::vector<double>> ev;
       std::vector<rmc_level_report> reps;
-      auto mods = api_couple_batch(ctx, As, Bs, bp, want, kk, qq, o, ev, &reps);
+      std::vector<rmc_module*> mods;
+      try {
+        mods = api_couple_batch(ctx, As, Bs, bp, want, kk, qq, o, ev, &reps);
+      } catch (const Error& e) {
+        // a root that did not converge keeps its best Ritz values (the error still
+        // ends the job)
+        if (e.code == RMC_ERR_NOCONV)
+          for (size_t i = 0; i < live.size() && i < ev.size(); ++i)
+            if (!want[i] && (int)ev[i].size() >= live[i].J->P.q)
+              for (int q = 0; q < live[i].J->P.q; ++q) live[i].J->e[q] = ev[i][q];
+        throw;
+      }
       project_new(live, mods);
       for (size_t i = 0; i < live.size(); ++i) after_module(live[i].J, live[i].node, mods[i], reps[i], ev[i]);
     };
@@ -463,7 +594,7 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
     const Node& nd = t.J->P.nodes[t.node];
     rmc_level_report r{};
     r.level = nd.level;
-    r.width = nd.b - nd.a;
+    r.width = nd.width;
     r.kind = nd.kind;
     r.reused = 1;
     if (rmc_module* m = t.J->by_key[nd.key]) {
@@ -472,6 +603,7 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
     }
     add_record(t.J->rep, r);
   }
+  RMC_HOST_SCOPE("level.finish");
   for (JobRun* J : jobs) {
     if (J->done) continue;
     if (J->level >= J->max_level) {
@@ -497,8 +629,6 @@ void run_jobs(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o)
 
 struct ServeJob {
   unsigned long long id = 0;
-  rmc_chain_desc desc{};
-  std::vector<rmc_term> terms;
   double t_submit = 0.0;
   size_t mem = 0;
   JobRun run;
@@ -529,34 +659,49 @@ struct ServeState {
 };
 
 // Device memory a job needs at its widest level (solver workspace of the distinct
-// modules of that level), from its plan.
-size_t job_memory(const Plan& P, int k) {
-  std::map<int, std::set<int>> keys_by_level;
-  std::map<int, int> dim_by_level;
-  std::map<int, size_t> pack_by_level;
-  for (const Node& nd : P.nodes) {
-    keys_by_level[nd.level].insert(nd.key);
-    int dim = nd.kind == 0 ? (1 << (nd.b - nd.a)) : k * k;
-    dim_by_level[nd.level] = std::max(dim_by_level[nd.level], dim);
-    if (nd.kind == 1) {
-      size_t pk = 0;
-      for (int pr = 0; pr < 3; ++pr) pk += kron_pack_bytes(pr, k, k, (int)nd.cut.size()) + 256;
-      pack_by_level[nd.level] = std::max(pack_by_level[nd.level], pk);
+// modules of that level) plus the projected operators its modules keep, from its plan.
+size_t job_memory(const Plan& P) {
+  const int n = (int)P.nodes.size();
+  std::vector<long> kept(n, 1);
+  std::map<int, std::map<int, size_t>> by_level;  // level -> key -> bytes
+  std::set<int> seen;
+  size_t keep_bytes = 0;
+  for (int i = 0; i < n; ++i) {
+    const Node& nd = P.nodes[i];
+    long dim, nev;
+    size_t b;
+    if (nd.kind == 0) {
+      dim = 1L << nd.width;
+      kept[i] = nd.root ? std::min<long>(P.q, dim) : std::min<long>(nd.k, dim);
+      nev = nd.root ? std::min<long>(P.q, dim) : std::min<long>(dim, nd.k + 1);
+      b = task_bytes((int)dim, (int)nev) + (size_t)dim * dim * 8;
+    } else {
+      const long kA = kept[nd.left], kB = kept[nd.right];
+      dim = kA * kB;
+      kept[i] = nd.root ? std::min<long>(P.q, dim) : std::min<long>(nd.k, dim);
+      nev = nd.root ? std::min<long>(P.q, dim) : std::min<long>(dim, nd.k + 1);
+      size_t packs = 0;
+      for (int pr = 0; pr < 3; ++pr) packs += kron_pack_bytes(pr, (int)kA, (int)kB, (int)nd.cut.size()) + 256;
+      b = task_bytes((int)dim, (int)nev) + (size_t)dim * 64 + packs;
     }
+    size_t& slot = by_level[nd.level][nd.key];
+    slot = std::max(slot, b);
+    if (seen.insert(nd.key).second)
+      keep_bytes += (P.need[nd.key].size() * kept[i] * kept[i] + kept[i]) * sizeof(double) +
+                    (size_t)kept[i] * dim * sizeof(double);  // basis until its projections
   }
   size_t best = 0;
-  for (auto& kv : keys_by_level) {
-    const int dim = dim_by_level[kv.first];
-    size_t b = kv.second.size() *
-               (task_bytes(dim, std::min(dim, k + 1)) + (size_t)dim * 64 + pack_by_level[kv.first]);
-    best = std::max(best, b);
+  for (auto& lv : by_level) {
+    size_t sum = 0;
+    for (auto& kv : lv.second) sum += kv.second;
+    best = std::max(best, sum);
   }
-  return best + (size_t)P.n_keys * 6 * (size_t)k * k * sizeof(double);
+  return best + keep_bytes;
 }
 
 void serve_loop(ServeState* S) {
   rmc_ctx* ctx = S->ctx;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
@@ -629,30 +774,50 @@ rmc_status guard(rmc_ctx* ctx, F&& f) {
 
 extern "C" {
 
-rmc_status rmc_recurse(rmc_ctx* ctx, const rmc_chain_desc* chain, const rmc_solve_opts* opts,
+namespace {
+rmc_status recurse_one(rmc_ctx* ctx, const rmc_job_desc* job, const rmc_solve_opts* opts,
                        double* energies, rmc_report* report) {
   if (!ctx) return RMC_ERR_ARG;
-  return guard(ctx, [&] {
-    validate_chain(chain);
+  JobRun J;
+  rmc_status st = guard(ctx, [&] {
     RMC_CHECK(energies != nullptr, RMC_ERR_ARG, "null energies");
     rmc_solve_opts o;
     rmc_default_opts(&o);
     if (opts) o = *opts;
     RMC_CHECK(o.precision >= RMC_FP64 && o.precision <= RMC_BF16, RMC_ERR_ARG, "bad precision");
-    JobRun J;
-    job_init(J, chain, report);
+    job_init(J, tree_of_job(job), report);
     std::vector<JobRun*> jobs{&J};
     run_jobs(ctx, jobs, o);
     if (J.status != RMC_OK) throw Error(J.status, J.err);
-    for (int i = 0; i < chain->q; ++i) energies[i] = J.e[i];
+    for (int i = 0; i < J.P.q; ++i) energies[i] = J.e[i];
   });
+  // a solve that did not converge: the root's best Ritz values where it was the root's
+  // (NaN otherwise), and the report as far as it got
+  if (st == RMC_ERR_NOCONV && J.status == RMC_ERR_NOCONV)
+    for (int i = 0; i < J.P.q; ++i) energies[i] = J.e[i];
+  return st;
+}
+}  // namespace
+
+rmc_status rmc_recurse(rmc_ctx* ctx, const rmc_tree_desc* tree, const rmc_solve_opts* opts,
+                       double* energies, rmc_report* report) {
+  rmc_job_desc j{tree, nullptr};
+  if (!tree) return RMC_ERR_ARG;
+  return recurse_one(ctx, &j, opts, energies, report);
 }
 
-rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_chain_desc* chains,
+rmc_status rmc_recurse_chain(rmc_ctx* ctx, const rmc_chain_desc* chain, const rmc_solve_opts* opts,
+                             double* energies, rmc_report* report) {
+  rmc_job_desc j{nullptr, chain};
+  if (!chain) return RMC_ERR_ARG;
+  return recurse_one(ctx, &j, opts, energies, report);
+}
+
+rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_job_desc* jobs,
                              const rmc_solve_opts* opts, double* energies, int q_stride,
                              int* status_host) {
   if (!ctx) return RMC_ERR_ARG;
-  if (n_jobs < 0 || (n_jobs > 0 && (!chains || !energies))) return RMC_ERR_ARG;
+  if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !energies))) return RMC_ERR_ARG;
   std::vector<JobRun> runs(n_jobs);
   std::vector<int> st(n_jobs, RMC_OK);
   rmc_status top = guard(ctx, [&] {
@@ -663,9 +828,9 @@ rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_chain_desc* cha
     std::vector<JobRun*> live;
     for (int j = 0; j < n_jobs; ++j) {
       try {
-        validate_chain(&chains[j]);
-        RMC_CHECK(chains[j].q <= q_stride, RMC_ERR_ARG, "q above q_stride");
-        job_init(runs[j], &chains[j], nullptr);
+        TreeStore T = tree_of_job(&jobs[j]);
+        RMC_CHECK(T.q <= q_stride, RMC_ERR_ARG, "q above q_stride");
+        job_init(runs[j], std::move(T), nullptr);
         live.push_back(&runs[j]);
       } catch (const Error& e) {
         st[j] = e.code;
@@ -673,11 +838,12 @@ rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_chain_desc* cha
     }
     run_jobs(ctx, live, o);
   });
+  host_trace_dump("rmc_recurse_batch");
   rmc_status worst = top;
   for (int j = 0; j < n_jobs; ++j) {
     if (st[j] == RMC_OK) st[j] = runs[j].status;
     if (st[j] == RMC_OK && top == RMC_OK)
-      for (int i = 0; i < chains[j].q; ++i) energies[(size_t)j * q_stride + i] = runs[j].e[i];
+      for (int i = 0; i < runs[j].P.q; ++i) energies[(size_t)j * q_stride + i] = runs[j].e[i];
     if (status_host) status_host[j] = top != RMC_OK ? top : st[j];
     if (st[j] != RMC_OK && worst == RMC_OK) worst = (rmc_status)st[j];
   }
@@ -704,18 +870,14 @@ rmc_status rmc_serve_start(rmc_ctx* ctx, const rmc_solve_opts* opts, int max_inf
   });
 }
 
-rmc_status rmc_submit(rmc_ctx* ctx, const rmc_chain_desc* chain, unsigned long long* job_id) {
+rmc_status rmc_submit(rmc_ctx* ctx, const rmc_job_desc* job, unsigned long long* job_id) {
   if (!ctx || !ctx->serving || !job_id) return !ctx ? RMC_ERR_ARG : (!job_id ? RMC_ERR_ARG : RMC_ERR_STATE);
   ServeState* S = (ServeState*)ctx->serve;
   try {
-    validate_chain(chain);
     auto j = std::make_unique<ServeJob>();
-    j->desc = *chain;
-    j->terms.assign(chain->terms, chain->terms + chain->n_terms);
-    j->desc.terms = j->terms.data();
     j->t_submit = now_ms();
-    job_init(j->run, &j->desc, nullptr);
-    j->mem = job_memory(j->run.P, j->desc.k);
+    job_init(j->run, tree_of_job(job), nullptr);
+    j->mem = job_memory(j->run.P);
     std::lock_guard<std::mutex> lk(S->mu);
     j->id = S->next_id++;
     *job_id = j->id;
@@ -731,8 +893,9 @@ rmc_status rmc_submit(rmc_ctx* ctx, const rmc_chain_desc* chain, unsigned long l
 }
 
 rmc_status rmc_poll(rmc_ctx* ctx, unsigned long long job_id, int* done, double* energies,
-                    int* job_status, double* latency_ms) {
+                    int capacity, int* job_status, double* latency_ms) {
   if (!ctx || !ctx->serving || !done) return !ctx || !done ? RMC_ERR_ARG : RMC_ERR_STATE;
+  if (energies && capacity < 0) return RMC_ERR_ARG;
   ServeState* S = (ServeState*)ctx->serve;
   std::lock_guard<std::mutex> lk(S->mu);
   auto it = S->done.find(job_id);
@@ -742,7 +905,10 @@ rmc_status rmc_poll(rmc_ctx* ctx, unsigned long long job_id, int* done, double* 
     return RMC_OK;
   }
   *done = 1;
-  if (energies) std::copy(it->second.e.begin(), it->second.e.end(), energies);
+  if (energies) {
+    const size_t nc = std::min(it->second.e.size(), (size_t)capacity);
+    std::copy(it->second.e.begin(), it->second.e.begin() + nc, energies);
+  }
   if (job_status) *job_status = it->second.status;
   if (latency_ms) *latency_ms = it->second.latency_ms;
   S->done.erase(it);

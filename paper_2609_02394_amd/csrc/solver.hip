@@ -389,14 +389,24 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
     vec_launch(B, VEC_AXPY3, v);
     return;
   }
-  for (int prec = 0; prec < 3; ++prec) {
+  // one launch per precision and tile class (the padded tile of the streaming
+  // kernel, 32 / 64 / 96 / 128, or wider): each problem gets the kernel of its own size
+  // rather than that of the largest problem of the batch
+  auto tile_class = [](const CoupledOp* op) {
+    const int k = std::max(op->kA, op->kB);
+    return k <= 32 ? 0 : (k <= 64 ? 1 : (k <= 96 ? 2 : (k <= 128 ? 3 : 4)));
+  };
+  for (int pc = 0; pc < 15; ++pc) {
+    const int prec = pc / 5, cls = pc % 5;
     std::vector<KronDesc> kd;
-    int nvmax = 0, Tm = 0;
+    int nvmax = 0, Tm = 0, kAm = 0, kBm = 0;
     long tv = 0;
     for (size_t i = 0; i < L.size(); ++i) {
       BP* p = L[i];
       int pr = use_prec ? p->prec : RMC_FP64;
-      if (pr != prec) continue;
+      if (pr != prec || tile_class(p->op) != cls) continue;
+      kAm = std::max(kAm, p->op->kA);
+      kBm = std::max(kBm, p->op->kB);
       KronDesc d{};
       d.kA = p->op->kA; d.kB = p->op->kB; d.T = p->op->T; d.nv = a.cnt[i];
       d.coef = p->op->coef_dev; d.OA = p->op->OAcat; d.OB = p->op->OBcat; d.Ediag = p->op->Ediag;
@@ -413,7 +423,7 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
     if (kd.empty()) continue;
     const KronDesc* dd = B.da->add(kd);
     hipStream_t st = B.st;
-    const int P = (int)kd.size(), kBm = B.kBmax, kAm = B.kAmax;
+    const int P = (int)kd.size();
     if (!ctx->prof) {
       B.da->defer([=] { kron_batched(st, dd, P, kBm, nvmax, kAm, prec, Tm, tv); });
       continue;
@@ -468,6 +478,7 @@ void read_state(Batch& B) {
   B.da->flush();
   RMC_HIP(hipMemcpyAsync(B.TRh.data(), B.TR, B.TRh.size() * sizeof(double), hipMemcpyDeviceToHost,
                          B.st));
+  RMC_HOST_SCOPE("solve.state_wait");
   RMC_HIP(hipStreamSynchronize(B.st));
   B.da->reset();
 }
@@ -1081,6 +1092,7 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
     p->matvecs = 0;
   }
   const int P = (int)probs.size();
+  std::unique_ptr<HostScope> alloc_scope(new HostScope("solve.alloc"));
   // K-slices of the Gram products: enough workgroups to cover the chip, slices of at
   // least 128 columns
   B.KS = std::max(1, std::min({64, (512 + P - 1) / P, std::max(1, B.nmax / 128)}));
@@ -1118,6 +1130,7 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
       (size_t)P * ((size_t)(pmax + 4) * B.mmax * 8 + (size_t)(pmax + 48) * 4 * 256) + (1 << 20);
   DescArena da(ctx, B.st, lane, sc, da_bytes);
   B.da = &da;
+  alloc_scope.reset();
 
   {
     std::vector<StartDesc> sd;
@@ -1144,6 +1157,7 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
     std::vector<BP*> act;
     std::vector<int> ai;
     static const bool trace = getenv("RMC_TRACE_SOLVER") != nullptr;
+    std::unique_ptr<HostScope> upd(new HostScope("solve.update"));
     for (int i = 0; i < P; ++i) {
       BP* p = probs[i];
       if (p->state != 0) continue;
@@ -1156,14 +1170,25 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
                   p->rr_sweeps);
       }
     }
+    upd.reset();
     if (act.empty()) break;
     // each phase's launches go out as soon as their tables are built, so the host
     // prepares the next phase while the device runs this one
-    const int r = filter(B, act);
-    B.da->flush();
-    orthonormalize(B, act, r);
-    B.da->flush();
-    rayleigh_ritz(B, act, r, r == 0 ? 1 : 0, false);
+    int r;
+    {
+      RMC_HOST_SCOPE("solve.filter_host");
+      r = filter(B, act);
+      B.da->flush();
+    }
+    {
+      RMC_HOST_SCOPE("solve.ortho_host");
+      orthonormalize(B, act, r);
+      B.da->flush();
+    }
+    {
+      RMC_HOST_SCOPE("solve.rr_host");
+      rayleigh_ritz(B, act, r, r == 0 ? 1 : 0, false);
+    }
     for (BP* p : act) p->iters++;
   }
   // final Rayleigh-Ritz over whole blocks (with the stored H X) and FP64 residual check

@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_NOCONV", 4: "ERR_HI
 
 EXPORTED = (
     "rmc_default_opts", "rmc_create", "rmc_destroy", "rmc_last_error", "rmc_arena_usage",
-    "rmc_module_ed", "rmc_project_ops", "rmc_couple_solve", "rmc_recurse", "rmc_recurse_batch",
+    "rmc_module_ed", "rmc_project_ops", "rmc_couple_solve", "rmc_recurse", "rmc_recurse_chain",
+    "rmc_recurse_batch",
     "rmc_module_info", "rmc_module_basis", "rmc_module_op", "rmc_module_free", "rmc_module_lift",
     "rmc_leaf_hamiltonian", "rmc_kron_apply", "rmc_sym_eig", "rmc_module_import",
     "rmc_profile", "rmc_profile_read", "rmc_profile_read_precision",
@@ -49,6 +50,19 @@ class BondDesc(C.Structure):
 class ChainDesc(C.Structure):
     _fields_ = [("n_sites", C.c_int), ("leaf_sites", C.c_int), ("n_terms", C.c_int),
                 ("terms", C.POINTER(Term)), ("k", C.c_int), ("q", C.c_int)]
+
+
+class TreeNode(C.Structure):
+    _fields_ = [("left", C.c_int), ("right", C.c_int), ("n_sites", C.c_int), ("n_terms", C.c_int),
+                ("terms", C.POINTER(Term)), ("k", C.c_int)]
+
+
+class TreeDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int), ("nodes", C.POINTER(TreeNode)), ("k", C.c_int), ("q", C.c_int)]
+
+
+class JobDesc(C.Structure):
+    _fields_ = [("tree", C.POINTER(TreeDesc)), ("chain", C.POINTER(ChainDesc))]
 
 
 class SolveOpts(C.Structure):
@@ -87,8 +101,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "rmc_project_ops": (i, [vp, vp, i, P(i), P(i), P(i)]),
         "rmc_couple_solve": (i, [vp, vp, vp, P(BondDesc), i, i, P(SolveOpts), P(vp), P(d),
                                  P(LevelReport)]),
-        "rmc_recurse": (i, [vp, P(ChainDesc), P(SolveOpts), P(d), P(Report)]),
-        "rmc_recurse_batch": (i, [vp, i, P(ChainDesc), P(SolveOpts), P(d), i, P(i)]),
+        "rmc_recurse": (i, [vp, P(TreeDesc), P(SolveOpts), P(d), P(Report)]),
+        "rmc_recurse_chain": (i, [vp, P(ChainDesc), P(SolveOpts), P(d), P(Report)]),
+        "rmc_recurse_batch": (i, [vp, i, P(JobDesc), P(SolveOpts), P(d), i, P(i)]),
         "rmc_module_info": (i, [vp, P(i), P(i), P(i), P(d)]),
         "rmc_module_basis": (i, [vp, vp, P(d)]),
         "rmc_module_lift": (i, [vp, vp, vp]),
@@ -103,8 +118,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "rmc_profile_read_precision": (i, [vp, i, P(C.c_longlong), P(d), P(d), P(d)]),
         "rmc_profile_read_kernel": (i, [vp, i, i, P(C.c_longlong), P(d), P(d), P(d)]),
         "rmc_serve_start": (i, [vp, P(SolveOpts), i, sz]),
-        "rmc_submit": (i, [vp, P(ChainDesc), P(C.c_ulonglong)]),
-        "rmc_poll": (i, [vp, C.c_ulonglong, P(i), P(d), P(i), P(d)]),
+        "rmc_submit": (i, [vp, P(JobDesc), P(C.c_ulonglong)]),
+        "rmc_poll": (i, [vp, C.c_ulonglong, P(i), P(d), i, P(i), P(d)]),
         "rmc_serve_stop": (i, [vp]),
         "rmc_merge_bound": (i, [vp, vp, P(LeafDesc), vp, P(LeafDesc), P(BondDesc), P(SolveOpts),
                                 P(d)]),
@@ -143,6 +158,42 @@ def make_terms(terms) -> "C.Array":
             arr[t].site[u] = int(s)
             arr[t].op[u] = OPS[o] if isinstance(o, str) else int(o)
     return arr, len(terms)
+
+
+def make_tree(nodes, k: int, q: int):
+    """A TreeDesc from nodes (children before parents, the last the root):
+    ("leaf", n_sites, terms, k_node) with terms as for make_terms (local sites), or
+    ("merge", left, right, terms, k_node) with terms (coef, site_A, op_A, site_B, op_B).
+    Returns (desc, keep-alive list)."""
+    arr = (TreeNode * max(1, len(nodes)))()
+    keep = [arr]
+    for i, nd in enumerate(nodes):
+        if nd[0] == "leaf":
+            _, n, terms, kn = nd
+            t, nt = make_terms(terms)
+            arr[i] = TreeNode(-1, -1, int(n), nt, t, int(kn))
+        else:
+            _, l, r, terms, kn = nd
+            t, nt = make_terms([(c, ((sa, oa), (sb, ob))) for c, sa, oa, sb, ob in terms])
+            arr[i] = TreeNode(int(l), int(r), 0, nt, t, int(kn))
+        keep.append(t)
+    desc = TreeDesc(len(nodes), arr, int(k), int(q))
+    keep.append(desc)
+    return desc, keep
+
+
+def make_job(job):
+    """A JobDesc from a chain tuple (n_sites, leaf_sites, terms, k, q) or a tree tuple
+    ("tree", nodes, k, q). Returns (desc, q, keep-alive list)."""
+    if job[0] == "tree":
+        _, nodes, k, q = job
+        td, keep = make_tree(nodes, k, q)
+        jd = JobDesc(C.pointer(td), None)
+        return jd, q, keep + [td]
+    ns, ls, terms, k, q = job
+    arr, nt = make_terms(terms)
+    cd = ChainDesc(ns, ls, nt, arr, int(k), int(q))
+    return JobDesc(None, C.pointer(cd)), q, [arr, cd]
 
 
 def default_opts(**kw) -> SolveOpts:
@@ -332,28 +383,47 @@ class Context:
 
     def recurse(self, n_sites: int, leaf_sites: int, terms, k: int, q: int,
                 opts: Optional[SolveOpts] = None, report_capacity: int = 64):
+        """The recursion over a chain (rmc_recurse_chain)."""
         arr, nt = make_terms(terms)
         ch = ChainDesc(n_sites, leaf_sites, nt, arr, int(k), int(q))
         e = np.zeros(q)
         recs = (LevelReport * report_capacity)()
         rep = Report(report_capacity, 0, recs, 0, 0, 0.0)
-        self._check(lib().rmc_recurse(self.h, C.byref(ch), C.byref(opts) if opts else None,
-                                      e.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rep)))
-        records = [recs[i].as_dict() for i in range(min(rep.n_records, report_capacity))]
-        return e, {"records": records, "n_leaf_ed": rep.n_leaf_ed, "n_merges": rep.n_merges,
-                   "total_ms": rep.total_ms}
+        self._check(lib().rmc_recurse_chain(self.h, C.byref(ch), C.byref(opts) if opts else None,
+                                            e.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rep)))
+        return e, self._report(rep, recs, report_capacity)
 
-    def recurse_batch(self, chains, opts: Optional[SolveOpts] = None):
-        """chains: list of (n_sites, leaf_sites, terms, k, q). Returns energies (n, qmax)
-        and per-job status codes."""
-        n = len(chains)
-        qmax = max(c[4] for c in chains) if chains else 1
-        descs = (ChainDesc * max(1, n))()
+    def recurse_tree(self, nodes, k: int, q: int, opts: Optional[SolveOpts] = None,
+                     report_capacity: int = 256, allow=()):
+        """The recursion over a module tree (rmc_recurse); nodes as for make_tree.
+        Returns (energies, report, status)."""
+        td, keep = make_tree(nodes, k, q)
+        e = np.full(q, np.nan)
+        recs = (LevelReport * report_capacity)()
+        rep = Report(report_capacity, 0, recs, 0, 0, 0.0)
+        st = self._check(lib().rmc_recurse(self.h, C.byref(td), C.byref(opts) if opts else None,
+                                           e.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rep)),
+                         allow=allow)
+        return e, self._report(rep, recs, report_capacity), st
+
+    @staticmethod
+    def _report(rep, recs, cap):
+        records = [recs[i].as_dict() for i in range(min(rep.n_records, cap))]
+        return {"records": records, "n_leaf_ed": rep.n_leaf_ed, "n_merges": rep.n_merges,
+                "total_ms": rep.total_ms}
+
+    def recurse_batch(self, jobs, opts: Optional[SolveOpts] = None):
+        """jobs: chain tuples (n_sites, leaf_sites, terms, k, q) or tree tuples
+        ("tree", nodes, k, q). Returns energies (n, qmax) and per-job status codes."""
+        n = len(jobs)
+        descs = (JobDesc * max(1, n))()
         keep = []
-        for j, (ns, ls, terms, k, q) in enumerate(chains):
-            arr, nt = make_terms(terms)
-            keep.append(arr)
-            descs[j] = ChainDesc(ns, ls, nt, arr, int(k), int(q))
+        qmax = 1
+        for j, job in enumerate(jobs):
+            jd, q, kp = make_job(job)
+            descs[j] = jd
+            keep.append(kp)
+            qmax = max(qmax, q)
         e = np.full((max(1, n), qmax), np.nan)
         sts = (C.c_int * max(1, n))()
         st = lib().rmc_recurse_batch(self.h, n, descs, C.byref(opts) if opts else None,
@@ -366,19 +436,19 @@ class Context:
         self._check(lib().rmc_serve_start(self.h, C.byref(opts) if opts else None,
                                           int(max_inflight), int(mem_budget)))
 
-    def submit(self, n_sites: int, leaf_sites: int, terms, k: int, q: int) -> int:
-        arr, nt = make_terms(terms)
-        ch = ChainDesc(n_sites, leaf_sites, nt, arr, int(k), int(q))
+    def submit(self, *job) -> int:
+        """Queue a chain (n_sites, leaf_sites, terms, k, q) or a tree ("tree", nodes, k, q)."""
+        jd, q, keep = make_job(job)
         jid = C.c_ulonglong()
-        self._check(lib().rmc_submit(self.h, C.byref(ch), C.byref(jid)))
+        self._check(lib().rmc_submit(self.h, C.byref(jd), C.byref(jid)))
         return jid.value
 
     def poll(self, job_id: int, q: int):
-        """(done, energies, status, latency_ms); energies valid once done."""
+        """(done, energies, status, latency_ms); energies (q of them) valid once done."""
         done, st, lat = C.c_int(), C.c_int(), C.c_double()
         e = np.full(q, np.nan)
         self._check(lib().rmc_poll(self.h, C.c_ulonglong(job_id), C.byref(done),
-                                   e.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st),
+                                   e.ctypes.data_as(C.POINTER(C.c_double)), int(q), C.byref(st),
                                    C.byref(lat)))
         return bool(done.value), e, st.value, lat.value
 

@@ -76,3 +76,50 @@ def block_terms(job, a, b) -> List[Term]:
         if all(a <= s < b for s, _ in ops):
             out.append((c, tuple((s - a, o) for s, o in ops)))
     return out
+
+
+def tree_from_spec(job, spec, k_of=None):
+    """Module-tree nodes (the binding's rmc_recurse format) of the sites of `job` split
+    and merged as `spec`: a leaf is a site range (a, b); a merge is a pair (left spec,
+    right spec) of adjacent ranges, left first. A leaf carries the terms inside its
+    range (sites from 0); a merge carries the two-site terms with one site in each
+    child, as (coef, site in left, op, site in right, op), each child's sites from 0.
+    k_of(width) gives a node's k (default 0: the tree's k)."""
+    terms = chain_terms(job)
+    nodes = []
+
+    def go(s):
+        if isinstance(s[0], int):
+            a, b = s
+            nodes.append(("leaf", b - a, block_terms(job, a, b), k_of(b - a) if k_of else 0))
+            return len(nodes) - 1, a, b
+        li, a, m = go(s[0])
+        ri, m2, b = go(s[1])
+        if m2 != m:
+            raise ValueError("children of a merge must be adjacent, left first")
+        cut = []
+        for c, ops in terms:
+            if len(ops) != 2:
+                continue
+            (s0, o0), (s1, o1) = ops
+            if a <= s0 < m <= s1 < b:
+                cut.append((c, s0 - a, o0, s1 - m, o1))
+            elif a <= s1 < m <= s0 < b:
+                cut.append((c, s1 - a, o1, s0 - m, o0))
+        nodes.append(("merge", li, ri, cut, k_of(b - a) if k_of else 0))
+        return len(nodes) - 1, a, b
+
+    go(spec)
+    return nodes
+
+
+def chain_spec(n_sites, leaf_sites):
+    """Spec of the default order on a chain: leaves of leaf_sites consecutive sites
+    merged pairwise left to right, an odd module carried up."""
+    mods = [(a, a + leaf_sites) for a in range(0, n_sites, leaf_sites)]
+    while len(mods) > 1:
+        nxt = [(mods[i], mods[i + 1]) for i in range(0, len(mods) - 1, 2)]
+        if len(mods) % 2:
+            nxt.append(mods[-1])
+        mods = nxt
+    return mods[0]

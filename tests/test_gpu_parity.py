@@ -352,9 +352,18 @@ def test_recurse_matches_oracle(ctx, name, job):
     ref = OR.recurse(job)
     assert rel_err(e, ref.energies) <= 1e-10, (e, ref.energies)
     if job.n_leaves > 1:  # a single leaf is solved directly, with no cut
-        kg = [r["k_eff"] for r in rep["records"] if r["kind"] != 2]
-        ko = [r.k_eff for r in ref.records]
-        assert sorted(set(kg)) == sorted(set(ko))
+        assert_records_match(rep, ref)
+
+
+def assert_records_match(rep, ref):
+    """The integer bookkeeping of a recursion, bit-exact: one (level, width, kind, k_req,
+    k_eff) record per computed module (reused modules and the root aside), as a multiset
+    (modules of one level may finish in any order)."""
+    kinds = {"leaf": 0, "merge": 1}
+    gpu = sorted((r["level"], r["width"], r["kind"], r["k_req"], r["k_eff"])
+                 for r in rep["records"] if r["kind"] != 2 and not r["reused"])
+    ora = sorted((r.level, r.width, kinds[r.kind], r.k_req, r.k_eff) for r in ref.records)
+    assert gpu == ora, (gpu, ora)
 
 
 # App. B coupling geometries: two 5-site TFIM modules (J=1, h=0.7) coupled by
@@ -605,12 +614,13 @@ def test_recurse_batch_mixed_precision(ctx, prec):
 # -- serving (continuous batching) ------------------------------------------------
 
 def _serving_jobs():
-    out = []
-    for i, (t, j) in enumerate(W.serving_stream(40)):
-        if j.n_sites <= 64 and j.k <= 64:
-            out.append(j)
-        if len(out) == 8:
-            break
+    """The first jobs of the seeded serving stream, up to 10, with at least one k = 128
+    and one N = 128 job among them (every size the stream draws)."""
+    stream = [j for _, j in W.serving_stream(80)]
+    out = stream[:8]
+    for want in (lambda j: j.k == 128, lambda j: j.n_sites == 128):
+        if not any(want(j) for j in out):
+            out.append(next(j for j in stream if want(j) and j not in out))
     return out
 
 
@@ -627,7 +637,7 @@ def test_serving_results_alone_equal_mix(ctx):
         ids = [ctx.submit(*rmc.job_chain(j)) for j in jobs]
         got = {}
         t0 = time.time()
-        while len(got) < len(ids) and time.time() - t0 < 120:
+        while len(got) < len(ids) and time.time() - t0 < 240:
             for jid, j in zip(ids, jobs):
                 if jid in got:
                     continue
@@ -893,3 +903,154 @@ def test_merge_bound_twenty_sites(ctx):
         assert abs(d["E0"] - e0) <= 1e-10 * abs(e0)
         assert d["gamma"] > 0
         assert 0.0 <= d["a"] - d["E0"] <= d["r"] <= d["b2_over_gamma"]
+
+
+# -- Algorithm 1 over caller-defined module trees ------------------------------------
+
+def _tree_pair(job, spec, k_of=None):
+    """The product's nodes (spin_models) and the oracle's nodes (oracle.recursion) of the
+    same tree, each built from its own term tables."""
+    return SM.tree_from_spec(job, spec, k_of), OR.tree_from_spec(job, spec, k_of)
+
+
+TREE_CASES = [
+    # unequal leaves, merges in several orders
+    ("tfim20_5_3_7_5", W.ChainJob("tfim", 20, 1, 16, 4, J=1.0, h=0.7),
+     (((0, 5), (5, 8)), ((8, 15), (15, 20)))),
+    ("tfim20_left_comb", W.ChainJob("tfim", 20, 1, 12, 4, J=1.0, h=0.9),
+     ((((0, 4), (4, 10)), (10, 13)), (13, 20))),
+    ("xxz18_right_comb", W.ChainJob("xxz", 18, 1, 24, 6, J=1.0, delta=0.8),
+     ((0, 6), ((6, 9), ((9, 12), (12, 18))))),
+    ("rfheis24_uneven", W.ChainJob("rfheis", 24, 1, 32, 8, J=1.0, fields=W.rfheis_batch(3)[2].fields[:24]),
+     (((0, 8), (8, 12)), ((12, 14), (14, 24)))),
+    ("nnn16_interior", W.ChainJob("tfim_nnn", 16, 1, 16, 4, J=1.0, h=0.7, j2=0.25),
+     (((0, 3), (3, 9)), (9, 16))),
+    ("ladder_2x8_cols_1_3_4", W.ChainJob("tfim_ladder", 16, 2, 32, 6, J=1.0, h=0.9, j_rung=0.5),
+     ((0, 2), ((2, 8), (8, 16)))),
+]
+
+
+@pytest.mark.parametrize("name,job,spec", TREE_CASES, ids=[c[0] for c in TREE_CASES])
+def test_recurse_tree_matches_oracle(ctx, name, job, spec):
+    """Unbalanced trees with unequal leaves through rmc_recurse against the oracle's tree
+    recursion: energies to 1e-10 and every module's (level, width, kind, k_req, k_eff)."""
+    say("recurse tree", name)
+    nodes, onodes = _tree_pair(job, spec)
+    e, rep, st = ctx.recurse_tree(nodes, job.k, job.q)
+    ref = OR.recurse_tree(onodes, job.k, job.q)
+    assert rel_err(e, ref.energies) <= 1e-10, (e, ref.energies)
+    assert_records_match(rep, ref)
+
+
+def test_recurse_tree_per_node_k(ctx):
+    """A node-level k: the 8-site leaves keep 48 states, their merges 24, the tree's k
+    (16) elsewhere; against the oracle with the same per-node k."""
+    say("recurse tree per-node k")
+    job = W.ChainJob("xxz", 32, 1, 16, 6, J=1.0, delta=0.9)
+    spec = (((0, 8), (8, 16)), ((16, 24), (24, 32)))
+    k_of = lambda w: {8: 48, 16: 24}.get(w, 0)
+    nodes, onodes = _tree_pair(job, spec, k_of)
+    e, rep, _ = ctx.recurse_tree(nodes, job.k, job.q)
+    ref = OR.recurse_tree(onodes, job.k, job.q)
+    assert rel_err(e, ref.energies) <= 1e-10, (e, ref.energies)
+    assert_records_match(rep, ref)
+
+
+def test_recurse_tree_ladder_widths_given_explicitly(ctx):
+    """The 2x48 ladder's tree written out (widths 4 -> 8 -> 16 -> (32, 16) -> 48 columns)
+    at k = 32 equals the chain form's default tree, bit for bit, and the oracle."""
+    say("recurse tree ladder 2x48 explicit")
+    from paper_2609_02394_amd import rmc
+
+    job = W.ChainJob("tfim_ladder", 96, 8, 32, 8, J=1.0, h=0.9, j_rung=0.5)
+    c = [(a, a + 8) for a in range(0, 96, 8)]
+    p8 = [(c[i], c[i + 1]) for i in range(0, 12, 2)]
+    p16 = [(p8[i], p8[i + 1]) for i in range(0, 6, 2)]
+    spec = ((p16[0], p16[1]), p16[2])
+    nodes, onodes = _tree_pair(job, spec)
+    e, rep, _ = ctx.recurse_tree(nodes, job.k, job.q)
+    ec, _ = ctx.recurse(*rmc.job_chain(job))
+    assert np.array_equal(e, ec)
+    ref = OR.recurse_tree(onodes, job.k, job.q)
+    assert rel_err(e, ref.energies) <= 1e-10, (e, ref.energies)
+    assert_records_match(rep, ref)
+
+
+def test_recurse_tree_declared_shared_subtrees(ctx):
+    """A homogeneous chain as a DAG (one leaf node and one node per level, each the child
+    of the next twice) equals the full tree: the same modules, computed once."""
+    say("recurse tree DAG")
+    job = W.ChainJob("xxz", 32, 8, 32, 6, J=1.0, delta=1.0)
+    full = SM.tree_from_spec(job, (((0, 8), (8, 16)), ((16, 24), (24, 32))))
+    dag = [full[0], ("merge", 0, 0, full[2][3], 0), ("merge", 1, 1, full[-1][3], 0)]
+    e1, r1, _ = ctx.recurse_tree(full, job.k, job.q)
+    e2, r2, _ = ctx.recurse_tree(dag, job.k, job.q)
+    assert np.array_equal(e1, e2)
+    assert r2["n_leaf_ed"] == 1 and r2["n_merges"] == 2
+    assert rel_err(e1, OR.recurse(job).energies) <= 1e-10
+
+
+def test_recurse_tree_rejects_malformed_trees(ctx):
+    from paper_2609_02394_amd import rmc
+
+    say("recurse tree errors")
+    job = W.ChainJob("tfim", 8, 4, 8, 4, J=1.0, h=0.7)
+    good = SM.tree_from_spec(job, ((0, 4), (4, 8)))
+    bad = {
+        "child after parent": [good[0], ("merge", 0, 2, good[2][3], 0), good[1]],
+        "node outside the tree": [good[0], good[1], good[0], ("merge", 0, 1, good[2][3], 0)],
+        "coupling site outside its child": [good[0], good[1], ("merge", 0, 1, [(-1.0, 4, "Z", 0, "Z")], 0)],
+        "leaf of 13 sites": [("leaf", 13, [], 0)],
+    }
+    for why, nodes in bad.items():
+        with pytest.raises(rmc.RmcError) as ei:
+            ctx.recurse_tree(nodes, 8, 4)
+        assert ei.value.status == rmc.ERR_ARG, why
+    e, _, _ = ctx.recurse_tree(good, 8, 4)
+    assert rel_err(e, OR.recurse(job).energies) <= 1e-10
+
+
+def test_recurse_noconv_returns_the_roots_best_ritz_values(ctx):
+    """A root solve cut off after one iteration: RMC_ERR_NOCONV, with the root's best
+    Ritz values in the energies, each at or above the exact eigenvalue of the merge
+    (Rayleigh-Ritz values bound the eigenvalues from above)."""
+    from paper_2609_02394_amd import rmc
+
+    say("recurse noconv energies")
+    job = W.ChainJob("xxz", 12, 6, 64, 4, J=1.0, delta=0.7)
+    nodes, onodes = _tree_pair(job, ((0, 6), (6, 12)))
+    o = rmc.default_opts(max_iter=1, max_degree=2)
+    e, rep, st = ctx.recurse_tree(nodes, job.k, job.q, opts=o, allow=(rmc.ERR_NOCONV,))
+    ref = OR.recurse_tree(onodes, job.k, job.q).energies
+    if st == rmc.ERR_NOCONV:
+        assert np.all(np.isfinite(e)) and np.all(e >= ref - 1e-9), (e, ref)
+    else:
+        assert rel_err(e, ref) <= 1e-10
+
+
+def test_serving_trees_and_chains_alone_equal_mix(ctx):
+    """Tree jobs and chain jobs queued together: each result equals its own run alone."""
+    import time
+
+    from paper_2609_02394_amd import rmc
+
+    say("serving trees")
+    jobs = [("tree", SM.tree_from_spec(c[1], c[2]), c[1].k, c[1].q) for c in TREE_CASES[:3]]
+    jobs += [rmc.job_chain(W.ChainJob("tfim", 32, 8, 32, 6, J=1.0, h=0.8))]
+    alone = [ctx.recurse_tree(j[1], j[2], j[3])[0] if j[0] == "tree" else ctx.recurse(*j)[0] for j in jobs]
+    ctx.serve_start(max_inflight=8)
+    try:
+        ids = [ctx.submit(*j) for j in jobs]
+        got = {}
+        t0 = time.time()
+        while len(got) < len(ids) and time.time() - t0 < 120:
+            for jid, j in zip(ids, jobs):
+                if jid not in got:
+                    done, e, st, lat = ctx.poll(jid, j[-1])
+                    if done:
+                        got[jid] = (e, st)
+            time.sleep(0.002)
+    finally:
+        ctx.serve_stop()
+    for jid, a in zip(ids, alone):
+        assert got[jid][1] == rmc.OK and rel_err(got[jid][0], a) <= 1e-10
