@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <set>
 #include <string>
@@ -19,74 +20,6 @@
 #include "rmc_batch.h"
 #include "rmc_internal.h"
 
-namespace rmc {
-
-// ---------------------------------------------------------------------------
-// Arena
-// ---------------------------------------------------------------------------
-static constexpr size_t kAlign = 256;
-
-void Arena::init(char* base, size_t size) {
-  base_ = base;
-  size_ = size & ~(kAlign - 1);
-  free_.clear();
-  used_.clear();
-  if (size_) free_[0] = size_;
-  in_use_ = peak_ = 0;
-}
-
-void* Arena::alloc(size_t bytes) {
-  std::lock_guard<std::mutex> lk(mu_);
-  size_t need = (bytes + kAlign - 1) & ~(kAlign - 1);
-  if (need == 0) need = kAlign;
-  for (auto it = free_.begin(); it != free_.end(); ++it) {
-    if (it->second >= need) {
-      size_t off = it->first, sz = it->second;
-      free_.erase(it);
-      if (sz > need) free_[off + need] = sz - need;
-      used_[off] = need;
-      in_use_ += need;
-      peak_ = std::max(peak_, in_use_);
-      return base_ + off;
-    }
-  }
-  throw Error(RMC_ERR_OOM, "device arena exhausted (" + std::to_string(bytes) + " bytes requested, " +
-                               std::to_string(size_ - in_use_) + " free)");
-}
-
-void Arena::release(void* p) {
-  if (!p) return;
-  std::lock_guard<std::mutex> lk(mu_);
-  size_t off = (size_t)((char*)p - base_);
-  auto it = used_.find(off);
-  if (it == used_.end()) return;
-  size_t sz = it->second;
-  used_.erase(it);
-  in_use_ -= sz;
-  auto nx = free_.lower_bound(off);
-  if (nx != free_.end() && nx->first == off + sz) {
-    sz += nx->second;
-    free_.erase(nx);
-  }
-  auto pv = free_.lower_bound(off);
-  if (pv != free_.begin()) {
-    --pv;
-    if (pv->first + pv->second == off) {
-      pv->second += sz;
-      return;
-    }
-  }
-  free_[off] = sz;
-}
-
-size_t Arena::largest_free() const {
-  std::lock_guard<std::mutex> lk(mu_);
-  size_t m = 0;
-  for (auto& kv : free_) m = std::max(m, kv.second);
-  return m;
-}
-
-}  // namespace rmc
 
 using namespace rmc;
 
@@ -821,6 +754,7 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
   const int P = (int)reqs.size();
   hipStream_t s = ctx->stream;
   Scratch sc(&ctx->arena);
+  std::unique_ptr<HostScope> phase(new HostScope("couple.setup"));
   std::vector<CoupledOp> ops(P);
   std::vector<const CoupledOp*> opp(P);
   std::vector<int> nevs(P), kreq(P);
@@ -921,7 +855,9 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
     op_setup_batched(s, sd_dev, P, work_max);
   }
   std::vector<SolveStats> st;
+  phase.reset(new HostScope("couple.solve"));
   eig_lowest_batch(ctx, opp, nevs, o, Xs, evals, st);
+  phase.reset(new HostScope("couple.modules"));
   const double dt = now_ms() - t0;
   if (reps) {
     reps->assign(P, rmc_level_report{});
@@ -1035,6 +971,7 @@ int api_project_op(rmc_ctx* ctx, rmc_module* m, int site, int op) {
 }
 void api_project_ops_batch(rmc_ctx* ctx, const std::vector<rmc_module*>& ms,
                            const std::vector<std::pair<int, int>>& so) {
+  RMC_HOST_SCOPE("project.batch");
   std::vector<ProjReq> r;
   for (size_t i = 0; i < ms.size(); ++i) r.push_back(ProjReq{ms[i], so[i].first, so[i].second});
   project_ops_batch(ctx, r);
@@ -1051,6 +988,7 @@ std::vector<rmc_module*> api_leaf_solve_batch(rmc_ctx* ctx,
                                               const rmc_solve_opts& o,
                                               std::vector<std::vector<double>>& evals,
                                               std::vector<rmc_level_report>* reps) {
+  RMC_HOST_SCOPE("leaf.solve_batch");
   return leaf_solve_batch(ctx, leaves, ks, q_only, o, evals, reps);
 }
 std::vector<rmc_module*> api_couple_batch(rmc_ctx* ctx, const std::vector<rmc_module*>& As,
@@ -1072,6 +1010,7 @@ void api_release_basis(rmc_ctx* ctx, rmc_module* m) {
   m->basis = nullptr;
 }
 void api_free_module(rmc_ctx* ctx, rmc_module* m) {
+  RMC_HOST_SCOPE("module.free");
   auto it = std::find(ctx->modules.begin(), ctx->modules.end(), m);
   if (it != ctx->modules.end()) ctx->modules.erase(it);
   free_module_mem(ctx, m);

@@ -1,24 +1,22 @@
-// Internal host-side structures of librmc: device arena, modules, the coupled
-// operator and the eigensolver interface.
+// Internal host-side structures of librmc: modules, the coupled operator and the
+// eigensolver interface (the arena and error type are in host_util.h).
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include <map>
 #include <mutex>
+#include <set>
 #include <stdexcept>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/rmc.h"
+#include "host_util.h"
 #include "rmc_batch.h"
 #include "rmc_kernels.h"
 
 namespace rmc {
-
-struct Error : std::runtime_error {
-  rmc_status code;
-  Error(rmc_status c, const std::string& m) : std::runtime_error(m), code(c) {}
-};
 
 #define RMC_HIP(x)                                                                      \
   do {                                                                                  \
@@ -26,30 +24,6 @@ struct Error : std::runtime_error {
     if (e_ != hipSuccess)                                                               \
       throw ::rmc::Error(RMC_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
-
-#define RMC_CHECK(cond, code, msg) \
-  do {                             \
-    if (!(cond)) throw ::rmc::Error((code), (msg)); \
-  } while (0)
-
-// First-fit sub-allocator over one device buffer (256-byte granules).
-class Arena {
- public:
-  void init(char* base, size_t size);
-  void* alloc(size_t bytes);
-  void release(void* p);
-  size_t in_use() const { return in_use_; }
-  size_t peak() const { return peak_; }
-  size_t size() const { return size_; }
-  size_t largest_free() const;
-
- private:
-  char* base_ = nullptr;
-  size_t size_ = 0, in_use_ = 0, peak_ = 0;
-  mutable std::mutex mu_;          // the solver's lanes allocate from their own threads
-  std::map<size_t, size_t> free_;  // offset -> bytes
-  std::map<size_t, size_t> used_;  // offset -> bytes
-};
 
 // RAII list of arena allocations released together.
 struct Scratch {
