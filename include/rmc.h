@@ -314,6 +314,21 @@ rmc_status rmc_leaf_hamiltonian(rmc_ctx* ctx, const rmc_leaf_desc* leaf, double*
 rmc_status rmc_kron_apply(rmc_ctx* ctx, rmc_module* A, rmc_module* B,
                           const rmc_bond_desc* bond, int precision, int n_vec,
                           const double* X_dev, double* Y_dev);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): rmc_kron_apply with every piece of
+ * its scratch (the coupling coefficients, the concatenated operators, the diagonal
+ * E_A + E_B, the operator pack of the precision, the launch descriptor) carved from a
+ * fixed device array of 4 MiB per GPU that the library holds until the process ends.
+ * It calls no hipMalloc, hipFree or arena allocation, never times tile candidates
+ * (an untuned shape takes the default variant) and does not synchronise: Y_dev is
+ * ready when the ctx stream reaches this point. Enough for T <= 8 terms at
+ * k_A = k_B <= 128; a coupling that needs more scratch fails with RMC_ERR_ARG. The
+ * array is shared by every call on that GPU and keeps the last call's contents: calls
+ * that overlap on one GPU (other streams or other contexts) race; calls in order on
+ * one stream do not. Arguments, layout and results as rmc_kron_apply. */
+rmc_status rmc_kron_apply_noalloc(rmc_ctx* ctx, rmc_module* A, rmc_module* B,
+                                  const rmc_bond_desc* bond, int precision, int n_vec,
+                                  const double* X_dev, double* Y_dev);
 /* Symmetric eigendecomposition of `batch` m x m matrices (device, row-major,
  * stride m*m) by parallel cyclic Jacobi: eigenvalues ascending into evals_dev
  * (batch x m), eigenvectors as columns into V_dev (batch x m x m). m <= 192. */

@@ -1018,6 +1018,35 @@ void api_free_module(rmc_ctx* ctx, rmc_module* m) {
 }
 }  // namespace rmc
 
+// ---------------------------------------------------------------------------
+// Scratch of the entry point that allocates nothing (rmc_kron_apply_noalloc): one
+// fixed array per GPU, held until the process ends. Host code never uses its name as
+// an address: rmc_create looks up each device's copy once (hipGetSymbolAddress, with
+// that device current) and every launch and copy uses that address.
+// ---------------------------------------------------------------------------
+static constexpr size_t kNoAllocScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex scratch_mu;
+std::map<int, char*> scratch_dev;  // device -> its copy of `scratch`
+
+void scratch_setup(int device) {  // `device` must be current
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_dev.count(device)) return;
+  void* p = nullptr;
+  RMC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  RMC_CHECK(p != nullptr && ((uintptr_t)p & 255) == 0, RMC_ERR_HIP, "scratch array address");
+  scratch_dev[device] = static_cast<char*>(p);
+}
+
+char* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  auto it = scratch_dev.find(device);
+  return it == scratch_dev.end() ? nullptr : it->second;
+}
+}  // namespace
+
 static void set_kernel_attrs() {
   static bool done = false;
   if (done) return;
@@ -1061,6 +1090,7 @@ rmc_status rmc_create(rmc_ctx** out, int device, void* arena_dev, size_t arena_b
     RMC_CHECK(((uintptr_t)ctx->arena_mem & 255) == 0, RMC_ERR_ARG, "arena must be 256-byte aligned");
     ctx->arena.init((char*)ctx->arena_mem, arena_bytes);
     set_kernel_attrs();
+    scratch_setup(device);
   });
   if (st != RMC_OK) {
     fprintf(stderr, "rmc_create: %s\n", ctx->last_error.c_str());
@@ -1338,6 +1368,68 @@ rmc_status rmc_kron_apply(rmc_ctx* ctx, rmc_module* A, rmc_module* B, const rmc_
     build_packs(s, sc, op);
     op_apply(ctx, op, n_vec, X_dev, Y_dev, nullptr, 1.0, 0.0, 0.0, nullptr, nullptr, precision);
     sync(ctx);
+  });
+}
+
+rmc_status rmc_kron_apply_noalloc(rmc_ctx* ctx, rmc_module* A, rmc_module* B,
+                                  const rmc_bond_desc* bond, int precision, int n_vec,
+                                  const double* X_dev, double* Y_dev) {
+  if (!ctx) return RMC_ERR_ARG;
+  return guard(ctx, [&] {
+    RMC_CHECK(A && B && bond && X_dev && Y_dev && n_vec >= 0, RMC_ERR_ARG, "bad arguments");
+    RMC_CHECK(precision >= RMC_FP64 && precision <= RMC_BF16, RMC_ERR_ARG, "bad precision");
+    RMC_CHECK(A->E && B->E, RMC_ERR_STATE, "module freed");
+    const int T = bond->n_terms, kA = A->k_eff, kB = B->k_eff, n = kA * kB;
+    RMC_CHECK(T >= 0 && (T == 0 || (bond->coef && bond->opA && bond->opB)), RMC_ERR_ARG, "bad bond");
+    RMC_CHECK(kA <= kron_max_k() && kB <= kron_max_k(), RMC_ERR_ARG, "module dimension above 192");
+    for (int i = 0; i < T; ++i) {
+      RMC_CHECK(bond->opA[i] >= 0 && bond->opA[i] < (int)A->ops.size(), RMC_ERR_ARG, "bad opA id");
+      RMC_CHECK(bond->opB[i] >= 0 && bond->opB[i] < (int)B->ops.size(), RMC_ERR_ARG, "bad opB id");
+    }
+    char* base = scratch_of(ctx->device);
+    RMC_CHECK(base != nullptr, RMC_ERR_STATE, "no scratch array on this device");
+    // the pieces of rmc_kron_apply's scratch, 256-byte aligned, in one fixed array
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_coef = al(sizeof(double) * std::max(T, 1));
+    const size_t b_oa = al(sizeof(double) * std::max(T, 1) * kA * kA);
+    const size_t b_ob = al(sizeof(double) * std::max(T, 1) * kB * kB);
+    const size_t b_ed = al(sizeof(double) * std::max(n, 1));
+    const size_t b_pk = al(kron_pack_bytes(precision, kA, kB, T));
+    const size_t b_desc = al(sizeof(KronDesc));
+    const size_t need = b_coef + b_oa + b_ob + b_ed + b_pk + b_desc;
+    RMC_CHECK(need <= kNoAllocScratchBytes, RMC_ERR_ARG,
+              "this coupling needs " + std::to_string(need) + " bytes of scratch, above the " +
+                  std::to_string(kNoAllocScratchBytes) + "-byte array of rmc_kron_apply_noalloc");
+    hipStream_t s = ctx->stream;
+    char* q = base;
+    double* coef_dev = reinterpret_cast<double*>(q); q += b_coef;
+    double* OAcat = reinterpret_cast<double*>(q); q += b_oa;
+    double* OBcat = reinterpret_cast<double*>(q); q += b_ob;
+    double* Ediag = reinterpret_cast<double*>(q); q += b_ed;
+    void* pack = b_pk ? static_cast<void*>(q) : nullptr; q += b_pk;
+    KronDesc* desc = reinterpret_cast<KronDesc*>(q);
+    if (T > 0)
+      RMC_HIP(hipMemcpyAsync(coef_dev, bond->coef, T * sizeof(double), hipMemcpyHostToDevice, s));
+    for (int i = 0; i < T; ++i) {
+      RMC_HIP(hipMemcpyAsync(OAcat + (size_t)i * kA * kA, A->ops[bond->opA[i]].data,
+                             (size_t)kA * kA * sizeof(double), hipMemcpyDeviceToDevice, s));
+      RMC_HIP(hipMemcpyAsync(OBcat + (size_t)i * kB * kB, B->ops[bond->opB[i]].data,
+                             (size_t)kB * kB * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    kron_diag(s, kA, kB, A->E, B->E, T, coef_dev, OAcat, OBcat, nullptr, Ediag);
+    if (pack)
+      kron_pack(s, T, kA, kB, coef_dev, OAcat, OBcat, precision == RMC_FP64 ? pack : nullptr,
+                precision == RMC_FP32 ? pack : nullptr, precision == RMC_BF16 ? pack : nullptr);
+    KronDesc d{};
+    d.kA = kA; d.kB = kB; d.T = T; d.nv = n_vec; d.vbase = 0;
+    d.pack = pack; d.pkm = kron_pack_km(kA, kB);
+    d.coef = coef_dev; d.OA = OAcat; d.OB = OBcat; d.Ediag = Ediag;
+    d.Y = X_dev; d.Xprev = nullptr; d.E = nullptr; d.phi = nullptr; d.out = Y_dev;
+    d.s1 = 1.0; d.s2 = 0.0; d.s3 = 0.0;
+    RMC_HIP(hipMemcpyAsync(desc, &d, sizeof(d), hipMemcpyHostToDevice, s));
+    // never times tile candidates (no events, no synchronisation)
+    kron_batched(s, desc, 1, kB, n_vec, kA, precision, T, n_vec, /*may_tune=*/false);
+    RMC_HIP(hipGetLastError());
   });
 }
 

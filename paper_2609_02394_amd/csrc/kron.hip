@@ -1331,7 +1331,7 @@ static bool tuning_enabled = true;
 void kron_set_tuning(bool on) { tuning_enabled = on; }
 
 void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
-                  int precision, int T, long total_vecs) {
+                  int precision, int T, long total_vecs, bool may_tune) {
   if (P <= 0 || nvmax <= 0 || kBmax <= 0 || total_vecs <= 0) return;
   const int RT = (kAmax + 15) / 16;
   const int mrt = RT <= 4 ? 1 : (RT <= 8 ? 2 : 3);
@@ -1381,7 +1381,7 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
     auto it = tune_cache.find(key);
     if (it != tune_cache.end() && valid(it->second)) ct = it->second;
   }
-  if (ct < 0 && !tuning_enabled) ct = valid(8) ? 8 : (valid(2) ? 2 : 1);
+  if (ct < 0 && (!tuning_enabled || !may_tune)) ct = valid(8) ? 8 : (valid(2) ? 2 : 1);
   if (ct < 0) {
     hipEvent_t e0, e1;
     hipEventCreate(&e0);

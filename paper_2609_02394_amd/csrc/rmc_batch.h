@@ -129,9 +129,11 @@ struct StartDesc {
 };
 
 // T: largest term count of the launch; total_vecs: vectors over all problems (both
-// only key the tile-shape autotuner).
+// only key the tile-shape autotuner). may_tune = false never times candidates (no
+// events, no synchronisation): an untuned shape takes the default variant.
 void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
-                  int precision, int T, long total_vecs);
+                  int precision, int T, long total_vecs,
+                  bool may_tune = true);
 void kron_set_tuning(bool on);
 int kron_max_k();
 // Operators of one coupling in the streaming kernel's layout: for term t, the

@@ -29,7 +29,7 @@ EXPORTED = (
     "rmc_leaf_hamiltonian", "rmc_kron_apply", "rmc_sym_eig", "rmc_module_import",
     "rmc_profile", "rmc_profile_read", "rmc_profile_read_precision",
     "rmc_serve_start", "rmc_submit", "rmc_poll", "rmc_serve_stop", "rmc_merge_bound",
-    "rmc_profile_read_kernel",
+    "rmc_profile_read_kernel", "rmc_kron_apply_noalloc",
 )
 PROF_KRON_STEP, PROF_KRON_FILTER, PROF_PAULI = 0, 1, 2
 
@@ -111,6 +111,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "rmc_module_free": (i, [vp, vp]),
         "rmc_leaf_hamiltonian": (i, [vp, P(LeafDesc), vp]),
         "rmc_kron_apply": (i, [vp, vp, vp, P(BondDesc), i, i, vp, vp]),
+        "rmc_kron_apply_noalloc": (i, [vp, vp, vp, P(BondDesc), i, i, vp, vp]),
         "rmc_sym_eig": (i, [vp, i, i, vp, vp, vp]),
         "rmc_module_import": (i, [vp, i, i, i, P(d), P(d), i, P(i), P(i), P(d), P(vp)]),
         "rmc_profile": (i, [vp, i]),
@@ -475,6 +476,17 @@ class Context:
         self._check(lib().rmc_kron_apply(self.h, A.h, B.h, C.byref(bd), int(precision),
                                          int(X.shape[0]), C.c_void_p(X.data_ptr()),
                                          C.c_void_p(Y.data_ptr())))
+        return Y
+
+    def kron_apply_noalloc(self, A: Module, B: Module, coefs, opA, opB, X, Y,
+                           precision: int = FP64):
+        """rmc_kron_apply_noalloc into the caller's Y (device tensor shaped like X):
+        enqueued on the context's stream, nothing allocated, no synchronisation."""
+        bd, keep = _bond(coefs, opA, opB)
+        assert X.is_contiguous() and Y.is_contiguous() and X.shape == Y.shape
+        self._check(lib().rmc_kron_apply_noalloc(self.h, A.h, B.h, C.byref(bd), int(precision),
+                                                 int(X.shape[0]), C.c_void_p(X.data_ptr()),
+                                                 C.c_void_p(Y.data_ptr())))
         return Y
 
     def sym_eig(self, A):
