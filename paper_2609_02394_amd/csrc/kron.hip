@@ -974,6 +974,252 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
   }
 }
 
+// A wave-uniform value passed through an empty asm statement: the compiler can neither
+// hoist what is computed from it out of a loop nor fold it (the value is unchanged).
+__device__ inline unsigned opaque_uniform(unsigned x) {
+  unsigned v = __builtin_amdgcn_readfirstlane(x);
+  asm volatile("" : "+s"(v));
+  return v;
+}
+template <class T>
+__device__ inline T* opaque_uniform_ptr(T* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = opaque_uniform((unsigned)v), hi = opaque_uniform((unsigned)(v >> 32));
+  return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+}
+
+// Wide tiles (KM = 96): the whole filter as above, operators streamed through
+// LDS, but with the register budget of 12 or 16 waves that own several column tiles
+// each: one staging buffer for the next term's tiles (O_B fetched at the start of a
+// term and stored after stage 1, then c O_A fetched and stored after stage 2), the
+// defect and the diagonal re-read from L2 in the epilogue, element indices recomputed,
+// and the K loops unrolled by two so that few operand fragments are in flight. LDS holds
+// the low-precision iterate, Z^T and the current term's two tiles. Same arithmetic, in
+// the same order, as the per-step kernel's epilogue.
+template <int P, int KM, int CPW>
+__global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_wide_kernel(
+    const FilterDesc* __restrict__ descs, int P_, long V, int G) {
+  typedef typename SK<P>::lt lt;
+  typedef typename SK<P>::acc accT;
+  typedef typename Grp<P>::t gv;
+  constexpr int RTM = KM / 16;
+  constexpr int NWR = RTM / CPW;  // waves per row tile
+  constexpr int NT = 64 * RTM * NWR;
+  constexpr int PW = sk_pitch<P>(KM);
+  constexpr int NCH = KM / SK<P>::CH;
+  constexpr int TILE = KM * PW;
+  constexpr int NG = KM * KM / (4 * NT);  // staging groups per thread per tile
+  static_assert(RTM % CPW == 0 && NG * 4 * NT == KM * KM, "tile split");
+  extern __shared__ char smem_raw[];
+  lt* Ys = reinterpret_cast<lt*>(smem_raw);
+  lt* Zt = Ys + TILE;
+  lt* Bs = Zt + TILE;
+  lt* As = Bs + TILE;
+  gv pf[NG];
+  // tile `which` (0: O_B, 1: c O_A) of term tt of problem e into pf (zeros past pkm)
+  auto fetch = [&](const FilterDesc* e, int tt, int which) {
+    const int pkm = e->pkm;
+    gptr<lt> base = gview(static_cast<const lt*>(e->pack)) + ((long)tt * 2 + which) * pkm * pkm;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const int q = (int)threadIdx.x + i * NT, r = q / (KM / 4), cc = (q % (KM / 4)) * 4;
+      gv x = gv{0, 0, 0, 0};
+      if (r < pkm && cc < pkm) x = *reinterpret_cast<gptr<gv>>(base + r * pkm + cc);
+      pf[i] = x;
+    }
+  };
+  auto put = [&](lt* dst) {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const int q = (int)threadIdx.x + i * NT, r = q / (KM / 4), cc = (q % (KM / 4)) * 4;
+      *reinterpret_cast<gv*>(dst + r * PW + cc) = pf[i];
+    }
+  };
+
+  const int w = blockIdx.x;
+  const int L = (w & 7) * (G >> 3) + (w >> 3);
+  const long v0 = (long)L * V / G, v1 = (long)(L + 1) * V / G;
+  if (v0 >= v1) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int rt = wave / NWR, c0 = (wave % NWR) * CPW;
+  const int arow = rt * 16 + l16;  // this lane's operand row
+
+  int p = 0;
+  {
+    int lo = 0, hi = P_ - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (descs[mid].vbase <= v0) lo = mid;
+      else hi = mid - 1;
+    }
+    p = lo;
+  }
+  int j = (int)(v0 - descs[p].vbase);
+  int staged = -1;  // problem whose term-0 tiles sit in LDS
+  for (long v = v0; v < v1; ++v) {
+    while (j >= descs[p].nv) {
+      j = 0;
+      ++p;
+    }
+    const FilterDesc* d = descs + p;
+    const int kA = d->kA, kB = d->kB, T = d->T, steps = d->steps, nv = d->nv;
+    // a filter has degree >= 2, so at least one step (the host never builds fewer); said
+    // here so that the compiler keeps no copy of the starting iterate for an empty loop
+    __builtin_assume(steps >= 1);
+    const long n = (long)kA * kB;
+    gptr<double> Ej = gview(d->E) + (long)j * n;
+    double Dc[CPW][4], Dp[CPW][4];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int col = (c0 + c) * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + acc_row<P>(g, r);
+        const bool in = row < kA && col < kB;
+        const double e0 = in ? Ej[row * kB + col] : 0.0;
+        Dc[c][r] = d->r0 * e0;
+        Dp[c][r] = 0.0;
+        Ys[row * PW + col] = to_lt<P>(Dc[c][r]);
+      }
+    }
+    if (T > 0 && staged != p) {  // every wave is past the previous vector's last reads
+      fetch(d, 0, 0);
+      put(Bs);
+      fetch(d, 0, 1);
+      put(As);
+      staged = p;
+    }
+    __syncthreads();
+    for (int k = 1; k <= steps; ++k) {
+      const double s1 = d->sc[3 * (k - 1)], s2 = d->sc[3 * (k - 1) + 1], s3 = d->sc[3 * (k - 1) + 2];
+      const double ph = s1 * d->phi[(long)(k - 1) * nv + j];
+      accT acc[CPW];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) acc[c] = accT{0, 0, 0, 0};
+      for (int t = 0; t < T; ++t) {
+        // the tiles the next term uses: this problem's next term, its term 0 for the
+        // next step, or the next vector's problem; nothing to stage when they are the
+        // ones already in LDS (a single-term problem)
+        const FilterDesc* nd = nullptr;
+        int ntt = 0;
+        if (t + 1 < T) {
+          nd = d;
+          ntt = t + 1;
+        } else if (k < steps) {
+          nd = T > 1 ? d : nullptr;
+        } else if (v + 1 < v1) {
+          int pn = p, jn = j + 1;
+          while (jn >= descs[pn].nv) {
+            jn = 0;
+            ++pn;
+          }
+          if (descs[pn].T > 0 && !(pn == p && T == 1)) nd = descs + pn;
+          staged = descs[pn].T > 0 ? pn : -1;
+        }
+        if (nd) fetch(nd, ntt, 0);
+        // stage 1: Z = D O_B^T, stored transposed
+        accT z[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) z[c] = accT{0, 0, 0, 0};
+#pragma unroll 1
+        for (int u = 0; u < NCH; ++u) {
+          Frag<P> a;
+          a.load(Ys + arow * PW, u, g);
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            Frag<P> b;
+            b.load(Bs + ((c0 + c) * 16 + l16) * PW, u, g);
+            mma_frag<P>(z[c], a.v, b);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          lt* zr = Zt + ((c0 + c) * 16 + l16) * PW + rt * 16;
+          if constexpr (P == 1) {
+            *reinterpret_cast<float4*>(zr + 4 * g) = float4{z[c][0], z[c][1], z[c][2], z[c][3]};
+          } else {
+            lt h[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h[r] = (__bf16)z[c][r];
+            *reinterpret_cast<uint2*>(zr + 4 * g) = *reinterpret_cast<const uint2*>(h);
+          }
+        }
+        __syncthreads();
+        if (nd) {  // every wave is past stage 1's reads of O_B
+          put(Bs);
+          fetch(nd, ntt, 1);
+        }
+        // stage 2: acc += c O_A Z
+#pragma unroll 1
+        for (int u = 0; u < NCH; ++u) {
+          Frag<P> a;
+          a.load(As + arow * PW, u, g);
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            Frag<P> b;
+            b.load(Zt + ((c0 + c) * 16 + l16) * PW, u, g);
+            mma_frag<P>(acc[c], a.v, b);
+          }
+        }
+        __syncthreads();  // every wave is past stage 2's reads of c O_A and Z^T
+        if (nd) put(As);  // visible to the next stage 2 after the next barrier
+      }
+      // the per-step kernel's epilogue on the register-resident iterates; the defect and
+      // the diagonal come from L2 through 32-bit offsets from uniform bases, which are
+      // laundered every step so that the compiler does not keep a 64-bit address per
+      // element live across the step loop
+      const char* eb = opaque_uniform_ptr(reinterpret_cast<const char*>(d->E) + (size_t)j * n * sizeof(double));
+      const char* db = opaque_uniform_ptr(reinterpret_cast<const char*>(d->Ediag));
+      const int kBs = (int)opaque_uniform((unsigned)kB);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int col = (c0 + c) * 16 + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rt * 16 + acc_row<P>(g, r);
+          const bool in = row < kA && col < kB;
+          const unsigned off = (unsigned)(row * kBs + col) * 8u;
+          const double ed = in ? *reinterpret_cast<gptr<double>>(gview(db) + off) : 0.0;
+          const double ev = in ? *reinterpret_cast<gptr<double>>(gview(eb) + off) : 0.0;
+          double o = fma(s1, fma(ed, Dc[c][r], (double)acc[c][r]), s2 * Dc[c][r]);
+          if (k > 1) o = fma(s3, Dp[c][r], o);  // the first step has no previous iterate
+          o = fma(ph, ev, o);
+          Dp[c][r] = Dc[c][r];
+          Dc[c][r] = in ? o : 0.0;
+        }
+      }
+      if (k < steps) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            Ys[(rt * 16 + acc_row<P>(g, r)) * PW + (c0 + c) * 16 + l16] = to_lt<P>(Dc[c][r]);
+        __syncthreads();
+      }
+    }
+    // out_j = phi_P X_j + D_P (as the scale-add kernel rounds), from laundered bases
+    const double phP = d->phi[(long)steps * nv + j];
+    const char* xb = opaque_uniform_ptr(reinterpret_cast<const char*>(d->X) + (size_t)j * n * sizeof(double));
+    char* ob = opaque_uniform_ptr(reinterpret_cast<char*>(d->out) + (size_t)j * n * sizeof(double));
+    const int kBs = (int)opaque_uniform((unsigned)kB);
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int col = (c0 + c) * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + acc_row<P>(g, r);
+        if (row < kA && col < kB) {
+          const unsigned off = (unsigned)(row * kBs + col) * 8u;
+          const double x = *reinterpret_cast<gptr<double>>(gview(xb) + off);
+          *reinterpret_cast<gptr_w<double>>(gview_w(ob) + off) = __dadd_rn(__dmul_rn(phP, x), Dc[c][r]);
+        }
+      }
+    }
+    ++j;
+  }
+}
+
 typedef void (*FilterKernel)(const FilterDesc*, int, long, int);
 
 // Column tiles per wave of the fused filter (RMC_FILTER_CPW = 1, 2 or 4): more tiles per
@@ -994,7 +1240,11 @@ static int filter_cpw() {
 static int filter_streamed_cpw(int prec, int km) {
   if (prec == RMC_FP64) return km <= 32 ? 1 : (km <= 64 ? 2 : 0);
   if (km <= 32) return 0;  // resident at this size in every precision
-  return km <= 64 ? 1 : 0;
+  if (km <= 64) return 1;
+  // 96: 6 x 6 tiles, 12 waves of three column tiles. 128 stays on the per-step path:
+  // four FP32 tiles of 128 do not fit in LDS, and in BF16 the FP64 iterates of 64 tiles
+  // spill registers with 16 waves of four tiles or 8 waves of eight
+  return km <= 96 ? 3 : 0;
 }
 
 template <int P, int KM>
@@ -1013,6 +1263,7 @@ static FilterKernel filter_kernel(int prec, int km, int cpw, bool res = true) {
       case 0: return nullptr;
       case 1: return prec == RMC_FP64 ? kron_filter_kernel<0, 32, 1, false>
                                       : (prec == RMC_FP32 ? kron_filter_kernel<1, 64, 1, false> : kron_filter_kernel<2, 64, 1, false>);
+      case 3: return prec == RMC_FP32 ? kron_filter_wide_kernel<1, 96, 3> : kron_filter_wide_kernel<2, 96, 3>;
       default: return kron_filter_kernel<0, 64, 2, false>;
     }
   }

@@ -828,13 +828,18 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr);
 // recurrences as the per-step path) and travel in the descriptor tables.
 void fused_filter(Batch& B, const std::vector<BP*>& L, int P, int outr) {
   rmc_ctx* ctx = B.ctx;
-  for (int prec = 0; prec < 3; ++prec) {
+  // one launch per precision and tile class: problems up to 64 share the 64-wide kernel
+  // (smaller operators padded inside its tiles), 96-wide problems take the wide kernel
+  auto wide = [](const CoupledOp& op) { return std::max(op.kA, op.kB) > 64; };
+  for (int pc = 0; pc < 6; ++pc) {
+    const int prec = pc / 2;
+    const bool cls_wide = pc % 2 == 1;
     std::vector<FilterDesc> fd;
     int kmax = 0, Tm = 0;
     long tv = 0;
     double flops = 0.0, bytes = 0.0;
     for (BP* p : L) {
-      if (p->prec != prec) continue;
+      if (p->prec != prec || wide(*p->op) != cls_wide) continue;
       const CoupledOp& op = *p->op;
       const int cn = p->cnt, steps = P - 1;
       std::vector<double> sc(3 * (size_t)std::max(steps, 1)), phi((size_t)(steps + 1) * cn);

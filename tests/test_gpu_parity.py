@@ -484,6 +484,10 @@ FUSED_CASES = [
     ("xxz_N16_k24", W.ChainJob("xxz", 16, 4, 24, 6, J=1.0, delta=0.7), [0, 1, 2]),
     ("rfheis_N32_k48", W.ChainJob("rfheis", 32, 8, 48, 8, J=1.0, fields=W.rfheis_batch(2)[1].fields),
      [1, 2]),
+    # 96-wide tiles: the wide form of the fused filter (12 waves of three column tiles)
+    ("rfheis_N32_k96", W.ChainJob("rfheis", 32, 8, 96, 8, J=1.0, fields=W.rfheis_batch(3)[2].fields),
+     [1, 2]),
+    ("xxz_N32_k80", W.ChainJob("xxz", 32, 8, 80, 6, J=1.0, delta=0.8), [1]),
 ]
 
 
