@@ -459,7 +459,10 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
   // the widest tiles are at the register limit already); the next vector's rows are
   // prefetched up to KM = 96 and loaded at the vector boundary beyond
   constexpr bool EPF = KM <= 64 && !(P == 0 && NWC == 1);
-  constexpr bool YPF = KM <= 96;
+  // FP64 at KM = 96: the vector's rows (stage 1's A operand) are read from L2 chunk by
+  // chunk instead of being held in registers (24 doubles a lane would spill)
+  constexpr bool YG = P == 0 && KM > 64;
+  constexpr bool YPF = KM <= 96 && !YG;
   static_assert(RTM % NWC == 0 && NG * 4 * NT == KM * KM, "tile split");
   extern __shared__ char smem_raw[];
   lt* Bs = reinterpret_cast<lt*>(smem_raw);
@@ -518,7 +521,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
       }
     }
   };
-  lt yf[NYE], yn[YPF ? NYE : 1];
+  lt yf[YG ? 1 : NYE], yn[YPF ? NYE : 1];
   auto load_y = [&](const KronDesc* e, int jj, lt* dst) {
     const int kA = e->kA, kB = e->kB;
     gptr<double> Y = gview(e->Y) + (long)jj * kA * kB;
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
     load_tile(descs + p, 0, true);
     store_tile(As);
   }
-  load_y(descs + p, j, yf);
+  if constexpr (!YG) load_y(descs + p, j, yf);
   __syncthreads();
   accT acc[CPW];
   while (true) {
@@ -576,14 +579,35 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
       accT z[CPW];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) z[c] = accT{0, 0, 0, 0};
+      if constexpr (YG) {
+        const int kA = d->kA, kB = d->kB;
+        const int a = rt * 16 + l16;
+        gptr<double> Yr = gview(d->Y) + (long)j * kA * kB + (long)(a < kA ? a : 0) * kB;
+#pragma unroll 2
+        for (int u = 0; u < NCH; ++u) {
+          lt ya[KR];
 #pragma unroll
-      for (int u = 0; u < NCH; ++u)
+          for (int x = 0; x < KR; ++x) {
+            const int k = CH * u + KR * g + x;
+            ya[x] = (a < kA && k < kB) ? Yr[k] : 0.0;
+          }
 #pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-          Frag<P> b;
-          b.load(Bs + ((c0 + c) * 16 + l16) * PW, u, g);
-          mma_frag<P>(z[c], yf + u * KR, b);
+          for (int c = 0; c < CPW; ++c) {
+            Frag<P> b;
+            b.load(Bs + ((c0 + c) * 16 + l16) * PW, u, g);
+            mma_frag<P>(z[c], ya, b);
+          }
         }
+      } else {
+#pragma unroll
+        for (int u = 0; u < NCH; ++u)
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            Frag<P> b;
+            b.load(Bs + ((c0 + c) * 16 + l16) * PW, u, g);
+            mma_frag<P>(z[c], yf + u * KR, b);
+          }
+      }
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         lt* zr = Zt + ((c0 + c) * 16 + l16) * PW + rt * 16;
@@ -688,7 +712,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
       if constexpr (YPF) {
 #pragma unroll
         for (int e = 0; e < NYE; ++e) yf[e] = yn[e];
-      } else {
+      } else if constexpr (!YG) {
         load_y(nd, nj, yf);  // every wave is past its last read of yf (barrier above)
       }
       ++v;
@@ -1336,6 +1360,8 @@ static StreamKernel stream_kernel(int prec, int km, int nwc, bool sh = false) {
   // the widest tiles fit in LDS only with one buffer for both operators (SH)
   if (prec == RMC_FP64) {
     RMC_SK(0, 32) RMC_SK(0, 64)
+    // 96: one LDS buffer for both operators (two 96-wide FP64 tiles), two waves a row tile
+    if (km <= 96) return (sh && nwc == 2) ? kron_stream_kernel<0, 96, 2, true> : nullptr;
   } else if (prec == RMC_FP32) {
     RMC_SK(1, 32) RMC_SK(1, 64) RMC_SK(1, 96)
     if (km <= 128) return (sh && nwc == 1) ? kron_stream_kernel<1, 128, 1, true> : nullptr;
@@ -1347,10 +1373,14 @@ static StreamKernel stream_kernel(int prec, int km, int nwc, bool sh = false) {
   return nullptr;
 }
 
-// Some streaming kernel (either LDS form) takes tiles of this size and precision: the
-// operators are then packed for it.
+// Some streaming kernel (either LDS form, one or two waves a row tile) takes tiles of
+// this size and precision: the operators are then packed for it. Every streaming
+// launch reads the packs, so a variant is a candidate only where this holds.
 static bool has_stream(int prec, int km) {
-  return stream_kernel(prec, km, 1, false) != nullptr || stream_kernel(prec, km, 1, true) != nullptr;
+  for (int nwc : {1, 2})
+    for (bool sh : {false, true})
+      if (stream_kernel(prec, km, nwc, sh) != nullptr) return true;
+  return false;
 }
 
 static int stream_km(int km) { return km <= 32 ? 32 : (km <= 64 ? 64 : (km <= 96 ? 96 : 128)); }
@@ -1581,9 +1611,9 @@ void tune_store(const std::string& key, int v) {
 static bool tuning_enabled = true;
 void kron_set_tuning(bool on) { tuning_enabled = on; }
 
-void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
-                  int precision, int T, long total_vecs, bool may_tune) {
-  if (P <= 0 || nvmax <= 0 || kBmax <= 0 || total_vecs <= 0) return;
+int kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
+                 int precision, int T, long total_vecs, bool may_tune, bool strict) {
+  if (P <= 0 || nvmax <= 0 || kBmax <= 0 || total_vecs <= 0) return 0;
   const int RT = (kAmax + 15) / 16;
   const int mrt = RT <= 4 ? 1 : (RT <= 8 ? 2 : 3);
   const size_t lds = kron_lds_bytes(kAmax, precision);
@@ -1592,7 +1622,8 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
   // kernel with one or two waves per row tile; 10, 11 = the same with one LDS buffer
   // for both operators of a step (two more barriers, one tile less of LDS)
   auto valid = [&](int c) {
-    if (c >= 8 && c <= 11) return stream_kernel(precision, KM, (c - 8) % 2 + 1, c >= 10) != nullptr;
+    if (c >= 8 && c <= 11)
+      return has_stream(precision, KM) && stream_kernel(precision, KM, (c - 8) % 2 + 1, c >= 10) != nullptr;
     if (c == 1) return true;
     if (c != 2 && c != 4) return false;
     if (16 * c > ((kBmax + 15) / 16) * 16 * 2) return false;  // at most two half-empty tiles
@@ -1612,13 +1643,18 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
     dim3 grid((kBmax + 16 * c - 1) / (16 * c), nvmax, P);
     hipLaunchKernelGGL(kron_kernel(precision, c, mrt), grid, dim3(256), lds, s, d);
   };
-  // RMC_KRON_VARIANT forces a candidate (where valid for the shape), e.g. to test it
+  // RMC_KRON_VARIANT forces a candidate, e.g. to test it: where it does not take the
+  // shape, a strict launch fails and any other takes the autotuner's choice
   if (const char* f = getenv("RMC_KRON_VARIANT")) {
     const int c = atoi(f);
     if (valid(c)) {
       launch(c);
-      return;
+      return c;
     }
+    RMC_CHECK(!strict, RMC_ERR_ARG,
+              "Kronecker variant " + std::to_string(c) + " does not take this shape (precision " +
+                  std::to_string(precision) + ", k_A " + std::to_string(kAmax) + ", k_B " +
+                  std::to_string(kBmax) + ")");
   }
   int lg = 0;
   while ((1L << (lg + 1)) <= total_vecs) ++lg;
@@ -1665,6 +1701,7 @@ void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax,
     tune_store(key, ct);
   }
   launch(ct);
+  return ct;
 }
 
 }  // namespace rmc

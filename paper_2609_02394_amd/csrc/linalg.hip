@@ -198,13 +198,16 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(int tA, int tB, int k
       }
 }
 
-// The same product for 64 < M <= 80 (a Rayleigh-Ritz block with its guard vectors):
-// one 80 x 64 output tile per workgroup, so M is not padded to two 64-row tiles. Wave
-// w owns columns 16w..16w+15 as five 16 x 16 MFMA tiles down the rows.
-constexpr int G80_M = 80;
-__global__ __launch_bounds__(256) void gemm_grouped80_kernel(int tA, int tB, int ksplit,
-                                                             const GemmDesc* __restrict__ descs) {
-  __shared__ double As[2][GB_K][G80_M + 1];
+// The same product for 64 < M <= 16 MT (a Rayleigh-Ritz block with its guard vectors,
+// MT = 5: 80 rows; MT = 8: 128 rows): one 16 MT x 64 output tile per workgroup, so M is
+// not padded to two 64-row tiles and the wide operand B is read once, not once per
+// row tile. Wave w owns columns 16w..16w+15 as MT 16 x 16 MFMA tiles down the rows.
+template <int MT>
+__global__ __launch_bounds__(256) void gemm_grouped_tall_kernel(int tA, int tB, int ksplit,
+                                                                const GemmDesc* __restrict__ descs) {
+  constexpr int GM = 16 * MT;
+  constexpr int NA = GM * GB_K / 256;  // A elements each thread stages per K slice
+  __shared__ double As[2][GB_K][GM + 1];
   __shared__ double Bs[2][GB_K][GB_N + 1];
   const GemmDesc d = descs[blockIdx.z / ksplit];
   const int ks = blockIdx.z % ksplit;
@@ -218,16 +221,16 @@ __global__ __launch_bounds__(256) void gemm_grouped80_kernel(int tA, int tB, int
   const int kend = min(K, kbeg + kchunk);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  d4 acc[5];
+  d4 acc[MT];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
-  double ra[5], rb[4];
+  for (int i = 0; i < MT; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  double ra[NA], rb[4];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 5; ++e) {
-      const int idx = tid + e * 256;  // < 80 * 16
+    for (int e = 0; e < NA; ++e) {
+      const int idx = tid + e * 256;  // < GM * 16
       int i, k;
-      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / G80_M; i = idx % G80_M; }
+      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / GM; i = idx % GM; }
       const int gk = k0 + k;
       ra[e] = (i < M && gk < kend) ? (tA ? d.A[(long)gk * d.lda + i] : d.A[(long)i * d.lda + gk]) : 0.0;
     }
@@ -242,10 +245,10 @@ __global__ __launch_bounds__(256) void gemm_grouped80_kernel(int tA, int tB, int
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 5; ++e) {
+    for (int e = 0; e < NA; ++e) {
       const int idx = tid + e * 256;
       int i, k;
-      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / G80_M; i = idx % G80_M; }
+      if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / GM; i = idx % GM; }
       As[buf][k][i] = ra[e];
     }
 #pragma unroll
@@ -269,7 +272,7 @@ __global__ __launch_bounds__(256) void gemm_grouped80_kernel(int tA, int tB, int
         const int kr = kk + (lane >> 4);
         const double b = Bs[buf][kr][wave * 16 + (lane & 15)];
 #pragma unroll
-        for (int t = 0; t < 5; ++t)
+        for (int t = 0; t < MT; ++t)
           acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[buf][kr][t * 16 + (lane & 15)], b, acc[t], 0, 0, 0);
       }
       if (more) store(buf ^ 1);
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(256) void gemm_grouped80_kernel(int tA, int tB, int
   double* P = parts ? d.work + (long)ks * M * N : nullptr;
   const int gj = col0 + wave * 16 + (lane & 15);
 #pragma unroll
-  for (int t = 0; t < 5; ++t)
+  for (int t = 0; t < MT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gi = t * 16 + 4 * r + (lane >> 4);
@@ -301,9 +304,12 @@ void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int
                   int ksplit) {
   if (P <= 0 || Mmax <= 0 || Nmax <= 0) return;
   if (ksplit < 1) ksplit = 1;
-  if (Mmax > GB_M && Mmax <= G80_M) {
+  if (Mmax > GB_M && Mmax <= 128) {
     dim3 grid((Nmax + GB_N - 1) / GB_N, 1, P * ksplit);
-    hipLaunchKernelGGL(gemm_grouped80_kernel, grid, dim3(256), 0, s, (int)tA, (int)tB, ksplit, d);
+    if (Mmax <= 80)
+      hipLaunchKernelGGL(gemm_grouped_tall_kernel<5>, grid, dim3(256), 0, s, (int)tA, (int)tB, ksplit, d);
+    else
+      hipLaunchKernelGGL(gemm_grouped_tall_kernel<8>, grid, dim3(256), 0, s, (int)tA, (int)tB, ksplit, d);
     return;
   }
   dim3 grid((Nmax + GB_N - 1) / GB_N, (Mmax + GB_M - 1) / GB_M, P * ksplit);
@@ -405,6 +411,8 @@ void gram_batched(hipStream_t s, const GramDesc* d, int P, int ks, int cmax) {
   const int t = (cmax + 15) / 16;
   if (t <= 5)
     hipLaunchKernelGGL((gram_kernel<4, 80>), dim3(ks, P), dim3(512), 0, s, d, ks);
+  else if (t <= 8)  // up to 128 rows: 70 KB of LDS, two workgroups a CU
+    hipLaunchKernelGGL((gram_kernel<8, 128>), dim3(ks, P), dim3(512), 0, s, d, ks);
   else
     hipLaunchKernelGGL((gram_kernel<18, 192>), dim3(ks, P), dim3(512), 0, s, d, ks);
 }

@@ -130,10 +130,12 @@ struct StartDesc {
 
 // T: largest term count of the launch; total_vecs: vectors over all problems (both
 // only key the tile-shape autotuner). may_tune = false never times candidates (no
-// events, no synchronisation): an untuned shape takes the default variant.
-void kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
-                  int precision, int T, long total_vecs,
-                  bool may_tune = true);
+// events, no synchronisation): an untuned shape takes the default variant. A variant
+// forced with RMC_KRON_VARIANT runs where it takes the shape; elsewhere the launch takes
+// the autotuner's choice, or, with strict = true, fails with RMC_ERR_ARG. Returns the
+// variant launched (1, 2, 4: tiled kernel column sub-tiles; 8 to 11: streaming kernel).
+int kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
+                 int precision, int T, long total_vecs, bool may_tune = true, bool strict = false);
 void kron_set_tuning(bool on);
 int kron_max_k();
 // Operators of one coupling in the streaming kernel's layout: for term t, the

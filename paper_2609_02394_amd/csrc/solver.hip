@@ -1386,7 +1386,8 @@ void op_apply(rmc_ctx* ctx, const CoupledOp& op, int nv, const double* Y, double
   d.s1 = s1; d.s2 = s2; d.s3 = s3;
   KronDesc* dd = sc.get<KronDesc>(1);
   RMC_HIP(hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream));
-  kron_batched(ctx->stream, dd, 1, op.kB, nv, op.kA, precision, op.T, nv);
+  // a variant forced for this one apply must take the shape (no silent substitute)
+  kron_batched(ctx->stream, dd, 1, op.kB, nv, op.kA, precision, op.T, nv, true, /*strict=*/true);
   sync(ctx);
 }
 

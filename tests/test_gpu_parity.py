@@ -236,18 +236,46 @@ def kron_env():
             os.environ[k] = v
 
 
+def _variant_takes(variant, prec, kA, kB):
+    """Whether a Kronecker variant takes the shape (the library's documented table):
+    the tiled kernel with 1 column sub-tile always; 2 or 4 sub-tiles while at most two of
+    them are half empty (and not 4 with more than 8 row tiles); the streaming kernel
+    (8, 9: one or two waves a row tile; 10, 11: the same with one LDS buffer for both
+    operators) where its padded tile KM (32, 64, 96, 128) fits LDS in the precision:
+    FP64 to 64, and 96 as variant 11 only; FP32 to 96, and 128 as variant 10 only; BF16
+    to 96, and 128 with one wave a row tile (8, 10)."""
+    if variant == 1:
+        return True
+    if variant in (2, 4):
+        rt = (kA + 15) // 16
+        mrt = 1 if rt <= 4 else (2 if rt <= 8 else 3)
+        return 16 * variant <= ((kB + 15) // 16) * 16 * 2 and not (variant == 4 and mrt == 3)
+    k = max(kA, kB)
+    km = 32 if k <= 32 else (64 if k <= 64 else (96 if k <= 96 else 128))
+    if prec == 0:
+        return km <= 64 or (km == 96 and variant == 11)
+    if prec == 1:
+        return km <= 96 or (km == 128 and variant == 10)
+    return km <= 96 or variant in (8, 10)
+
+
 # every kernel variant of the Kronecker matvec (1, 2, 4: column sub-tiles of the
 # tiled kernel; 8, 9: streaming kernel; 10, 11: streaming with one LDS buffer for both
 # operators), at the largest k each streaming form takes, ragged shapes, no terms, and
-# a capped grid so that workgroups walk many vectors
+# a capped grid so that workgroups walk many vectors. A forced variant either runs (the
+# result is checked) or, where it does not take the shape, the call fails with
+# RMC_ERR_ARG: nothing else runs in its place.
 @pytest.mark.parametrize("variant", [1, 2, 4, 8, 9, 10, 11])
 @pytest.mark.parametrize("prec,kA,kB,T,nv", [(0, 64, 64, 3, 7), (0, 33, 17, 2, 9), (0, 20, 20, 0, 3),
+                                            (0, 96, 96, 3, 5), (0, 90, 70, 2, 6),
                                             (1, 96, 96, 3, 5), (1, 50, 70, 2, 6),
                                             (1, 128, 128, 2, 5), (1, 100, 120, 3, 4),
                                             (2, 128, 128, 2, 4), (2, 90, 40, 3, 11)])
 @pytest.mark.parametrize("max_grid", [None, 8])
 def test_kron_apply_variants(ctx, kron_env, variant, prec, kA, kB, T, nv, max_grid):
     import torch
+
+    from paper_2609_02394_amd import rmc
 
     say("kron_variant", variant, prec, kA, kB, T, nv, max_grid)
     kron_env(variant, max_grid)
@@ -260,6 +288,13 @@ def test_kron_apply_variants(ctx, kron_env, variant, prec, kA, kB, T, nv, max_gr
     idA = A.project_ops([s for s, _ in keys], [o for _, o in keys])
     idB = B.project_ops([s for s, _ in keysB], [o for _, o in keysB])
     X = rng.standard_normal((nv, kA * kB))
+    if not _variant_takes(variant, prec, kA, kB):
+        with pytest.raises(rmc.RmcError) as ei:
+            ctx.kron_apply(A, B, coefs, idA, idB, torch.tensor(X, device="cuda"), prec)
+        assert ei.value.status == rmc.ERR_ARG
+        A.free()
+        B.free()
+        return
     Y = ctx.kron_apply(A, B, coefs, idA, idB, torch.tensor(X, device="cuda"), prec).cpu().numpy()
     H = OR.effective_hamiltonian(EA, EB, [(c, mA[ka], mB[kb]) for c, ka, kb in zip(coefs, keys, keysB)])
     ref = X @ H.T
@@ -1058,3 +1093,64 @@ def test_serving_trees_and_chains_alone_equal_mix(ctx):
         ctx.serve_stop()
     for jid, a in zip(ids, alone):
         assert got[jid][1] == rmc.OK and rel_err(got[jid][0], a) <= 1e-10
+
+
+# -- the large workloads against the oracle's stored whole-recursion results ----------
+
+def _golden(name):
+    import importlib.util
+
+    p = os.path.join(os.path.dirname(__file__), "golden", "make_recursion_goldens.py")
+    spec = importlib.util.spec_from_file_location("make_recursion_goldens", p)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.read(os.path.join(os.path.dirname(__file__), "golden", name))
+
+
+def _golden_records_match(rep, recs):
+    kinds = {"leaf": 0, "merge": 1}
+    gpu = sorted((r["level"], r["width"], r["kind"], r["k_req"], r["k_eff"])
+                 for r in rep["records"] if r["kind"] != 2 and not r["reused"])
+    ora = sorted((lv, w, kinds[k], kr, ke) for lv, w, k, kr, ke, _ in recs)
+    assert gpu == ora, (gpu, ora)
+
+
+def test_rfheis_subset_matches_oracle_golden(ctx):
+    """32 seeded random-field chains (8 per k in {32, 48, 64, 96}) against the oracle's
+    stored energies and per-module records: FP64 one job at a time at 1e-10 with the
+    records bit-exact, then the batched FP32 and BF16 forms at 1e-8."""
+    from paper_2609_02394_amd import rmc
+
+    gold = _golden("recursion_rfheis_subset.txt")
+    assert len(gold) == 32
+    jobs_all = W.rfheis_batch(512)
+    idx = sorted(int(n.split(":")[1]) for n in gold)
+    chains = [rmc.job_chain(jobs_all[i]) for i in idx]
+    for i, ch in zip(idx, chains):
+        g = gold[f"rfheis:{i}"]
+        say("rfheis golden fp64", i, g["k"])
+        e, rep = ctx.recurse(*ch)
+        assert rel_err(e, g["E"]) <= 1e-10, (i, e, g["E"])
+        _golden_records_match(rep, g["R"])
+    for prec in (1, 2):
+        say("rfheis golden batch", prec)
+        E, st, top = ctx.recurse_batch(chains, opts=rmc.default_opts(precision=prec))
+        assert top == rmc.OK and all(x == rmc.OK for x in st)
+        for t, i in enumerate(idx):
+            assert rel_err(E[t, :8], gold[f"rfheis:{i}"]["E"]) <= 1e-8, (prec, i)
+
+
+def test_ladder_2x48_k128_matches_oracle_golden(ctx):
+    """The TFIM ladder 2x48 at k = 128 (four 16384-dimensional merges) against the
+    oracle's stored result: FP64 at 1e-10 with every module's record, FP32 at 1e-8."""
+    from paper_2609_02394_amd import rmc
+
+    g = _golden("recursion_ladder96_k128.txt")["ladder96"]
+    job = W.tfim_ladder96()
+    say("ladder golden fp64")
+    e, rep = ctx.recurse(*rmc.job_chain(job))
+    assert rel_err(e, g["E"]) <= 1e-10, (e, g["E"])
+    _golden_records_match(rep, g["R"])
+    say("ladder golden fp32")
+    e32, _ = ctx.recurse(*rmc.job_chain(job), opts=rmc.default_opts(precision=1))
+    assert rel_err(e32, g["E"]) <= 1e-8, (e32, g["E"])
