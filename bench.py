@@ -1,15 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark: coupled eigensolves/s of the recursive module-coupling eigensolver.
 
-A step is one whole recursion (leaf ED, projections, every coupling step with its
-Kronecker-sum eigensolve, edge-operator transforms) of the open XXZ chain N=64,
-J=1, Delta=1, 8-site leaves (dense 256-dim ED), k=64 (coupled space 4096), three
-bond operators per cut, lowest 8 states, on synthetic parameters. Only steps whose
-8 energies match the FP64 reference to |dE|/max(|E|,1) <= 1e-8 count as solves.
+Default line (the metric's workload): 512 random-field Heisenberg chains N=32, J=1,
+h_i ~ U[-2, 2] seeded per chain, 8-site leaves (dense 256-dim leaf ED), retained k
+drawn per chain from {32, 48, 64, 96}, three bond operators per cut, lowest 8 states.
+One step solves every chain once (leaf EDs, projections, every coupling step with its
+Kronecker-sum eigensolve, edge-operator transforms), all modules of a tree level across
+all chains in batched launches, with FP32 (or BF16) Kronecker matvecs and FP64
+correction. A chain counts as a solve only if its 8 energies match the FP64 reference
+to |dE|/max(|E|,1) <= 1e-8; the FP64 references are the GPU's FP64 path, itself
+checked against the oracle's stored energies (tests/golden) on a 32-chain subset.
 
-Prints one JSON line with the metric, p50/p99 step latency, the roofline of the
-dominant kernel (the Kronecker matvec, timed with HIP events on the library's
-stream inside the timed region) and the CPU oracle timed on the host cores.
+Beside it, in the same run: the plain per-job FP64 recursion of the same chains, the
+roofline of the dominant kernel (HIP events on the library's stream inside the timed
+region), the oracle timed on the host cores (all cores and one thread), and extra
+keys for the other workloads: the XXZ chain N=64 k=64 (32 jobs per step, and one job
+at a time), the TFIM ladder 2x48 k=128, and a bounded serving run.
 """
 from __future__ import annotations
 
@@ -17,6 +23,8 @@ import argparse
 import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -25,6 +33,17 @@ sys.path.insert(0, ROOT)
 # Kronecker kernel variants measured on MI355X for the benchmark shapes (the
 # autotuner's cache format); used through a private copy so that runs do not edit it.
 TUNE_FILE = os.path.join(ROOT, "paper_2609_02394_amd", "kron_tune_gfx950.txt")
+GOLDEN_RFHEIS = os.path.join(ROOT, "tests", "golden", "recursion_rfheis_subset.txt")
+GOLDEN_LADDER = os.path.join(ROOT, "tests", "golden", "recursion_ladder96_k128.txt")
+
+METRIC = "coupled eigensolves/s (lowest 8, rel err≤1e-8 vs FP64) + p50/p99 latency"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+HBM_GBS = 8000.0
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+KINDS = {0: "kron_step", 1: "kron_filter_kernel"}
+# the one-step launches run the streaming kernel or, where its tiles do not fit, the
+# tiled one; the profiler counts them as one kind
+KIND_NAMES = {0: "kron_stream_kernel|kron_batched_kernel", 1: "kron_filter_kernel"}
 
 
 def use_tune_file():
@@ -38,46 +57,371 @@ def use_tune_file():
     shutil.copyfile(TUNE_FILE, path)
     os.environ["RMC_TUNE_CACHE"] = path
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
-HBM_GBS = 8000.0
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kron_traffic.json")
-
 
 def kron_source_hash() -> str:
     p = os.path.join(ROOT, "paper_2609_02394_amd", "csrc", "kron.hip")
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def cpu_baseline(job):
-    """The oracle (dense LAPACK recursion) on the host cores, one whole job."""
-    import numpy as np
-    from oracle import recursion as OR
-
+def measured_traffic(workload: str, kernel: str, prec: str):
+    """HBM bytes per launch of a Kronecker kernel kind from committed rocprofv3 counter
+    runs of this workload (scaled by a copy kernel of known size), or None when the
+    counters were taken on another kernel source."""
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    t0 = time.perf_counter()
-    res = OR.recurse(job)
-    dt = time.perf_counter() - t0
-    return np.asarray(res.energies), dt, threads
-
-
-KERNELS = {0: "kron_stream_kernel", 1: "kron_filter_kernel"}
-
-
-def measured_traffic(kernel: str, prec: str):
-    """HBM bytes per launch of a Kronecker kernel from committed rocprofv3 counter runs
-    (scaled by a copy kernel of known size), if taken on the current kernel source."""
-    try:
-        d = json.load(open(TRAFFIC_FILE))
+        d = json.load(open(os.path.join(ROOT, "profiles", f"kron_traffic_{workload}.json")))
     except Exception:
         return None
     if d.get("kron_source_sha") != kron_source_hash():
         return None
     return d.get("bytes_per_launch", {}).get(f"{kernel}:{prec}")
+
+
+def rel_err(a, b):
+    import numpy as np
+
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    e = np.abs(a - b) / np.maximum(np.abs(b), 1.0)
+    return float(np.max(e)) if np.all(np.isfinite(e)) else float("inf")
+
+
+def read_golden(path):
+    """{name: (k, q, energies)} from a golden file written by the oracle."""
+    out, cur = {}, None
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "job":
+            kv = dict(x.split("=") for x in f[2:])
+            cur = f[1]
+            out[cur] = (int(kv["k"]), int(kv["q"]), [])
+        elif f[0] == "E":
+            out[cur][2].extend(float(x) for x in f[1:])
+    return out
+
+
+# ---- measurement helpers -------------------------------------------------------------
+
+def kron_profile(ctx, steps):
+    """Per (kind, precision) totals of the Kronecker launches since profile(True)."""
+    table = {}
+    for kk in KINDS:
+        for name in PREC:
+            pr = ctx.profile_read(PREC[name], kernel=kk)
+            if pr["launches"]:
+                table[(kk, name)] = pr
+    out = {}
+    for (kk, name), pr in table.items():
+        sec = pr["ms"] * 1e-3
+        out[f"{KINDS[kk]}:{name}"] = {
+            "kernel": KIND_NAMES[kk], "launches": pr["launches"],
+            "ms_per_step": pr["ms"] / steps, "avg_launch_us": pr["ms"] * 1e3 / pr["launches"],
+            "tflops": pr["flops"] / sec / 1e12 if sec > 0 else 0.0,
+            "gbs": pr["bytes"] / sec / 1e9 if sec > 0 else 0.0,
+            "flops_per_launch": pr["flops"] / pr["launches"],
+            "bytes_per_launch": pr["bytes"] / pr["launches"]}
+    return table, out
+
+
+def roofline(table, workload):
+    """Roofline of the dominant Kronecker kernel kind and precision (most event time)."""
+    if not table:
+        return None
+    (kk, name) = max(table, key=lambda k: table[k]["ms"])
+    pr = table[(kk, name)]
+    sec = pr["ms"] * 1e-3
+    if name == "bf16":  # HBM-bound: the BF16 MFMA roof lies far above the HBM roof
+        achieved = pr["bytes"] / sec / 1e9 if sec > 0 else 0.0
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_GBS}
+    else:
+        achieved = pr["flops"] / sec / 1e12 if sec > 0 else 0.0
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[name],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[name]}
+    roof.update({"traffic": measured_traffic(workload, KINDS[kk], name),
+                 "kernel": KIND_NAMES[kk], "precision": name, "launches": pr["launches"],
+                 "avg_launch_us": pr["ms"] * 1e3 / max(1, pr["launches"]),
+                 "flops_per_launch": pr["flops"] / max(1, pr["launches"]),
+                 "bytes_per_launch": pr["bytes"] / max(1, pr["launches"])})
+    return roof
+
+
+def timed_batches(ctx, jobs, refs, opts, steps, warmup, qs):
+    """Time `steps` solves of the whole batch after `warmup` untimed ones; a job counts
+    when its energies match refs to 1e-8. Returns the measurement and the kernel table."""
+    import numpy as np
+    import torch
+
+    for _ in range(warmup):
+        ctx.recurse_batch(jobs, opts=opts)
+    lat, ok, max_err = [], 0, 0.0
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        e, st, top = ctx.recurse_batch(jobs, opts=opts)
+        lat.append(time.perf_counter() - s0)
+        for i in range(len(jobs)):
+            err = rel_err(e[i, : qs[i]], refs[i]) if st[i] == 0 else float("inf")
+            max_err = max(max_err, err)
+            ok += err <= 1e-8
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    table, ktab = kron_profile(ctx, steps)
+    ctx.profile(False)
+    lat_ms = np.array(lat) * 1e3
+    return {"value": ok / total, "ms_per_step": total / steps * 1e3,
+            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+            "accurate_solves": ok, "jobs_per_step": len(jobs), "max_rel_err": max_err}, table, ktab
+
+
+def plain_per_job(ctx, jobs, refs, qs, reps=1):
+    """The plain per-job FP64 recursion: one job at a time, every job FP64."""
+    from paper_2609_02394_amd import rmc
+
+    fp64 = rmc.default_opts(precision=0)
+    ctx.recurse(*jobs[0], opts=fp64)
+    ok, t0 = 0, time.perf_counter()
+    for _ in range(reps):
+        for j, r, q in zip(jobs, refs, qs):
+            e, _ = ctx.recurse(*j, opts=fp64)
+            ok += rel_err(e[:q], r) <= 1e-8
+    dt = time.perf_counter() - t0
+    return {"form": "plain per-job FP64 recursion, one job at a time", "jobs": len(jobs) * reps,
+            "value": ok / dt, "unit": "solves/s", "seconds": dt}
+
+
+def host_info():
+    info = {"nproc": os.cpu_count(), "cpu_model": platform.processor() or None, "blas": None}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        r = subprocess.run(["nproc"], capture_output=True, text=True, timeout=10)
+        info["nproc"] = int(r.stdout.strip())
+    except Exception:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+
+        b = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        if b:
+            info["blas"] = f"{b[0].get('internal_api')} {b[0].get('version')} ({b[0].get('architecture')})"
+            info["blas_threads_default"] = b[0].get("num_threads")
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline_rfheis(jobs_all):
+    """The oracle (dense LAPACK recursion via NumPy, as it stands) on a bounded sample of
+    the 512 chains: the first chain of each k in {32, 48, 64} on all host cores, and the
+    k = 32 and k = 48 ones on one thread. A k = 96 chain alone takes minutes on the host
+    (three dense 9216 x 9216 eigensolves), so it is left out of the sample; the rate is
+    the sample's, not the workload mix's."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import recursion as OR
+
+    first = {}
+    for i, j in enumerate(jobs_all):
+        first.setdefault(j.k, i)
+    info = host_info()
+    out = {"kind": "oracle", "unit": "solves/s", **info}
+    runs = {}
+    for label, ks, threads in (("all_cores", (32, 48, 64), None), ("one_thread", (32, 48), 1)):
+        with threadpool_limits(limits=threads):
+            used = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+            per = {}
+            t0 = time.perf_counter()
+            for k in ks:
+                s0 = time.perf_counter()
+                OR.recurse(jobs_all[first[k]])
+                per[str(k)] = time.perf_counter() - s0
+            dt = time.perf_counter() - t0
+        runs[label] = {"value": len(ks) / dt, "cores": used, "seconds": dt,
+                       "chains": [first[k] for k in ks], "seconds_per_chain_by_k": per}
+    out.update({"value": runs["all_cores"]["value"], "cores": runs["all_cores"]["cores"],
+                "sample": "chains " + ", ".join(str(first[k]) for k in (32, 48, 64)) +
+                          " of the 512 (the first with k = 32, 48, 64; one whole recursion each; "
+                          "k = 96 left out: one such chain takes minutes on the host)",
+                "one_thread": runs["one_thread"], "all_cores": runs["all_cores"]})
+    return out
+
+
+# ---- workloads ---------------------------------------------------------------------------
+
+def bench_rfheis(args, ctx, extras_out):
+    """The default line: 512 random-field chains per step."""
+    from paper_2609_02394_amd import rmc, workloads as W
+
+    jobs_all = W.rfheis_batch(512)
+    jobs = [rmc.job_chain(j) for j in jobs_all]
+    qs = [j.q for j in jobs_all]
+    # FP64 references: the GPU's FP64 path for all chains, checked against the oracle's
+    # stored energies on the golden subset
+    e64, st64, _ = ctx.recurse_batch(jobs, opts=rmc.default_opts(precision=0))
+    assert all(s == 0 for s in st64), "FP64 reference batch failed"
+    refs = [e64[i, : qs[i]] for i in range(len(jobs))]
+    gold = read_golden(GOLDEN_RFHEIS)
+    gold_err = 0.0
+    for name, (k, q, E) in gold.items():
+        i = int(name.split(":")[1])
+        gold_err = max(gold_err, rel_err(refs[i], E))
+    assert not gold or gold_err <= 1e-10, f"FP64 path vs oracle golden {gold_err}"
+    opts = rmc.default_opts(precision=PREC[args.precision], max_degree=args.max_degree)
+    meas, table, ktab = timed_batches(ctx, jobs, refs, opts, args.steps, args.warmup, qs)
+    oracle_err = max((rel_err(refs[int(n.split(":")[1])], E) for n, (_, _, E) in gold.items()),
+                     default=None)
+    plain = None
+    if not args.no_plain:
+        idx = list(range(0, 512, 16))  # 32 chains, every k
+        plain = plain_per_job(ctx, [jobs[i] for i in idx], [refs[i] for i in idx],
+                              [qs[i] for i in idx])
+        plain["sample"] = "chains 0, 16, ..., 496 (32 of the 512)"
+    config = {"workload": "512 random-field Heisenberg chains N=32, J=1, h_i~U[-2,2] seeded per "
+                          "chain, 8-site leaves (dense 256 ED), k per chain from {32,48,64,96}, "
+                          "3 bond ops per cut, lowest 8; every chain solved once per step, all "
+                          "modules of a tree level across all chains in batched launches",
+              "precision": args.precision, "form": "batched levels",
+              "max_rel_err_vs_fp64": meas["max_rel_err"],
+              "fp64_path_vs_oracle_golden": {"chains": len(gold), "max_rel_err": oracle_err},
+              "jobs_per_step": meas["jobs_per_step"], "accurate_solves": meas["accurate_solves"]}
+    return meas, table, ktab, config, plain, (lambda: cpu_baseline_rfheis(jobs_all))
+
+
+def bench_chain_batch(args, ctx, job, batch, golden=None):
+    """`batch` copies of one chain job per step."""
+    from paper_2609_02394_amd import rmc
+
+    chain = rmc.job_chain(job)
+    ref, _ = ctx.recurse(*chain, opts=rmc.default_opts(precision=0))
+    gerr = rel_err(ref, golden) if golden is not None else None
+    assert gerr is None or gerr <= 1e-10, f"FP64 path vs oracle golden {gerr}"
+    opts = rmc.default_opts(precision=PREC[args.precision], max_degree=args.max_degree)
+    jobs = [chain] * batch
+    meas, table, ktab = timed_batches(ctx, jobs, [ref] * batch, opts, args.steps, args.warmup,
+                                      [job.q] * batch)
+    meas["fp64_path_vs_oracle_golden"] = gerr
+    return meas, table, ktab, ref
+
+
+def serve_run(ctx, precision, rate, n_jobs, warm, check_every=8):
+    """Open-loop Poisson stream through rmc_submit / rmc_poll: achieved rate, p50/p99
+    latency (submission to completion) of the measured jobs, and accuracy against the
+    FP64 per-job path on a sample."""
+    import threading
+
+    import numpy as np
+
+    from paper_2609_02394_amd import rmc, workloads as W
+
+    stream = W.serving_stream(warm + n_jobs, rate=rate)
+    sample = list(range(warm, warm + n_jobs, check_every))
+    refs = {i: ctx.recurse(*rmc.job_chain(stream[i][1]))[0] for i in sample}
+    ctx.serve_start(opts=rmc.default_opts(precision=precision), max_inflight=64)
+    ids = [None] * len(stream)
+    t0 = time.perf_counter()
+
+    def feeder():
+        for i, (t, job) in enumerate(stream):
+            d = t - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            ids[i] = ctx.submit(*rmc.job_chain(job))
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    res, t_done = {}, {}
+    try:
+        while len(res) < len(stream):
+            for i, (t, job) in enumerate(stream):
+                if i in res or ids[i] is None:
+                    continue
+                done, e, st, lat = ctx.poll(ids[i], job.q)
+                if done:
+                    res[i] = (e, st, lat)
+                    t_done[i] = time.perf_counter() - t0
+            time.sleep(0.0005)
+    finally:
+        th.join()
+        ctx.serve_stop()
+    meas = list(range(warm, len(stream)))
+    lat = np.array([res[i][2] for i in meas])
+    ok = sum(res[i][1] == 0 for i in meas)
+    errs = [rel_err(res[i][0], refs[i]) for i in sample]
+    span = max(t_done[i] for i in meas) - stream[warm][0]
+    offered = n_jobs / max(stream[-1][0] - stream[warm][0], 1e-9)
+    # the rate is sustained when the server keeps up (completions at >= 90% of the
+    # offered rate) and the queue does not grow (the last quarter of the jobs waits not
+    # much longer than the first)
+    q = max(1, len(lat) // 4)
+    first, last = float(np.median(lat[:q])), float(np.median(lat[-q:]))
+    return {"rate_offered_per_s": rate, "offered_measured_per_s": offered, "value": ok / span,
+            "unit": "solves/s", "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "jobs": n_jobs, "warmup_jobs": warm,
+            "completed_ok": int(ok), "median_latency_first_quarter_ms": first,
+            "median_latency_last_quarter_ms": last,
+            "sustained": bool(ok / span >= 0.9 * offered and last <= 2.0 * first + 50.0),
+            "max_rel_err_sample": max(errs), "sample_size": len(sample)}
+
+
+def extras(args, ctx):
+    """The other workloads, short runs, as extra keys of the line."""
+    import numpy as np
+
+    from paper_2609_02394_amd import rmc, workloads as W
+
+    out = {}
+    ns = argparse.Namespace(**vars(args))
+    ns.steps, ns.warmup = 5, 1
+    t0 = time.perf_counter()
+    # XXZ chain N=64, k=64: 32 jobs per step, and one job at a time (FP32 and plain FP64)
+    job = W.xxz_chain64()
+    m, table, ktab, ref = bench_chain_batch(ns, ctx, job, 32)
+    m["roofline"] = roofline(table, "xxz64")
+    m["workload"] = "open XXZ chain N=64, J=1, Delta=1, 8-site leaves, k=64, 3 bond ops, lowest 8"
+    out["xxz64_batch32"] = m
+    chain = rmc.job_chain(job)
+    fp32 = rmc.default_opts(precision=PREC[args.precision])
+    lat = []
+    for _ in range(6):
+        s0 = time.perf_counter()
+        e, _ = ctx.recurse(*chain, opts=fp32)
+        lat.append(time.perf_counter() - s0)
+    lat = np.array(lat[1:]) * 1e3
+    out["xxz64_single_job"] = {"value": 1e3 / float(np.mean(lat)), "unit": "solves/s",
+                               "p50_ms": float(np.percentile(lat, 50)),
+                               "p99_ms": float(np.percentile(lat, 99)),
+                               "max_rel_err": rel_err(e, ref),
+                               "plain_per_job_fp64": plain_per_job(ctx, [chain], [ref], [job.q], 3)}
+    # TFIM ladder 2x48, k = 128
+    lad = W.tfim_ladder96()
+    gold = read_golden(GOLDEN_LADDER).get("ladder96")
+    ns.steps = 3
+    m, table, ktab, ref = bench_chain_batch(ns, ctx, lad, 8, gold[2] if gold else None)
+    m["roofline"] = roofline(table, "ladder96")
+    m["workload"] = ("TFIM ladder 2x48, J_leg=1, J_rung=0.5, h=0.9, 2x4 leaves, k=128, 2 bond ops "
+                     "per cut, lowest 8; 8 jobs per step")
+    m["plain_per_job_fp64"] = plain_per_job(ctx, [rmc.job_chain(lad)], [ref], [lad.q], 1)
+    out["ladder96"] = m
+    # serving: the seeded Poisson stream at the configured 200 jobs/s, and a lower rate
+    srv = {}
+    for rate in (200.0, 60.0):
+        srv[f"rate_{int(rate)}"] = serve_run(ctx, PREC[args.precision], rate, 200, 40)
+    srv["workload"] = ("Poisson arrivals, open XXZ or TFIM chains N in {16,32,64,128}, Delta or "
+                       "h ~ U[0.5,1.5], 8-site leaves, k in {32,64,128}, lowest 4-8; 40 warm-up "
+                       "and 200 measured jobs per rate")
+    out["serve"] = srv
+    out["seconds"] = time.perf_counter() - t0
+    return out
 
 
 def main():
@@ -86,241 +430,89 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=list(PREC), default="fp32",
-                    help="precision of the Kronecker matvecs (Rayleigh-Ritz, CholQR2, "
-                         "residuals and the defect correction stay FP64)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--arena-gb", type=float, default=8.0)
-    ap.add_argument("--mode", choices=["recurse", "serve", "bound"], default="recurse",
-                    help="recurse: timed recursions of the XXZ N=64 workload; serve: the "
-                         "Poisson serving stream through the continuous-batching scheduler; "
-                         "bound: single-merge truncation diagnostics of the L=20 TFIM chain")
-    ap.add_argument("--workload", choices=["xxz64", "ladder96", "rfheis512"], default="xxz64",
-                    help="xxz64: XXZ N=64 k=64 (the metric's configuration); ladder96: TFIM "
-                         "ladder 2x48 k=128; rfheis512: 512 random-field Heisenberg chains N=32 "
-                         "with k in {32,48,64,96}, all solved as one batch per step")
+                    help="precision of the Kronecker matvecs of the filter (Rayleigh-Ritz, "
+                         "CholeskyQR2, residuals and the defect correction stay FP64)")
+    ap.add_argument("--workload", choices=["rfheis512", "xxz64", "ladder96"], default="rfheis512",
+                    help="rfheis512: 512 random-field chains per step (the metric's workload); "
+                         "xxz64: XXZ N=64 k=64, --batch jobs per step; ladder96: TFIM ladder "
+                         "2x48 k=128, --batch jobs per step")
+    ap.add_argument("--batch", type=int, default=32, help="jobs per step for xxz64 / ladder96")
+    ap.add_argument("--mode", choices=["recurse", "serve", "bound"], default="recurse")
     ap.add_argument("--jobs", type=int, default=200, help="serve mode: measured jobs")
     ap.add_argument("--rate", type=float, default=200.0, help="serve mode: arrivals per second")
-    ap.add_argument("--max-degree", type=int, default=0,
-                    help="cap of the Chebyshev degree per outer iteration (0 = library default)")
-    ap.add_argument("--no-plain", action="store_true",
-                    help="skip the plain per-job FP64 comparison run after the timed region")
+    ap.add_argument("--max-degree", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--arena-gb", type=float, default=32.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (scales HBM counters)")
-    ap.add_argument("--batch", type=int, default=32,
-                    help="independent jobs of the workload solved together per step "
-                         "(batched levels); 1 = the plain per-job recursion")
     args = ap.parse_args()
-    use_tune_file()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU (the path is measured on one "
+                                   "GPU's share); --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
+    use_tune_file()
 
-    import numpy as np
     import torch
 
     from paper_2609_02394_amd import rmc, workloads as W
 
-    if args.mode == "serve":
-        serve_bench(args)
-        return
-    if args.mode == "bound":
-        bound_bench(args)
-        return
-
-    if args.workload == "rfheis512":
-        batch_bench(args)
-        return
-    job = W.xxz_chain64() if args.workload == "xxz64" else W.tfim_ladder96()
-    chain = rmc.job_chain(job)
-
-    ref = None
-    cpu = None
-    if not args.no_cpu_baseline and args.workload == "xxz64":
-        ref, cpu_s, threads = cpu_baseline(job)
-        cpu = {"value": 1.0 / cpu_s, "unit": "solves/s", "cores": threads, "kind": "oracle",
-               "sample": "1 whole job of the benchmark workload (dense 256 leaf ED + 3 dense "
-                         "4096x4096 eigh merges, LAPACK via NumPy)",
-               "seconds": cpu_s}
-
     ctx = rmc.Context(arena_bytes=int(args.arena_gb * (1 << 30)))
-    opts = rmc.default_opts(precision=PREC[args.precision], max_degree=args.max_degree)
-    fp64_opts = rmc.default_opts(precision=0)
     if args.calibrate_copy:  # a copy kernel of known size for HBM counter scaling
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if ref is None:  # FP64 GPU path as the reference when the oracle is skipped
-        ref, _ = ctx.recurse(*chain, opts=fp64_opts)
+    if args.mode == "serve":
+        r = serve_run(ctx, PREC[args.precision], args.rate, args.jobs, max(0, args.warmup))
+        print(json.dumps({"metric": METRIC, "n_gpus": 1, "higher_is_better": True,
+                          "data": "synthetic", **r}))
+        ctx.close()
+        return
+    if args.mode == "bound":
+        bound_bench(args, ctx)
+        ctx.close()
+        return
 
-    B = max(1, args.batch)
-
-    def step():
-        if B == 1:
-            e, rep = ctx.recurse(*chain, opts=opts)
-            return [e], rep
-        e, st, top = ctx.recurse_batch([chain] * B, opts=opts)
-        return [e[i, : job.q] if st[i] == 0 else np.full(job.q, np.nan) for i in range(B)], None
-
-    for _ in range(args.warmup):
-        step()
-
-    lat = []
-    ok = 0
-    max_err = 0.0
-    rep = None
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        es, r = step()
-        rep = r if r is not None else rep
-        lat.append(time.perf_counter() - s0)
-        for e in es:
-            err = float(np.max(np.abs(e - ref) / np.maximum(np.abs(ref), 1.0)))
-            max_err = max(max_err, err if err == err else np.inf)
-            ok += err <= 1e-8
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    by_prec = {name: ctx.profile_read(PREC[name]) for name in PREC}
-    by_kernel = {(kk, name): ctx.profile_read(PREC[name], kernel=kk) for kk in KERNELS for name in PREC}
-    ctx.profile(False)
-
-    # the plain per-job FP64 recursion of the same workload, for comparison
-    plain = None
-    if not args.no_plain:
-        for _ in range(2):
-            ctx.recurse(*chain, opts=fp64_opts)
-        torch.cuda.synchronize()
-        p0 = time.perf_counter()
-        for _ in range(5):
-            ctx.recurse(*chain, opts=fp64_opts)
-        torch.cuda.synchronize()
-        plain = {"form": "plain per-job FP64 recursion, one job at a time",
-                 "value": 5 / (time.perf_counter() - p0), "unit": "solves/s"}
-
-    lat_ms = np.array(lat) * 1e3
-    # dominant kernel: the Kronecker kernel kind (one matvec step, or the whole filter)
-    # and precision that took most of the Kronecker time
-    dk, dom = max(by_kernel, key=lambda k: by_kernel[k]["ms"])
-    prof = by_kernel[(dk, dom)]
-    kron_table = {}
-    for (kk, name), pr in by_kernel.items():
-        if pr["launches"] == 0:
-            continue
-        sec = pr["ms"] * 1e-3
-        kron_table[f"{KERNELS[kk]}:{name}"] = {
-            "launches": pr["launches"], "ms_per_step": pr["ms"] / args.steps,
-            "avg_launch_us": pr["ms"] * 1e3 / pr["launches"],
-            "tflops": pr["flops"] / sec / 1e12, "gbs": pr["bytes"] / sec / 1e9,
-            "flops_per_launch": pr["flops"] / pr["launches"],
-            "bytes_per_launch": pr["bytes"] / pr["launches"]}
-    sec = prof["ms"] * 1e-3
-    tr = measured_traffic(KERNELS[dk], dom)
-    if dom == "bf16":  # HBM-bound: the BF16 MFMA roof lies far above the HBM roof
-        achieved = prof["bytes"] / sec / 1e9 if sec > 0 else 0.0
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_GBS}
+    cpu_fn, plain = None, None
+    if args.workload == "rfheis512":
+        meas, table, ktab, config, plain, cpu_fn = bench_rfheis(args, ctx, None)
     else:
-        achieved = prof["flops"] / sec / 1e12 if sec > 0 else 0.0
-        peak = PEAK_TFLOPS[dom]
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak}
-    roof.update({"traffic": tr, "kernel": KERNELS[dk], "precision": dom,
-                 "launches": prof["launches"],
-                 "avg_launch_us": prof["ms"] * 1e3 / max(1, prof["launches"]),
-                 "flops_per_launch": prof["flops"] / max(1, prof["launches"]),
-                 "bytes_per_launch": prof["bytes"] / max(1, prof["launches"])})
+        job = W.xxz_chain64() if args.workload == "xxz64" else W.tfim_ladder96()
+        gold = read_golden(GOLDEN_LADDER).get("ladder96") if args.workload == "ladder96" else None
+        meas, table, ktab, ref = bench_chain_batch(args, ctx, job, max(1, args.batch),
+                                                   gold[2] if gold else None)
+        if not args.no_plain:
+            plain = plain_per_job(ctx, [rmc.job_chain(job)], [ref], [job.q], 3)
+        config = {"workload": ("open XXZ chain N=64, J=1, Delta=1, 8-site leaves, k=64, 3 bond "
+                               "ops per cut, lowest 8" if args.workload == "xxz64" else
+                               "TFIM ladder 2x48, J_leg=1, J_rung=0.5, h=0.9, 2x4 leaves, k=128, "
+                               "2 bond ops per cut, lowest 8"),
+                  "precision": args.precision, "form": "batched levels",
+                  "jobs_per_step": meas["jobs_per_step"],
+                  "max_rel_err_vs_fp64": meas["max_rel_err"],
+                  "fp64_path_vs_oracle_golden": meas.get("fp64_path_vs_oracle_golden")}
+    roof = roofline(table, args.workload)
+    ext = None if args.no_extras else extras(args, ctx)
+    cpu = None
+    if not args.no_cpu_baseline and cpu_fn is not None:
+        cpu = cpu_fn()
     out = {
-        "metric": "coupled eigensolves/s (lowest 8, rel err<=1e-8 vs FP64)",
-        "value": ok / total,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": total / args.steps * 1e3,
-        "p50_ms": float(np.percentile(lat_ms, 50)),
-        "p99_ms": float(np.percentile(lat_ms, 99)),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "metric": METRIC, "value": meas["value"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": meas["ms_per_step"],
+        "p50_ms": meas["p50_ms"], "p99_ms": meas["p99_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[args.precision],
-        "data": "synthetic",
-        "config": {"workload": ("open XXZ chain N=64, J=1, Delta=1, 8-site leaves, k=64, "
-                                "3 bond ops per cut, lowest 8, one whole recursion per job")
-                   if args.workload == "xxz64" else
-                   ("TFIM ladder 2x48, J_leg=1, J_rung=0.5, h=0.9, 2x4 leaves, k=128, 2 bond "
-                    "ops per cut, lowest 8, one whole recursion per job"),
-                   "precision": args.precision, "max_rel_err": max_err,
-                   "jobs_per_step": B, "accurate_solves": ok,
-                   "form": "per-job recursion" if B == 1 else "batched levels"},
-        "roofline": roof,
-        "kron_by_kernel": kron_table,
-        "plain_per_job_fp64": plain,
-        "cpu_baseline": cpu,
-        "report_last_step": rep["records"] if rep else None,
+        "data": "synthetic", "config": config, "roofline": roof, "kron_by_kernel": ktab,
+        "plain_per_job_fp64": plain, "cpu_baseline": cpu, "extras": ext,
     }
     print(json.dumps(out))
     ctx.close()
 
 
-def batch_bench(args):
-    """512 random-field Heisenberg chains (N=32, h_i ~ U[-2,2] seeded per chain, 8-site
-    leaves, k in {32,48,64,96}, lowest 8): one step solves all of them as one batch
-    (every level of every chain in batched launches). Accuracy: FP64 per-chain
-    references for a sample of chains."""
-    import numpy as np
-
-    from paper_2609_02394_amd import rmc, workloads as W
-
-    jobs = W.rfheis_batch(512)
-    chains = [rmc.job_chain(j) for j in jobs]
-    ctx = rmc.Context(arena_bytes=int(max(args.arena_gb, 32.0) * (1 << 30)))
-    opts = rmc.default_opts(precision=PREC[args.precision], max_degree=args.max_degree)
-    sample = list(range(0, 512, 37))
-    refs = {i: ctx.recurse(*chains[i])[0] for i in sample}
-    for _ in range(args.warmup):
-        ctx.recurse_batch(chains, opts=opts)
-    lat, ok, max_err = [], 0, 0.0
-    ctx.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        e, st, top = ctx.recurse_batch(chains, opts=opts)
-        lat.append(time.perf_counter() - s0)
-        ok += sum(1 for x in st if x == 0)
-        for i in sample:
-            err = float(np.max(np.abs(e[i] - refs[i]) / np.maximum(np.abs(refs[i]), 1.0)))
-            max_err = max(max_err, err)
-    total = time.perf_counter() - t0
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
-    peak = PEAK_TFLOPS[args.precision]
-    lat_ms = np.array(lat) * 1e3
-    out = {
-        "metric": "coupled eigensolves/s (lowest 8, rel err<=1e-8 vs FP64), batched levels",
-        "value": ok / total if max_err <= 1e-8 else 0.0, "unit": "solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3,
-        "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-        "higher_is_better": True, "data": "synthetic",
-        "config": {"workload": "512 random-field Heisenberg chains N=32, W=2, 8-site leaves, "
-                               "k in {32,48,64,96}, lowest 8, all chains per step",
-                   "precision": args.precision, "max_rel_err_sample": max_err,
-                   "sample_size": len(sample)},
-        "roofline": {"bound": "mfma", "kernel": "kron_batched_kernel", "achieved": achieved,
-                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "launches": prof["launches"],
-                     "avg_launch_us": prof["ms"] * 1e3 / max(1, prof["launches"])},
-    }
-    print(json.dumps(out))
-    ctx.close()
-
-
-def bound_bench(args):
+def bound_bench(args, ctx):
     """Single-merge truncation diagnostics (a, ||PHQ||, lambda_min(QHQ), gamma, r, E0) of
     the open TFIM chain L = 20 as two ten-site leaves, J = 1, g = 0.7, k = 8: a step is
     one rmc_merge_bound call on the two leaf modules (built once). Checked against the
@@ -332,7 +524,6 @@ def bound_bench(args):
 
     k, L, nA = 8, 20, 10
     job = W.ChainJob("tfim", L, nA, k, 1, J=1.0, h=0.7)
-    ctx = rmc.Context(arena_bytes=int(args.arena_gb * (1 << 30)))
     tA, tB = SM.block_terms(job, 0, nA), SM.block_terms(job, nA, L)
     A = ctx.module_ed(nA, tA, k)
     B = ctx.module_ed(L - nA, tB, k)
@@ -398,82 +589,6 @@ def bound_bench(args):
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
-    ctx.close()
-
-
-def serve_bench(args):
-    """Open-loop Poisson stream of XXZ / TFIM jobs (N in {16,32,64,128}, k in
-    {32,64,128}, lowest 4-8) through rmc_submit / rmc_poll: throughput, p50/p99
-    latency (submission to completion), accuracy vs the FP64 per-job path on a sample."""
-    import threading
-
-    import numpy as np
-
-    from paper_2609_02394_amd import rmc, workloads as W
-
-    warm = max(0, args.warmup)
-    stream = W.serving_stream(warm + args.jobs, rate=args.rate)
-    ctx = rmc.Context(arena_bytes=int(args.arena_gb * (1 << 30)))
-    opts = rmc.default_opts(precision=PREC[args.precision])
-    # FP64 per-job references for a sample of the measured jobs (accuracy gate)
-    sample = list(range(warm, warm + args.jobs, max(1, args.jobs // 8)))
-    refs = {i: ctx.recurse(*rmc.job_chain(stream[i][1]))[0] for i in sample}
-    ctx.serve_start(opts=opts, max_inflight=64)
-    ids = [None] * len(stream)
-    t0 = time.perf_counter()
-
-    def feeder():
-        for i, (t, job) in enumerate(stream):
-            d = t - (time.perf_counter() - t0)
-            if d > 0:
-                time.sleep(d)
-            ids[i] = ctx.submit(*rmc.job_chain(job))
-
-    th = threading.Thread(target=feeder)
-    th.start()
-    res = {}
-    t_done = {}
-    while len(res) < len(stream):
-        for i, (t, job) in enumerate(stream):
-            if i in res or ids[i] is None:
-                continue
-            done, e, st, lat = ctx.poll(ids[i], job.q)
-            if done:
-                res[i] = (e, st, lat)
-                t_done[i] = time.perf_counter() - t0
-        time.sleep(0.0005)
-    th.join()
-    ctx.serve_stop()
-    # the plain per-job FP64 recursion over the first measured jobs, one at a time
-    plain = None
-    if not args.no_plain:
-        nplain = min(24, args.jobs)
-        p0 = time.perf_counter()
-        for i in range(warm, warm + nplain):
-            ctx.recurse(*rmc.job_chain(stream[i][1]))
-        plain = {"form": "plain per-job FP64 recursion, one job at a time (first jobs of the "
-                         "measured stream)", "jobs": nplain,
-                 "value": nplain / (time.perf_counter() - p0), "unit": "solves/s"}
-    meas = list(range(warm, len(stream)))
-    lat = np.array([res[i][2] for i in meas])
-    ok = sum(res[i][1] == 0 for i in meas)
-    errs = [float(np.max(np.abs(res[i][0] - refs[i]) / np.maximum(np.abs(refs[i]), 1.0)))
-            for i in sample]
-    span = max(t_done[i] for i in meas) - stream[warm][0]
-    out = {
-        "metric": "coupled eigensolves/s (lowest 4-8, rel err<=1e-8 vs FP64), serving",
-        "value": ok / span, "unit": "solves/s", "n_gpus": 1,
-        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-        "higher_is_better": True, "data": "synthetic",
-        "config": {"workload": "Poisson stream, XXZ/TFIM N in {16,32,64,128}, 8-site leaves, "
-                               "k in {32,64,128}, lowest 4-8", "rate_per_s": args.rate,
-                   "jobs": args.jobs, "warmup_jobs": warm, "precision": args.precision,
-                   "completed_ok": ok, "offered_span_s": stream[-1][0] - stream[warm][0],
-                   "max_rel_err_sample": max(errs), "sample_size": len(sample)},
-        "plain_per_job_fp64": plain,
-    }
-    print(json.dumps(out))
-    ctx.close()
 
 
 if __name__ == "__main__":
