@@ -23,73 +23,50 @@ __device__ inline double op_sign(int op, int br) {
   return br == 0 ? 1.0 : -1.0;
 }
 
-// Zero fill, coalesced.
-__global__ void fill_zero_kernel(long n, double* __restrict__ p) {
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
-    p[t] = 0.0;
-}
-
-// One thread per basis row r: for every term, in list order, find the column
-// c = r with the bits of X/T sites flipped and add coef * (product of +-1 factors)
-// to H[r][c]. Each entry is accumulated in term order from +0.0, exactly as a
-// dense sum of Kronecker products would be.
-__global__ void leaf_assemble_kernel(int D, int n_terms, const DevTerm* __restrict__ terms,
-                                     double* __restrict__ H) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= D) return;
-  double* row = H + (long)r * D;
+// Entry-parallel assembly: thread (r, c) walks the term list in order and adds
+// coef * (product of +-1 factors) for every term that maps row r to column c (its X / T
+// sites flipped: c = r ^ flip). Each entry is accumulated in term order from +0.0,
+// exactly as a dense sum of Kronecker products would be, and consecutive threads write
+// consecutive entries of a row (coalesced; no separate zero pass). The term list is
+// read with wave-uniform indices (scalar loads).
+__device__ inline double leaf_entry(int r, int c, int n_terms, const DevTerm* __restrict__ terms) {
+  double acc = 0.0;
   for (int t = 0; t < n_terms; ++t) {
-    DevTerm tm = terms[t];
-    int c = r;
+    const DevTerm tm = terms[t];
+    int flip = 0;
     double sgn = 1.0;
     for (int u = 0; u < tm.nsite; ++u) {
-      int b = tm.bit[u];
-      int br = (r >> b) & 1;
-      sgn *= op_sign(tm.op[u], br);
-      if (op_flips(tm.op[u])) c ^= (1 << b);
+      const int b = tm.bit[u];
+      sgn *= op_sign(tm.op[u], (r >> b) & 1);
+      if (op_flips(tm.op[u])) flip |= 1 << b;
     }
-    double val = sgn > 0.0 ? tm.coef : -tm.coef;
-    row[c] = row[c] + val;
+    if ((r ^ flip) == c) acc = acc + (sgn > 0.0 ? tm.coef : -tm.coef);
   }
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void leaf_assemble_kernel(int D, int n_terms,
+                                                            const DevTerm* __restrict__ terms,
+                                                            double* __restrict__ H) {
+  const long nn = (long)D * D;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < nn; e += (long)gridDim.x * 256)
+    H[e] = leaf_entry((int)(e / D), (int)(e % D), n_terms, terms);
 }
 
 void leaf_assemble(hipStream_t s, int n_sites, int n_terms, const DevTerm* terms, double* H) {
-  int D = 1 << n_sites;
-  long nn = (long)D * D;
-  int blocks = (int)((nn + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, s, nn, H);
-  hipLaunchKernelGGL(leaf_assemble_kernel, dim3((D + 63) / 64), dim3(64), 0, s, D, n_terms, terms, H);
+  const long D = 1L << n_sites, nn = D * D;
+  const int blocks = (int)std::min<long>((nn + 255) / 256, 4096);
+  hipLaunchKernelGGL(leaf_assemble_kernel, dim3(blocks), dim3(256), 0, s, (int)D, n_terms, terms, H);
 }
 
-// ---- batched leaf set-up (every leaf of a level in four launches) ------------------
-__global__ void leaf_zero_batched_kernel(const LeafSetDesc* __restrict__ descs) {
-  const LeafSetDesc d = descs[blockIdx.y];
-  const long D = 1L << d.n_sites, nn = D * D;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nn; t += (long)gridDim.x * blockDim.x)
-    d.H[t] = 0.0;
-}
-
-// The row-per-thread accumulation of leaf_assemble_kernel (same order, same values).
-__global__ void leaf_assemble_batched_kernel(const LeafSetDesc* __restrict__ descs) {
+// ---- batched leaf set-up (every leaf of a level in three launches) -----------------
+// The entry-parallel assembly of leaf_assemble_kernel for every leaf of a batch.
+__global__ __launch_bounds__(256) void leaf_assemble_batched_kernel(const LeafSetDesc* __restrict__ descs) {
   const LeafSetDesc d = descs[blockIdx.y];
   const int D = 1 << d.n_sites;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= D) return;
-  double* row = d.H + (long)r * D;
-  for (int t = 0; t < d.n_terms; ++t) {
-    DevTerm tm = d.terms[t];
-    int c = r;
-    double sgn = 1.0;
-    for (int u = 0; u < tm.nsite; ++u) {
-      int b = tm.bit[u];
-      int br = (r >> b) & 1;
-      sgn *= op_sign(tm.op[u], br);
-      if (op_flips(tm.op[u])) c ^= (1 << b);
-    }
-    double val = sgn > 0.0 ? tm.coef : -tm.coef;
-    row[c] = row[c] + val;
-  }
+  const long nn = (long)D * D;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < nn; e += (long)gridDim.x * 256)
+    d.H[e] = leaf_entry((int)(e / D), (int)(e % D), d.n_terms, d.terms);
 }
 
 // Diagonal and Gershgorin row bounds (as dense_diag_kernel), one workgroup per row.
@@ -133,9 +110,8 @@ __global__ __launch_bounds__(256) void leaf_bound_batched_kernel(const LeafSetDe
 void leaf_setup_batched(hipStream_t s, const LeafSetDesc* d, int P, int n_sites_max) {
   if (P <= 0) return;
   const long D = 1L << n_sites_max, nn = D * D;
-  const int zb = (int)std::min<long>((nn + 255) / 256, 1024);
-  hipLaunchKernelGGL(leaf_zero_batched_kernel, dim3(zb, P), dim3(256), 0, s, d);
-  hipLaunchKernelGGL(leaf_assemble_batched_kernel, dim3((unsigned)((D + 63) / 64), P), dim3(64), 0, s, d);
+  const int ab = (int)std::min<long>((nn + 255) / 256, 1024);
+  hipLaunchKernelGGL(leaf_assemble_batched_kernel, dim3(ab, P), dim3(256), 0, s, d);
   hipLaunchKernelGGL(leaf_diag_batched_kernel, dim3((unsigned)D, P), dim3(256), 0, s, d);
   hipLaunchKernelGGL(leaf_bound_batched_kernel, dim3(P), dim3(256), 0, s, d);
 }

@@ -55,8 +55,8 @@ struct DevTerm {
 };
 void leaf_assemble(hipStream_t s, int n_sites, int n_terms, const DevTerm* terms, double* H);
 
-// Every leaf of a batch: H (zeroed, then assembled as leaf_assemble does), its
-// diagonal D, Gershgorin row bounds rb and their maximum bmax[0]; four launches.
+// Every leaf of a batch: H (assembled as leaf_assemble does), its diagonal D, Gershgorin
+// row bounds rb and their maximum bmax[0]; three launches.
 struct LeafSetDesc {
   int n_sites, n_terms;
   const DevTerm* terms;

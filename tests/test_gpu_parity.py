@@ -1154,3 +1154,63 @@ def test_ladder_2x48_k128_matches_oracle_golden(ctx):
     say("ladder golden fp32")
     e32, _ = ctx.recurse(*rmc.job_chain(job), opts=rmc.default_opts(precision=1))
     assert rel_err(e32, g["E"]) <= 1e-8, (e32, g["E"])
+
+
+# -- the gap study and the leaf-size study of the error density (Sec. IV, App. C) ------
+
+def test_gap_vs_field_through_the_transition(ctx):
+    """Open TFIM, J = 1, 5-site leaves, L = 10, 20, 40, 80, g = h / J = 0.5 ... 1.5 through
+    the transition at g = 1, k = 4 ... 32: the two lowest energies from the recursion
+    against the exact free-fermion levels (the gap E1 - E0 is the smallest single-particle
+    energy of the open chain). Every energy is an upper bound; L = 10 at k = 32 keeps
+    every leaf state and is exact; L <= 40 matches the oracle recursion; at k = 32 the gap
+    is within 10% of the exact gap for g >= 0.8 up to L = 40 (the quasi-degenerate edge
+    modes of g = 0.5 have gaps of 1e-3 ... 1e-12, below what a relative gap error means)."""
+    from paper_2609_02394_amd import rmc
+
+    gs, ks = (0.5, 0.8, 1.0, 1.2, 1.5), (4, 8, 16, 32)
+    table = {}
+    for L in (10, 20, 40, 80):
+        for g in gs:
+            ex = OX.tfim_free_fermion(L, 1.0, g, 2)
+            for k in ks:
+                job = W.ChainJob("tfim", L, 5, k, 2, J=1.0, h=g)
+                e, _ = ctx.recurse(*rmc.job_chain(job))
+                assert np.all(e >= ex - 1e-9 * np.maximum(np.abs(ex), 1.0)), (L, g, k, e, ex)
+                if L <= 40:
+                    assert rel_err(e, OR.recurse(job).energies) <= 1e-10, (L, g, k)
+                table[L, g, k] = (e[1] - e[0], ex[1] - ex[0])
+    for g in gs:
+        gk, gx = table[10, g, 32]
+        assert abs(gk - gx) <= 1e-10 * max(1.0, abs(gx)), (g, gk, gx)
+    for L in (20, 40):
+        for g in gs[1:]:
+            gk, gx = table[L, g, 32]
+            assert abs(gk - gx) <= 0.1 * gx, (L, g, gk, gx)
+    say("gap E1-E0 (rows L, g; columns exact, k=4..32):")
+    for L in (10, 20, 40, 80):
+        for g in gs:
+            say(L, g, f"{table[L, g, 4][1]:.4e}", " ".join(f"{table[L, g, k][0]:.4e}" for k in ks))
+
+
+def test_error_density_by_leaf_size(ctx):
+    """Open TFIM, J = 1, h = 0.7 at L ~ 80 with leaves of L0 = 5, 7 and 9 sites (L = 80,
+    84, 81): the ground-state error density against free fermions for k = 4 ... 32 (the
+    leaf-size study of App. C). Non-negative, falling with k for each L0, and equal to
+    the oracle recursion's."""
+    from paper_2609_02394_amd import rmc
+
+    ks = (4, 8, 16, 32)
+    dens = {}
+    for L0, L in ((5, 80), (7, 84), (9, 81)):
+        e0 = OX.tfim_free_fermion(L, 1.0, 0.7, 1)[0]
+        for k in ks:
+            job = W.ChainJob("tfim", L, L0, k, 1, J=1.0, h=0.7)
+            e, _ = ctx.recurse(*rmc.job_chain(job))
+            assert rel_err(e, OR.recurse(job).energies) <= 1e-10, (L0, k)
+            dens[L0, k] = (e[0] - e0) / L
+            assert dens[L0, k] >= -1e-12
+        assert all(dens[L0, a] >= dens[L0, b] for a, b in zip(ks, ks[1:])), L0
+    say("error density dE0/L (rows L0, columns k=4..32):")
+    for L0 in (5, 7, 9):
+        say(L0, " ".join(f"{dens[L0, k]:.3e}" for k in ks))
