@@ -27,46 +27,80 @@ __device__ inline double op_sign(int op, int br) {
 // coef * (product of +-1 factors) for every term that maps row r to column c (its X / T
 // sites flipped: c = r ^ flip). Each entry is accumulated in term order from +0.0,
 // exactly as a dense sum of Kronecker products would be, and consecutive threads write
-// consecutive entries of a row (coalesced; no separate zero pass). The term list is
-// read with wave-uniform indices (scalar loads).
-__device__ inline double leaf_entry(int r, int c, int n_terms, const DevTerm* __restrict__ terms) {
+// consecutive entries of a row (coalesced; no separate zero pass). Each workgroup first
+// turns the term list into (coef, flip, Z mask, T mask) in LDS: a term acts on row r
+// with the sign (-1)^(|r & Z mask| + |~r & T mask|) (Z: -1 on a set bit; T = -i sigma^y:
+// -1 on a clear bit), so an entry costs one compare per term and a sign only on a match.
+struct LeafTermMask {
+  double coef;
+  int flip, zm, tm, pad;
+};
+constexpr int kLeafTermsLds = 1024;
+
+__device__ inline LeafTermMask leaf_term_mask(const DevTerm& t) {
+  LeafTermMask m{t.coef, 0, 0, 0, 0};
+  for (int u = 0; u < t.nsite; ++u) {
+    const int bit = 1 << t.bit[u];
+    if (op_flips(t.op[u])) m.flip |= bit;
+    if (t.op[u] == 3) m.zm |= bit;
+    if (t.op[u] == 2) m.tm |= bit;
+  }
+  return m;
+}
+
+__device__ inline double leaf_entry(int r, int c, int n_terms, const LeafTermMask* tl) {
+  const int x = r ^ c;
   double acc = 0.0;
   for (int t = 0; t < n_terms; ++t) {
-    const DevTerm tm = terms[t];
-    int flip = 0;
-    double sgn = 1.0;
-    for (int u = 0; u < tm.nsite; ++u) {
-      const int b = tm.bit[u];
-      sgn *= op_sign(tm.op[u], (r >> b) & 1);
-      if (op_flips(tm.op[u])) flip |= 1 << b;
-    }
-    if ((r ^ flip) == c) acc = acc + (sgn > 0.0 ? tm.coef : -tm.coef);
+    const LeafTermMask m = tl[t];
+    if (m.flip != x) continue;
+    const int odd = (__popc(r & m.zm) + __popc(~r & m.tm)) & 1;
+    acc = acc + (odd ? -m.coef : m.coef);
   }
   return acc;
 }
 
-__global__ __launch_bounds__(256) void leaf_assemble_kernel(int D, int n_terms,
+// Stages the term list of a leaf in LDS (up to kLeafTermsLds terms) and fills the D x D
+// entries from e0 on, with a grid stride; longer lists read their masks from `spill`.
+__device__ inline void leaf_fill(int n_sites, int n_terms, const DevTerm* __restrict__ terms,
+                                 double* __restrict__ H, LeafTermMask* tl, long e0, long stride) {
+  const int nl = min(n_terms, kLeafTermsLds);
+  for (int t = threadIdx.x; t < nl; t += blockDim.x) tl[t] = leaf_term_mask(terms[t]);
+  __syncthreads();
+  const int D = 1 << n_sites;
+  const long nn = (long)D * D;
+  for (long e = e0; e < nn; e += stride) {
+    const int r = (int)(e >> n_sites), c = (int)(e & (D - 1));
+    double v = leaf_entry(r, c, nl, tl);
+    for (int t = nl; t < n_terms; ++t) {  // beyond the LDS table, in the same order
+      const LeafTermMask m = leaf_term_mask(terms[t]);
+      if (m.flip != (r ^ c)) continue;
+      const int odd = (__popc(r & m.zm) + __popc(~r & m.tm)) & 1;
+      v = v + (odd ? -m.coef : m.coef);
+    }
+    H[e] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void leaf_assemble_kernel(int n_sites, int n_terms,
                                                             const DevTerm* __restrict__ terms,
                                                             double* __restrict__ H) {
-  const long nn = (long)D * D;
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < nn; e += (long)gridDim.x * 256)
-    H[e] = leaf_entry((int)(e / D), (int)(e % D), n_terms, terms);
+  __shared__ LeafTermMask tl[kLeafTermsLds];
+  leaf_fill(n_sites, n_terms, terms, H, tl, blockIdx.x * 256L + threadIdx.x, (long)gridDim.x * 256);
 }
 
 void leaf_assemble(hipStream_t s, int n_sites, int n_terms, const DevTerm* terms, double* H) {
   const long D = 1L << n_sites, nn = D * D;
   const int blocks = (int)std::min<long>((nn + 255) / 256, 4096);
-  hipLaunchKernelGGL(leaf_assemble_kernel, dim3(blocks), dim3(256), 0, s, (int)D, n_terms, terms, H);
+  hipLaunchKernelGGL(leaf_assemble_kernel, dim3(blocks), dim3(256), 0, s, n_sites, n_terms, terms, H);
 }
 
 // ---- batched leaf set-up (every leaf of a level in three launches) -----------------
 // The entry-parallel assembly of leaf_assemble_kernel for every leaf of a batch.
 __global__ __launch_bounds__(256) void leaf_assemble_batched_kernel(const LeafSetDesc* __restrict__ descs) {
+  __shared__ LeafTermMask tl[kLeafTermsLds];
   const LeafSetDesc d = descs[blockIdx.y];
-  const int D = 1 << d.n_sites;
-  const long nn = (long)D * D;
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < nn; e += (long)gridDim.x * 256)
-    d.H[e] = leaf_entry((int)(e / D), (int)(e % D), d.n_terms, d.terms);
+  leaf_fill(d.n_sites, d.n_terms, d.terms, d.H, tl, blockIdx.x * 256L + threadIdx.x, (long)gridDim.x * 256);
 }
 
 // Diagonal and Gershgorin row bounds (as dense_diag_kernel), one workgroup per row.

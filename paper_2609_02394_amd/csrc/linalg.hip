@@ -1435,24 +1435,58 @@ __global__ __launch_bounds__(256) void vec_batched_kernel(int op, const VecDesc*
     const int j = blockIdx.x;
     if (j >= d.nv) return;
     double acc = 0.0;
+    // rows of even length start 16-byte aligned (the arena is 256-byte aligned): pairs
+    // of elements move as one 16-byte access; each thread's partial sum keeps the order
+    // i, i + 1 within a pair and ascending pairs
+    const bool pairs = (n & 1) == 0;
     if (op == VEC_NORMALIZE) {
       double* y = d.out + (long)j * n;
-      for (int i = threadIdx.x; i < n; i += 256) acc += y[i] * y[i];
+      if (pairs) {
+        double2* y2 = reinterpret_cast<double2*>(y);
+        for (int i = threadIdx.x; i < n / 2; i += 256) {
+          const double2 v = y2[i];
+          acc += v.x * v.x;
+          acc += v.y * v.y;
+        }
+      } else {
+        for (int i = threadIdx.x; i < n; i += 256) acc += y[i] * y[i];
+      }
       double nr = sqrt(block_sum256(acc, red));
       if (threadIdx.x == 0 && d.norms) d.norms[j] = nr;
       if (nr > 0.0) {
         double inv = 1.0 / nr;
-        for (int i = threadIdx.x; i < n; i += 256) y[i] *= inv;
+        if (pairs) {
+          double2* y2 = reinterpret_cast<double2*>(y);
+          for (int i = threadIdx.x; i < n / 2; i += 256) {
+            const double2 v = y2[i];
+            y2[i] = double2{v.x * inv, v.y * inv};
+          }
+        } else {
+          for (int i = threadIdx.x; i < n; i += 256) y[i] *= inv;
+        }
       }
     } else {
       const double* hx = d.P + (long)j * n;
       const double* x = d.Q + (long)j * n;
       const double th = d.a[j];
       double* rout = d.out ? d.out + (long)j * n : nullptr;
-      for (int i = threadIdx.x; i < n; i += 256) {
-        double r = hx[i] - th * x[i];
-        acc += r * r;
-        if (rout) rout[i] = r;
+      if (pairs) {
+        const double2* h2 = reinterpret_cast<const double2*>(hx);
+        const double2* x2 = reinterpret_cast<const double2*>(x);
+        double2* r2 = reinterpret_cast<double2*>(rout);
+        for (int i = threadIdx.x; i < n / 2; i += 256) {
+          const double2 h = h2[i], v = x2[i];
+          const double ra = h.x - th * v.x, rb = h.y - th * v.y;
+          acc += ra * ra;
+          acc += rb * rb;
+          if (rout) r2[i] = double2{ra, rb};
+        }
+      } else {
+        for (int i = threadIdx.x; i < n; i += 256) {
+          double r = hx[i] - th * x[i];
+          acc += r * r;
+          if (rout) rout[i] = r;
+        }
       }
       double nr = sqrt(block_sum256(acc, red));
       if (threadIdx.x == 0) d.norms[j] = nr;

@@ -41,6 +41,8 @@ struct FilterDesc {
   const void* pack;
   int pkm, steps;
   const double* Ediag;
+  const double* EA;  // the module energies: Ediag[a k_B + b] = EA[a] + EB[b]
+  const double* EB;
   const double* E;
   const double* X;
   double* out;

@@ -864,7 +864,8 @@ void fused_filter(Batch& B, const std::vector<BP*>& L, int P, int outr) {
       FilterDesc d{};
       d.kA = op.kA; d.kB = op.kB; d.T = op.T; d.nv = cn; d.vbase = tv;
       d.pack = op.pack[prec]; d.pkm = op.pkm; d.steps = steps;
-      d.Ediag = op.Ediag; d.E = defect_of(p); d.X = role_ptr(p, 3); d.out = p->Y[outr];
+      d.Ediag = op.Ediag; d.EA = op.EA; d.EB = op.EB;
+      d.E = defect_of(p); d.X = role_ptr(p, 3); d.out = p->Y[outr];
       d.sc = B.da->add(sc);
       d.phi = B.da->add(phi);
       d.r0 = p->sigma1 / p->e;

@@ -76,12 +76,13 @@ def _per_dispatch(rows, counter: str):
 
 
 def _kron_key(name: str):
-    """'kron_stream_kernel:fp32' style key of a Kronecker launch (the tiled kernel is
-    counted with the streaming one: both are the one-step matvec)."""
-    m = re.search(r"kron_(stream|batched|filter)_kernel<(\d)", name)
+    """'kron_step:fp64' or 'kron_filter_kernel:fp32' style key of a Kronecker launch: the
+    one-step matvec (streaming or tiled kernel) or the whole fused filter (64- or
+    96-wide form), by precision, as the benchmark's event timing groups them."""
+    m = re.search(r"kron_(stream|batched|filter|filter_wide)_kernel<(\d)", name)
     if not m:
         return None
-    kind = "kron_filter_kernel" if m.group(1) == "filter" else "kron_stream_kernel"
+    kind = "kron_filter_kernel" if m.group(1).startswith("filter") else "kron_step"
     return f"{kind}:{PREC_NAMES.get(m.group(2))}"
 
 
