@@ -1611,7 +1611,9 @@ void tune_store(const std::string& key, int v) {
 }  // namespace
 
 static bool tuning_enabled = true;
+static thread_local bool thread_tuning = true;
 void kron_set_tuning(bool on) { tuning_enabled = on; }
+void kron_thread_tuning(bool on) { thread_tuning = on; }
 
 int kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
                  int precision, int T, long total_vecs, bool may_tune, bool strict) {
@@ -1670,7 +1672,7 @@ int kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, 
     auto it = tune_cache.find(key);
     if (it != tune_cache.end() && valid(it->second)) ct = it->second;
   }
-  if (ct < 0 && (!tuning_enabled || !may_tune)) ct = valid(8) ? 8 : (valid(2) ? 2 : 1);
+  if (ct < 0 && (!tuning_enabled || !may_tune || !thread_tuning)) ct = valid(8) ? 8 : (valid(2) ? 2 : 1);
   if (ct < 0) {
     hipEvent_t e0, e1;
     hipEventCreate(&e0);

@@ -139,6 +139,9 @@ struct StartDesc {
 int kron_batched(hipStream_t s, const KronDesc* d, int P, int kBmax, int nvmax, int kAmax,
                  int precision, int T, long total_vecs, bool may_tune = true, bool strict = false);
 void kron_set_tuning(bool on);
+// Per host thread: off while a stream is being captured into a graph (untuned shapes
+// then take the default variant instead of timing candidates).
+void kron_thread_tuning(bool on);
 int kron_max_k();
 // Operators of one coupling in the streaming kernel's layout: for term t, the
 // pkm x pkm zero-padded tiles O_B^t and c_t O_A^t (in that order, row-major) in the

@@ -100,15 +100,25 @@ struct DescArena {
   T* add(const std::vector<T>& v) {
     return add(v.data(), v.size());
   }
-  // Launches are queued and issued after one upload of everything added so far.
+  // Launches are queued and issued after one upload of everything added so far. While
+  // `hold` is set (an iteration being built for graph replay) flushes wait for the one
+  // at its end.
   std::vector<std::function<void()>> pending;
+  bool hold = false;
   void defer(std::function<void()> f) { pending.push_back(std::move(f)); }
   void flush() {
+    if (hold) return;
     if (used > flushed)
       RMC_HIP(hipMemcpyAsync(dev + flushed, host + flushed, used - flushed,
                              hipMemcpyHostToDevice, st));
     flushed = used;
     for (auto& f : pending) f();
+    pending.clear();
+  }
+  // Replay of an already captured iteration: its graph copies the (rewritten, equally
+  // laid out) host tables and runs the same launches, so the queued ones are dropped.
+  void drop() {
+    flushed = used;
     pending.clear();
   }
   void reset() { used = flushed = 0; }  // only after the stream has been synchronised
@@ -1157,6 +1167,23 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
 
   const double tol = o.tol > 0 ? o.tol : 1e-13;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  // RMC_GRAPHS=1: each outer iteration's launch sequence (filter, orthonormalisation,
+  // Rayleigh-Ritz, with the upload of their tables) is captured once per shape (every
+  // active problem's index, row count, lock count, precision, and the filter degree) and
+  // replayed when the shape repeats; the tables are rebuilt on the host each iteration
+  // in the same layout and the graph's copy node uploads them. No memset is captured.
+  static const bool use_graphs = [] {
+    const char* e = getenv("RMC_GRAPHS");
+    return e && atoi(e) != 0;
+  }();
+  std::map<std::string, hipGraphExec_t> graphs;
+  struct GraphsGuard {
+    std::map<std::string, hipGraphExec_t>& g;
+    ~GraphsGuard() {
+      for (auto& kv : g) (void)hipGraphExecDestroy(kv.second);
+    }
+  } graphs_guard{graphs};
+  long graph_hits = 0, graph_misses = 0;
   for (;;) {
     read_state(B);
     if (ortho_fixup(B, probs)) read_state(B);
@@ -1178,6 +1205,18 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
     }
     upd.reset();
     if (act.empty()) break;
+    // (not on the legacy null stream, which cannot be captured)
+    const bool graph_iter = use_graphs && !ctx->prof && B.st != nullptr;
+    std::string sig;
+    if (graph_iter) {
+      sig.reserve(act.size() * 24);
+      for (size_t t = 0; t < act.size(); ++t) {
+        const BP* p = act[t];
+        int v[6] = {ai[t], p->cnt, p->nlock, p->prec, p->deg, p->m};
+        sig.append(reinterpret_cast<const char*>(v), sizeof(v));
+      }
+      B.da->hold = true;
+    }
     // each phase's launches go out as soon as their tables are built, so the host
     // prepares the next phase while the device runs this one
     int r;
@@ -1195,8 +1234,45 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
       RMC_HOST_SCOPE("solve.rr_host");
       rayleigh_ritz(B, act, r, r == 0 ? 1 : 0, false);
     }
+    if (graph_iter) {
+      RMC_HOST_SCOPE("solve.graph");
+      B.da->hold = false;
+      auto it = graphs.find(sig);
+      if (it == graphs.end()) {
+        ++graph_misses;
+        kron_thread_tuning(false);  // no timed candidates while the stream is captured
+        hipGraph_t g = nullptr;
+        // relaxed: the other lanes' threads synchronise their own streams meanwhile
+        hipError_t e = hipStreamBeginCapture(B.st, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+          try {
+            B.da->flush();
+          } catch (...) {
+            (void)hipStreamEndCapture(B.st, &g);
+            if (g) (void)hipGraphDestroy(g);
+            kron_thread_tuning(true);
+            throw;
+          }
+          e = hipStreamEndCapture(B.st, &g);
+        }
+        kron_thread_tuning(true);
+        RMC_HIP(e);
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        RMC_HIP(e);
+        it = graphs.emplace(sig, ex).first;
+      } else {
+        ++graph_hits;
+        B.da->drop();
+      }
+      RMC_HIP(hipGraphLaunch(it->second, B.st));
+    }
     for (BP* p : act) p->iters++;
   }
+  if (use_graphs && getenv("RMC_TRACE_SOLVER"))
+    fprintf(stderr, "[rmc] lane %d: %ld iterations replayed from %zu graphs, %ld captured\n", lane,
+            graph_hits, graphs.size(), graph_misses);
   // final Rayleigh-Ritz over whole blocks (with the stored H X) and FP64 residual check
   std::vector<BP*> fin;
   std::vector<int> fi;

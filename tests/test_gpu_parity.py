@@ -1216,3 +1216,50 @@ def test_error_density_by_leaf_size(ctx):
     say("error density dE0/L (rows L0, columns k=4..32):")
     for L0 in (5, 7, 9):
         say(L0, " ".join(f"{dens[L0, k]:.3e}" for k in ks))
+
+
+def test_graph_replay_of_iterations_matches_eager(ctx):
+    """RMC_GRAPHS=1 captures each outer iteration's launch sequence once per shape and
+    replays it when the shape repeats (the host tables rebuilt in the same layout between
+    replays, with the program's own synchronisations in between): the same energies as
+    the eager launches, and the oracle's, for a batch of random-field chains of every k
+    and for a serving mix."""
+    import time
+
+    from paper_2609_02394_amd import rmc
+
+    say("graph replay")
+    gold = _golden("recursion_rfheis_subset.txt")
+    jobs_all = W.rfheis_batch(512)
+    idx = sorted(int(n.split(":")[1]) for n in gold)[::2]
+    chains = [rmc.job_chain(jobs_all[i]) for i in idx]
+    opts = rmc.default_opts(precision=1)
+    E0, st0, _ = ctx.recurse_batch(chains, opts=opts)
+    os.environ["RMC_GRAPHS"] = "1"
+    try:
+        for rep in range(2):
+            E1, st1, top = ctx.recurse_batch(chains, opts=opts)
+            assert top == rmc.OK and all(x == rmc.OK for x in st1)
+            assert rel_err(E1, E0) <= 1e-12, rep
+            for t, i in enumerate(idx):
+                assert rel_err(E1[t, :8], gold[f"rfheis:{i}"]["E"]) <= 1e-8
+        jobs = [j for _, j in W.serving_stream(12)]
+        alone = [ctx.recurse(*rmc.job_chain(j))[0] for j in jobs]
+        ctx.serve_start(opts=opts, max_inflight=8)
+        try:
+            ids = [ctx.submit(*rmc.job_chain(j)) for j in jobs]
+            got = {}
+            t0 = time.time()
+            while len(got) < len(ids) and time.time() - t0 < 240:
+                for jid, j in zip(ids, jobs):
+                    if jid not in got:
+                        done, e, st, lat = ctx.poll(jid, j.q)
+                        if done:
+                            got[jid] = (e, st)
+                time.sleep(0.002)
+        finally:
+            ctx.serve_stop()
+    finally:
+        os.environ.pop("RMC_GRAPHS", None)
+    for jid, a in zip(ids, alone):
+        assert got[jid][1] == rmc.OK and rel_err(got[jid][0], a) <= 1e-8
