@@ -243,8 +243,10 @@ rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_job_desc* jobs,
  * at most max_inflight are in flight and their estimated device memory fits in
  * mem_budget bytes (0 = half the arena), then advances every job in flight by
  * one tree level in one batched level solve, so jobs that arrive while others run
- * share the device with them. Module bases and projected operators stay
- * device-resident between a job's levels. */
+ * share the device with them. A step solves the merges first and the leaves last;
+ * jobs that arrive during its merges are admitted (by the same rule) before its
+ * leaf phase and have their leaves solved in that step. Module bases and projected
+ * operators stay device-resident between a job's levels. */
 rmc_status rmc_serve_start(rmc_ctx* ctx, const rmc_solve_opts* opts, int max_inflight,
                            size_t mem_budget);
 /* Queue a job (the descriptor, its tree or chain and their terms are copied); never

@@ -463,6 +463,9 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
   // chunk instead of being held in registers (24 doubles a lane would spill)
   constexpr bool YG = P == 0 && KM > 64;
   constexpr bool YPF = KM <= 96 && !YG;
+  // the epilogue's loads of a column tile issued together (where the registers allow;
+  // elsewhere each element's loads go out alone)
+  constexpr bool EPB = YG || EPF;
   static_assert(RTM % NWC == 0 && NG * 4 * NT == KM * KM, "tile split");
   extern __shared__ char smem_raw[];
   lt* Bs = reinterpret_cast<lt*>(smem_raw);
@@ -580,16 +583,29 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
 #pragma unroll
       for (int c = 0; c < CPW; ++c) z[c] = accT{0, 0, 0, 0};
       if constexpr (YG) {
+        // the row's next chunk is in flight while the current one computes (two buffers
+        // taken in turn, so no register copy waits for a load); the loads are
+        // unconditional: a padded entry, or the chunk after the last (k >= KM >= kB),
+        // reads the row's first element, which is dropped
+        static_assert(NCH % 2 == 0, "chunk pairs");
         const int kA = d->kA, kB = d->kB;
         const int a = rt * 16 + l16;
-        gptr<double> Yr = gview(d->Y) + (long)j * kA * kB + (long)(a < kA ? a : 0) * kB;
-#pragma unroll 2
-        for (int u = 0; u < NCH; ++u) {
+        const bool ain = a < kA;
+        gptr<double> Yr = gview(d->Y) + (long)j * kA * kB + (long)(ain ? a : 0) * kB;
+        double y0[KR], y1[KR];
+        auto ld = [&](double* yb, int u) {
+#pragma unroll
+          for (int x = 0; x < KR; ++x) {
+            const int k = CH * u + KR * g + x;
+            yb[x] = Yr[k < kB ? k : 0];
+          }
+        };
+        auto mm = [&](const double* yb, int u) {
           lt ya[KR];
 #pragma unroll
           for (int x = 0; x < KR; ++x) {
             const int k = CH * u + KR * g + x;
-            ya[x] = (a < kA && k < kB) ? Yr[k] : 0.0;
+            ya[x] = (ain && k < kB) ? yb[x] : 0.0;
           }
 #pragma unroll
           for (int c = 0; c < CPW; ++c) {
@@ -597,6 +613,16 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
             b.load(Bs + ((c0 + c) * 16 + l16) * PW, u, g);
             mma_frag<P>(z[c], ya, b);
           }
+        };
+        ld(y0, 0);
+#pragma unroll 1
+        for (int u = 0; u < NCH; u += 2) {
+          ld(y1, u + 1);
+          __builtin_amdgcn_sched_barrier(0);  // the scheduler keeps the loads ahead
+          mm(y0, u);
+          ld(y0, u + 2);
+          __builtin_amdgcn_sched_barrier(0);
+          mm(y1, u + 1);
         }
       } else {
 #pragma unroll
@@ -677,8 +703,42 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
       gptr<double> Ej = d->E ? gview(d->E) + (long)j * n : nullptr;
       const double ph = d->E ? s1 * d->phi[j] : 0.0;
       gptr_w<double> oj = gview_w(d->out) + (long)j * n;
+      // one column tile at a time: its operands are loaded unconditionally (a padded
+      // element reads element 0 and drops it), so they issue together
 #pragma unroll
-      for (int c = 0; c < CPW; ++c) {
+      for (int c = 0; c < (EPB ? CPW : 0); ++c) {
+        const int col = (c0 + c) * 16 + l16;
+        double yv[4], dv[4], xv[4], ev[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rt * 16 + acc_row<P>(g, r);
+          const long idx = (row < kA && col < kB) ? (long)row * kB + col : 0;
+          yv[r] = Yj[idx];
+          dv[r] = Ed[idx];
+          if constexpr (EPF) {
+            xv[r] = exq[c][r];
+            ev[r] = eeq[c][r];
+          } else {
+            xv[r] = Xp ? Xp[idx] : 0.0;
+            ev[r] = Ej ? Ej[idx] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rt * 16 + acc_row<P>(g, r);
+          if (row < kA && col < kB) {
+            const long idx = (long)row * kB + col;
+            const double y = yv[r];
+            // explicit fused multiply-adds: the fused filter kernel rounds the same way
+            double o = fma(s1, fma(dv[r], y, (double)acc[c][r]), s2 * y);
+            if (Xp) o = fma(s3, xv[r], o);
+            if (Ej) o = fma(ph, ev[r], o);
+            oj[idx] = o;
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < (EPB ? 0 : CPW); ++c) {
         const int col = (c0 + c) * 16 + l16;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -686,15 +746,9 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
           if (row < kA && col < kB) {
             const long idx = (long)row * kB + col;
             const double y = Yj[idx];
-            // explicit fused multiply-adds: the fused filter kernel rounds the same way
             double o = fma(s1, fma(Ed[idx], y, (double)acc[c][r]), s2 * y);
-            if constexpr (EPF) {
-              if (Xp) o = fma(s3, exq[c][r], o);
-              if (Ej) o = fma(ph, eeq[c][r], o);
-            } else {
-              if (Xp) o = fma(s3, Xp[idx], o);
-              if (Ej) o = fma(ph, Ej[idx], o);
-            }
+            if (Xp) o = fma(s3, Xp[idx], o);
+            if (Ej) o = fma(ph, Ej[idx], o);
             oj[idx] = o;
           }
         }
@@ -857,10 +911,23 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
         const int row = rt * 16 + acc_row<P>(g, r);
         const bool in = row < kA && col < kB;
         idx[c][r] = in ? row * kB + col : -1;
-        const double e0 = in ? Ej[idx[c][r]] : 0.0;
+        // unconditional loads (a padded element reads element 0 and discards it), so the
+        // group issues together and costs one round trip
+        Dc[c][r] = Ej[in ? idx[c][r] : 0];
+        if constexpr (HOLD) Ed[c][r] = Edg[in ? idx[c][r] : 0];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int col = (c0 + c) * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + acc_row<P>(g, r);
+        const bool in = idx[c][r] >= 0;
+        const double e0 = in ? Dc[c][r] : 0.0;
         if constexpr (HOLD) {
           Ev[c][r] = e0;
-          Ed[c][r] = in ? Edg[idx[c][r]] : 0.0;
+          Ed[c][r] = in ? Ed[c][r] : 0.0;
         }
         Dc[c][r] = d->r0 * e0;
         Dp[c][r] = 0.0;
@@ -967,8 +1034,10 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
             ed = Ed[c][r];
             ev = Ev[c][r];
           } else {
-            ed = in ? Edg[idx[c][r]] : 0.0;
-            ev = in ? Ej[idx[c][r]] : 0.0;
+            ed = Edg[in ? idx[c][r] : 0];
+            ev = Ej[in ? idx[c][r] : 0];
+            ed = in ? ed : 0.0;
+            ev = in ? ev : 0.0;
           }
           double o = fma(s1, fma(ed, Dc[c][r], (double)acc[c][r]), s2 * Dc[c][r]);
           if (k > 1) o = fma(s3, Dp[c][r], o);  // the first step has no previous iterate
@@ -988,12 +1057,17 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
     const double phP = d->phi[(long)steps * nv + j];
     gptr<double> Xj = gview(d->X) + (long)j * n;
     gptr_w<double> oj = gview_w(d->out) + (long)j * n;
+    double xv[CPW][4];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xv[c][r] = Xj[idx[c][r] >= 0 ? idx[c][r] : 0];
 #pragma unroll
     for (int c = 0; c < CPW; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (idx[c][r] >= 0)
-          oj[idx[c][r]] = __dadd_rn(__dmul_rn(phP, Xj[idx[c][r]]), Dc[c][r]);  // as the scale-add kernel
+          oj[idx[c][r]] = __dadd_rn(__dmul_rn(phP, xv[c][r]), Dc[c][r]);  // as the scale-add kernel
     ++j;
   }
 }
@@ -1011,15 +1085,28 @@ __device__ inline T* opaque_uniform_ptr(T* p) {
   const unsigned lo = opaque_uniform((unsigned)v), hi = opaque_uniform((unsigned)(v >> 32));
   return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
 }
+// A raw buffer resource over `bytes` bytes at a wave-uniform address (word 3: the CDNA
+// raw-buffer format). Loads through it take a 32-bit byte offset in a VGPR and the base
+// in SGPRs, so a group of them needs no 64-bit address per element.
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline double buf_f64(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
 
 // Wide tiles (KM = 96): the whole filter as above, operators streamed through LDS, but
 // within the register budget of 12 waves that own three column tiles each: one staging
 // buffer for the next term's tiles (O_B fetched at the start of a term and stored after
-// stage 1, then c O_A fetched and stored after stage 2), the defect re-read from L2 and
-// the diagonal formed from the two module energies in the epilogue, element indices
-// recomputed, and the K loops not unrolled so that few operand fragments are in flight.
-// LDS holds the low-precision iterate, Z^T and the current term's two tiles. Same
-// arithmetic, in the same order, as the per-step kernel's epilogue.
+// stage 1, then c O_A fetched and stored after stage 2), the defect and the diagonal
+// E_A[a] + E_B[b] (the sum the set-up stores, so the same value) re-read from L2 every
+// step, element indices recomputed, and the K loops not unrolled so that few operand
+// fragments are in flight. LDS holds the low-precision iterate, Z^T and the current
+// term's two tiles. The epilogue's loads go out unconditionally (a padded element reads
+// a valid in-range address and discards it), so they issue together and cost one round
+// trip, not one each. Same arithmetic, in the same
+// order, as the per-step kernel's epilogue. (The staging loads stay conditional: a select
+// on their value would wait for them before the stage they are meant to overlap.)
 template <int P, int KM, int CPW>
 __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_wide_kernel(
     const FilterDesc* __restrict__ descs, int P_, long V, int G) {
@@ -1040,14 +1127,14 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
   lt* Bs = Zt + TILE;
   lt* As = Bs + TILE;
   gv pf[NG];
-  // tile `which` (0: O_B, 1: c O_A) of term tt of problem e into pf (zeros past pkm)
-  auto fetch = [&](const FilterDesc* e, int tt, int which) {
-    const int pkm = e->pkm;
-    gptr<lt> base = gview(static_cast<const lt*>(e->pack)) + ((long)tt * 2 + which) * pkm * pkm;
+  // tile `which` (0: O_B, 1: c O_A) of term tt of a pack with tile size pkm into pf
+  // (zeros past pkm)
+  auto fetch = [&](const lt* pack, int pkm, int tt, int which) {
+    gptr<lt> base = gview(pack) + ((long)tt * 2 + which) * pkm * pkm;
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
       const int q = (int)threadIdx.x + i * NT, r = q / (KM / 4), cc = (q % (KM / 4)) * 4;
-      gv x = gv{0, 0, 0, 0};
+      gv x = gv{0, 0, 0, 0};  // (a branch, not a select: no wait before the stage)
       if (r < pkm && cc < pkm) x = *reinterpret_cast<gptr<gv>>(base + r * pkm + cc);
       pf[i] = x;
     }
@@ -1091,6 +1178,22 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
     // a filter has degree >= 2, so at least one step (the host never builds fewer); said
     // here so that the compiler keeps no copy of the starting iterate for an empty loop
     __builtin_assume(steps >= 1);
+    const lt* packd = opaque_uniform_ptr(static_cast<const lt*>(d->pack));
+    const int pkmd = (int)opaque_uniform((unsigned)d->pkm);
+    // the problem of the next vector of this workgroup, whose term-0 tiles the last
+    // term of this vector stages
+    int pn = p, Tn = 0, pkmn = 0;
+    const lt* packn = nullptr;
+    if (v + 1 < v1) {
+      int jn = j + 1;
+      while (jn >= descs[pn].nv) {
+        jn = 0;
+        ++pn;
+      }
+      Tn = descs[pn].T;
+      packn = opaque_uniform_ptr(static_cast<const lt*>(descs[pn].pack));
+      pkmn = (int)opaque_uniform((unsigned)descs[pn].pkm);
+    }
     const long n = (long)kA * kB;
     gptr<double> Ej = gview(d->E) + (long)j * n;
     double Dc[CPW][4], Dp[CPW][4];
@@ -1101,16 +1204,25 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
       for (int r = 0; r < 4; ++r) {
         const int row = rt * 16 + acc_row<P>(g, r);
         const bool in = row < kA && col < kB;
-        const double e0 = in ? Ej[row * kB + col] : 0.0;
-        Dc[c][r] = d->r0 * e0;
+        Dc[c][r] = Ej[in ? row * kB + col : 0];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int col = (c0 + c) * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + acc_row<P>(g, r);
+        const bool in = row < kA && col < kB;
+        Dc[c][r] = d->r0 * (in ? Dc[c][r] : 0.0);
         Dp[c][r] = 0.0;
         Ys[row * PW + col] = to_lt<P>(Dc[c][r]);
       }
     }
     if (T > 0 && staged != p) {  // every wave is past the previous vector's last reads
-      fetch(d, 0, 0);
+      fetch(packd, pkmd, 0, 0);
       put(Bs);
-      fetch(d, 0, 1);
+      fetch(packd, pkmd, 0, 1);
       put(As);
       staged = p;
     }
@@ -1125,23 +1237,25 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
         // the tiles the next term uses: this problem's next term, its term 0 for the
         // next step, or the next vector's problem; nothing to stage when they are the
         // ones already in LDS (a single-term problem)
-        const FilterDesc* nd = nullptr;
-        int ntt = 0;
+        const lt* npack = nullptr;
+        int npkm = 0, ntt = 0;
         if (t + 1 < T) {
-          nd = d;
+          npack = packd;
+          npkm = pkmd;
           ntt = t + 1;
         } else if (k < steps) {
-          nd = T > 1 ? d : nullptr;
-        } else if (v + 1 < v1) {
-          int pn = p, jn = j + 1;
-          while (jn >= descs[pn].nv) {
-            jn = 0;
-            ++pn;
+          if (T > 1) {
+            npack = packd;
+            npkm = pkmd;
           }
-          if (descs[pn].T > 0 && !(pn == p && T == 1)) nd = descs + pn;
-          staged = descs[pn].T > 0 ? pn : -1;
+        } else if (v + 1 < v1) {
+          if (Tn > 0 && !(pn == p && T == 1)) {
+            npack = packn;
+            npkm = pkmn;
+          }
+          staged = Tn > 0 ? pn : -1;
         }
-        if (nd) fetch(nd, ntt, 0);
+        if (npack) fetch(npack, npkm, ntt, 0);
         // stage 1: Z = D O_B^T, stored transposed
         accT z[CPW];
 #pragma unroll
@@ -1170,9 +1284,9 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
           }
         }
         __syncthreads();
-        if (nd) {  // every wave is past stage 1's reads of O_B
+        if (npack) {  // every wave is past stage 1's reads of O_B
           put(Bs);
-          fetch(nd, ntt, 1);
+          fetch(npack, npkm, ntt, 1);
         }
         // stage 2: acc += c O_A Z
 #pragma unroll 1
@@ -1187,17 +1301,33 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
           }
         }
         __syncthreads();  // every wave is past stage 2's reads of c O_A and Z^T
-        if (nd) put(As);  // visible to the next stage 2 after the next barrier
+        if (npack) put(As);  // visible to the next stage 2 after the next barrier
       }
-      // the per-step kernel's epilogue on the register-resident iterates; the defect
-      // comes from L2 through 32-bit offsets from a uniform base, laundered every step so
-      // that the compiler does not keep a 64-bit address per element live across the step
-      // loop, and the diagonal E_A[a] + E_B[b] is formed from the two module energies (the
-      // same sum the set-up stored, so the same value)
-      const char* eb = opaque_uniform_ptr(reinterpret_cast<const char*>(d->E) + (size_t)j * n * sizeof(double));
-      const double* EAs = opaque_uniform_ptr(d->EA);
-      const double* EBs = opaque_uniform_ptr(d->EB);
+      // the per-step kernel's epilogue on the register-resident iterates; the defect and
+      // the module energies come from L2 through buffer loads (uniform bases, 32-bit
+      // offsets), all issued before the first use
+      const __amdgpu_buffer_rsrc_t rE = buf_rsrc(opaque_uniform_ptr(d->E + (size_t)j * n), (unsigned)n * 8u);
+      const __amdgpu_buffer_rsrc_t rA = buf_rsrc(opaque_uniform_ptr(d->EA), (unsigned)kA * 8u);
+      const __amdgpu_buffer_rsrc_t rB = buf_rsrc(opaque_uniform_ptr(d->EB), (unsigned)kB * 8u);
+      // (laundered: offsets recomputed every step rather than kept live across the loop)
       const int kBs = (int)opaque_uniform((unsigned)kB);
+      double ev[CPW][4], ea[4], ebv[CPW];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + acc_row<P>(g, r);
+        ea[r] = buf_f64(rA, (unsigned)(row < kA ? row : 0) * 8u);
+      }
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int col = (c0 + c) * 16 + l16;
+        ebv[c] = buf_f64(rB, (unsigned)(col < kB ? col : 0) * 8u);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rt * 16 + acc_row<P>(g, r);
+          const bool in = row < kA && col < kB;
+          ev[c][r] = buf_f64(rE, in ? (unsigned)(row * kBs + col) * 8u : 0u);
+        }
+      }
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const int col = (c0 + c) * 16 + l16;
@@ -1205,12 +1335,11 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
         for (int r = 0; r < 4; ++r) {
           const int row = rt * 16 + acc_row<P>(g, r);
           const bool in = row < kA && col < kB;
-          const unsigned off = (unsigned)(row * kBs + col) * 8u;
-          const double ed = in ? gview(EAs)[row] + gview(EBs)[col] : 0.0;
-          const double ev = in ? *reinterpret_cast<gptr<double>>(gview(eb) + off) : 0.0;
+          const double ed = in ? ea[r] + ebv[c] : 0.0;
+          const double e1 = in ? ev[c][r] : 0.0;
           double o = fma(s1, fma(ed, Dc[c][r], (double)acc[c][r]), s2 * Dc[c][r]);
           if (k > 1) o = fma(s3, Dp[c][r], o);  // the first step has no previous iterate
-          o = fma(ph, ev, o);
+          o = fma(ph, e1, o);
           Dp[c][r] = Dc[c][r];
           Dc[c][r] = in ? o : 0.0;
         }
@@ -1224,11 +1353,20 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
         __syncthreads();
       }
     }
-    // out_j = phi_P X_j + D_P (as the scale-add kernel rounds), from laundered bases
+    // out_j = phi_P X_j + D_P (as the scale-add kernel rounds)
     const double phP = d->phi[(long)steps * nv + j];
-    const char* xb = opaque_uniform_ptr(reinterpret_cast<const char*>(d->X) + (size_t)j * n * sizeof(double));
+    const __amdgpu_buffer_rsrc_t rX = buf_rsrc(opaque_uniform_ptr(d->X + (size_t)j * n), (unsigned)n * 8u);
     char* ob = opaque_uniform_ptr(reinterpret_cast<char*>(d->out) + (size_t)j * n * sizeof(double));
-    const int kBs = (int)opaque_uniform((unsigned)kB);
+    double xv[CPW][4];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int col = (c0 + c) * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + acc_row<P>(g, r);
+        xv[c][r] = buf_f64(rX, row < kA && col < kB ? (unsigned)(row * kB + col) * 8u : 0u);
+      }
+    }
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
       const int col = (c0 + c) * 16 + l16;
@@ -1236,9 +1374,8 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
       for (int r = 0; r < 4; ++r) {
         const int row = rt * 16 + acc_row<P>(g, r);
         if (row < kA && col < kB) {
-          const unsigned off = (unsigned)(row * kBs + col) * 8u;
-          const double x = *reinterpret_cast<gptr<double>>(gview(xb) + off);
-          *reinterpret_cast<gptr_w<double>>(gview_w(ob) + off) = __dadd_rn(__dmul_rn(phP, x), Dc[c][r]);
+          const unsigned off = (unsigned)(row * kB + col) * 8u;
+          *reinterpret_cast<gptr_w<double>>(gview_w(ob) + off) = __dadd_rn(__dmul_rn(phP, xv[c][r]), Dc[c][r]);
         }
       }
     }

@@ -14,6 +14,7 @@
 #include <condition_variable>
 #include <cstdio>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -382,26 +383,33 @@ struct Task {
   int node;
 };
 
-// Runs one level (the next level of every job in `jobs`) as batched solves.
-void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o) {
+// Runs one level (the next level of every job in `jobs`) as batched solves: the merges
+// first, then the leaves. `admit`, if set, is called between the two and may append
+// jobs that have not started; their leaves join this round's leaf solve.
+void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o,
+               const std::function<void(std::vector<JobRun*>&)>& admit = {}) {
   std::unique_ptr<HostScope> tasks_scope(new HostScope("level.tasks"));
   std::vector<Task> leaf_t, merge_t, reused;
-  for (JobRun* J : jobs) {
-    if (J->done) continue;
-    const int L = J->level;
-    std::vector<char> seen(J->P.n_keys, 0);
-    for (size_t i = 0; i < J->P.nodes.size(); ++i) {
-      const Node& nd = J->P.nodes[i];
-      if (nd.level != L) continue;
-      const bool single = (int)i == J->P.root && nd.kind == 0;
-      if (!nd.root && !single && (J->by_key[nd.key] || seen[nd.key])) {
-        reused.push_back(Task{J, (int)i});
-        continue;
+  auto collect = [&](size_t from) {
+    for (size_t ji = from; ji < jobs.size(); ++ji) {
+      JobRun* J = jobs[ji];
+      if (J->done) continue;
+      const int L = J->level;
+      std::vector<char> seen(J->P.n_keys, 0);
+      for (size_t i = 0; i < J->P.nodes.size(); ++i) {
+        const Node& nd = J->P.nodes[i];
+        if (nd.level != L) continue;
+        const bool single = (int)i == J->P.root && nd.kind == 0;
+        if (!nd.root && !single && (J->by_key[nd.key] || seen[nd.key])) {
+          reused.push_back(Task{J, (int)i});
+          continue;
+        }
+        seen[nd.key] = 1;
+        (nd.kind == 0 ? leaf_t : merge_t).push_back(Task{J, (int)i});
       }
-      seen[nd.key] = 1;
-      (nd.kind == 0 ? leaf_t : merge_t).push_back(Task{J, (int)i});
     }
-  }
+  };
+  collect(0);
   // memory-admitted chunks
   auto chunks = [&](std::vector<Task>& T, auto size_of) {
     std::vector<std::vector<Task>> out;
@@ -452,62 +460,6 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
     }
     api_project_ops_batch(ctx, ms, so);
   };
-  // leaves
-  for (auto& ch : chunks(leaf_t, [&](const Task& t) {
-         const Node& nd = t.J->P.nodes[t.node];
-         const int D = 1 << nd.width;
-         return task_bytes(D, std::min(D, nd.k + 1)) + (size_t)D * D * 8;
-       })) {
-    auto solve = [&](std::vector<Task>& C) {
-      std::vector<rmc_leaf_desc> lds(C.size());
-      std::vector<const rmc_leaf_desc*> lp;
-      std::vector<int> ks, qo;
-      for (size_t i = 0; i < C.size(); ++i) {
-        const Node& nd = C[i].J->P.nodes[C[i].node];
-        lds[i] = rmc_leaf_desc{nd.width, (int)nd.terms.size(), nd.terms.data()};
-        lp.push_back(&lds[i]);
-        ks.push_back(nd.k);
-        const bool single = C[i].node == C[i].J->P.root;
-        qo.push_back(single ? C[i].J->P.q : 0);
-      }
-      std::vector<std::vector<double>> ev;
-      std::vector<rmc_level_report> reps;
-      std::vector<rmc_module*> mods;
-      try {
-        mods = api_leaf_solve_batch(ctx, lp, ks, qo, o, ev, &reps);
-      } catch (const Error& e) {
-        if (e.code == RMC_ERR_NOCONV)  // a single-leaf job's best Ritz values
-          for (size_t i = 0; i < C.size() && i < ev.size(); ++i)
-            if (qo[i] > 0 && (int)ev[i].size() >= qo[i])
-              for (int q = 0; q < qo[i]; ++q) C[i].J->e[q] = ev[i][q];
-        throw;
-      }
-      project_new(C, mods);
-      for (size_t i = 0; i < C.size(); ++i) {
-        reps[i].kind = qo[i] > 0 ? 2 : 0;
-        after_module(C[i].J, C[i].node, mods[i], reps[i], ev[i]);
-      }
-    };
-    try {
-      solve(ch);
-    } catch (const Error& e) {
-      if (getenv("RMC_TRACE_SOLVER"))
-        fprintf(stderr, "[rmc] level chunk of %zu tasks failed: %s\n", ch.size(), e.what());
-      if (ch.size() == 1) {
-        job_fail(ctx, *ch[0].J, e.code, e.what());
-        continue;
-      }
-      for (Task& t : ch) {  // isolate the failing job(s)
-        if (t.J->done) continue;
-        std::vector<Task> one{t};
-        try {
-          solve(one);
-        } catch (const Error& e2) {
-          job_fail(ctx, *t.J, e2.code, e2.what());
-        }
-      }
-    }
-  }
   // merges
   for (auto& ch : chunks(merge_t, [&](const Task& t) {
          const Node& nd = t.J->P.nodes[t.node];
@@ -579,6 +531,68 @@ void run_level(rmc_ctx* ctx, std::vector<JobRun*>& jobs, const rmc_solve_opts& o
         continue;
       }
       for (Task& t : ch) {
+        if (t.J->done) continue;
+        std::vector<Task> one{t};
+        try {
+          solve(one);
+        } catch (const Error& e2) {
+          job_fail(ctx, *t.J, e2.code, e2.what());
+        }
+      }
+    }
+  }
+  // jobs admitted between the merge and leaf phases start with this round's leaves
+  if (admit) {
+    const size_t before = jobs.size();
+    admit(jobs);
+    collect(before);
+  }
+  // leaves
+  for (auto& ch : chunks(leaf_t, [&](const Task& t) {
+         const Node& nd = t.J->P.nodes[t.node];
+         const int D = 1 << nd.width;
+         return task_bytes(D, std::min(D, nd.k + 1)) + (size_t)D * D * 8;
+       })) {
+    auto solve = [&](std::vector<Task>& C) {
+      std::vector<rmc_leaf_desc> lds(C.size());
+      std::vector<const rmc_leaf_desc*> lp;
+      std::vector<int> ks, qo;
+      for (size_t i = 0; i < C.size(); ++i) {
+        const Node& nd = C[i].J->P.nodes[C[i].node];
+        lds[i] = rmc_leaf_desc{nd.width, (int)nd.terms.size(), nd.terms.data()};
+        lp.push_back(&lds[i]);
+        ks.push_back(nd.k);
+        const bool single = C[i].node == C[i].J->P.root;
+        qo.push_back(single ? C[i].J->P.q : 0);
+      }
+      std::vector<std::vector<double>> ev;
+      std::vector<rmc_level_report> reps;
+      std::vector<rmc_module*> mods;
+      try {
+        mods = api_leaf_solve_batch(ctx, lp, ks, qo, o, ev, &reps);
+      } catch (const Error& e) {
+        if (e.code == RMC_ERR_NOCONV)  // a single-leaf job's best Ritz values
+          for (size_t i = 0; i < C.size() && i < ev.size(); ++i)
+            if (qo[i] > 0 && (int)ev[i].size() >= qo[i])
+              for (int q = 0; q < qo[i]; ++q) C[i].J->e[q] = ev[i][q];
+        throw;
+      }
+      project_new(C, mods);
+      for (size_t i = 0; i < C.size(); ++i) {
+        reps[i].kind = qo[i] > 0 ? 2 : 0;
+        after_module(C[i].J, C[i].node, mods[i], reps[i], ev[i]);
+      }
+    };
+    try {
+      solve(ch);
+    } catch (const Error& e) {
+      if (getenv("RMC_TRACE_SOLVER"))
+        fprintf(stderr, "[rmc] level chunk of %zu tasks failed: %s\n", ch.size(), e.what());
+      if (ch.size() == 1) {
+        job_fail(ctx, *ch[0].J, e.code, e.what());
+        continue;
+      }
+      for (Task& t : ch) {  // isolate the failing job(s)
         if (t.J->done) continue;
         std::vector<Task> one{t};
         try {
@@ -699,6 +713,31 @@ size_t job_memory(const Plan& P) {
   return best + keep_bytes;
 }
 
+// Admission (S->mu held): queued jobs go into flight, in arrival order, while a slot is
+// free and their memory estimate fits beside the jobs in flight; a job that could never
+// fit finishes with RMC_ERR_OOM. Returns the admitted jobs.
+std::vector<JobRun*> admit_locked(ServeState* S) {
+  std::vector<JobRun*> out;
+  while (!S->queue.empty() && (int)S->inflight.size() < S->max_inflight) {
+    ServeJob* j = S->queue.front().get();
+    if (j->mem > S->budget) {
+      ServeResult r;
+      r.status = RMC_ERR_OOM;
+      r.latency_ms = now_ms() - j->t_submit;
+      S->done[j->id] = r;
+      S->pending.erase(j->id);
+      S->queue.pop_front();
+      continue;
+    }
+    if (!S->inflight.empty() && S->inflight_mem + j->mem > S->budget) break;
+    S->inflight_mem += j->mem;
+    S->inflight.push_back(std::move(S->queue.front()));
+    S->queue.pop_front();
+    out.push_back(&S->inflight.back()->run);
+  }
+  return out;
+}
+
 void serve_loop(ServeState* S) {
   rmc_ctx* ctx = S->ctx;
   (void)hipSetDevice(ctx->device);
@@ -707,28 +746,17 @@ void serve_loop(ServeState* S) {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->inflight.empty(); });
       if (S->stop && S->queue.empty() && S->inflight.empty()) break;
-      // admission: slots and memory
-      while (!S->queue.empty() && (int)S->inflight.size() < S->max_inflight) {
-        ServeJob* j = S->queue.front().get();
-        if (j->mem > S->budget) {
-          ServeResult r;
-          r.status = RMC_ERR_OOM;
-          r.latency_ms = now_ms() - j->t_submit;
-          S->done[j->id] = r;
-          S->pending.erase(j->id);
-          S->queue.pop_front();
-          continue;
-        }
-        if (!S->inflight.empty() && S->inflight_mem + j->mem > S->budget) break;
-        S->inflight_mem += j->mem;
-        S->inflight.push_back(std::move(S->queue.front()));
-        S->queue.pop_front();
-      }
+      admit_locked(S);
     }
     std::vector<JobRun*> runs;
     for (auto& j : S->inflight) runs.push_back(&j->run);
+    // jobs that arrive while this round's merges run are admitted before its leaf phase
+    auto admit_more = [S](std::vector<JobRun*>& js) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (JobRun* J : admit_locked(S)) js.push_back(J);
+    };
     try {
-      run_level(ctx, runs, S->opts);
+      run_level(ctx, runs, S->opts, admit_more);
     } catch (const Error& e) {
       for (JobRun* J : runs)
         if (!J->done) job_fail(ctx, *J, e.code, e.what());
