@@ -13,6 +13,7 @@
 namespace rmc {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------
 // GEMM: 64x64 output tile per 256-thread workgroup, K staged 16 at a time in LDS.
@@ -323,11 +324,20 @@ void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int
 // chunk (the order of K inside an MFMA step is free), so operands are contiguous
 // LDS reads. Rows past ca / cb are staged as zeros. A slice past n writes zeros.
 // For A A^T only the tiles on and above the diagonal are formed and each is written
-// to both triangles. ROWS bounds ca, cb (LDS is sized for it).
+// to both triangles. ROWS bounds ca, cb (LDS is sized for it). A chunk is loaded in
+// K pairs (16-byte loads when n is even) from clamped addresses, all of a thread's
+// loads at once, and the out-of-block elements are zeroed when stored; for up to 80
+// rows the next chunk is in flight while the current one computes.
 constexpr int GR_KC = 32, GR_PW = GR_KC + 2;
 
 template <int TPW, int ROWS>
 __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ descs, int ks) {
+  constexpr int HK = GR_KC / 2;                  // K pairs per row and chunk
+  constexpr int NPF = (ROWS * HK + 511) / 512;   // pairs staged per thread and operand
+  // the next chunk in flight during the current one (one workgroup a CU from 81 rows
+  // on); for the widest blocks the registers do not allow it and a chunk is loaded and
+  // stored in one go
+  constexpr bool PF = ROWS <= 128;
   __shared__ double As[ROWS * GR_PW];
   __shared__ double Bs[ROWS * GR_PW];
   const GramDesc d = descs[blockIdx.y];
@@ -339,9 +349,13 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
   const int k0 = s * lk, k1 = min(n, k0 + lk);
   const bool same = d.A == d.B && ca == cb;
   const int TA = (ca + 15) / 16, TB = (cb + 15) / 16;
+  const int ra = TA * 16, rb = TB * 16;
   const int nt = same ? TA * (TA + 1) / 2 : TA * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
+  // rows start 16-byte aligned when n is even (the arena aligns blocks to 256 bytes),
+  // and then a chunk's pairs never straddle the slice end (k0, k1 even)
+  const bool pairs = (n & 1) == 0;
   // output tile of slot i: row-major over TA x TB, or the upper triangle row by row
   auto tile_of = [&](int t, int& tr, int& tc) {
     if (!same) { tr = t / TB; tc = t % TB; return; }
@@ -349,28 +363,73 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
     while (left >= TA - r) { left -= TA - r; ++r; }
     tr = r; tc = r + left;
   };
-  d4 acc[TPW];
+  typedef const __attribute__((address_space(1))) double gdbl;  // global, not flat, loads
+  typedef const __attribute__((address_space(1))) d2 gd2;
+  d2 pa[NPF], pb[NPF];
+  auto fetch = [&](const double* M, int c, int kc, d2* st) {
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
-  const double* Bsrc = same ? As : Bs;
-  for (int kc = k0; kc < k1; kc += GR_KC) {
-    const int ra = TA * 16, rb = TB * 16;
-    for (int e = tid; e < ra * GR_KC; e += 512) {
-      const int r = e / GR_KC, c = e % GR_KC, k = kc + c;
-      As[r * GR_PW + c] = (r < ca && k < k1) ? d.A[(long)r * n + k] : 0.0;
-    }
-    if (!same)
-      for (int e = tid; e < rb * GR_KC; e += 512) {
-        const int r = e / GR_KC, c = e % GR_KC, k = kc + c;
-        Bs[r * GR_PW + c] = (r < cb && k < k1) ? d.B[(long)r * n + k] : 0.0;
+    for (int i = 0; i < NPF; ++i) {
+      const int e = tid + i * 512, row = e / HK, k = kc + 2 * (e % HK);
+      gdbl* rp = (gdbl*)M + (long)(row < c ? row : 0) * n;
+      if (pairs) {
+        st[i] = *reinterpret_cast<gd2*>(rp + (k < k1 ? k : 0));
+      } else {
+        st[i].x = rp[k < k1 ? k : 0];
+        st[i].y = rp[k + 1 < k1 ? k + 1 : 0];
       }
+    }
+  };
+  auto put = [&](int c, int r, int kc, const d2* st, double* dst) {
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+      const int e = tid + i * 512, row = e / HK, cp = e % HK, k = kc + 2 * cp;
+      if (row < r) {
+        const bool rin = row < c;
+        d2 v;
+        v.x = rin && k < k1 ? st[i].x : 0.0;
+        v.y = rin && k + 1 < k1 ? st[i].y : 0.0;
+        *reinterpret_cast<d2*>(dst + row * GR_PW + 2 * cp) = v;
+      }
+    }
+  };
+  d4 acc[TPW];
+  int tco[TPW];  // tile coordinates tr << 8 | tc of slot i
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    int tr = 0, tc = 0;
+    if (wave + 8 * i < nt) tile_of(wave + 8 * i, tr, tc);
+    tco[i] = tr << 8 | tc;
+  }
+  const double* Bsrc = same ? As : Bs;
+  if (PF && k0 < k1) {
+    fetch(d.A, ca, k0, pa);
+    if (!same) fetch(d.B, cb, k0, pb);
+    put(ca, ra, k0, pa, As);
+    if (!same) put(cb, rb, k0, pb, Bs);
     __syncthreads();
+  }
+  for (int kc = k0; kc < k1; kc += GR_KC) {
+    const bool more = kc + GR_KC < k1;
+    if constexpr (PF) {
+      if (more) {
+        fetch(d.A, ca, kc + GR_KC, pa);
+        if (!same) fetch(d.B, cb, kc + GR_KC, pb);
+      }
+    } else {  // A, then B through the same registers
+      fetch(d.A, ca, kc, pa);
+      put(ca, ra, kc, pa, As);
+      if (!same) {
+        fetch(d.B, cb, kc, pa);
+        put(cb, rb, kc, pa, Bs);
+      }
+      __syncthreads();
+    }
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int t = wave + 8 * i;
       if (t >= nt) break;
-      int tr, tc;
-      tile_of(t, tr, tc);
+      const int tr = tco[i] >> 8, tc = tco[i] & 255;
       const double* ar = As + (tr * 16 + l16) * GR_PW + 8 * g;
       const double* br = Bsrc + (tc * 16 + l16) * GR_PW + 8 * g;
       double av[8], bv[8];
@@ -385,6 +444,11 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
       for (int st = 0; st < 8; ++st) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st], acc[i], 0, 0, 0);
     }
     __syncthreads();
+    if (PF && more) {
+      put(ca, ra, kc + GR_KC, pa, As);
+      if (!same) put(cb, rb, kc + GR_KC, pb, Bs);
+      __syncthreads();
+    }
   }
   double* out = d.work + (long)s * ca * cb;
 #pragma unroll
