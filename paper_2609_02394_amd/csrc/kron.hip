@@ -101,6 +101,9 @@ struct Mfma<2> {
 // chunk is one MFMA with k = kc + 8g + s (s = 0..7).
 template <int P>
 struct Run;
+// The loads sit in branches whose result is only used after the last of them (the
+// scaling and conversion come afterwards), so a run's loads issue together instead of
+// waiting one by one.
 template <>
 struct Run<0> {
   double v[16];
@@ -110,8 +113,12 @@ struct Run<0> {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int k = kc + 16 * u + 4 * g + s;
-        v[4 * u + s] = (ok && k < K) ? row[k] * scale : 0.0;
+        double x = 0.0;
+        if (ok && k < K) x = row[k];
+        v[4 * u + s] = x;
       }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] *= scale;
   }
   template <class F>
   __device__ void load_fn(F f, int kc, int K, int g) {
@@ -120,7 +127,9 @@ struct Run<0> {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int k = kc + 16 * u + 4 * g + s;
-        v[4 * u + s] = k < K ? f(k) : 0.0;
+        double x = 0.0;
+        if (k < K) x = f(k);
+        v[4 * u + s] = x;
       }
   }
 };
@@ -128,13 +137,17 @@ template <>
 struct Run<1> {
   float v[16];
   __device__ void load(const double* __restrict__ row, bool ok, int kc, int K, double scale, int g) {
+    double x[16];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int k = kc + 16 * u + 4 * g + s;
-        v[4 * u + s] = (float)((ok && k < K) ? row[k] * scale : 0.0);
+        x[4 * u + s] = 0.0;
+        if (ok && k < K) x[4 * u + s] = row[k];
       }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = (float)(x[i] * scale);
   }
   template <class F>
   __device__ void load_fn(F f, int kc, int K, int g) {
@@ -143,7 +156,9 @@ struct Run<1> {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int k = kc + 16 * u + 4 * g + s;
-        v[4 * u + s] = (float)(k < K ? f(k) : 0.0);
+        double x = 0.0;
+        if (k < K) x = f(k);
+        v[4 * u + s] = (float)x;
       }
   }
 };
@@ -151,18 +166,24 @@ template <>
 struct Run<2> {
   bf8 v;
   __device__ void load(const double* __restrict__ row, bool ok, int kc, int K, double scale, int g) {
+    double x[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int k = kc + 8 * g + s;
-      v[s] = (__bf16)(float)((ok && k < K) ? row[k] * scale : 0.0);
+      x[s] = 0.0;
+      if (ok && k < K) x[s] = row[k];
     }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = (__bf16)(float)(x[s] * scale);
   }
   template <class F>
   __device__ void load_fn(F f, int kc, int K, int g) {
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int k = kc + 8 * g + s;
-      v[s] = (__bf16)(float)(k < K ? f(k) : 0.0);
+      double x = 0.0;
+      if (k < K) x = f(k);
+      v[s] = (__bf16)(float)x;
     }
   }
 };
@@ -285,16 +306,29 @@ __device__ void kron_body(const KronDesc& d, int j, int b0, char* smem_raw) {
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
       const int col = b0 + 16 * c + l16;
-      if (col >= kB) continue;
+      // the sub-tile's operands first (loaded together), then the outputs
+      double yv[4], dv[4], xv[4], ev[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rt * 16 + acc_row<P>(g, r);
-        if (row >= kA) continue;
         const long idx = (long)row * kB + col;
-        const double y = Yj[idx];
-        double v = d.s1 * ((double)acc[q][c][r] + d.Ediag[idx] * y) + d.s2 * y;
-        if (Xp) v += d.s3 * Xp[idx];
-        if (Ej) v += ph * Ej[idx];
+        yv[r] = dv[r] = xv[r] = ev[r] = 0.0;
+        if (row < kA && col < kB) {
+          yv[r] = Yj[idx];
+          dv[r] = d.Ediag[idx];
+          if (Xp) xv[r] = Xp[idx];
+          if (Ej) ev[r] = Ej[idx];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + acc_row<P>(g, r);
+        if (row >= kA || col >= kB) continue;
+        const long idx = (long)row * kB + col;
+        const double y = yv[r];
+        double v = d.s1 * ((double)acc[q][c][r] + dv[r] * y) + d.s2 * y;
+        if (Xp) v += d.s3 * xv[r];
+        if (Ej) v += ph * ev[r];
         oj[idx] = v;
       }
     }
