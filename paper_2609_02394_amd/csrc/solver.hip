@@ -835,8 +835,9 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr);
 
 // Whole-filter launches (kron_filter_batched), one per precision: the step scalars
 // and the phi_k rows of every problem are computed on the host up front (the same
-// recurrences as the per-step path) and travel in the descriptor tables.
-void fused_filter(Batch& B, const std::vector<BP*>& L, int P, int outr) {
+// recurrences as the per-step path) and travel in the descriptor tables. Each problem
+// is filtered to its own degree (the kernel takes the step count per descriptor).
+void fused_filter(Batch& B, const std::vector<BP*>& L, int outr) {
   rmc_ctx* ctx = B.ctx;
   // one launch per precision and tile class: problems up to 64 share the 64-wide kernel
   // (smaller operators padded inside its tiles), 96-wide problems take the wide kernel
@@ -851,7 +852,7 @@ void fused_filter(Batch& B, const std::vector<BP*>& L, int P, int outr) {
     for (BP* p : L) {
       if (p->prec != prec || wide(*p->op) != cls_wide) continue;
       const CoupledOp& op = *p->op;
-      const int cn = p->cnt, steps = P - 1;
+      const int cn = p->cnt, steps = p->deg - 1;
       std::vector<double> sc(3 * (size_t)std::max(steps, 1)), phi((size_t)(steps + 1) * cn);
       std::vector<double> pm1(cn, 1.0), pk(cn);
       for (int j = 0; j < cn; ++j) pk[j] = (p->sigma1 / p->e) * (p->th[p->nlock + j] - p->c);
@@ -988,14 +989,15 @@ int filter(Batch& B, const std::vector<BP*>& L) {
       (ok ? Lf : Ls).push_back(p);
     }
   }
-  if (!Lf.empty()) fused_filter(B, Lf, P, outr);
-  for (BP* p : Lf) p->matvecs += p->cnt * (P - 1);
+  if (!Lf.empty()) fused_filter(B, Lf, outr);
+  for (BP* p : Lf) p->matvecs += p->cnt * (p->deg - 1);
   if (Ls.empty()) return outr;
   return filter_steps(B, Ls, P, outr);
 }
 
-// The per-step path of the defect-form filter (one Kronecker launch per step for all
-// problems of L); the result ends in Y[outr].
+// The per-step path of the defect-form filter (one Kronecker launch per step for the
+// problems of L that still have steps to go: each is filtered to its own degree); the
+// result ends in Y[outr].
 int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr) {
   // phi_k at the active Ritz values, one row per filter step, computed on the host just
   // before the step that uses it (so the device starts on the first steps while later
@@ -1025,6 +1027,7 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr) {
     vec_launch(B, VEC_SCALE_ADD, dd);  // D_1
   }
   int prev = -1, cur = 0;
+  std::vector<int> last(NL, 0);  // buffer holding a problem's D at its own degree
   for (int k = 1; k < P; ++k) {
     int nw = -1;
     for (int q = 0; q < 3; ++q)
@@ -1033,9 +1036,12 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr) {
         break;
       }
     Apply a;
+    std::vector<BP*> Lk;
     std::vector<double> sk1v(NL);
     for (size_t i = 0; i < NL; ++i) {
       BP* p = L[i];
+      if (k >= p->deg) continue;  // done: D at its degree sits in Y[last[i]]
+      Lk.push_back(p);
       const double sk = sgp[i], sk1 = 1.0 / (tau2[i] - sk);
       sk1v[i] = sk1;
       a.Y.push_back(role_ptr(p, cur));
@@ -1046,11 +1052,13 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr) {
       a.sc.push_back({2.0 * sk1 / p->e, -2.0 * p->c * sk1 / p->e, prev >= 0 ? -sk * sk1 : 0.0});
       a.cnt.push_back(p->cnt);
     }
-    apply_launch(B, L, a, true);
+    apply_launch(B, Lk, a, true);
     if (k % 8 == 1) B.da->flush();
-    // row k+1 of every problem
+    // row k+1 of every problem still filtering
     for (size_t i = 0; i < NL; ++i) {
       BP* p = L[i];
+      if (k >= p->deg) continue;
+      last[i] = nw;
       const int cn = p->cnt;
       const double sg = sgp[i], sg2 = sk1v[i];
       for (int j = 0; j < cn; ++j) {
@@ -1066,17 +1074,18 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr) {
   }
   RMC_CHECK(outr == ((cur == 0) ? 1 : 0), RMC_ERR_STATE, "filter buffer rotation");
   {
+    // (elementwise, so a problem whose D already sits in Y[outr] is combined in place)
     std::vector<VecDesc> dd;
     for (size_t i = 0; i < L.size(); ++i) {
       BP* p = L[i];
       VecDesc v{};
       v.nv = p->cnt; v.n = p->n; v.out = p->Y[outr]; v.P = role_ptr(p, 3);
-      v.a = rowk[i]; v.asgn = 1.0; v.b = 1.0; v.Q = p->Y[cur];
+      v.a = rowk[i]; v.asgn = 1.0; v.b = 1.0; v.Q = p->Y[last[i]];
       dd.push_back(v);
     }
-    vec_launch(B, VEC_SCALE_ADD, dd);  // Y_P = X phi_P + D_P
+    vec_launch(B, VEC_SCALE_ADD, dd);  // Y_deg = X phi_deg + D_deg
   }
-  for (BP* p : L) p->matvecs += p->cnt * (P - 1);
+  for (BP* p : L) p->matvecs += p->cnt * (p->deg - 1);
   return outr;
 }
 
