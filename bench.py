@@ -119,6 +119,7 @@ def kron_profile(ctx, steps):
             "kernel": KIND_NAMES[kk], "launches": pr["launches"],
             "ms_per_step": pr["ms"] / steps, "avg_launch_us": pr["ms"] * 1e3 / pr["launches"],
             "tflops": pr["flops"] / sec / 1e12 if sec > 0 else 0.0,
+            "frac_of_mfma_peak": (pr["flops"] / sec / 1e12 / PEAK_TFLOPS[name]) if sec > 0 else 0.0,
             "gbs": pr["bytes"] / sec / 1e9 if sec > 0 else 0.0,
             "flops_per_launch": pr["flops"] / pr["launches"],
             "bytes_per_launch": pr["bytes"] / pr["launches"]}
@@ -132,7 +133,10 @@ def roofline(table, workload):
     (kk, name) = max(table, key=lambda k: table[k]["ms"])
     pr = table[(kk, name)]
     sec = pr["ms"] * 1e-3
-    if name == "bf16":  # HBM-bound: the BF16 MFMA roof lies far above the HBM roof
+    # the bound is the roof the kernel's algorithmic intensity meets first: HBM below the
+    # ridge (peak flops / 8 TB/s), the MFMA peak of its precision above it
+    intensity = pr["flops"] / pr["bytes"] if pr["bytes"] > 0 else float("inf")
+    if intensity < PEAK_TFLOPS[name] * 1e12 / (HBM_GBS * 1e9):
         achieved = pr["bytes"] / sec / 1e9 if sec > 0 else 0.0
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_GBS}
@@ -141,7 +145,8 @@ def roofline(table, workload):
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[name],
                 "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[name]}
     roof.update({"traffic": measured_traffic(workload, KINDS[kk], name),
-                 "kernel": KIND_NAMES[kk], "precision": name, "launches": pr["launches"],
+                 "kernel": KIND_NAMES[kk], "precision": name, "intensity_flop_per_byte": intensity,
+                 "launches": pr["launches"],
                  "avg_launch_us": pr["ms"] * 1e3 / max(1, pr["launches"]),
                  "flops_per_launch": pr["flops"] / max(1, pr["launches"]),
                  "bytes_per_launch": pr["bytes"] / max(1, pr["launches"])})
@@ -280,6 +285,17 @@ def bench_rfheis(args, ctx, extras_out):
     meas, table, ktab = timed_batches(ctx, jobs, refs, opts, args.steps, args.warmup, qs)
     oracle_err = max((rel_err(refs[int(n.split(":")[1])], E) for n, (_, _, E) in gold.items()),
                      default=None)
+    # the other precision forms of the same batch, after the timed region (same gate)
+    forms = {}
+    if not args.no_extras:
+        for name, steps in (("bf16", 3), ("fp32", 3), ("fp64", 2)):
+            if name == args.precision:
+                continue
+            o = rmc.default_opts(precision=PREC[name], max_degree=args.max_degree)
+            m, t, kt = timed_batches(ctx, jobs, refs, o, steps, 1, qs)
+            m["roofline"] = roofline(t, "rfheis512")
+            m["kron_by_kernel"] = kt
+            forms[f"rfheis512_{name}"] = m
     plain = None
     if not args.no_plain:
         idx = list(range(0, 512, 16))  # 32 chains, every k
@@ -294,7 +310,7 @@ def bench_rfheis(args, ctx, extras_out):
               "max_rel_err_vs_fp64": meas["max_rel_err"],
               "fp64_path_vs_oracle_golden": {"chains": len(gold), "max_rel_err": oracle_err},
               "jobs_per_step": meas["jobs_per_step"], "accurate_solves": meas["accurate_solves"]}
-    return meas, table, ktab, config, plain, (lambda: cpu_baseline_rfheis(jobs_all))
+    return meas, table, ktab, config, plain, (lambda: cpu_baseline_rfheis(jobs_all)), forms
 
 
 def bench_chain_batch(args, ctx, job, batch, golden=None):
@@ -476,9 +492,9 @@ def main():
         ctx.close()
         return
 
-    cpu_fn, plain = None, None
+    cpu_fn, plain, forms = None, None, {}
     if args.workload == "rfheis512":
-        meas, table, ktab, config, plain, cpu_fn = bench_rfheis(args, ctx, None)
+        meas, table, ktab, config, plain, cpu_fn, forms = bench_rfheis(args, ctx, None)
     else:
         job = W.xxz_chain64() if args.workload == "xxz64" else W.tfim_ladder96()
         gold = read_golden(GOLDEN_LADDER).get("ladder96") if args.workload == "ladder96" else None
@@ -495,7 +511,7 @@ def main():
                   "max_rel_err_vs_fp64": meas["max_rel_err"],
                   "fp64_path_vs_oracle_golden": meas.get("fp64_path_vs_oracle_golden")}
     roof = roofline(table, args.workload)
-    ext = None if args.no_extras else extras(args, ctx)
+    ext = None if args.no_extras else {**forms, **extras(args, ctx)}
     cpu = None
     if not args.no_cpu_baseline and cpu_fn is not None:
         cpu = cpu_fn()
