@@ -8,6 +8,13 @@ counters read for a plain device copy of known size taken in the same runs.
     python -m paper_2609_02394_amd.profiling stats <kernel_stats.csv> <out.md> <title> <command>
     python -m paper_2609_02394_amd.profiling traffic <fetch_dir> <write_dir> <out.json> <out.md> \
         <fetch command> <write command>
+    python -m paper_2609_02394_amd.profiling mfma <counter_dir> <out.md> <title> <command>
+
+The mfma summary reads one counter run with SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE and
+the SQ_INSTS_VALU_MFMA_MOPS_* counters: per kernel, the share of the MI355X SIMDs'
+cycles their MFMA units were busy (the busy cycles summed over the SIMDs over
+GRBM_GUI_ACTIVE / 8 XCDs times 1024 SIMDs), and the MFMA flops (MOPS x 512) per second
+of dispatch time, dispatches being serialised while counters are collected.
 """
 from __future__ import annotations
 
@@ -131,6 +138,51 @@ def traffic_md(t: dict, fetch_cmd: str, write_cmd: str) -> str:
     return "\n".join(lines)
 
 
+SIMDS = 1024  # 256 CUs x 4 SIMDs
+XCDS = 8      # GRBM_GUI_ACTIVE reads summed over the XCDs
+
+
+def mfma(d: str):
+    per_disp = defaultdict(lambda: defaultdict(float))
+    info = {}
+    for r in _counter_rows(d):
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        per_disp[key][r["Counter_Name"]] += float(r["Counter_Value"])
+        info[key] = (_short(r["Kernel_Name"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    per = defaultdict(lambda: defaultdict(float))
+    for key, c in per_disp.items():
+        name, ns = info[key]
+        a = per[name]
+        a["n"] += 1
+        a["ns"] += ns
+        for cn, v in c.items():
+            a[cn] += v
+    rows = []
+    for name, a in per.items():
+        cyc = a.get("GRBM_GUI_ACTIVE", 0.0) / XCDS
+        busy = a.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (cyc * SIMDS) if cyc > 0 else 0.0
+        sec = a["ns"] * 1e-9
+        tf = {p: a.get(f"SQ_INSTS_VALU_MFMA_MOPS_{p}", 0.0) * 512 / sec / 1e12 if sec > 0 else 0.0
+              for p in ("F64", "F32", "BF16")}
+        rows.append((name, int(a["n"]), a["ns"] / 1e6, busy, tf))
+    rows.sort(key=lambda x: -x[2])
+    return rows
+
+
+def mfma_md(rows, title: str, command: str) -> str:
+    out = [f"# {title}", "", "Command (from the repository root on the GPU host):", "", "```",
+           command, "```", "",
+           "Dispatches are serialised while counters are collected, so the times and rates "
+           "are per kernel alone on the chip.", "",
+           "| kernel | dispatches | ms | MFMA busy | FP64 TF/s | FP32 TF/s | BF16 TF/s |",
+           "|---|---|---|---|---|---|---|"]
+    for name, n, ms, busy, tf in rows:
+        out.append(f"| `{name}` | {n} | {ms:.1f} | {100 * busy:.1f}% | {tf['F64']:.1f} | "
+                   f"{tf['F32']:.1f} | {tf['BF16']:.1f} |")
+    out.append("")
+    return "\n".join(out)
+
+
 def main(argv):
     if argv[0] == "stats":
         _, csv_path, out, title, cmd = argv
@@ -141,6 +193,9 @@ def main(argv):
         t["commands"] = [fcmd, wcmd]
         json.dump(t, open(out_json, "w"), indent=1)
         open(out_md, "w").write(traffic_md(t, fcmd, wcmd))
+    elif argv[0] == "mfma":
+        _, d, out, title, cmd = argv
+        open(out, "w").write(mfma_md(mfma(d), title, cmd))
     else:
         raise SystemExit(__doc__)
 
