@@ -323,8 +323,8 @@ void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int
 // its 16x16 output tiles with FP64 MFMA. Lane group g takes the K run 8g..8g+7 of a
 // chunk (the order of K inside an MFMA step is free), so operands are contiguous
 // LDS reads. Rows past ca / cb are staged as zeros. A slice past n writes zeros.
-// For A A^T only the tiles on and above the diagonal are formed and each is written
-// to both triangles. ROWS bounds ca, cb (LDS is sized for it). A chunk is loaded in
+// For A A^T, and for a product the caller declares symmetric (Q^T H Q), only the tiles
+// on and above the diagonal are formed and each is written to both triangles. ROWS bounds ca, cb (LDS is sized for it). A chunk is loaded in
 // K pairs (16-byte loads when n is even) from clamped addresses, all of a thread's
 // loads at once, and the out-of-block elements are zeroed when stored; for up to 80
 // rows the next chunk is in flight while the current one computes.
@@ -348,9 +348,10 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
   lk = ((lk + GR_KC - 1) / GR_KC) * GR_KC;
   const int k0 = s * lk, k1 = min(n, k0 + lk);
   const bool same = d.A == d.B && ca == cb;
+  const bool tri = same || (d.sym && ca == cb);  // upper tiles only, mirrored
   const int TA = (ca + 15) / 16, TB = (cb + 15) / 16;
   const int ra = TA * 16, rb = TB * 16;
-  const int nt = same ? TA * (TA + 1) / 2 : TA * TB;
+  const int nt = tri ? TA * (TA + 1) / 2 : TA * TB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   // rows start 16-byte aligned when n is even (the arena aligns blocks to 256 bytes),
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
   const bool pairs = (n & 1) == 0;
   // output tile of slot i: row-major over TA x TB, or the upper triangle row by row
   auto tile_of = [&](int t, int& tr, int& tc) {
-    if (!same) { tr = t / TB; tc = t % TB; return; }
+    if (!tri) { tr = t / TB; tc = t % TB; return; }
     int r = 0, left = t;
     while (left >= TA - r) { left -= TA - r; ++r; }
     tr = r; tc = r + left;
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
       const int row = tr * 16 + 4 * r + g;  // FP64 accumulator layout
       if (row < ca && col < cb) {
         out[(long)row * cb + col] = acc[i][r];
-        if (same && tr != tc) out[(long)col * cb + row] = acc[i][r];
+        if (tri && tr != tc) out[(long)col * cb + row] = acc[i][r];
       }
     }
   }

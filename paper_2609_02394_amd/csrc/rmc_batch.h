@@ -69,7 +69,7 @@ struct GemmDesc {
 // Gram partials of tall-skinny blocks: work[s][i][j] = sum over K-slice s of
 // A[i][k] B[j][k] (A: ca x n, B: cb x n, row-major, ca, cb <= 192), ks slices.
 struct GramDesc {
-  int ca, cb, n, pad;
+  int ca, cb, n, sym;  // sym: A B^T is symmetric; upper tiles formed and mirrored
   const double* A;
   const double* B;
   double* work;

@@ -463,17 +463,19 @@ void apply_launch(Batch& B, const std::vector<BP*>& L, const Apply& a, bool use_
   }
 }
 
-// Gram partials A B^T (ca x cb per problem) into p->kwork.
+// Gram partials A B^T (ca x cb per problem) into p->kwork. `sym`: the product is
+// symmetric (Q^T H Q), so only the tiles on and above the diagonal are formed and
+// mirrored (the consumer symmetrises the diagonal tiles).
 void gram_launch(Batch& B, const std::vector<BP*>& L, const std::vector<const double*>& Ap,
                  const std::vector<const double*>& Bp, const std::vector<int>& ca,
-                 const std::vector<int>& cb) {
+                 const std::vector<int>& cb, bool sym = false) {
   if (L.empty()) return;
   std::vector<GramDesc> g;
   int cmax = 0;
   for (size_t i = 0; i < L.size(); ++i) {
     BP* p = L[i];
     GramDesc d{};
-    d.ca = ca[i]; d.cb = cb[i]; d.n = p->n;
+    d.ca = ca[i]; d.cb = cb[i]; d.n = p->n; d.sym = sym && ca[i] == cb[i] ? 1 : 0;
     d.A = Ap[i]; d.B = Bp[i]; d.work = p->kwork;
     g.push_back(d);
     cmax = std::max(cmax, std::max(ca[i], cb[i]));
@@ -632,7 +634,7 @@ void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full)
     Bm.push_back(role_ptr(p, w));
     cnt.push_back(p->cnt);
   }
-  gram_launch(B, L, A, Bm, cnt, cnt);
+  gram_launch(B, L, A, Bm, cnt, cnt, true);
   const double* G = reduce_parts(B, L);
   std::vector<EigDesc> ed;
   int mm = 0;
