@@ -331,7 +331,7 @@ void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int
 constexpr int GR_KC = 32, GR_PW = GR_KC + 2;
 
 template <int TPW, int ROWS>
-__global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ descs, int ks) {
+__global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ descs) {
   constexpr int HK = GR_KC / 2;                  // K pairs per row and chunk
   constexpr int NPF = (ROWS * HK + 511) / 512;   // pairs staged per thread and operand
   // the next chunk in flight during the current one (one workgroup a CU from 81 rows
@@ -342,8 +342,8 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
   __shared__ double Bs[ROWS * GR_PW];
   const GramDesc d = descs[blockIdx.y];
   const int ca = d.ca, cb = d.cb, n = d.n;
-  if (ca <= 0 || cb <= 0) return;
-  const int s = blockIdx.x;
+  const int s = blockIdx.x, ks = d.ks;  // (the grid's x is the call's largest ks)
+  if (ca <= 0 || cb <= 0 || s >= ks) return;
   int lk = (n + ks - 1) / ks;
   lk = ((lk + GR_KC - 1) / GR_KC) * GR_KC;
   const int k0 = s * lk, k1 = min(n, k0 + lk);
@@ -472,14 +472,14 @@ __global__ __launch_bounds__(512) void gram_kernel(const GramDesc* __restrict__ 
 
 void gram_batched(hipStream_t s, const GramDesc* d, int P, int ks, int cmax) {
   if (P <= 0 || cmax <= 0) return;
-  if (ks < 1) ks = 1;
+  if (ks < 1) ks = 1;  // the largest ks of the descriptors
   const int t = (cmax + 15) / 16;
   if (t <= 5)
-    hipLaunchKernelGGL((gram_kernel<4, 80>), dim3(ks, P), dim3(512), 0, s, d, ks);
+    hipLaunchKernelGGL((gram_kernel<4, 80>), dim3(ks, P), dim3(512), 0, s, d);
   else if (t <= 8)  // up to 128 rows: 70 KB of LDS, two workgroups a CU
-    hipLaunchKernelGGL((gram_kernel<8, 128>), dim3(ks, P), dim3(512), 0, s, d, ks);
+    hipLaunchKernelGGL((gram_kernel<8, 128>), dim3(ks, P), dim3(512), 0, s, d);
   else
-    hipLaunchKernelGGL((gram_kernel<18, 192>), dim3(ks, P), dim3(512), 0, s, d, ks);
+    hipLaunchKernelGGL((gram_kernel<18, 192>), dim3(ks, P), dim3(512), 0, s, d);
 }
 
 int gemm_pick_ksplit(int M, int N, int K, int batch) {

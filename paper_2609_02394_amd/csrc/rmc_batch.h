@@ -70,6 +70,7 @@ struct GemmDesc {
 // A[i][k] B[j][k] (A: ca x n, B: cb x n, row-major, ca, cb <= 192), ks slices.
 struct GramDesc {
   int ca, cb, n, sym;  // sym: A B^T is symmetric; upper tiles formed and mirrored
+  int ks, pad;         // K-slices of this product: partials ks x ca x cb in work
   const double* A;
   const double* B;
   double* work;

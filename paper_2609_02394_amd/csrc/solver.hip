@@ -128,6 +128,7 @@ struct BP {
   const CoupledOp* op;
   double* Xout;
   int n, m, nev, guard;
+  int ks = 1;  // K-slices of its Gram products (partials summed before use)
   double *X, *HX, *Y[3], *E, *S, *Linv, *Vwork, *Pm, *kwork;
   double *theta, *res;
   double *wPY = nullptr, *wH = nullptr, *wPH = nullptr, *wT = nullptr, *wU = nullptr;  // kind 2, projected
@@ -151,7 +152,6 @@ struct Batch {
   hipStream_t st = nullptr;  // the lane's stream: every launch of this batch goes there
   int lane = 0;
   int kind;
-  int KS = 1;  // split-K of the Gram products
   int mmax = 0, nmax = 0, kAmax = 0, kBmax = 0;
   DescArena* da;
   double* TR = nullptr;  // per-problem theta / res / info block
@@ -471,19 +471,21 @@ void gram_launch(Batch& B, const std::vector<BP*>& L, const std::vector<const do
                  const std::vector<int>& cb, bool sym = false) {
   if (L.empty()) return;
   std::vector<GramDesc> g;
-  int cmax = 0;
+  int cmax = 0, ksmax = 1;
   for (size_t i = 0; i < L.size(); ++i) {
     BP* p = L[i];
     GramDesc d{};
     d.ca = ca[i]; d.cb = cb[i]; d.n = p->n; d.sym = sym && ca[i] == cb[i] ? 1 : 0;
+    d.ks = p->ks;
     d.A = Ap[i]; d.B = Bp[i]; d.work = p->kwork;
     g.push_back(d);
     cmax = std::max(cmax, std::max(ca[i], cb[i]));
+    ksmax = std::max(ksmax, p->ks);
   }
   const GramDesc* dd = B.da->add(g);
   hipStream_t st = B.st;
-  const int P = (int)g.size(), ks = B.KS;
-  B.da->defer([=] { gram_batched(st, dd, P, ks, cmax); });
+  const int P = (int)g.size();
+  B.da->defer([=] { gram_batched(st, dd, P, ksmax, cmax); });
 }
 
 void read_state(Batch& B) {
@@ -504,11 +506,13 @@ int info_of(const Batch& B, int idx, int k) {
 // chip-wide launch, so that the one-workgroup Cholesky and Jacobi kernels read a single
 // matrix instead of every partial; returns null when there is one partial only.
 const double* reduce_parts(Batch& B, const std::vector<BP*>& L) {
-  if (B.KS <= 1 || L.empty()) return nullptr;
+  bool any = false;
+  for (BP* p : L) any = any || p->ks > 1;
+  if (!any) return nullptr;
   std::vector<VecDesc> rd;
   for (BP* p : L) {
     VecDesc v{};
-    v.nv = B.KS; v.n = p->cnt * p->cnt; v.out = p->Pm; v.P = p->kwork;
+    v.nv = p->ks; v.n = p->cnt * p->cnt; v.out = p->Pm; v.P = p->kwork;
     rd.push_back(v);
   }
   vec_launch(B, VEC_REDUCE, rd);
@@ -531,7 +535,7 @@ void cholqr_pass(Batch& B, const std::vector<BP*>& L, int src, int dst, int slot
   int mm = 0;
   for (BP* p : L) {
     CholDesc c{};
-    c.m = p->cnt; c.nparts = G ? 1 : B.KS; c.G = G ? p->Pm : p->kwork; c.pstride = (long)p->cnt * p->cnt;
+    c.m = p->cnt; c.nparts = G ? 1 : p->ks; c.G = G ? p->Pm : p->kwork; c.pstride = (long)p->cnt * p->cnt;
     c.Linv = p->Linv; c.info = p->info + slot;
     c.shift = 11.0 * ((double)p->n * p->cnt + (double)p->cnt * (p->cnt + 1)) * u * p->cnt;
     cd.push_back(c);
@@ -578,7 +582,7 @@ void orthonormalize(Batch& B, const std::vector<BP*>& L, int r) {
       std::vector<GemmDesc> g2;
       for (BP* p : LL) {
         VecDesc v{};
-        v.nv = B.KS; v.n = p->cnt * p->nlock; v.out = p->Pm; v.P = p->kwork;
+        v.nv = p->ks; v.n = p->cnt * p->nlock; v.out = p->Pm; v.P = p->kwork;
         rd.push_back(v);
         GemmDesc e{};
         e.M = p->cnt; e.N = p->n; e.K = p->nlock;
@@ -640,7 +644,7 @@ void rayleigh_ritz(Batch& B, const std::vector<BP*>& L, int q, int w, bool full)
   int mm = 0;
   for (BP* p : L) {
     EigDesc d{};
-    d.m = p->cnt; d.nparts = G ? 1 : B.KS; d.A = G ? p->Pm : p->kwork; d.pstride = (long)p->cnt * p->cnt;
+    d.m = p->cnt; d.nparts = G ? 1 : p->ks; d.A = G ? p->Pm : p->kwork; d.pstride = (long)p->cnt * p->cnt;
     d.evals = p->theta + (full ? 0 : p->nlock); d.V = p->S; d.Vwork = p->Vwork; d.info = p->info + 1;
     ed.push_back(d);
     mm = std::max(mm, p->cnt);
@@ -1120,9 +1124,15 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
   }
   const int P = (int)probs.size();
   std::unique_ptr<HostScope> alloc_scope(new HostScope("solve.alloc"));
-  // K-slices of the Gram products: enough workgroups to cover the chip, slices of at
-  // least 128 columns
-  B.KS = std::max(1, std::min({64, (512 + P - 1) / P, std::max(1, B.nmax / 128)}));
+  // K-slices of the Gram products, per problem and in proportion to its length, so that
+  // every workgroup of a launch gets about the same columns: about 1024 slices over the
+  // call (four workgroups a CU), each at least 128 columns wide, at most 64 a problem
+  {
+    long ntot = 0;
+    for (BP* p : probs) ntot += p->n;
+    const long w = std::max(128L, (ntot + 1023) / 1024);
+    for (BP* p : probs) p->ks = (int)std::max(1L, std::min(64L, ((long)p->n + w - 1) / w));
+  }
   B.trs = 2 * B.mmax + 4;  // theta, res, then room for 8 ints
   B.TR = sc.get<double>((size_t)P * B.trs);
   B.TRh.assign((size_t)P * B.trs, 0.0);
@@ -1137,7 +1147,7 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
     p->Linv = sc.get<double>((size_t)p->m * p->m);
     p->Vwork = sc.get<double>((size_t)p->m * p->m);
     p->Pm = sc.get<double>((size_t)p->m * p->m);
-    p->kwork = sc.get<double>((size_t)B.KS * p->m * p->m);
+    p->kwork = sc.get<double>((size_t)p->ks * p->m * p->m);
     p->theta = B.TR + (size_t)i * B.trs;
     p->res = p->theta + B.mmax;
     p->info = reinterpret_cast<int*>(p->res + B.mmax);
