@@ -499,7 +499,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
   constexpr bool YPF = KM <= 96 && !YG;
   // the epilogue's loads of a column tile issued together (where the registers allow;
   // elsewhere each element's loads go out alone)
-  constexpr bool EPB = YG || EPF;
+  constexpr bool EPB = YG || EPF || KM == 128;
   static_assert(RTM % NWC == 0 && NG * 4 * NT == KM * KM, "tile split");
   extern __shared__ char smem_raw[];
   lt* Bs = reinterpret_cast<lt*>(smem_raw);
