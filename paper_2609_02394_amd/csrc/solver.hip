@@ -1136,29 +1136,41 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
   B.trs = 2 * B.mmax + 4;  // theta, res, then room for 8 ints
   B.TR = sc.get<double>((size_t)P * B.trs);
   B.TRh.assign((size_t)P * B.trs, 0.0);
+  // each problem's buffers carved from one arena block (256-byte aligned pieces), so a
+  // call costs one allocation per problem rather than a dozen (the lanes share the arena)
   for (int i = 0; i < P; ++i) {
     BP* p = probs[i];
-    const size_t mn = (size_t)p->m * p->n;
-    p->X = sc.get<double>(mn);
-    p->HX = sc.get<double>(mn);
-    for (int q = 0; q < 3; ++q) p->Y[q] = sc.get<double>(mn);
-    p->E = sc.get<double>(mn);
-    p->S = sc.get<double>((size_t)p->m * p->m);
-    p->Linv = sc.get<double>((size_t)p->m * p->m);
-    p->Vwork = sc.get<double>((size_t)p->m * p->m);
-    p->Pm = sc.get<double>((size_t)p->m * p->m);
-    p->kwork = sc.get<double>((size_t)p->ks * p->m * p->m);
+    const size_t mn = (size_t)p->m * p->n, mm = (size_t)p->m * p->m;
+    const bool full = p->op->kind == 2 && p->op->PsiA;
+    const size_t DA = full ? (size_t)1 << p->op->nA : 0;
+    auto al = [](size_t doubles) { return (doubles + 31) / 32 * 32; };
+    size_t total = 6 * al(mn) + 4 * al(mm) + al((size_t)p->ks * mm) + al(((size_t)p->m + 1) / 2);
+    if (full) total += 3 * al(mn) + al((size_t)p->m * DA * p->op->kB) + al((size_t)p->m * p->op->kA * p->op->kB);
+    double* blk = sc.get<double>(total);
+    auto take = [&](size_t doubles) {
+      double* q = blk;
+      blk += al(doubles);
+      return q;
+    };
+    p->X = take(mn);
+    p->HX = take(mn);
+    for (int q = 0; q < 3; ++q) p->Y[q] = take(mn);
+    p->E = take(mn);
+    p->S = take(mm);
+    p->Linv = take(mm);
+    p->Vwork = take(mm);
+    p->Pm = take(mm);
+    p->kwork = take((size_t)p->ks * mm);
     p->theta = B.TR + (size_t)i * B.trs;
     p->res = p->theta + B.mmax;
     p->info = reinterpret_cast<int*>(p->res + B.mmax);
-    p->sel = sc.get<int>(p->m);
-    if (p->op->kind == 2 && p->op->PsiA) {
-      const size_t DA = (size_t)1 << p->op->nA;
-      p->wPY = sc.get<double>(mn);
-      p->wH = sc.get<double>(mn);
-      p->wPH = sc.get<double>(mn);
-      p->wT = sc.get<double>((size_t)p->m * DA * p->op->kB);
-      p->wU = sc.get<double>((size_t)p->m * p->op->kA * p->op->kB);
+    p->sel = reinterpret_cast<int*>(take(((size_t)p->m + 1) / 2));
+    if (full) {
+      p->wPY = take(mn);
+      p->wH = take(mn);
+      p->wPH = take(mn);
+      p->wT = take((size_t)p->m * DA * p->op->kB);
+      p->wU = take((size_t)p->m * p->op->kA * p->op->kB);
     }
   }
   RMC_HIP(hipMemsetAsync(B.TR, 0, (size_t)P * B.trs * sizeof(double), B.st));
