@@ -299,15 +299,18 @@ void leaf_blocks_solve(rmc_ctx* ctx, Scratch& sc, const std::vector<const rmc_le
   };
   std::vector<Blk> blks;
   std::vector<int> idx;
+  std::vector<std::pair<int, int>> range(leaves.size(), {0, 0});  // a leaf's blocks
   size_t sq = 0;
   int nbmax = 0;
   for (int i : sel) {
+    range[i].first = (int)blks.size();
     for (const auto& c : leaf_blocks(leaves[i]).comps) {
       blks.push_back({i, (int)c.size(), idx.size(), sq});
       idx.insert(idx.end(), c.begin(), c.end());
       sq += c.size() * c.size();
       nbmax = std::max(nbmax, (int)c.size());
     }
+    range[i].second = (int)blks.size();
   }
   const int NB = (int)blks.size();
   int* idx_dev = sc.get<int>(idx.size());
@@ -340,25 +343,28 @@ void leaf_blocks_solve(rmc_ctx* ctx, Scratch& sc, const std::vector<const rmc_le
   sync(ctx);
   // per leaf: (eigenvalue, block, column) sorted; the lowest nevs rows scattered
   std::vector<BlockScatterDesc> sd;
+  size_t nsd = 0;
+  for (int i : sel) nsd += (size_t)std::max(0, nevs[i]);
+  sd.reserve(nsd);
+  std::vector<std::tuple<double, int, int>> all;
   for (int i : sel) {
-    std::vector<std::tuple<double, int, int>> all;
+    all.clear();
     int sweeps = 0;
     bool ok = true;
-    for (int b = 0; b < NB; ++b) {
-      if (blks[b].leaf != i) continue;
+    for (int b = range[i].first; b < range[i].second; ++b) {
       for (int j = 0; j < blks[b].nb; ++j) all.emplace_back(evh[blks[b].off + j], b, j);
       sweeps += std::abs(infoh[b]);
       ok = ok && infoh[b] >= 0;
     }
-    std::sort(all.begin(), all.end());
+    // only the lowest ne in order (the same order as a full sort: the key is total)
     const int ne = std::min<int>(nevs[i], (int)all.size());
+    std::partial_sort(all.begin(), all.begin() + ne, all.end());
     evals[i].resize(ne);
-    RMC_HIP(hipMemsetAsync(Xs[i], 0, (size_t)ne * ops[i].n * sizeof(double), s));
-    for (int mu = 0; mu < ne; ++mu) {
+    for (int mu = 0; mu < ne; ++mu) {  // (each row is zeroed by the scatter kernel)
       const int b = std::get<1>(all[mu]), j = std::get<2>(all[mu]);
       evals[i][mu] = std::get<0>(all[mu]);
-      sd.push_back(BlockScatterDesc{blks[b].nb, j, idx_dev + blks[b].off, V + blks[b].offsq,
-                                    Xs[i] + (size_t)mu * ops[i].n});
+      sd.push_back(BlockScatterDesc{blks[b].nb, j, ops[i].n, 0, idx_dev + blks[b].off,
+                                    V + blks[b].offsq, Xs[i] + (size_t)mu * ops[i].n});
     }
     st[i] = SolveStats();
     st[i].rr_sweeps = sweeps;

@@ -414,16 +414,18 @@ void gather_blocks(hipStream_t s, const BlockGatherDesc* d, int P, int nbmax) {
   hipLaunchKernelGGL(gather_blocks_kernel, dim3(bx, P), dim3(256), 0, s, d);
 }
 
+// One workgroup per output row: the row is zeroed, then (after the barrier) the block's
+// entries are written, so no separate fill per leaf is needed.
 __global__ __launch_bounds__(256) void scatter_block_rows_kernel(const BlockScatterDesc* __restrict__ descs) {
-  const BlockScatterDesc& d = descs[blockIdx.y];
-  for (int r = blockIdx.x * 256 + threadIdx.x; r < d.nb; r += gridDim.x * 256)
-    d.out[d.idx[r]] = d.V[(long)r * d.nb + d.col];
+  const BlockScatterDesc& d = descs[blockIdx.x];
+  for (int t = threadIdx.x; t < d.n; t += 256) d.out[t] = 0.0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < d.nb; r += 256) d.out[d.idx[r]] = d.V[(long)r * d.nb + d.col];
 }
 
 void scatter_block_rows(hipStream_t s, const BlockScatterDesc* d, int P, int nbmax) {
   if (P <= 0 || nbmax <= 0) return;
-  const int bx = std::max(1, std::min((nbmax + 255) / 256, 16));
-  hipLaunchKernelGGL(scatter_block_rows_kernel, dim3(bx, P), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(scatter_block_rows_kernel, dim3(P), dim3(256), 0, s, d);
 }
 
 void start_batched(hipStream_t s, const StartDesc* d, int P, int nmax, int mmax) {

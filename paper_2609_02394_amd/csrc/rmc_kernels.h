@@ -89,8 +89,10 @@ struct BlockGatherDesc {
 void gather_blocks(hipStream_t s, const BlockGatherDesc* d, int P, int nbmax);
 // Full-space rows from block eigenvectors: out[idx[r]] = V[r * nb + col], r < nb (the row
 // is zero elsewhere and must be cleared first).
+// Row `out` (n entries) of a leaf's retained basis: zero, then column col of the block
+// eigenvector matrix V (nb x nb) scattered to the block's basis indices idx.
 struct BlockScatterDesc {
-  int nb, col;
+  int nb, col, n, pad;
   const int* idx;
   const double* V;
   double* out;
