@@ -699,6 +699,45 @@ def test_serving_results_alone_equal_mix(ctx):
     assert rel_err(e, alone[0]) <= 1e-10
 
 
+def test_serving_admits_jobs_that_arrive_during_a_round(ctx):
+    """Jobs submitted while the scheduler is inside a round (the XXZ N=64 job's merges)
+    are admitted before that round's leaf phase; every result equals the job alone."""
+    import time
+
+    from paper_2609_02394_amd import rmc
+
+    say("serving arrivals during a round")
+    big = W.xxz_chain64()
+    smalls = [W.ChainJob("tfim", 16, 8, 16, 4, J=1.0, h=h) for h in (0.7, 0.9, 1.1, 1.3)]
+    alone_big = ctx.recurse(*rmc.job_chain(big))[0]
+    alone = [ctx.recurse(*rmc.job_chain(j))[0] for j in smalls]
+    ctx.serve_start(max_inflight=8)
+    try:
+        id_big = ctx.submit(*rmc.job_chain(big))
+        ids = []
+        for j in smalls:
+            time.sleep(0.004)
+            ids.append(ctx.submit(*rmc.job_chain(j)))
+        pending = {id_big: big.q, **{i: j.q for i, j in zip(ids, smalls)}}
+        got = {}
+        t0 = time.time()
+        while len(got) < len(pending) and time.time() - t0 < 240:
+            for jid, q in pending.items():
+                if jid not in got:
+                    done, e, st, lat = ctx.poll(jid, q)
+                    if done:
+                        got[jid] = (e, st)
+            time.sleep(0.002)
+    finally:
+        ctx.serve_stop()
+    assert len(got) == len(pending)
+    e, st = got[id_big]
+    assert st == rmc.OK and rel_err(e, alone_big) <= 1e-10
+    for jid, a in zip(ids, alone):
+        e, st = got[jid]
+        assert st == rmc.OK and rel_err(e, a) <= 1e-10, (e, a)
+
+
 def test_serving_memory_admission_and_oom(ctx):
     import time
 
