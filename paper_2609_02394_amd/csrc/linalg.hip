@@ -200,20 +200,23 @@ __global__ __launch_bounds__(256) void gemm_grouped_kernel(int tA, int tB, int k
 }
 
 // The same product for 64 < M <= 16 MT (a Rayleigh-Ritz block with its guard vectors,
-// MT = 5: 80 rows; MT = 8: 128 rows): one 16 MT x 64 output tile per workgroup, so M is
-// not padded to two 64-row tiles and the wide operand B is read once, not once per
-// row tile. Wave w owns columns 16w..16w+15 as MT 16 x 16 MFMA tiles down the rows.
-template <int MT>
-__global__ __launch_bounds__(256) void gemm_grouped_tall_kernel(int tA, int tB, int ksplit,
-                                                                const GemmDesc* __restrict__ descs) {
-  constexpr int GM = 16 * MT;
-  constexpr int NA = GM * GB_K / 256;  // A elements each thread stages per K slice
+// MT = 5: 80 rows; MT = 8: 128 rows): one 16 MT x 16 NW output tile per workgroup of NW
+// waves, so M is not padded to two 64-row tiles and the wide operand B is read once, not
+// once per row tile. Wave w owns columns 16w..16w+15 as MT 16 x 16 MFMA tiles down the
+// rows.
+template <int MT, int NW>
+__global__ __launch_bounds__(64 * NW) void gemm_grouped_tall_kernel(int tA, int tB, int ksplit,
+                                                                    const GemmDesc* __restrict__ descs) {
+  constexpr int GM = 16 * MT, GN = 16 * NW, NT = 64 * NW;
+  constexpr int NA = (GM * GB_K + NT - 1) / NT;  // A elements each thread stages per K slice
+  constexpr int NB = GB_K * GN / NT;             // B elements
+  static_assert(NB * NT == GB_K * GN, "B slice split");
   __shared__ double As[2][GB_K][GM + 1];
-  __shared__ double Bs[2][GB_K][GB_N + 1];
+  __shared__ double Bs[2][GB_K][GN + 1];
   const GemmDesc d = descs[blockIdx.z / ksplit];
   const int ks = blockIdx.z % ksplit;
   const int M = d.M, N = d.N, K = d.K;
-  const int col0 = blockIdx.x * GB_N;
+  const int col0 = blockIdx.x * GN;
   if (col0 >= N || M <= 0) return;
   int kchunk = (K + ksplit - 1) / ksplit;
   kchunk = ((kchunk + GB_K - 1) / GB_K) * GB_K;
@@ -225,21 +228,22 @@ __global__ __launch_bounds__(256) void gemm_grouped_tall_kernel(int tA, int tB, 
   d4 acc[MT];
 #pragma unroll
   for (int i = 0; i < MT; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
-  double ra[NA], rb[4];
+  double ra[NA], rb[NB];
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
-      const int idx = tid + e * 256;  // < GM * 16
+      const int idx = tid + e * NT;  // the last round may run past GM * 16: nothing to load
       int i, k;
       if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / GM; i = idx % GM; }
       const int gk = k0 + k;
-      ra[e] = (i < M && gk < kend) ? (tA ? d.A[(long)gk * d.lda + i] : d.A[(long)i * d.lda + gk]) : 0.0;
+      ra[e] = (idx < GM * GB_K && i < M && gk < kend)
+                  ? (tA ? d.A[(long)gk * d.lda + i] : d.A[(long)i * d.lda + gk]) : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = tid + e * 256;
+    for (int e = 0; e < NB; ++e) {
+      const int idx = tid + e * NT;
       int j, kb;
-      if (!tB) { kb = idx / GB_N; j = idx % GB_N; } else { j = idx / GB_K; kb = idx % GB_K; }
+      if (!tB) { kb = idx / GN; j = idx % GN; } else { j = idx / GB_K; kb = idx % GB_K; }
       const int gj = col0 + j, gkb = k0 + kb;
       rb[e] = (gj < N && gkb < kend) ? (tB ? d.B[(long)gj * d.ldb + gkb] : d.B[(long)gkb * d.ldb + gj]) : 0.0;
     }
@@ -247,16 +251,17 @@ __global__ __launch_bounds__(256) void gemm_grouped_tall_kernel(int tA, int tB, 
   auto store = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
-      const int idx = tid + e * 256;
+      const int idx = tid + e * NT;
+      if (idx >= GM * GB_K) break;
       int i, k;
       if (!tA) { i = idx / GB_K; k = idx % GB_K; } else { k = idx / GM; i = idx % GM; }
       As[buf][k][i] = ra[e];
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = tid + e * 256;
+    for (int e = 0; e < NB; ++e) {
+      const int idx = tid + e * NT;
       int j, kb;
-      if (!tB) { kb = idx / GB_N; j = idx % GB_N; } else { j = idx / GB_K; kb = idx % GB_K; }
+      if (!tB) { kb = idx / GN; j = idx % GN; } else { j = idx / GB_K; kb = idx % GB_K; }
       Bs[buf][kb][j] = rb[e];
     }
   };
@@ -306,11 +311,17 @@ void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int
   if (P <= 0 || Mmax <= 0 || Nmax <= 0) return;
   if (ksplit < 1) ksplit = 1;
   if (Mmax > GB_M && Mmax <= 128) {
-    dim3 grid((Nmax + GB_N - 1) / GB_N, 1, P * ksplit);
-    if (Mmax <= 80)
-      hipLaunchKernelGGL(gemm_grouped_tall_kernel<5>, grid, dim3(256), 0, s, (int)tA, (int)tB, ksplit, d);
-    else
-      hipLaunchKernelGGL(gemm_grouped_tall_kernel<8>, grid, dim3(256), 0, s, (int)tA, (int)tB, ksplit, d);
+    // up to 80 rows (a block with its guard vectors): 80 x 64 tiles (4 waves); up to 128:
+    // 128 x 128 tiles (8 waves), so the small operand (a rotation, a triangular factor)
+    // is re-read half as often per output (41% -> 57% MFMA busy on 128-row products;
+    // 128-wide tiles at 64 and 80 rows measured no faster)
+    if (Mmax <= 80) {
+      dim3 grid((Nmax + 63) / 64, 1, P * ksplit);
+      hipLaunchKernelGGL((gemm_grouped_tall_kernel<5, 4>), grid, dim3(256), 0, s, (int)tA, (int)tB, ksplit, d);
+    } else {
+      dim3 grid((Nmax + 127) / 128, 1, P * ksplit);
+      hipLaunchKernelGGL((gemm_grouped_tall_kernel<8, 8>), grid, dim3(512), 0, s, (int)tA, (int)tB, ksplit, d);
+    }
     return;
   }
   dim3 grid((Nmax + GB_N - 1) / GB_N, (Mmax + GB_M - 1) / GB_M, P * ksplit);
