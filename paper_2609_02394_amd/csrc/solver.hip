@@ -817,11 +817,12 @@ bool update_problem(Batch& B, BP* p, int idx, int max_iter, double tol, int pmax
     deg = std::max(deg, (int)std::ceil(need));
   }
   // FP32 filters above degree ~24 stall at a noise floor on these spectra (rounding
-  // noise grows with the spread of T_deg over the wanted set); BF16 is held lower by
-  // its reduction target above
+  // noise grows with the spread of T_deg over the wanted set); with each problem at its
+  // own degree, a cap of 22 balances filter length against outer iterations best on the
+  // random-field batch (caps 16-24 measured); BF16 is held lower by its reduction target
   static const int fp32_cap = [] {
     const char* e = getenv("RMC_FP32_MAXDEG");
-    return e ? std::max(2, atoi(e)) : 24;
+    return e ? std::max(2, atoi(e)) : 22;
   }();
   if (p->prec == RMC_FP32) deg = std::min(deg, fp32_cap);
   p->deg = std::min(std::max(deg, 2), pmax);

@@ -558,7 +558,8 @@ def test_fused_filter_equals_per_step_filter(ctx, name, job, precs):
     workgroup) against the per-step launches: the same arithmetic, the K sums of the
     MFMAs aside, so the energies agree to rounding noise, both match FP64 to 1e-8, and
     the iteration histories match up to a locking decision flipped by a last-bit
-    difference (Kronecker flop totals within 8%)."""
+    difference (Kronecker flop totals within 8%; 15% in BF16, whose precision
+    escalations are decided on its noise level and can flip as well)."""
     from paper_2609_02394_amd import rmc
 
     e64, _ = ctx.recurse(*rmc.job_chain(job))
@@ -569,7 +570,8 @@ def test_fused_filter_equals_per_step_filter(ctx, name, job, precs):
         for f in ("1", "s"):
             assert rel_err(out[f][0], out["0"][0]) <= 1e-13, (prec, f, out)
             assert rel_err(out[f][0], e64) <= 1e-8, (prec, f, out[f][0], e64)
-            assert abs(out[f][1] - out["0"][1]) <= 0.08 * out["0"][1], (prec, f, out[f][1], out["0"][1])
+            tol = 0.15 if prec == rmc.BF16 else 0.08
+            assert abs(out[f][1] - out["0"][1]) <= tol * out["0"][1], (prec, f, out[f][1], out["0"][1])
 
 
 def test_fused_filter_batch_mixes_sizes_and_paths(ctx):
