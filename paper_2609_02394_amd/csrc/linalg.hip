@@ -1462,6 +1462,248 @@ __device__ __forceinline__ void jacobi_shift_body(int m, const double* __restric
   if (tid == 0) info[0] = converged ? sweeps : -(sweeps + 1);
 }
 
+// ---------------------------------------------------------------------------
+// The same cyclic Jacobi for 81 <= m <= 112, one barrier a round, with A and V kept
+// by index and updated in place. The position-frame storage above needs A and V
+// twice and from m = 81 on no longer fits in LDS; in place needs them once: the
+// rotations of a round act on disjoint index pairs, so every entry of A (in the 2x2
+// block of two slots) and of V (a row pair of one column) that a round touches is
+// read and written by one thread, and only the rotation tables are double-buffered.
+// Slots, the fixed owner of each block and the next round's rotation computed by
+// wave 0 from the entry its block has just produced are those of the position-frame
+// form; the indices in slot k's positions k, M-1-k at round r come from the
+// round-robin schedule (rr_player). A is packed upper, V by column (the eigenvector
+// estimate of each index) with rows in pairs. Same rotation and thresholds as
+// jacobi_body; m odd is padded with a zero index M-1 whose rotations never qualify.
+// ---------------------------------------------------------------------------
+constexpr int JI_MIN = 81, JI_MAX = 112;
+
+size_t jacobi_inplace_lds_doubles(int m) {
+  const int M = m + (m & 1), H = M / 2;
+  const size_t na = ((size_t)M * (M + 1) / 2 + 1) & ~(size_t)1;
+  return na + (size_t)M * M + 8 * (size_t)H + 40;
+}
+
+__device__ __forceinline__ void jacobi_inplace_body(int m, const double* __restrict__ Ab, int nparts, long pstride,
+                                    double* __restrict__ evals, double* __restrict__ Vout, int max_sweeps,
+                                    int* __restrict__ info, double* sm) {
+  constexpr int VJ = 4;  // eigenvector items per thread: ceil(H / floor(960 / H)) <= 4 for H <= 56
+  constexpr int VH = VJ / 2;
+  constexpr int BJ = 2;  // blocks per thread of waves 1..15: H (H - 1) / 2 <= 2 * 960
+  const int M = m + (m & 1), H = M / 2;
+  const int na = (M * (M + 1) / 2 + 1) & ~1;
+  double* A = sm;                         // packed upper, by index
+  double2* V2 = (double2*)(A + na);       // [M][H]: column i, rows 2 rp and 2 rp + 1
+  double2* CS = V2 + M * H;               // [2][H] (c, s)
+  double2* DD = CS + 2 * H;               // [2][H] the pair's diagonals after its rotation
+  double* red = (double*)(DD + 2 * H);    // 32
+  int* flag = (int*)(red + 32);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63;
+  const bool w0 = tid < 64;
+
+  double nrm = 0.0;
+  const int np = M * (M + 1) / 2;
+  for (int t = tid; t < np; t += nt) {
+    int j = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (j * (j + 1) / 2 > t) --j;
+    while ((j + 1) * (j + 2) / 2 <= t) ++j;
+    const int i = t - j * (j + 1) / 2;
+    double v = 0.0;
+    if (j < m)
+      for (int ks = 0; ks < nparts; ++ks) {
+        const double* g = Ab + (long)ks * pstride;
+        v += 0.5 * (g[(long)i * m + j] + g[(long)j * m + i]);
+      }
+    A[t] = v;
+    nrm += (i == j ? 1.0 : 2.0) * v * v;
+  }
+  for (int t = tid; t < M * H; t += nt) {
+    const int i = t / H, rp = t % H;
+    V2[t] = make_double2(2 * rp == i ? 1.0 : 0.0, 2 * rp + 1 == i ? 1.0 : 0.0);
+  }
+  nrm = wave_sum(nrm);
+  if ((tid & 63) == 0) red[tid >> 6] = nrm;
+  __syncthreads();
+  double fro = 0.0;
+  for (int w = 0; w < (nt >> 6); ++w) fro += red[w];
+  fro = sqrt(fro);
+  const double eps = 2.220446049250313e-16, eps2 = eps * eps;
+  const double floor_abs = eps * fro;
+
+  // This thread's blocks (slots k <= l). Wave 0 lane kp owns the block holding the
+  // two indices that meet in slot kp next round: they sit this round at positions
+  // js_next(kp) (slot pa, side psa) and js_next(M-1-kp) (slot pb, side psb). Waves
+  // 1.. own the other blocks in column order, as in the position-frame form.
+  int bk[BJ], bl[BJ];
+  int pa = 0, psa = 0, pb = 0, psb = 0, sel = 0;
+#pragma unroll
+  for (int q = 0; q < BJ; ++q) { bk[q] = -1; bl[q] = -1; }
+  if (w0) {
+    if (lane < H) {
+      const int x = js_next(lane, M), y = js_next(M - 1 - lane, M);
+      pa = x < H ? x : M - 1 - x; psa = x < H ? 0 : 1;
+      pb = y < H ? y : M - 1 - y; psb = y < H ? 0 : 1;
+      bk[0] = min(pa, pb); bl[0] = max(pa, pb);
+      sel = pa < pb ? psa * 2 + psb : psb * 2 + psa;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < BJ; ++q) {
+      const int j = tid - 64 + q * (nt - 64);
+      if (j == 0) {
+        bk[q] = 0; bl[q] = 0;
+      } else if (j < H * (H - 1) / 2) {
+        int l = 1;
+        while (l + 1 < H && 1 + l * (l + 1) / 2 <= j) ++l;
+        const int r = j - (1 + (l - 1) * l / 2);
+        bl[q] = l;
+        if (l == 1) bk[q] = 1;
+        else if (l == H - 1) bk[q] = r < H - 3 ? r : r + 2;
+        else bk[q] = r < l - 2 ? r : r + 1;
+      }
+    }
+  }
+  // eigenvector items (waves 1..): row pair vr of the columns in slots vrg + j RG
+  const int RG = (nt - 64) / H;
+  const int vr = (tid - 64) % H, vrg = (tid - 64) / H;
+  int vk[VJ];
+#pragma unroll
+  for (int j = 0; j < VJ; ++j) {
+    const int k = vrg + j * RG;
+    vk[j] = (!w0 && vrg < RG && k < H) ? k : -1;
+  }
+  // rotations of round 0 (every index at its own position)
+  for (int k = tid; k < H; k += nt) {
+    const int p = k, q = M - 1 - k;
+    const double app = A[uidx(p, p)], apq = A[uidx(p, q)], aqq = A[uidx(q, q)];
+    double c, s, t;
+    js_rot(apq, app, aqq, eps2, floor_abs, c, s, t);
+    CS[k] = make_double2(c, s);
+    DD[k] = make_double2(app - t * apq, aqq + t * apq);
+  }
+
+  int sweeps = 0, rc = 0;
+  bool converged = false;
+  for (;;) {
+    // any off-diagonal entry above its threshold? (a sweep starts at round 0, where
+    // slot k holds the indices k and M-1-k)
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    bool big = false;
+    auto test = [&](int i, int j) {
+      const double apq = A[sidx(i, j)];
+      big |= apq * apq > eps2 * fabs(A[uidx(i, i)] * A[uidx(j, j)]) && fabs(apq) > floor_abs;
+    };
+#pragma unroll
+    for (int q = 0; q < BJ; ++q) {
+      const int k = bk[q], l = bl[q];
+      if (k < 0) continue;
+      if (k == l) {
+        test(k, M - 1 - k);
+      } else {
+        test(k, l); test(k, M - 1 - l); test(M - 1 - k, l); test(M - 1 - k, M - 1 - l);
+      }
+    }
+    if (big) *flag = 1;
+    __syncthreads();
+    if (*flag == 0) { converged = true; break; }
+    if (sweeps >= max_sweeps) break;
+    ++sweeps;
+    for (int step = 0; step < M - 1; ++step, ++rc) {
+      const int bb = rc & 1;
+      const double2* cs_ = CS + bb * H;
+      const double2* dd_ = DD + bb * H;
+      if (!w0) {
+        // the entries a round touches are this thread's alone: the first half of the
+        // eigenvector items is loaded before the blocks are updated, the second after
+        double2 c_[VH], x0[VH], x1[VH];
+        int i0[VH], i1[VH];
+        auto vload = [&](int j0) {
+#pragma unroll
+          for (int j = 0; j < VH; ++j)
+            if (vk[j0 + j] >= 0) {
+              i0[j] = rr_player(vk[j0 + j], step, M) * H + vr;
+              i1[j] = rr_player(M - 1 - vk[j0 + j], step, M) * H + vr;
+              c_[j] = cs_[vk[j0 + j]];
+              x0[j] = V2[i0[j]];
+              x1[j] = V2[i1[j]];
+            }
+        };
+        auto vstore = [&](int j0) {
+#pragma unroll
+          for (int j = 0; j < VH; ++j)
+            if (vk[j0 + j] >= 0 && c_[j].y != 0.0) {
+              const double c = c_[j].x, s = c_[j].y;
+              V2[i0[j]] = make_double2(c * x0[j].x - s * x1[j].x, c * x0[j].y - s * x1[j].y);
+              V2[i1[j]] = make_double2(s * x0[j].x + c * x1[j].x, s * x0[j].y + c * x1[j].y);
+            }
+        };
+        vload(0);
+#pragma unroll
+        for (int q = 0; q < BJ; ++q) {
+          const int k = bk[q], l = bl[q];
+          if (k < 0) continue;
+          const int Pk = rr_player(k, step, M), Qk = rr_player(M - 1 - k, step, M);
+          const double2 k2 = cs_[k];
+          if (k == l) {
+            const double2 dk = dd_[k];
+            A[uidx(Pk, Pk)] = dk.x;
+            A[uidx(Qk, Qk)] = dk.y;
+            if (k2.y != 0.0) A[sidx(Pk, Qk)] = 0.0;
+          } else {
+            const int Pl = rr_player(l, step, M), Ql = rr_player(M - 1 - l, step, M);
+            const int i00 = sidx(Pk, Pl), i01 = sidx(Pk, Ql), i10 = sidx(Qk, Pl), i11 = sidx(Qk, Ql);
+            const double2 l2 = cs_[l];
+            const double m00 = A[i00], m01 = A[i01], m10 = A[i10], m11 = A[i11];
+            const double r00 = k2.x * m00 - k2.y * m10, r01 = k2.x * m01 - k2.y * m11;
+            const double r10 = k2.y * m00 + k2.x * m10, r11 = k2.y * m01 + k2.x * m11;
+            A[i00] = r00 * l2.x - r01 * l2.y;
+            A[i01] = r00 * l2.y + r01 * l2.x;
+            A[i10] = r10 * l2.x - r11 * l2.y;
+            A[i11] = r10 * l2.y + r11 * l2.x;
+          }
+        }
+        vstore(0);
+        vload(VH);
+        vstore(VH);
+      } else if (bk[0] >= 0) {
+        const int k = bk[0], l = bl[0];
+        const int Pk = rr_player(k, step, M), Qk = rr_player(M - 1 - k, step, M);
+        const int Pl = rr_player(l, step, M), Ql = rr_player(M - 1 - l, step, M);
+        const int i00 = sidx(Pk, Pl), i01 = sidx(Pk, Ql), i10 = sidx(Qk, Pl), i11 = sidx(Qk, Ql);
+        const double2 ka = cs_[k], la = cs_[l];
+        const double2 da = dd_[pa], db = dd_[pb];
+        const double m00 = A[i00], m01 = A[i01], m10 = A[i10], m11 = A[i11];
+        const double r00 = ka.x * m00 - ka.y * m10, r01 = ka.x * m01 - ka.y * m11;
+        const double r10 = ka.y * m00 + ka.x * m10, r11 = ka.y * m01 + ka.x * m11;
+        const double n00 = r00 * la.x - r01 * la.y, n01 = r00 * la.y + r01 * la.x;
+        const double n10 = r10 * la.x - r11 * la.y, n11 = r10 * la.y + r11 * la.x;
+        A[i00] = n00; A[i01] = n01; A[i10] = n10; A[i11] = n11;
+        const double apq = sel == 0 ? n00 : sel == 1 ? n01 : sel == 2 ? n10 : n11;
+        const double app = psa ? da.y : da.x, aqq = psb ? db.y : db.x;
+        double c, s, t;
+        js_rot(apq, app, aqq, eps2, floor_abs, c, s, t);
+        CS[(bb ^ 1) * H + lane] = make_double2(c, s);
+        DD[(bb ^ 1) * H + lane] = make_double2(app - t * apq, aqq + t * apq);
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < m; i += nt) {
+    const double di = A[uidx(i, i)];
+    int rank = 0;
+    for (int j = 0; j < m; ++j) {
+      const double dj = A[uidx(j, j)];
+      rank += (dj < di) || (dj == di && j < i);
+    }
+    evals[rank] = di;
+    const double* col = reinterpret_cast<const double*>(V2 + (long)i * H);
+    for (int r = 0; r < m; ++r) Vout[(long)r * m + rank] = col[r];
+  }
+  if (tid == 0) info[0] = converged ? sweeps : -(sweeps + 1);
+}
+
 __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, const double* __restrict__ Ain, long sA,
                                                              int nparts, long pstride,
                                                              double* __restrict__ evals, long sE,
@@ -1473,6 +1715,9 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, const double
   if (m >= JS_MIN && m <= JS_MAX)
     jacobi_shift_body(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
                       max_sweeps, info + b, sm);
+  else if (m >= JI_MIN && m <= JI_MAX)
+    jacobi_inplace_body(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
+                        max_sweeps, info + b, sm);
   else
     jacobi_body(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
                 Vwork + (long)b * m * m, vlds, max_sweeps, info + b, sm);
@@ -1484,14 +1729,18 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_batched_kernel(const EigDe
   const EigDesc d = descs[blockIdx.x];
   if (d.m >= JS_MIN && d.m <= JS_MAX)
     jacobi_shift_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, max_sweeps, d.info, sm);
+  else if (d.m >= JI_MIN && d.m <= JI_MAX)
+    jacobi_inplace_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, max_sweeps, d.info, sm);
   else
     jacobi_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, d.Vwork, vlds, max_sweeps, d.info, sm);
 }
 
 // LDS for a launch whose largest matrix is mmax: either body may run
 static size_t jacobi_launch_lds(int mmax, int vl) {
-  size_t d = jacobi_lds_doubles(mmax, vl);
+  // the generic body runs below JS_MIN and above JI_MAX only
+  size_t d = jacobi_lds_doubles(mmax > JI_MAX ? mmax : std::min(mmax, JS_MIN - 1), vl);
   if (mmax >= JS_MIN) d = std::max(d, jacobi_shift_lds_doubles(std::min(mmax, JS_MAX)));
+  if (mmax >= JI_MIN) d = std::max(d, jacobi_inplace_lds_doubles(std::min(mmax, JI_MAX)));
   return d * sizeof(double);
 }
 
