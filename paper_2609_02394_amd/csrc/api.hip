@@ -336,48 +336,47 @@ void leaf_blocks_solve(rmc_ctx* ctx, Scratch& sc, const std::vector<const rmc_le
   RMC_HIP(hipMemcpyAsync(ed_dev, ed.data(), NB * sizeof(EigDesc), hipMemcpyHostToDevice, s));
   gather_blocks(s, gd_dev, NB, nbmax);
   jacobi_batched(s, ed_dev, NB, nbmax);
-  std::vector<double> evh(idx.size());
+  // per leaf, on the device: the lowest ne of the union of its blocks' spectra (in the
+  // order (eigenvalue, block, column)), their values and the scatter descriptors of the
+  // rows they fill; only the kept eigenvalues and the sweep counts come back
+  std::vector<LeafSelDesc> ls;
+  std::vector<long> evo(leaves.size(), 0);
+  long nsd = 0;
+  for (int i : sel) {
+    const int D = (int)(blks[range[i].second - 1].off + blks[range[i].second - 1].nb - blks[range[i].first].off);
+    const int ne = std::min(nevs[i], D);
+    evo[i] = nsd;
+    ls.push_back(LeafSelDesc{range[i].first, range[i].second - range[i].first, ne, ops[i].n, nsd, Xs[i], nullptr});
+    nsd += ne;
+  }
+  double* evsel = sc.get<double>(std::max(nsd, 1L));
+  for (size_t t = 0; t < ls.size(); ++t) ls[t].evout = evsel + ls[t].sdbase;
+  LeafSelDesc* ls_dev = sc.get<LeafSelDesc>(ls.size());
+  BlockScatterDesc* sd_dev = sc.get<BlockScatterDesc>(std::max(nsd, 1L));
+  RMC_HIP(hipMemcpyAsync(ls_dev, ls.data(), ls.size() * sizeof(LeafSelDesc), hipMemcpyHostToDevice, s));
+  // the ranks of a leaf are a permutation of 0..D-1 unless an eigenvalue is NaN; a
+  // descriptor no rank claims then stays all zero and scatters nothing
+  RMC_HIP(hipMemsetAsync(sd_dev, 0, std::max(nsd, 1L) * sizeof(BlockScatterDesc), s));
+  leaf_select(s, ls_dev, (int)ls.size(), ed_dev, gd_dev, sd_dev);
+  scatter_block_rows(s, sd_dev, (int)nsd, nbmax);  // (each row is zeroed by the scatter kernel)
+  std::vector<double> evh(nsd);
   std::vector<int> infoh(NB);
-  RMC_HIP(hipMemcpyAsync(evh.data(), ev, evh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (nsd > 0) RMC_HIP(hipMemcpyAsync(evh.data(), evsel, nsd * sizeof(double), hipMemcpyDeviceToHost, s));
   RMC_HIP(hipMemcpyAsync(infoh.data(), info, NB * sizeof(int), hipMemcpyDeviceToHost, s));
   sync(ctx);
-  // per leaf: (eigenvalue, block, column) sorted; the lowest nevs rows scattered
-  std::vector<BlockScatterDesc> sd;
-  size_t nsd = 0;
-  for (int i : sel) nsd += (size_t)std::max(0, nevs[i]);
-  sd.reserve(nsd);
-  std::vector<std::tuple<double, int, int>> all;
-  for (int i : sel) {
-    all.clear();
+  for (size_t t = 0; t < ls.size(); ++t) {
+    const int i = sel[t];
     int sweeps = 0;
     bool ok = true;
     for (int b = range[i].first; b < range[i].second; ++b) {
-      for (int j = 0; j < blks[b].nb; ++j) all.emplace_back(evh[blks[b].off + j], b, j);
       sweeps += std::abs(infoh[b]);
       ok = ok && infoh[b] >= 0;
     }
-    // only the lowest ne in order (the same order as a full sort: the key is total)
-    const int ne = std::min<int>(nevs[i], (int)all.size());
-    std::partial_sort(all.begin(), all.begin() + ne, all.end());
-    evals[i].resize(ne);
-    for (int mu = 0; mu < ne; ++mu) {  // (each row is zeroed by the scatter kernel)
-      const int b = std::get<1>(all[mu]), j = std::get<2>(all[mu]);
-      evals[i][mu] = std::get<0>(all[mu]);
-      sd.push_back(BlockScatterDesc{blks[b].nb, j, ops[i].n, 0, idx_dev + blks[b].off,
-                                    V + blks[b].offsq, Xs[i] + (size_t)mu * ops[i].n});
-    }
+    evals[i].assign(evh.begin() + evo[i], evh.begin() + evo[i] + ls[t].ne);
     st[i] = SolveStats();
     st[i].rr_sweeps = sweeps;
     st[i].status = ok ? RMC_OK : RMC_ERR_NOCONV;
   }
-  if (!sd.empty()) {
-    BlockScatterDesc* sd_dev = sc.get<BlockScatterDesc>(sd.size());
-    RMC_HIP(hipMemcpyAsync(sd_dev, sd.data(), sd.size() * sizeof(BlockScatterDesc), hipMemcpyHostToDevice, s));
-    scatter_block_rows(s, sd_dev, (int)sd.size(), nbmax);
-  }
-  // the scratch tables are read by kernels queued on the stream; the caller's later
-  // copies and its final synchronisation on the same stream order them
-  sync(ctx);
 }
 
 // Lowest eigenpairs of several dense leaves in one batched solve; builds a module

@@ -428,6 +428,53 @@ void scatter_block_rows(hipStream_t s, const BlockScatterDesc* d, int P, int nbm
   hipLaunchKernelGGL(scatter_block_rows_kernel, dim3(P), dim3(256), 0, s, d);
 }
 
+// One workgroup per leaf, a thread per eigenvalue of the leaf. Within its own block an
+// eigenvalue's column is its count of smaller keys (the block is ascending, equal values
+// in column order); every other block adds the count of its values below (blocks after
+// it) or not above (blocks before it: equal values there come first), by bisection.
+__global__ __launch_bounds__(256) void leaf_select_kernel(const LeafSelDesc* __restrict__ descs,
+                                                          const EigDesc* __restrict__ ed,
+                                                          const BlockGatherDesc* __restrict__ gd,
+                                                          BlockScatterDesc* __restrict__ sd) {
+  const LeafSelDesc L = descs[blockIdx.x];
+  const EigDesc* eb = ed + L.b0;
+  const double* ev0 = eb[0].evals;  // the leaf's eigenvalues, block after block
+  const int D = (int)(eb[L.nblk - 1].evals - ev0) + eb[L.nblk - 1].m;
+  for (int e = threadIdx.x; e < D; e += 256) {
+    const double v = ev0[e];
+    int rank = 0, b = 0, j = 0;
+    for (int q = 0; q < L.nblk; ++q) {
+      const double* x = eb[q].evals;
+      const int nb = eb[q].m, o = (int)(x - ev0);
+      if (e >= o && e < o + nb) {
+        b = q;
+        j = e - o;
+        rank += j;
+        continue;
+      }
+      const bool before = o + nb <= e;
+      int lo = 0, hi = nb;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const double xm = x[mid];
+        if (before ? xm <= v : xm < v) lo = mid + 1;
+        else hi = mid;
+      }
+      rank += lo;
+    }
+    if (rank < L.ne) {
+      L.evout[rank] = v;
+      sd[L.sdbase + rank] = BlockScatterDesc{eb[b].m, j, L.n, 0, gd[L.b0 + b].idx, eb[b].V, L.X + (long)rank * L.n};
+    }
+  }
+}
+
+void leaf_select(hipStream_t s, const LeafSelDesc* d, int P, const EigDesc* ed, const BlockGatherDesc* gd,
+                 BlockScatterDesc* sd) {
+  if (P <= 0) return;
+  hipLaunchKernelGGL(leaf_select_kernel, dim3(P), dim3(256), 0, s, d, ed, gd, sd);
+}
+
 void start_batched(hipStream_t s, const StartDesc* d, int P, int nmax, int mmax) {
   if (P <= 0) return;
   hipLaunchKernelGGL(rank_select_batched_kernel, dim3(P), dim3(256), 0, s, d);

@@ -98,6 +98,20 @@ struct BlockScatterDesc {
   double* out;
 };
 void scatter_block_rows(hipStream_t s, const BlockScatterDesc* d, int P, int nbmax);
+// Selection of a block-diagonal leaf's lowest ne eigenpairs from its blocks' spectra
+// (each block's eigenvalues ascending, the leaf's blocks consecutive from b0 in the
+// eigensolver and gather tables): the rank of an eigenvalue is its place in the order
+// (value, block, column) over the whole leaf; rank mu < ne goes to evout[mu] and to the
+// scatter descriptor sd[sdbase + mu], which fills row mu of X (n entries each).
+struct EigDesc;
+struct LeafSelDesc {
+  int b0, nblk, ne, n;
+  long sdbase;
+  double* X;
+  double* evout;
+};
+void leaf_select(hipStream_t s, const LeafSelDesc* d, int P, const EigDesc* ed, const BlockGatherDesc* gd,
+                 BlockScatterDesc* sd);
 
 // Diagonal of H_eff: D[a*kB+b] = EA[a] + EB[b] + sum_i c_i OA_i[a,a] OB_i[b,b];
 // Ediag[a*kB+b] = EA[a] + EB[b].

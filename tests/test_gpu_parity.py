@@ -156,6 +156,32 @@ def test_leaf_blocks_equal_iterative_leaf_ed(ctx, job, k):
         assert np.max(np.abs(_projector_rows(B1) - _projector_rows(B0))) <= 1e-9
 
 
+@pytest.mark.parametrize("fields,k", [(False, 16), (True, 20)])
+def test_leaf_blocks_of_one_state_each(ctx, fields, k):
+    """A diagonal leaf (an 8-site Ising chain, with or without random longitudinal
+    fields) splits into 256 one-state blocks: the lowest k of the union, in the order
+    (energy, block, column), are those of the oracle's dense ED. Without fields the
+    levels are highly degenerate; k = 16 ends at a gap (the states with at most one
+    domain wall), so the retained subspace is unique there as well."""
+    say("leaf one-state blocks", fields, k)
+    rng = np.random.default_rng(7)
+    terms = [(1.0, ((s, "Z"), (s + 1, "Z"))) for s in range(7)]
+    if fields:
+        terms += [(float(h), ((s, "Z"),)) for s, h in enumerate(rng.uniform(-0.5, 0.5, 8))]
+    H = np.zeros((256, 256))
+    for c, ops in terms:
+        H = H + c * OH.term_matrix(8, {s: o for s, o in ops})
+    m = ctx.module_ed(8, terms, k)
+    info, B = m.info(), m.basis()
+    m.free()
+    E_or, V_or, k_eff, gap, w = OR.leaf_ed(H, k)
+    assert info["k_eff"] == k_eff
+    assert rel_err(info["E"], E_or) <= 1e-12
+    assert np.max(np.abs(B @ B.T - np.eye(k_eff))) <= 1e-12
+    if gap > 1e-3:
+        assert np.max(np.abs(_projector_rows(B) - _projector_rows(V_or.T))) <= 1e-9
+
+
 @pytest.mark.parametrize("chain,leaf", [(60, 0), (195, 3), (227, 1)])
 def test_leaf_ed_guard_rows_stay_out_of_the_final_rayleigh_ritz(ctx, chain, leaf):
     """Random-field leaves whose guard Ritz values sit just outside the wanted
