@@ -854,6 +854,7 @@ rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_job_desc* jobs,
     if (opts) o = *opts;
     RMC_CHECK(o.precision >= RMC_FP64 && o.precision <= RMC_BF16, RMC_ERR_ARG, "bad precision");
     std::vector<JobRun*> live;
+    std::unique_ptr<HostScope> plans(new HostScope("batch.plans"));
     for (int j = 0; j < n_jobs; ++j) {
       try {
         TreeStore T = tree_of_job(&jobs[j]);
@@ -864,6 +865,8 @@ rmc_status rmc_recurse_batch(rmc_ctx* ctx, int n_jobs, const rmc_job_desc* jobs,
         st[j] = e.code;
       }
     }
+    plans.reset();
+    RMC_HOST_SCOPE("batch.run");
     run_jobs(ctx, live, o);
   });
   host_trace_dump("rmc_recurse_batch");

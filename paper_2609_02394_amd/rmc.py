@@ -197,6 +197,26 @@ def make_job(job):
     return JobDesc(None, C.pointer(cd)), q, [arr, cd]
 
 
+class JobBatch:
+    """Jobs marshalled once into the library's job descriptors, for callers that solve
+    the same batch repeatedly (the descriptors are read-only inputs of
+    rmc_recurse_batch and stay valid while this object lives)."""
+
+    def __init__(self, jobs):
+        self.n = len(jobs)
+        self.descs = (JobDesc * max(1, self.n))()
+        self.keep = []
+        self.qmax = 1
+        for j, job in enumerate(jobs):
+            jd, q, kp = make_job(job)
+            self.descs[j] = jd
+            self.keep.append(kp)
+            self.qmax = max(self.qmax, q)
+
+    def __len__(self):
+        return self.n
+
+
 def default_opts(**kw) -> SolveOpts:
     o = SolveOpts()
     lib().rmc_default_opts(C.byref(o))
@@ -414,21 +434,15 @@ class Context:
                 "total_ms": rep.total_ms}
 
     def recurse_batch(self, jobs, opts: Optional[SolveOpts] = None):
-        """jobs: chain tuples (n_sites, leaf_sites, terms, k, q) or tree tuples
-        ("tree", nodes, k, q). Returns energies (n, qmax) and per-job status codes."""
-        n = len(jobs)
-        descs = (JobDesc * max(1, n))()
-        keep = []
-        qmax = 1
-        for j, job in enumerate(jobs):
-            jd, q, kp = make_job(job)
-            descs[j] = jd
-            keep.append(kp)
-            qmax = max(qmax, q)
-        e = np.full((max(1, n), qmax), np.nan)
+        """jobs: a JobBatch, or chain tuples (n_sites, leaf_sites, terms, k, q) and tree
+        tuples ("tree", nodes, k, q). Returns energies (n, qmax), per-job status codes
+        and the call's status."""
+        b = jobs if isinstance(jobs, JobBatch) else JobBatch(jobs)
+        n = b.n
+        e = np.full((max(1, n), b.qmax), np.nan)
         sts = (C.c_int * max(1, n))()
-        st = lib().rmc_recurse_batch(self.h, n, descs, C.byref(opts) if opts else None,
-                                     e.ctypes.data_as(C.POINTER(C.c_double)), qmax, sts)
+        st = lib().rmc_recurse_batch(self.h, n, b.descs, C.byref(opts) if opts else None,
+                                     e.ctypes.data_as(C.POINTER(C.c_double)), b.qmax, sts)
         return e[:n], list(sts)[:n], st
 
     # -- serving (continuous batching) --------------------------------------------

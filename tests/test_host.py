@@ -66,6 +66,25 @@ def test_default_opts_without_gpu():
     assert o.precision == rmc.FP64 and o.tol == 1e-13 and o.gap_tol == 1e-6
 
 
+def test_job_batch_marshals_each_job_once():
+    """A JobBatch holds one descriptor per job with the chain's fields and its terms,
+    site by site and operator by operator, as make_terms writes them."""
+    from paper_2609_02394_amd import rmc
+
+    jobs = [rmc.job_chain(j) for j in W.rfheis_batch(6)] + [rmc.job_chain(W.tfim_small())]
+    b = rmc.JobBatch(jobs)
+    assert len(b) == 7 and b.qmax == max(j[4] for j in jobs)
+    for d, (ns, ls, terms, k, q) in zip(b.descs, jobs):
+        assert not d.tree and d.chain
+        c = d.chain.contents
+        assert (c.n_sites, c.leaf_sites, c.n_terms, c.k, c.q) == (ns, ls, len(terms), k, q)
+        for t, (coef, ops) in enumerate(terms):
+            tm = c.terms[t]
+            assert tm.coef == coef and tm.nsite == len(ops)
+            assert [(tm.site[u], tm.op[u]) for u in range(len(ops))] == \
+                [(s, rmc.OPS[o]) for s, o in ops]
+
+
 @pytest.mark.parametrize("job", [
     W.tfim_small(),
     W.ChainJob("xxz", 8, 8, 8, 4, J=1.0, delta=0.7),
