@@ -335,7 +335,25 @@ void leaf_blocks_solve(rmc_ctx* ctx, Scratch& sc, const std::vector<const rmc_le
   RMC_HIP(hipMemcpyAsync(gd_dev, gd.data(), NB * sizeof(BlockGatherDesc), hipMemcpyHostToDevice, s));
   RMC_HIP(hipMemcpyAsync(ed_dev, ed.data(), NB * sizeof(EigDesc), hipMemcpyHostToDevice, s));
   gather_blocks(s, gd_dev, NB, nbmax);
-  jacobi_batched(s, ed_dev, NB, nbmax);
+  // the Jacobi launches take the blocks largest first: blocks above 56 with 1024-thread
+  // workgroups, the rest with 512 threads (two workgroups a CU); the selection below
+  // reads the tables in leaf order
+  std::vector<EigDesc> es(NB);  // (alive until the final synchronisation)
+  {
+    std::vector<int> ord(NB);
+    for (int b = 0; b < NB; ++b) ord[b] = b;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return blks[a].nb > blks[b].nb; });
+    int nbig = 0, msmall = 0;
+    for (int t = 0; t < NB; ++t) {
+      es[t] = ed[ord[t]];
+      if (blks[ord[t]].nb > 56) ++nbig;
+      else msmall = std::max(msmall, blks[ord[t]].nb);
+    }
+    EigDesc* es_dev = sc.get<EigDesc>(NB);
+    RMC_HIP(hipMemcpyAsync(es_dev, es.data(), NB * sizeof(EigDesc), hipMemcpyHostToDevice, s));
+    jacobi_batched(s, es_dev, nbig, nbmax);
+    jacobi_batched(s, es_dev + nbig, NB - nbig, msmall, 512);
+  }
   // per leaf, on the device: the lowest ne of the union of its blocks' spectra (in the
   // order (eigenvalue, block, column)), their values and the scatter descriptors of the
   // rows they fill; only the kept eigenvalues and the sweep counts come back

@@ -1218,6 +1218,7 @@ __device__ __forceinline__ void jacobi_body(int m, const double* __restrict__ Ab
 // is padded with a zero index whose rotations never qualify.
 // ---------------------------------------------------------------------------
 constexpr int JS_MIN = 8, JS_MAX = 80;
+constexpr int JS_HALF_MAX = 56;  // largest m the body takes with 512 threads
 
 __device__ inline int js_next(int j, int M) { return j == 0 ? 0 : (j == M - 1 ? 1 : j + 1); }  // pos -> its index's previous pos
 __device__ inline int js_prev(int x, int M) { return x == 0 ? 0 : (x == 1 ? M - 1 : x - 1); }  // where pos x moves
@@ -1744,11 +1745,14 @@ static size_t jacobi_launch_lds(int mmax, int vl) {
   return d * sizeof(double);
 }
 
-void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax) {
+void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax, int threads) {
   if (P <= 0) return;
   const int vl = jacobi_v_in_lds(mmax) ? 1 : 0;
   size_t lds = jacobi_launch_lds(mmax, vl);
-  hipLaunchKernelGGL(jacobi_batched_kernel, dim3(P), dim3(JAC_THREADS), lds, s, d, vl, 40);
+  // half-size workgroups only where the m <= 80 body's work split holds with 448
+  // threads besides wave 0 (two eigenvector items and one block per thread)
+  const int nt = (threads == JAC_THREADS / 2 && mmax <= JS_HALF_MAX) ? JAC_THREADS / 2 : JAC_THREADS;
+  hipLaunchKernelGGL(jacobi_batched_kernel, dim3(P), dim3(nt), lds, s, d, vl, 40);
 }
 
 // Row-block vector operations (one workgroup per row for the reductions).

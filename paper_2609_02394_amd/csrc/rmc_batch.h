@@ -174,7 +174,9 @@ void kron_pack(hipStream_t s, int T, int kA, int kB, const double* coef, const d
 void gemm_batched(hipStream_t s, bool tA, bool tB, const GemmDesc* d, int P, int Mmax, int Nmax,
                   int ksplit);
 void gram_batched(hipStream_t s, const GramDesc* d, int P, int ks, int cmax);
-void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax);
+// threads: 1024, or 512 when every m <= 56 (two workgroups share a CU; the m <= 80 body
+// needs no more threads up to that size)
+void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax, int threads = 1024);
 void chol_batched(hipStream_t s, const CholDesc* d, int P, int mmax);
 void vec_batched(hipStream_t s, VecOp op, const VecDesc* d, int P, int nvmax, long elems_max);
 void start_batched(hipStream_t s, const StartDesc* d, int P, int nmax, int mmax);

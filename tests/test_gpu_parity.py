@@ -653,6 +653,12 @@ def test_recurse_batch_matches_single_jobs(ctx):
         assert rel_err(e[i, : j.q], e1) <= 1e-10, (i, e[i], e1)
     for i in (0, 6, 7, 8):
         assert rel_err(e[i, : jobs[i].q], OR.recurse(jobs[i]).energies) <= 1e-10
+    # the same jobs marshalled once and solved twice: the same energies as the list call
+    b = rmc.JobBatch([rmc.job_chain(j) for j in jobs])
+    for _ in range(2):
+        e2, st2, top2 = ctx.recurse_batch(b)
+        assert top2 == rmc.OK and st2 == st
+        assert np.array_equal(e2, e, equal_nan=True)
 
 
 def test_recurse_batch_isolates_bad_job(ctx):
