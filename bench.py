@@ -467,7 +467,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--arena-gb", type=float, default=32.0)
+    # the device arena, sized for the MI355X's 288 GB: at 128 GB every merge of a
+    # random-field level fits one memory chunk (32 GB split the first level in two)
+    ap.add_argument("--arena-gb", type=float, default=128.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (scales HBM counters)")
     args = ap.parse_args()

@@ -1181,10 +1181,15 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
     }
   };
 
+  // XCD x (blockIdx % 8) owns the launch's vectors [x V/8, (x+1) V/8); its GX
+  // workgroups take them in turn (stride GX), so that at any time they work on
+  // neighbouring vectors, mostly of one problem, whose operator tiles its L2 then
+  // serves to all of them
   const int w = blockIdx.x;
-  const int L = (w & 7) * (G >> 3) + (w >> 3);
-  const long v0 = (long)L * V / G, v1 = (long)(L + 1) * V / G;
-  if (v0 >= v1) return;
+  const int GX = G >> 3;
+  const long r0 = (long)(w & 7) * V / 8, r1 = (long)((w & 7) + 1) * V / 8;
+  const long v0 = r0 + (w >> 3);
+  if (v0 >= r1) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int rt = wave / NWR, c0 = (wave % NWR) * CPW;
@@ -1202,9 +1207,9 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
   }
   int j = (int)(v0 - descs[p].vbase);
   int staged = -1;  // problem whose term-0 tiles sit in LDS
-  for (long v = v0; v < v1; ++v) {
+  for (long v = v0; v < r1; v += GX) {
     while (j >= descs[p].nv) {
-      j = 0;
+      j -= descs[p].nv;
       ++p;
     }
     const FilterDesc* d = descs + p;
@@ -1218,10 +1223,10 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
     // term of this vector stages
     int pn = p, Tn = 0, pkmn = 0;
     const lt* packn = nullptr;
-    if (v + 1 < v1) {
-      int jn = j + 1;
+    if (v + GX < r1) {
+      int jn = j + GX;
       while (jn >= descs[pn].nv) {
-        jn = 0;
+        jn -= descs[pn].nv;
         ++pn;
       }
       Tn = descs[pn].T;
@@ -1282,7 +1287,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
             npack = packd;
             npkm = pkmd;
           }
-        } else if (v + 1 < v1) {
+        } else if (v + GX < r1) {
           if (Tn > 0 && !(pn == p && T == 1)) {
             npack = packn;
             npkm = pkmn;
@@ -1413,7 +1418,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
         }
       }
     }
-    ++j;
+    j += GX;
   }
 }
 
