@@ -506,9 +506,12 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
   lt* As = SH ? Bs : Bs + KM * PW;  // SH: one buffer holds O_B, then c O_A, of a step
   lt* Zt = As + KM * PW;
 
+  // XCD x (blockIdx % 8) owns the launch's vectors [x V/8, (x+1) V/8); its GX
+  // workgroups take them in turn, so that at any time they work on neighbouring
+  // vectors, mostly of one problem, whose operator tiles its L2 serves to all of them
   const int w = blockIdx.x;
-  const int L = (w & 7) * (G >> 3) + (w >> 3);
-  const long v0 = (long)L * V / G, v1 = (long)(L + 1) * V / G;
+  const int GX = G >> 3;
+  const long v0 = (long)(w & 7) * V / 8 + (w >> 3), v1 = (long)((w & 7) + 1) * V / 8;
   if (v0 >= v1) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
@@ -591,14 +594,13 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
     int nj = j, nt = t + 1, np = p;
     if (nt >= Td) {
       nt = 0;
-      if (v + 1 >= v1) {
+      if (v + GX >= v1) {
         has_next = false;
       } else {
-        nj = j + 1;
-        if (nj >= d->nv) {
-          np = p + 1;
-          while (descs[np].nv == 0) ++np;
-          nj = 0;
+        nj = j + GX;
+        while (nj >= descs[np].nv) {
+          nj -= descs[np].nv;
+          ++np;
         }
       }
     }
@@ -803,7 +805,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * NWC, (sk_blocks_per_cu<P, KM, SH>(
       } else if constexpr (!YG) {
         load_y(nd, nj, yf);  // every wave is past its last read of yf (barrier above)
       }
-      ++v;
+      v += GX;
     }
     p = np;
     j = nj;
@@ -884,9 +886,22 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
   };
   int staged = -1;  // streamed form: problem whose term-0 tiles sit in LDS
 
+  // XCD x (blockIdx % 8) owns the launch's vectors [x V/8, (x+1) V/8). Resident form:
+  // each of its GX workgroups takes a contiguous run (fewer operator loads into LDS);
+  // streamed form: they take the vectors in turn, so that at any time they work on
+  // neighbouring vectors of mostly one problem and share its tiles in L2
   const int w = blockIdx.x;
-  const int L = (w & 7) * (G >> 3) + (w >> 3);
-  const long v0 = (long)L * V / G, v1 = (long)(L + 1) * V / G;
+  const int GX = G >> 3;
+  const int vs = RES ? 1 : GX;
+  long v0, v1;
+  if constexpr (RES) {
+    const int L = (w & 7) * GX + (w >> 3);
+    v0 = (long)L * V / G;
+    v1 = (long)(L + 1) * V / G;
+  } else {
+    v0 = (long)(w & 7) * V / 8 + (w >> 3);
+    v1 = (long)((w & 7) + 1) * V / 8;
+  }
   if (v0 >= v1) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
@@ -904,9 +919,9 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
   }
   int j = (int)(v0 - descs[p].vbase);
   int loaded = -1;
-  for (long v = v0; v < v1; ++v) {
+  for (long v = v0; v < v1; v += vs) {
     while (j >= descs[p].nv) {
-      j = 0;
+      j -= descs[p].nv;
       ++p;
     }
     const FilterDesc* d = descs + p;
@@ -997,10 +1012,10 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
             nd = d;
           } else if (k < steps) {
             nd = d;
-          } else if (v + 1 < v1) {
-            int pn = p, jn = j + 1;
+          } else if (v + vs < v1) {
+            int pn = p, jn = j + vs;
             while (jn >= descs[pn].nv) {
-              jn = 0;
+              jn -= descs[pn].nv;
               ++pn;
             }
             nd = descs + pn;
@@ -1102,7 +1117,7 @@ __global__ __launch_bounds__(64 * (KM / 16) * (KM / 16) / CPW) void kron_filter_
       for (int r = 0; r < 4; ++r)
         if (idx[c][r] >= 0)
           oj[idx[c][r]] = __dadd_rn(__dmul_rn(phP, xv[c][r]), Dc[c][r]);  // as the scale-add kernel
-    ++j;
+    j += vs;
   }
 }
 
