@@ -1860,6 +1860,30 @@ void vec_batched(hipStream_t s, VecOp op, const VecDesc* d, int P, int nvmax, lo
   hipLaunchKernelGGL(vec_batched_kernel, dim3(gx, 1, P), dim3(256), 0, s, (int)op, d);
 }
 
+// One workgroup per filter, a thread per vector: its phi_k by the recurrence, every
+// product and the difference rounded on their own (no contraction), as on the host.
+__global__ __launch_bounds__(128) void filter_phi_kernel(const PhiDesc* __restrict__ descs) {
+  const PhiDesc d = descs[blockIdx.x];
+  for (int j = threadIdx.x; j < d.cn; j += 128) {
+    const double t = d.t[j];
+    double pk = __dmul_rn(d.r0, t), pm1 = 1.0;
+    d.phi[j] = pk;
+    for (int k = 1; k <= d.steps; ++k) {
+      const double a = d.sc[3 * (k - 1)];
+      const double b = k == 1 ? d.b1 : -d.sc[3 * (k - 1) + 2];
+      const double nx = __dsub_rn(__dmul_rn(__dmul_rn(a, t), pk), __dmul_rn(b, pm1));
+      pm1 = pk;
+      pk = nx;
+      d.phi[(long)k * d.cn + j] = pk;
+    }
+  }
+}
+
+void filter_phi_batched(hipStream_t s, const PhiDesc* d, int P) {
+  if (P <= 0) return;
+  hipLaunchKernelGGL(filter_phi_kernel, dim3(P), dim3(128), 0, s, d);
+}
+
 int jacobi_max_m() { return JMAX; }
 
 // Ct_v = (C_v)^T for the k_A x k_B coefficient blocks C_v of a merged basis:

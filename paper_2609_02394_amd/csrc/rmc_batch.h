@@ -50,6 +50,18 @@ struct FilterDesc {
   const double* phi;
   double r0;
 };
+// The phi_k rows of a fused filter (steps + 1 rows of cn): phi_0 = r0 t_j, then
+// phi_k = (s1_k t_j) phi_{k-1} - b_k phi_{k-2} with phi_{-1} = 1, b_1 = b1 and
+// b_k = -s3_k after (s1_k, s3_k from sc, 3 per step); t_j = theta_j - c. Each product
+// and the difference are rounded separately, as the host computes the same rows.
+struct PhiDesc {
+  int cn, steps;
+  double r0, b1;
+  const double* t;
+  const double* sc;
+  double* phi;
+};
+void filter_phi_batched(hipStream_t s, const PhiDesc* d, int P);
 bool kron_filter_fits(int precision, int kA, int kB, int T);
 void kron_filter_batched(hipStream_t s, const FilterDesc* d, int P, long total_vecs, int precision,
                          int kmax, int Tmax);

@@ -157,6 +157,8 @@ struct Batch {
   double* TR = nullptr;  // per-problem theta / res / info block
   long trs = 0;          // its stride (doubles)
   std::vector<double> TRh;
+  double* phi_dev = nullptr;  // the fused filters' phi_k rows (device), phi_cap doubles
+  size_t phi_cap = 0;
 };
 
 // Row-block roles: 0..2 = Y[i], 3 = X + nlock rows, 4 = HX + nlock rows, 5 = E,
@@ -846,6 +848,43 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr);
 // is filtered to its own degree (the kernel takes the step count per descriptor).
 void fused_filter(Batch& B, const std::vector<BP*>& L, int outr) {
   rmc_ctx* ctx = B.ctx;
+  // the step scalars of every problem (host) and its phi_k rows, computed by one device
+  // launch ahead of the filters from theta_j - c (the same recurrence, in the same
+  // operation order, as the per-step path's host rows)
+  std::vector<const double*> scp(L.size());
+  std::vector<double*> php(L.size());
+  {
+    std::vector<PhiDesc> phd;
+    size_t off = 0;
+    for (size_t i = 0; i < L.size(); ++i) {
+      BP* p = L[i];
+      const int cn = p->cnt, steps = p->deg - 1;
+      std::vector<double> sc(3 * (size_t)std::max(steps, 1)), t(std::max(cn, 1));
+      for (int j = 0; j < cn; ++j) t[j] = p->th[p->nlock + j] - p->c;
+      double sg = p->sigma1, b1 = 0.0;
+      const double tau2 = 2.0 / p->sigma1;
+      for (int k = 1; k <= steps; ++k) {
+        const double sk1 = 1.0 / (tau2 - sg);
+        sc[3 * (k - 1)] = 2.0 * sk1 / p->e;
+        sc[3 * (k - 1) + 1] = -2.0 * p->c * sk1 / p->e;
+        sc[3 * (k - 1) + 2] = k > 1 ? -sg * sk1 : 0.0;
+        if (k == 1) b1 = sg * sk1;
+        sg = sk1;
+      }
+      const size_t need = (size_t)(steps + 1) * cn;
+      RMC_CHECK(off + need <= B.phi_cap, RMC_ERR_OOM, "filter scalar table overflow");
+      php[i] = B.phi_dev + off;
+      off += need;
+      scp[i] = B.da->add(sc);
+      phd.push_back(PhiDesc{cn, steps, p->sigma1 / p->e, b1, B.da->add(t), scp[i], php[i]});
+    }
+    if (!phd.empty()) {
+      const PhiDesc* dd = B.da->add(phd);
+      const int np = (int)phd.size();
+      hipStream_t st = B.st;
+      B.da->defer([=] { filter_phi_batched(st, dd, np); });
+    }
+  }
   // one launch per precision and tile class: problems up to 64 share the 64-wide kernel
   // (smaller operators padded inside its tiles), 96-wide problems take the wide kernel
   auto wide = [](const CoupledOp& op) { return std::max(op.kA, op.kB) > 64; };
@@ -856,36 +895,18 @@ void fused_filter(Batch& B, const std::vector<BP*>& L, int outr) {
     int kmax = 0, Tm = 0;
     long tv = 0;
     double flops = 0.0, bytes = 0.0;
-    for (BP* p : L) {
+    for (size_t i = 0; i < L.size(); ++i) {
+      BP* p = L[i];
       if (p->prec != prec || wide(*p->op) != cls_wide) continue;
       const CoupledOp& op = *p->op;
       const int cn = p->cnt, steps = p->deg - 1;
-      std::vector<double> sc(3 * (size_t)std::max(steps, 1)), phi((size_t)(steps + 1) * cn);
-      std::vector<double> pm1(cn, 1.0), pk(cn);
-      for (int j = 0; j < cn; ++j) pk[j] = (p->sigma1 / p->e) * (p->th[p->nlock + j] - p->c);
-      std::copy(pk.begin(), pk.end(), phi.begin());
-      double sg = p->sigma1;
-      const double tau2 = 2.0 / p->sigma1;
-      for (int k = 1; k <= steps; ++k) {
-        const double sk1 = 1.0 / (tau2 - sg);
-        sc[3 * (k - 1)] = 2.0 * sk1 / p->e;
-        sc[3 * (k - 1) + 1] = -2.0 * p->c * sk1 / p->e;
-        sc[3 * (k - 1) + 2] = k > 1 ? -sg * sk1 : 0.0;
-        for (int j = 0; j < cn; ++j) {
-          const double nx = (2.0 * sk1 / p->e) * (p->th[p->nlock + j] - p->c) * pk[j] - sg * sk1 * pm1[j];
-          pm1[j] = pk[j];
-          pk[j] = nx;
-        }
-        std::copy(pk.begin(), pk.end(), phi.begin() + (size_t)k * cn);
-        sg = sk1;
-      }
       FilterDesc d{};
       d.kA = op.kA; d.kB = op.kB; d.T = op.T; d.nv = cn; d.vbase = tv;
       d.pack = op.pack[prec]; d.pkm = op.pkm; d.steps = steps;
       d.Ediag = op.Ediag; d.EA = op.EA; d.EB = op.EB;
       d.E = defect_of(p); d.X = role_ptr(p, 3); d.out = p->Y[outr];
-      d.sc = B.da->add(sc);
-      d.phi = B.da->add(phi);
+      d.sc = scp[i];
+      d.phi = php[i];
       d.r0 = p->sigma1 / p->e;
       fd.push_back(d);
       kmax = std::max(kmax, std::max(op.kA, op.kB));
@@ -1176,6 +1197,8 @@ void solve_attempt(rmc_ctx* ctx, std::vector<BP*>& probs, const rmc_solve_opts& 
   }
   RMC_HIP(hipMemsetAsync(B.TR, 0, (size_t)P * B.trs * sizeof(double), B.st));
   const int pmax = o.max_degree > 0 ? o.max_degree : 40;
+  B.phi_cap = (size_t)P * pmax * B.mmax;  // (deg <= pmax rows of at most m entries each)
+  B.phi_dev = sc.get<double>(B.phi_cap);
   const size_t da_bytes =
       (size_t)P * ((size_t)(pmax + 4) * B.mmax * 8 + (size_t)(pmax + 48) * 4 * 256) + (1 << 20);
   DescArena da(ctx, B.st, lane, sc, da_bytes);
