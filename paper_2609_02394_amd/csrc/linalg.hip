@@ -1464,44 +1464,52 @@ __device__ __forceinline__ void jacobi_shift_body(int m, const double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// The same cyclic Jacobi for 81 <= m <= 112, one barrier a round, with A and V kept
-// by index and updated in place. The position-frame storage above needs A and V
+// The same cyclic Jacobi, one barrier a round, with A and V kept by index and updated
+// in place: 81 <= m <= 112 with V in LDS, and even m from 114 to 146 with V in global
+// memory (the workgroup's own Vwork). The position-frame storage above needs A and V
 // twice and from m = 81 on no longer fits in LDS; in place needs them once: the
 // rotations of a round act on disjoint index pairs, so every entry of A (in the 2x2
 // block of two slots) and of V (a row pair of one column) that a round touches is
 // read and written by one thread, and only the rotation tables are double-buffered.
-// Slots, the fixed owner of each block and the next round's rotation computed by
-// wave 0 from the entry its block has just produced are those of the position-frame
-// form; the indices in slot k's positions k, M-1-k at round r come from the
-// round-robin schedule (rr_player). A is packed upper, V by column (the eigenvector
-// estimate of each index) with rows in pairs. Same rotation and thresholds as
-// jacobi_body; m odd is padded with a zero index M-1 whose rotations never qualify.
+// Slots, the fixed owner of each block and the next round's rotation, computed by the
+// thread of the slot (threads 0..H-1) from the entry its block has just produced, are
+// those of the position-frame form; the indices in slot k's positions k, M-1-k at
+// round r come from the round-robin schedule (rr_player). A is packed upper, V by
+// column (the eigenvector estimate of each index) with rows in pairs. Same rotation
+// and thresholds as jacobi_body; m odd is padded with a zero index M-1 whose rotations
+// never qualify (V in LDS only: in global memory V takes exactly m x m).
 // ---------------------------------------------------------------------------
-constexpr int JI_MIN = 81, JI_MAX = 112;
+constexpr int JI_MIN = 81, JI_MAX = 112;   // V in LDS
+constexpr int JG_MIN = 114, JG_MAX = 146;  // V in global memory, m even (H <= 73)
 
-size_t jacobi_inplace_lds_doubles(int m) {
+size_t jacobi_inplace_lds_doubles(int m, bool vg) {
   const int M = m + (m & 1), H = M / 2;
   const size_t na = ((size_t)M * (M + 1) / 2 + 1) & ~(size_t)1;
-  return na + (size_t)M * M + 8 * (size_t)H + 40;
+  return na + (vg ? 0 : (size_t)M * M) + 8 * (size_t)H + 40;
 }
 
+// VG: V in global memory (Vg); BJ blocks and VJ eigenvector items (in groups of VH,
+// loaded together) at most per thread past the next-rotation threads:
+//   V in LDS (H <= 56): 64 next-rotation threads, 960 others: BJ = 2, VJ = 4;
+//   V in global (H <= 73): 128 next-rotation threads from H = 65 on, 896 others:
+//   H (H - 1) / 2 <= 3 * 896 blocks, ceil(H / floor(896 / H)) <= 7 items.
+template <bool VG, int BJ, int VJ, int VH>
 __device__ __forceinline__ void jacobi_inplace_body(int m, const double* __restrict__ Ab, int nparts, long pstride,
-                                    double* __restrict__ evals, double* __restrict__ Vout, int max_sweeps,
-                                    int* __restrict__ info, double* sm) {
-  constexpr int VJ = 4;  // eigenvector items per thread: ceil(H / floor(960 / H)) <= 4 for H <= 56
-  constexpr int VH = VJ / 2;
-  constexpr int BJ = 2;  // blocks per thread of waves 1..15: H (H - 1) / 2 <= 2 * 960
+                                    double* __restrict__ evals, double* __restrict__ Vout,
+                                    double* __restrict__ Vg, int max_sweeps, int* __restrict__ info,
+                                    double* sm) {
+  static_assert(VJ % VH == 0, "item groups");
   const int M = m + (m & 1), H = M / 2;
   const int na = (M * (M + 1) / 2 + 1) & ~1;
-  double* A = sm;                         // packed upper, by index
-  double2* V2 = (double2*)(A + na);       // [M][H]: column i, rows 2 rp and 2 rp + 1
-  double2* CS = V2 + M * H;               // [2][H] (c, s)
-  double2* DD = CS + 2 * H;               // [2][H] the pair's diagonals after its rotation
-  double* red = (double*)(DD + 2 * H);    // 32
+  double* A = sm;                                           // packed upper, by index
+  double2* V2 = VG ? (double2*)Vg : (double2*)(A + na);     // [M][H]: column i, rows 2 rp, 2 rp + 1
+  double2* CS = (double2*)(A + na) + (VG ? 0 : M * H);      // [2][H] (c, s)
+  double2* DD = CS + 2 * H;                                 // [2][H] the pair's diagonals after its rotation
+  double* red = (double*)(DD + 2 * H);                      // 32
   int* flag = (int*)(red + 32);
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int lane = tid & 63;
-  const bool w0 = tid < 64;
+  const int NRT = ((H + 63) / 64) * 64;  // next-rotation threads (whole waves)
+  const bool w0 = tid < NRT;
 
   double nrm = 0.0;
   const int np = M * (M + 1) / 2;
@@ -1532,48 +1540,46 @@ __device__ __forceinline__ void jacobi_inplace_body(int m, const double* __restr
   const double eps = 2.220446049250313e-16, eps2 = eps * eps;
   const double floor_abs = eps * fro;
 
-  // This thread's blocks (slots k <= l). Wave 0 lane kp owns the block holding the
-  // two indices that meet in slot kp next round: they sit this round at positions
-  // js_next(kp) (slot pa, side psa) and js_next(M-1-kp) (slot pb, side psb). Waves
-  // 1.. own the other blocks in column order, as in the position-frame form.
-  int bk[BJ], bl[BJ];
+  // This thread's blocks (slots k <= l). Thread kp < H owns the block holding the two
+  // indices that meet in slot kp next round: they sit this round at positions
+  // js_next(kp) (slot pa, side psa) and js_next(M-1-kp) (slot pb, side psb). The
+  // threads past NRT own the other blocks in column order, as in the position-frame
+  // form.
+  int bkl[BJ];  // block q as k << 8 | l, or -1
   int pa = 0, psa = 0, pb = 0, psb = 0, sel = 0;
 #pragma unroll
-  for (int q = 0; q < BJ; ++q) { bk[q] = -1; bl[q] = -1; }
+  for (int q = 0; q < BJ; ++q) bkl[q] = -1;
   if (w0) {
-    if (lane < H) {
-      const int x = js_next(lane, M), y = js_next(M - 1 - lane, M);
+    if (tid < H) {
+      const int x = js_next(tid, M), y = js_next(M - 1 - tid, M);
       pa = x < H ? x : M - 1 - x; psa = x < H ? 0 : 1;
       pb = y < H ? y : M - 1 - y; psb = y < H ? 0 : 1;
-      bk[0] = min(pa, pb); bl[0] = max(pa, pb);
+      bkl[0] = min(pa, pb) << 8 | max(pa, pb);
       sel = pa < pb ? psa * 2 + psb : psb * 2 + psa;
     }
   } else {
 #pragma unroll
     for (int q = 0; q < BJ; ++q) {
-      const int j = tid - 64 + q * (nt - 64);
+      const int j = tid - NRT + q * (nt - NRT);
       if (j == 0) {
-        bk[q] = 0; bl[q] = 0;
+        bkl[q] = 0;
       } else if (j < H * (H - 1) / 2) {
         int l = 1;
         while (l + 1 < H && 1 + l * (l + 1) / 2 <= j) ++l;
         const int r = j - (1 + (l - 1) * l / 2);
-        bl[q] = l;
-        if (l == 1) bk[q] = 1;
-        else if (l == H - 1) bk[q] = r < H - 3 ? r : r + 2;
-        else bk[q] = r < l - 2 ? r : r + 1;
+        int k;
+        if (l == 1) k = 1;
+        else if (l == H - 1) k = r < H - 3 ? r : r + 2;
+        else k = r < l - 2 ? r : r + 1;
+        bkl[q] = k << 8 | l;
       }
     }
   }
-  // eigenvector items (waves 1..): row pair vr of the columns in slots vrg + j RG
-  const int RG = (nt - 64) / H;
-  const int vr = (tid - 64) % H, vrg = (tid - 64) / H;
-  int vk[VJ];
-#pragma unroll
-  for (int j = 0; j < VJ; ++j) {
-    const int k = vrg + j * RG;
-    vk[j] = (!w0 && vrg < RG && k < H) ? k : -1;
-  }
+  // eigenvector items (threads past NRT): row pair vr of the columns in slots vrg + j RG
+  const int RG = (nt - NRT) / H;
+  const int vr = (tid - NRT) % H, vrg = (tid - NRT) / H;
+  const bool vown = !w0 && vrg < RG;
+  auto vk = [&](int j) { const int k = vrg + j * RG; return vown && k < H ? k : -1; };
   // rotations of round 0 (every index at its own position)
   for (int k = tid; k < H; k += nt) {
     const int p = k, q = M - 1 - k;
@@ -1598,8 +1604,8 @@ __device__ __forceinline__ void jacobi_inplace_body(int m, const double* __restr
     };
 #pragma unroll
     for (int q = 0; q < BJ; ++q) {
-      const int k = bk[q], l = bl[q];
-      if (k < 0) continue;
+      if (bkl[q] < 0) continue;
+      const int k = bkl[q] >> 8, l = bkl[q] & 255;
       if (k == l) {
         test(k, M - 1 - k);
       } else {
@@ -1616,17 +1622,19 @@ __device__ __forceinline__ void jacobi_inplace_body(int m, const double* __restr
       const double2* cs_ = CS + bb * H;
       const double2* dd_ = DD + bb * H;
       if (!w0) {
-        // the entries a round touches are this thread's alone: the first half of the
-        // eigenvector items is loaded before the blocks are updated, the second after
+        // the entries a round touches are this thread's alone: the eigenvector items go
+        // in groups of VH (loads together, then the rotated stores), the first group's
+        // loads ahead of the block updates
         double2 c_[VH], x0[VH], x1[VH];
         int i0[VH], i1[VH];
         auto vload = [&](int j0) {
 #pragma unroll
           for (int j = 0; j < VH; ++j)
-            if (vk[j0 + j] >= 0) {
-              i0[j] = rr_player(vk[j0 + j], step, M) * H + vr;
-              i1[j] = rr_player(M - 1 - vk[j0 + j], step, M) * H + vr;
-              c_[j] = cs_[vk[j0 + j]];
+            if (vk(j0 + j) >= 0) {
+              const int k = vk(j0 + j);
+              i0[j] = rr_player(k, step, M) * H + vr;
+              i1[j] = rr_player(M - 1 - k, step, M) * H + vr;
+              c_[j] = cs_[k];
               x0[j] = V2[i0[j]];
               x1[j] = V2[i1[j]];
             }
@@ -1634,17 +1642,27 @@ __device__ __forceinline__ void jacobi_inplace_body(int m, const double* __restr
         auto vstore = [&](int j0) {
 #pragma unroll
           for (int j = 0; j < VH; ++j)
-            if (vk[j0 + j] >= 0 && c_[j].y != 0.0) {
+            if (vk(j0 + j) >= 0 && c_[j].y != 0.0) {
               const double c = c_[j].x, s = c_[j].y;
               V2[i0[j]] = make_double2(c * x0[j].x - s * x1[j].x, c * x0[j].y - s * x1[j].y);
               V2[i1[j]] = make_double2(s * x0[j].x + c * x1[j].x, s * x0[j].y + c * x1[j].y);
             }
         };
-        vload(0);
+        // (V in global memory: every group before the blocks, so that no group's
+        // registers are live across the block updates)
+        if constexpr (VG) {
+#pragma unroll
+          for (int j0 = 0; j0 < VJ; j0 += VH) {
+            vload(j0);
+            vstore(j0);
+          }
+        } else {
+          vload(0);
+        }
 #pragma unroll
         for (int q = 0; q < BJ; ++q) {
-          const int k = bk[q], l = bl[q];
-          if (k < 0) continue;
+          if (bkl[q] < 0) continue;
+          const int k = bkl[q] >> 8, l = bkl[q] & 255;
           const int Pk = rr_player(k, step, M), Qk = rr_player(M - 1 - k, step, M);
           const double2 k2 = cs_[k];
           if (k == l) {
@@ -1665,11 +1683,16 @@ __device__ __forceinline__ void jacobi_inplace_body(int m, const double* __restr
             A[i11] = r10 * l2.y + r11 * l2.x;
           }
         }
-        vstore(0);
-        vload(VH);
-        vstore(VH);
-      } else if (bk[0] >= 0) {
-        const int k = bk[0], l = bl[0];
+        if constexpr (!VG) {
+          vstore(0);
+#pragma unroll
+          for (int j0 = VH; j0 < VJ; j0 += VH) {
+            vload(j0);
+            vstore(j0);
+          }
+        }
+      } else if (bkl[0] >= 0) {
+        const int k = bkl[0] >> 8, l = bkl[0] & 255;
         const int Pk = rr_player(k, step, M), Qk = rr_player(M - 1 - k, step, M);
         const int Pl = rr_player(l, step, M), Ql = rr_player(M - 1 - l, step, M);
         const int i00 = sidx(Pk, Pl), i01 = sidx(Pk, Ql), i10 = sidx(Qk, Pl), i11 = sidx(Qk, Ql);
@@ -1685,8 +1708,8 @@ __device__ __forceinline__ void jacobi_inplace_body(int m, const double* __restr
         const double app = psa ? da.y : da.x, aqq = psb ? db.y : db.x;
         double c, s, t;
         js_rot(apq, app, aqq, eps2, floor_abs, c, s, t);
-        CS[(bb ^ 1) * H + lane] = make_double2(c, s);
-        DD[(bb ^ 1) * H + lane] = make_double2(app - t * apq, aqq + t * apq);
+        CS[(bb ^ 1) * H + tid] = make_double2(c, s);
+        DD[(bb ^ 1) * H + tid] = make_double2(app - t * apq, aqq + t * apq);
       }
       __syncthreads();
     }
@@ -1705,35 +1728,68 @@ __device__ __forceinline__ void jacobi_inplace_body(int m, const double* __restr
   if (tid == 0) info[0] = converged ? sweeps : -(sweeps + 1);
 }
 
+// V in global memory: a function of its own, so that its register pressure stays out
+// of the kernel's other bodies
+__device__ __noinline__ void jacobi_inplace_global(int m, const double* Ab, int nparts, long pstride,
+                                                  double* evals, double* Vout, double* Vg, int max_sweeps,
+                                                  int* info, double* sm) {
+  jacobi_inplace_body<true, 3, 8, 4>(m, Ab, nparts, pstride, evals, Vout, Vg, max_sweeps, info, sm);
+}
+
+// Largest launch that takes the in-place body with V in global memory: alone on a CU
+// it is faster than the two-barrier body (m = 128, random: 5.1 against 7.2 ms), but
+// every round moves the eigenvector matrix through L2, and with many workgroups a CU
+// the L2 traffic makes it slower (512 problems: 19.8 against 15.1 ms)
+constexpr int JG_BATCH = 128;
+
+// the in-place body for m, if it takes m: V in LDS (BJ 2, VJ 4), or in global memory
+// where the launch allows it (glob)
+__device__ __forceinline__ bool jacobi_inplace(int m, const double* Ab, int nparts, long pstride,
+                                               double* evals, double* Vout, double* Vg, int max_sweeps,
+                                               int* info, double* sm, bool glob) {
+  if (m >= JI_MIN && m <= JI_MAX) {
+    jacobi_inplace_body<false, 2, 4, 2>(m, Ab, nparts, pstride, evals, Vout, nullptr, max_sweeps, info, sm);
+    return true;
+  }
+  if (glob && m >= JG_MIN && m <= JG_MAX && (m & 1) == 0) {
+    jacobi_inplace_global(m, Ab, nparts, pstride, evals, Vout, Vg, max_sweeps, info, sm);
+    return true;
+  }
+  return false;
+}
+
 __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(int m, const double* __restrict__ Ain, long sA,
                                                              int nparts, long pstride,
                                                              double* __restrict__ evals, long sE,
                                                              double* __restrict__ Vout, long sV,
                                                              double* __restrict__ Vwork, int vlds,
                                                              int max_sweeps, int* __restrict__ info) {
+  // vlds: bit 0 V in LDS for the two-barrier body, bit 1 the global-V in-place body allowed
   extern __shared__ double sm[];
   const int b = blockIdx.x;
   if (m >= JS_MIN && m <= JS_MAX)
     jacobi_shift_body(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
                       max_sweeps, info + b, sm);
-  else if (m >= JI_MIN && m <= JI_MAX)
-    jacobi_inplace_body(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
-                        max_sweeps, info + b, sm);
+  else if (jacobi_inplace(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
+                          Vwork + (long)b * m * m, max_sweeps, info + b, sm, (vlds & 2) != 0))
+    ;
   else
     jacobi_body(m, Ain + (long)b * sA, nparts, pstride, evals + (long)b * sE, Vout + (long)b * sV,
-                Vwork + (long)b * m * m, vlds, max_sweeps, info + b, sm);
+                Vwork + (long)b * m * m, vlds & 1, max_sweeps, info + b, sm);
 }
 
 __global__ __launch_bounds__(JAC_THREADS) void jacobi_batched_kernel(const EigDesc* __restrict__ descs,
                                                                      int vlds, int max_sweeps) {
+  // vlds: as for jacobi_kernel
   extern __shared__ double sm[];
   const EigDesc d = descs[blockIdx.x];
   if (d.m >= JS_MIN && d.m <= JS_MAX)
     jacobi_shift_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, max_sweeps, d.info, sm);
-  else if (d.m >= JI_MIN && d.m <= JI_MAX)
-    jacobi_inplace_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, max_sweeps, d.info, sm);
+  else if (jacobi_inplace(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, d.Vwork, max_sweeps, d.info, sm,
+                          (vlds & 2) != 0))
+    ;
   else
-    jacobi_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, d.Vwork, vlds, max_sweeps, d.info, sm);
+    jacobi_body(d.m, d.A, d.nparts, d.pstride, d.evals, d.V, d.Vwork, vlds & 1, max_sweeps, d.info, sm);
 }
 
 // LDS for a launch whose largest matrix is mmax: either body may run
@@ -1741,7 +1797,8 @@ static size_t jacobi_launch_lds(int mmax, int vl) {
   // the generic body runs below JS_MIN and above JI_MAX only
   size_t d = jacobi_lds_doubles(mmax > JI_MAX ? mmax : std::min(mmax, JS_MIN - 1), vl);
   if (mmax >= JS_MIN) d = std::max(d, jacobi_shift_lds_doubles(std::min(mmax, JS_MAX)));
-  if (mmax >= JI_MIN) d = std::max(d, jacobi_inplace_lds_doubles(std::min(mmax, JI_MAX)));
+  if (mmax >= JI_MIN) d = std::max(d, jacobi_inplace_lds_doubles(std::min(mmax, JI_MAX), false));
+  if (mmax >= JG_MIN) d = std::max(d, jacobi_inplace_lds_doubles(std::min(mmax, JG_MAX), true));
   return d * sizeof(double);
 }
 
@@ -1752,7 +1809,7 @@ void jacobi_batched(hipStream_t s, const EigDesc* d, int P, int mmax, int thread
   // half-size workgroups only where the m <= 80 body's work split holds with 448
   // threads besides wave 0 (two eigenvector items and one block per thread)
   const int nt = (threads == JAC_THREADS / 2 && mmax <= JS_HALF_MAX) ? JAC_THREADS / 2 : JAC_THREADS;
-  hipLaunchKernelGGL(jacobi_batched_kernel, dim3(P), dim3(nt), lds, s, d, vl, 40);
+  hipLaunchKernelGGL(jacobi_batched_kernel, dim3(P), dim3(nt), lds, s, d, vl | (P <= JG_BATCH ? 2 : 0), 40);
 }
 
 // Row-block vector operations (one workgroup per row for the reductions).
@@ -1924,7 +1981,8 @@ void jacobi_eig(hipStream_t s, int batch, int m, const double* A, long sA, int n
   const int vl = jacobi_v_in_lds(m) ? 1 : 0;
   size_t lds = jacobi_launch_lds(m, vl);
   hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(JAC_THREADS), lds, s, m, A, sA,
-                     nparts < 1 ? 1 : nparts, pstride, evals, sE, V, sV, Vwork, vl, 40, info);
+                     nparts < 1 ? 1 : nparts, pstride, evals, sE, V, sV, Vwork,
+                     vl | (batch <= JG_BATCH ? 2 : 0), 40, info);
 }
 
 }  // namespace rmc

@@ -48,7 +48,7 @@ def rel_err(a, b):
 
 # -- dense building blocks -------------------------------------------------------
 
-@pytest.mark.parametrize("m", [1, 2, 3, 7, 8, 9, 16, 33, 64, 65, 72, 79, 80, 81, 100, 108, 111, 112, 113, 145, 192])
+@pytest.mark.parametrize("m", [1, 2, 3, 7, 8, 9, 16, 33, 64, 65, 72, 79, 80, 81, 100, 108, 111, 112, 113, 114, 128, 144, 145, 146, 148, 192])
 def test_sym_eig_jacobi(ctx, m):
     import torch
 
