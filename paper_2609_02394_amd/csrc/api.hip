@@ -527,7 +527,7 @@ std::vector<rmc_module*> leaf_solve_batch(rmc_ctx* ctx, const std::vector<const 
       m->k_eff = k_eff;
       m->gap = gap;
       m->E_host.assign(evals[i].begin(), evals[i].begin() + k_eff);
-      ctx->modules.push_back(m);
+      ctx->modules.insert(m);
       out[i] = m;
       m->E = (double*)ctx->arena.alloc(k_eff * sizeof(double));
       m->basis = (double*)ctx->arena.alloc((size_t)k_eff * D * sizeof(double));
@@ -559,8 +559,7 @@ std::vector<rmc_module*> leaf_solve_batch(rmc_ctx* ctx, const std::vector<const 
   } catch (...) {
     for (rmc_module* m : out)
       if (m) {
-        auto it = std::find(ctx->modules.begin(), ctx->modules.end(), m);
-        if (it != ctx->modules.end()) ctx->modules.erase(it);
+        ctx->modules.erase(m);
         free_module_mem(ctx, m);
         delete m;
       }
@@ -925,7 +924,7 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
       m->B = reqs[p].B;
       m->gap = gap;
       m->E_host.assign(evals[p].begin(), evals[p].begin() + k_eff);
-      ctx->modules.push_back(m);
+      ctx->modules.insert(m);
       out[p] = m;
       m->E = (double*)ctx->arena.alloc(k_eff * sizeof(double));
       m->basis = (double*)ctx->arena.alloc((size_t)k_eff * n * sizeof(double));
@@ -956,8 +955,7 @@ std::vector<rmc_module*> couple_batch(rmc_ctx* ctx, const std::vector<CoupleReq>
   } catch (...) {
     for (rmc_module* m : out)
       if (m) {
-        auto it = std::find(ctx->modules.begin(), ctx->modules.end(), m);
-        if (it != ctx->modules.end()) ctx->modules.erase(it);
+        ctx->modules.erase(m);
         free_module_mem(ctx, m);
         delete m;
       }
@@ -1034,8 +1032,7 @@ void api_release_basis(rmc_ctx* ctx, rmc_module* m) {
 }
 void api_free_module(rmc_ctx* ctx, rmc_module* m) {
   RMC_HOST_SCOPE("module.free");
-  auto it = std::find(ctx->modules.begin(), ctx->modules.end(), m);
-  if (it != ctx->modules.end()) ctx->modules.erase(it);
+  ctx->modules.erase(m);
   free_module_mem(ctx, m);
   delete m;
 }
@@ -1234,8 +1231,8 @@ namespace {
 // 2^{n_A} x 2^{n_B} matrix (A holds the high bits). Two GEMMs per level: one for
 // all mu (C psi_B), one strided batch over mu (psi_A^T T_mu).
 void lift_module(rmc_ctx* ctx, const rmc_module* m, double* out) {
-  RMC_CHECK(std::find(ctx->modules.begin(), ctx->modules.end(), m) != ctx->modules.end(),
-            RMC_ERR_STATE, "module (or a module below it) is not owned by this context");
+  RMC_CHECK(ctx->modules.count(const_cast<rmc_module*>(m)) != 0, RMC_ERR_STATE,
+            "module (or a module below it) is not owned by this context");
   RMC_CHECK(m->basis != nullptr, RMC_ERR_STATE, "module basis freed");
   hipStream_t s = ctx->stream;
   const long D = 1L << m->n_sites;
@@ -1289,7 +1286,7 @@ rmc_status rmc_module_free(rmc_ctx* ctx, rmc_module* m) {
   if (!ctx || !m) return RMC_ERR_ARG;
   return guard(ctx, [&] {
     hipStreamSynchronize(ctx->stream);
-    auto it = std::find(ctx->modules.begin(), ctx->modules.end(), m);
+    auto it = ctx->modules.find(m);
     RMC_CHECK(it != ctx->modules.end(), RMC_ERR_ARG, "module not owned by this context");
     for (rmc_module* o : ctx->modules)
       if (o->A == m || o->B == m) {
@@ -1340,7 +1337,7 @@ rmc_status rmc_module_import(rmc_ctx* ctx, int n_sites, int k, int dim, const do
       delete m;
       throw;
     }
-    ctx->modules.push_back(m);
+    ctx->modules.insert(m);
     *out = m;
   });
 }
@@ -1496,8 +1493,8 @@ void merge_bound(rmc_ctx* ctx, rmc_module* A, const rmc_leaf_desc* la, rmc_modul
   validate_leaf(lb);
   RMC_CHECK(A && B && bond && out, RMC_ERR_ARG, "null argument");
   for (const rmc_module* m : {A, B}) {
-    RMC_CHECK(std::find(ctx->modules.begin(), ctx->modules.end(), m) != ctx->modules.end(),
-              RMC_ERR_ARG, "module not owned by this context");
+    RMC_CHECK(ctx->modules.count(const_cast<rmc_module*>(m)) != 0, RMC_ERR_ARG,
+              "module not owned by this context");
     RMC_CHECK(m->kind == 0 && m->dim == (1 << m->n_sites), RMC_ERR_ARG,
               "the diagnostics need two leaf modules");
     RMC_CHECK(m->basis != nullptr, RMC_ERR_STATE, "module basis freed");

@@ -9,6 +9,7 @@
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/rmc.h"
@@ -90,7 +91,7 @@ struct rmc_ctx {
   void* arena_mem = nullptr;
   rmc::Arena arena;
   std::string last_error;
-  std::vector<rmc_module*> modules;
+  std::unordered_set<rmc_module*> modules;  // every live module of this context
   // measurement of the Kronecker matvec launches
   bool prof = false;
   struct ProfRec {
