@@ -1,5 +1,6 @@
-// Host-only pieces of librmc that need no HIP: the error type, phase timing and the
-// device-arena sub-allocator (which only does offset arithmetic on a base pointer).
+// Host-only pieces of librmc that need no HIP: the error type, phase timing, the
+// device-arena sub-allocator and scoped scratch over it (which only do offset
+// arithmetic on a base pointer).
 // Compiled into the library and, on its own, into the host sanitizer test.
 #pragma once
 #include <stddef.h>
@@ -10,6 +11,7 @@
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "../../include/rmc.h"
 
@@ -67,6 +69,44 @@ class Arena {
   std::map<size_t, size_t> free_;                // offset -> bytes
   std::set<std::pair<size_t, size_t>> by_size_;  // (bytes, offset) of the free blocks
   std::unordered_map<size_t, size_t> used_;      // offset -> bytes
+};
+
+
+// Scoped scratch memory, released together at the end of its scope. Requests up to
+// 1 MiB are carved in order from 4 MiB arena blocks (256-byte aligned, as the arena's
+// own blocks), so the many small tables of a batched level cost one arena call per
+// block rather than one each; larger requests take an arena block of their own.
+struct Scratch {
+  static constexpr size_t kBlock = (size_t)4 << 20, kOwn = (size_t)1 << 20;
+  Arena* arena;
+  std::vector<void*> ptrs;
+  char* cur = nullptr;
+  size_t left = 0;
+  explicit Scratch(Arena* a) : arena(a) {}
+  ~Scratch() {
+    for (void* p : ptrs) arena->release(p);
+  }
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
+  template <class T>
+  T* get(size_t count) {
+    size_t b = count * sizeof(T) > 0 ? count * sizeof(T) : 8;
+    b = (b + 255) & ~(size_t)255;
+    if (b > kOwn) {
+      void* p = arena->alloc(b);
+      ptrs.push_back(p);
+      return static_cast<T*>(p);
+    }
+    if (b > left) {
+      cur = static_cast<char*>(arena->alloc(kBlock));
+      ptrs.push_back(cur);
+      left = kBlock;
+    }
+    T* r = reinterpret_cast<T*>(cur);
+    cur += b;
+    left -= b;
+    return r;
+  }
 };
 
 }  // namespace rmc

@@ -4,10 +4,12 @@
 // blocks are 256-byte aligned, lie inside the arena and never overlap, that the
 // in-use count is the sum of the live blocks, that an allocation that cannot fit
 // throws RMC_ERR_OOM and leaves the arena as it was, and that releasing every block
-// merges the free space back into one block of the whole arena.
+// merges the free space back into one block of the whole arena; then the scoped
+// scratch carved from it (alignment, bounds, disjoint pieces, release at scope end).
 #include <stdint.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <map>
 #include <random>
 #include <vector>
@@ -73,6 +75,43 @@ int main() {
   EXPECT(A.in_use() == 0);
   EXPECT(A.free_blocks() == 1);
   EXPECT(A.largest_free() == size);
+  // Scoped scratch: requests up to 1 MiB carved in order from 4 MiB blocks, larger ones
+  // a block each; every piece 256-byte aligned, inside the arena, disjoint from the
+  // others of its scope (and of an enclosing scope), and everything released at the
+  // end of the scope.
+  {
+    struct Piece { size_t off, bytes; };
+    std::vector<Piece> outer;
+    rmc::Scratch so(&A);
+    auto take = [&](rmc::Scratch& sc, std::vector<Piece>& v, size_t count) -> int {
+      double* p = sc.get<double>(count);
+      const size_t off = (size_t)((char*)p - base), bytes = (count ? count : 1) * sizeof(double);
+      EXPECT(off % 256 == 0);
+      EXPECT(off + bytes <= size);
+      v.push_back({off, bytes});
+      return 0;
+    };
+    for (int i = 0; i < 300; ++i) EXPECT(take(so, outer, rng() % 3000) == 0);
+    const size_t used_outer = A.in_use();
+    for (int round = 0; round < 20; ++round) {
+      std::vector<Piece> inner;
+      {
+        rmc::Scratch si(&A);
+        for (int i = 0; i < 100; ++i) {
+          const size_t c = rng() % 10 == 0 ? (size_t)(1 << 17) + rng() % 200000 : rng() % 20000;
+          EXPECT(take(si, inner, c) == 0);
+        }
+        std::vector<Piece> all(outer);
+        all.insert(all.end(), inner.begin(), inner.end());
+        std::sort(all.begin(), all.end(), [](const Piece& x, const Piece& y) { return x.off < y.off; });
+        for (size_t i = 1; i < all.size(); ++i) EXPECT(all[i - 1].off + all[i - 1].bytes <= all[i].off);
+        EXPECT(A.in_use() > used_outer);
+      }
+      EXPECT(A.in_use() == used_outer);
+    }
+  }
+  EXPECT(A.in_use() == 0);
+  EXPECT(A.free_blocks() == 1);
   printf("arena_check ok: %ld allocations refused for lack of space\n", ooms);
   return 0;
 }
