@@ -1144,6 +1144,7 @@ rmc_status rmc_destroy(rmc_ctx* ctx) {
     }
   for (hipEvent_t e : ctx->lane_ev)
     if (e) hipEventDestroy(e);
+  if (ctx->filter_ev) hipEventDestroy(ctx->filter_ev);
   if (ctx->own_arena && ctx->arena_mem) hipFree(ctx->arena_mem);
   delete ctx;
   return RMC_OK;

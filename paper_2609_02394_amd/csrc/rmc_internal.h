@@ -78,6 +78,12 @@ struct rmc_ctx {
   // lane l)
   hipStream_t lane_stream[kMaxLanes] = {};  // [0] unused: lane 0 runs on `stream`
   hipEvent_t lane_ev[kMaxLanes] = {};
+  // whole-filter launches of all lanes in one chain on the device (filter_ev: the last
+  // one's end), so that a filter has the CUs to itself rather than sharing them with
+  // another lane's filter; guarded by filter_mu
+  std::mutex filter_mu;
+  hipEvent_t filter_ev = nullptr;
+  bool filter_ev_set = false;
   // serving: scheduler state (owned by recurse.hip); other calls are refused while set
   void* serve = nullptr;
   bool serving = false;

@@ -846,6 +846,28 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr);
 // and the phi_k rows of every problem are computed on the host up front (the same
 // recurrences as the per-step path) and travel in the descriptor tables. Each problem
 // is filtered to its own degree (the kernel takes the step count per descriptor).
+// A whole-filter launch (launch()) placed in the lanes' common chain: it starts once
+// the previous filter of any lane has ended (RMC_FILTER_CHAIN=0: no chain)
+template <class F>
+void filter_in_chain(rmc_ctx* ctx, hipStream_t st, F&& launch) {
+  static const bool on = [] {
+    const char* e = getenv("RMC_FILTER_CHAIN");
+    return !(e && atoi(e) == 0);
+  }();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  RMC_HIP(hipStreamIsCapturing(st, &cs));
+  if (!on || cs != hipStreamCaptureStatusNone) {  // (a captured iteration keeps its own order)
+    launch();
+    return;
+  }
+  std::lock_guard<std::mutex> lk(ctx->filter_mu);
+  if (!ctx->filter_ev) RMC_HIP(hipEventCreateWithFlags(&ctx->filter_ev, hipEventDisableTiming));
+  if (ctx->filter_ev_set) RMC_HIP(hipStreamWaitEvent(st, ctx->filter_ev, 0));
+  launch();
+  RMC_HIP(hipEventRecord(ctx->filter_ev, st));
+  ctx->filter_ev_set = true;
+}
+
 void fused_filter(Batch& B, const std::vector<BP*>& L, int outr) {
   rmc_ctx* ctx = B.ctx;
   // the step scalars of every problem (host) and its phi_k rows, computed by one device
@@ -921,7 +943,7 @@ void fused_filter(Batch& B, const std::vector<BP*>& L, int outr) {
     hipStream_t st = B.st;
     const int nd = (int)fd.size();
     if (!ctx->prof) {
-      B.da->defer([=] { kron_filter_batched(st, dd, nd, tv, prec, kmax, Tm); });
+      B.da->defer([=] { filter_in_chain(ctx, st, [&] { kron_filter_batched(st, dd, nd, tv, prec, kmax, Tm); }); });
       continue;
     }
     rmc_ctx::ProfRec r;
@@ -932,9 +954,11 @@ void fused_filter(Batch& B, const std::vector<BP*>& L, int outr) {
     }
     hipEvent_t ea = r.a, eb = r.b;
     B.da->defer([=] {
-      RMC_HIP(hipEventRecord(ea, st));
-      kron_filter_batched(st, dd, nd, tv, prec, kmax, Tm);
-      RMC_HIP(hipEventRecord(eb, st));
+      filter_in_chain(ctx, st, [&] {
+        RMC_HIP(hipEventRecord(ea, st));
+        kron_filter_batched(st, dd, nd, tv, prec, kmax, Tm);
+        RMC_HIP(hipEventRecord(eb, st));
+      });
     });
     r.flops = flops;
     r.bytes = bytes;
