@@ -49,6 +49,23 @@ HostScope::~HostScope() {
   if (host_trace_on()) host_trace_add(name, host_now_ms() - t0);
 }
 
+std::string admit_pass(const std::vector<size_t>& queued, size_t inflight_mem, int inflight,
+                       int max_inflight, size_t budget) {
+  std::string out;
+  for (size_t i = 0; i < queued.size() && inflight < max_inflight; ++i) {
+    const size_t m = queued[i];
+    if (m > budget) {
+      out.push_back('r');
+      continue;
+    }
+    if (inflight > 0 && inflight_mem + m > budget) break;
+    inflight_mem += m;
+    ++inflight;
+    out.push_back('a');
+  }
+  return out;
+}
+
 void Arena::init(char* base, size_t size) {
   base_ = base;
   size_ = size & ~(kAlign - 1);

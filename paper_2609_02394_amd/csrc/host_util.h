@@ -72,6 +72,16 @@ class Arena {
 };
 
 
+// Serving admission, the policy alone (host only, unit-tested without a GPU). In: the
+// queued jobs' memory estimates in arrival order, the memory and number of the jobs in
+// flight, the slot limit and the memory budget. Jobs go into flight in order while a
+// slot is free and the job fits beside those in flight; a job above the budget can never
+// run and is rejected where it stands (when a slot is free); the first job that has to
+// wait ends the pass, so no later job overtakes it. Returns one letter per queued job
+// the pass decided, in order: 'a' admitted, 'r' rejected; the others stay queued.
+std::string admit_pass(const std::vector<size_t>& queued, size_t inflight_mem, int inflight,
+                       int max_inflight, size_t budget);
+
 // Scoped scratch memory, released together at the end of its scope. Requests up to
 // 1 MiB are carved in order from 4 MiB arena blocks (256-byte aligned, as the arena's
 // own blocks), so the many small tables of a batched level cost one arena call per

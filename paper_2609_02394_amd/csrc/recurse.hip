@@ -717,10 +717,14 @@ size_t job_memory(const Plan& P) {
 // free and their memory estimate fits beside the jobs in flight; a job that could never
 // fit finishes with RMC_ERR_OOM. Returns the admitted jobs.
 std::vector<JobRun*> admit_locked(ServeState* S) {
+  std::vector<size_t> mem;
+  mem.reserve(S->queue.size());
+  for (const auto& j : S->queue) mem.push_back(j->mem);
+  const std::string d = admit_pass(mem, S->inflight_mem, (int)S->inflight.size(), S->max_inflight, S->budget);
   std::vector<JobRun*> out;
-  while (!S->queue.empty() && (int)S->inflight.size() < S->max_inflight) {
+  for (char c : d) {
     ServeJob* j = S->queue.front().get();
-    if (j->mem > S->budget) {
+    if (c == 'r') {  // can never fit: finished with RMC_ERR_OOM
       ServeResult r;
       r.status = RMC_ERR_OOM;
       r.latency_ms = now_ms() - j->t_submit;
@@ -729,7 +733,6 @@ std::vector<JobRun*> admit_locked(ServeState* S) {
       S->queue.pop_front();
       continue;
     }
-    if (!S->inflight.empty() && S->inflight_mem + j->mem > S->budget) break;
     S->inflight_mem += j->mem;
     S->inflight.push_back(std::move(S->queue.front()));
     S->queue.pop_front();

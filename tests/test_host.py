@@ -144,6 +144,28 @@ def test_product_tree_nodes_match_oracle_tree_nodes(job, spec):
             assert [tuple(t) for t in x[3]] == [tuple(t) for t in y[3]]
 
 
+def test_serving_admission_under_sanitizers(tmp_path):
+    """The serving admission policy (host code, no GPU) built with the address and
+    undefined-behaviour sanitizers and driven through a seeded random stream of
+    submissions and completions, checking its invariants after every pass."""
+    import shutil
+    import subprocess
+
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    exe = str(tmp_path / "admission_check")
+    src = [os.path.join(ROOT, "tests", "host", "admission_check.cpp"),
+           os.path.join(ROOT, "paper_2609_02394_amd", "csrc", "host_util.cpp")]
+    r = subprocess.run([cxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                        "-fno-sanitize-recover=undefined", "-I", os.path.join(ROOT, "include"),
+                        *src, "-o", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "admission_check ok" in r.stdout
+
+
 def test_arena_allocator_under_sanitizers(tmp_path):
     """The device-arena sub-allocator (host code, no GPU) built with the address and
     undefined-behaviour sanitizers and driven through a seeded random sequence of
