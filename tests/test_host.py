@@ -166,6 +166,28 @@ def test_serving_admission_under_sanitizers(tmp_path):
     assert "admission_check ok" in r.stdout
 
 
+def test_arena_from_four_threads_under_thread_sanitizer(tmp_path):
+    """The arena and the host trace table, which the solver's lanes share, driven from
+    four host threads at once under the thread sanitizer (host code, no GPU)."""
+    import shutil
+    import subprocess
+
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    exe = str(tmp_path / "arena_threads_check")
+    src = [os.path.join(ROOT, "tests", "host", "arena_threads_check.cpp"),
+           os.path.join(ROOT, "paper_2609_02394_amd", "csrc", "host_util.cpp")]
+    r = subprocess.run([cxx, "-std=c++17", "-O1", "-g", "-fsanitize=thread", "-pthread",
+                        "-I", os.path.join(ROOT, "include"), *src, "-o", exe],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", RMC_TRACE_HOST="1")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "arena_threads_check ok" in r.stdout and "ThreadSanitizer" not in r.stderr
+
+
 def test_arena_allocator_under_sanitizers(tmp_path):
     """The device-arena sub-allocator (host code, no GPU) built with the address and
     undefined-behaviour sanitizers and driven through a seeded random sequence of
