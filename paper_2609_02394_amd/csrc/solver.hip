@@ -847,13 +847,16 @@ int filter_steps(Batch& B, const std::vector<BP*>& L, int P, int outr);
 // recurrences as the per-step path) and travel in the descriptor tables. Each problem
 // is filtered to its own degree (the kernel takes the step count per descriptor).
 // A whole-filter launch (launch()) placed in the lanes' common chain: it starts once
-// the previous filter of any lane has ended (RMC_FILTER_CHAIN=0: no chain)
+// the previous chained filter of any lane has ended. RMC_FILTER_CHAIN=0: no chain; 2:
+// only the 96-wide launches (one workgroup a CU), so that 64-wide launches of lanes in
+// lockstep (a batch of identical jobs) may still share the CUs
 template <class F>
-void filter_in_chain(rmc_ctx* ctx, hipStream_t st, F&& launch) {
-  static const bool on = [] {
+void filter_in_chain(rmc_ctx* ctx, hipStream_t st, bool wide, F&& launch) {
+  static const int mode = [] {
     const char* e = getenv("RMC_FILTER_CHAIN");
-    return !(e && atoi(e) == 0);
+    return e ? atoi(e) : 1;
   }();
+  const bool on = mode == 1 || (mode == 2 && wide);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   RMC_HIP(hipStreamIsCapturing(st, &cs));
   if (!on || cs != hipStreamCaptureStatusNone) {  // (a captured iteration keeps its own order)
@@ -943,7 +946,7 @@ void fused_filter(Batch& B, const std::vector<BP*>& L, int outr) {
     hipStream_t st = B.st;
     const int nd = (int)fd.size();
     if (!ctx->prof) {
-      B.da->defer([=] { filter_in_chain(ctx, st, [&] { kron_filter_batched(st, dd, nd, tv, prec, kmax, Tm); }); });
+      B.da->defer([=] { filter_in_chain(ctx, st, cls_wide, [&] { kron_filter_batched(st, dd, nd, tv, prec, kmax, Tm); }); });
       continue;
     }
     rmc_ctx::ProfRec r;
@@ -954,7 +957,7 @@ void fused_filter(Batch& B, const std::vector<BP*>& L, int outr) {
     }
     hipEvent_t ea = r.a, eb = r.b;
     B.da->defer([=] {
-      filter_in_chain(ctx, st, [&] {
+      filter_in_chain(ctx, st, cls_wide, [&] {
         RMC_HIP(hipEventRecord(ea, st));
         kron_filter_batched(st, dd, nd, tv, prec, kmax, Tm);
         RMC_HIP(hipEventRecord(eb, st));
